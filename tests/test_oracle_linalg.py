@@ -1,0 +1,116 @@
+"""Pins of the assembly, the TSVD solve and the outer loops."""
+import numpy as np
+
+import workloads as W
+from oracle import linalg as L
+from oracle.walker import build_toolbox
+from oracle.volume import cell_weights
+
+
+def _random_tb(n=12, p=5, d=2, seed=0):
+    rng = np.random.default_rng(seed)
+    return {"A": rng.random((n, n)), "B": rng.normal(size=(d, n, n)), "H": rng.random((n, p)),
+            "K": rng.normal(size=(d, n, p))}
+
+
+def test_regrouped_sums_equal_per_cell_sums():
+    n, p, d = 12, 5, 2
+    tb = _random_tb(n, p, d)
+    rng = np.random.default_rng(1)
+    lam = rng.random(n)
+    M = rng.normal(size=(n, d, d))
+    Ac = M @ M.transpose(0, 2, 1) + np.eye(d)
+    bc = rng.normal(size=(n, d))
+    cc = rng.random(n)
+    Lam, Sig = L.assemble(tb, lam, Ac, bc, cc)
+    A, B, H, K = tb["A"], tb["B"], tb["H"], tb["K"]
+    # literal form of the paper's definitions, one cell at a time
+    Lam2 = np.zeros((n, n))
+    Sig2 = np.zeros((n, p))
+    Bb = np.zeros((n, n))
+    Kb = np.zeros((n, p))
+    Hc = np.zeros((n, p))
+    for i in range(n):
+        Bi, Ki = B[:, i, :], K[:, i, :]
+        Lam2 += lam[i] * Bi.T @ Ac[i] @ Bi
+        Sig2 += lam[i] * Bi.T @ Ac[i] @ Ki
+        for j in range(n):
+            Bb[i, j] = lam[i] * sum(B[a, i, j] * bc[i, a] for a in range(d))
+        for j in range(p):
+            Kb[i, j] = lam[i] * sum(K[a, i, j] * bc[i, a] for a in range(d))
+            Hc[i, j] = lam[i] * cc[i] * H[i, j]
+    Lam2 += -A.T @ Bb + A.T @ np.diag(lam * cc) @ A
+    Sig2 += -A.T @ Kb + A.T @ Hc
+    assert np.allclose(Lam, Lam2, rtol=1e-12, atol=1e-12)
+    assert np.allclose(Sig, Sig2, rtol=1e-12, atol=1e-12)
+
+
+def test_tsvd_against_numpy_pinv():
+    rng = np.random.default_rng(2)
+    U, _ = np.linalg.qr(rng.normal(size=(30, 30)))
+    V, _ = np.linalg.qr(rng.normal(size=(30, 30)))
+    s = np.logspace(0, -7, 30)
+    M = U @ np.diag(s) @ V.T
+    r = rng.normal(size=30)
+    for rcond in (1e-3, 1e-2, 1e-9):
+        assert np.allclose(L.tsvd_solve(M, r, rcond), np.linalg.pinv(M, rcond=rcond) @ r, rtol=1e-9, atol=1e-9)
+
+
+def test_newton_on_quadratic_energy_is_the_linear_system():
+    # F = |p|^2/2 + c u^2/2 - f u: grad J = 0 is exactly eq. linear_q with
+    # A = I, b = 0, c, and the paper's f = -f.  One Newton step from any h
+    # lands on it.
+    tb = _random_tb(10, 4, 2, 3)
+    tb["B"] *= 3
+    rng = np.random.default_rng(4)
+    lam = rng.random(10)
+    f = rng.normal(size=10)
+    g = rng.normal(size=4)
+    c = rng.random(10)
+    lin = L.solve_linear(tb, lam, -f, g, ccoef=c, rcond=1e-14)
+    h = L.newton(tb, lam, g, dFu=lambda u: c * u - f, d2Fu=lambda u: c, rcond=1e-14, h0=rng.normal(size=10),
+                 max_iter=1)["h"]
+    assert np.allclose(h, lin["q"], rtol=1e-8, atol=1e-10)
+
+
+def test_newton_cubic_reaches_stationary_point():
+    tb = _random_tb(10, 4, 2, 5)
+    rng = np.random.default_rng(6)
+    lam = rng.random(10)
+    f = rng.normal(size=10)
+    g = rng.normal(size=4)
+    out = L.newton_cubic(tb, lam, f, g, kappa=1.0, rcond=1e-14, tol=1e-12)
+    assert out["grad_norm"] <= 1e-10 * out["grad_norm0"]
+    # kappa = 0 is the linear problem -Lap u = f
+    lin = L.solve_linear(tb, lam, -f, g, rcond=1e-14)
+    out0 = L.newton_cubic(tb, lam, f, g, kappa=0.0, rcond=1e-14)
+    assert np.allclose(out0["u"], lin["u"], rtol=1e-9, atol=1e-11)
+
+
+def _rings(K):
+    pts = []
+    for k in range(1, K + 1):
+        nk = 6 * k - 3
+        r = (k - 0.5) / K
+        th = 2 * np.pi * np.arange(nk) / nk
+        pts.append(np.stack([r * np.cos(th), r * np.sin(th)], 1))
+    return np.concatenate(pts)
+
+
+def test_disk_poisson_end_to_end():
+    # -Lap u = 1 on the unit disk, u = 0 on the boundary: u = (1 - |x|^2)/4.
+    # Direct apply (1/2) A 1 and the Galerkin system both recover it, on the
+    # paper's ring layout with 5 rings (75 sites).
+    dom = W.unit_disk()
+    sites = _rings(5)
+    n = len(sites)
+    bn = W.circle_nodes(30)
+    tb = build_toolbox(dom, sites, bn, 1500, 1e-3, 8)
+    lam, _ = cell_weights(dom, sites, 2, 1 << 18)
+    exact = (1 - (sites**2).sum(1)) / 4
+    u_direct, _ = L.apply_direct(tb, 0.5 * np.ones(n), np.zeros(30))
+    assert np.sqrt(np.mean((u_direct - exact) ** 2)) < 0.01
+    sol = L.solve_linear(tb, lam, -np.ones(n), np.zeros(30), rcond=3e-2)
+    err = np.sqrt(np.sum(lam * (sol["u"] - exact) ** 2)) / np.sqrt(np.sum(lam * exact**2))
+    # measured 0.049; a sign error in Lambda or in the right-hand side gives ~1
+    assert err < 0.08

@@ -1,0 +1,266 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module generates INPUTS only: domains, interior sites, boundary nodes,
+coefficient fields and manufactured solutions.  It holds none of the
+method's arithmetic (no distance to the boundary, no walks, no binning, no
+assembly), and neither the oracle nor the GPU path is imported here.
+
+Recipes (the paper publishes no data; shapes follow its experiments and the
+benchmark configurations):
+
+* sites: uniform in D by rejection from the bounding box with numpy's PCG64
+  generator, keeping points whose distance to the boundary exceeds a margin
+  (10 * eps by default, so that no site starts inside the stopping shell);
+* the paper's deterministic layouts: the disk's rings r_k = (k - 1/2)/10
+  with 6k - 3 points each (k = 1..10, n = 300) and 60 boundary nodes; the
+  square's 20 x 20 cell centres with 20 boundary nodes per edge at the edge
+  midpoints of the boundary cells (Sec. "Numerical examples", setup);
+* boundary nodes: equispaced angles on the circle; (k + 1/2)/q on each edge
+  of a box face; Fibonacci points on a sphere (z_k = 1 - (2k+1)/p,
+  phi_k = k pi (3 - sqrt 5)); equispaced arc length along a polygon's edges;
+  face-cell midpoints on the faces of a cube.
+"""
+import numpy as np
+
+# ---------------------------------------------------------------- domains
+
+
+def unit_disk():
+    return {"kind": "ball", "dim": 2, "center": [0.0, 0.0], "radius": 1.0}
+
+
+def unit_ball():
+    return {"kind": "ball", "dim": 3, "center": [0.0, 0.0, 0.0], "radius": 1.0}
+
+
+def unit_square():
+    return {"kind": "box", "dim": 2, "lo": [0.0, 0.0], "hi": [1.0, 1.0]}
+
+
+def l_shape():
+    """(-1,1)^2 minus [0,1) x (-1,0], counter-clockwise (the paper's L-shape)."""
+    verts = [[-1.0, -1.0], [0.0, -1.0], [0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [-1.0, 1.0]]
+    return {"kind": "polygon", "dim": 2, "verts": verts}
+
+
+def cube_minus_ball():
+    return {"kind": "box_minus_ball", "dim": 3, "lo": [0.0, 0.0, 0.0], "hi": [1.0, 1.0, 1.0],
+            "center": [0.5, 0.5, 0.5], "radius": 0.3}
+
+
+# ------------------------------------------------- interior with a margin
+
+
+def _box_gap(x, lo, hi):
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    return np.minimum(x - lo, hi - x).min(axis=1)
+
+
+def _outside_box_gap(x, lo, hi):
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    e = np.maximum(np.maximum(lo - x, x - hi), 0.0)
+    return np.sqrt((e * e).sum(axis=1))
+
+
+def interior_with_margin(dom, x, margin):
+    """True where x lies in D at distance > margin from the boundary
+    (written per workload domain; used only to draw inputs)."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    k = dom["kind"]
+    if k == "ball":
+        c = np.asarray(dom["center"], dtype=np.float64)
+        return np.linalg.norm(x - c, axis=1) < dom["radius"] - margin
+    if k == "box":
+        return _box_gap(x, dom["lo"], dom["hi"]) > margin
+    if k == "polygon":
+        if dom["verts"] != l_shape()["verts"]:
+            raise ValueError("only the L-shape polygon has an input recipe")
+        return (_box_gap(x, [-1, -1], [1, 1]) > margin) & \
+            (_outside_box_gap(x, [0, -1], [1, 0]) > margin)
+    if k == "box_minus_ball":
+        c = np.asarray(dom["center"], dtype=np.float64)
+        return (_box_gap(x, dom["lo"], dom["hi"]) > margin) & \
+            (np.linalg.norm(x - c, axis=1) > dom["radius"] + margin)
+    raise ValueError(k)
+
+
+def bbox(dom):
+    k = dom["kind"]
+    d = dom["dim"]
+    if k == "ball":
+        c = np.asarray(dom["center"], dtype=np.float64)[:d]
+        return c - dom["radius"], c + dom["radius"]
+    if k == "polygon":
+        v = np.asarray(dom["verts"], dtype=np.float64)
+        return v.min(axis=0), v.max(axis=0)
+    return np.asarray(dom["lo"], dtype=np.float64), np.asarray(dom["hi"], dtype=np.float64)
+
+
+def sample_sites(dom, n, seed, margin):
+    """n points uniform in {x in D : dist(x, boundary) > margin}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi = bbox(dom)
+    out = []
+    have = 0
+    while have < n:
+        cand = lo + (hi - lo) * rng.random((max(64, 2 * (n - have)), dom["dim"]))
+        cand = cand[interior_with_margin(dom, cand, margin)]
+        out.append(cand)
+        have += len(cand)
+    return np.concatenate(out)[:n]
+
+
+# --------------------------------------------------------- boundary nodes
+
+
+def circle_nodes(p, center=(0.0, 0.0), radius=1.0):
+    th = 2.0 * np.pi * np.arange(p) / p
+    return np.stack([center[0] + radius * np.cos(th), center[1] + radius * np.sin(th)], axis=1)
+
+
+def square_nodes(per_edge, lo=(0.0, 0.0), hi=(1.0, 1.0)):
+    t = (np.arange(per_edge) + 0.5) / per_edge
+    x0, y0 = lo
+    x1, y1 = hi
+    bottom = np.stack([x0 + (x1 - x0) * t, np.full(per_edge, y0)], axis=1)
+    right = np.stack([np.full(per_edge, x1), y0 + (y1 - y0) * t], axis=1)
+    top = np.stack([x1 - (x1 - x0) * t, np.full(per_edge, y1)], axis=1)
+    left = np.stack([np.full(per_edge, x0), y1 - (y1 - y0) * t], axis=1)
+    return np.concatenate([bottom, right, top, left])
+
+
+def fibonacci_sphere(p, center=(0.0, 0.0, 0.0), radius=1.0):
+    k = np.arange(p)
+    z = 1.0 - (2.0 * k + 1.0) / p
+    ph = k * np.pi * (3.0 - np.sqrt(5.0))
+    s = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    pts = np.stack([s * np.cos(ph), s * np.sin(ph), z], axis=1)
+    return np.asarray(center) + radius * pts
+
+
+def polygon_nodes(verts, p):
+    """p nodes equispaced by arc length (midpoint offset) along a closed polygon."""
+    v = np.asarray(verts, dtype=np.float64)
+    seg = np.roll(v, -1, axis=0) - v
+    L = np.linalg.norm(seg, axis=1)
+    cum = np.concatenate([[0.0], np.cumsum(L)])
+    s = (np.arange(p) + 0.5) * cum[-1] / p
+    e = np.searchsorted(cum, s, side="right") - 1
+    t = (s - cum[e]) / L[e]
+    return v[e] + t[:, None] * seg[e]
+
+
+def cube_face_nodes(per_side, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+    t = (np.arange(per_side) + 0.5) / per_side
+    a, b = np.meshgrid(t, t, indexing="ij")
+    a = a.ravel()
+    b = b.ravel()
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    faces = []
+    for ax in range(3):
+        o = [q for q in range(3) if q != ax]
+        for side in (lo[ax], hi[ax]):
+            pts = np.empty((len(a), 3))
+            pts[:, ax] = side
+            pts[:, o[0]] = lo[o[0]] + (hi[o[0]] - lo[o[0]]) * a
+            pts[:, o[1]] = lo[o[1]] + (hi[o[1]] - lo[o[1]]) * b
+            faces.append(pts)
+    return np.concatenate(faces)
+
+
+# --------------------------------------------------- the paper's layouts
+
+
+def paper_disk_layout():
+    """Rings r_k = (k - 1/2)/10, 6k - 3 equispaced points each, k = 1..10
+    (n = 300), and 60 boundary nodes."""
+    pts = []
+    for k in range(1, 11):
+        nk = 6 * k - 3
+        r = (k - 0.5) / 10.0
+        th = 2.0 * np.pi * np.arange(nk) / nk
+        pts.append(np.stack([r * np.cos(th), r * np.sin(th)], axis=1))
+    return np.concatenate(pts), circle_nodes(60)
+
+
+def paper_square_layout():
+    """20 x 20 cell centres of the unit square, 20 boundary nodes per edge."""
+    g = (np.arange(20) + 0.5) / 20.0
+    sites = np.stack(np.meshgrid(g, g, indexing="ij"), axis=-1).reshape(-1, 2)
+    return sites, square_nodes(20)
+
+
+# ------------------------------------------------------- configurations
+
+
+def config(name, seed=20260807):
+    """The benchmark configurations (sizes and seeds); returns a dict with
+    domain, sites, bnodes, walks, eps, precision and a label."""
+    if name == "disk64":
+        dom = unit_disk()
+        eps = 1e-3
+        sites = sample_sites(dom, 64, seed, 10 * eps)
+        return dict(name=name, domain=dom, sites=sites, bnodes=circle_nodes(64), walks=2000,
+                    eps=eps, precision="f64", seed=seed,
+                    label="2D unit disk, 64 sites, 64 boundary nodes, 2000 walks/site, eps 1e-3, FP64")
+    if name == "square1024":
+        dom = unit_square()
+        eps = 1e-4
+        sites = sample_sites(dom, 1024, seed, 10 * eps)
+        return dict(name=name, domain=dom, sites=sites, bnodes=square_nodes(64), walks=10000,
+                    eps=eps, precision="f32", seed=seed,
+                    label="2D unit square, 1024 sites, 256 boundary nodes, 1e4 walks/site, eps 1e-4, FP32")
+    if name == "ball4096":
+        dom = unit_ball()
+        eps = 1e-4
+        sites = sample_sites(dom, 4096, seed, 10 * eps)
+        return dict(name=name, domain=dom, sites=sites, bnodes=fibonacci_sphere(1024), walks=10000,
+                    eps=eps, precision="f32", seed=seed,
+                    label="3D unit ball, 4096 sites, 1024 Fibonacci boundary nodes, 1e4 walks/site, eps 1e-4")
+    if name.startswith("lshape"):
+        n = int(name[len("lshape"):])
+        dom = l_shape()
+        eps = 1e-4
+        sites = sample_sites(dom, n, seed, 10 * eps)
+        return dict(name=name, domain=dom, sites=sites, bnodes=polygon_nodes(dom["verts"], n // 4),
+                    walks=10000, eps=eps, precision="f32", seed=seed,
+                    label=f"2D L-shape, {n} sites, {n // 4} boundary nodes, 1e4 walks/site, eps 1e-4")
+    if name == "cubeball32768":
+        dom = cube_minus_ball()
+        eps = 1e-5
+        sites = sample_sites(dom, 32768, seed, 10 * eps)
+        bn = np.concatenate([cube_face_nodes(34), fibonacci_sphere(1256, dom["center"], dom["radius"])])
+        return dict(name=name, domain=dom, sites=sites, bnodes=bn, walks=100000, eps=eps,
+                    precision="f32", seed=seed,
+                    label="3D unit cube minus ball r=0.3, 32768 sites, 8192 boundary nodes, 1e5 walks/site, eps 1e-5")
+    raise KeyError(name)
+
+
+# ------------------------------------------- manufactured problem data
+
+
+def smooth_field(seed, dim, terms=8, max_freq=3.0, scale=0.5):
+    """A seeded smooth function sum_k a_k cos(w_k . x + phi_k) with its
+    gradient and Laplacian in closed form.  Returns (f, grad, lap)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.normal(0.0, scale, terms)
+    w = rng.normal(0.0, 1.0, (terms, dim))
+    w *= (max_freq * rng.random(terms) ** (1.0 / dim) / np.linalg.norm(w, axis=1))[:, None]
+    ph = rng.uniform(0, 2 * np.pi, terms)
+
+    def val(x):
+        x = np.atleast_2d(x)
+        return np.cos(x @ w.T + ph) @ a
+
+    def grad(x):
+        x = np.atleast_2d(x)
+        return -(np.sin(x @ w.T + ph) * a) @ w
+
+    def lap(x):
+        x = np.atleast_2d(x)
+        return -np.cos(x @ w.T + ph) @ (a * (w * w).sum(axis=1))
+
+    return val, grad, lap
