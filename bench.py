@@ -1,0 +1,151 @@
+"""Benchmark: WoS toolbox build throughput on one MI355X.
+
+A step is one complete pass of the hot path over one batch of synthetic
+input: a toolbox build (cell weights lambda, the walks of every (site, walk)
+pair binned into A, B, H, K, normalisation) followed by its direct
+application to the boundary data g = x^2 - y^2 (u = A 0 + H g,
+grad u = B 0 + K g).  Each step uses a new seed.  `value` is walk-steps per
+second over the whole step, inputs resident in HBM.
+
+Workload (default): 2-D unit square, 1024 uniform interior sites, 256
+equispaced boundary nodes, 1e4 walks per site, eps = 1e-4, FP32 walker.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "WoS walk-steps/s (toolbox build)"
+MI355X_CUS = 256
+MI355X_CLOCK = 2.4e9
+LANE_OPS_PEAK = MI355X_CUS * 64 * MI355X_CLOCK          # non-packed FP32 lane-ops/s
+# Algorithmic lane-op budget of the walker (slots: full-rate op = 1,
+# transcendental / 32-bit integer multiply = 4), per walk-step and per walk.
+WALKER_BUDGET = {  # (C_step, C_walk) by workload geometry
+    "disk": (113, 450), "square": (113, 450), "lshape": (187, 450), "ball": (216, 700), "cubeball": (228, 700),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="square1024")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=2)
+    return ap.parse_args()
+
+
+def geometry_key(name):
+    for k in ("disk", "square", "lshape", "ball", "cubeball"):
+        if name.startswith(k):
+            return k
+    return "square"
+
+
+def cpu_baseline(cfg, rows):
+    """The oracle, as it stands, on a bounded sample: `rows` whole sites of the
+    same workload (all N walks each).  Rate in walk-steps/s."""
+    from oracle.walker import site_events, bin_site
+    t0 = time.perf_counter()
+    steps = 0
+    for i in range(rows):
+        ev = site_events(cfg["domain"], cfg["sites"][i], i, np.arange(cfg["walks"]), cfg["eps"], cfg["seed"])
+        bin_site(ev, cfg["sites"], cfg["bnodes"])
+        steps += int(ev.nsteps.sum())
+    dt = time.perf_counter() - t0
+    return {"value": steps / dt, "unit": "walk-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d of %d sites x %d walks (%d walk-steps, %.1f s), FP64 NumPy, one thread"
+                      % (rows, len(cfg["sites"]), cfg["walks"], steps, dt)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: the toolbox build shards by sites across GPUs "
+              "(see DESIGN.md), which this build does not launch; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_2608_07017_amd as P
+
+    cfg = W.config(a.workload)
+    prec = cfg["precision"]
+    tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], cfg["walks"], cfg["eps"], seed=cfg["seed"],
+                   precision=prec)
+    bn = cfg["bnodes"]
+    g = torch.tensor(bn[:, 0] ** 2 - bn[:, 1] ** 2, dtype=torch.float64, device="cuda")
+    zero = torch.zeros(len(cfg["sites"]), dtype=torch.float64, device="cuda")
+
+    def step(k):
+        tb.build(seed=cfg["seed"] + 1000 + k)
+        return tb.apply(zero, g)
+
+    for k in range(a.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        step(a.warmup + k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # walk-steps of the timed builds: every build is a different seed, so the
+    # counts differ slightly; re-run the per-step statistics pass after timing
+    tb.set_timing(True)
+    kernel_ms = []
+    walk_steps = []
+    walks = []
+    for k in range(a.steps):
+        step(a.warmup + k)
+        t = tb.timings()
+        inf = tb.info()
+        kernel_ms.append(t["walker_ms"])
+        walk_steps.append(inf["walk_steps"])
+        walks.append(inf["walks"])
+    total_steps = float(np.sum(walk_steps))
+    elapsed = t1 - t0
+    value = total_steps / elapsed
+    u, gu = step(0)
+    torch.cuda.synchronize()
+    exact = cfg["sites"][:, 0] ** 2 - cfg["sites"][:, 1] ** 2
+    herr = float(np.sqrt(np.mean((u.cpu().numpy() - exact) ** 2)))
+
+    c_step, c_walk = WALKER_BUDGET[geometry_key(a.workload)]
+    mean_steps = total_steps / a.steps
+    mean_walks = float(np.mean(walks))
+    walker_s = float(np.mean(kernel_ms)) * 1e-3
+    alg_ops = c_step * mean_steps + c_walk * mean_walks
+    achieved = alg_ops / walker_s / 1e12
+    peak = LANE_OPS_PEAK / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": "walk-steps/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * elapsed / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": cfg["label"], "sites": len(cfg["sites"]), "bnodes": len(bn),
+                   "walks_per_site": cfg["walks"], "eps": cfg["eps"], "seed": cfg["seed"]},
+        "walker": {"kernel_ms": float(np.mean(kernel_ms)), "walk_steps_per_s": mean_steps / walker_s,
+                   "walk_steps_per_build": mean_steps, "walks_per_build": mean_walks,
+                   "harmonic_extension_rms_err": herr},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "budget": {"per_walk_step": c_step, "per_walk": c_walk}},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * wos.h -- C ABI of libwos, the MI355X (gfx950) Walk-on-Spheres operator
+ * toolbox.
+ *
+ * The library builds, on one GPU, the "Laplacian Operator Toolbox" of
+ * Cimpean, Grecu & Zarnescu, "Extended Walk-on-Spheres Algorithm for Linear
+ * and Nonlinear Elliptic Problems of Divergence-type" (eq. LOT): for interior
+ * sites x_1..x_n (the W- and V-centres, n = m) and boundary nodes
+ * z_1..z_p (the Gamma-centres) of a domain D in R^d (d = 2, 3),
+ *
+ *   A   (n x m)     estimates U = (-Lap/2)^{-1} binned over the Voronoi
+ *                   cells of the sites          (eq. Estimator_A),
+ *   B   (d x n x m) estimates grad U            (eq. Estimator_B),
+ *   H   (n x p)     estimates the harmonic extension binned over the
+ *                   Voronoi cells of the nodes   (eq. Estimator_H),
+ *   K   (d x n x p) estimates grad H            (eq. Estimator_K),
+ *
+ * by the one-pass walk of Alg. "WoS-LOT" in the refined form of Rem.
+ * "MC_no_singular", and reduces Dirichlet problems to the system for the
+ * unknown source q with u = A q + H g (eq. linear_q and the boxed
+ * reconstruction of Sec. "Second order linear elliptic PDEs").
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns a wos_status; a message for the last error of
+ *     the calling thread is returned by wos_last_error().  No C++ exception
+ *     crosses this interface.
+ *   - Arrays are row-major and dense.  "host" pointers are read during the
+ *     call only; "device" pointers must be GPU memory of the current device
+ *     and stay valid until the work queued on `stream` has completed.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Functions that
+ *     take a stream only queue work on it and return; the caller
+ *     synchronises.  Device-side faults surface as WOS_EDEVICE from the next
+ *     call that synchronises.
+ *   - The caller owns every buffer it passes; a wos_toolbox owns its own
+ *     device memory until wos_toolbox_free().
+ */
+#ifndef WOS_H
+#define WOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WOS_OK = 0,
+  WOS_EINVAL = -1,    /* null pointer, bad size, NaN, unsupported option      */
+  WOS_EDOMAIN = -2,   /* a site outside D or at zero distance from the boundary */
+  WOS_ENOMEM = -3,    /* device or host allocation failed                     */
+  WOS_EDEVICE = -4,   /* a HIP call or kernel failed                          */
+  WOS_ENOTCONV = -5,  /* an iteration stopped at its cap before its tolerance  */
+  WOS_EBUSY = -6,
+  WOS_ENOTIMPL = -7
+} wos_status;
+
+/* Domains (the distance to the boundary r(x) of eq. r and an inside test). */
+typedef enum {
+  WOS_BALL = 1,           /* disk (dim 2) or ball (dim 3): center, radius     */
+  WOS_BOX = 2,            /* [lo, hi]                                          */
+  WOS_POLYGON = 3,        /* dim 2, simple polygon, counter-clockwise vertices */
+  WOS_BOX_MINUS_BALL = 4  /* dim 3: [lo, hi] minus the closed ball (center, radius) */
+} wos_domain_kind;
+
+typedef struct {
+  int32_t kind;          /* wos_domain_kind                          */
+  int32_t dim;           /* 2 or 3                                   */
+  double center[3];
+  double radius;
+  double lo[3];
+  double hi[3];
+  int32_t nvert;         /* polygon: number of vertices, 3 .. 64     */
+  const double* verts;   /* polygon: host, nvert x 2                 */
+} wos_domain;
+
+typedef enum { WOS_F32 = 0, WOS_F64 = 1 } wos_precision;
+
+typedef struct {
+  int64_t walks_per_site;   /* N >= 1 (eqs. Estimator_A..K)                      */
+  double eps;               /* stop at the first k >= 1 with r(X_k) < eps; > 0
+                               unless fixed_M > 0                                 */
+  int32_t max_steps;        /* cap on chain tallies per walk; 0 -> 10000          */
+  int32_t fixed_M;          /* > 0: the paper's rule, exactly M chain steps,
+                               eps ignored                                        */
+  uint64_t seed;            /* Philox4x32-10 key                                  */
+  int32_t precision;        /* wos_precision of the walk arithmetic and tallies   */
+  int64_t volume_samples;   /* candidate points for lambda_i; 0 -> 2^24           */
+  int32_t walks_per_item;   /* walks one workgroup takes per site; 0 -> automatic */
+  int32_t regen_threshold;  /* idle lanes per wavefront that trigger new walks;
+                               0 -> automatic (1 .. 64)                            */
+} wos_build_opts;
+
+typedef struct wos_toolbox wos_toolbox;
+
+/* Creates a toolbox: validates the inputs, builds the nearest-centre grids
+ * for the sites and the boundary nodes, and allocates the device storage.
+ * Queues no walk.
+ *   dom     host; sites host n x dim (double); bnodes host p x dim (double).
+ *   Every site must be inside D with r(x) > 0 (else WOS_EDOMAIN).
+ *   opts    host; copied.
+ *   out     receives the toolbox (NULL on error).                              */
+wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_t n,
+                              const double* bnodes, int32_t p, const wos_build_opts* opts,
+                              wos_toolbox** out);
+
+/* Queues one complete toolbox build on `stream`: the cell weights lambda_i,
+ * the walks of Alg. "WoS-LOT" for all (site, walk) pairs, and the
+ * normalisation by N.  `seed` replaces opts.seed for this build.  Previous
+ * contents are overwritten.  Asynchronous.                                      */
+wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream);
+
+/* create + build + synchronise: the one-call form
+ * build_toolbox(domain, sites, bnodes, walks, eps, seed).                       */
+wos_status wos_build_toolbox(const wos_domain* dom, const double* sites, int32_t n,
+                             const double* bnodes, int32_t p, const wos_build_opts* opts,
+                             void* stream, wos_toolbox** out);
+
+typedef struct {
+  int32_t dim, n, m, p, precision;
+  int64_t walks_per_site;
+  /* statistics of the last completed build (valid after the stream that ran
+     it has been synchronised) */
+  uint64_t walk_steps;      /* k = 0 tallies plus chain tallies, all walks */
+  uint64_t walks;           /* walks simulated                             */
+  uint64_t capped_walks;    /* walks stopped by max_steps                  */
+  uint64_t max_walk_steps;  /* longest walk                                */
+  uint64_t volume_inside;   /* volume points inside D                      */
+  size_t device_bytes;      /* device memory held by the toolbox           */
+} wos_toolbox_info;
+
+/* Fills *info.  Synchronises the toolbox's last build stream.                  */
+wos_status wos_toolbox_get_info(const wos_toolbox* tb, wos_toolbox_info* info);
+
+typedef enum {
+  WOS_EXPORT_A = 0,       /* n x m,      toolbox precision             */
+  WOS_EXPORT_B = 1,       /* d x n x m,  toolbox precision             */
+  WOS_EXPORT_H = 2,       /* n x p,      toolbox precision (counts / N)  */
+  WOS_EXPORT_K = 3,       /* d x n x p,  toolbox precision             */
+  WOS_EXPORT_HCOUNT = 4,  /* n x p,      uint32 exit counts            */
+  WOS_EXPORT_LAMBDA = 5,  /* n,          double lambda_i               */
+  WOS_EXPORT_VCOUNT = 6   /* n,          uint64 volume-point counts    */
+} wos_export_what;
+
+/* Copies one toolbox array into dst (device if dst_is_device, else host),
+ * ordered on `stream`.  `bytes` must equal the array's size.  A host copy
+ * synchronises the stream.                                                     */
+wos_status wos_toolbox_export(const wos_toolbox* tb, int32_t what, void* dst, size_t bytes,
+                              int32_t dst_is_device, void* stream);
+
+/* Direct application with a known source (Sec. "Matrix estimators" and the
+ * boxed reconstruction):  u = A fbar + H g,  grad_u = B fbar + K g,
+ * i.e. the solution of -(1/2) Lap u = f, u = g with fbar_j = f(y_j).
+ *   fbar device double (m); g device double (p); u device double (n);
+ *   grad_u device double (d x n) or NULL.  Asynchronous.                        */
+wos_status wos_apply(const wos_toolbox* tb, const double* fbar, const double* g, double* u,
+                     double* grad_u, void* stream);
+
+/* Kernel timing.  When enabled, wos_toolbox_build records HIP events on its
+ * stream around the volume kernel, the walker kernel and the normalisation;
+ * wos_toolbox_get_timings synchronises and returns their durations in
+ * milliseconds for the last build (walker first).  Timing adds four event
+ * records per build and is off by default.                                     */
+wos_status wos_toolbox_set_timing(wos_toolbox* tb, int32_t enable);
+wos_status wos_toolbox_get_timings(const wos_toolbox* tb, double* ms_walker, double* ms_volume,
+                                   double* ms_finalize);
+
+void wos_toolbox_free(wos_toolbox* tb);
+
+/* Message for the last failing call of this thread ("" if none).             */
+const char* wos_last_error(void);
+
+/* Library version string. */
+const char* wos_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WOS_H */

@@ -1,0 +1,145 @@
+"""MI355X-native Walk-on-Spheres operator toolbox (Python face of libwos).
+
+    tb = Toolbox(domain, sites, bnodes, walks=10_000, eps=1e-4, seed=1)
+    tb.build()                      # queued on torch's current stream
+    A = tb.export("A")              # device tensors
+    u, grad_u = tb.apply(fbar, g)   # u = A fbar + H g, grad u = B fbar + K g
+
+`domain` is a dict {"kind": "ball"|"box"|"polygon"|"box_minus_ball",
+"dim", "center", "radius", "lo", "hi", "verts"}.  All arithmetic runs in the
+HIP kernels of libwos.so; this module marshals arguments.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import (EXPORTS, KINDS, PRECISION, WosBuildOpts, WosDomain, WosError, WosToolboxInfo,
+                   check, lib)
+
+__all__ = ["Toolbox", "build_toolbox", "WosError", "lib"]
+
+
+def _stream_handle(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _domain_struct(domain):
+    d = WosDomain()
+    d.kind = KINDS[domain["kind"]]
+    d.dim = int(domain["dim"])
+    for key in ("center", "lo", "hi"):
+        if key in domain:
+            v = list(domain[key]) + [0.0] * (3 - len(domain[key]))
+            getattr(d, key)[:] = [float(t) for t in v]
+    d.radius = float(domain.get("radius", 0.0))
+    keep = None
+    if "verts" in domain:
+        keep = np.ascontiguousarray(np.asarray(domain["verts"], dtype=np.float64))
+        d.nvert = keep.shape[0]
+        d.verts = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return d, keep
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Toolbox:
+    """A resident toolbox {x, z, A, B, H, K, lambda} on the current GPU."""
+
+    def __init__(self, domain, sites, bnodes, walks, eps, seed=0, precision="f32", max_steps=0,
+                 fixed_M=0, volume_samples=0, walks_per_item=0, regen_threshold=0):
+        self.domain = domain
+        self.sites = np.ascontiguousarray(np.asarray(sites, dtype=np.float64))
+        self.bnodes = np.ascontiguousarray(np.asarray(bnodes, dtype=np.float64))
+        self.dim = int(domain["dim"])
+        self.n = self.sites.shape[0]
+        self.p = self.bnodes.shape[0]
+        self.seed = int(seed)
+        self.precision = precision
+        self.walks = int(walks)
+        dom, keep = _domain_struct(domain)
+        opts = WosBuildOpts(walks_per_site=int(walks), eps=float(eps), max_steps=int(max_steps),
+                            fixed_M=int(fixed_M), seed=self.seed, precision=PRECISION[precision],
+                            volume_samples=int(volume_samples), walks_per_item=int(walks_per_item),
+                            regen_threshold=int(regen_threshold))
+        h = ctypes.c_void_p()
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(lib().wos_toolbox_create(ctypes.byref(dom), self.sites.ctypes.data_as(dp), self.n,
+                                       self.bnodes.ctypes.data_as(dp), self.p, ctypes.byref(opts),
+                                       ctypes.byref(h)))
+        del keep
+        self._h = h
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+
+    # -------------------------------------------------------------- build
+    def build(self, seed=None, stream=None):
+        """Queue a full build (lambda, walks, normalisation) on the stream."""
+        s = self.seed if seed is None else int(seed)
+        check(lib().wos_toolbox_build(self._h, s, _stream_handle(stream)))
+        return self
+
+    def set_timing(self, enable=True):
+        check(lib().wos_toolbox_set_timing(self._h, 1 if enable else 0))
+
+    def timings(self):
+        """Kernel durations (ms) of the last build, from HIP events on its stream."""
+        w, v, f = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        check(lib().wos_toolbox_get_timings(self._h, ctypes.byref(w), ctypes.byref(v), ctypes.byref(f)))
+        return {"walker_ms": w.value, "volume_ms": v.value, "finalize_ms": f.value}
+
+    def info(self):
+        inf = WosToolboxInfo()
+        check(lib().wos_toolbox_get_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in inf._fields_}
+
+    # ------------------------------------------------------------- export
+    def _shape(self, what):
+        n, p, d = self.n, self.p, self.dim
+        return {"A": ((n, n), self.dtype), "B": ((d, n, n), self.dtype), "H": ((n, p), self.dtype),
+                "K": ((d, n, p), self.dtype), "Hcount": ((n, p), torch.int32),
+                "lambda": ((n,), torch.float64), "vcount": ((n,), torch.int64)}[what]
+
+    def export(self, what, stream=None):
+        """A copy of one toolbox array as a device tensor (Hcount as int32
+        holding the uint32 counts)."""
+        shape, dt = self._shape(what)
+        out = torch.empty(shape, dtype=dt, device="cuda")
+        check(lib().wos_toolbox_export(self._h, EXPORTS[what], _dptr(out),
+                                       out.numel() * out.element_size(), 1, _stream_handle(stream)))
+        return out
+
+    # -------------------------------------------------------------- apply
+    def apply(self, fbar, g, grad=True, stream=None):
+        """u = A fbar + H g and grad u = B fbar + K g (device float64)."""
+        fbar = torch.as_tensor(fbar, dtype=torch.float64, device="cuda").contiguous()
+        g = torch.as_tensor(g, dtype=torch.float64, device="cuda").contiguous()
+        if fbar.numel() != self.n or g.numel() != self.p:
+            raise ValueError("fbar must have n entries and g p entries")
+        u = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        gu = torch.empty((self.dim, self.n), dtype=torch.float64, device="cuda") if grad else None
+        check(lib().wos_apply(self._h, _dptr(fbar), _dptr(g), _dptr(u),
+                              _dptr(gu) if grad else ctypes.c_void_p(0), _stream_handle(stream)))
+        return u, gu
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().wos_toolbox_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_toolbox(domain, sites, bnodes, walks, eps, seed, **kw):
+    """build_toolbox(domain, sites, bnodes, walks, eps, seed): create, build
+    and wait."""
+    tb = Toolbox(domain, sites, bnodes, walks, eps, seed=seed, **kw)
+    tb.build()
+    torch.cuda.current_stream().synchronize()
+    return tb

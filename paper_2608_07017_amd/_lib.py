@@ -1,0 +1,93 @@
+"""ctypes binding of libwos.so (argument marshalling only).
+
+Device buffers are torch tensors on the current HIP device; the stream is
+torch's current stream.  Every computation happens in the library's
+kernels; nothing here falls back to a CPU path: if the library is missing
+the import fails.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwos.so")
+
+WOS_OK = 0
+STATUS = {0: "WOS_OK", -1: "WOS_EINVAL", -2: "WOS_EDOMAIN", -3: "WOS_ENOMEM", -4: "WOS_EDEVICE",
+          -5: "WOS_ENOTCONV", -6: "WOS_EBUSY", -7: "WOS_ENOTIMPL"}
+KINDS = {"ball": 1, "box": 2, "polygon": 3, "box_minus_ball": 4}
+PRECISION = {"f32": 0, "f64": 1}
+EXPORTS = {"A": 0, "B": 1, "H": 2, "K": 3, "Hcount": 4, "lambda": 5, "vcount": 6}
+
+
+class WosDomain(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("center", ctypes.c_double * 3), ("radius", ctypes.c_double),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("nvert", ctypes.c_int32), ("verts", ctypes.POINTER(ctypes.c_double))]
+
+
+class WosBuildOpts(ctypes.Structure):
+    _fields_ = [("walks_per_site", ctypes.c_int64), ("eps", ctypes.c_double),
+                ("max_steps", ctypes.c_int32), ("fixed_M", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
+                ("volume_samples", ctypes.c_int64), ("walks_per_item", ctypes.c_int32),
+                ("regen_threshold", ctypes.c_int32)]
+
+
+class WosToolboxInfo(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("p", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("walks_per_site", ctypes.c_int64), ("walk_steps", ctypes.c_uint64),
+                ("walks", ctypes.c_uint64), ("capped_walks", ctypes.c_uint64),
+                ("max_walk_steps", ctypes.c_uint64), ("volume_inside", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_size_t)]
+
+
+# every symbol include/wos.h declares, with its ctypes signature
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "wos_toolbox_create": (ctypes.c_int, [ctypes.POINTER(WosDomain), _D, ctypes.c_int32, _D, ctypes.c_int32,
+                                          ctypes.POINTER(WosBuildOpts), ctypes.POINTER(_P)]),
+    "wos_toolbox_build": (ctypes.c_int, [_P, ctypes.c_uint64, _P]),
+    "wos_build_toolbox": (ctypes.c_int, [ctypes.POINTER(WosDomain), _D, ctypes.c_int32, _D, ctypes.c_int32,
+                                         ctypes.POINTER(WosBuildOpts), _P, ctypes.POINTER(_P)]),
+    "wos_toolbox_get_info": (ctypes.c_int, [_P, ctypes.POINTER(WosToolboxInfo)]),
+    "wos_toolbox_export": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_size_t, ctypes.c_int32, _P]),
+    "wos_apply": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "wos_toolbox_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "wos_toolbox_get_timings": (ctypes.c_int, [_P, _D, _D, _D]),
+    "wos_toolbox_free": (None, [_P]),
+    "wos_last_error": (ctypes.c_char_p, []),
+    "wos_version": (ctypes.c_char_p, []),
+}
+
+
+class WosError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if libwos.so has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libwos.so not built: run `python -m paper_2608_07017_amd.build` "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != WOS_OK:
+        raise WosError(status, lib().wos_last_error().decode())

@@ -1,0 +1,731 @@
+// C ABI of libwos (declared in include/wos.h): validation, device storage of
+// a toolbox, and the order of the kernels of one build.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "grid.hpp"
+#include "wos_kernels.hpp"
+
+using namespace wos;
+
+namespace {
+
+thread_local std::string g_err;
+
+wos_status fail(wos_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define WOS_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? WOS_ENOMEM : WOS_EDEVICE, "%s: %s (%s:%d)", \
+                  #call, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+  } while (0)
+
+// ------------------------------------------------------------ host geometry
+// FP64 distance to the boundary and inside test, used to validate sites.
+struct HostDomain {
+  int kind = 0, dim = 0;
+  double c[3] = {0, 0, 0}, rad = 0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  std::vector<double> verts;
+};
+
+double seg_dist(const double* x, const double* a, const double* b) {
+  const double ex = b[0] - a[0], ey = b[1] - a[1];
+  double t = ((x[0] - a[0]) * ex + (x[1] - a[1]) * ey) / (ex * ex + ey * ey);
+  t = std::min(1.0, std::max(0.0, t));
+  const double qx = x[0] - a[0] - t * ex, qy = x[1] - a[1] - t * ey;
+  return std::sqrt(qx * qx + qy * qy);
+}
+
+double host_distance(const HostDomain& d, const double* x) {
+  switch (d.kind) {
+    case WOS_BALL: {
+      double s = 0;
+      for (int a = 0; a < d.dim; ++a) s += (x[a] - d.c[a]) * (x[a] - d.c[a]);
+      return d.rad - std::sqrt(s);
+    }
+    case WOS_BOX: {
+      double r = 1e300;
+      for (int a = 0; a < d.dim; ++a) r = std::min(r, std::min(x[a] - d.lo[a], d.hi[a] - x[a]));
+      return r;
+    }
+    case WOS_POLYGON: {
+      const int nv = (int)d.verts.size() / 2;
+      double r = 1e300;
+      for (int e = 0; e < nv; ++e) r = std::min(r, seg_dist(x, &d.verts[2 * e], &d.verts[2 * ((e + 1) % nv)]));
+      return r;
+    }
+    default: {
+      double r = 1e300, s = 0;
+      for (int a = 0; a < d.dim; ++a) {
+        r = std::min(r, std::min(x[a] - d.lo[a], d.hi[a] - x[a]));
+        s += (x[a] - d.c[a]) * (x[a] - d.c[a]);
+      }
+      return std::min(r, std::sqrt(s) - d.rad);
+    }
+  }
+}
+
+bool host_inside(const HostDomain& d, const double* x) {
+  switch (d.kind) {
+    case WOS_BALL: {
+      double s = 0;
+      for (int a = 0; a < d.dim; ++a) s += (x[a] - d.c[a]) * (x[a] - d.c[a]);
+      return s < d.rad * d.rad;
+    }
+    case WOS_BOX: {
+      for (int a = 0; a < d.dim; ++a)
+        if (!(x[a] > d.lo[a] && x[a] < d.hi[a])) return false;
+      return true;
+    }
+    case WOS_POLYGON: {
+      const int nv = (int)d.verts.size() / 2;
+      bool odd = false;
+      for (int e = 0; e < nv; ++e) {
+        const double* a = &d.verts[2 * e];
+        const double* b = &d.verts[2 * ((e + 1) % nv)];
+        if ((a[1] > x[1]) != (b[1] > x[1])) {
+          const double xint = a[0] + (x[1] - a[1]) * (b[0] - a[0]) / (b[1] - a[1]);
+          if (x[0] < xint) odd = !odd;
+        }
+      }
+      return odd;
+    }
+    default: {
+      double s = 0;
+      for (int a = 0; a < d.dim; ++a) {
+        if (!(x[a] > d.lo[a] && x[a] < d.hi[a])) return false;
+        s += (x[a] - d.c[a]) * (x[a] - d.c[a]);
+      }
+      return s > d.rad * d.rad;
+    }
+  }
+}
+
+void host_bbox(const HostDomain& d, double* lo, double* hi) {
+  for (int a = 0; a < 3; ++a) lo[a] = hi[a] = 0;
+  switch (d.kind) {
+    case WOS_BALL:
+      for (int a = 0; a < d.dim; ++a) {
+        lo[a] = d.c[a] - d.rad;
+        hi[a] = d.c[a] + d.rad;
+      }
+      break;
+    case WOS_POLYGON: {
+      lo[0] = lo[1] = 1e300;
+      hi[0] = hi[1] = -1e300;
+      for (size_t v = 0; v < d.verts.size(); v += 2)
+        for (int a = 0; a < 2; ++a) {
+          lo[a] = std::min(lo[a], d.verts[v + a]);
+          hi[a] = std::max(hi[a], d.verts[v + a]);
+        }
+      break;
+    }
+    default:
+      for (int a = 0; a < d.dim; ++a) {
+        lo[a] = d.lo[a];
+        hi[a] = d.hi[a];
+      }
+  }
+}
+
+// boundary measure: length (d = 2) or area (d = 3)
+double host_boundary_measure(const HostDomain& d) {
+  const double pi = 3.14159265358979323846;
+  switch (d.kind) {
+    case WOS_BALL: return d.dim == 2 ? 2 * pi * d.rad : 4 * pi * d.rad * d.rad;
+    case WOS_BOX: {
+      if (d.dim == 2) return 2 * ((d.hi[0] - d.lo[0]) + (d.hi[1] - d.lo[1]));
+      const double e0 = d.hi[0] - d.lo[0], e1 = d.hi[1] - d.lo[1], e2 = d.hi[2] - d.lo[2];
+      return 2 * (e0 * e1 + e1 * e2 + e0 * e2);
+    }
+    case WOS_POLYGON: {
+      const int nv = (int)d.verts.size() / 2;
+      double L = 0;
+      for (int e = 0; e < nv; ++e) {
+        const double* a = &d.verts[2 * e];
+        const double* b = &d.verts[2 * ((e + 1) % nv)];
+        L += std::hypot(b[0] - a[0], b[1] - a[1]);
+      }
+      return L;
+    }
+    default: {
+      const double e0 = d.hi[0] - d.lo[0], e1 = d.hi[1] - d.lo[1], e2 = d.hi[2] - d.lo[2];
+      return 2 * (e0 * e1 + e1 * e2 + e0 * e2) + 4 * pi * d.rad * d.rad;
+    }
+  }
+}
+
+template <typename T>
+DomainDev<T> to_dev(const HostDomain& d) {
+  DomainDev<T> o{};
+  o.kind = d.kind;
+  o.dim = d.dim;
+  for (int a = 0; a < 3; ++a) {
+    o.c[a] = (T)d.c[a];
+    o.lo[a] = (T)d.lo[a];
+    o.hi[a] = (T)d.hi[a];
+  }
+  o.rad = (T)d.rad;
+  return o;
+}
+
+struct DevGrid {
+  int n[3] = {1, 1, 1};
+  double lo[3] = {0, 0, 0}, h[3] = {1, 1, 1};
+  int* cell = nullptr;
+  int* list = nullptr;
+  size_t ncell = 0, nlist = 0;
+  double frac_single = 1, mean_multi = 1;
+  int max_cand = 1;
+};
+
+template <typename T>
+GridDev<T> view(const DevGrid& g, const void* pts) {
+  GridDev<T> v{};
+  for (int a = 0; a < 3; ++a) {
+    v.n[a] = g.n[a];
+    v.lo[a] = (T)g.lo[a];
+    v.inv_h[a] = (T)(1.0 / g.h[a]);
+  }
+  v.cell = g.cell;
+  v.list = g.list;
+  v.pts = static_cast<const T*>(pts);
+  return v;
+}
+
+}  // namespace
+
+struct wos_toolbox {
+  HostDomain dom;
+  wos_build_opts opts{};
+  int dim = 0, n = 0, m = 0, p = 0;
+  bool f64 = false;
+  int items_per_site = 1, walks_per_item = 1, regen_T = 32;
+  std::vector<double> sites, bnodes;
+  // device
+  DevGrid gv, gg;
+  void* d_sites_f32 = nullptr;   // padded centres
+  void* d_sites_f64 = nullptr;
+  void* d_bnodes = nullptr;      // toolbox precision, padded
+  void* d_segs = nullptr;        // toolbox precision, 5 per edge
+  double* d_verts = nullptr;
+  void* d_A = nullptr;
+  void* d_B = nullptr;
+  void* d_K = nullptr;
+  void* d_H = nullptr;
+  uint32_t* d_Hc = nullptr;
+  unsigned long long* d_vcount = nullptr;
+  unsigned long long* d_stats = nullptr;  // [0..3] walker, [4] volume inside
+  double* d_lambda = nullptr;
+  size_t bytes = 0;
+  hipStream_t last_stream = nullptr;
+  bool built = false;
+  bool timing = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+size_t tsize(const wos_toolbox* tb) { return tb->f64 ? 8 : 4; }
+
+wos_status dev_alloc(wos_toolbox* tb, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(WOS_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+  }
+  tb->bytes += bytes;
+  return WOS_OK;
+}
+
+template <typename T>
+std::vector<T> padded(const std::vector<double>& pts, int count, int dim) {
+  const int st = dim == 2 ? 2 : 4;
+  std::vector<T> o((size_t)count * st, T(0));
+  for (int j = 0; j < count; ++j)
+    for (int a = 0; a < dim; ++a) o[(size_t)j * st + a] = (T)pts[(size_t)j * dim + a];
+  return o;
+}
+
+wos_status upload(wos_toolbox* tb, void** dst, const void* src, size_t bytes) {
+  wos_status s = dev_alloc(tb, dst, bytes);
+  if (s != WOS_OK) return s;
+  WOS_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  return WOS_OK;
+}
+
+wos_status upload_grid(wos_toolbox* tb, const GridHost& h, DevGrid* g) {
+  for (int a = 0; a < 3; ++a) {
+    g->n[a] = h.n[a];
+    g->lo[a] = h.lo[a];
+    g->h[a] = h.h[a];
+  }
+  g->ncell = h.cell.size();
+  g->nlist = h.list.size();
+  g->frac_single = h.frac_single;
+  g->mean_multi = h.mean_multi;
+  g->max_cand = h.max_cand;
+  wos_status s = upload(tb, (void**)&g->cell, h.cell.data(), h.cell.size() * sizeof(int));
+  if (s != WOS_OK) return s;
+  return upload(tb, (void**)&g->list, h.list.data(), h.list.size() * sizeof(int));
+}
+
+void release(wos_toolbox* tb) {
+  for (auto& e : tb->ev)
+    if (e) {
+      (void)hipEventDestroy(e);
+      e = nullptr;
+    }
+  void* ptrs[] = {tb->gv.cell, tb->gv.list, tb->gg.cell, tb->gg.list, tb->d_sites_f32,
+                  tb->d_sites_f64, tb->d_bnodes, tb->d_segs, tb->d_verts, tb->d_A, tb->d_B,
+                  tb->d_K, tb->d_H, tb->d_Hc, tb->d_vcount, tb->d_stats, tb->d_lambda};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+}
+
+bool finite3(const double* v, int k) {
+  for (int i = 0; i < k; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wos_last_error(void) { return g_err.c_str(); }
+
+const char* wos_version(void) { return "libwos 0.1 (gfx950)"; }
+
+wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_t n,
+                              const double* bnodes, int32_t p, const wos_build_opts* opts,
+                              wos_toolbox** out) {
+  g_err.clear();
+  if (!out) return fail(WOS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!dom || !sites || !bnodes || !opts) return fail(WOS_EINVAL, "NULL argument");
+  if (dom->dim != 2 && dom->dim != 3) return fail(WOS_EINVAL, "dim must be 2 or 3");
+  if (n < 1 || p < 1) return fail(WOS_EINVAL, "need n >= 1 and p >= 1 (n=%d, p=%d)", n, p);
+  if (opts->walks_per_site < 1 || opts->walks_per_site > (int64_t)INT32_MAX)
+    return fail(WOS_EINVAL, "walks_per_site must be in [1, 2^31)");
+  if (opts->fixed_M < 0) return fail(WOS_EINVAL, "fixed_M must be >= 0");
+  if (opts->fixed_M == 0 && !(opts->eps > 0.0 && std::isfinite(opts->eps)))
+    return fail(WOS_EINVAL, "eps must be finite and > 0");
+  if (opts->max_steps < 0) return fail(WOS_EINVAL, "max_steps must be >= 0");
+  if (opts->precision != WOS_F32 && opts->precision != WOS_F64)
+    return fail(WOS_EINVAL, "precision must be WOS_F32 or WOS_F64");
+  if (opts->volume_samples < 0) return fail(WOS_EINVAL, "volume_samples must be >= 0");
+  if (opts->regen_threshold < 0 || opts->regen_threshold > 64)
+    return fail(WOS_EINVAL, "regen_threshold must be in [0, 64]");
+  if (opts->walks_per_item < 0) return fail(WOS_EINVAL, "walks_per_item must be >= 0");
+
+  HostDomain hd;
+  hd.kind = dom->kind;
+  hd.dim = dom->dim;
+  for (int a = 0; a < 3; ++a) {
+    hd.c[a] = dom->center[a];
+    hd.lo[a] = dom->lo[a];
+    hd.hi[a] = dom->hi[a];
+  }
+  hd.rad = dom->radius;
+  switch (dom->kind) {
+    case WOS_BALL:
+      if (!(dom->radius > 0) || !finite3(dom->center, dom->dim)) return fail(WOS_EINVAL, "bad ball");
+      break;
+    case WOS_BOX:
+      for (int a = 0; a < dom->dim; ++a)
+        if (!(dom->hi[a] > dom->lo[a])) return fail(WOS_EINVAL, "bad box");
+      break;
+    case WOS_POLYGON:
+      if (dom->dim != 2) return fail(WOS_EINVAL, "polygon needs dim 2");
+      if (!dom->verts || dom->nvert < 3 || dom->nvert > kMaxPolyVerts)
+        return fail(WOS_EINVAL, "polygon needs 3..%d vertices", kMaxPolyVerts);
+      hd.verts.assign(dom->verts, dom->verts + 2 * dom->nvert);
+      if (!finite3(hd.verts.data(), 2 * dom->nvert)) return fail(WOS_EINVAL, "non-finite vertex");
+      {
+        double area2 = 0;
+        for (int e = 0; e < dom->nvert; ++e) {
+          const double* a = &hd.verts[2 * e];
+          const double* b = &hd.verts[2 * ((e + 1) % dom->nvert)];
+          area2 += a[0] * b[1] - a[1] * b[0];
+        }
+        if (!(area2 > 0)) return fail(WOS_EINVAL, "polygon vertices must be counter-clockwise");
+      }
+      break;
+    case WOS_BOX_MINUS_BALL:
+      if (dom->dim != 3) return fail(WOS_EINVAL, "box-minus-ball needs dim 3");
+      for (int a = 0; a < 3; ++a)
+        if (!(dom->hi[a] > dom->lo[a])) return fail(WOS_EINVAL, "bad box");
+      if (!(dom->radius > 0)) return fail(WOS_EINVAL, "bad radius");
+      break;
+    default:
+      return fail(WOS_EINVAL, "unknown domain kind %d", dom->kind);
+  }
+  const int d = dom->dim;
+  for (int i = 0; i < n; ++i) {
+    const double* x = sites + (size_t)i * d;
+    if (!finite3(x, d)) return fail(WOS_EINVAL, "site %d is not finite", i);
+    if (!host_inside(hd, x) || !(host_distance(hd, x) > 0))
+      return fail(WOS_EDOMAIN, "site %d is not inside the domain (r = %g)", i, host_distance(hd, x));
+  }
+  for (int j = 0; j < p; ++j)
+    if (!finite3(bnodes + (size_t)j * d, d)) return fail(WOS_EINVAL, "boundary node %d is not finite", j);
+
+  wos_toolbox* tb = new (std::nothrow) wos_toolbox();
+  if (!tb) return fail(WOS_ENOMEM, "host allocation failed");
+  tb->dom = hd;
+  tb->opts = *opts;
+  tb->dim = d;
+  tb->n = tb->m = n;
+  tb->p = p;
+  tb->f64 = opts->precision == WOS_F64;
+  tb->sites.assign(sites, sites + (size_t)n * d);
+  tb->bnodes.assign(bnodes, bnodes + (size_t)p * d);
+  if (tb->opts.max_steps == 0) tb->opts.max_steps = kDefaultMaxSteps;
+  if (tb->opts.volume_samples == 0) tb->opts.volume_samples = (int64_t)1 << 24;
+  tb->regen_T = tb->opts.regen_threshold ? tb->opts.regen_threshold : 32;
+
+  const int nseg = hd.kind == WOS_POLYGON ? dom->nvert : 0;
+  const size_t lds = walker_lds_bytes(d, n, p, nseg, tb->f64);
+  if (lds > 160 * 1024) {
+    delete tb;
+    return fail(WOS_ENOTIMPL, "site rows need %zu bytes of LDS (> 160 KiB); reduce n or p", lds);
+  }
+
+  // work split: enough (site, chunk) items to fill the chip
+  const int64_t N = opts->walks_per_site;
+  if (opts->walks_per_item > 0) {
+    tb->walks_per_item = (int)std::min<int64_t>(opts->walks_per_item, N);
+  } else {
+    const int64_t target_items = 2048;
+    const int64_t ips = std::max<int64_t>(1, (target_items + n - 1) / n);
+    tb->walks_per_item = (int)((N + ips - 1) / ips);
+  }
+  tb->items_per_site = (int)((N + tb->walks_per_item - 1) / tb->walks_per_item);
+  if ((int64_t)tb->items_per_site * n > (int64_t)INT32_MAX) {
+    delete tb;
+    return fail(WOS_EINVAL, "too many work items");
+  }
+
+  // nearest-centre grids
+  double lo[3], hi[3];
+  host_bbox(hd, lo, hi);
+  double vol = 1;
+  for (int a = 0; a < d; ++a) vol *= (hi[a] - lo[a]);
+  const double sp_v = std::pow(vol / n, 1.0 / d);
+  GridHost gvh = build_grid(sites, n, d, lo, hi, sp_v / (d == 2 ? 6.0 : 3.0), 1 << 24);
+  const double bm = host_boundary_measure(hd);
+  const double sp_b = d == 2 ? bm / p : std::sqrt(bm / p);
+  GridHost ggh = build_grid(bnodes, p, d, lo, hi, sp_b / 4.0, 1 << 23);
+
+  wos_status s = WOS_OK;
+#define TRY(x)          \
+  do {                  \
+    s = (x);            \
+    if (s != WOS_OK) {  \
+      release(tb);      \
+      delete tb;        \
+      return s;         \
+    }                   \
+  } while (0)
+  TRY(upload_grid(tb, gvh, &tb->gv));
+  TRY(upload_grid(tb, ggh, &tb->gg));
+  {
+    auto s32 = padded<float>(tb->sites, n, d);
+    auto s64 = padded<double>(tb->sites, n, d);
+    TRY(upload(tb, &tb->d_sites_f32, s32.data(), s32.size() * 4));
+    TRY(upload(tb, &tb->d_sites_f64, s64.data(), s64.size() * 8));
+    if (tb->f64) {
+      auto b = padded<double>(tb->bnodes, p, d);
+      TRY(upload(tb, &tb->d_bnodes, b.data(), b.size() * 8));
+    } else {
+      auto b = padded<float>(tb->bnodes, p, d);
+      TRY(upload(tb, &tb->d_bnodes, b.data(), b.size() * 4));
+    }
+  }
+  {
+    std::vector<double> seg(5 * std::max(nseg, 1), 0.0);
+    for (int e = 0; e < nseg; ++e) {
+      const double* a = &hd.verts[2 * e];
+      const double* b = &hd.verts[2 * ((e + 1) % nseg)];
+      const double ex = b[0] - a[0], ey = b[1] - a[1];
+      seg[5 * e + 0] = a[0];
+      seg[5 * e + 1] = a[1];
+      seg[5 * e + 2] = ex;
+      seg[5 * e + 3] = ey;
+      seg[5 * e + 4] = 1.0 / (ex * ex + ey * ey);
+    }
+    if (tb->f64) {
+      TRY(upload(tb, &tb->d_segs, seg.data(), seg.size() * 8));
+    } else {
+      std::vector<float> sf(seg.begin(), seg.end());
+      TRY(upload(tb, &tb->d_segs, sf.data(), sf.size() * 4));
+    }
+    std::vector<double> v = hd.verts;
+    if (v.empty()) v.assign(2, 0.0);
+    TRY(upload(tb, (void**)&tb->d_verts, v.data(), v.size() * 8));
+  }
+  const size_t ts = tsize(tb);
+  TRY(dev_alloc(tb, &tb->d_A, ts * (size_t)n * n));
+  TRY(dev_alloc(tb, &tb->d_B, ts * (size_t)d * n * n));
+  TRY(dev_alloc(tb, &tb->d_K, ts * (size_t)d * n * p));
+  TRY(dev_alloc(tb, &tb->d_H, ts * (size_t)n * p));
+  TRY(dev_alloc(tb, (void**)&tb->d_Hc, 4 * (size_t)n * p));
+  TRY(dev_alloc(tb, (void**)&tb->d_vcount, 8 * (size_t)n));
+  TRY(dev_alloc(tb, (void**)&tb->d_stats, 8 * 8));
+  TRY(dev_alloc(tb, (void**)&tb->d_lambda, 8 * (size_t)n));
+#undef TRY
+  *out = tb;
+  return WOS_OK;
+}
+
+wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
+  g_err.clear();
+  if (!tb) return fail(WOS_EINVAL, "toolbox is NULL");
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  const int d = tb->dim, n = tb->n, m = tb->m, p = tb->p;
+  const size_t ts = tsize(tb);
+  const bool direct = tb->items_per_site == 1;
+  const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFull), k1 = (uint32_t)(seed >> 32);
+
+  WOS_HIP(hipMemsetAsync(tb->d_stats, 0, 8 * 8, stream));
+  WOS_HIP(hipMemsetAsync(tb->d_vcount, 0, 8 * (size_t)n, stream));
+  if (!direct) {
+    WOS_HIP(hipMemsetAsync(tb->d_A, 0, ts * (size_t)n * m, stream));
+    WOS_HIP(hipMemsetAsync(tb->d_B, 0, ts * (size_t)d * n * m, stream));
+    WOS_HIP(hipMemsetAsync(tb->d_K, 0, ts * (size_t)d * n * p, stream));
+    WOS_HIP(hipMemsetAsync(tb->d_Hc, 0, 4 * (size_t)n * p, stream));
+  }
+
+  if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[0], stream));
+  // cell weights lambda_i
+  {
+    VolumeParams V{};
+    V.dom = to_dev<double>(tb->dom);
+    host_bbox(tb->dom, V.dom.lo, V.dom.hi);  // points are drawn in the bounding box
+    V.verts = tb->d_verts;
+    V.nvert = (int)tb->dom.verts.size() / 2;
+    V.gv = view<double>(tb->gv, tb->d_sites_f64);
+    V.n = n;
+    V.dim = d;
+    V.npoints = tb->opts.volume_samples;
+    V.nblocks = d == 2 ? (V.npoints + 1) / 2 : V.npoints;
+    V.k0 = k0;
+    V.k1 = k1;
+    V.counts = tb->d_vcount;
+    V.inside = tb->d_stats + 4;
+    WOS_HIP(launch_volume(V, stream));
+    WOS_HIP(launch_lambda(tb->d_vcount, n, tb->d_lambda, stream));
+  }
+  if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[1], stream));
+
+  const int nseg = (int)tb->dom.verts.size() / 2;
+  const int items = tb->items_per_site * n;
+  if (tb->f64) {
+    WalkerParams<double> P{};
+    P.dom = to_dev<double>(tb->dom);
+    P.segs = static_cast<const double*>(tb->d_segs);
+    P.nseg = nseg;
+    P.sites = static_cast<const double*>(tb->d_sites_f64);
+    P.gv = view<double>(tb->gv, tb->d_sites_f64);
+    P.gg = view<double>(tb->gg, tb->d_bnodes);
+    P.n = n;
+    P.m = m;
+    P.p = p;
+    P.walks = tb->opts.walks_per_site;
+    P.walks_per_item = tb->walks_per_item;
+    P.items_per_site = tb->items_per_site;
+    P.eps = tb->opts.eps;
+    P.max_steps = tb->opts.max_steps;
+    P.fixed_M = tb->opts.fixed_M;
+    P.k0 = k0;
+    P.k1 = k1;
+    P.inv_N = 1.0 / (double)tb->opts.walks_per_site;
+    P.regen_T = tb->regen_T;
+    P.direct_store = direct ? 1 : 0;
+    P.A = static_cast<double*>(tb->d_A);
+    P.B = static_cast<double*>(tb->d_B);
+    P.Hc = tb->d_Hc;
+    P.K = static_cast<double*>(tb->d_K);
+    P.stats = tb->d_stats;
+    WOS_HIP(launch_walker_f64(P, d, tb->dom.kind, items, stream));
+    if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[2], stream));
+    WOS_HIP(launch_h_from_counts_f64(tb->d_Hc, (size_t)n * p, P.inv_N, static_cast<double*>(tb->d_H), stream));
+  } else {
+    WalkerParams<float> P{};
+    P.dom = to_dev<float>(tb->dom);
+    P.segs = static_cast<const float*>(tb->d_segs);
+    P.nseg = nseg;
+    P.sites = static_cast<const float*>(tb->d_sites_f32);
+    P.gv = view<float>(tb->gv, tb->d_sites_f32);
+    P.gg = view<float>(tb->gg, tb->d_bnodes);
+    P.n = n;
+    P.m = m;
+    P.p = p;
+    P.walks = tb->opts.walks_per_site;
+    P.walks_per_item = tb->walks_per_item;
+    P.items_per_site = tb->items_per_site;
+    P.eps = (float)tb->opts.eps;
+    P.max_steps = tb->opts.max_steps;
+    P.fixed_M = tb->opts.fixed_M;
+    P.k0 = k0;
+    P.k1 = k1;
+    P.inv_N = (float)(1.0 / (double)tb->opts.walks_per_site);
+    P.regen_T = tb->regen_T;
+    P.direct_store = direct ? 1 : 0;
+    P.A = static_cast<float*>(tb->d_A);
+    P.B = static_cast<float*>(tb->d_B);
+    P.Hc = tb->d_Hc;
+    P.K = static_cast<float*>(tb->d_K);
+    P.stats = tb->d_stats;
+    WOS_HIP(launch_walker_f32(P, d, tb->dom.kind, items, stream));
+    if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[2], stream));
+    WOS_HIP(launch_h_from_counts_f32(tb->d_Hc, (size_t)n * p, P.inv_N, static_cast<float*>(tb->d_H), stream));
+  }
+  if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[3], stream));
+  tb->last_stream = stream;
+  tb->built = true;
+  return WOS_OK;
+}
+
+wos_status wos_toolbox_set_timing(wos_toolbox* tb, int32_t enable) {
+  g_err.clear();
+  if (!tb) return fail(WOS_EINVAL, "toolbox is NULL");
+  if (enable && !tb->ev[0])
+    for (auto& e : tb->ev) WOS_HIP(hipEventCreate(&e));
+  tb->timing = enable != 0;
+  return WOS_OK;
+}
+
+wos_status wos_toolbox_get_timings(const wos_toolbox* tb, double* ms_walker, double* ms_volume,
+                                   double* ms_finalize) {
+  g_err.clear();
+  if (!tb || !ms_walker || !ms_volume || !ms_finalize) return fail(WOS_EINVAL, "NULL argument");
+  if (!tb->timing || !tb->built) return fail(WOS_EINVAL, "timing not enabled before the last build");
+  WOS_HIP(hipEventSynchronize(tb->ev[3]));
+  float a = 0, b = 0, c = 0;
+  WOS_HIP(hipEventElapsedTime(&a, tb->ev[0], tb->ev[1]));
+  WOS_HIP(hipEventElapsedTime(&b, tb->ev[1], tb->ev[2]));
+  WOS_HIP(hipEventElapsedTime(&c, tb->ev[2], tb->ev[3]));
+  *ms_volume = a;
+  *ms_walker = b;
+  *ms_finalize = c;
+  return WOS_OK;
+}
+
+wos_status wos_build_toolbox(const wos_domain* dom, const double* sites, int32_t n,
+                             const double* bnodes, int32_t p, const wos_build_opts* opts,
+                             void* stream, wos_toolbox** out) {
+  wos_status s = wos_toolbox_create(dom, sites, n, bnodes, p, opts, out);
+  if (s != WOS_OK) return s;
+  s = wos_toolbox_build(*out, opts->seed, stream);
+  if (s == WOS_OK) {
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) s = fail(WOS_EDEVICE, "build failed: %s", hipGetErrorString(e));
+  }
+  if (s != WOS_OK) {
+    wos_toolbox_free(*out);
+    *out = nullptr;
+  }
+  return s;
+}
+
+wos_status wos_toolbox_get_info(const wos_toolbox* tb, wos_toolbox_info* info) {
+  g_err.clear();
+  if (!tb || !info) return fail(WOS_EINVAL, "NULL argument");
+  std::memset(info, 0, sizeof *info);
+  info->dim = tb->dim;
+  info->n = tb->n;
+  info->m = tb->m;
+  info->p = tb->p;
+  info->precision = tb->f64 ? WOS_F64 : WOS_F32;
+  info->walks_per_site = tb->opts.walks_per_site;
+  info->device_bytes = tb->bytes;
+  if (tb->built) {
+    WOS_HIP(hipStreamSynchronize(tb->last_stream));
+    unsigned long long st[8];
+    WOS_HIP(hipMemcpy(st, tb->d_stats, sizeof st, hipMemcpyDeviceToHost));
+    info->walk_steps = st[0];
+    info->walks = st[1];
+    info->capped_walks = st[2];
+    info->max_walk_steps = st[3];
+    info->volume_inside = st[4];
+  }
+  return WOS_OK;
+}
+
+wos_status wos_toolbox_export(const wos_toolbox* tb, int32_t what, void* dst, size_t bytes,
+                              int32_t dst_is_device, void* stream_) {
+  g_err.clear();
+  if (!tb || !dst) return fail(WOS_EINVAL, "NULL argument");
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  const size_t ts = tsize(tb), n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
+  const void* src = nullptr;
+  size_t want = 0;
+  switch (what) {
+    case WOS_EXPORT_A: src = tb->d_A; want = ts * n * m; break;
+    case WOS_EXPORT_B: src = tb->d_B; want = ts * d * n * m; break;
+    case WOS_EXPORT_H: src = tb->d_H; want = ts * n * p; break;
+    case WOS_EXPORT_K: src = tb->d_K; want = ts * d * n * p; break;
+    case WOS_EXPORT_HCOUNT: src = tb->d_Hc; want = 4 * n * p; break;
+    case WOS_EXPORT_LAMBDA: src = tb->d_lambda; want = 8 * n; break;
+    case WOS_EXPORT_VCOUNT: src = tb->d_vcount; want = 8 * n; break;
+    default: return fail(WOS_EINVAL, "unknown export %d", what);
+  }
+  if (bytes != want) return fail(WOS_EINVAL, "export %d needs %zu bytes, got %zu", what, want, bytes);
+  if (dst_is_device) {
+    WOS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream));
+  } else {
+    WOS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, stream));
+    WOS_HIP(hipStreamSynchronize(stream));
+  }
+  return WOS_OK;
+}
+
+wos_status wos_apply(const wos_toolbox* tb, const double* fbar, const double* g, double* u,
+                     double* grad_u, void* stream_) {
+  g_err.clear();
+  if (!tb || !fbar || !g || !u) return fail(WOS_EINVAL, "NULL argument");
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  if (tb->f64) {
+    WOS_HIP(launch_apply_f64(static_cast<const double*>(tb->d_A), tb->n, tb->m, fbar,
+                             static_cast<const double*>(tb->d_H), tb->p, g, u, 1, stream));
+    if (grad_u)
+      WOS_HIP(launch_apply_f64(static_cast<const double*>(tb->d_B), tb->n, tb->m, fbar,
+                               static_cast<const double*>(tb->d_K), tb->p, g, grad_u, tb->dim, stream));
+  } else {
+    WOS_HIP(launch_apply_f32(static_cast<const float*>(tb->d_A), tb->n, tb->m, fbar,
+                             static_cast<const float*>(tb->d_H), tb->p, g, u, 1, stream));
+    if (grad_u)
+      WOS_HIP(launch_apply_f32(static_cast<const float*>(tb->d_B), tb->n, tb->m, fbar,
+                               static_cast<const float*>(tb->d_K), tb->p, g, grad_u, tb->dim, stream));
+  }
+  return WOS_OK;
+}
+
+void wos_toolbox_free(wos_toolbox* tb) {
+  if (!tb) return;
+  if (tb->built && tb->last_stream) (void)hipStreamSynchronize(tb->last_stream);
+  release(tb);
+  delete tb;
+}
+
+}  // extern "C"

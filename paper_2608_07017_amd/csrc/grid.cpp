@@ -1,0 +1,189 @@
+// Construction of the nearest-centre grids (host, FP64).
+//
+// The toolbox bins points by their nearest centre (Voronoi membership,
+// Sec. "Matrix estimators", and Rem. "implementation_tips" (iii)).  A
+// uniform grid over the bounding box stores, per cell, every centre that can
+// be the nearest one for some point of the cell: with c the cell centre,
+// hd its half-diagonal and d* = min_j |c - y_j|, any point q of the cell has
+// its nearest centre within d* + hd of q, hence within d* + 2 hd of c, so
+// {j : |c - y_j| <= d* + 2 hd + margin} is a superset of the answers.  A
+// cell with a single candidate stores that index directly, which is the
+// common case the walker's lookup is built around.  The small relative
+// margin absorbs the rounding of a lookup done in FP32 and of cell indices
+// computed in FP32 near cell faces.
+#include <algorithm>
+#include <cmath>
+#include <thread>
+#include <vector>
+
+#include "grid.hpp"
+
+namespace wos {
+
+namespace {
+
+struct Buckets {
+  std::vector<int> start;  // ncell + 1
+  std::vector<int> items;
+};
+
+}  // namespace
+
+GridHost build_grid(const double* pts, int npts, int dim, const double* lo, const double* hi,
+                    double h_target, int max_cells) {
+  GridHost g;
+  g.dim = dim;
+  for (int a = 0; a < 3; ++a) {
+    g.n[a] = 1;
+    g.lo[a] = 0.0;
+    g.h[a] = 1.0;
+  }
+  double h = h_target;
+  for (;;) {
+    long long tot = 1;
+    for (int a = 0; a < dim; ++a) {
+      const double ext = hi[a] - lo[a];
+      g.n[a] = std::max(1, (int)std::ceil(ext / h));
+      tot *= g.n[a];
+    }
+    if (tot <= max_cells) break;
+    h *= 1.1;
+  }
+  for (int a = 0; a < dim; ++a) {
+    g.lo[a] = lo[a];
+    g.h[a] = (hi[a] - lo[a]) / g.n[a];
+  }
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+  const long long ncell = (long long)n0 * n1 * n2;
+
+  auto cell_of = [&](const double* q, int* c) {
+    for (int a = 0; a < 3; ++a) {
+      if (a < dim) {
+        int v = (int)std::floor((q[a] - g.lo[a]) / g.h[a]);
+        c[a] = std::min(std::max(v, 0), g.n[a] - 1);
+      } else {
+        c[a] = 0;
+      }
+    }
+  };
+  auto lin = [&](int c0, int c1, int c2) -> long long { return ((long long)c0 * n1 + c1) * n2 + c2; };
+
+  Buckets bk;
+  bk.start.assign(ncell + 1, 0);
+  std::vector<long long> where(npts);
+  for (int j = 0; j < npts; ++j) {
+    int c[3];
+    cell_of(pts + (size_t)j * dim, c);
+    where[j] = lin(c[0], c[1], c[2]);
+    bk.start[where[j] + 1]++;
+  }
+  for (long long i = 0; i < ncell; ++i) bk.start[i + 1] += bk.start[i];
+  bk.items.resize(npts);
+  {
+    std::vector<int> fill(bk.start.begin(), bk.start.end() - 1);
+    for (int j = 0; j < npts; ++j) bk.items[fill[where[j]]++] = j;  // ascending j per bucket
+  }
+
+  double hd2 = 0.0, hmin = 1e300, extent = 0.0;
+  for (int a = 0; a < dim; ++a) {
+    hd2 += 0.25 * g.h[a] * g.h[a];
+    hmin = std::min(hmin, g.h[a]);
+    extent = std::max(extent, hi[a] - lo[a]);
+  }
+  const double hd = std::sqrt(hd2);
+  const double margin = 1e-2 * hd + 1e-9 * extent;
+  const int maxn = std::max(n0, std::max(n1, n2));
+
+  g.cell.assign(ncell, 0);
+  const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::vector<int>> lists(nthreads);
+  std::vector<std::vector<std::pair<long long, int>>> offs(nthreads);  // (cell, offset in lists[t])
+
+  auto work = [&](unsigned t) {
+    std::vector<int> cand;
+    for (long long cid = t; cid < ncell; cid += nthreads) {
+      const int c0 = (int)(cid / ((long long)n1 * n2));
+      const int c1 = (int)((cid / n2) % n1);
+      const int c2 = (int)(cid % n2);
+      const int cc[3] = {c0, c1, c2};
+      double ctr[3] = {0, 0, 0};
+      for (int a = 0; a < dim; ++a) ctr[a] = g.lo[a] + (cc[a] + 0.5) * g.h[a];
+      // nearest distance by rings of buckets (Chebyshev radius s)
+      double best2 = 1e300;
+      for (int s = 0; s <= maxn; ++s) {
+        const int lo0 = c0 - s, hi0 = c0 + s;
+        const int lo1 = (dim > 1) ? c1 - s : 0, hi1 = (dim > 1) ? c1 + s : 0;
+        const int lo2 = (dim > 2) ? c2 - s : 0, hi2 = (dim > 2) ? c2 + s : 0;
+        for (int i0 = std::max(lo0, 0); i0 <= std::min(hi0, n0 - 1); ++i0)
+          for (int i1 = std::max(lo1, 0); i1 <= std::min(hi1, n1 - 1); ++i1)
+            for (int i2 = std::max(lo2, 0); i2 <= std::min(hi2, n2 - 1); ++i2) {
+              const int cheb = std::max(std::abs(i0 - c0), std::max(std::abs(i1 - c1), std::abs(i2 - c2)));
+              if (cheb != s) continue;
+              const long long b = lin(i0, i1, i2);
+              for (int it = bk.start[b]; it < bk.start[b + 1]; ++it) {
+                const double* y = pts + (size_t)bk.items[it] * dim;
+                double d2 = 0.0;
+                for (int a = 0; a < dim; ++a) d2 += (y[a] - ctr[a]) * (y[a] - ctr[a]);
+                best2 = std::min(best2, d2);
+              }
+            }
+        if (best2 < 1e300 && std::sqrt(best2) <= (s + 0.5) * hmin) break;
+      }
+      const double R = std::sqrt(best2) + 2.0 * hd + margin;
+      const double R2 = R * R;
+      int r0[3] = {0, 0, 0}, r1[3] = {0, 0, 0};
+      for (int a = 0; a < dim; ++a) {
+        r0[a] = std::max(0, (int)std::floor((ctr[a] - R - g.lo[a]) / g.h[a]));
+        r1[a] = std::min(g.n[a] - 1, (int)std::floor((ctr[a] + R - g.lo[a]) / g.h[a]));
+      }
+      cand.clear();
+      for (int i0 = r0[0]; i0 <= r1[0]; ++i0)
+        for (int i1 = r0[1]; i1 <= r1[1]; ++i1)
+          for (int i2 = r0[2]; i2 <= r1[2]; ++i2) {
+            const long long b = lin(i0, i1, i2);
+            for (int it = bk.start[b]; it < bk.start[b + 1]; ++it) {
+              const int j = bk.items[it];
+              const double* y = pts + (size_t)j * dim;
+              double d2 = 0.0;
+              for (int a = 0; a < dim; ++a) d2 += (y[a] - ctr[a]) * (y[a] - ctr[a]);
+              if (d2 <= R2) cand.push_back(j);
+            }
+          }
+      std::sort(cand.begin(), cand.end());
+      if (cand.size() == 1) {
+        g.cell[cid] = cand[0];
+      } else {
+        offs[t].push_back({cid, (int)lists[t].size()});
+        lists[t].push_back((int)cand.size());
+        lists[t].insert(lists[t].end(), cand.begin(), cand.end());
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nthreads; ++t) th.emplace_back(work, t);
+  for (auto& x : th) x.join();
+
+  size_t total = 0;
+  for (unsigned t = 0; t < nthreads; ++t) total += lists[t].size();
+  g.list.reserve(total + 1);
+  long long nmulti = 0, sumc = 0;
+  int maxc = 1;
+  for (unsigned t = 0; t < nthreads; ++t) {
+    const int base = (int)g.list.size();
+    g.list.insert(g.list.end(), lists[t].begin(), lists[t].end());
+    for (auto& pr : offs[t]) {
+      g.cell[pr.first] = -(base + pr.second) - 1;
+      const int cnt = lists[t][pr.second];
+      nmulti++;
+      sumc += cnt;
+      maxc = std::max(maxc, cnt);
+    }
+  }
+  if (g.list.empty()) g.list.push_back(0);
+  g.frac_single = 1.0 - (double)nmulti / (double)ncell;
+  g.mean_multi = nmulti ? (double)sumc / nmulti : 1.0;
+  g.max_cand = maxc;
+  return g;
+}
+
+}  // namespace wos

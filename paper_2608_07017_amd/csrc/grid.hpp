@@ -1,0 +1,26 @@
+// Host-side nearest-centre grid (see grid.cpp).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace wos {
+
+struct GridHost {
+  int dim = 2;
+  int n[3] = {1, 1, 1};
+  double lo[3] = {0, 0, 0};
+  double h[3] = {1, 1, 1};
+  std::vector<int> cell;  // >= 0: the only candidate; < 0: -(offset + 1) into list
+  std::vector<int> list;  // [count, j_1 < j_2 < ...] blocks
+  double frac_single = 1.0;
+  double mean_multi = 1.0;
+  int max_cand = 1;
+};
+
+// pts: npts x dim (double, host).  [lo, hi]: the box covered.  h_target:
+// requested cell side (enlarged until the cell count is <= max_cells).
+GridHost build_grid(const double* pts, int npts, int dim, const double* lo, const double* hi,
+                    double h_target, int max_cells);
+
+}  // namespace wos

@@ -1,0 +1,168 @@
+// Device-side building blocks of the walker: the counter-based generator,
+// uniforms, unit directions, the distance to the boundary r(x) and the
+// nearest-centre grid lookup.  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "wos_types.hpp"
+
+namespace wos {
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of two
+// 32x32->64 multiplies with XOR/permute mixing of the 128-bit counter, the
+// 64-bit key advanced by the two Weyl constants between rounds.  The key is
+// wave-uniform, so its schedule stays in scalar registers.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// ((x >> 9) + 1/2) * 2^-23: 24 significant bits, exact in float and double.
+template <typename T>
+__device__ __forceinline__ T u01(uint32_t x) {
+  return (T(x >> 9) + T(0.5)) * T(1.0 / 8388608.0);
+}
+
+// ------------------------------------------------------------ directions
+// d = 2: angle 2*pi*a.  float uses the hardware sine/cosine, whose input is
+// in revolutions, so no range reduction is needed for a in (0,1).
+__device__ __forceinline__ void dir2(float a, float* v) {
+  v[0] = __builtin_amdgcn_cosf(a);
+  v[1] = __builtin_amdgcn_sinf(a);
+}
+__device__ __forceinline__ void dir2(double a, double* v) {
+  double s, c;
+  sincospi(2.0 * a, &s, &c);
+  v[0] = c;
+  v[1] = s;
+}
+// d = 3: z = 2u - 1 uniform (Archimedes), azimuth 2*pi*b.
+__device__ __forceinline__ void dir3(float u, float b, float* v) {
+  const float z = 2.0f * u - 1.0f;
+  const float s = __builtin_sqrtf(fmaxf(0.0f, 1.0f - z * z));
+  v[0] = s * __builtin_amdgcn_cosf(b);
+  v[1] = s * __builtin_amdgcn_sinf(b);
+  v[2] = z;
+}
+__device__ __forceinline__ void dir3(double u, double b, double* v) {
+  const double z = 2.0 * u - 1.0;
+  const double s = sqrt(fmax(0.0, 1.0 - z * z));
+  double sn, cs;
+  sincospi(2.0 * b, &sn, &cs);
+  v[0] = s * cs;
+  v[1] = s * sn;
+  v[2] = z;
+}
+
+__device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
+
+// -(2/3) ln R / (1 - R), the d = 2 weight that turns Beta(2,2) into the
+// radial law of the ball-Green density.  R - 1 is exact for R > 1/2.
+template <typename T>
+__device__ __forceinline__ T omega2(T R) {
+  const T lr = (R > T(0.5)) ? log1p(R - T(1)) : log(R);
+  return T(-2.0 / 3.0) * lr / (T(1) - R);
+}
+
+// ------------------------------------------------------------- geometry
+// r(x): distance to the boundary (eq. r), specialised per domain kind.
+// Polygon edges are read from LDS: (ax, ay, ex, ey, 1/|e|^2) per edge.
+template <typename T, int D, int KIND>
+__device__ __forceinline__ T boundary_distance(const DomainDev<T>& dom, const T* x, const T* seg,
+                                               int nseg) {
+  if constexpr (KIND == WOS_BALL) {
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const T t = x[a] - dom.c[a];
+      s += t * t;
+    }
+    return dom.rad - dsqrt(s);
+  } else if constexpr (KIND == WOS_BOX) {
+    T r = fmin(x[0] - dom.lo[0], dom.hi[0] - x[0]);
+#pragma unroll
+    for (int a = 1; a < D; ++a) r = fmin(r, fmin(x[a] - dom.lo[a], dom.hi[a] - x[a]));
+    return r;
+  } else if constexpr (KIND == WOS_POLYGON) {
+    T best = T(3.0e38);
+    for (int e = 0; e < nseg; ++e) {
+      const T* s = seg + 5 * e;
+      const T px = x[0] - s[0], py = x[1] - s[1];
+      T t = (px * s[2] + py * s[3]) * s[4];
+      t = fmin(fmax(t, T(0)), T(1));
+      const T qx = px - t * s[2], qy = py - t * s[3];
+      best = fmin(best, qx * qx + qy * qy);
+    }
+    return dsqrt(best);
+  } else {  // WOS_BOX_MINUS_BALL
+    T r = fmin(x[0] - dom.lo[0], dom.hi[0] - x[0]);
+#pragma unroll
+    for (int a = 1; a < D; ++a) r = fmin(r, fmin(x[a] - dom.lo[a], dom.hi[a] - x[a]));
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const T t = x[a] - dom.c[a];
+      s += t * t;
+    }
+    return fmin(r, dsqrt(s) - dom.rad);
+  }
+}
+
+// ------------------------------------------------------ nearest centre
+// Uniform grid over the bounding box; each cell holds either the one centre
+// that is nearest to every point of the cell (code >= 0) or an offset into a
+// list [count, j_1 < j_2 < ...] of every centre that can be nearest somewhere
+// in the cell (code < 0).  The list is scanned with a strict '<', so ties go
+// to the lowest index.
+template <typename T, int D>
+__device__ __forceinline__ int grid_nearest(const GridDev<T>& g, const T* q) {
+  int idx = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int c = (int)((q[a] - g.lo[a]) * g.inv_h[a]);
+    c = min(max(c, 0), g.n[a] - 1);
+    idx = idx * g.n[a] + c;
+  }
+  const int code = g.cell[idx];
+  if (code >= 0) return code;
+  const int* lst = g.list + (-code - 1);
+  const int cnt = lst[0];
+  int bj = lst[1];
+  T best = T(3.0e38);
+  for (int c = 0; c < cnt; ++c) {
+    const int j = lst[1 + c];
+    const T* y = g.pts + (size_t)j * PtStride<D>::value;
+    T d2 = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const T t = q[a] - y[a];
+      d2 += t * t;
+    }
+    if (d2 < best) {
+      best = d2;
+      bj = j;
+    }
+  }
+  return bj;
+}
+
+}  // namespace wos

@@ -1,0 +1,81 @@
+// Plain structures shared by the host runtime and the kernels.
+#pragma once
+
+#include <cstdint>
+
+#include "../../include/wos.h"
+
+namespace wos {
+
+constexpr int kMaxPolyVerts = 64;
+constexpr int kStepBlock0 = 4;      // first Philox block of the per-step draws
+constexpr uint32_t kTagWalk = 0;
+constexpr uint32_t kTagVolume = 1;
+constexpr int kDefaultMaxSteps = 10000;
+
+template <int D>
+struct PtStride {
+  static constexpr int value = (D == 2) ? 2 : 4;  // 3-D centres padded to 16 B
+};
+
+template <typename T>
+struct DomainDev {
+  int kind;
+  int dim;
+  T c[3];
+  T rad;
+  T lo[3];
+  T hi[3];
+};
+
+template <typename T>
+struct GridDev {
+  int n[3];
+  T lo[3];
+  T inv_h[3];
+  const int* cell;  // n0*n1*n2 codes, x slowest
+  const int* list;  // [count, indices...] blocks
+  const T* pts;     // centres, PtStride<D> values each
+};
+
+template <typename T>
+struct WalkerParams {
+  DomainDev<T> dom;
+  const T* segs;   // polygon edges, 5 values each
+  int nseg;
+  const T* sites;  // n centres, padded stride
+  GridDev<T> gv;   // nearest site
+  GridDev<T> gg;   // nearest boundary node
+  int n, m, p;
+  int64_t walks;
+  int walks_per_item;
+  int items_per_site;
+  T eps;
+  int max_steps;
+  int fixed_M;
+  uint32_t k0, k1;
+  T inv_N;
+  int regen_T;
+  int direct_store;
+  T* A;
+  T* B;
+  uint32_t* Hc;
+  T* K;
+  unsigned long long* stats;  // [0] walk-steps, [1] walks, [2] capped, [3] max walk-steps
+};
+
+struct VolumeParams {
+  DomainDev<double> dom;  // lo/hi hold the bounding box the points are drawn in
+  const double* verts;  // polygon vertices, 2 per vertex
+  int nvert;
+  GridDev<double> gv;
+  int n;
+  int dim;
+  int64_t npoints;      // candidate points
+  int64_t nblocks;      // Philox blocks
+  uint32_t k0, k1;
+  unsigned long long* counts;  // n
+  unsigned long long* inside;  // 1
+};
+
+}  // namespace wos

@@ -1,0 +1,258 @@
+"""GPU path (libwos through its C ABI) against the CPU oracle.
+
+Both sides draw the same Philox4x32-10 streams, so walks are the same up to
+rounding.  In FP64 the walks agree step for step: exit counts must match
+exactly and the matrices to summation-order rounding.  In FP32 a walk can
+take a different branch where its FP32 position decides a comparison
+differently (the eps test, a near-tie between two centres); the comparison
+there is statistical, against the oracle's own Monte Carlo standard errors.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.volume import cell_counts
+from oracle.walker import build_toolbox as oracle_build, site_events, bin_site
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2608_07017_amd")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu_tb(dom, sites, bnodes, walks, eps, seed, **kw):
+    _say("GPU build:", dom["kind"], "n=%d p=%d N=%d eps=%g" % (len(sites), len(bnodes), walks, eps), kw)
+    tb = P.Toolbox(dom, sites, bnodes, walks, eps, seed=seed, **kw)
+    tb.build()
+    torch.cuda.synchronize()
+    return tb
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _export_all(tb):
+    out = {k: _np(tb.export(k)) for k in ("A", "B", "H", "K", "Hcount", "lambda", "vcount")}
+    out["Hcount"] = out["Hcount"].astype(np.int64)
+    return out
+
+
+# ---------------------------------------------------------------- volume
+
+
+@pytest.mark.parametrize("name,dom", [("disk", W.unit_disk()), ("lshape", W.l_shape()),
+                                      ("ball", W.unit_ball()), ("cubeball", W.cube_minus_ball())])
+def test_volume_counts_bit_exact(name, dom):
+    sites = W.sample_sites(dom, 57, 3, 1e-3)
+    bn = sites[:5]    # any centres: only the volume stream is checked here
+    npts = (1 << 19) + 3   # ragged: the last Philox block is partly used
+    tb = _gpu_tb(dom, sites, bn, 1, 1e-3, 777, precision="f64", volume_samples=npts)
+    got = _np(tb.export("vcount")).astype(np.int64)
+    ref = cell_counts(dom, sites, 777, npts)
+    assert np.array_equal(got, ref)
+    lam = _np(tb.export("lambda"))
+    assert np.allclose(lam, ref / ref.sum(), rtol=1e-15, atol=0)
+    assert tb.info()["volume_inside"] == ref.sum()
+
+
+# ---------------------------------------------------------- FP64 walker
+
+
+def _compare_f64(dom, sites, bn, walks, eps, seed, **kw):
+    tb = _gpu_tb(dom, sites, bn, walks, eps, seed, precision="f64", volume_samples=1 << 12, **kw)
+    g = _export_all(tb)
+    info = tb.info()
+    ref = oracle_build(dom, sites, bn, walks, eps, seed, fixed_M=kw.get("fixed_M", 0),
+                       max_steps=kw.get("max_steps", 0) or 10000)
+    assert info["walks"] == len(sites) * walks
+    assert info["walk_steps"] == ref["walk_steps"].sum()
+    assert info["max_walk_steps"] == ref["max_steps"].max()
+    assert info["capped_walks"] == ref["capped"].sum()
+    assert np.array_equal(g["Hcount"], ref["Hcount"])
+    for key in ("A", "B", "K"):
+        scale = np.abs(ref[key]).max()
+        assert np.allclose(g[key], ref[key], rtol=1e-10, atol=1e-12 * scale), key
+    assert np.allclose(g["H"], ref["H"], rtol=1e-15, atol=0)
+    return tb, g, ref
+
+
+def test_disk64_fp64_full_size():
+    """The 2-D unit-disk configuration at its full size: 64 sites, 64 boundary
+    nodes, 2000 walks per site, eps 1e-3, FP64."""
+    c = W.config("disk64")
+    _compare_f64(c["domain"], c["sites"], c["bnodes"], c["walks"], c["eps"], c["seed"])
+
+
+def test_ragged_multi_item_and_regeneration_schedules():
+    """37 sites, 333 walks split in items of 100 (atomic flush path, ragged last
+    item); the result must not depend on the lane schedule."""
+    dom = W.unit_disk()
+    sites = W.sample_sites(dom, 37, 5, 1e-3)
+    bn = W.circle_nodes(19)
+    tb1, g1, _ = _compare_f64(dom, sites, bn, 333, 1e-3, 42, walks_per_item=100, regen_threshold=1)
+    tb2 = _gpu_tb(dom, sites, bn, 333, 1e-3, 42, precision="f64", volume_samples=1 << 12,
+                  walks_per_item=333, regen_threshold=64)
+    g2 = _export_all(tb2)
+    assert np.array_equal(g1["Hcount"], g2["Hcount"])
+    for key in ("A", "B", "K"):
+        assert np.allclose(g1[key], g2[key], rtol=1e-12, atol=1e-15)
+
+
+def test_single_walk_and_single_site():
+    dom = W.unit_disk()
+    _compare_f64(dom, np.array([[0.2, -0.3]]), W.circle_nodes(7), 1, 1e-3, 9)
+
+
+def test_paper_fixed_M_mode():
+    sites, bn = W.paper_square_layout()
+    _compare_f64(W.unit_square(), sites[::13], bn, 200, 0.0, 3, fixed_M=30)
+
+
+def test_step_cap_counts():
+    dom = W.unit_disk()
+    sites = W.sample_sites(dom, 9, 8, 1e-2)
+    _compare_f64(dom, sites, W.circle_nodes(12), 300, 1e-9, 4, max_steps=6)
+
+
+@pytest.mark.parametrize("name", ["ball3d", "lshape", "cubeball"])
+def test_other_domains_fp64(name):
+    if name == "ball3d":
+        dom, bn = W.unit_ball(), W.fibonacci_sphere(48)
+    elif name == "lshape":
+        dom = W.l_shape()
+        bn = W.polygon_nodes(dom["verts"], 40)
+    else:
+        dom = W.cube_minus_ball()
+        bn = np.concatenate([W.cube_face_nodes(4), W.fibonacci_sphere(30, dom["center"], dom["radius"])])
+    sites = W.sample_sites(dom, 23, 11, 1e-3)
+    _compare_f64(dom, sites, bn, 400, 1e-4, 17)
+
+
+# ---------------------------------------------------------- FP32 walker
+
+
+def _row_functionals(A, B, H, K, g):
+    ones = np.ones(A.shape[1])
+    return {"A1": A @ ones, "B1": np.einsum("anm,m->an", B, ones), "Hg": H @ g,
+            "Kg": np.einsum("anp,p->an", K, g)}
+
+
+def _oracle_rows_with_se(dom, sites, bn, walks, eps, seed, rows, g):
+    """Oracle rows plus per-walk standard errors of the four functionals."""
+    out = {k: [] for k in ("A", "B", "H", "K", "seA1", "seB1", "seHg", "seKg", "steps")}
+    for i in rows:
+        ev = site_events(dom, sites[i], int(i), np.arange(walks), eps, seed)
+        a, b, h, kk = bin_site(ev, sites, bn)
+        out["A"].append(a / walks)
+        out["B"].append(b / walks)
+        out["H"].append(h / walks)
+        out["K"].append(kk / walks)
+        N = walks
+        cA = np.bincount(ev.ev_walk, weights=ev.ev_tA, minlength=N)
+        cB = np.stack([np.bincount(ev.ev_walk, weights=ev.ev_tB[:, d], minlength=N) + ev.ball_w[:, d]
+                       for d in range(sites.shape[1])], 1)
+        from oracle.voronoi import nearest
+        gj = g[nearest(bn, ev.term_pts)]
+        out["seA1"].append(cA.std(ddof=1) / np.sqrt(N))
+        out["seB1"].append(cB.std(axis=0, ddof=1) / np.sqrt(N))
+        out["seHg"].append(gj.std(ddof=1) / np.sqrt(N))
+        out["seKg"].append((ev.term_w * gj[:, None]).std(axis=0, ddof=1) / np.sqrt(N))
+        out["steps"].append(ev.nsteps.sum())
+    r = {k: np.array(v) for k, v in out.items()}
+    r["B"] = r["B"].transpose(1, 0, 2)
+    r["K"] = r["K"].transpose(1, 0, 2)
+    return r
+
+
+def _check_f32_rows(g, ref, rows, bn_g):
+    fg = _row_functionals(g["A"][rows], g["B"][:, rows], g["H"][rows], g["K"][:, rows], bn_g)
+    fr = _row_functionals(ref["A"], ref["B"], ref["H"], ref["K"], bn_g)
+    assert np.all(np.abs(fg["A1"] - fr["A1"]) <= 4 * ref["seA1"])
+    assert np.all(np.abs(fg["B1"] - fr["B1"]) <= 4 * ref["seB1"].T)
+    assert np.all(np.abs(fg["Hg"] - fr["Hg"]) <= 4 * ref["seHg"])
+    assert np.all(np.abs(fg["Kg"] - fr["Kg"]) <= 4 * ref["seKg"].T)
+    # entries: the same walks up to FP32 branch flips, which move a few
+    # tallies between neighbouring cells; the mass moved stays below 1 %
+    for key in ("A", "B", "H", "K"):
+        ga = g[key][rows] if key in ("A", "H") else g[key][:, rows]
+        ra = ref[key]
+        moved = np.abs(ga - ra).sum(axis=-1)
+        mass = np.abs(ra).sum(axis=-1)
+        assert np.all(moved <= 0.01 * mass), (key, (moved / mass).max())
+
+
+def test_square_fp32_small():
+    dom = W.unit_square()
+    sites = W.sample_sites(dom, 96, 21, 1e-3)
+    bn = W.square_nodes(16)
+    walks, eps, seed = 4000, 1e-4, 5
+    tb = _gpu_tb(dom, sites, bn, walks, eps, seed, precision="f32", volume_samples=1 << 16)
+    g = _export_all(tb)
+    rows = np.arange(0, 96, 7)
+    gb = bn[:, 0] ** 2 - bn[:, 1] ** 2
+    ref = _oracle_rows_with_se(dom, sites, bn, walks, eps, seed, rows, gb)
+    _check_f32_rows(g, ref, rows, gb)
+    assert np.all(g["Hcount"].sum(axis=1) == walks)
+
+
+def test_square1024_fp32_full_size_sampled_rows():
+    """The 2-D unit-square configuration at full size, in the launch shape the
+    benchmark times: 1024 sites, 256 boundary nodes, 1e4 walks, eps 1e-4, FP32.
+    The oracle recomputes 6 sampled rows (rows are independent streams)."""
+    c = W.config("square1024")
+    tb = _gpu_tb(c["domain"], c["sites"], c["bnodes"], c["walks"], c["eps"], c["seed"], precision="f32")
+    g = _export_all(tb)
+    info = tb.info()
+    assert info["walks"] == 1024 * 10000
+    assert np.all(g["Hcount"].sum(axis=1) == c["walks"])          # each walk exits once
+    rows = np.array([0, 1, 257, 511, 800, 1023])
+    gb = c["bnodes"][:, 0] ** 2 - c["bnodes"][:, 1] ** 2
+    ref = _oracle_rows_with_se(c["domain"], c["sites"], c["bnodes"], c["walks"], c["eps"], c["seed"], rows, gb)
+    _check_f32_rows(g, ref, rows, gb)
+    # harmonic extension of x^2 - y^2 at every site (accuracy, not parity):
+    # bias from binning g on the boundary cells is O(h^2)
+    hg = g["H"] @ gb
+    exact = c["sites"][:, 0] ** 2 - c["sites"][:, 1] ** 2
+    assert np.sqrt(np.mean((hg - exact) ** 2)) < 0.01
+
+
+# ----------------------------------------------------------------- apply
+
+
+def test_apply_matches_exported_matrices():
+    dom = W.unit_disk()
+    sites = W.sample_sites(dom, 70, 2, 1e-3)
+    bn = W.circle_nodes(33)
+    for prec in ("f64", "f32"):
+        tb = _gpu_tb(dom, sites, bn, 500, 1e-3, 6, precision=prec, volume_samples=1 << 12)
+        g = _export_all(tb)
+        rng = np.random.default_rng(0)
+        fbar = rng.normal(size=70)
+        gg = rng.normal(size=33)
+        u, gu = tb.apply(torch.tensor(fbar, device="cuda"), torch.tensor(gg, device="cuda"))
+        torch.cuda.synchronize()
+        A = g["A"].astype(np.float64)
+        ref_u = A @ fbar + g["H"].astype(np.float64) @ gg
+        ref_g = np.einsum("anm,m->an", g["B"].astype(np.float64), fbar) + \
+            np.einsum("anp,p->an", g["K"].astype(np.float64), gg)
+        assert np.allclose(_np(u), ref_u, rtol=1e-12, atol=1e-12)
+        assert np.allclose(_np(gu), ref_g, rtol=1e-12, atol=1e-12)
+
+
+def test_disk_poisson_direct_apply():
+    """-Lap u = 1 on the unit disk: (1/2) A 1 -> (1 - |x|^2)/4 (accuracy)."""
+    c = W.config("disk64")
+    tb = _gpu_tb(c["domain"], c["sites"], c["bnodes"], 20000, c["eps"], 1, precision="f64",
+                 volume_samples=1 << 12)
+    u, _ = tb.apply(torch.full((64,), 0.5, dtype=torch.float64, device="cuda"),
+                    torch.zeros(64, dtype=torch.float64, device="cuda"))
+    exact = (1 - (c["sites"] ** 2).sum(1)) / 4
+    assert np.abs(_np(u) - exact).max() < 0.01
