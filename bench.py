@@ -28,9 +28,15 @@ sys.path.insert(0, ROOT)
 METRIC = "WoS walk-steps/s (toolbox build)"
 MI355X_CUS = 256
 MI355X_CLOCK = 2.4e9
-LANE_OPS_PEAK = MI355X_CUS * 64 * MI355X_CLOCK          # non-packed FP32 lane-ops/s
+# FP32 vector peak 157.3 TFLOP/s = 256 CU x 128 FMA lanes x 2.4 GHz: 7.86e13
+# full-rate lane-ops/s (one FMA = one lane-op).  Measured on gfx950: plain
+# (non-packed) FP32 and INT32 VALU ops issue at 128 lanes/clk/CU, FP64 FMA,
+# v_mul_hi at 64, transcendentals and 32x32->64 multiplies at 32.
+LANE_OPS_PEAK = MI355X_CUS * 128 * MI355X_CLOCK
 # Algorithmic lane-op budget of the walker (slots: full-rate op = 1,
-# transcendental / 32-bit integer multiply = 4), per walk-step and per walk.
+# transcendental / 32-bit integer multiply = 4), per walk-step and per walk
+# (the per-step and per-walk counts of the method: distance, tally point,
+# nearest-centre scan, tally weights, direction, move, Philox words).
 WALKER_BUDGET = {  # (C_step, C_walk) by workload geometry
     "disk": (113, 450), "square": (113, 450), "lshape": (187, 450), "ball": (216, 700), "cubeball": (228, 700),
 }
@@ -43,7 +49,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="square1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=2)
+    ap.add_argument("--cpu-rows", type=int, default=3)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, copy a MIB-sized device buffer 3 times (a known-size "
+                         "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -95,7 +104,6 @@ def main():
     for k in range(a.warmup):
         step(k)
     torch.cuda.synchronize()
-    infos = []
     t0 = time.perf_counter()
     for k in range(a.steps):
         step(a.warmup + k)
@@ -142,6 +150,13 @@ def main():
                      "frac": achieved / peak, "traffic": None,
                      "budget": {"per_walk_step": c_step, "per_walk": c_walk}},
     }
+    if a.calibrate_copy > 0:
+        src = torch.ones(a.calibrate_copy * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = src.numel() * 4
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_rows)
     print(json.dumps(out), flush=True)

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -190,7 +191,7 @@ DomainDev<T> to_dev(const HostDomain& d) {
 struct DevGrid {
   int n[3] = {1, 1, 1};
   double lo[3] = {0, 0, 0}, h[3] = {1, 1, 1};
-  int* cell = nullptr;
+  int4* rec = nullptr;
   int* list = nullptr;
   size_t ncell = 0, nlist = 0;
   double frac_single = 1, mean_multi = 1;
@@ -205,7 +206,7 @@ GridDev<T> view(const DevGrid& g, const void* pts) {
     v.lo[a] = (T)g.lo[a];
     v.inv_h[a] = (T)(1.0 / g.h[a]);
   }
-  v.cell = g.cell;
+  v.rec = g.rec;
   v.list = g.list;
   v.pts = static_cast<const T*>(pts);
   return v;
@@ -219,6 +220,9 @@ struct wos_toolbox {
   int dim = 0, n = 0, m = 0, p = 0;
   bool f64 = false;
   int items_per_site = 1, walks_per_item = 1, regen_T = 32;
+  int acc_fixed = 1;
+  int serve_T = 16;
+  int* d_item_order = nullptr;
   std::vector<double> sites, bnodes;
   // device
   DevGrid gv, gg;
@@ -278,12 +282,12 @@ wos_status upload_grid(wos_toolbox* tb, const GridHost& h, DevGrid* g) {
     g->lo[a] = h.lo[a];
     g->h[a] = h.h[a];
   }
-  g->ncell = h.cell.size();
+  g->ncell = h.rec.size() / 4;
   g->nlist = h.list.size();
   g->frac_single = h.frac_single;
   g->mean_multi = h.mean_multi;
   g->max_cand = h.max_cand;
-  wos_status s = upload(tb, (void**)&g->cell, h.cell.data(), h.cell.size() * sizeof(int));
+  wos_status s = upload(tb, (void**)&g->rec, h.rec.data(), h.rec.size() * sizeof(int));
   if (s != WOS_OK) return s;
   return upload(tb, (void**)&g->list, h.list.data(), h.list.size() * sizeof(int));
 }
@@ -294,9 +298,10 @@ void release(wos_toolbox* tb) {
       (void)hipEventDestroy(e);
       e = nullptr;
     }
-  void* ptrs[] = {tb->gv.cell, tb->gv.list, tb->gg.cell, tb->gg.list, tb->d_sites_f32,
+  void* ptrs[] = {tb->gv.rec, tb->gv.list, tb->gg.rec, tb->gg.list, tb->d_sites_f32,
                   tb->d_sites_f64, tb->d_bnodes, tb->d_segs, tb->d_verts, tb->d_A, tb->d_B,
-                  tb->d_K, tb->d_H, tb->d_Hc, tb->d_vcount, tb->d_stats, tb->d_lambda};
+                  tb->d_K, tb->d_H, tb->d_Hc, tb->d_vcount, tb->d_stats, tb->d_lambda,
+                  tb->d_item_order};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -410,14 +415,23 @@ wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_
     return fail(WOS_ENOTIMPL, "site rows need %zu bytes of LDS (> 160 KiB); reduce n or p", lds);
   }
 
-  // work split: enough (site, chunk) items to fill the chip
+  // work split: about one (site, chunk) item per workgroup slot of the chip
   const int64_t N = opts->walks_per_site;
   if (opts->walks_per_item > 0) {
     tb->walks_per_item = (int)std::min<int64_t>(opts->walks_per_item, N);
   } else {
-    const int64_t target_items = 2048;
-    const int64_t ips = std::max<int64_t>(1, (target_items + n - 1) / n);
-    tb->walks_per_item = (int)((N + ips - 1) / ips);
+    const int bs = walker_block_size(lds);
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(160 * 1024 / std::max<size_t>(lds, 1), 2048 / bs));
+    const int64_t slots = 256 * per_cu;
+    const int64_t ips = std::max<int64_t>(1, 2 * slots / n);
+    const int64_t floor_w = std::min<int64_t>(N, 4 * (int64_t)bs);  // >= 4 walks per lane
+    tb->walks_per_item = (int)std::max<int64_t>((N + ips - 1) / ips, floor_w);
+  }
+  {
+    const char* e = std::getenv("WOS_TALLY");
+    tb->acc_fixed = (e && std::strcmp(e, "f64") == 0) ? 0 : 1;
+    const char* st = std::getenv("WOS_SERVE_T");
+    if (st) tb->serve_T = std::max(1, std::min(64, std::atoi(st)));
   }
   tb->items_per_site = (int)((N + tb->walks_per_item - 1) / tb->walks_per_item);
   if ((int64_t)tb->items_per_site * n > (int64_t)INT32_MAX) {
@@ -446,6 +460,22 @@ wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_
       return s;         \
     }                   \
   } while (0)
+  {
+    // items in order of decreasing expected work: walks from sites far from
+    // the boundary take more steps
+    std::vector<int> site_rank(n);
+    std::vector<double> r0(n);
+    for (int i = 0; i < n; ++i) {
+      site_rank[i] = i;
+      r0[i] = host_distance(hd, sites + (size_t)i * d);
+    }
+    std::stable_sort(site_rank.begin(), site_rank.end(), [&](int a, int b) { return r0[a] > r0[b]; });
+    std::vector<int> order;
+    order.reserve((size_t)n * tb->items_per_site);
+    for (int i : site_rank)
+      for (int c = 0; c < tb->items_per_site; ++c) order.push_back(i * tb->items_per_site + c);
+    TRY(upload(tb, (void**)&tb->d_item_order, order.data(), order.size() * sizeof(int)));
+  }
   TRY(upload_grid(tb, gvh, &tb->gv));
   TRY(upload_grid(tb, ggh, &tb->gg));
   {
@@ -560,7 +590,10 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
     P.k1 = k1;
     P.inv_N = 1.0 / (double)tb->opts.walks_per_site;
     P.regen_T = tb->regen_T;
+    P.serve_T = tb->serve_T;
+    P.item_order = tb->d_item_order;
     P.direct_store = direct ? 1 : 0;
+    P.acc_fixed = 0;  // FP64 toolboxes accumulate in FP64
     P.A = static_cast<double*>(tb->d_A);
     P.B = static_cast<double*>(tb->d_B);
     P.Hc = tb->d_Hc;
@@ -590,7 +623,10 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
     P.k1 = k1;
     P.inv_N = (float)(1.0 / (double)tb->opts.walks_per_site);
     P.regen_T = tb->regen_T;
+    P.serve_T = tb->serve_T;
+    P.item_order = tb->d_item_order;
     P.direct_store = direct ? 1 : 0;
+    P.acc_fixed = tb->acc_fixed;
     P.A = static_cast<float*>(tb->d_A);
     P.B = static_cast<float*>(tb->d_B);
     P.Hc = tb->d_Hc;

@@ -6,9 +6,9 @@
 // be the nearest one for some point of the cell: with c the cell centre,
 // hd its half-diagonal and d* = min_j |c - y_j|, any point q of the cell has
 // its nearest centre within d* + hd of q, hence within d* + 2 hd of c, so
-// {j : |c - y_j| <= d* + 2 hd + margin} is a superset of the answers.  A
-// cell with a single candidate stores that index directly, which is the
-// common case the walker's lookup is built around.  The small relative
+// {j : |c - y_j| <= d* + 2 hd + margin} is a superset of the answers.  Up to
+// four candidates are stored inline in the cell's 16-byte record, so one
+// load resolves almost every lookup; most cells have a single candidate.  The small relative
 // margin absorbs the rounding of a lookup done in FP32 and of cell indices
 // computed in FP32 near cell faces.
 #include <algorithm>
@@ -94,10 +94,11 @@ GridHost build_grid(const double* pts, int npts, int dim, const double* lo, cons
   const double margin = 1e-2 * hd + 1e-9 * extent;
   const int maxn = std::max(n0, std::max(n1, n2));
 
-  g.cell.assign(ncell, 0);
+  g.rec.assign(4 * ncell, -1);
   const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   std::vector<std::vector<int>> lists(nthreads);
   std::vector<std::vector<std::pair<long long, int>>> offs(nthreads);  // (cell, offset in lists[t])
+  std::vector<std::pair<long long, long long>> counts(nthreads, {0, 0});  // multi cells, candidates
 
   auto work = [&](unsigned t) {
     std::vector<int> cand;
@@ -150,8 +151,12 @@ GridHost build_grid(const double* pts, int npts, int dim, const double* lo, cons
             }
           }
       std::sort(cand.begin(), cand.end());
-      if (cand.size() == 1) {
-        g.cell[cid] = cand[0];
+      if (cand.size() <= 4) {
+        for (size_t c = 0; c < cand.size(); ++c) g.rec[4 * cid + c] = cand[c];
+        if (cand.size() > 1) {
+          counts[t].first++;
+          counts[t].second += (long long)cand.size();
+        }
       } else {
         offs[t].push_back({cid, (int)lists[t].size()});
         lists[t].push_back((int)cand.size());
@@ -169,15 +174,25 @@ GridHost build_grid(const double* pts, int npts, int dim, const double* lo, cons
   long long nmulti = 0, sumc = 0;
   int maxc = 1;
   for (unsigned t = 0; t < nthreads; ++t) {
+    nmulti += counts[t].first;
+    sumc += counts[t].second;
+    if (counts[t].first) maxc = std::max(maxc, 2);
+  }
+  for (unsigned t = 0; t < nthreads; ++t) {
     const int base = (int)g.list.size();
     g.list.insert(g.list.end(), lists[t].begin(), lists[t].end());
     for (auto& pr : offs[t]) {
-      g.cell[pr.first] = -(base + pr.second) - 1;
+      g.rec[4 * pr.first] = -(base + pr.second) - 1;
       const int cnt = lists[t][pr.second];
       nmulti++;
       sumc += cnt;
       maxc = std::max(maxc, cnt);
     }
+  }
+  for (long long cid = 0; cid < ncell; ++cid) {
+    int c = 0;
+    while (c < 4 && g.rec[4 * cid + c] >= 0) ++c;
+    if (g.rec[4 * cid] >= 0) maxc = std::max(maxc, c);
   }
   if (g.list.empty()) g.list.push_back(0);
   g.frac_single = 1.0 - (double)nmulti / (double)ncell;

@@ -11,8 +11,11 @@ struct GridHost {
   int n[3] = {1, 1, 1};
   double lo[3] = {0, 0, 0};
   double h[3] = {1, 1, 1};
-  std::vector<int> cell;  // >= 0: the only candidate; < 0: -(offset + 1) into list
-  std::vector<int> list;  // [count, j_1 < j_2 < ...] blocks
+  // One 16-byte record per cell: up to four candidates inline, ascending,
+  // unused slots -1; a cell with more candidates stores x = -(offset + 1)
+  // into `list` ([count, j_1 < j_2 < ...]).
+  std::vector<int> rec;   // 4 ints per cell
+  std::vector<int> list;
   double frac_single = 1.0;
   double mean_multi = 1.0;
   int max_cand = 1;

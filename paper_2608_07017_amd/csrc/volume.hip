@@ -17,78 +17,76 @@ namespace wos {
 namespace {
 
 constexpr int kVolBlock = 256;
-constexpr int kHistLdsMax = 15360;  // sites whose counts fit in LDS (60 KiB)
+constexpr int kHistLdsMax = 8192;  // sites whose counts are binned in LDS (32 KiB, dynamic)
 
 #pragma clang fp contract(off)
 
+template <int D, int KIND>
 __device__ __forceinline__ bool inside_exact(const VolumeParams& P, const double* x) {
-  switch (P.dom.kind) {
-    case WOS_BALL: {
-      double s = 0.0;
-      for (int a = 0; a < P.dim; ++a) {
-        const double t = x[a] - P.dom.c[a];
-        const double tt = t * t;
-        s = (a == 0) ? tt : s + tt;
+  if constexpr (KIND == WOS_BALL) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double t = x[a] - P.dom.c[a];
+      const double tt = t * t;
+      s = (a == 0) ? tt : s + tt;
+    }
+    return s < P.dom.rad * P.dom.rad;
+  } else if constexpr (KIND == WOS_BOX) {
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) in = in && (x[a] > P.dom.lo[a]) && (x[a] < P.dom.hi[a]);
+    return in;
+  } else if constexpr (KIND == WOS_POLYGON) {
+    bool odd = false;
+    for (int e = 0; e < P.nvert; ++e) {
+      const int f = (e + 1 == P.nvert) ? 0 : e + 1;
+      const double a0 = P.verts[2 * e], a1 = P.verts[2 * e + 1];
+      const double b0 = P.verts[2 * f], b1 = P.verts[2 * f + 1];
+      const bool crosses = (a1 > x[1]) != (b1 > x[1]);
+      if (crosses) {
+        const double num = (x[1] - a1) * (b0 - a0);
+        const double xint = a0 + num / (b1 - a1);
+        if (x[0] < xint) odd = !odd;
       }
-      return s < P.dom.rad * P.dom.rad;
     }
-    case WOS_BOX: {
-      bool in = true;
-      for (int a = 0; a < P.dim; ++a) in = in && (x[a] > P.dom.lo[a]) && (x[a] < P.dom.hi[a]);
-      return in;
+    return odd;
+  } else {  // WOS_BOX_MINUS_BALL
+    bool in = true;
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      in = in && (x[a] > P.dom.lo[a]) && (x[a] < P.dom.hi[a]);
+      const double t = x[a] - P.dom.c[a];
+      const double tt = t * t;
+      s = (a == 0) ? tt : s + tt;
     }
-    case WOS_POLYGON: {
-      bool odd = false;
-      for (int e = 0; e < P.nvert; ++e) {
-        const int f = (e + 1 == P.nvert) ? 0 : e + 1;
-        const double a0 = P.verts[2 * e], a1 = P.verts[2 * e + 1];
-        const double b0 = P.verts[2 * f], b1 = P.verts[2 * f + 1];
-        const bool crosses = (a1 > x[1]) != (b1 > x[1]);
-        if (crosses) {
-          const double num = (x[1] - a1) * (b0 - a0);
-          const double xint = a0 + num / (b1 - a1);
-          if (x[0] < xint) odd = !odd;
-        }
-      }
-      return odd;
-    }
-    default: {  // WOS_BOX_MINUS_BALL
-      bool in = true;
-      for (int a = 0; a < P.dim; ++a) in = in && (x[a] > P.dom.lo[a]) && (x[a] < P.dom.hi[a]);
-      double s = 0.0;
-      for (int a = 0; a < P.dim; ++a) {
-        const double t = x[a] - P.dom.c[a];
-        const double tt = t * t;
-        s = (a == 0) ? tt : s + tt;
-      }
-      return in && (s > P.dom.rad * P.dom.rad);
-    }
+    return in && (s > P.dom.rad * P.dom.rad);
   }
 }
 
-__device__ __forceinline__ int nearest_exact(const GridDev<double>& g, int dim, const double* q) {
-  int idx = 0;
-  for (int a = 0; a < dim; ++a) {
-    int c = (int)((q[a] - g.lo[a]) * g.inv_h[a]);
-    c = min(max(c, 0), g.n[a] - 1);
-    idx = idx * g.n[a] + c;
+template <int D>
+__device__ __forceinline__ double d2_exact(const double* pts, int j, const double* q) {
+  const double* y = pts + (size_t)j * PtStride<D>::value;
+  double d2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const double t = q[a] - y[a];
+    const double tt = t * t;
+    d2 = (a == 0) ? tt : d2 + tt;
   }
-  const int code = g.cell[idx];
-  if (code >= 0) return code;
+  return d2;
+}
+
+template <int D>
+__device__ __noinline__ int nearest_exact_list(const GridDev<double>& g, int code, const double* q) {
   const int* lst = g.list + (-code - 1);
   const int cnt = lst[0];
-  const int stride = (dim == 2) ? 2 : 4;
   int bj = lst[1];
-  double best = 1.0e300;
-  for (int c = 0; c < cnt; ++c) {
+  double best = d2_exact<D>(g.pts, bj, q);
+  for (int c = 1; c < cnt; ++c) {
     const int j = lst[1 + c];
-    const double* y = g.pts + (size_t)j * stride;
-    double d2 = 0.0;
-    for (int a = 0; a < dim; ++a) {
-      const double t = q[a] - y[a];
-      const double tt = t * t;
-      d2 = (a == 0) ? tt : d2 + tt;
-    }
+    const double d2 = d2_exact<D>(g.pts, j, q);
     if (d2 < best) {
       best = d2;
       bj = j;
@@ -97,8 +95,49 @@ __device__ __forceinline__ int nearest_exact(const GridDev<double>& g, int dim, 
   return bj;
 }
 
+// Exact FP64 nearest site from a loaded cell record (strict '<' over the
+// ascending candidates: ties to the lowest index).
+template <int D>
+__device__ __forceinline__ int nearest_exact(const GridDev<double>& g, int4 r, const double* q) {
+  if (r.x < 0) return nearest_exact_list<D>(g, r.x, q);
+  int bj = r.x;
+  if (r.y >= 0) {
+    double best = d2_exact<D>(g.pts, r.x, q);
+    const double d1 = d2_exact<D>(g.pts, r.y, q);
+    if (d1 < best) {
+      best = d1;
+      bj = r.y;
+    }
+    if (r.z >= 0) {
+      const double d2 = d2_exact<D>(g.pts, r.z, q);
+      if (d2 < best) {
+        best = d2;
+        bj = r.z;
+      }
+      if (r.w >= 0) {
+        const double d3 = d2_exact<D>(g.pts, r.w, q);
+        if (d3 < best) bj = r.w;
+      }
+    }
+  }
+  return bj;
+}
+
+template <int D>
+__device__ __forceinline__ int cell_exact(const GridDev<double>& g, const double* q) {
+  int idx = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int c = (int)((q[a] - g.lo[a]) * g.inv_h[a]);
+    c = min(max(c, 0), g.n[a] - 1);
+    idx = idx * g.n[a] + c;
+  }
+  return idx;
+}
+
+template <int D, int KIND>
 __global__ __launch_bounds__(kVolBlock) void volume_kernel(VolumeParams P) {
-  __shared__ unsigned int hist[kHistLdsMax];
+  extern __shared__ unsigned int hist[];  // n counters when n <= kHistLdsMax
   __shared__ unsigned long long s_in;
   const bool use_lds = P.n <= kHistLdsMax;
   if (use_lds)
@@ -106,27 +145,41 @@ __global__ __launch_bounds__(kVolBlock) void volume_kernel(VolumeParams P) {
   if (threadIdx.x == 0) s_in = 0ull;
   __syncthreads();
 
-  double ext[3];
-  for (int a = 0; a < P.dim; ++a) ext[a] = P.dom.hi[a] - P.dom.lo[a];
+  double ext[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) ext[a] = P.dom.hi[a] - P.dom.lo[a];
   unsigned int my_in = 0;
+  constexpr int PER = (D == 2) ? 2 : 1;  // points per Philox block
   const int64_t stride = (int64_t)gridDim.x * kVolBlock;
   for (int64_t q = (int64_t)blockIdx.x * kVolBlock + threadIdx.x; q < P.nblocks; q += stride) {
     const uint4 w = philox((uint32_t)((uint64_t)q & 0xFFFFFFFFull), (uint32_t)((uint64_t)q >> 32), 0u,
                            kTagVolume, P.k0, P.k1);
-    const uint32_t words[4] = {w.x, w.y, w.z, w.w};
-    const int per = (P.dim == 2) ? 2 : 1;
-    for (int t = 0; t < per; ++t) {
-      const int64_t pid = q * per + t;
-      if (pid >= P.npoints) break;
-      double x[3];
-      for (int a = 0; a < P.dim; ++a) {
-        const double u = u01<double>(words[t * P.dim + a]);
-        const double prod = ext[a] * u;
-        x[a] = P.dom.lo[a] + prod;
+    double x[PER][D];
+    bool ok[PER];
+    int4 rec[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      if constexpr (D == 2) {
+        const double u0 = u01<double>(t == 0 ? w.x : w.z);
+        const double u1 = u01<double>(t == 0 ? w.y : w.w);
+        const double p0 = ext[0] * u0, p1 = ext[1] * u1;
+        x[t][0] = P.dom.lo[0] + p0;
+        x[t][1] = P.dom.lo[1] + p1;
+      } else {
+        const double p0 = ext[0] * u01<double>(w.x), p1 = ext[1] * u01<double>(w.y),
+                     p2 = ext[2] * u01<double>(w.z);
+        x[t][0] = P.dom.lo[0] + p0;
+        x[t][1] = P.dom.lo[1] + p1;
+        x[t][2] = P.dom.lo[2] + p2;
       }
-      if (!inside_exact(P, x)) continue;
+      ok[t] = (q * PER + t < P.npoints) && inside_exact<D, KIND>(P, x[t]);
+      rec[t] = ok[t] ? P.gv.rec[cell_exact<D>(P.gv, x[t])] : make_int4(0, -1, -1, -1);
+    }
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      if (!ok[t]) continue;
       my_in += 1u;
-      const int j = nearest_exact(P.gv, P.dim, x);
+      const int j = nearest_exact<D>(P.gv, rec[t], x[t]);
       if (use_lds)
         atomicAdd(&hist[j], 1u);
       else
@@ -176,10 +229,30 @@ int grid_for(size_t count, int block) {
 
 hipError_t launch_volume(const VolumeParams& P, hipStream_t stream) {
   if (P.nblocks <= 0) return hipSuccess;
-  int grid = (int)((P.nblocks + kVolBlock * 8 - 1) / (kVolBlock * 8));
-  if (grid > 4096) grid = 4096;
+  // Two workgroups per CU, each thread looping over many points: the per-
+  // workgroup histogram flush (n atomics) is then paid only 512 times.
+  int grid = (int)((P.nblocks + kVolBlock * 4 - 1) / (kVolBlock * 4));
+  if (grid > 512) grid = 512;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(volume_kernel, dim3(grid), dim3(kVolBlock), 0, stream, P);
+  const size_t lds = (P.n <= kHistLdsMax) ? sizeof(unsigned int) * (size_t)P.n : 0;
+  const dim3 g(grid), b(kVolBlock);
+  if (P.dim == 2) {
+    switch (P.dom.kind) {
+      case WOS_BALL: hipLaunchKernelGGL((volume_kernel<2, WOS_BALL>), g, b, lds, stream, P); break;
+      case WOS_BOX: hipLaunchKernelGGL((volume_kernel<2, WOS_BOX>), g, b, lds, stream, P); break;
+      case WOS_POLYGON: hipLaunchKernelGGL((volume_kernel<2, WOS_POLYGON>), g, b, lds, stream, P); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (P.dom.kind) {
+      case WOS_BALL: hipLaunchKernelGGL((volume_kernel<3, WOS_BALL>), g, b, lds, stream, P); break;
+      case WOS_BOX: hipLaunchKernelGGL((volume_kernel<3, WOS_BOX>), g, b, lds, stream, P); break;
+      case WOS_BOX_MINUS_BALL:
+        hipLaunchKernelGGL((volume_kernel<3, WOS_BOX_MINUS_BALL>), g, b, lds, stream, P);
+        break;
+      default: return hipErrorInvalidValue;
+    }
+  }
   return hipGetLastError();
 }
 

@@ -19,16 +19,15 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
                                         uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0;
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    // one 32x32->64 product each (a single multiply-add instruction)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
     c0 = n0;
-    c1 = lo1;
+    c1 = (uint32_t)p1;
     c2 = n2;
-    c3 = lo0;
+    c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -128,13 +127,15 @@ __device__ __forceinline__ T boundary_distance(const DomainDev<T>& dom, const T*
 }
 
 // ------------------------------------------------------ nearest centre
-// Uniform grid over the bounding box; each cell holds either the one centre
-// that is nearest to every point of the cell (code >= 0) or an offset into a
-// list [count, j_1 < j_2 < ...] of every centre that can be nearest somewhere
-// in the cell (code < 0).  The list is scanned with a strict '<', so ties go
-// to the lowest index.
+// Uniform grid over the bounding box.  Each cell's 16-byte record lists, in
+// ascending order, every centre that can be nearest somewhere in the cell
+// (unused slots -1); a cell with more than four candidates holds
+// x = -(offset + 1) into a list [count, j_1 < j_2 < ...].  Candidates are
+// compared with a strict '<' in ascending order, so ties go to the lowest
+// index.  `pts` (centres, PtStride<D> values each) may live in LDS or in
+// global memory.
 template <typename T, int D>
-__device__ __forceinline__ int grid_nearest(const GridDev<T>& g, const T* q) {
+__device__ __forceinline__ int grid_cell(const GridDev<T>& g, const T* q) {
   int idx = 0;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -142,27 +143,69 @@ __device__ __forceinline__ int grid_nearest(const GridDev<T>& g, const T* q) {
     c = min(max(c, 0), g.n[a] - 1);
     idx = idx * g.n[a] + c;
   }
-  const int code = g.cell[idx];
-  if (code >= 0) return code;
+  return idx;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T centre_d2(const T* pts, int j, const T* q) {
+  const T* y = pts + (size_t)j * PtStride<D>::value;
+  T d2 = T(0);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const T t = q[a] - y[a];
+    d2 += t * t;
+  }
+  return d2;
+}
+
+template <typename T, int D>
+__device__ __noinline__ int grid_overflow(const GridDev<T>& g, const T* pts, int code, const T* q) {
   const int* lst = g.list + (-code - 1);
   const int cnt = lst[0];
   int bj = lst[1];
-  T best = T(3.0e38);
-  for (int c = 0; c < cnt; ++c) {
+  T best = centre_d2<T, D>(pts, bj, q);
+  for (int c = 1; c < cnt; ++c) {
     const int j = lst[1 + c];
-    const T* y = g.pts + (size_t)j * PtStride<D>::value;
-    T d2 = T(0);
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const T t = q[a] - y[a];
-      d2 += t * t;
-    }
+    const T d2 = centre_d2<T, D>(pts, j, q);
     if (d2 < best) {
       best = d2;
       bj = j;
     }
   }
   return bj;
+}
+
+// Resolve a loaded record for the point q.
+template <typename T, int D>
+__device__ __forceinline__ int grid_resolve(const GridDev<T>& g, const T* pts, int4 r, const T* q) {
+  if (r.x < 0) return grid_overflow<T, D>(g, pts, r.x, q);
+  int bj = r.x;
+  if (r.y >= 0) {
+    T best = centre_d2<T, D>(pts, r.x, q);
+    const T d1 = centre_d2<T, D>(pts, r.y, q);
+    if (d1 < best) {
+      best = d1;
+      bj = r.y;
+    }
+    if (r.z >= 0) {
+      const T d2 = centre_d2<T, D>(pts, r.z, q);
+      if (d2 < best) {
+        best = d2;
+        bj = r.z;
+      }
+      if (r.w >= 0) {
+        const T d3 = centre_d2<T, D>(pts, r.w, q);
+        if (d3 < best) bj = r.w;
+      }
+    }
+  }
+  return bj;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ int grid_nearest(const GridDev<T>& g, const T* pts, const T* q) {
+  const int4 r = g.rec[grid_cell<T, D>(g, q)];
+  return grid_resolve<T, D>(g, pts, r, q);
 }
 
 }  // namespace wos

@@ -8,6 +8,7 @@
 namespace wos {
 
 size_t walker_lds_bytes(int dim, int m, int p, int nseg, bool f64);
+int walker_block_size(size_t lds);
 hipError_t launch_walker_f32(const WalkerParams<float>& P, int dim, int kind, int items,
                              hipStream_t stream);
 hipError_t launch_walker_f64(const WalkerParams<double>& P, int dim, int kind, int items,

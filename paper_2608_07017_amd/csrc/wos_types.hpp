@@ -1,9 +1,11 @@
 // Plain structures shared by the host runtime and the kernels.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
-#include "../../include/wos.h"
+#include "wos.h"
 
 namespace wos {
 
@@ -33,8 +35,8 @@ struct GridDev {
   int n[3];
   T lo[3];
   T inv_h[3];
-  const int* cell;  // n0*n1*n2 codes, x slowest
-  const int* list;  // [count, indices...] blocks
+  const int4* rec;  // n0*n1*n2 cell records, x slowest
+  const int* list;  // overflow lists [count, indices...]
   const T* pts;     // centres, PtStride<D> values each
 };
 
@@ -55,8 +57,11 @@ struct WalkerParams {
   int fixed_M;
   uint32_t k0, k1;
   T inv_N;
-  int regen_T;
+  int regen_T;     // prepare walks when this many lanes of a wavefront lack one
+  int serve_T;     // serve finished walks when this many lanes are waiting
+  const int* item_order;  // blockIdx -> item (longest expected work first)
   int direct_store;
+  int acc_fixed;   // tally accumulators: 0 FP64, 1 64-bit fixed point
   T* A;
   T* B;
   uint32_t* Hc;
