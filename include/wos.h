@@ -156,6 +156,59 @@ wos_status wos_toolbox_export(const wos_toolbox* tb, int32_t what, void* dst, si
 wos_status wos_apply(const wos_toolbox* tb, const double* fbar, const double* g, double* u,
                      double* grad_u, void* stream);
 
+/* ------------------------------------------------------------- solves */
+typedef enum {
+  WOS_LINEAR = 0,            /* div(A grad u) + b . grad u - c u = f, u = g (eq. linearPDE) */
+  WOS_SEMILINEAR_CUBIC = 1,  /* -Lap u + kappa u^3 = f, u = g: Newton on grad J = 0 for
+                                F = |p|^2/2 + kappa u^4/4 - f u (eq. gradJ)             */
+  WOS_QUASILINEAR = 2        /* -div((1 + u^2) grad u) = f, u = g: Picard, each iterate
+                                the linear problem with A = (1 + u_k^2) I              */
+} wos_problem_kind;
+
+typedef struct {
+  int32_t kind;          /* wos_problem_kind                                        */
+  const double* A;       /* LINEAR: device, n x d x d symmetric A(x_i), or NULL (= I) */
+  const double* b;       /* LINEAR: device, n x d b(x_i), or NULL (= 0)               */
+  const double* c;       /* LINEAR: device, n c(x_i) >= 0, or NULL (= 0)             */
+  double kappa;          /* SEMILINEAR_CUBIC coefficient                            */
+  double rcond;          /* truncated SVD: singular values <= rcond * sigma_max are
+                            dropped; 0 -> 1e-3                                      */
+  double tol;            /* Newton: |grad J| <= tol |grad J(h_0)| (0 -> 1e-8);
+                            Picard: |u_{k+1} - u_k|_lambda <= tol |u_{k+1}|_lambda
+                            (0 -> 1e-10)                                              */
+  int32_t max_iter;      /* outer iterations; 0 -> 50 (Newton), 100 (Picard)        */
+  int32_t max_sweeps;    /* Jacobi sweeps of each eigen-decomposition; 0 -> 40      */
+} wos_coeffs;
+
+typedef struct {
+  int32_t iters;          /* outer iterations taken (1 for LINEAR)               */
+  int32_t rank;           /* singular values kept in the last truncated solve    */
+  int32_t sweeps;         /* Jacobi sweeps of the last eigen-decomposition       */
+  double sigma_max;       /* largest singular value of the last system          */
+  double sigma_threshold; /* rcond * sigma_max: the truncation threshold        */
+  double grad_norm;       /* Newton: final |grad J|                              */
+  double grad_norm0;      /* Newton: |grad J(h_0)|                               */
+  double update_norm;     /* Picard: final |u_{k+1} - u_k|_lambda                */
+} wos_solve_info;
+
+/* Solves a Dirichlet problem on the toolbox's domain (Sec. "Second order
+ * linear elliptic PDEs" and Sec. "Euler-Lagrange boundary value problems"):
+ * assembles Lambda, Sigma and the right-hand side of eq. linear_q from the
+ * toolbox and the coefficients sampled at the sites, solves it with the
+ * truncated SVD, and reconstructs u = A q + H g, grad u = B q + K g.
+ *   f       device double (n): f(x_i) in the convention of `kind`
+ *   g       device double (p): g(z_j)
+ *   u       device double (n) output; grad_u device (d x n) or NULL;
+ *   q       device double (m) output (the unknown source) or NULL;
+ *   info    host, optional.
+ * Runs on `stream` and synchronises it before returning (the eigensolver
+ * and the outer loops read convergence scalars on the host).  The toolbox
+ * must have been built; its solve workspace (about (d+1) n (m+p) + 4 m^2
+ * doubles) is allocated on the first call and kept.  Not thread-safe for
+ * one toolbox.                                                               */
+wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* coeffs, const double* f, const double* g,
+                     double* u, double* grad_u, double* q, wos_solve_info* info, void* stream);
+
 /* Kernel timing.  When enabled, wos_toolbox_build records HIP events on its
  * stream around the volume kernel, the walker kernel and the normalisation;
  * wos_toolbox_get_timings synchronises and returns their durations in

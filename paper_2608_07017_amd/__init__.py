@@ -14,8 +14,8 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import (EXPORTS, KINDS, PRECISION, WosBuildOpts, WosDomain, WosError, WosToolboxInfo,
-                   check, lib)
+from ._lib import (EXPORTS, KINDS, PRECISION, PROBLEMS, WosBuildOpts, WosCoeffs, WosDomain, WosError,
+                   WosSolveInfo, WosToolboxInfo, check, lib)
 
 __all__ = ["Toolbox", "build_toolbox", "WosError", "lib"]
 
@@ -123,6 +123,35 @@ class Toolbox:
         check(lib().wos_apply(self._h, _dptr(fbar), _dptr(g), _dptr(u),
                               _dptr(gu) if grad else ctypes.c_void_p(0), _stream_handle(stream)))
         return u, gu
+
+    # -------------------------------------------------------------- solve
+    def solve(self, f, g, kind="linear", A=None, b=None, c=None, kappa=1.0, rcond=1e-3, tol=0.0,
+              max_iter=0, max_sweeps=0, stream=None):
+        """Solve a Dirichlet problem (see include/wos.h, wos_solve).
+
+        f: (n,) right-hand side at the sites in the convention of `kind`;
+        g: (p,) boundary data at the nodes; A (n,d,d), b (n,d), c (n,)
+        coefficients at the sites for kind="linear".  Returns
+        (u, grad_u, q, info) with device float64 tensors."""
+        dev = lambda x: None if x is None else torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+        f, g, A, b, c = dev(f), dev(g), dev(A), dev(b), dev(c)
+        if f.numel() != self.n or g.numel() != self.p:
+            raise ValueError("f must have n entries and g p entries")
+        d = self.dim
+        for name, x, size in (("A", A, self.n * d * d), ("b", b, self.n * d), ("c", c, self.n)):
+            if x is not None and x.numel() != size:
+                raise ValueError("%s must have %d entries (sites x its shape)" % (name, size))
+        co = WosCoeffs(kind=PROBLEMS[kind], A=None if A is None else A.data_ptr(),
+                       b=None if b is None else b.data_ptr(), c=None if c is None else c.data_ptr(),
+                       kappa=float(kappa), rcond=float(rcond), tol=float(tol), max_iter=int(max_iter),
+                       max_sweeps=int(max_sweeps))
+        u = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        gu = torch.empty((self.dim, self.n), dtype=torch.float64, device="cuda")
+        q = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        info = WosSolveInfo()
+        check(lib().wos_solve(self._h, ctypes.byref(co), _dptr(f), _dptr(g), _dptr(u), _dptr(gu), _dptr(q),
+                              ctypes.byref(info), _stream_handle(stream)))
+        return u, gu, q, {k: getattr(info, k) for k, _ in info._fields_}
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -43,6 +43,21 @@ class WosToolboxInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_size_t)]
 
 
+class WosCoeffs(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("A", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("c", ctypes.c_void_p), ("kappa", ctypes.c_double), ("rcond", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_sweeps", ctypes.c_int32)]
+
+
+class WosSolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("rank", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("sigma_max", ctypes.c_double), ("sigma_threshold", ctypes.c_double),
+                ("grad_norm", ctypes.c_double), ("grad_norm0", ctypes.c_double),
+                ("update_norm", ctypes.c_double)]
+
+
+PROBLEMS = {"linear": 0, "semilinear_cubic": 1, "quasilinear": 2}
+
 # every symbol include/wos.h declares, with its ctypes signature
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
@@ -55,6 +70,8 @@ SIGNATURES = {
     "wos_toolbox_get_info": (ctypes.c_int, [_P, ctypes.POINTER(WosToolboxInfo)]),
     "wos_toolbox_export": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_size_t, ctypes.c_int32, _P]),
     "wos_apply": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "wos_solve": (ctypes.c_int, [_P, ctypes.POINTER(WosCoeffs), _P, _P, _P, _P, _P,
+                                 ctypes.POINTER(WosSolveInfo), _P]),
     "wos_toolbox_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "wos_toolbox_get_timings": (ctypes.c_int, [_P, _D, _D, _D]),
     "wos_toolbox_free": (None, [_P]),

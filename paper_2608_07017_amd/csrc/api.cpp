@@ -13,13 +13,22 @@
 #include <vector>
 
 #include "grid.hpp"
+#include "toolbox.hpp"
 #include "wos_kernels.hpp"
 
 using namespace wos;
 
 namespace {
-
 thread_local std::string g_err;
+}
+
+namespace wos {
+void set_last_error(const char* msg) { g_err = msg; }
+}  // namespace wos
+
+namespace {
+
+
 
 wos_status fail(wos_status s, const char* fmt, ...) {
   char buf[512];
@@ -40,13 +49,6 @@ wos_status fail(wos_status s, const char* fmt, ...) {
   } while (0)
 
 // ------------------------------------------------------------ host geometry
-// FP64 distance to the boundary and inside test, used to validate sites.
-struct HostDomain {
-  int kind = 0, dim = 0;
-  double c[3] = {0, 0, 0}, rad = 0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-  std::vector<double> verts;
-};
-
 double seg_dist(const double* x, const double* a, const double* b) {
   const double ex = b[0] - a[0], ey = b[1] - a[1];
   double t = ((x[0] - a[0]) * ex + (x[1] - a[1]) * ey) / (ex * ex + ey * ey);
@@ -188,16 +190,6 @@ DomainDev<T> to_dev(const HostDomain& d) {
   return o;
 }
 
-struct DevGrid {
-  int n[3] = {1, 1, 1};
-  double lo[3] = {0, 0, 0}, h[3] = {1, 1, 1};
-  int4* rec = nullptr;
-  int* list = nullptr;
-  size_t ncell = 0, nlist = 0;
-  double frac_single = 1, mean_multi = 1;
-  int max_cand = 1;
-};
-
 template <typename T>
 GridDev<T> view(const DevGrid& g, const void* pts) {
   GridDev<T> v{};
@@ -213,38 +205,6 @@ GridDev<T> view(const DevGrid& g, const void* pts) {
 }
 
 }  // namespace
-
-struct wos_toolbox {
-  HostDomain dom;
-  wos_build_opts opts{};
-  int dim = 0, n = 0, m = 0, p = 0;
-  bool f64 = false;
-  int items_per_site = 1, walks_per_item = 1, regen_T = 32;
-  int acc_fixed = 1;
-  int serve_T = 16;
-  int* d_item_order = nullptr;
-  std::vector<double> sites, bnodes;
-  // device
-  DevGrid gv, gg;
-  void* d_sites_f32 = nullptr;   // padded centres
-  void* d_sites_f64 = nullptr;
-  void* d_bnodes = nullptr;      // toolbox precision, padded
-  void* d_segs = nullptr;        // toolbox precision, 5 per edge
-  double* d_verts = nullptr;
-  void* d_A = nullptr;
-  void* d_B = nullptr;
-  void* d_K = nullptr;
-  void* d_H = nullptr;
-  uint32_t* d_Hc = nullptr;
-  unsigned long long* d_vcount = nullptr;
-  unsigned long long* d_stats = nullptr;  // [0..3] walker, [4] volume inside
-  double* d_lambda = nullptr;
-  size_t bytes = 0;
-  hipStream_t last_stream = nullptr;
-  bool built = false;
-  bool timing = false;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-};
 
 namespace {
 
@@ -293,6 +253,13 @@ wos_status upload_grid(wos_toolbox* tb, const GridHost& h, DevGrid* g) {
 }
 
 void release(wos_toolbox* tb) {
+  {
+    SolveWork& w = tb->sw;
+    void* sp[] = {w.R, w.Lam, w.Sig, w.Lam0, w.Sig0, w.Hess, w.G, w.V, w.E, w.rot, w.pq, w.vec, w.Ac, w.red};
+    for (void* q : sp)
+      if (q) (void)hipFree(q);
+    w = SolveWork();
+  }
   for (auto& e : tb->ev)
     if (e) {
       (void)hipEventDestroy(e);

@@ -1,0 +1,87 @@
+// Host-side state of a toolbox (shared by the C ABI and the solve driver).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "wos.h"
+
+namespace wos {
+
+// Domain description kept on the host (FP64).
+struct HostDomain {
+  int kind = 0, dim = 0;
+  double c[3] = {0, 0, 0}, rad = 0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  std::vector<double> verts;
+};
+
+struct DevGrid {
+  int n[3] = {1, 1, 1};
+  double lo[3] = {0, 0, 0}, h[3] = {1, 1, 1};
+  int4* rec = nullptr;
+  int* list = nullptr;
+  size_t ncell = 0, nlist = 0;
+  double frac_single = 1, mean_multi = 1;
+  int max_cand = 1;
+};
+
+
+// Workspace of the solve path, allocated on first use and kept with the
+// toolbox (sizes depend only on n, m, p, d).
+struct SolveWork {
+  bool ready = false;
+  int M = 0;  // m rounded up to even (Jacobi pairs)
+  double* R = nullptr;      // (d+1) n x (m+p) weighted rows
+  double* Lam = nullptr;    // m x m
+  double* Sig = nullptr;    // m x p
+  double* Lam0 = nullptr;   // m x m   (Newton: A = I, b = c = 0)
+  double* Sig0 = nullptr;   // m x p
+  double* Hess = nullptr;   // m x m
+  double* G = nullptr;      // M x M Jacobi work
+  double* V = nullptr;      // M x M eigenvectors
+  double* E = nullptr;      // M eigenvalues
+  double* rot = nullptr;    // M
+  int* pq = nullptr;        // M
+  double* vec = nullptr;    // scratch vectors, 8 x max(n, M, p)
+  double* Ac = nullptr;     // n x d x d (Picard coefficients)
+  double* red = nullptr;    // 2 reduction slots
+  size_t vlen = 0;
+};
+
+}  // namespace wos
+
+struct wos_toolbox {
+  wos::SolveWork sw;
+  wos::HostDomain dom;
+  wos_build_opts opts{};
+  int dim = 0, n = 0, m = 0, p = 0;
+  bool f64 = false;
+  int items_per_site = 1, walks_per_item = 1, regen_T = 32;
+  int acc_fixed = 1;
+  int serve_T = 16;
+  int* d_item_order = nullptr;
+  std::vector<double> sites, bnodes;
+  // device
+  wos::DevGrid gv, gg;
+  void* d_sites_f32 = nullptr;   // padded centres
+  void* d_sites_f64 = nullptr;
+  void* d_bnodes = nullptr;      // toolbox precision, padded
+  void* d_segs = nullptr;        // toolbox precision, 5 per edge
+  double* d_verts = nullptr;
+  void* d_A = nullptr;
+  void* d_B = nullptr;
+  void* d_K = nullptr;
+  void* d_H = nullptr;
+  uint32_t* d_Hc = nullptr;
+  unsigned long long* d_vcount = nullptr;
+  unsigned long long* d_stats = nullptr;  // [0..3] walker, [4] volume inside
+  double* d_lambda = nullptr;
+  size_t bytes = 0;
+  hipStream_t last_stream = nullptr;
+  bool built = false;
+  bool timing = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+

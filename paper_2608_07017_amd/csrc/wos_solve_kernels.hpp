@@ -1,0 +1,40 @@
+// Launchers of the solve-path kernels (solve.hip).  All FP64 unless noted;
+// `f64` selects the toolbox storage precision of toolbox operands.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace wos {
+
+hipError_t launch_weight_rows(bool f64, const void* A, const void* B, const void* H, const void* K,
+                              const double* lam, const double* Ac, const double* bc, const double* cc, int n,
+                              int m, int p, int d, double* R, hipStream_t st);
+// C (M x N) = alpha L^T X + beta C, L = (nblk) row blocks of n x M: blocks
+// 0..nblk-2 contiguous at Lb, the last at La.
+hipError_t launch_gemm_tn(bool f64, const void* Lb, const void* La, int nblk, int n, int M, const double* X,
+                          int ldx, int N, double* C, int ldc, double alpha, double beta, hipStream_t st);
+hipError_t launch_gemv_t(bool f64, const void* X, int rows, int cols, const double* v, double alpha, double beta,
+                         double* y, hipStream_t st);
+hipError_t launch_gemv_n(bool f64, const void* X, int rows, int cols, const double* v, double alpha, double beta,
+                         double* y, hipStream_t st);
+hipError_t launch_axpby(int n, double a, const double* x, double b, const double* y, double* z, hipStream_t st);
+hipError_t launch_pointwise(int n, const double* lam, const double* u, const double* f, double c0, double c1,
+                            double c2, double c3, double cf, double* out, hipStream_t st);
+// C (cols x cols) += X^T diag(w) X
+hipError_t launch_gram(bool f64, const void* X, int rows, int cols, const double* w, double* C, hipStream_t st);
+// C = X^T X (FP64 X)
+hipError_t launch_gram64(const double* X, int rows, int cols, double* C, hipStream_t st);
+hipError_t launch_jacobi_round(double* G, double* V, int M, int r, double* rot, int* pq, hipStream_t st);
+hipError_t launch_offnorm(const double* G, int M, double* out2, hipStream_t st);
+hipError_t launch_set_identity(double* V, int M, hipStream_t st);
+hipError_t launch_pad_copy(const double* src, int m, int lds, double* dst, int M, hipStream_t st);
+hipError_t launch_diag(const double* G, int M, double* e, hipStream_t st);
+hipError_t launch_tsvd_filter(int M, const double* e, double thr, double* z, hipStream_t st);
+hipError_t launch_symmetrize(double* G, int M, hipStream_t st);
+hipError_t launch_dot(int n, const double* x, const double* y, const double* w, double* out, hipStream_t st);
+hipError_t launch_picard_coef(int n, int d, const double* u, double* Ac, hipStream_t st);
+// out (one double slot) = max |e_i|;  count of |e_i| > thr (as an integer in the slot)
+hipError_t launch_absmax(int n, const double* e, double* out, hipStream_t st);
+hipError_t launch_count_above(int n, const double* e, double thr, double* out, hipStream_t st);
+
+}  // namespace wos

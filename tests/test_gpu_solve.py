@@ -1,0 +1,192 @@
+"""Solve path on the GPU (wos_solve through the C ABI) against the oracle.
+
+The GPU toolbox is exported and handed to the oracle's assembly and
+truncated-SVD solve (FP64, numpy SVD), so both sides solve the same
+system; they must agree to rounding.  The truncation keeps the same
+singular values on both sides only if none sits at the threshold: each case
+checks the gap first.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import linalg as OL
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_2608_07017_amd")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rings(K):
+    pts = []
+    for k in range(1, K + 1):
+        nk = 6 * k - 3
+        r = (k - 0.5) / K
+        th = 2 * np.pi * np.arange(nk) / nk
+        pts.append(np.stack([r * np.cos(th), r * np.sin(th)], 1))
+    return np.concatenate(pts)
+
+
+def _build(dom, sites, bn, walks, eps, precision="f64", seed=11):
+    _say("GPU build", dom["kind"], len(sites), len(bn), walks, precision)
+    tb = P.Toolbox(dom, sites, bn, walks, eps, seed=seed, precision=precision, volume_samples=1 << 18)
+    tb.build()
+    torch.cuda.synchronize()
+    mats = {k: tb.export(k).cpu().numpy().astype(np.float64) for k in ("A", "B", "H", "K", "lambda")}
+    return tb, mats
+
+
+def _lam_rel(u, v, lam):
+    return np.sqrt(np.sum(lam * (u - v) ** 2)) / np.sqrt(np.sum(lam * v ** 2))
+
+
+def _safe_rcond(M, candidates=(1e-3, 2e-3, 5e-3, 1e-2, 3e-2)):
+    s = np.linalg.svd(M, compute_uv=False)
+    for rc in candidates:
+        thr = rc * s[0]
+        if np.min(np.abs(s - thr)) > 1e-4 * thr:
+            return rc, int(np.sum(s > thr))
+    pytest.skip("every candidate threshold sits on a singular value")
+
+
+@pytest.fixture(scope="module")
+def disk_tb():
+    dom = W.unit_disk()
+    sites = _rings(5)
+    return _build(dom, sites, W.circle_nodes(30), 1500, 1e-3)
+
+
+def test_linear_laplace_symmetric(disk_tb):
+    tb, mats = disk_tb
+    n = tb.n
+    lam = mats["lambda"]
+    f = -np.ones(n)          # paper's convention: Lap u = -1
+    g = np.zeros(tb.p)
+    Lam, Sig = OL.assemble(mats, lam)
+    rc, rank = _safe_rcond(Lam)
+    ref = OL.solve_linear(mats, lam, f, g, rcond=rc)
+    u, gu, q, info = tb.solve(f, g, kind="linear", rcond=rc)
+    torch.cuda.synchronize()
+    assert info["rank"] == rank
+    assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < 1e-9
+    assert np.allclose(gu.cpu().numpy(), ref["grad_u"], rtol=1e-7, atol=1e-9)
+    # the system itself: Lambda q = rhs on the kept subspace
+    assert np.isclose(info["sigma_max"], np.linalg.svd(Lam, compute_uv=False)[0], rtol=1e-10)
+
+
+def test_linear_anisotropic_reaction_symmetric(disk_tb):
+    tb, mats = disk_tb
+    n = tb.n
+    lam = mats["lambda"]
+    rng = np.random.default_rng(3)
+    x = _rings(5)
+    th = np.pi * x[:, 0]
+    kap = 1.0 + 9.0 * (0.5 + 0.5 * np.sin(3 * x[:, 1]))
+    R = np.stack([np.stack([np.cos(th), -np.sin(th)], -1), np.stack([np.sin(th), np.cos(th)], -1)], -2)
+    A = R @ (np.eye(2)[None] * np.stack([np.ones(n), kap], -1)[:, None, :]) @ np.transpose(R, (0, 2, 1))
+    c = 0.5 + rng.random(n)
+    f = np.cos(2 * x[:, 0]) + x[:, 1]
+    g = np.sin(np.arctan2(*W.circle_nodes(30).T[::-1]))
+    Lam, Sig = OL.assemble(mats, lam, A, None, c)
+    rc, rank = _safe_rcond(Lam)
+    ref = OL.solve_linear(mats, lam, f, g, Acoef=A, ccoef=c, rcond=rc)
+    u, gu, q, info = tb.solve(f, g, kind="linear", A=A, c=c, rcond=rc)
+    torch.cuda.synchronize()
+    assert info["rank"] == rank
+    assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < 1e-9
+
+
+def test_linear_advection_nonsymmetric(disk_tb):
+    tb, mats = disk_tb
+    n = tb.n
+    lam = mats["lambda"]
+    x = _rings(5)
+    b = np.stack([-x[:, 1], x[:, 0]], 1)       # the paper's Ex. elliptic-div drift
+    A = np.stack([np.stack([2 + x[:, 0] ** 2, x[:, 0] * x[:, 1]], -1),
+                  np.stack([x[:, 0] * x[:, 1], 2 + x[:, 1] ** 2], -1)], -2)
+    c = np.ones(n)
+    f = np.sin(np.pi * x[:, 0])
+    g = np.zeros(tb.p)
+    Lam, Sig = OL.assemble(mats, lam, A, b, c)
+    rc, rank = _safe_rcond(Lam)
+    ref = OL.solve_linear(mats, lam, f, g, Acoef=A, bcoef=b, ccoef=c, rcond=rc)
+    u, gu, q, info = tb.solve(f, g, kind="linear", A=A, b=b, c=c, rcond=rc)
+    torch.cuda.synchronize()
+    assert info["rank"] == rank
+    # the right singular vectors come from Lambda^T Lambda: cond^2 rounding
+    assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < 1e-7
+
+
+def test_newton_semilinear_cubic(disk_tb):
+    # The truncated directions keep a gradient component that Newton cannot
+    # remove, so the iteration is compared at a fixed count (tol never met).
+    tb, mats = disk_tb
+    lam = mats["lambda"]
+    x = _rings(5)
+    ue, ge, le = W.smooth_field(7, 2, terms=4, max_freq=2.0, scale=0.5)
+    f = -le(x) + ue(x) ** 3
+    g = ue(W.circle_nodes(30))
+    Lam0, _ = OL.assemble(mats, lam)
+    rc, _ = _safe_rcond(Lam0, (1e-2, 2e-2, 3e-2, 5e-2))
+    ref = OL.newton_cubic(mats, lam, f, g, kappa=1.0, rcond=rc, tol=1e-300, max_iter=6)
+    u, gu, q, info = tb.solve(f, g, kind="semilinear_cubic", kappa=1.0, rcond=rc, tol=1e-300, max_iter=6)
+    torch.cuda.synchronize()
+    assert info["iters"] == ref["iters"] == 6
+    assert np.isclose(info["grad_norm0"], ref["grad_norm0"], rtol=1e-8)
+    assert np.isclose(info["grad_norm"], ref["grad_norm"], rtol=1e-6)
+    assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < 1e-8
+    assert np.allclose(q.cpu().numpy(), ref["h"], rtol=1e-6, atol=1e-8 * np.abs(ref["h"]).max())
+
+
+def test_picard_quasilinear(disk_tb):
+    tb, mats = disk_tb
+    lam = mats["lambda"]
+    x = _rings(5)
+    f = 2.0 + x[:, 0]
+    g = 0.2 * W.circle_nodes(30)[:, 1]
+    Lam0, _ = OL.assemble(mats, lam)
+    rc, _ = _safe_rcond(Lam0, (1e-2, 2e-2, 3e-2, 5e-2))
+    # the update ratio falls by about 10x per sweep here: tol = 1e-9 is met
+    # after a handful of sweeps on both sides, far from any crossing
+    ref = OL.picard_quasilinear(mats, lam, f, g, rcond=rc, tol=1e-9, max_iter=60)
+    u, gu, q, info = tb.solve(f, g, kind="quasilinear", rcond=rc, tol=1e-9, max_iter=60)
+    torch.cuda.synchronize()
+    assert 2 < ref["iters"] < 60
+    assert info["iters"] == ref["iters"]
+    assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < 1e-8
+    # fixed sweep count, tolerance never met
+    ref = OL.picard_quasilinear(mats, lam, f, g, rcond=rc, tol=1e-300, max_iter=4)
+    u, gu, q, info = tb.solve(f, g, kind="quasilinear", rcond=rc, tol=1e-300, max_iter=4)
+    torch.cuda.synchronize()
+    assert info["iters"] == ref["iters"] == 4
+    assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < 1e-8
+
+
+def test_fp32_toolbox_square_linear():
+    dom = W.unit_square()
+    sites, bn = W.paper_square_layout()
+    sites = sites[::4]                 # 100 cell centres, ragged against 64-wide tiles
+    tb, mats = _build(dom, sites, bn, 2000, 1e-4, precision="f32")
+    lam = mats["lambda"]
+    f = np.ones(len(sites))
+    g = bn[:, 0] ** 2 - bn[:, 1] ** 2
+    Lam, _ = OL.assemble(mats, lam)
+    rc, rank = _safe_rcond(Lam)
+    ref = OL.solve_linear(mats, lam, f, g, rcond=rc)
+    u, gu, q, info = tb.solve(f, g, kind="linear", rcond=rc)
+    torch.cuda.synchronize()
+    assert info["rank"] == rank
+    assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < 1e-9
+
+
+def test_solve_rejects_bad_input(disk_tb):
+    tb, _ = disk_tb
+    with pytest.raises(P.WosError):
+        tb.solve(np.zeros(tb.n), np.zeros(tb.p), kind="linear", rcond=2.0)
