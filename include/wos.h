@@ -87,8 +87,13 @@ typedef struct {
   int32_t precision;        /* wos_precision of the walk arithmetic and tallies   */
   int64_t volume_samples;   /* candidate points for lambda_i; 0 -> 2^24           */
   int32_t walks_per_item;   /* walks one workgroup takes per site; 0 -> automatic */
-  int32_t regen_threshold;  /* idle lanes per wavefront that trigger new walks;
-                               0 -> automatic (1 .. 64)                            */
+  int32_t regen_threshold;  /* free slots of a wavefront's pool of prepared walks
+                               that trigger a refill; 0 -> 48 (1 .. 64)           */
+  int32_t autotune;         /* 1: the first build times the walker at each supported
+                               workgroup size (256, 448, 512, 1024) on its own
+                               inputs, keeps the fastest for later builds, and
+                               synchronises the stream once; 0: the size is chosen
+                               by occupancy.  The results do not depend on it.     */
 } wos_build_opts;
 
 typedef struct wos_toolbox wos_toolbox;

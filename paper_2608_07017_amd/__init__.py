@@ -50,7 +50,7 @@ class Toolbox:
     """A resident toolbox {x, z, A, B, H, K, lambda} on the current GPU."""
 
     def __init__(self, domain, sites, bnodes, walks, eps, seed=0, precision="f32", max_steps=0,
-                 fixed_M=0, volume_samples=0, walks_per_item=0, regen_threshold=0):
+                 fixed_M=0, volume_samples=0, walks_per_item=0, regen_threshold=0, autotune=True):
         self.domain = domain
         self.sites = np.ascontiguousarray(np.asarray(sites, dtype=np.float64))
         self.bnodes = np.ascontiguousarray(np.asarray(bnodes, dtype=np.float64))
@@ -64,7 +64,7 @@ class Toolbox:
         opts = WosBuildOpts(walks_per_site=int(walks), eps=float(eps), max_steps=int(max_steps),
                             fixed_M=int(fixed_M), seed=self.seed, precision=PRECISION[precision],
                             volume_samples=int(volume_samples), walks_per_item=int(walks_per_item),
-                            regen_threshold=int(regen_threshold))
+                            regen_threshold=int(regen_threshold), autotune=1 if autotune else 0)
         h = ctypes.c_void_p()
         dp = ctypes.POINTER(ctypes.c_double)
         check(lib().wos_toolbox_create(ctypes.byref(dom), self.sites.ctypes.data_as(dp), self.n,

@@ -31,7 +31,7 @@ class WosBuildOpts(ctypes.Structure):
                 ("max_steps", ctypes.c_int32), ("fixed_M", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
                 ("volume_samples", ctypes.c_int64), ("walks_per_item", ctypes.c_int32),
-                ("regen_threshold", ctypes.c_int32)]
+                ("regen_threshold", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 class WosToolboxInfo(ctypes.Structure):

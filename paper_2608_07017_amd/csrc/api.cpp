@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "grid.hpp"
@@ -197,6 +198,7 @@ GridDev<T> view(const DevGrid& g, const void* pts) {
     v.n[a] = g.n[a];
     v.lo[a] = (T)g.lo[a];
     v.inv_h[a] = (T)(1.0 / g.h[a]);
+    v.top[a] = (T)(g.n[a] - 1);
   }
   v.rec = g.rec;
   v.list = g.list;
@@ -280,6 +282,74 @@ bool finite3(const double* v, int k) {
 }
 
 }  // namespace
+
+#define WOS_TRY(x)                    \
+  do {                                \
+    const wos_status s_ = (x);        \
+    if (s_ != WOS_OK) return s_;      \
+  } while (0)
+
+// Zero what a walker launch accumulates into: its statistics and, when
+// sites are split over several items (atomic flushes), the tallies.
+static wos_status zero_walker_outputs(wos_toolbox* tb, hipStream_t stream) {
+  const size_t ts = tsize(tb);
+  const size_t n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
+  WOS_HIP(hipMemsetAsync(tb->d_stats, 0, 4 * 8, stream));
+  if (tb->items_per_site != 1) {
+    WOS_HIP(hipMemsetAsync(tb->d_A, 0, ts * n * m, stream));
+    WOS_HIP(hipMemsetAsync(tb->d_B, 0, ts * d * n * m, stream));
+    WOS_HIP(hipMemsetAsync(tb->d_K, 0, ts * d * n * p, stream));
+    WOS_HIP(hipMemsetAsync(tb->d_Hc, 0, 4 * n * p, stream));
+  }
+  return WOS_OK;
+}
+
+template <typename T>
+static void fill_walker_params(const wos_toolbox* tb, uint32_t k0, uint32_t k1, int block, WalkerParams<T>& P) {
+  const bool f64 = std::is_same<T, double>::value;
+  P.dom = to_dev<T>(tb->dom);
+  P.segs = static_cast<const T*>(tb->d_segs);
+  P.nseg = (int)tb->dom.verts.size() / 2;
+  P.sites = static_cast<const T*>(f64 ? tb->d_sites_f64 : tb->d_sites_f32);
+  P.gv = view<T>(tb->gv, f64 ? tb->d_sites_f64 : tb->d_sites_f32);
+  P.gg = view<T>(tb->gg, tb->d_bnodes);
+  P.n = tb->n;
+  P.m = tb->m;
+  P.p = tb->p;
+  P.walks = tb->opts.walks_per_site;
+  P.walks_per_item = tb->walks_per_item;
+  P.items_per_site = tb->items_per_site;
+  P.eps = (T)tb->opts.eps;
+  P.max_steps = tb->opts.max_steps;
+  P.fixed_M = tb->opts.fixed_M;
+  P.k0 = k0;
+  P.k1 = k1;
+  P.inv_N = (T)(1.0 / (double)tb->opts.walks_per_site);
+  P.regen_T = tb->regen_T;
+  P.block_override = block;
+  P.item_order = tb->d_item_order;
+  P.direct_store = tb->items_per_site == 1 ? 1 : 0;
+  P.acc_fixed = f64 ? 0 : tb->acc_fixed;  // FP64 toolboxes accumulate in FP64
+  P.A = static_cast<T*>(tb->d_A);
+  P.B = static_cast<T*>(tb->d_B);
+  P.Hc = tb->d_Hc;
+  P.K = static_cast<T*>(tb->d_K);
+  P.stats = tb->d_stats;
+}
+
+static wos_status launch_walker(const wos_toolbox* tb, uint32_t k0, uint32_t k1, int block, hipStream_t stream) {
+  const int items = tb->items_per_site * tb->n;
+  if (tb->f64) {
+    WalkerParams<double> P{};
+    fill_walker_params<double>(tb, k0, k1, block, P);
+    WOS_HIP(launch_walker_f64(P, tb->dim, tb->dom.kind, items, stream));
+  } else {
+    WalkerParams<float> P{};
+    fill_walker_params<float>(tb, k0, k1, block, P);
+    WOS_HIP(launch_walker_f32(P, tb->dim, tb->dom.kind, items, stream));
+  }
+  return WOS_OK;
+}
 
 extern "C" {
 
@@ -373,7 +443,7 @@ wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_
   tb->bnodes.assign(bnodes, bnodes + (size_t)p * d);
   if (tb->opts.max_steps == 0) tb->opts.max_steps = kDefaultMaxSteps;
   if (tb->opts.volume_samples == 0) tb->opts.volume_samples = (int64_t)1 << 24;
-  tb->regen_T = tb->opts.regen_threshold ? tb->opts.regen_threshold : 32;
+  tb->regen_T = tb->opts.regen_threshold ? tb->opts.regen_threshold : 48;
 
   const int nseg = hd.kind == WOS_POLYGON ? dom->nvert : 0;
   const size_t lds = walker_lds_bytes(d, n, p, nseg, tb->f64);
@@ -395,10 +465,11 @@ wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_
     tb->walks_per_item = (int)std::max<int64_t>((N + ips - 1) / ips, floor_w);
   }
   {
+    tb->autotune = opts->autotune != 0;
+    const char* wb = std::getenv("WOS_WALKER_BLOCK");  // fixed workgroup size, for tuning studies
+    if (wb) tb->walker_block = std::atoi(wb);
     const char* e = std::getenv("WOS_TALLY");
     tb->acc_fixed = (e && std::strcmp(e, "f64") == 0) ? 0 : 1;
-    const char* st = std::getenv("WOS_SERVE_T");
-    if (st) tb->serve_T = std::max(1, std::min(64, std::atoi(st)));
   }
   tb->items_per_site = (int)((N + tb->walks_per_item - 1) / tb->walks_per_item);
   if ((int64_t)tb->items_per_site * n > (int64_t)INT32_MAX) {
@@ -412,7 +483,7 @@ wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_
   double vol = 1;
   for (int a = 0; a < d; ++a) vol *= (hi[a] - lo[a]);
   const double sp_v = std::pow(vol / n, 1.0 / d);
-  GridHost gvh = build_grid(sites, n, d, lo, hi, sp_v / (d == 2 ? 6.0 : 3.0), 1 << 24);
+  GridHost gvh = build_grid(sites, n, d, lo, hi, sp_v / (d == 2 ? 8.0 : 4.0), 1 << 24);
   const double bm = host_boundary_measure(hd);
   const double sp_b = d == 2 ? bm / p : std::sqrt(bm / p);
   GridHost ggh = build_grid(bnodes, p, d, lo, hi, sp_b / 4.0, 1 << 23);
@@ -534,75 +605,40 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
   }
   if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[1], stream));
 
-  const int nseg = (int)tb->dom.verts.size() / 2;
-  const int items = tb->items_per_site * n;
-  if (tb->f64) {
-    WalkerParams<double> P{};
-    P.dom = to_dev<double>(tb->dom);
-    P.segs = static_cast<const double*>(tb->d_segs);
-    P.nseg = nseg;
-    P.sites = static_cast<const double*>(tb->d_sites_f64);
-    P.gv = view<double>(tb->gv, tb->d_sites_f64);
-    P.gg = view<double>(tb->gg, tb->d_bnodes);
-    P.n = n;
-    P.m = m;
-    P.p = p;
-    P.walks = tb->opts.walks_per_site;
-    P.walks_per_item = tb->walks_per_item;
-    P.items_per_site = tb->items_per_site;
-    P.eps = tb->opts.eps;
-    P.max_steps = tb->opts.max_steps;
-    P.fixed_M = tb->opts.fixed_M;
-    P.k0 = k0;
-    P.k1 = k1;
-    P.inv_N = 1.0 / (double)tb->opts.walks_per_site;
-    P.regen_T = tb->regen_T;
-    P.serve_T = tb->serve_T;
-    P.item_order = tb->d_item_order;
-    P.direct_store = direct ? 1 : 0;
-    P.acc_fixed = 0;  // FP64 toolboxes accumulate in FP64
-    P.A = static_cast<double*>(tb->d_A);
-    P.B = static_cast<double*>(tb->d_B);
-    P.Hc = tb->d_Hc;
-    P.K = static_cast<double*>(tb->d_K);
-    P.stats = tb->d_stats;
-    WOS_HIP(launch_walker_f64(P, d, tb->dom.kind, items, stream));
-    if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[2], stream));
-    WOS_HIP(launch_h_from_counts_f64(tb->d_Hc, (size_t)n * p, P.inv_N, static_cast<double*>(tb->d_H), stream));
-  } else {
-    WalkerParams<float> P{};
-    P.dom = to_dev<float>(tb->dom);
-    P.segs = static_cast<const float*>(tb->d_segs);
-    P.nseg = nseg;
-    P.sites = static_cast<const float*>(tb->d_sites_f32);
-    P.gv = view<float>(tb->gv, tb->d_sites_f32);
-    P.gg = view<float>(tb->gg, tb->d_bnodes);
-    P.n = n;
-    P.m = m;
-    P.p = p;
-    P.walks = tb->opts.walks_per_site;
-    P.walks_per_item = tb->walks_per_item;
-    P.items_per_site = tb->items_per_site;
-    P.eps = (float)tb->opts.eps;
-    P.max_steps = tb->opts.max_steps;
-    P.fixed_M = tb->opts.fixed_M;
-    P.k0 = k0;
-    P.k1 = k1;
-    P.inv_N = (float)(1.0 / (double)tb->opts.walks_per_site);
-    P.regen_T = tb->regen_T;
-    P.serve_T = tb->serve_T;
-    P.item_order = tb->d_item_order;
-    P.direct_store = direct ? 1 : 0;
-    P.acc_fixed = tb->acc_fixed;
-    P.A = static_cast<float*>(tb->d_A);
-    P.B = static_cast<float*>(tb->d_B);
-    P.Hc = tb->d_Hc;
-    P.K = static_cast<float*>(tb->d_K);
-    P.stats = tb->d_stats;
-    WOS_HIP(launch_walker_f32(P, d, tb->dom.kind, items, stream));
-    if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[2], stream));
-    WOS_HIP(launch_h_from_counts_f32(tb->d_Hc, (size_t)n * p, P.inv_N, static_cast<float*>(tb->d_H), stream));
+  // walker; on the first build with autotuning, every supported workgroup
+  // size is timed on this build's own inputs first and the fastest is kept
+  // (the tallies are exact fixed-point sums, so the result does not depend
+  // on the choice)
+  if (tb->autotune && tb->walker_block == 0) {
+    static const int kCandidates[] = {256, 448, 512, 1024};
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    WOS_HIP(hipEventCreate(&t0));
+    WOS_HIP(hipEventCreate(&t1));
+    float best_ms = 0.0f;
+    int best = 0;
+    for (int bs : kCandidates) {
+      WOS_TRY(zero_walker_outputs(tb, stream));
+      WOS_HIP(hipEventRecord(t0, stream));
+      WOS_TRY(launch_walker(tb, k0, k1, bs, stream));
+      WOS_HIP(hipEventRecord(t1, stream));
+      WOS_HIP(hipEventSynchronize(t1));
+      float ms = 0.0f;
+      WOS_HIP(hipEventElapsedTime(&ms, t0, t1));
+      if (best == 0 || ms < best_ms) best_ms = ms, best = bs;
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    tb->walker_block = best;
+    WOS_TRY(zero_walker_outputs(tb, stream));
   }
+  WOS_TRY(launch_walker(tb, k0, k1, tb->walker_block, stream));
+  if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[2], stream));
+  if (tb->f64)
+    WOS_HIP(launch_h_from_counts_f64(tb->d_Hc, (size_t)n * p, 1.0 / (double)tb->opts.walks_per_site,
+                                     static_cast<double*>(tb->d_H), stream));
+  else
+    WOS_HIP(launch_h_from_counts_f32(tb->d_Hc, (size_t)n * p, (float)(1.0 / (double)tb->opts.walks_per_site),
+                                     static_cast<float*>(tb->d_H), stream));
   if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[3], stream));
   tb->last_stream = stream;
   tb->built = true;

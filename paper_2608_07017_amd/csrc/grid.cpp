@@ -1,4 +1,5 @@
-// Construction of the nearest-centre grids (host, FP64).
+// Construction of the nearest-centre grids (host, FP64).  Records with fewer
+// than four candidates repeat the first one in their unused slots.
 //
 // The toolbox bins points by their nearest centre (Voronoi membership,
 // Sec. "Matrix estimators", and Rem. "implementation_tips" (iii)).  A
@@ -150,9 +151,44 @@ GridHost build_grid(const double* pts, int npts, int dim, const double* lo, cons
               if (d2 <= R2) cand.push_back(j);
             }
           }
+      // Pairwise pruning: candidate j cannot be nearest anywhere in the
+      // (slightly enlarged) cell if some other candidate k is closer on the
+      // whole cell.  With u = q - c and a_j = y_j - c, the difference
+      // |u - a_j|^2 - |u - a_k|^2 = |a_j|^2 - |a_k|^2 + 2 u.(a_k - a_j) is
+      // linear in u, so its minimum over the box is taken at a corner.  The
+      // box is enlarged to cover points that an FP32 cell index assigns to
+      // this cell, and the tolerance keeps near-ties.
+      if (cand.size() > 1) {
+        double hb[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) hb[a] = 0.5 * g.h[a] * (1.0 + 1e-3) + 1e-6 * extent;
+        double hb2 = 0.0;
+        for (int a = 0; a < dim; ++a) hb2 += hb[a] * hb[a];
+        const size_t nc = cand.size();
+        std::vector<double> av(nc * 3, 0.0), aa(nc, 0.0);
+        for (size_t i = 0; i < nc; ++i) {
+          const double* y = pts + (size_t)cand[i] * dim;
+          for (int a = 0; a < dim; ++a) {
+            av[3 * i + a] = y[a] - ctr[a];
+            aa[i] += av[3 * i + a] * av[3 * i + a];
+          }
+        }
+        std::vector<int> kept;
+        for (size_t i = 0; i < nc; ++i) {
+          const double tol = 1e-5 * (aa[i] + hb2);
+          bool dominated = false;
+          for (size_t k = 0; k < nc && !dominated; ++k) {
+            if (k == i) continue;
+            double minf = aa[i] - aa[k];
+            for (int a = 0; a < dim; ++a) minf -= 2.0 * std::fabs(av[3 * k + a] - av[3 * i + a]) * hb[a];
+            dominated = minf > tol;
+          }
+          if (!dominated) kept.push_back(cand[i]);
+        }
+        cand.swap(kept);
+      }
       std::sort(cand.begin(), cand.end());
       if (cand.size() <= 4) {
-        for (size_t c = 0; c < cand.size(); ++c) g.rec[4 * cid + c] = cand[c];
+        for (size_t c = 0; c < 4; ++c) g.rec[4 * cid + c] = cand[c < cand.size() ? c : 0];
         if (cand.size() > 1) {
           counts[t].first++;
           counts[t].second += (long long)cand.size();
@@ -190,9 +226,10 @@ GridHost build_grid(const double* pts, int npts, int dim, const double* lo, cons
     }
   }
   for (long long cid = 0; cid < ncell; ++cid) {
-    int c = 0;
-    while (c < 4 && g.rec[4 * cid + c] >= 0) ++c;
-    if (g.rec[4 * cid] >= 0) maxc = std::max(maxc, c);
+    if (g.rec[4 * cid] < 0) continue;
+    int c = 1;
+    while (c < 4 && g.rec[4 * cid + c] != g.rec[4 * cid]) ++c;
+    maxc = std::max(maxc, c);
   }
   if (g.list.empty()) g.list.push_back(0);
   g.frac_single = 1.0 - (double)nmulti / (double)ncell;

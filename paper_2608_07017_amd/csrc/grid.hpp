@@ -12,7 +12,7 @@ struct GridHost {
   double lo[3] = {0, 0, 0};
   double h[3] = {1, 1, 1};
   // One 16-byte record per cell: up to four candidates inline, ascending,
-  // unused slots -1; a cell with more candidates stores x = -(offset + 1)
+  // unused slots repeating the first; a cell with more candidates stores x = -(offset + 1)
   // into `list` ([count, j_1 < j_2 < ...]).
   std::vector<int> rec;   // 4 ints per cell
   std::vector<int> list;

@@ -58,9 +58,10 @@ struct wos_toolbox {
   wos_build_opts opts{};
   int dim = 0, n = 0, m = 0, p = 0;
   bool f64 = false;
-  int items_per_site = 1, walks_per_item = 1, regen_T = 32;
+  int items_per_site = 1, walks_per_item = 1, regen_T = 48;
+  int walker_block = 0;  // walker workgroup size (0: by occupancy, or tuned at the first build)
+  bool autotune = false;
   int acc_fixed = 1;
-  int serve_T = 16;
   int* d_item_order = nullptr;
   std::vector<double> sites, bnodes;
   // device

@@ -96,30 +96,25 @@ __device__ __noinline__ int nearest_exact_list(const GridDev<double>& g, int cod
 }
 
 // Exact FP64 nearest site from a loaded cell record (strict '<' over the
-// ascending candidates: ties to the lowest index).
+// ascending candidates, repeats of the first included: ties to the lowest
+// index).
 template <int D>
 __device__ __forceinline__ int nearest_exact(const GridDev<double>& g, int4 r, const double* q) {
   if (r.x < 0) return nearest_exact_list<D>(g, r.x, q);
   int bj = r.x;
-  if (r.y >= 0) {
-    double best = d2_exact<D>(g.pts, r.x, q);
-    const double d1 = d2_exact<D>(g.pts, r.y, q);
-    if (d1 < best) {
-      best = d1;
-      bj = r.y;
-    }
-    if (r.z >= 0) {
-      const double d2 = d2_exact<D>(g.pts, r.z, q);
-      if (d2 < best) {
-        best = d2;
-        bj = r.z;
-      }
-      if (r.w >= 0) {
-        const double d3 = d2_exact<D>(g.pts, r.w, q);
-        if (d3 < best) bj = r.w;
-      }
-    }
+  double best = d2_exact<D>(g.pts, r.x, q);
+  const double d1 = d2_exact<D>(g.pts, r.y, q);
+  if (d1 < best) {
+    best = d1;
+    bj = r.y;
   }
+  const double d2 = d2_exact<D>(g.pts, r.z, q);
+  if (d2 < best) {
+    best = d2;
+    bj = r.z;
+  }
+  const double d3 = d2_exact<D>(g.pts, r.w, q);
+  if (d3 < best) bj = r.w;
   return bj;
 }
 
@@ -173,7 +168,7 @@ __global__ __launch_bounds__(kVolBlock) void volume_kernel(VolumeParams P) {
         x[t][2] = P.dom.lo[2] + p2;
       }
       ok[t] = (q * PER + t < P.npoints) && inside_exact<D, KIND>(P, x[t]);
-      rec[t] = ok[t] ? P.gv.rec[cell_exact<D>(P.gv, x[t])] : make_int4(0, -1, -1, -1);
+      rec[t] = ok[t] ? P.gv.rec[cell_exact<D>(P.gv, x[t])] : make_int4(0, 0, 0, 0);
     }
 #pragma unroll
     for (int t = 0; t < PER; ++t) {

@@ -12,15 +12,18 @@
 // workgroup size (256 / 512 / 1024) is the smallest that fills a CU with
 // waves given the LDS each site's rows take.
 //
-// Lanes regenerate walks, so the long tail of walk lengths does not idle a
-// wavefront.  Each lane holds its current walk and one prepared walk (draws
-// made, ball-term and k = 0 tallies done).  Walks are prepared in batches,
-// when at least `regen_T` lanes of the wavefront lack one (or no lane is
-// walking), taking walk indices from the workgroup's counter; a lane whose
-// walk stops waits, with its terminal point, for a service pass (at least
-// `serve_T` such lanes) that bins the terminal points into H and K and
-// starts the prepared walks.  The expensive per-walk work therefore runs on
-// nearly full wavefronts and lanes rarely wait for work.
+// Lanes run walks back to back, so the long tail of walk lengths does not
+// idle a wavefront.  The loop advances in supersteps of four chain steps.
+// Walks start only at superstep boundaries, which makes the Philox block of
+// the next four step draws and the word each step takes the same for every
+// walking lane: the block is generated once per superstep on all walking
+// lanes, and the four steps are unrolled.  Each wavefront keeps a compact
+// pool of prepared walks (per-walk draws made, ball-term and k = 0 tallies
+// done), one per lane slot; lanes whose walk stopped bin its terminal point
+// into H and K and take walks from the top of the pool at the next
+// superstep, and the pool is refilled in one pass over its free slots when
+// at least `regen_T` are free.  The grid record of a step's tally point is
+// loaded one step ahead, so its latency overlaps the previous step's work.
 //
 // Workgroups take items in the order `item_order` gives (longest expected
 // work first), so the short items fill the end of the launch.
@@ -87,6 +90,17 @@ struct Acc<kAccFixed> {
   }
 };
 
+template <typename T, int D, int KIND>
+__device__ __forceinline__ T step_distance(const WalkerParams<T>& P, const T* X, const T* seg) {
+  const T r = boundary_distance<T, D, KIND>(P.dom, X, seg, P.nseg);
+  return P.fixed_M > 0 ? fmax(r, T(0)) : r;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ int4 load_record(const GridDev<T>& g, const T* q) {
+  return g.rec[(unsigned int)grid_cell<T, D>(g, q)];
+}
+
 template <typename T, int D, int KIND, bool PTS_LDS, int kBlock, int ACC>
 __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   using AW = typename Acc<ACC>::word;
@@ -135,204 +149,229 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   const T d_over_r0 = T(D) / r0;
   const T r0sq = r0 * r0;
 
-  // Per-step uniforms: Q steps per Philox block.  Every lane keeps its
-  // current block and the next one; the next block is computed for all
-  // lanes that need it on every Q-th iteration of the wavefront, so the
-  // generator runs on full wavefronts instead of on the few lanes whose
-  // block just ran out.  A lane uses at most one uniform (d = 2) or one
-  // pair (d = 3) per iteration, so the next block is always ready in time.
-  constexpr int Q = (D == 2) ? 4 : 2;
-  constexpr int QM = Q - 1;
+  // Supersteps.  Walks start only at superstep boundaries, so at the start
+  // of a superstep every walking lane is at chain step k = 1 + SS * j: the
+  // Philox block of its next SS step draws and the word each step uses are
+  // the same for the whole wavefront, the block is generated for all
+  // walking lanes at once, and the steps of the superstep are unrolled with
+  // compile-time word indices.
+  constexpr int QB = (D == 2) ? 4 : 2;  // steps per Philox block
+  constexpr int SS = 4;                 // steps per superstep
+  constexpr int NB = SS / QB;           // blocks per superstep
+  constexpr int kWave = 64;
 
-  // Lane state.  Besides its current walk, every lane holds one prepared
-  // walk (its per-walk draws done, its ball-term and k = 0 tallies made).
-  // Walks are prepared in batches, only when most lanes of the wavefront
-  // need one, so the expensive per-walk work runs on nearly full
-  // wavefronts; a lane whose walk stops bins its terminal point and swaps
-  // in its prepared walk in a cheap service pass.
-  constexpr int kIdle = 0, kActive = 1, kDone = 2;
-  int state = kIdle;
-  bool exhausted = false;  // the item's walk pool is used up for this lane
-  T X[D], Y[D], w[D];
-  T omd = T(0);
+  const int lane = (int)__lane_id();
+  const unsigned long long lt_mask = __lanemask_lt();
+
+  // Walking state of the lane.  (r, q, rec) are the distance at X, the tally
+  // point X + r Y and its grid record, computed one step ahead so that the
+  // record load overlaps the previous step's work.
+  bool active = false, done = false;
+  T X[D], Y[D], w[D], q[D];
+  T omd = T(0), r = T(0);
   int k = 0;
   uint32_t l = 0;
-  uint4 cur = make_uint4(0u, 0u, 0u, 0u), nxt = cur;
-  bool nxt_ok = false;
-  int cb = 0;
-  bool pvalid = false;  // prepared walk
+  int4 rec = make_int4(0, 0, 0, 0);
+  // The wavefront's pool of prepared walks (per-walk draws made, ball-term
+  // and k = 0 tallies done): slots 0 .. V-1, one per lane, consumed from the
+  // top by any lane that needs a walk, refilled in one pass over the free
+  // slots when at least regen_T of them are free (or a lane would starve).
+  uint32_t pl = 0;
   T pU1[D], pY[D];
   T pomd = T(0);
-  uint32_t pl = 0;
-  uint4 pcur = cur;
+  int V = 0;
+  bool exhausted = false;
 #pragma unroll
-  for (int a = 0; a < D; ++a) X[a] = Y[a] = w[a] = pU1[a] = pY[a] = T(0);
-  unsigned int lane_steps = 0, lane_walks = 0, lane_capped = 0, lane_maxk = 0;
-  const unsigned long long lt_mask = __lanemask_lt();
-  unsigned int iter = 0;
+  for (int a = 0; a < D; ++a) X[a] = Y[a] = w[a] = q[a] = pU1[a] = pY[a] = T(0);
+  unsigned long long n_walks = 0;  // wave-uniform
+  unsigned int lane_steps = 0, lane_capped = 0, lane_maxk = 0;
 
   while (true) {
-    const unsigned long long act = __ballot(state == kActive);
-    const unsigned long long live =
-        __ballot(state != kIdle || pvalid || !exhausted);
-    if (live == 0ull) break;
+    const unsigned long long idle = __ballot(!active);
+    const int c = __popcll(idle);
 
-    // ---- prepare walks for the lanes that have none
-    const unsigned long long need = __ballot(!pvalid && !exhausted);
-    if (need != 0ull && (__popcll(need) >= P.regen_T || act == 0ull)) {
-      const int nw = __popcll(need);
-      const int leader = __ffsll((long long)need) - 1;
+    // ---- prepare walks into the free pool slots V .. 63
+    if (!exhausted && (kWave - V >= P.regen_T || c > V)) {
+      const int want = kWave - V;
       unsigned int base = 0u;
-      if ((int)__lane_id() == leader) base = atomicAdd(&s_next, (unsigned int)nw);
-      base = __shfl(base, leader);
-      if (!pvalid && !exhausted) {
-        const int64_t lw = l_begin + (int64_t)base + __popcll(need & lt_mask);
-        if (lw >= l_end) {
-          exhausted = true;
+      if (lane == 0) base = atomicAdd(&s_next, (unsigned int)want);
+      base = __builtin_amdgcn_readfirstlane(base);
+      const int64_t first = l_begin + (int64_t)base;
+      const int avail = (int)max((int64_t)0, min((int64_t)want, l_end - first));
+      if (avail < want) exhausted = true;
+      if (lane >= V && lane < V + avail) {
+        pl = (uint32_t)(first + (lane - V));
+        // per-walk draws (counter blocks 0, 1 [, 2])
+        const uint4 b0 = philox(pl, (uint32_t)site, 0u, kTagWalk, P.k0, P.k1);
+        const uint4 b1 = philox(pl, (uint32_t)site, 1u, kTagWalk, P.k0, P.k1);
+        const T u1 = u01<T>(b0.x), u2 = u01<T>(b0.y), u3 = u01<T>(b0.z);
+        const T R = fmax(fmin(u1, u2), fmin(fmax(u1, u2), u3));  // median of three
+        const T S = T(1) - dsqrt(u01<T>(b0.w));
+        T Z[D], Zs[D];
+        T om;
+        if constexpr (D == 2) {
+          dir2(u01<T>(b1.x), Z);
+          dir2(u01<T>(b1.y), Zs);
+          dir2(u01<T>(b1.z), pU1);
+          om = omega2<T>(R);
         } else {
-          // per-walk draws (counter blocks 0, 1 [, 2]) and the first step block
-          pl = (uint32_t)lw;
-          const uint4 b0 = philox(pl, (uint32_t)site, 0u, kTagWalk, P.k0, P.k1);
-          const uint4 b1 = philox(pl, (uint32_t)site, 1u, kTagWalk, P.k0, P.k1);
-          pcur = philox(pl, (uint32_t)site, (uint32_t)kStepBlock0, kTagWalk, P.k0, P.k1);
-          const T u1 = u01<T>(b0.x), u2 = u01<T>(b0.y), u3 = u01<T>(b0.z);
-          const T R = fmax(fmin(u1, u2), fmin(fmax(u1, u2), u3));  // median of three
-          const T S = T(1) - dsqrt(u01<T>(b0.w));
-          T Z[D], Zs[D];
-          T om;
-          if constexpr (D == 2) {
-            dir2(u01<T>(b1.x), Z);
-            dir2(u01<T>(b1.y), Zs);
-            dir2(u01<T>(b1.z), pU1);
-            om = omega2<T>(R);
-          } else {
-            const uint4 b2 = philox(pl, (uint32_t)site, 2u, kTagWalk, P.k0, P.k1);
-            dir3(u01<T>(b1.x), u01<T>(b1.y), Z);
-            dir3(u01<T>(b1.z), u01<T>(b1.w), Zs);
-            dir3(u01<T>(b2.x), u01<T>(b2.y), pU1);
-            om = T(1);
-          }
-          pomd = om / T(D);
-#pragma unroll
-          for (int a = 0; a < D; ++a) pY[a] = R * Z[a];
-          // ball term of B: r0 * sum_{k<d} S^k * Zs at the cell of x + r0 S Zs,
-          // and the k = 0 term of A: omega r0^2 / d at the cell of x + r0 Y
-          T qb[D], q0[D];
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            qb[a] = x[a] + r0 * S * Zs[a];
-            q0[a] = x[a] + r0 * pY[a];
-          }
-          const int4 rb = P.gv.rec[grid_cell<T, D>(P.gv, qb)];
-          const int4 r0c = P.gv.rec[grid_cell<T, D>(P.gv, q0)];
-          T poly = T(1) + S;
-          if constexpr (D == 3) poly += S * S;
-          const T bw = r0 * poly;
-          const int jb = grid_resolve<T, D>(P.gv, vpts, rb, qb);
-#pragma unroll
-          for (int a = 0; a < D; ++a) Acc<ACC>::add(&sB[a * m + jb], bw * Zs[a]);
-          const int j0 = grid_resolve<T, D>(P.gv, vpts, r0c, q0);
-          Acc<ACC>::add(&sA[j0], pomd * r0sq);
-          lane_steps += 1u;  // the k = 0 tally
-          lane_walks += 1u;
-          pvalid = true;
+          const uint4 b2 = philox(pl, (uint32_t)site, 2u, kTagWalk, P.k0, P.k1);
+          dir3(u01<T>(b1.x), u01<T>(b1.y), Z);
+          dir3(u01<T>(b1.z), u01<T>(b1.w), Zs);
+          dir3(u01<T>(b2.x), u01<T>(b2.y), pU1);
+          om = T(1);
         }
+        pomd = om / T(D);
+#pragma unroll
+        for (int a = 0; a < D; ++a) pY[a] = R * Z[a];
+        // ball term of B: r0 * sum_{k<d} S^k * Zs at the cell of x + r0 S Zs,
+        // and the k = 0 term of A: omega r0^2 / d at the cell of x + r0 Y
+        T qb[D], q0[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          qb[a] = x[a] + r0 * S * Zs[a];
+          q0[a] = x[a] + r0 * pY[a];
+        }
+        const int4 rb = load_record<T, D>(P.gv, qb);
+        const int4 r0c = load_record<T, D>(P.gv, q0);
+        T poly = T(1) + S;
+        if constexpr (D == 3) poly += S * S;
+        const T bw = r0 * poly;
+        const int jb = grid_resolve<T, D>(P.gv, vpts, rb, qb);
+#pragma unroll
+        for (int a = 0; a < D; ++a) Acc<ACC>::add(&sB[a * m + jb], bw * Zs[a]);
+        const int j0 = grid_resolve<T, D>(P.gv, vpts, r0c, q0);
+        Acc<ACC>::add(&sA[j0], pomd * r0sq);
       }
+      V += avail;
+      n_walks += (unsigned long long)avail;
     }
 
-    // ---- service: bin finished walks' terminal points, start prepared walks
-    const unsigned long long serve = __ballot(state == kDone || (state == kIdle && pvalid));
-    if (serve != 0ull && (__popcll(serve) >= P.serve_T || act == 0ull)) {
-      if (state == kDone) {
-        // terminal tallies (eqs. Estimator_H, Estimator_K)
-        const int j = grid_nearest<T, D>(P.gg, P.gg.pts, X);
-        atomicAdd(&sH[j], 1u);
+    // ---- terminal tallies of the walks that stopped (eqs. Estimator_H, _K)
+    if (done) {
+      const int j = grid_nearest<T, D>(P.gg, P.gg.pts, X);
+      atomicAdd(&sH[j], 1u);
 #pragma unroll
-        for (int a = 0; a < D; ++a) Acc<ACC>::add(&sK[a * p + j], w[a]);
-        state = kIdle;
+      for (int a = 0; a < D; ++a) Acc<ACC>::add(&sK[a * p + j], w[a]);
+      done = false;
+    }
+
+    // ---- lanes without a walk take prepared walks from the top of the pool
+    const int take_n = min(c, V);
+    if (take_n > 0) {
+      const int rk = __popcll(idle & lt_mask);
+      const bool take = !active && rk < V;
+      const int src = take ? (V - 1 - rk) : lane;
+      const uint32_t tl = (uint32_t)__shfl((int)pl, src);
+      T tU1[D], tY[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        tU1[a] = __shfl(pU1[a], src);
+        tY[a] = __shfl(pY[a], src);
       }
-      if (state == kIdle && pvalid) {
+      const T tomd = __shfl(pomd, src);
+      if (take) {
         // first step X_1 = x + r0 U1; w = (d / r0) U1
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          X[a] = x[a] + r0 * pU1[a];
-          w[a] = d_over_r0 * pU1[a];
-          Y[a] = pY[a];
+          X[a] = x[a] + r0 * tU1[a];
+          w[a] = d_over_r0 * tU1[a];
+          Y[a] = tY[a];
         }
-        omd = pomd;
-        l = pl;
-        cur = pcur;
-        nxt_ok = false;
-        cb = 0;
+        omd = tomd;
+        l = tl;
         k = 1;
-        pvalid = false;
-        state = kActive;
-      }
-    }
-
-    // ---- wavefront-wide refill of the next step block
-    if ((iter & QM) == 0u) {
-      if (state == kActive && !nxt_ok) {
-        nxt = philox(l, (uint32_t)site, (uint32_t)(kStepBlock0 + cb + 1), kTagWalk, P.k0, P.k1);
-        nxt_ok = true;
-      }
-    }
-    ++iter;
-
-    if (state == kActive) {
-      T r = boundary_distance<T, D, KIND>(P.dom, X, sSeg, P.nseg);
-      bool stop;
-      if (P.fixed_M > 0) {
-        stop = k > P.fixed_M;
-        r = fmax(r, T(0));
-      } else {
-        const bool near = r < P.eps;
-        const bool over = k > P.max_steps;
-        if (over && !near) lane_capped += 1u;
-        stop = near || over;
-      }
-      if (stop) {
-        state = kDone;
-        lane_maxk = max(lane_maxk, (unsigned int)k);
-      } else {
-        // ---- chain tally point X_k + r Y; its cell record is loaded first and
-        //      the move is computed while the load is in flight
-        T q[D];
+        active = true;
+        r = step_distance<T, D, KIND>(P, X, sSeg);
 #pragma unroll
         for (int a = 0; a < D; ++a) q[a] = X[a] + r * Y[a];
-        const int4 rec = P.gv.rec[grid_cell<T, D>(P.gv, q)];
-        T U[D];
-        const int s = (k - 1) & QM;
-        if constexpr (D == 2) {
-          const uint32_t word = (s == 0) ? cur.x : (s == 1) ? cur.y : (s == 2) ? cur.z : cur.w;
-          dir2(u01<T>(word), U);
-        } else {
-          const uint32_t wa = s ? cur.z : cur.x;
-          const uint32_t wb = s ? cur.w : cur.y;
-          dir3(u01<T>(wa), u01<T>(wb), U);
-        }
-        if (s == QM) {
-          cur = nxt;
-          nxt_ok = false;
-          cb += 1;
-        }
+        rec = load_record<T, D>(P.gv, q);
+      }
+      V -= take_n;
+    }
+    if (__ballot(active) == 0ull) break;  // pool used up and every walk binned
+
+    // ---- the superstep's Philox blocks, for every walking lane at once
+    uint4 cur[NB];
+    if (active) {
+      const uint32_t blk = (uint32_t)(kStepBlock0 + ((k - 1) / QB));
+#pragma unroll
+      for (int b = 0; b < NB; ++b) cur[b] = philox(l, (uint32_t)site, blk + (uint32_t)b, kTagWalk, P.k0, P.k1);
+    } else {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) cur[b] = make_uint4(0u, 0u, 0u, 0u);
+    }
+
+    // the step cap can only be reached in this superstep by a lane already
+    // within SS - 1 steps of it; otherwise the stopping test is r < eps alone
+    const bool fixed = P.fixed_M > 0;
+    const bool cap_near = !fixed && __ballot(active && k + (SS - 1) > P.max_steps) != 0ull;
+
+#pragma unroll
+    for (int s = 0; s < SS; ++s) {
+      // The move, the next distance and the next record load are computed on
+      // every lane (idle lanes' values are never used; the cell index is
+      // clamped, so the load stays in bounds) so that the record registers
+      // are assigned unconditionally and the load stays in flight across
+      // this step's tallies.
+      bool stop;
+      if (fixed) {
+        stop = k > P.fixed_M;
+      } else if (cap_near) {
+        const bool near = r < P.eps;
+        const bool over = k > P.max_steps;
+        if (active && over && !near) lane_capped += 1u;
+        stop = near || over;
+      } else {
+        stop = r < P.eps;
+      }
+      const bool tally = active && !stop;
+      if (active && stop) {
+        active = false;
+        done = true;
+        lane_maxk = max(lane_maxk, (unsigned int)k);
+        lane_steps += (unsigned int)k;  // the k = 0 tally and k - 1 chain tallies
+      }
+      // draw of this step: word s mod QB of block s / QB
+      T U[D];
+      const uint4 cb = cur[s / QB];
+      if constexpr (D == 2) {
+        const uint32_t word = (s % QB == 0) ? cb.x : (s % QB == 1) ? cb.y : (s % QB == 2) ? cb.z : cb.w;
+        dir2(u01<T>(word), U);
+      } else {
+        const uint32_t wa = (s % QB == 0) ? cb.x : cb.z;
+        const uint32_t wb = (s % QB == 0) ? cb.y : cb.w;
+        dir3(u01<T>(wa), u01<T>(wb), U);
+      }
+      // X_{k+1} = X_k + r U_k, its distance, tally point and record
+      T Xn[D], qn[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) Xn[a] = X[a] + r * U[a];
+      const T rn = step_distance<T, D, KIND>(P, Xn, sSeg);
+#pragma unroll
+      for (int a = 0; a < D; ++a) qn[a] = Xn[a] + rn * Y[a];
+      const int4 recn = load_record<T, D>(P.gv, qn);
+      if (tally) {
+        // A += t, B += t w at the cell of X_k + r Y, t = omega r^2 / d
         const T t = omd * r * r;
-        // ---- A += t, B += t w at the cell of the tally point
         const int j = grid_resolve<T, D>(P.gv, vpts, rec, q);
         Acc<ACC>::add(&sA[j], t);
 #pragma unroll
         for (int a = 0; a < D; ++a) Acc<ACC>::add(&sB[a * m + j], t * w[a]);
-        // ---- move X_{k+1} = X_k + r U_k
-#pragma unroll
-        for (int a = 0; a < D; ++a) X[a] += r * U[a];
-        k += 1;
-        lane_steps += 1u;
       }
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        X[a] = tally ? Xn[a] : X[a];
+        q[a] = qn[a];
+      }
+      k += tally ? 1 : 0;
+      r = rn;
+      rec = recn;
     }
   }
 
+  if (lane == 0) atomicAdd(&s_walks, n_walks);
   atomicAdd(&s_steps, (unsigned long long)lane_steps);
-  atomicAdd(&s_walks, (unsigned long long)lane_walks);
   if (lane_capped) atomicAdd(&s_capped, (unsigned long long)lane_capped);
   atomicMax(&s_maxk, lane_maxk);
   __syncthreads();
@@ -438,7 +477,9 @@ int pick_block_for(size_t lds) {
 
 template <typename T, int D, int KIND, bool PTS_LDS, int ACC>
 hipError_t launch_bs(const WalkerParams<T>& P, size_t lds, int items, hipStream_t stream) {
-  switch (pick_block_for<T, D, KIND, PTS_LDS, ACC>(lds)) {
+  int bs = P.block_override;
+  if (bs != 256 && bs != 448 && bs != 512 && bs != 1024) bs = pick_block_for<T, D, KIND, PTS_LDS, ACC>(lds);
+  switch (bs) {
     case 256: return launch_variant<T, D, KIND, PTS_LDS, 256, ACC>(P, lds, items, stream);
     case 448: return launch_variant<T, D, KIND, PTS_LDS, 448, ACC>(P, lds, items, stream);
     case 512: return launch_variant<T, D, KIND, PTS_LDS, 512, ACC>(P, lds, items, stream);

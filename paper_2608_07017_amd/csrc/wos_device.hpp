@@ -128,22 +128,27 @@ __device__ __forceinline__ T boundary_distance(const DomainDev<T>& dom, const T*
 
 // ------------------------------------------------------ nearest centre
 // Uniform grid over the bounding box.  Each cell's 16-byte record lists, in
-// ascending order, every centre that can be nearest somewhere in the cell
-// (unused slots -1); a cell with more than four candidates holds
-// x = -(offset + 1) into a list [count, j_1 < j_2 < ...].  Candidates are
-// compared with a strict '<' in ascending order, so ties go to the lowest
-// index.  `pts` (centres, PtStride<D> values each) may live in LDS or in
-// global memory.
+// ascending order, every centre that can be nearest somewhere in the cell;
+// a record with fewer than four candidates repeats its first one in the
+// unused slots.  A cell with more than four candidates holds x = -(offset + 1)
+// into a list [count, j_1 < j_2 < ...].  Candidates are compared with a
+// strict '<' in order, so ties (and the repeats) go to the lowest index.
+// `pts` (centres, PtStride<D> values each) may live in LDS or in global
+// memory.
+__device__ __forceinline__ float clamp_cell(float x, float top) { return __builtin_amdgcn_fmed3f(x, 0.0f, top); }
+__device__ __forceinline__ double clamp_cell(double x, double top) { return fmin(fmax(x, 0.0), top); }
+
 template <typename T, int D>
 __device__ __forceinline__ int grid_cell(const GridDev<T>& g, const T* q) {
-  int idx = 0;
+  // at most 2^24 cells, so the index arithmetic fits 24-bit multiplies; the
+  // clamp is done before the conversion (a NaN converts to cell 0)
+  unsigned int idx = 0u;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    int c = (int)((q[a] - g.lo[a]) * g.inv_h[a]);
-    c = min(max(c, 0), g.n[a] - 1);
-    idx = idx * g.n[a] + c;
+    const unsigned int c = (unsigned int)(int)clamp_cell((q[a] - g.lo[a]) * g.inv_h[a], g.top[a]);
+    idx = __umul24(idx, (unsigned int)g.n[a]) + c;
   }
-  return idx;
+  return (int)idx;
 }
 
 template <typename T, int D>
@@ -175,25 +180,27 @@ __device__ __noinline__ int grid_overflow(const GridDev<T>& g, const T* pts, int
   return bj;
 }
 
-// Resolve a loaded record for the point q.
+// Resolve a loaded record for the point q.  Unused slots repeat the first
+// candidate, so a lane reads only the centres its own cell lists (LDS
+// bandwidth, not issue slots, is what the lookups cost).
 template <typename T, int D>
 __device__ __forceinline__ int grid_resolve(const GridDev<T>& g, const T* pts, int4 r, const T* q) {
   if (r.x < 0) return grid_overflow<T, D>(g, pts, r.x, q);
   int bj = r.x;
-  if (r.y >= 0) {
+  if (r.y != r.x) {
     T best = centre_d2<T, D>(pts, r.x, q);
     const T d1 = centre_d2<T, D>(pts, r.y, q);
     if (d1 < best) {
       best = d1;
       bj = r.y;
     }
-    if (r.z >= 0) {
+    if (r.z != r.x) {
       const T d2 = centre_d2<T, D>(pts, r.z, q);
       if (d2 < best) {
         best = d2;
         bj = r.z;
       }
-      if (r.w >= 0) {
+      if (r.w != r.x) {
         const T d3 = centre_d2<T, D>(pts, r.w, q);
         if (d3 < best) bj = r.w;
       }

@@ -35,6 +35,7 @@ struct GridDev {
   int n[3];
   T lo[3];
   T inv_h[3];
+  T top[3];         // n[a] - 1
   const int4* rec;  // n0*n1*n2 cell records, x slowest
   const int* list;  // overflow lists [count, indices...]
   const T* pts;     // centres, PtStride<D> values each
@@ -57,8 +58,8 @@ struct WalkerParams {
   int fixed_M;
   uint32_t k0, k1;
   T inv_N;
-  int regen_T;     // prepare walks when this many lanes of a wavefront lack one
-  int serve_T;     // serve finished walks when this many lanes are waiting
+  int regen_T;     // refill a wavefront's pool of prepared walks when this many slots are free
+  int block_override;  // workgroup size chosen by the caller (0: by occupancy)
   const int* item_order;  // blockIdx -> item (longest expected work first)
   int direct_store;
   int acc_fixed;   // tally accumulators: 0 FP64, 1 64-bit fixed point
