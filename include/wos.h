@@ -170,6 +170,24 @@ typedef enum {
                                 the linear problem with A = (1 + u_k^2) I              */
 } wos_problem_kind;
 
+/* Generalised inverse of the assembled system (Sec. "Second order linear
+ * elliptic PDEs" allows any, possibly regularised, generalised inverse). */
+typedef enum {
+  WOS_SOLVER_TSVD = 0,     /* truncated SVD: singular values <= rcond sigma_max dropped  */
+  WOS_SOLVER_TIKHONOV = 1  /* Tikhonov: minimise |Lambda q - rhs|^2 + reg |q|^2 with
+                              reg = rcond^2 max_j (Lambda^T Lambda)_jj, solved through
+                              the Cholesky factor of the normal matrix (LINEAR only)  */
+} wos_solver;
+
+typedef enum {
+  WOS_SOLVE_F64 = 0,   /* every step in FP64                                          */
+  WOS_SOLVE_MIXED = 1  /* Tikhonov on an FP32 toolbox: Lambda and the normal matrix
+                          formed and factored in FP32 on the matrix cores, then
+                          iterative refinement with FP64 residuals of the exact
+                          system (matrix-free) to refine_tol; falls back to FP64 when
+                          the FP32 factorisation fails                                 */
+} wos_solve_precision;
+
 typedef struct {
   int32_t kind;          /* wos_problem_kind                                        */
   const double* A;       /* LINEAR: device, n x d x d symmetric A(x_i), or NULL (= I) */
@@ -183,6 +201,10 @@ typedef struct {
                             (0 -> 1e-10)                                              */
   int32_t max_iter;      /* outer iterations; 0 -> 50 (Newton), 100 (Picard)        */
   int32_t max_sweeps;    /* Jacobi sweeps of each eigen-decomposition; 0 -> 40      */
+  int32_t solver;        /* wos_solver (0: TSVD)                                    */
+  int32_t precision;     /* wos_solve_precision (0: FP64)                           */
+  int32_t max_refine;    /* MIXED: refinement steps at most; 0 -> 10                */
+  double refine_tol;     /* MIXED: stop at |r| <= refine_tol |Lambda^T rhs|; 0 -> 1e-10 */
 } wos_coeffs;
 
 typedef struct {
@@ -194,6 +216,10 @@ typedef struct {
   double grad_norm;       /* Newton: final |grad J|                              */
   double grad_norm0;      /* Newton: |grad J(h_0)|                               */
   double update_norm;     /* Picard: final |u_{k+1} - u_k|_lambda                */
+  double reg;             /* Tikhonov: the regularisation parameter used         */
+  int32_t refine_iters;   /* MIXED: refinement steps taken                       */
+  int32_t fallback;       /* MIXED: 1 when the request was solved in FP64        */
+  double refine_residual; /* MIXED: final |r| / |Lambda^T rhs|                    */
 } wos_solve_info;
 
 /* Solves a Dirichlet problem on the toolbox's domain (Sec. "Second order

@@ -92,6 +92,16 @@ def tsvd_solve(M, r, rcond):
     return Vt[keep].T @ ((U[:, keep].T @ r) / s[keep])
 
 
+def tikhonov_solve(M, r, rcond):
+    """Tikhonov-regularised generalised inverse (a regularised inverse in the
+    sense of the paper's solve step): q minimises |M q - r|^2 + reg |q|^2 with
+    reg = rcond^2 max_j (M^T M)_jj, i.e. (M^T M + reg I) q = M^T r.
+    Returns (q, reg)."""
+    N = M.T @ M
+    reg = rcond * rcond * float(np.max(np.diag(N)))
+    return np.linalg.solve(N + reg * np.eye(N.shape[0]), M.T @ r), reg
+
+
 def reconstruct(tb, q, g):
     """u = A q + H g~ and grad u (d, n)."""
     u = tb["A"] @ q + tb["H"] @ g
@@ -99,9 +109,12 @@ def reconstruct(tb, q, g):
     return u, gu
 
 
-def solve_linear(tb, lam, f, g, Acoef=None, bcoef=None, ccoef=None, rcond=1e-3):
+def solve_linear(tb, lam, f, g, Acoef=None, bcoef=None, ccoef=None, rcond=1e-3, solver="tsvd"):
     L, S = assemble(tb, lam, Acoef, bcoef, ccoef)
-    q = tsvd_solve(L, rhs(tb, lam, S, f, g), rcond)
+    if solver == "tikhonov":
+        q, _ = tikhonov_solve(L, rhs(tb, lam, S, f, g), rcond)
+    else:
+        q = tsvd_solve(L, rhs(tb, lam, S, f, g), rcond)
     u, gu = reconstruct(tb, q, g)
     return {"q": q, "u": u, "grad_u": gu, "Lambda": L, "Sigma": S}
 

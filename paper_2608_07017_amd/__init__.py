@@ -14,8 +14,8 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import (EXPORTS, KINDS, PRECISION, PROBLEMS, WosBuildOpts, WosCoeffs, WosDomain, WosError,
-                   WosSolveInfo, WosToolboxInfo, check, lib)
+from ._lib import (EXPORTS, KINDS, PRECISION, PROBLEMS, SOLVE_PRECISION, SOLVERS, WosBuildOpts, WosCoeffs,
+                   WosDomain, WosError, WosSolveInfo, WosToolboxInfo, check, lib)
 
 __all__ = ["Toolbox", "build_toolbox", "WosError", "lib"]
 
@@ -126,7 +126,8 @@ class Toolbox:
 
     # -------------------------------------------------------------- solve
     def solve(self, f, g, kind="linear", A=None, b=None, c=None, kappa=1.0, rcond=1e-3, tol=0.0,
-              max_iter=0, max_sweeps=0, stream=None):
+              max_iter=0, max_sweeps=0, solver="tsvd", precision="f64", max_refine=0, refine_tol=0.0,
+              stream=None):
         """Solve a Dirichlet problem (see include/wos.h, wos_solve).
 
         f: (n,) right-hand side at the sites in the convention of `kind`;
@@ -144,7 +145,8 @@ class Toolbox:
         co = WosCoeffs(kind=PROBLEMS[kind], A=None if A is None else A.data_ptr(),
                        b=None if b is None else b.data_ptr(), c=None if c is None else c.data_ptr(),
                        kappa=float(kappa), rcond=float(rcond), tol=float(tol), max_iter=int(max_iter),
-                       max_sweeps=int(max_sweeps))
+                       max_sweeps=int(max_sweeps), solver=SOLVERS[solver], precision=SOLVE_PRECISION[precision],
+                       max_refine=int(max_refine), refine_tol=float(refine_tol))
         u = torch.empty(self.n, dtype=torch.float64, device="cuda")
         gu = torch.empty((self.dim, self.n), dtype=torch.float64, device="cuda")
         q = torch.empty(self.n, dtype=torch.float64, device="cuda")

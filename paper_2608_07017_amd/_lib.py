@@ -46,17 +46,22 @@ class WosToolboxInfo(ctypes.Structure):
 class WosCoeffs(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("A", ctypes.c_void_p), ("b", ctypes.c_void_p),
                 ("c", ctypes.c_void_p), ("kappa", ctypes.c_double), ("rcond", ctypes.c_double),
-                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_sweeps", ctypes.c_int32)]
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("solver", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+                ("refine_tol", ctypes.c_double)]
 
 
 class WosSolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("rank", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("sigma_max", ctypes.c_double), ("sigma_threshold", ctypes.c_double),
                 ("grad_norm", ctypes.c_double), ("grad_norm0", ctypes.c_double),
-                ("update_norm", ctypes.c_double)]
+                ("update_norm", ctypes.c_double), ("reg", ctypes.c_double), ("refine_iters", ctypes.c_int32),
+                ("fallback", ctypes.c_int32), ("refine_residual", ctypes.c_double)]
 
 
 PROBLEMS = {"linear": 0, "semilinear_cubic": 1, "quasilinear": 2}
+SOLVERS = {"tsvd": 0, "tikhonov": 1}
+SOLVE_PRECISION = {"f64": 0, "mixed": 1}
 
 # every symbol include/wos.h declares, with its ctypes signature
 _P = ctypes.c_void_p

@@ -255,13 +255,7 @@ wos_status upload_grid(wos_toolbox* tb, const GridHost& h, DevGrid* g) {
 }
 
 void release(wos_toolbox* tb) {
-  {
-    SolveWork& w = tb->sw;
-    void* sp[] = {w.R, w.Lam, w.Sig, w.Lam0, w.Sig0, w.Hess, w.G, w.V, w.E, w.rot, w.pq, w.vec, w.Ac, w.red};
-    for (void* q : sp)
-      if (q) (void)hipFree(q);
-    w = SolveWork();
-  }
+  free_work(tb->sw);
   for (auto& e : tb->ev)
     if (e) {
       (void)hipEventDestroy(e);
@@ -697,7 +691,7 @@ wos_status wos_toolbox_get_info(const wos_toolbox* tb, wos_toolbox_info* info) {
   info->p = tb->p;
   info->precision = tb->f64 ? WOS_F64 : WOS_F32;
   info->walks_per_site = tb->opts.walks_per_site;
-  info->device_bytes = tb->bytes;
+  info->device_bytes = tb->bytes + tb->sw.bytes;
   if (tb->built) {
     WOS_HIP(hipStreamSynchronize(tb->last_stream));
     unsigned long long st[8];

@@ -1,0 +1,177 @@
+// Dense GEMM on the matrix cores: C = alpha op(A) op(B) + beta C, row-major,
+// op = identity or transpose, in FP32 (v_mfma_f32_16x16x4f32) or FP64
+// (v_mfma_f64_16x16x4f64), accumulating in the operand precision.  Used by
+// the solve path for the assembly of Lambda and Sigma, the normal matrix
+// Lambda^T Lambda and the trailing updates of the Cholesky factorisation.
+//
+// Tiling: a 256-thread workgroup (four wavefronts) owns a 64 x 64 tile of
+// C; each wavefront a 32 x 32 quarter made of 2 x 2 MFMA blocks of 16 x 16.
+// K advances in slabs of 16 staged in LDS (row-major 16 x 64 slabs of
+// op(A)^T and op(B), padded against bank conflicts).
+//
+// MFMA 16x16x4 operand layout (wave64, lane l): the A operand holds
+// A[l % 16][l / 16], the B operand B[l / 16][l % 16]; the 4 results of lane
+// l are D[4 (l / 16) + r][l % 16] for FP32 and D[l / 16 + 4 r][l % 16] for
+// FP64, r = 0..3 (both checked on gfx950).
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "wos_solve_kernels.hpp"
+
+namespace wos {
+
+namespace {
+
+constexpr int GT = 64;   // C tile
+constexpr int GK = 16;   // K slab
+constexpr int GPAD = 4;  // LDS row padding (elements)
+
+template <typename T>
+__device__ __forceinline__ void mfma_16x16x4(T a, T b, T (&acc)[4]);
+
+template <>
+__device__ __forceinline__ void mfma_16x16x4<float>(float a, float b, float (&acc)[4]) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  v4f c = {acc[0], acc[1], acc[2], acc[3]};
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  acc[0] = c[0];
+  acc[1] = c[1];
+  acc[2] = c[2];
+  acc[3] = c[3];
+}
+
+template <>
+__device__ __forceinline__ void mfma_16x16x4<double>(double a, double b, double (&acc)[4]) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  v4d c = {acc[0], acc[1], acc[2], acc[3]};
+  c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  acc[0] = c[0];
+  acc[1] = c[1];
+  acc[2] = c[2];
+  acc[3] = c[3];
+}
+
+// element (r, c) of op(X) for an X of leading dimension ld
+template <bool TRANS, typename S>
+__device__ __forceinline__ S op_at(const S* X, int ld, int r, int c) {
+  return TRANS ? X[(size_t)c * ld + r] : X[(size_t)r * ld + c];
+}
+
+// C (M x N) = alpha op(A) (M x K) op(B) (K x N) + beta C.  Operands may be
+// stored in a narrower type SA / SB than the arithmetic type T.
+template <typename T, typename SA, typename SB, bool TA, bool TB>
+__global__ __launch_bounds__(256) void mfma_gemm_kernel(int M, int N, int K, T alpha, const SA* __restrict__ A,
+                                                        int lda, const SB* __restrict__ B, int ldb, T beta,
+                                                        T* __restrict__ C, int ldc) {
+  __shared__ T sA[GK][GT + GPAD];  // sA[k][i] = op(A)[m0 + i][k0 + k]
+  __shared__ T sB[GK][GT + GPAD];  // sB[k][j] = op(B)[k0 + k][n0 + j]
+  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;  // wavefront's quarter
+  const int li = lane & 15, lk = lane >> 4;
+
+  T acc[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[a][b][r] = T(0);
+
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    // stage the slabs: 16 x 64 elements each, 4 per thread
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + 256 * e;
+      int kk, ii;
+      if (TA) {  // op(A)[i][k] = A[k][i]: consecutive threads walk i
+        kk = idx / GT;
+        ii = idx % GT;
+      } else {  // consecutive threads walk k
+        ii = idx / GK;
+        kk = idx % GK;
+      }
+      const int gi = m0 + ii, gk = k0 + kk;
+      sA[kk][ii] = (gi < M && gk < K) ? (T)op_at<TA>(A, lda, gi, gk) : T(0);
+      int kb, jj;
+      if (TB) {  // op(B)[k][j] = B[j][k]: consecutive threads walk k
+        jj = idx / GK;
+        kb = idx % GK;
+      } else {
+        kb = idx / GT;
+        jj = idx % GT;
+      }
+      const int gj = n0 + jj, gkb = k0 + kb;
+      sB[kb][jj] = (gj < N && gkb < K) ? (T)op_at<TB>(B, ldb, gkb, gj) : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 4) {
+      T av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = sA[ks + lk][wm + 16 * a + li];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = sB[ks + lk][wn + 16 * b + li];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) mfma_16x16x4<T>(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = m0 + wm + 16 * a + (std::is_same<T, double>::value ? lk + 4 * r : 4 * lk + r);
+        const int gj = n0 + wn + 16 * b + li;
+        if (gi < M && gj < N) {
+          T* dst = C + (size_t)gi * ldc + gj;
+          *dst = alpha * acc[a][b][r] + (beta == T(0) ? T(0) : beta * *dst);
+        }
+      }
+}
+
+template <typename T, typename SA, typename SB>
+hipError_t gemm_dispatch(bool ta, bool tb, int M, int N, int K, T alpha, const SA* A, int lda, const SB* B, int ldb,
+                         T beta, T* C, int ldc, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((mfma_gemm_kernel<T, SA, SB, false, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B,
+                       ldb, beta, C, ldc);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((mfma_gemm_kernel<T, SA, SB, true, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B,
+                       ldb, beta, C, ldc);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((mfma_gemm_kernel<T, SA, SB, false, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B,
+                       ldb, beta, C, ldc);
+  else
+    hipLaunchKernelGGL((mfma_gemm_kernel<T, SA, SB, true, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B,
+                       ldb, beta, C, ldc);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t mfma_gemm_f64(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
+                         const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st) {
+  return gemm_dispatch<double, double, double>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st);
+}
+
+hipError_t mfma_gemm_f32(bool ta, bool tb, int M, int N, int K, float alpha, const float* A, int lda,
+                         const float* B, int ldb, float beta, float* C, int ldc, hipStream_t st) {
+  return gemm_dispatch<float, float, float>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st);
+}
+
+// FP64 arithmetic on an FP32-stored left operand (the toolbox rows)
+hipError_t mfma_gemm_f64_a32(bool ta, bool tb, int M, int N, int K, double alpha, const float* A, int lda,
+                             const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st) {
+  return gemm_dispatch<double, float, double>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st);
+}
+
+}  // namespace wos

@@ -54,44 +54,42 @@ wos_status sfail(wos_status s, const char* fmt, ...) {
   } while (0)
 
 template <typename P>
-wos_status walloc(wos_toolbox* tb, P** p, size_t count) {
+wos_status walloc(SolveWork& w, P** p, size_t count) {
   hipError_t e = hipMalloc((void**)p, std::max<size_t>(count * sizeof(P), 16));
   if (e != hipSuccess) return sfail(WOS_ENOMEM, "solve workspace: hipMalloc(%zu) failed", count * sizeof(P));
-  tb->bytes += count * sizeof(P);
+  w.bytes += count * sizeof(P);
   return WOS_OK;
 }
 
-wos_status ensure_work(wos_toolbox* tb) {
-  SolveWork& w = tb->sw;
+wos_status ensure_work(wos_toolbox* tb, SolveWork& w) {
   if (w.ready) return WOS_OK;
   const size_t n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
   w.M = (int)(m + (m & 1));
   const size_t M = w.M;
   w.vlen = std::max(std::max(n, M), std::max(p, d * n));
   wos_status s;
-  if ((s = walloc(tb, &w.R, (d + 1) * n * (m + p))) != WOS_OK) return s;
-  if ((s = walloc(tb, &w.Lam, m * m)) != WOS_OK) return s;
-  if ((s = walloc(tb, &w.Sig, m * p)) != WOS_OK) return s;
-  if ((s = walloc(tb, &w.Lam0, m * m)) != WOS_OK) return s;
-  if ((s = walloc(tb, &w.Sig0, m * p)) != WOS_OK) return s;
-  if ((s = walloc(tb, &w.Hess, m * m)) != WOS_OK) return s;
-  if ((s = walloc(tb, &w.G, M * M)) != WOS_OK) return s;
-  if ((s = walloc(tb, &w.V, M * M)) != WOS_OK) return s;
-  if ((s = walloc(tb, &w.E, M)) != WOS_OK) return s;
-  if ((s = walloc(tb, &w.rot, M)) != WOS_OK) return s;
-  if ((s = walloc(tb, &w.pq, M)) != WOS_OK) return s;
-  if ((s = walloc(tb, &w.vec, 10 * w.vlen)) != WOS_OK) return s;
-  if ((s = walloc(tb, &w.Ac, n * d * d)) != WOS_OK) return s;
-  if ((s = walloc(tb, &w.red, 2)) != WOS_OK) return s;
+  if ((s = walloc(w, &w.R, (d + 1) * n * (m + p))) != WOS_OK) return s;
+  if ((s = walloc(w, &w.Lam, m * m)) != WOS_OK) return s;
+  if ((s = walloc(w, &w.Sig, m * p)) != WOS_OK) return s;
+  if ((s = walloc(w, &w.Lam0, m * m)) != WOS_OK) return s;
+  if ((s = walloc(w, &w.Sig0, m * p)) != WOS_OK) return s;
+  if ((s = walloc(w, &w.Hess, m * m)) != WOS_OK) return s;
+  if ((s = walloc(w, &w.G, M * M)) != WOS_OK) return s;
+  if ((s = walloc(w, &w.V, M * M)) != WOS_OK) return s;
+  if ((s = walloc(w, &w.E, M)) != WOS_OK) return s;
+  if ((s = walloc(w, &w.rot, M)) != WOS_OK) return s;
+  if ((s = walloc(w, &w.pq, M)) != WOS_OK) return s;
+  if ((s = walloc(w, &w.vec, 10 * w.vlen)) != WOS_OK) return s;
+  if ((s = walloc(w, &w.Ac, n * d * d)) != WOS_OK) return s;
+  if ((s = walloc(w, &w.red, 2)) != WOS_OK) return s;
   w.ready = true;
   return WOS_OK;
 }
 
 // Lambda (m x m) and Sigma (m x p) for coefficients (Ac, bc, cc) into
 // (Lam, Sig); Ac == NULL means A = I.
-wos_status assemble(wos_toolbox* tb, const double* Ac, const double* bc, const double* cc, double* Lam,
-                    double* Sig, hipStream_t st) {
-  SolveWork& w = tb->sw;
+wos_status assemble(wos_toolbox* tb, SolveWork& w, const double* Ac, const double* bc, const double* cc,
+                    double* Lam, double* Sig, hipStream_t st) {
   const int n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
   const bool f64 = tb->f64;
   SHIP(launch_weight_rows(f64, tb->d_A, tb->d_B, tb->d_H, tb->d_K, tb->d_lambda, Ac, bc, cc, n, m, p, d, w.R, st));
@@ -108,9 +106,8 @@ struct TsvdResult {
 };
 
 // q (m) = TSVD(Mat) r (m), Mat m x m; `symmetric` selects the eigen route.
-wos_status tsvd_solve(wos_toolbox* tb, const double* Mat, bool symmetric, const double* r, double rcond,
-                      int max_sweeps, double* q, TsvdResult* res, hipStream_t st) {
-  SolveWork& w = tb->sw;
+wos_status tsvd_solve(wos_toolbox* tb, SolveWork& w, const double* Mat, bool symmetric, const double* r,
+                      double rcond, int max_sweeps, double* q, TsvdResult* res, hipStream_t st) {
   const int m = tb->m, M = w.M;
   double* rr = w.vec + 6 * w.vlen;  // padded right-hand side (M)
   double* z = w.vec + 7 * w.vlen;   // M
@@ -182,9 +179,8 @@ wos_status reconstruct(wos_toolbox* tb, const double* q, const double* g, double
 }
 
 // rhs = -A^T (lambda o fp) - Sigma g   (fp: the paper's right-hand side)
-wos_status linear_rhs(wos_toolbox* tb, const double* Sig, const double* fp, const double* g, double* rhs,
-                      hipStream_t st) {
-  SolveWork& w = tb->sw;
+wos_status linear_rhs(wos_toolbox* tb, SolveWork& w, const double* Sig, const double* fp, const double* g,
+                      double* rhs, hipStream_t st) {
   double* lf = w.vec + 5 * w.vlen;
   SHIP(launch_pointwise(tb->n, tb->d_lambda, nullptr, fp, 0.0, 0.0, 0.0, 0.0, -1.0, lf, st));  // lam * f
   SHIP(launch_gemv_t(tb->f64, tb->d_A, tb->n, tb->m, lf, -1.0, 0.0, rhs, st));
@@ -193,27 +189,191 @@ wos_status linear_rhs(wos_toolbox* tb, const double* Sig, const double* fp, cons
 }
 
 // sum_i w_i x_i y_i on the device; the scalar is read back
-wos_status dev_dot(wos_toolbox* tb, const double* dx, const double* dy, const double* dw, int n, double* out,
+wos_status dev_dot(SolveWork& w, const double* dx, const double* dy, const double* dw, int n, double* out,
                    hipStream_t st) {
-  SHIP(launch_dot(n, dx, dy, dw, tb->sw.red, st));
-  SHIP(hipMemcpyAsync(out, tb->sw.red, sizeof(double), hipMemcpyDeviceToHost, st));
+  SHIP(launch_dot(n, dx, dy, dw, w.red, st));
+  SHIP(hipMemcpyAsync(out, w.red, sizeof(double), hipMemcpyDeviceToHost, st));
   SHIP(hipStreamSynchronize(st));
   return WOS_OK;
 }
 
+
+// ------------------------------------------------------------ Tikhonov
+// Regularised generalised inverse: q minimises |Lambda q - rhs|^2 + reg |q|^2
+// with reg = rcond^2 max_j (Lambda^T Lambda)_jj, i.e. q solves the normal
+// equations (Lambda^T Lambda + reg I) q = Lambda^T rhs.
+//
+// FP64: Lambda and the normal matrix are formed by FP64 MFMA GEMMs and
+// factored by Cholesky in FP64.  MIXED (FP32 toolbox): both are formed and
+// factored in FP32 on the matrix cores; the solution is then refined with
+// residuals of the exact system evaluated matrix-free in FP64
+// (Lambda = L^T W L applied as GEMVs over the toolbox rows with FP64
+// accumulation), until |r| <= refine_tol |Lambda^T rhs|.  If the FP32
+// factorisation meets a non-positive pivot the request is solved in FP64.
+wos_status ensure_tik(wos_toolbox* tb, SolveWork& w, bool mixed) {
+  const size_t n = tb->n, m = tb->m, d = tb->dim;
+  wos_status s;
+  if (!w.blk) {
+    if ((s = walloc(w, &w.blk, 2 * (d + 1) * std::max<size_t>(n, 1))) != WOS_OK) return s;
+    if ((s = walloc(w, &w.regv, 2)) != WOS_OK) return s;
+    if ((s = walloc(w, &w.info, 2)) != WOS_OK) return s;
+  }
+  if (mixed && !w.R32) {
+    if ((s = walloc(w, &w.R32, (d + 1) * n * m)) != WOS_OK) return s;
+    if ((s = walloc(w, &w.Lam32, m * m)) != WOS_OK) return s;
+    if ((s = walloc(w, &w.N32, m * m)) != WOS_OK) return s;
+    if ((s = walloc(w, &w.v32, m)) != WOS_OK) return s;
+  }
+  return WOS_OK;
+}
+
+// y ((d+1) n) = L x, L = [B; A]
+wos_status apply_L(wos_toolbox* tb, const double* x, double* y, hipStream_t st) {
+  const int n = tb->n, m = tb->m, d = tb->dim;
+  SHIP(launch_gemv_n_ld(tb->f64, tb->d_B, d * n, m, m, x, 1.0, 0.0, y, st));
+  SHIP(launch_gemv_n_ld(tb->f64, tb->d_A, n, m, m, x, 1.0, 0.0, y + (size_t)d * n, st));
+  return WOS_OK;
+}
+// x (m) = alpha L^T y + beta x
+wos_status apply_Lt(wos_toolbox* tb, const double* y, double alpha, double beta, double* x, hipStream_t st) {
+  const int n = tb->n, m = tb->m, d = tb->dim;
+  SHIP(launch_gemv_t_ld(tb->f64, tb->d_B, d * n, m, m, y, alpha, beta, x, st));
+  SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, y + (size_t)d * n, alpha, 1.0, x, st));
+  return WOS_OK;
+}
+// out = Lambda x (trans = false) or Lambda^T x, Lambda = L^T W L
+wos_status apply_Lambda(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, const double* x, bool trans,
+                        double* out, hipStream_t st) {
+  const int n = tb->n, d = tb->dim;
+  double* y1 = w.blk;
+  double* y2 = w.blk + (size_t)(d + 1) * n;
+  wos_status s;
+  if ((s = apply_L(tb, x, y1, st)) != WOS_OK) return s;
+  SHIP(launch_apply_w(n, d, tb->d_lambda, co->A, co->b, co->c, y1, trans, nullptr, y2, st));
+  return apply_Lt(tb, y2, 1.0, 0.0, out, st);
+}
+
+wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, double rcond, const double* f,
+                           const double* g, double* q, wos_solve_info* inf, hipStream_t st) {
+  const int n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
+  const int K = d * n;
+  bool mixed = co->precision == WOS_SOLVE_MIXED && !tb->f64;
+  wos_status s;
+  if ((s = ensure_tik(tb, w, mixed)) != WOS_OK) return s;
+  double* rhs = w.vec + 5 * w.vlen;
+  double* c = w.vec + 6 * w.vlen;
+  double* r = w.vec + 7 * w.vlen;
+  double* t = w.vec + 8 * w.vlen;
+  double* y1 = w.blk;
+  double* y2 = w.blk + (size_t)(d + 1) * n;
+
+  // right-hand side and c = Lambda^T rhs, matrix-free in FP64
+  SHIP(launch_gemv_n_ld(tb->f64, tb->d_K, d * n, p, p, g, 1.0, 0.0, y1, st));
+  SHIP(launch_gemv_n_ld(tb->f64, tb->d_H, n, p, p, g, 1.0, 0.0, y1 + (size_t)d * n, st));
+  SHIP(launch_apply_w(n, d, tb->d_lambda, co->A, co->b, co->c, y1, false, f, y2, st));
+  if ((s = apply_Lt(tb, y2, -1.0, 0.0, rhs, st)) != WOS_OK) return s;
+  if ((s = apply_Lambda(tb, w, co, rhs, true, c, st)) != WOS_OK) return s;
+  SHIP(hipMemsetAsync(w.info, 0, 2 * sizeof(int), st));
+
+  if (mixed) {
+    // Lambda (FP32) = L^T R, R = W L; N = Lambda^T Lambda + reg I; Cholesky
+    SHIP(launch_weight_rows_any(false, true, tb->d_A, tb->d_B, tb->d_H, tb->d_K, tb->d_lambda, co->A, co->b, co->c,
+                                n, m, p, d, m, w.R32, st));
+    SHIP(mfma_gemm_f32(true, false, m, m, K, 1.0f, (const float*)tb->d_B, m, w.R32, m, 0.0f, w.Lam32, m, st));
+    SHIP(mfma_gemm_f32(true, false, m, m, n, 1.0f, (const float*)tb->d_A, m, w.R32 + (size_t)K * m, m, 1.0f,
+                       w.Lam32, m, st));
+    SHIP(mfma_gemm_f32(true, false, m, m, m, 1.0f, w.Lam32, m, w.Lam32, m, 0.0f, w.N32, m, st));
+    SHIP(launch_reg_from_diag(false, w.N32, m, m, rcond, w.regv, st));
+    SHIP(launch_add_diag(false, w.N32, m, m, w.regv, st));
+    SHIP(cholesky_f32(w.N32, m, m, w.info, st));
+    int hinfo = 0;
+    SHIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
+    SHIP(hipStreamSynchronize(st));
+    if (hinfo != 0) {
+      mixed = false;  // fall back to FP64 for this request
+      inf->fallback = 1;
+      SHIP(hipMemsetAsync(w.info, 0, 2 * sizeof(int), st));
+    }
+  }
+  if (mixed) {
+    const double tol = co->refine_tol > 0 ? co->refine_tol : 1e-10;
+    const int maxit = co->max_refine > 0 ? co->max_refine : 10;
+    double cn = 0.0, rn = 0.0;
+    if ((s = dev_dot(w, c, c, nullptr, m, &cn, st)) != WOS_OK) return s;
+    cn = std::sqrt(cn);
+    SHIP(hipMemsetAsync(q, 0, sizeof(double) * m, st));
+    SHIP(hipMemcpyAsync(r, c, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    int it = 0;
+    for (it = 1; it <= maxit; ++it) {
+      SHIP(launch_to_f32(m, r, w.v32, st));
+      SHIP(cholesky_solve_f32(w.N32, m, m, w.v32, st));
+      SHIP(launch_add_f32(m, w.v32, q, st));
+      // r = c - Lambda^T Lambda q - reg q   (FP64)
+      if ((s = apply_Lambda(tb, w, co, q, false, t, st)) != WOS_OK) return s;
+      if ((s = apply_Lambda(tb, w, co, t, true, r, st)) != WOS_OK) return s;
+      SHIP(launch_axpy_reg(m, c, nullptr, -1.0, r, r, st));
+      SHIP(launch_axpy_reg(m, r, w.regv, -1.0, q, r, st));
+      if ((s = dev_dot(w, r, r, nullptr, m, &rn, st)) != WOS_OK) return s;
+      rn = std::sqrt(rn);
+      if (rn <= tol * cn) break;
+    }
+    inf->refine_iters = std::min(it, maxit);
+    inf->refine_residual = cn > 0 ? rn / cn : 0.0;
+  } else {
+    // FP64: Lambda = L^T R (R = W L in FP64), N = Lambda^T Lambda + reg I
+    SHIP(launch_weight_rows_any(tb->f64, false, tb->d_A, tb->d_B, tb->d_H, tb->d_K, tb->d_lambda, co->A, co->b,
+                                co->c, n, m, p, d, m, w.R, st));
+    if (tb->f64) {
+      SHIP(mfma_gemm_f64(true, false, m, m, K, 1.0, (const double*)tb->d_B, m, w.R, m, 0.0, w.Lam, m, st));
+      SHIP(mfma_gemm_f64(true, false, m, m, n, 1.0, (const double*)tb->d_A, m, w.R + (size_t)K * m, m, 1.0, w.Lam,
+                         m, st));
+    } else {
+      SHIP(mfma_gemm_f64_a32(true, false, m, m, K, 1.0, (const float*)tb->d_B, m, w.R, m, 0.0, w.Lam, m, st));
+      SHIP(mfma_gemm_f64_a32(true, false, m, m, n, 1.0, (const float*)tb->d_A, m, w.R + (size_t)K * m, m, 1.0,
+                             w.Lam, m, st));
+    }
+    SHIP(mfma_gemm_f64(true, false, m, m, m, 1.0, w.Lam, m, w.Lam, m, 0.0, w.Hess, m, st));
+    SHIP(launch_reg_from_diag(true, w.Hess, m, m, rcond, w.regv, st));
+    SHIP(launch_add_diag(true, w.Hess, m, m, w.regv, st));
+    SHIP(cholesky_f64(w.Hess, m, m, w.info, st));
+    SHIP(hipMemcpyAsync(q, c, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    SHIP(cholesky_solve_f64(w.Hess, m, m, q, st));
+    int hinfo = 0;
+    SHIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
+    SHIP(hipStreamSynchronize(st));
+    if (hinfo != 0) return sfail(WOS_ENOTCONV, "normal matrix not positive definite at column %d", hinfo - 1);
+  }
+  SHIP(hipMemcpyAsync(&inf->reg, w.regv, sizeof(double), hipMemcpyDeviceToHost, st));
+  return WOS_OK;
+}
 }  // namespace
 
-extern "C" wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* co, const double* f, const double* g,
-                                double* u, double* grad_u, double* q_out, wos_solve_info* info, void* stream_) {
+namespace wos {
+
+void free_work(SolveWork& w) {
+  void* ptrs[] = {w.R, w.Lam, w.Sig, w.Lam0, w.Sig0, w.Hess, w.G, w.V, w.E, w.rot, w.pq, w.vec, w.Ac, w.red,
+                  w.blk, w.regv, w.info, w.R32, w.Lam32, w.N32, w.v32};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  w = SolveWork();
+}
+
+// One solve on the workspace `w` (the toolbox's own, or a server slot's).
+wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, const double* f, const double* g,
+                         double* u, double* grad_u, double* q_out, wos_solve_info* info, hipStream_t st) {
   if (!tb || !co || !f || !g || !u) return sfail(WOS_EINVAL, "NULL argument");
   if (!tb->built) return sfail(WOS_EINVAL, "toolbox has not been built");
-  hipStream_t st = static_cast<hipStream_t>(stream_);
   const double rcond = co->rcond > 0 ? co->rcond : 1e-3;
   if (!(rcond < 1.0)) return sfail(WOS_EINVAL, "rcond must be in (0, 1)");
+  if (co->solver != WOS_SOLVER_TSVD && co->solver != WOS_SOLVER_TIKHONOV)
+    return sfail(WOS_EINVAL, "unknown solver %d", co->solver);
+  if (co->precision != WOS_SOLVE_F64 && co->precision != WOS_SOLVE_MIXED)
+    return sfail(WOS_EINVAL, "unknown solve precision %d", co->precision);
+  if (co->solver == WOS_SOLVER_TIKHONOV && co->kind != WOS_LINEAR)
+    return sfail(WOS_EINVAL, "the Tikhonov solver is available for linear problems");
   const int max_sweeps = co->max_sweeps > 0 ? co->max_sweeps : 40;
-  wos_status s = ensure_work(tb);
+  wos_status s = ensure_work(tb, w);
   if (s != WOS_OK) return s;
-  SolveWork& w = tb->sw;
   const int n = tb->n, m = tb->m, d = tb->dim;
   double* rhs = w.vec + 0 * w.vlen;
   double* q = w.vec + 1 * w.vlen;
@@ -223,22 +383,25 @@ extern "C" wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* co, const dou
   wos_solve_info inf{};
   TsvdResult tr;
 
-  if (co->kind == WOS_LINEAR) {
-    if ((s = assemble(tb, co->A, co->b, co->c, w.Lam, w.Sig, st)) != WOS_OK) return s;
-    if ((s = linear_rhs(tb, w.Sig, f, g, rhs, st)) != WOS_OK) return s;
-    if ((s = tsvd_solve(tb, w.Lam, co->b == nullptr, rhs, rcond, max_sweeps, q, &tr, st)) != WOS_OK) return s;
+  if (co->kind == WOS_LINEAR && co->solver == WOS_SOLVER_TIKHONOV) {
+    if ((s = tikhonov_linear(tb, w, co, rcond, f, g, q, &inf, st)) != WOS_OK) return s;
+    inf.iters = 1;
+  } else if (co->kind == WOS_LINEAR) {
+    if ((s = assemble(tb, w, co->A, co->b, co->c, w.Lam, w.Sig, st)) != WOS_OK) return s;
+    if ((s = linear_rhs(tb, w, w.Sig, f, g, rhs, st)) != WOS_OK) return s;
+    if ((s = tsvd_solve(tb, w, w.Lam, co->b == nullptr, rhs, rcond, max_sweeps, q, &tr, st)) != WOS_OK) return s;
     inf.iters = 1;
   } else if (co->kind == WOS_SEMILINEAR_CUBIC) {
     // F = |p|^2/2 + kappa u^4/4 - f u; grad J = A^T(lam (kappa u^3 - f)) + Lam0 h + Sig0 g
     const double kappa = co->kappa;
     const double tol = co->tol > 0 ? co->tol : 1e-8;
     const int max_iter = co->max_iter > 0 ? co->max_iter : 50;
-    if ((s = assemble(tb, nullptr, nullptr, nullptr, w.Lam0, w.Sig0, st)) != WOS_OK) return s;
+    if ((s = assemble(tb, w, nullptr, nullptr, nullptr, w.Lam0, w.Sig0, st)) != WOS_OK) return s;
     // h0: the problem without the cubic term, rhs = A^T (lam f) - Sig0 g
     SHIP(launch_pointwise(n, tb->d_lambda, nullptr, f, 0.0, 0.0, 0.0, 0.0, -1.0, t1, st));
     SHIP(launch_gemv_t(tb->f64, tb->d_A, n, m, t1, 1.0, 0.0, rhs, st));
     SHIP(launch_gemv_n(true, w.Sig0, m, tb->p, g, -1.0, 1.0, rhs, st));
-    if ((s = tsvd_solve(tb, w.Lam0, true, rhs, rcond, max_sweeps, q, &tr, st)) != WOS_OK) return s;
+    if ((s = tsvd_solve(tb, w, w.Lam0, true, rhs, rcond, max_sweeps, q, &tr, st)) != WOS_OK) return s;
     double gn0 = -1.0, gn = 0.0;
     int it = 0;
     for (it = 0; it <= max_iter; ++it) {
@@ -248,7 +411,7 @@ extern "C" wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* co, const dou
       SHIP(launch_gemv_t(tb->f64, tb->d_A, n, m, t1, 1.0, 0.0, rhs, st));
       SHIP(launch_gemv_n(true, w.Lam0, m, m, q, 1.0, 1.0, rhs, st));
       SHIP(launch_gemv_n(true, w.Sig0, m, tb->p, g, 1.0, 1.0, rhs, st));
-      if ((s = dev_dot(tb, rhs, rhs, nullptr, m, &gn, st)) != WOS_OK) return s;
+      if ((s = dev_dot(w, rhs, rhs, nullptr, m, &gn, st)) != WOS_OK) return s;
       gn = std::sqrt(gn);
       if (gn0 < 0) gn0 = gn;
       if (gn <= tol * gn0 || it == max_iter) break;
@@ -256,7 +419,7 @@ extern "C" wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* co, const dou
       SHIP(hipMemcpyAsync(w.Hess, w.Lam0, sizeof(double) * m * m, hipMemcpyDeviceToDevice, st));
       SHIP(launch_pointwise(n, tb->d_lambda, uu, nullptr, 0.0, 0.0, 3.0 * kappa, 0.0, 0.0, t2, st));
       SHIP(launch_gram(tb->f64, tb->d_A, n, m, t2, w.Hess, st));
-      if ((s = tsvd_solve(tb, w.Hess, true, rhs, rcond, max_sweeps, t1, &tr, st)) != WOS_OK) return s;
+      if ((s = tsvd_solve(tb, w, w.Hess, true, rhs, rcond, max_sweeps, t1, &tr, st)) != WOS_OK) return s;
       SHIP(launch_axpby(m, 1.0, q, -1.0, t1, q, st));
     }
     inf.iters = it;
@@ -273,14 +436,14 @@ extern "C" wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* co, const dou
     double du = 0, nu = 0;
     for (it = 1; it <= max_iter; ++it) {
       SHIP(launch_picard_coef(n, d, uu, w.Ac, st));  // A(x_i) = (1 + u_i^2) I
-      if ((s = assemble(tb, w.Ac, nullptr, nullptr, w.Lam, w.Sig, st)) != WOS_OK) return s;
-      if ((s = linear_rhs(tb, w.Sig, fp, g, rhs, st)) != WOS_OK) return s;
-      if ((s = tsvd_solve(tb, w.Lam, true, rhs, rcond, max_sweeps, q, &tr, st)) != WOS_OK) return s;
+      if ((s = assemble(tb, w, w.Ac, nullptr, nullptr, w.Lam, w.Sig, st)) != WOS_OK) return s;
+      if ((s = linear_rhs(tb, w, w.Sig, fp, g, rhs, st)) != WOS_OK) return s;
+      if ((s = tsvd_solve(tb, w, w.Lam, true, rhs, rcond, max_sweeps, q, &tr, st)) != WOS_OK) return s;
       if ((s = reconstruct(tb, q, g, t1, nullptr, st)) != WOS_OK) return s;
       // du = |u_new - u|_lam, nu = |u_new|_lam
       SHIP(launch_axpby(n, 1.0, t1, -1.0, uu, rhs, st));
-      if ((s = dev_dot(tb, rhs, rhs, tb->d_lambda, n, &du, st)) != WOS_OK) return s;
-      if ((s = dev_dot(tb, t1, t1, tb->d_lambda, n, &nu, st)) != WOS_OK) return s;
+      if ((s = dev_dot(w, rhs, rhs, tb->d_lambda, n, &du, st)) != WOS_OK) return s;
+      if ((s = dev_dot(w, t1, t1, tb->d_lambda, n, &nu, st)) != WOS_OK) return s;
       SHIP(hipMemcpyAsync(uu, t1, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
       if (std::sqrt(du) <= tol * std::sqrt(nu)) break;
     }
@@ -292,10 +455,20 @@ extern "C" wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* co, const dou
   if ((s = reconstruct(tb, q, g, u, grad_u, st)) != WOS_OK) return s;
   if (q_out) SHIP(hipMemcpyAsync(q_out, q, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
   SHIP(hipStreamSynchronize(st));
-  inf.rank = tr.rank;
-  inf.sweeps = tr.sweeps;
-  inf.sigma_max = tr.smax;
-  inf.sigma_threshold = tr.smin_kept;
+  if (co->solver == WOS_SOLVER_TSVD) {
+    inf.rank = tr.rank;
+    inf.sweeps = tr.sweeps;
+    inf.sigma_max = tr.smax;
+    inf.sigma_threshold = tr.smin_kept;
+  }
   if (info) *info = inf;
   return WOS_OK;
+}
+
+}  // namespace wos
+
+extern "C" wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* co, const double* f, const double* g,
+                                double* u, double* grad_u, double* q_out, wos_solve_info* info, void* stream) {
+  if (!tb) return sfail(WOS_EINVAL, "NULL argument");
+  return wos::solve_request(tb, tb->sw, co, f, g, u, grad_u, q_out, info, static_cast<hipStream_t>(stream));
 }

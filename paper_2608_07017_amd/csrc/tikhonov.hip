@@ -1,0 +1,252 @@
+// Kernels of the regularised (Tikhonov) solve of the assembled system and
+// of its matrix-free FP64 operator, used for mixed-precision iterative
+// refinement.
+//
+// With L = [B^(0); ..; B^(d-1); A] ((d+1) n x m) and, per site i, the
+// (d+1) x (d+1) block W_i
+//   W_i[a][b] = lambda_i A_ab(x_i)   (a, b < d),   W_i[a][d] = 0,
+//   W_i[d][b] = -lambda_i b_b(x_i),  W_i[d][d] = lambda_i c(x_i),
+// the system matrix of eq. linear_q is Lambda = L^T W L, Sigma = L^T W [K; H]
+// and the right-hand side -A^T (lambda o f) - Sigma g = -L^T (e_d (lambda o f)
+// + W [K; H] g).  Vectors over the (d+1) n rows are stored block by block
+// (row block a, then site i).
+#include <hip/hip_runtime.h>
+
+#include "wos_solve_kernels.hpp"
+
+namespace wos {
+
+namespace {
+
+int nblocks(size_t count, int block) {
+  size_t g = (count + block - 1) / block;
+  if (g > 65536) g = 65536;
+  return (int)(g < 1 ? 1 : g);
+}
+
+// R (rows (d+1) n, `cols` = m or m + p columns) = W applied to the row
+// blocks of [B; A] (left columns) and [K; H] (right columns), in TO.
+template <typename T, typename TO>
+__global__ void weight_rows_any_kernel(const T* __restrict__ A, const T* __restrict__ B, const T* __restrict__ H,
+                                       const T* __restrict__ K, const double* __restrict__ lam,
+                                       const double* __restrict__ Ac, const double* __restrict__ bc,
+                                       const double* __restrict__ cc, int n, int m, int p, int d, int cols,
+                                       TO* __restrict__ R) {
+  const size_t total = (size_t)(d + 1) * n * cols;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+    const size_t col = idx % cols;
+    const size_t row = idx / cols;
+    const int a = (int)(row / n);
+    const int i = (int)(row % n);
+    const bool left = col < (size_t)m;
+    const size_t jj = left ? col : col - m;
+    const size_t w = left ? (size_t)m : (size_t)p;
+    const T* G = left ? B : K;
+    const T* Z = left ? A : H;
+    const double li = lam[i];
+    double v = 0.0;
+    if (a < d) {
+      for (int b = 0; b < d; ++b) {
+        const double ab = Ac ? Ac[((size_t)i * d + a) * d + b] : (a == b ? 1.0 : 0.0);
+        if (ab != 0.0) v += li * ab * (double)G[((size_t)b * n + i) * w + jj];
+      }
+    } else {
+      if (bc)
+        for (int b = 0; b < d; ++b) v -= li * bc[(size_t)i * d + b] * (double)G[((size_t)b * n + i) * w + jj];
+      if (cc) v += li * cc[i] * (double)Z[(size_t)i * w + jj];
+    }
+    R[idx] = (TO)v;
+  }
+}
+
+// z (block vector) = W y (trans = 0) or W^T y (trans = 1), plus e_d (s o f)
+// when f is given
+__global__ void apply_w_kernel(int n, int d, const double* __restrict__ lam, const double* __restrict__ Ac,
+                               const double* __restrict__ bc, const double* __restrict__ cc,
+                               const double* __restrict__ y, int trans, const double* __restrict__ f,
+                               double* __restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double li = lam[i];
+  double yv[4] = {0, 0, 0, 0};
+  for (int a = 0; a <= d; ++a) yv[a] = y[(size_t)a * n + i];
+  auto wab = [&](int a, int b) -> double {  // W_i[a][b]
+    if (a < d) {
+      if (b == d) return 0.0;
+      return li * (Ac ? Ac[((size_t)i * d + a) * d + b] : (a == b ? 1.0 : 0.0));
+    }
+    if (b < d) return bc ? -li * bc[(size_t)i * d + b] : 0.0;
+    return cc ? li * cc[i] : 0.0;
+  };
+  for (int a = 0; a <= d; ++a) {
+    double s = 0.0;
+    for (int b = 0; b <= d; ++b) s += (trans ? wab(b, a) : wab(a, b)) * yv[b];
+    if (a == d && f) s += li * f[i];
+    z[(size_t)a * n + i] = s;
+  }
+}
+
+// y[j] += alpha sum_{r in chunk} X[r][j] v[r]  (y pre-scaled by the caller)
+template <typename T>
+__global__ __launch_bounds__(256) void gemv_t_split_kernel(const T* __restrict__ X, int rows, int cols, int ld,
+                                                           const double* __restrict__ v, double alpha,
+                                                           double* __restrict__ y, int chunk) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
+  double acc = 0.0;
+  for (int r = r0; r < r1; ++r) acc += (double)X[(size_t)r * ld + j] * v[r];
+  if (acc != 0.0) atomicAdd(&y[j], alpha * acc);
+}
+
+// y[i] = alpha sum_j X[i][j] v[j] + beta y[i], one wavefront per row
+template <typename T>
+__global__ __launch_bounds__(256) void gemv_n_ld_kernel(const T* __restrict__ X, int rows, int cols, int ld,
+                                                        const double* __restrict__ v, double alpha, double beta,
+                                                        double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  double acc = 0.0;
+  for (int j = lane; j < cols; j += 64) acc += (double)X[(size_t)row * ld + j] * v[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) y[row] = alpha * acc + (beta == 0.0 ? 0.0 : beta * y[row]);
+}
+
+__global__ void scale_kernel(int n, double beta, double* __restrict__ y) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += stride)
+    y[i] = beta == 0.0 ? 0.0 : beta * y[i];
+}
+
+// out = rcond^2 * max_i N[i][i]; one workgroup
+template <typename T>
+__global__ __launch_bounds__(256) void reg_from_diag_kernel(const T* __restrict__ N, int m, int ld, double rcond,
+                                                            double* __restrict__ out) {
+  __shared__ double s[256];
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) mx = fmax(mx, (double)N[(size_t)i * ld + i]);
+  s[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = rcond * rcond * s[0];
+}
+
+template <typename T>
+__global__ void add_diag_kernel(T* __restrict__ N, int m, int ld, const double* __restrict__ reg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) N[(size_t)i * ld + i] += (T)reg[0];
+}
+
+// y (double) = x + s * z with s read from the device (reg) or 1
+__global__ void axpy_reg_kernel(int n, const double* __restrict__ x, const double* __restrict__ reg, double sign,
+                                const double* __restrict__ z, double* __restrict__ y) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const double s = sign * (reg ? reg[0] : 1.0);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += stride) y[i] = x[i] + s * z[i];
+}
+
+__global__ void to_f32_kernel(int n, const double* __restrict__ x, float* __restrict__ y) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += stride) y[i] = (float)x[i];
+}
+
+__global__ void add_f32_kernel(int n, const float* __restrict__ d, double* __restrict__ q) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += stride) q[i] += (double)d[i];
+}
+
+}  // namespace
+
+hipError_t launch_weight_rows_any(bool f64_in, bool f32_out, const void* A, const void* B, const void* H,
+                                  const void* K, const double* lam, const double* Ac, const double* bc,
+                                  const double* cc, int n, int m, int p, int d, int cols, void* R, hipStream_t st) {
+  const size_t total = (size_t)(d + 1) * n * cols;
+  const dim3 g(nblocks(total, 256)), b(256);
+  if (f64_in && !f32_out)
+    hipLaunchKernelGGL((weight_rows_any_kernel<double, double>), g, b, 0, st, (const double*)A, (const double*)B,
+                       (const double*)H, (const double*)K, lam, Ac, bc, cc, n, m, p, d, cols, (double*)R);
+  else if (f64_in && f32_out)
+    hipLaunchKernelGGL((weight_rows_any_kernel<double, float>), g, b, 0, st, (const double*)A, (const double*)B,
+                       (const double*)H, (const double*)K, lam, Ac, bc, cc, n, m, p, d, cols, (float*)R);
+  else if (!f64_in && !f32_out)
+    hipLaunchKernelGGL((weight_rows_any_kernel<float, double>), g, b, 0, st, (const float*)A, (const float*)B,
+                       (const float*)H, (const float*)K, lam, Ac, bc, cc, n, m, p, d, cols, (double*)R);
+  else
+    hipLaunchKernelGGL((weight_rows_any_kernel<float, float>), g, b, 0, st, (const float*)A, (const float*)B,
+                       (const float*)H, (const float*)K, lam, Ac, bc, cc, n, m, p, d, cols, (float*)R);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_w(int n, int d, const double* lam, const double* Ac, const double* bc, const double* cc,
+                          const double* y, bool trans, const double* f, double* z, hipStream_t st) {
+  hipLaunchKernelGGL(apply_w_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, d, lam, Ac, bc, cc, y,
+                     trans ? 1 : 0, f, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_t_ld(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
+                            double beta, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(scale_kernel, dim3(nblocks(cols, 256)), dim3(256), 0, st, cols, beta, y);
+  if (rows <= 0) return hipGetLastError();
+  const int chunk = 128;
+  const dim3 g((cols + 255) / 256, (rows + chunk - 1) / chunk);
+  if (f64)
+    hipLaunchKernelGGL(gemv_t_split_kernel<double>, g, dim3(256), 0, st, (const double*)X, rows, cols, ld, v, alpha, y,
+                       chunk);
+  else
+    hipLaunchKernelGGL(gemv_t_split_kernel<float>, g, dim3(256), 0, st, (const float*)X, rows, cols, ld, v, alpha, y,
+                       chunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_n_ld(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
+                            double beta, double* y, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(gemv_n_ld_kernel<double>, dim3((rows + 3) / 4), dim3(256), 0, st, (const double*)X, rows, cols,
+                       ld, v, alpha, beta, y);
+  else
+    hipLaunchKernelGGL(gemv_n_ld_kernel<float>, dim3((rows + 3) / 4), dim3(256), 0, st, (const float*)X, rows, cols,
+                       ld, v, alpha, beta, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_reg_from_diag(bool f64, const void* N, int m, int ld, double rcond, double* out, hipStream_t st) {
+  if (f64)
+    hipLaunchKernelGGL(reg_from_diag_kernel<double>, dim3(1), dim3(256), 0, st, (const double*)N, m, ld, rcond, out);
+  else
+    hipLaunchKernelGGL(reg_from_diag_kernel<float>, dim3(1), dim3(256), 0, st, (const float*)N, m, ld, rcond, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_diag(bool f64, void* N, int m, int ld, const double* reg, hipStream_t st) {
+  if (f64)
+    hipLaunchKernelGGL(add_diag_kernel<double>, dim3((m + 255) / 256), dim3(256), 0, st, (double*)N, m, ld, reg);
+  else
+    hipLaunchKernelGGL(add_diag_kernel<float>, dim3((m + 255) / 256), dim3(256), 0, st, (float*)N, m, ld, reg);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_reg(int n, const double* x, const double* reg, double sign, const double* z, double* y,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(axpy_reg_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, n, x, reg, sign, z, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32(int n, const double* x, float* y, hipStream_t st) {
+  hipLaunchKernelGGL(to_f32_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, n, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_f32(int n, const float* dlt, double* q, hipStream_t st) {
+  hipLaunchKernelGGL(add_f32_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, n, dlt, q);
+  return hipGetLastError();
+}
+
+}  // namespace wos

@@ -48,7 +48,21 @@ struct SolveWork {
   double* Ac = nullptr;     // n x d x d (Picard coefficients)
   double* red = nullptr;    // 2 reduction slots
   size_t vlen = 0;
+  // regularised solve
+  double* blk = nullptr;    // 2 block vectors of (d+1) n
+  double* regv = nullptr;   // the regularisation parameter (device)
+  int* info = nullptr;      // Cholesky status (device)
+  float* R32 = nullptr;     // (d+1) n x m weighted rows, FP32
+  float* Lam32 = nullptr;   // m x m
+  float* N32 = nullptr;     // m x m normal matrix / its factor
+  float* v32 = nullptr;     // m
+  size_t bytes = 0;         // device memory held
 };
+
+// One solve on workspace `w` (C ABI wos_solve uses the toolbox's own).
+wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, const double* f, const double* g,
+                         double* u, double* grad_u, double* q_out, wos_solve_info* info, hipStream_t st);
+void free_work(SolveWork& w);
 
 }  // namespace wos
 

@@ -37,4 +37,36 @@ hipError_t launch_picard_coef(int n, int d, const double* u, double* Ac, hipStre
 hipError_t launch_absmax(int n, const double* e, double* out, hipStream_t st);
 hipError_t launch_count_above(int n, const double* e, double thr, double* out, hipStream_t st);
 
+
+// ---- MFMA GEMM (mfma_gemm.hip): C = alpha op(A) op(B) + beta C, row-major
+hipError_t mfma_gemm_f64(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
+                         const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st);
+hipError_t mfma_gemm_f32(bool ta, bool tb, int M, int N, int K, float alpha, const float* A, int lda,
+                         const float* B, int ldb, float beta, float* C, int ldc, hipStream_t st);
+hipError_t mfma_gemm_f64_a32(bool ta, bool tb, int M, int N, int K, double alpha, const float* A, int lda,
+                             const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st);
+
+// ---- Cholesky (chol.hip): in place, lower, row-major; info = first bad pivot + 1
+hipError_t cholesky_f64(double* A, int n, int lda, int* info, hipStream_t st);
+hipError_t cholesky_f32(float* A, int n, int lda, int* info, hipStream_t st);
+hipError_t cholesky_solve_f64(const double* L, int n, int lda, double* y, hipStream_t st);
+hipError_t cholesky_solve_f32(const float* L, int n, int lda, float* y, hipStream_t st);
+
+// ---- regularised solve and matrix-free operator (tikhonov.hip)
+hipError_t launch_weight_rows_any(bool f64_in, bool f32_out, const void* A, const void* B, const void* H,
+                                  const void* K, const double* lam, const double* Ac, const double* bc,
+                                  const double* cc, int n, int m, int p, int d, int cols, void* R, hipStream_t st);
+hipError_t launch_apply_w(int n, int d, const double* lam, const double* Ac, const double* bc, const double* cc,
+                          const double* y, bool trans, const double* f, double* z, hipStream_t st);
+hipError_t launch_gemv_t_ld(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
+                            double beta, double* y, hipStream_t st);
+hipError_t launch_gemv_n_ld(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
+                            double beta, double* y, hipStream_t st);
+hipError_t launch_reg_from_diag(bool f64, const void* N, int m, int ld, double rcond, double* out, hipStream_t st);
+hipError_t launch_add_diag(bool f64, void* N, int m, int ld, const double* reg, hipStream_t st);
+hipError_t launch_axpy_reg(int n, const double* x, const double* reg, double sign, const double* z, double* y,
+                           hipStream_t st);
+hipError_t launch_to_f32(int n, const double* x, float* y, hipStream_t st);
+hipError_t launch_add_f32(int n, const float* dlt, double* q, hipStream_t st);
+
 }  // namespace wos

@@ -190,3 +190,65 @@ def test_solve_rejects_bad_input(disk_tb):
     tb, _ = disk_tb
     with pytest.raises(P.WosError):
         tb.solve(np.zeros(tb.n), np.zeros(tb.p), kind="linear", rcond=2.0)
+
+
+# ---------------------------------------------------------------- Tikhonov
+def _tik_problem(x, n, d):
+    th = np.pi * x[:, 0]
+    kap = 1.0 + 49.0 * (0.5 + 0.5 * np.sin(3 * x[:, 1]))
+    R = np.stack([np.stack([np.cos(th), -np.sin(th)], -1), np.stack([np.sin(th), np.cos(th)], -1)], -2)
+    A = R @ (np.eye(2)[None] * np.stack([np.ones(n), kap], -1)[:, None, :]) @ np.transpose(R, (0, 2, 1))
+    b = 0.5 * np.stack([np.sin(2 * x[:, 1]), np.cos(x[:, 0])], 1)
+    c = 0.2 + 0.0 * x[:, 0]
+    return A, b, c
+
+
+@pytest.mark.parametrize("rcond", [1e-3, 1e-2])
+def test_tikhonov_f64_matches_oracle(disk_tb, rcond):
+    tb, mats = disk_tb
+    n = tb.n
+    lam = mats["lambda"]
+    x = _rings(5)
+    A, b, c = _tik_problem(x, n, 2)
+    f = np.cos(2 * x[:, 0]) + x[:, 1]
+    g = 0.3 * W.circle_nodes(30)[:, 0]
+    ref = OL.solve_linear(mats, lam, f, g, Acoef=A, bcoef=b, ccoef=c, rcond=rcond, solver="tikhonov")
+    _, reg = OL.tikhonov_solve(ref["Lambda"], OL.rhs(mats, lam, ref["Sigma"], f, g), rcond)
+    u, gu, q, info = tb.solve(f, g, kind="linear", A=A, b=b, c=c, rcond=rcond, solver="tikhonov")
+    torch.cuda.synchronize()
+    assert np.isclose(info["reg"], reg, rtol=1e-10)
+    assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < 1e-9
+    assert np.allclose(q.cpu().numpy(), ref["q"], rtol=1e-7, atol=1e-9 * np.abs(ref["q"]).max())
+
+
+@pytest.fixture(scope="module")
+def square_f32_tb():
+    dom = W.unit_square()
+    sites = W.sample_sites(dom, 300, 5, 1e-3)    # several Cholesky panels, ragged last one
+    bn = W.square_nodes(20)
+    return _build(dom, sites, bn, 1500, 1e-4, precision="f32")
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_tikhonov_on_fp32_toolbox_matches_oracle(square_f32_tb, precision):
+    tb, mats = square_f32_tb
+    n = tb.n
+    lam = mats["lambda"]
+    x = tb.sites
+    A, b, c = _tik_problem(x, n, 2)
+    f = np.sin(np.pi * x[:, 0]) * (1 + x[:, 1])
+    bn = tb.bnodes
+    g = bn[:, 0] ** 2 - bn[:, 1] ** 2
+    ref = OL.solve_linear(mats, lam, f, g, Acoef=A, bcoef=b, ccoef=c, rcond=1e-3, solver="tikhonov")
+    u, gu, q, info = tb.solve(f, g, kind="linear", A=A, b=b, c=c, rcond=1e-3, solver="tikhonov",
+                              precision=precision, refine_tol=1e-13, max_refine=30)
+    torch.cuda.synchronize()
+    _say(precision, info)
+    if precision == "mixed":
+        assert info["fallback"] == 0
+        assert info["refine_iters"] >= 1 and info["refine_residual"] <= 1e-13
+        # reg comes from the FP32 normal matrix: relative difference ~1e-7
+        tol = 1e-6
+    else:
+        tol = 1e-9
+    assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < tol

@@ -114,3 +114,26 @@ def test_disk_poisson_end_to_end():
     err = np.sqrt(np.sum(lam * (sol["u"] - exact) ** 2)) / np.sqrt(np.sum(lam * exact**2))
     # measured 0.049; a sign error in Lambda or in the right-hand side gives ~1
     assert err < 0.08
+
+
+def test_tikhonov_matches_svd_filter_factors():
+    # q = sum_j s_j / (s_j^2 + reg) v_j u_j^T r: the closed form of the
+    # regularised least-squares solution from the SVD
+    rng = np.random.default_rng(12)
+    U, _ = np.linalg.qr(rng.normal(size=(25, 25)))
+    V, _ = np.linalg.qr(rng.normal(size=(25, 25)))
+    s = np.logspace(0, -6, 25)
+    M = U @ np.diag(s) @ V.T
+    r = rng.normal(size=25)
+    q, reg = L.tikhonov_solve(M, r, 1e-2)
+    assert np.isclose(reg, 1e-4 * np.max(np.sum(M * M, axis=0)))
+    ref = V @ ((s / (s * s + reg)) * (U.T @ r))
+    assert np.allclose(q, ref, rtol=1e-9, atol=1e-12)
+
+
+def test_tikhonov_tends_to_the_inverse_for_a_well_conditioned_matrix():
+    rng = np.random.default_rng(13)
+    M = rng.normal(size=(12, 12)) + 6 * np.eye(12)
+    r = rng.normal(size=12)
+    q, _ = L.tikhonov_solve(M, r, 1e-7)
+    assert np.allclose(q, np.linalg.solve(M, r), rtol=1e-9, atol=1e-11)
