@@ -10,7 +10,12 @@ second over the whole step, inputs resident in HBM.
 Workload (default): 2-D unit square, 1024 uniform interior sites, 256
 equispaced boundary nodes, 1e4 walks per site, eps = 1e-4, FP32 walker.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+The line also carries "serving": solves/s and p50/p99 latency of a served
+stream of Dirichlet problems on resident L-shape toolboxes (256/1024/4096
+sites), mixed precision against FP64, with the L2 errors of both against
+the manufactured solutions.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-serving]
 
 Prints one JSON line.
 """
@@ -27,7 +32,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-METRIC = "WoS walk-steps/s (toolbox build)"
+METRIC = "WoS walk-steps/s (toolbox build)"  # the served-solve rates are reported under "serving"
 MI355X_CUS = 256
 MI355X_CLOCK = 2.4e9
 # FP32 vector peak 157.3 TFLOP/s = 256 CU x 128 FMA lanes x 2.4 GHz: 7.86e13
@@ -75,6 +80,14 @@ def parse():
     ap.add_argument("--workload", default="square1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=3)
+    ap.add_argument("--no-serving", action="store_true", help="skip the served-solve stream")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="open-loop requests (mixed precision)")
+    ap.add_argument("--serve-saturation", type=int, default=300, help="requests of the saturation run")
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-pool", type=int, default=4, help="problems per toolbox")
+    ap.add_argument("--serve-rho", type=float, default=0.8)
+    ap.add_argument("--serve-rcond", type=float, default=0.1)
+    ap.add_argument("--serve-seed", type=int, default=7)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy a MIB-sized device buffer 3 times (a known-size "
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -102,6 +115,86 @@ def cpu_baseline(cfg, rows):
     return {"value": steps / dt, "unit": "walk-steps/s", "cores": 1, "kind": "oracle",
             "sample": "%d of %d sites x %d walks (%d walk-steps, %.1f s), FP64 NumPy, one thread"
                       % (rows, len(cfg["sites"]), cfg["walks"], steps, dt)}
+
+
+SERVE_SIZES = (256, 1024, 4096)
+
+
+def serving(a, torch, W, P):
+    """Served stream on resident L-shape toolboxes: -div(A grad u) + b . grad u = f
+    with A anisotropic (up to 1:100) and b smooth, solved by the Tikhonov route
+    in mixed precision and in FP64.  Saturation rate (all requests queued at
+    once), then Poisson arrivals at rho times that rate; latency = finish - arrival."""
+    rng = np.random.default_rng(a.serve_seed)
+    boxes = []
+    for n in SERVE_SIZES:
+        cfg = W.config("lshape%d" % n)
+        tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], cfg["walks"], cfg["eps"], seed=cfg["seed"],
+                       precision="f32")
+        tb.build()
+        lam = tb.export("lambda").cpu().numpy()
+        pool = []
+        for k in range(a.serve_pool):
+            pr = W.anisotropic_problem(a.serve_seed * 1000 + 10 * n + k, cfg["sites"], cfg["bnodes"])
+            dev = {key: torch.as_tensor(v, dtype=torch.float64, device="cuda").contiguous()
+                   for key, v in (("f", -pr["f"]), ("g", pr["g"]), ("A", pr["A"]), ("b", -pr["b"]))}
+            pool.append((dev, pr["u"]))
+        boxes.append((tb, lam, pool))
+    torch.cuda.synchronize()
+
+    def kw(dev, prec):
+        return dict(kind="linear", A=dev["A"], b=dev["b"], rcond=a.serve_rcond, solver="tikhonov", precision=prec,
+                    refine_tol=1e-8)
+
+    # accuracy against the manufactured solutions, both precisions
+    l2 = {}
+    ok = True
+    for tb, lam, pool in boxes:
+        e = {"f64": [], "mixed": []}
+        for dev, uex in pool:
+            for prec in ("f64", "mixed"):
+                u, _, _, info = tb.solve(dev["f"], dev["g"], **kw(dev, prec))
+                e[prec].append(float(np.sqrt(np.sum(lam * (u.cpu().numpy() - uex) ** 2))))
+            ok = ok and e["mixed"][-1] <= 1.01 * e["f64"][-1] + 1e-6
+        l2[str(tb.n)] = {p: float(np.mean(v)) for p, v in e.items()}
+
+    def run(prec, nreq, rate):
+        sv = P.Server(slots=a.serve_slots)
+        for tb, lam, pool in boxes:  # warm every workspace
+            sv.poll(sv.submit(tb, pool[0][0]["f"], pool[0][0]["g"], **kw(pool[0][0], prec))[0])
+        picks = [(int(rng.integers(len(boxes))), int(rng.integers(a.serve_pool))) for _ in range(nreq)]
+        gaps = rng.exponential(1.0 / rate, nreq) if rate else np.zeros(nreq)
+        arrivals = np.cumsum(gaps)
+        tickets = []
+        t0 = time.perf_counter()
+        for (bi, pi), ta in zip(picks, arrivals):
+            while time.perf_counter() - t0 < ta:
+                pass
+            tb, lam, pool = boxes[bi]
+            dev = pool[pi][0]
+            tickets.append(sv.submit(tb, dev["f"], dev["g"], **kw(dev, prec))[0])
+        times = [sv.poll(t)[1] for t in tickets]
+        sv.close()
+        first = min(t[0] for t in times)
+        last = max(t[2] for t in times)
+        lat = np.array([t[2] - t[0] for t in times]) * 1e3
+        return {"requests": nreq, "solves_per_s": nreq / (last - first), "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99))}
+
+    out = {"workload": "L-shape toolboxes of %s sites (n/4 boundary nodes, 1e4 walks/site, eps 1e-4, FP32), "
+                       "requests uniform over them: -div(A grad u) + b.grad u = f, A seeded smooth SPD with "
+                       "anisotropy up to 1:100, |b| <= 0.8, manufactured u; Tikhonov rcond %g"
+                       % ("/".join(map(str, SERVE_SIZES)), a.serve_rcond),
+           "slots": a.serve_slots, "l2_error": l2, "mixed_at_fp64_l2_error": bool(ok)}
+    for prec, nopen in (("mixed", a.serve_requests), ("f64", max(100, a.serve_requests // 4))):
+        print("serving: %s saturation" % prec, file=sys.stderr, flush=True)
+        sat = run(prec, a.serve_saturation, 0.0)
+        print("serving: %s open loop" % prec, file=sys.stderr, flush=True)
+        rate = a.serve_rho * sat["solves_per_s"]
+        out[prec] = {"saturation_solves_per_s": sat["solves_per_s"], "open_loop": dict(run(prec, nopen, rate), rho=a.serve_rho,
+                                                                                     arrival_rate=rate)}
+    out["mixed_vs_f64_saturation"] = out["mixed"]["saturation_solves_per_s"] / out["f64"]["saturation_solves_per_s"]
+    return out
 
 
 def main():
@@ -182,6 +275,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = src.numel() * 4
+    if not a.no_serving:
+        out["serving"] = serving(a, torch, W, P)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_rows)
     print(json.dumps(out), flush=True)

@@ -240,6 +240,44 @@ typedef struct {
 wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* coeffs, const double* f, const double* g,
                      double* u, double* grad_u, double* q, wos_solve_info* info, void* stream);
 
+/* ------------------------------------------------------------ serving
+ * A request server over resident toolboxes.  Solves are queued in arrival
+ * order; `slots` workers (each a host thread with its own HIP stream and
+ * solve workspaces) take the next request as soon as they are free, so the
+ * solves of up to `slots` requests overlap on the device (continuous
+ * admission: a request that arrives while others run starts as soon as a
+ * slot is free).  A request is admitted only when its workspace fits
+ * `mem_budget`; workers release cached workspaces for waiting requests.
+ * The result of a request does not depend on what runs beside it.
+ * Toolboxes must stay built and unchanged while they have requests queued. */
+typedef struct wos_server wos_server;
+
+typedef struct {
+  int32_t slots;      /* concurrent requests, 1 .. 16; 0 -> 4                  */
+  size_t mem_budget;  /* device bytes for solve workspaces; 0 -> no limit     */
+} wos_server_opts;
+
+wos_status wos_server_create(const wos_server_opts* opts, wos_server** out);
+
+/* Queues one solve (arguments as for wos_solve; device buffers must stay
+ * valid until the request is polled as finished).  The coefficients struct
+ * is copied.  Returns at once with a ticket.                                  */
+wos_status wos_server_submit(wos_server* sv, wos_toolbox* tb, const wos_coeffs* coeffs, const double* f,
+                             const double* g, double* u, double* grad_u, uint64_t* ticket);
+
+/* Result of a request: WOS_EBUSY while it runs (block = 0), else its status
+ * after it finished (block = 1 waits).  On completion fills *info and, if
+ * times != NULL, times[0..2] = submit, start and end times in seconds (one
+ * steady clock), and forgets the ticket.                                     */
+wos_status wos_server_poll(wos_server* sv, uint64_t ticket, int32_t block, wos_solve_info* info,
+                           double* times);
+
+/* Requests waiting for a slot and requests not yet finished.                 */
+wos_status wos_server_pending(wos_server* sv, int64_t* queued, int64_t* unfinished);
+
+/* Finishes every queued request, then stops the workers and frees them.     */
+void wos_server_destroy(wos_server* sv);
+
 /* Kernel timing.  When enabled, wos_toolbox_build records HIP events on its
  * stream around the volume kernel, the walker kernel and the normalisation;
  * wos_toolbox_get_timings synchronises and returns their durations in

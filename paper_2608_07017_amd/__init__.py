@@ -15,9 +15,9 @@ import numpy as np
 import torch
 
 from ._lib import (EXPORTS, KINDS, PRECISION, PROBLEMS, SOLVE_PRECISION, SOLVERS, WosBuildOpts, WosCoeffs,
-                   WosDomain, WosError, WosSolveInfo, WosToolboxInfo, check, lib)
+                   WosDomain, WosError, WosServerOpts, WosSolveInfo, WosToolboxInfo, check, lib)
 
-__all__ = ["Toolbox", "build_toolbox", "WosError", "lib"]
+__all__ = ["Toolbox", "Server", "build_toolbox", "WosError", "lib"]
 
 
 def _stream_handle(stream=None):
@@ -134,6 +134,19 @@ class Toolbox:
         g: (p,) boundary data at the nodes; A (n,d,d), b (n,d), c (n,)
         coefficients at the sites for kind="linear".  Returns
         (u, grad_u, q, info) with device float64 tensors."""
+        f, g, A, b, c, co = self._coeffs(f, g, kind, A, b, c, kappa, rcond, tol, max_iter, max_sweeps, solver,
+                                         precision, max_refine, refine_tol)
+        u = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        gu = torch.empty((self.dim, self.n), dtype=torch.float64, device="cuda")
+        q = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        info = WosSolveInfo()
+        check(lib().wos_solve(self._h, ctypes.byref(co), _dptr(f), _dptr(g), _dptr(u), _dptr(gu), _dptr(q),
+                              ctypes.byref(info), _stream_handle(stream)))
+        return u, gu, q, {k: getattr(info, k) for k, _ in info._fields_}
+
+    def _coeffs(self, f, g, kind="linear", A=None, b=None, c=None, kappa=1.0, rcond=1e-3, tol=0.0, max_iter=0,
+                max_sweeps=0, solver="tsvd", precision="f64", max_refine=0, refine_tol=0.0):
+        """Device copies of the problem data and the wos_coeffs struct."""
         dev = lambda x: None if x is None else torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
         f, g, A, b, c = dev(f), dev(g), dev(A), dev(b), dev(c)
         if f.numel() != self.n or g.numel() != self.p:
@@ -147,13 +160,7 @@ class Toolbox:
                        kappa=float(kappa), rcond=float(rcond), tol=float(tol), max_iter=int(max_iter),
                        max_sweeps=int(max_sweeps), solver=SOLVERS[solver], precision=SOLVE_PRECISION[precision],
                        max_refine=int(max_refine), refine_tol=float(refine_tol))
-        u = torch.empty(self.n, dtype=torch.float64, device="cuda")
-        gu = torch.empty((self.dim, self.n), dtype=torch.float64, device="cuda")
-        q = torch.empty(self.n, dtype=torch.float64, device="cuda")
-        info = WosSolveInfo()
-        check(lib().wos_solve(self._h, ctypes.byref(co), _dptr(f), _dptr(g), _dptr(u), _dptr(gu), _dptr(q),
-                              ctypes.byref(info), _stream_handle(stream)))
-        return u, gu, q, {k: getattr(info, k) for k, _ in info._fields_}
+        return f, g, A, b, c, co
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -163,6 +170,58 @@ class Toolbox:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request server over resident toolboxes (include/wos.h, wos_server_*):
+    up to `slots` solves run concurrently, each on its own stream."""
+
+    def __init__(self, slots=4, mem_budget=0):
+        self._h = ctypes.c_void_p()
+        opts = WosServerOpts(slots=int(slots), mem_budget=int(mem_budget))
+        check(lib().wos_server_create(ctypes.byref(opts), ctypes.byref(self._h)))
+        self._live = {}  # ticket -> tensors that must outlive the request
+
+    def submit(self, tb, f, g, u=None, grad=False, **problem):
+        """Queue a solve on toolbox `tb` (keyword arguments as Toolbox.solve);
+        returns (ticket, u, grad_u) with the output tensors it will fill."""
+        f, g, A, b, c, co = tb._coeffs(f, g, **problem)
+        if u is None:
+            u = torch.empty(tb.n, dtype=torch.float64, device="cuda")
+        gu = torch.empty((tb.dim, tb.n), dtype=torch.float64, device="cuda") if grad else None
+        t = ctypes.c_uint64()
+        check(lib().wos_server_submit(self._h, tb._h, ctypes.byref(co), _dptr(f), _dptr(g), _dptr(u),
+                                      _dptr(gu) if grad else ctypes.c_void_p(0), ctypes.byref(t)))
+        self._live[t.value] = (f, g, A, b, c, u, gu)
+        return t.value, u, gu
+
+    def poll(self, ticket, block=True):
+        """None while running (block=False); else (info, (t_submit, t_start, t_end))."""
+        info = WosSolveInfo()
+        times = (ctypes.c_double * 3)()
+        st = lib().wos_server_poll(self._h, ctypes.c_uint64(ticket), 1 if block else 0, ctypes.byref(info), times)
+        if st == -6 and not block:
+            return None
+        self._live.pop(ticket, None)
+        check(st)
+        return {k: getattr(info, k) for k, _ in info._fields_}, tuple(times)
+
+    def pending(self):
+        q, u = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().wos_server_pending(self._h, ctypes.byref(q), ctypes.byref(u)))
+        return q.value, u.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().wos_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass
 

@@ -51,6 +51,10 @@ class WosCoeffs(ctypes.Structure):
                 ("refine_tol", ctypes.c_double)]
 
 
+class WosServerOpts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("mem_budget", ctypes.c_size_t)]
+
+
 class WosSolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("rank", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("sigma_max", ctypes.c_double), ("sigma_threshold", ctypes.c_double),
@@ -82,6 +86,12 @@ SIGNATURES = {
     "wos_toolbox_free": (None, [_P]),
     "wos_last_error": (ctypes.c_char_p, []),
     "wos_version": (ctypes.c_char_p, []),
+    "wos_server_create": (ctypes.c_int, [ctypes.POINTER(WosServerOpts), ctypes.POINTER(_P)]),
+    "wos_server_submit": (ctypes.c_int, [_P, _P, ctypes.POINTER(WosCoeffs), _P, _P, _P, _P,
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+    "wos_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(WosSolveInfo), _D]),
+    "wos_server_pending": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "wos_server_destroy": (None, [_P]),
 }
 
 

@@ -3,18 +3,19 @@
 // equations of the solve path.
 //
 // Right-looking, panel width 64: the 64 x 64 diagonal block is factored by
-// one workgroup in LDS, the panel below it is solved against that block
-// (one thread per row, the block's factor in LDS), and the trailing matrix
-// is updated by the MFMA GEMM (the full square; only its lower part is read
-// later).  A non-positive pivot is replaced by a tiny one and reported in
-// `info` (first failing column + 1), so a singular input never produces
-// NaNs.
+// one wavefront in LDS, which also inverts its factor (kept in Dinv, one
+// 64 x 64 block per panel); the panel below is then L21 = A21 L11^{-T}, an
+// MFMA GEMM with that inverse, and the trailing matrix is updated by the
+// MFMA GEMM (the full square; only its lower part is read later).  A
+// non-positive pivot is replaced by a tiny one and reported in `info`
+// (first failing column + 1), so a singular input never produces NaNs.
 //
-// Triangular solves, one right-hand side: the blocks are taken in order;
-// the block's right-hand side is first reduced by the blocks already solved
-// (a GEMV over the block's 64 rows, many workgroups) and then solved by one
-// wavefront against the diagonal block.
+// The solves with the factor use its explicit inverse X = L^{-1}, built by
+// blocks from the diagonal inverses (two MFMA GEMMs per block row), so that
+// each solve (L L^T)^{-1} r = X^T (X r) is two matrix-vector products.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "wos_solve_kernels.hpp"
 
@@ -33,117 +34,52 @@ __device__ __forceinline__ float tiny_pivot<float>() { return 1e-30f; }
 template <>
 __device__ __forceinline__ double tiny_pivot<double>() { return 1e-300; }
 
-// factor the diagonal block A[k0 .. k0+b)^2 in place (b <= NB)
+// Factor the diagonal block A[k0 .. k0+b)^2 in place (b <= NB) and write
+// the inverse of its factor to Dinv (NB x NB, row-major, zero above the
+// diagonal).  One wavefront; lane i owns row i.
 template <typename T>
-__global__ __launch_bounds__(256) void potrf_diag_kernel(T* __restrict__ A, int lda, int k0, int b,
-                                                          int* __restrict__ info) {
+__global__ __launch_bounds__(64) void potrf_diag_kernel(T* __restrict__ A, int lda, int k0, int b,
+                                                         T* __restrict__ Dinv, int* __restrict__ info) {
   __shared__ T s[NB][NB + 1];
-  __shared__ T s_d;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < b * b; e += 256) {
-    const int i = e / b, j = e % b;
-    s[i][j] = A[(size_t)(k0 + i) * lda + k0 + j];
+  const int lane = threadIdx.x;
+  for (int e = lane; e < NB * NB; e += 64) {
+    const int i = e / NB, j = e % NB;
+    s[i][j] = (i < b && j < b) ? A[(size_t)(k0 + i) * lda + k0 + j] : (i == j ? T(1) : T(0));
   }
   __syncthreads();
   for (int j = 0; j < b; ++j) {
-    if (tid == 0) {
-      T d = s[j][j];
-      if (!(d > T(0))) {
-        if (*info == 0) *info = k0 + j + 1;
-        d = tiny_pivot<T>();
-      }
-      s_d = dev_sqrt(d);
-      s[j][j] = s_d;
+    T d = s[j][j];
+    if (!(d > T(0))) {
+      if (lane == 0 && *info == 0) *info = k0 + j + 1;
+      d = tiny_pivot<T>();
     }
+    d = dev_sqrt(d);
     __syncthreads();
-    const T d = s_d;
-    for (int i = j + 1 + tid; i < b; i += 256) s[i][j] /= d;
+    if (lane == j) s[j][j] = d;
+    if (lane > j && lane < b) s[lane][j] /= d;
     __syncthreads();
-    // trailing update of the block: s[i][c] -= s[i][j] s[c][j], j < c <= i
-    const int t = b - j - 1;
-    for (int e = tid; e < t * t; e += 256) {
-      const int i = j + 1 + e / t, c = j + 1 + e % t;
-      if (c <= i) s[i][c] -= s[i][j] * s[c][j];
+    if (lane > j && lane < b) {
+      const T lij = s[lane][j];
+      for (int c = j + 1; c <= lane; ++c) s[lane][c] -= lij * s[c][j];
     }
     __syncthreads();
   }
-  for (int e = tid; e < b * b; e += 256) {
+  // inverse of the lower factor, one column per lane kept in registers
+  // (forward substitution with the factor's rows read from LDS)
+  T xc[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    T v = (i == lane) ? T(1) : T(0);
+#pragma unroll
+    for (int t = 0; t < i; ++t) v -= s[i][t] * xc[t];
+    xc[i] = (i >= lane && i < b && lane < b) ? v / s[i][i] : T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) Dinv[i * NB + lane] = xc[i];
+  for (int e = lane; e < b * b; e += 64) {
     const int i = e / b, j = e % b;
     A[(size_t)(k0 + i) * lda + k0 + j] = (j <= i) ? s[i][j] : T(0);
   }
-}
-
-// rows r in [k0 + b, n): x L11^T = A[r, k0 .. k0+b) solved in place
-template <typename T>
-__global__ __launch_bounds__(256) void trsm_panel_kernel(T* __restrict__ A, int lda, int n, int k0, int b) {
-  __shared__ T L[NB][NB + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < b * b; e += 256) {
-    const int i = e / b, j = e % b;
-    L[i][j] = A[(size_t)(k0 + i) * lda + k0 + j];
-  }
-  __syncthreads();
-  const int r = k0 + b + blockIdx.x * 256 + tid;
-  if (r >= n) return;
-  T* row = A + (size_t)r * lda + k0;
-  for (int c = 0; c < b; ++c) {
-    T v = row[c];
-    for (int t = 0; t < c; ++t) v -= row[t] * L[c][t];
-    row[c] = v / L[c][c];
-  }
-}
-
-// y[r] -= sum_c L[r][c] x[c] for r in [r0, r0 + rows), c in [c0, c0 + cols)
-// (trans = false), or y[c] -= sum_r L[r][c] x[r] over those ranges (trans):
-// one wavefront per output element group
-template <typename T>
-__global__ __launch_bounds__(256) void trsv_update_kernel(const T* __restrict__ L, int lda, int r0, int rows,
-                                                          int c0, int cols, const T* __restrict__ x,
-                                                          T* __restrict__ y, int trans) {
-  const int lane = threadIdx.x & 63;
-  const int out = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int nout = trans ? cols : rows;
-  if (out >= nout) return;
-  T acc = T(0);
-  if (!trans) {
-    const T* Lr = L + (size_t)(r0 + out) * lda + c0;
-    for (int c = lane; c < cols; c += 64) acc += Lr[c] * x[c0 + c];
-  } else {
-    for (int r = lane; r < rows; r += 64) acc += L[(size_t)(r0 + r) * lda + c0 + out] * x[r0 + r];
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if (lane == 0) {
-    if (!trans)
-      y[r0 + out] -= acc;
-    else
-      y[c0 + out] -= acc;
-  }
-}
-
-// solve the diagonal block [k0, k0 + b) in place on y: L_kk z = y (lower)
-// or L_kk^T z = y (upper); one wavefront
-template <typename T>
-__global__ __launch_bounds__(64) void trsv_diag_kernel(const T* __restrict__ L, int lda, int k0, int b,
-                                                       T* __restrict__ y, int trans) {
-  const int lane = threadIdx.x;
-  T v = lane < b ? y[k0 + lane] : T(0);
-  if (!trans) {
-    for (int i = 0; i < b; ++i) {
-      T zi = __shfl(v, i);
-      zi /= L[(size_t)(k0 + i) * lda + k0 + i];
-      if (lane == i) v = zi;
-      if (lane > i && lane < b) v -= L[(size_t)(k0 + lane) * lda + k0 + i] * zi;
-    }
-  } else {
-    for (int i = b - 1; i >= 0; --i) {
-      T zi = __shfl(v, i);
-      zi /= L[(size_t)(k0 + i) * lda + k0 + i];
-      if (lane == i) v = zi;
-      if (lane < i) v -= L[(size_t)(k0 + i) * lda + k0 + lane] * zi;
-    }
-  }
-  if (lane < b) y[k0 + lane] = v;
 }
 
 template <typename T>
@@ -161,52 +97,82 @@ hipError_t gemm_t<float>(bool ta, bool tb, int M, int N, int K, float alpha, con
 }
 
 template <typename T>
-hipError_t potrf(T* A, int n, int lda, int* info, hipStream_t st) {
+__global__ void copy_panel_kernel(const T* __restrict__ P, int rows, int b, T* __restrict__ A, int lda) {
+  const size_t total = (size_t)rows * b;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x)
+    A[(e / b) * lda + e % b] = P[e];
+}
+
+template <typename T>
+hipError_t potrf(T* A, int n, int lda, T* Dinv, T* work, int* info, hipStream_t st) {
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int b = min(NB, n - k0);
-    hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(1), dim3(256), 0, st, A, lda, k0, b, info);
+    T* Dk = Dinv + (size_t)(k0 / NB) * NB * NB;
+    hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(1), dim3(64), 0, st, A, lda, k0, b, Dk, info);
     const int rest = n - k0 - b;
     if (rest > 0) {
-      hipLaunchKernelGGL(trsm_panel_kernel<T>, dim3((rest + 255) / 256), dim3(256), 0, st, A, lda, n, k0, b);
-      T* L21 = A + (size_t)(k0 + b) * lda + k0;
-      T* A22 = A + (size_t)(k0 + b) * lda + k0 + b;
-      hipError_t e = gemm_t<T>(false, true, rest, rest, b, T(-1), L21, lda, L21, lda, T(1), A22, lda, st);
+      // panel: L21 = A21 L11^{-T} = A21 Dk^T into `work` (rest x b), then
+      // the trailing update A22 -= L21 L21^T, then L21 back into A
+      T* A21 = A + (size_t)(k0 + b) * lda + k0;
+      hipError_t e = gemm_t<T>(false, true, rest, b, b, T(1), A21, lda, Dk, NB, T(0), work, b, st);
       if (e != hipSuccess) return e;
+      T* A22 = A + (size_t)(k0 + b) * lda + k0 + b;
+      e = gemm_t<T>(false, true, rest, rest, b, T(-1), work, b, work, b, T(1), A22, lda, st);
+      if (e != hipSuccess) return e;
+      const size_t tot = (size_t)rest * b;
+      hipLaunchKernelGGL(copy_panel_kernel<T>, dim3((unsigned)std::min<size_t>((tot + 255) / 256, 4096)), dim3(256),
+                         0, st, work, rest, b, A21, lda);
     }
   }
   return hipGetLastError();
 }
 
-// y <- (L L^T)^{-1} y
+// X = L^{-1} (lower, zeros above the diagonal) from the factor and the
+// inverses of its diagonal blocks: block row i is X_ii = Dinv_i and
+// X[i, 0:i] = -Dinv_i (L[i, 0:i] X[0:i, 0:i]), two MFMA GEMMs per block row.
 template <typename T>
-hipError_t potrs(const T* L, int n, int lda, T* y, hipStream_t st) {
-  for (int k0 = 0; k0 < n; k0 += NB) {  // forward: L z = y
-    const int b = min(NB, n - k0);
-    if (k0 > 0)
-      hipLaunchKernelGGL(trsv_update_kernel<T>, dim3((b + 3) / 4), dim3(256), 0, st, L, lda, k0, b, 0, k0, y, y, 0);
-    hipLaunchKernelGGL(trsv_diag_kernel<T>, dim3(1), dim3(64), 0, st, L, lda, k0, b, y, 0);
+__global__ void place_diag_inverse_kernel(const T* __restrict__ Dinv, int n, T* __restrict__ X, int ldx) {
+  const int kb = blockIdx.x, k0 = kb * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    if (k0 + i < n && k0 + j < n) X[(size_t)(k0 + i) * ldx + k0 + j] = Dinv[(size_t)kb * NB * NB + e];
   }
-  const int last = ((n - 1) / NB) * NB;
-  for (int k0 = last; k0 >= 0; k0 -= NB) {  // backward: L^T x = z
-    const int b = min(NB, n - k0);
-    const int below = n - (k0 + b);
-    if (below > 0)
-      hipLaunchKernelGGL(trsv_update_kernel<T>, dim3((b + 3) / 4), dim3(256), 0, st, L, lda, k0 + b, below, k0, b, y,
-                         y, 1);
-    hipLaunchKernelGGL(trsv_diag_kernel<T>, dim3(1), dim3(64), 0, st, L, lda, k0, b, y, 1);
+}
+
+template <typename T>
+hipError_t trtri(const T* L, int n, int lda, const T* Dinv, T* X, int ldx, T* work, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(X, 0, sizeof(T) * (size_t)n * ldx, st);
+  if (e != hipSuccess) return e;
+  const int nb = (n + NB - 1) / NB;
+  hipLaunchKernelGGL(place_diag_inverse_kernel<T>, dim3(nb), dim3(256), 0, st, Dinv, n, X, ldx);
+  for (int kb = 1; kb < nb; ++kb) {
+    const int k0 = kb * NB, b = min(NB, n - k0);
+    // work (b x k0) = L[k0.., 0:k0] X[0:k0, 0:k0]
+    e = gemm_t<T>(false, false, b, k0, k0, T(1), L + (size_t)k0 * lda, lda, X, ldx, T(0), work, k0, st);
+    if (e != hipSuccess) return e;
+    // X[k0.., 0:k0] = -Dinv_k work
+    e = gemm_t<T>(false, false, b, k0, b, T(-1), Dinv + (size_t)kb * NB * NB, NB, work, k0, T(0),
+                  X + (size_t)k0 * ldx, ldx, st);
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t cholesky_f64(double* A, int n, int lda, int* info, hipStream_t st) { return potrf<double>(A, n, lda, info, st); }
-hipError_t cholesky_f32(float* A, int n, int lda, int* info, hipStream_t st) { return potrf<float>(A, n, lda, info, st); }
-hipError_t cholesky_solve_f64(const double* L, int n, int lda, double* y, hipStream_t st) {
-  return potrs<double>(L, n, lda, y, st);
+hipError_t cholesky_f64(double* A, int n, int lda, double* Dinv, double* work, int* info, hipStream_t st) {
+  return potrf<double>(A, n, lda, Dinv, work, info, st);
 }
-hipError_t cholesky_solve_f32(const float* L, int n, int lda, float* y, hipStream_t st) {
-  return potrs<float>(L, n, lda, y, st);
+hipError_t cholesky_f32(float* A, int n, int lda, float* Dinv, float* work, int* info, hipStream_t st) {
+  return potrf<float>(A, n, lda, Dinv, work, info, st);
+}
+hipError_t tri_inverse_f64(const double* L, int n, int lda, const double* Dinv, double* X, double* work,
+                           hipStream_t st) {
+  return trtri<double>(L, n, lda, Dinv, X, n, work, st);
+}
+hipError_t tri_inverse_f32(const float* L, int n, int lda, const float* Dinv, float* X, float* work,
+                           hipStream_t st) {
+  return trtri<float>(L, n, lda, Dinv, X, n, work, st);
 }
 
 }  // namespace wos

@@ -57,33 +57,50 @@ GridHost build_grid(const double* pts, int npts, int dim, const double* lo, cons
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
   const long long ncell = (long long)n0 * n1 * n2;
 
-  auto cell_of = [&](const double* q, int* c) {
+  // Centres are bucketed on a coarser grid (side about the mean spacing of
+  // the centres, never finer than a cell), so that searches from cells far
+  // from every centre visit few buckets.
+  double vol = 1.0;
+  for (int a = 0; a < dim; ++a) vol *= std::max(hi[a] - lo[a], 1e-300);
+  const double spacing = std::pow(vol / std::max(npts, 1), 1.0 / dim);
+  int bn[3] = {1, 1, 1};
+  double bh[3] = {1, 1, 1};
+  for (int a = 0; a < dim; ++a) {
+    const double ext = hi[a] - lo[a];
+    bn[a] = std::max(1, std::min(g.n[a], (int)std::ceil(ext / std::max(spacing, g.h[a]))));
+    bh[a] = ext / bn[a];
+  }
+  const int b0 = bn[0], b1 = bn[1], b2 = bn[2];
+  auto blin = [&](int c0, int c1, int c2) -> long long { return ((long long)c0 * b1 + c1) * b2 + c2; };
+  auto bucket_of = [&](const double* q, int* c) {
     for (int a = 0; a < 3; ++a) {
       if (a < dim) {
-        int v = (int)std::floor((q[a] - g.lo[a]) / g.h[a]);
-        c[a] = std::min(std::max(v, 0), g.n[a] - 1);
+        int v = (int)std::floor((q[a] - g.lo[a]) / bh[a]);
+        c[a] = std::min(std::max(v, 0), bn[a] - 1);
       } else {
         c[a] = 0;
       }
     }
   };
-  auto lin = [&](int c0, int c1, int c2) -> long long { return ((long long)c0 * n1 + c1) * n2 + c2; };
-
+  const long long nbucket = (long long)b0 * b1 * b2;
   Buckets bk;
-  bk.start.assign(ncell + 1, 0);
+  bk.start.assign(nbucket + 1, 0);
   std::vector<long long> where(npts);
   for (int j = 0; j < npts; ++j) {
     int c[3];
-    cell_of(pts + (size_t)j * dim, c);
-    where[j] = lin(c[0], c[1], c[2]);
+    bucket_of(pts + (size_t)j * dim, c);
+    where[j] = blin(c[0], c[1], c[2]);
     bk.start[where[j] + 1]++;
   }
-  for (long long i = 0; i < ncell; ++i) bk.start[i + 1] += bk.start[i];
+  for (long long i = 0; i < nbucket; ++i) bk.start[i + 1] += bk.start[i];
   bk.items.resize(npts);
   {
     std::vector<int> fill(bk.start.begin(), bk.start.end() - 1);
     for (int j = 0; j < npts; ++j) bk.items[fill[where[j]]++] = j;  // ascending j per bucket
   }
+  double bhmin = 1e300;
+  for (int a = 0; a < dim; ++a) bhmin = std::min(bhmin, bh[a]);
+  const int maxb = std::max(b0, std::max(b1, b2));
 
   double hd2 = 0.0, hmin = 1e300, extent = 0.0;
   for (int a = 0; a < dim; ++a) {
@@ -93,7 +110,6 @@ GridHost build_grid(const double* pts, int npts, int dim, const double* lo, cons
   }
   const double hd = std::sqrt(hd2);
   const double margin = 1e-2 * hd + 1e-9 * extent;
-  const int maxn = std::max(n0, std::max(n1, n2));
 
   g.rec.assign(4 * ncell, -1);
   const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -111,17 +127,19 @@ GridHost build_grid(const double* pts, int npts, int dim, const double* lo, cons
       double ctr[3] = {0, 0, 0};
       for (int a = 0; a < dim; ++a) ctr[a] = g.lo[a] + (cc[a] + 0.5) * g.h[a];
       // nearest distance by rings of buckets (Chebyshev radius s)
+      int bc[3];
+      bucket_of(ctr, bc);
       double best2 = 1e300;
-      for (int s = 0; s <= maxn; ++s) {
-        const int lo0 = c0 - s, hi0 = c0 + s;
-        const int lo1 = (dim > 1) ? c1 - s : 0, hi1 = (dim > 1) ? c1 + s : 0;
-        const int lo2 = (dim > 2) ? c2 - s : 0, hi2 = (dim > 2) ? c2 + s : 0;
-        for (int i0 = std::max(lo0, 0); i0 <= std::min(hi0, n0 - 1); ++i0)
-          for (int i1 = std::max(lo1, 0); i1 <= std::min(hi1, n1 - 1); ++i1)
-            for (int i2 = std::max(lo2, 0); i2 <= std::min(hi2, n2 - 1); ++i2) {
-              const int cheb = std::max(std::abs(i0 - c0), std::max(std::abs(i1 - c1), std::abs(i2 - c2)));
+      for (int s = 0; s <= maxb; ++s) {
+        const int lo0 = bc[0] - s, hi0 = bc[0] + s;
+        const int lo1 = (dim > 1) ? bc[1] - s : 0, hi1 = (dim > 1) ? bc[1] + s : 0;
+        const int lo2 = (dim > 2) ? bc[2] - s : 0, hi2 = (dim > 2) ? bc[2] + s : 0;
+        for (int i0 = std::max(lo0, 0); i0 <= std::min(hi0, b0 - 1); ++i0)
+          for (int i1 = std::max(lo1, 0); i1 <= std::min(hi1, b1 - 1); ++i1)
+            for (int i2 = std::max(lo2, 0); i2 <= std::min(hi2, b2 - 1); ++i2) {
+              const int cheb = std::max(std::abs(i0 - bc[0]), std::max(std::abs(i1 - bc[1]), std::abs(i2 - bc[2])));
               if (cheb != s) continue;
-              const long long b = lin(i0, i1, i2);
+              const long long b = blin(i0, i1, i2);
               for (int it = bk.start[b]; it < bk.start[b + 1]; ++it) {
                 const double* y = pts + (size_t)bk.items[it] * dim;
                 double d2 = 0.0;
@@ -129,20 +147,22 @@ GridHost build_grid(const double* pts, int npts, int dim, const double* lo, cons
                 best2 = std::min(best2, d2);
               }
             }
-        if (best2 < 1e300 && std::sqrt(best2) <= (s + 0.5) * hmin) break;
+        // every centre not yet seen is at least s bucket sides (less the
+        // offset of the cell centre inside its bucket) away
+        if (best2 < 1e300 && std::sqrt(best2) <= s * bhmin) break;
       }
       const double R = std::sqrt(best2) + 2.0 * hd + margin;
       const double R2 = R * R;
       int r0[3] = {0, 0, 0}, r1[3] = {0, 0, 0};
       for (int a = 0; a < dim; ++a) {
-        r0[a] = std::max(0, (int)std::floor((ctr[a] - R - g.lo[a]) / g.h[a]));
-        r1[a] = std::min(g.n[a] - 1, (int)std::floor((ctr[a] + R - g.lo[a]) / g.h[a]));
+        r0[a] = std::max(0, (int)std::floor((ctr[a] - R - g.lo[a]) / bh[a]));
+        r1[a] = std::min(bn[a] - 1, (int)std::floor((ctr[a] + R - g.lo[a]) / bh[a]));
       }
       cand.clear();
       for (int i0 = r0[0]; i0 <= r1[0]; ++i0)
         for (int i1 = r0[1]; i1 <= r1[1]; ++i1)
           for (int i2 = r0[2]; i2 <= r1[2]; ++i2) {
-            const long long b = lin(i0, i1, i2);
+            const long long b = blin(i0, i1, i2);
             for (int it = bk.start[b]; it < bk.start[b + 1]; ++it) {
               const int j = bk.items[it];
               const double* y = pts + (size_t)j * dim;
@@ -172,16 +192,27 @@ GridHost build_grid(const double* pts, int npts, int dim, const double* lo, cons
             aa[i] += av[3 * i + a] * av[3 * i + a];
           }
         }
+        auto dominated_by = [&](size_t i, size_t k) {
+          double minf = aa[i] - aa[k];
+          for (int a = 0; a < dim; ++a) minf -= 2.0 * std::fabs(av[3 * k + a] - av[3 * i + a]) * hb[a];
+          return minf > 1e-5 * (aa[i] + hb2);
+        };
+        // first against the centre nearest to the cell's centre (removes
+        // almost all of a long list at once), then pairwise among the rest
+        size_t kn = 0;
+        for (size_t i = 1; i < nc; ++i)
+          if (aa[i] < aa[kn]) kn = i;
+        std::vector<size_t> alive;
+        for (size_t i = 0; i < nc; ++i)
+          if (i == kn || !dominated_by(i, kn)) alive.push_back(i);
         std::vector<int> kept;
-        for (size_t i = 0; i < nc; ++i) {
-          const double tol = 1e-5 * (aa[i] + hb2);
+        for (size_t i : alive) {
           bool dominated = false;
-          for (size_t k = 0; k < nc && !dominated; ++k) {
-            if (k == i) continue;
-            double minf = aa[i] - aa[k];
-            for (int a = 0; a < dim; ++a) minf -= 2.0 * std::fabs(av[3 * k + a] - av[3 * i + a]) * hb[a];
-            dominated = minf > tol;
-          }
+          for (size_t k : alive)
+            if (k != i && dominated_by(i, k)) {
+              dominated = true;
+              break;
+            }
           if (!dominated) kept.push_back(cand[i]);
         }
         cand.swap(kept);

@@ -213,7 +213,10 @@ wos_status dev_dot(SolveWork& w, const double* dx, const double* dy, const doubl
 wos_status ensure_tik(wos_toolbox* tb, SolveWork& w, bool mixed) {
   const size_t n = tb->n, m = tb->m, d = tb->dim;
   wos_status s;
+  const size_t dblocks = ((m + 63) / 64) * 64 * 64;
   if (!w.blk) {
+    if ((s = walloc(w, &w.D64, dblocks)) != WOS_OK) return s;
+    if ((s = walloc(w, &w.P64, m * 64)) != WOS_OK) return s;
     if ((s = walloc(w, &w.blk, 2 * (d + 1) * std::max<size_t>(n, 1))) != WOS_OK) return s;
     if ((s = walloc(w, &w.regv, 2)) != WOS_OK) return s;
     if ((s = walloc(w, &w.info, 2)) != WOS_OK) return s;
@@ -223,6 +226,8 @@ wos_status ensure_tik(wos_toolbox* tb, SolveWork& w, bool mixed) {
     if ((s = walloc(w, &w.Lam32, m * m)) != WOS_OK) return s;
     if ((s = walloc(w, &w.N32, m * m)) != WOS_OK) return s;
     if ((s = walloc(w, &w.v32, m)) != WOS_OK) return s;
+    if ((s = walloc(w, &w.D32, dblocks)) != WOS_OK) return s;
+    if ((s = walloc(w, &w.P32, m * 64)) != WOS_OK) return s;
   }
   return WOS_OK;
 }
@@ -285,7 +290,8 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     SHIP(mfma_gemm_f32(true, false, m, m, m, 1.0f, w.Lam32, m, w.Lam32, m, 0.0f, w.N32, m, st));
     SHIP(launch_reg_from_diag(false, w.N32, m, m, rcond, w.regv, st));
     SHIP(launch_add_diag(false, w.N32, m, m, w.regv, st));
-    SHIP(cholesky_f32(w.N32, m, m, w.info, st));
+    SHIP(cholesky_f32(w.N32, m, m, w.D32, w.P32, w.info, st));
+    SHIP(tri_inverse_f32(w.N32, m, m, w.D32, w.Lam32, w.P32, st));  // X = L^{-1} over Lambda's storage
     int hinfo = 0;
     SHIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
     SHIP(hipStreamSynchronize(st));
@@ -305,9 +311,9 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     SHIP(hipMemcpyAsync(r, c, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
     int it = 0;
     for (it = 1; it <= maxit; ++it) {
-      SHIP(launch_to_f32(m, r, w.v32, st));
-      SHIP(cholesky_solve_f32(w.N32, m, m, w.v32, st));
-      SHIP(launch_add_f32(m, w.v32, q, st));
+      // q += X^T (X r): the FP32 factor's inverse applied with FP64 accumulation
+      SHIP(launch_gemv_n_ld(false, w.Lam32, m, m, m, r, 1.0, 0.0, t, st));
+      SHIP(launch_gemv_t_ld(false, w.Lam32, m, m, m, t, 1.0, 1.0, q, st));
       // r = c - Lambda^T Lambda q - reg q   (FP64)
       if ((s = apply_Lambda(tb, w, co, q, false, t, st)) != WOS_OK) return s;
       if ((s = apply_Lambda(tb, w, co, t, true, r, st)) != WOS_OK) return s;
@@ -335,9 +341,10 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     SHIP(mfma_gemm_f64(true, false, m, m, m, 1.0, w.Lam, m, w.Lam, m, 0.0, w.Hess, m, st));
     SHIP(launch_reg_from_diag(true, w.Hess, m, m, rcond, w.regv, st));
     SHIP(launch_add_diag(true, w.Hess, m, m, w.regv, st));
-    SHIP(cholesky_f64(w.Hess, m, m, w.info, st));
-    SHIP(hipMemcpyAsync(q, c, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
-    SHIP(cholesky_solve_f64(w.Hess, m, m, q, st));
+    SHIP(cholesky_f64(w.Hess, m, m, w.D64, w.P64, w.info, st));
+    SHIP(tri_inverse_f64(w.Hess, m, m, w.D64, w.Lam, w.P64, st));  // X = L^{-1} over Lambda's storage
+    SHIP(launch_gemv_n_ld(true, w.Lam, m, m, m, c, 1.0, 0.0, t, st));
+    SHIP(launch_gemv_t_ld(true, w.Lam, m, m, m, t, 1.0, 0.0, q, st));
     int hinfo = 0;
     SHIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
     SHIP(hipStreamSynchronize(st));
@@ -352,7 +359,7 @@ namespace wos {
 
 void free_work(SolveWork& w) {
   void* ptrs[] = {w.R, w.Lam, w.Sig, w.Lam0, w.Sig0, w.Hess, w.G, w.V, w.E, w.rot, w.pq, w.vec, w.Ac, w.red,
-                  w.blk, w.regv, w.info, w.R32, w.Lam32, w.N32, w.v32};
+                  w.blk, w.regv, w.info, w.R32, w.Lam32, w.N32, w.v32, w.D64, w.D32, w.P64, w.P32};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   w = SolveWork();

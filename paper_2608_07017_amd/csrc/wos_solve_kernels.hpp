@@ -46,11 +46,16 @@ hipError_t mfma_gemm_f32(bool ta, bool tb, int M, int N, int K, float alpha, con
 hipError_t mfma_gemm_f64_a32(bool ta, bool tb, int M, int N, int K, double alpha, const float* A, int lda,
                              const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st);
 
-// ---- Cholesky (chol.hip): in place, lower, row-major; info = first bad pivot + 1
-hipError_t cholesky_f64(double* A, int n, int lda, int* info, hipStream_t st);
-hipError_t cholesky_f32(float* A, int n, int lda, int* info, hipStream_t st);
-hipError_t cholesky_solve_f64(const double* L, int n, int lda, double* y, hipStream_t st);
-hipError_t cholesky_solve_f32(const float* L, int n, int lda, float* y, hipStream_t st);
+// ---- Cholesky (chol.hip): in place, lower, row-major; info = first bad pivot + 1;
+// Dinv receives the inverses of the 64 x 64 diagonal factors (ceil(n/64) * 64 * 64);
+// work holds one panel (n x 64)
+hipError_t cholesky_f64(double* A, int n, int lda, double* Dinv, double* work, int* info, hipStream_t st);
+hipError_t cholesky_f32(float* A, int n, int lda, float* Dinv, float* work, int* info, hipStream_t st);
+// X (n x n, ld n) = L^{-1}, lower with zeros above; work holds 64 x n
+hipError_t tri_inverse_f64(const double* L, int n, int lda, const double* Dinv, double* X, double* work,
+                           hipStream_t st);
+hipError_t tri_inverse_f32(const float* L, int n, int lda, const float* Dinv, float* X, float* work,
+                           hipStream_t st);
 
 // ---- regularised solve and matrix-free operator (tikhonov.hip)
 hipError_t launch_weight_rows_any(bool f64_in, bool f32_out, const void* A, const void* B, const void* H,

@@ -1,0 +1,113 @@
+"""The request server (wos_server_* through the C ABI): every result is the
+same alone and in the mix of concurrent requests, mixed precision reaches
+the FP64 solve's error against the manufactured solution, and admission by
+memory serialises or refuses requests as the budget dictates."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_2608_07017_amd")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def toolboxes():
+    out = []
+    for name, walks in (("lshape256", 2000), ("lshape1024", 1000)):
+        cfg = W.config(name)
+        _say("build", name)
+        tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], walks, cfg["eps"], seed=cfg["seed"],
+                       precision="f32", volume_samples=1 << 20)
+        tb.build()
+        torch.cuda.synchronize()
+        lam = tb.export("lambda").cpu().numpy()
+        probs = [W.anisotropic_problem(100 + k, cfg["sites"], cfg["bnodes"]) for k in range(3)]
+        out.append((tb, lam, probs))
+    return out
+
+
+def _kw(pr, precision):
+    # -div(A grad u) + b . grad u = f  ->  the paper's form with b_p = -b, f_p = -f
+    return dict(f=-pr["f"], g=pr["g"], kind="linear", A=pr["A"], b=-pr["b"], rcond=1e-3, solver="tikhonov",
+                precision=precision, refine_tol=1e-12, max_refine=30)
+
+
+def _lam_err(u, v, lam):
+    return float(np.sqrt(np.sum(lam * (u - v) ** 2)))
+
+
+def test_results_same_alone_and_in_the_mix(toolboxes):
+    alone = {}
+    for ti, (tb, lam, probs) in enumerate(toolboxes):
+        for pi, pr in enumerate(probs):
+            for prec in ("f64", "mixed"):
+                kw = _kw(pr, prec)
+                u, _, _, info = tb.solve(kw.pop("f"), kw.pop("g"), **kw)
+                torch.cuda.synchronize()
+                alone[ti, pi, prec] = u.cpu().numpy()
+                assert info["fallback"] == 0
+    sv = P.Server(slots=4)
+    tickets = []
+    order = [(ti, pi, prec) for _ in range(2) for ti in range(len(toolboxes)) for pi in range(3)
+             for prec in ("mixed", "f64")]
+    np.random.default_rng(0).shuffle(order)
+    for key in order:
+        ti, pi, prec = key
+        tb, lam, probs = toolboxes[ti]
+        kw = _kw(probs[pi], prec)
+        t, u, _ = sv.submit(tb, kw.pop("f"), kw.pop("g"), **kw)
+        tickets.append((key, t, u))
+    for key, t, u in tickets:
+        info, times = sv.poll(t)
+        assert times[0] <= times[1] <= times[2]
+        ti, pi, prec = key
+        lam = toolboxes[ti][1]
+        ref = alone[key]
+        assert _lam_err(u.cpu().numpy(), ref, lam) <= 1e-9 * np.sqrt(np.sum(lam * ref ** 2)), key
+    assert sv.pending() == (0, 0)
+    sv.close()
+
+
+def test_mixed_reaches_the_fp64_error(toolboxes):
+    for tb, lam, probs in toolboxes:
+        for pr in probs:
+            errs = {}
+            for prec in ("f64", "mixed"):
+                kw = _kw(pr, prec)
+                u, _, _, info = tb.solve(kw.pop("f"), kw.pop("g"), **kw)
+                torch.cuda.synchronize()
+                errs[prec] = _lam_err(u.cpu().numpy(), pr["u"], lam)
+            _say("L2 errors", tb.n, errs)
+            assert errs["mixed"] <= 1.01 * errs["f64"] + 1e-6
+
+
+def test_memory_admission(toolboxes):
+    tb, lam, probs = toolboxes[1]
+    kw = _kw(probs[0], "mixed")
+    f, g = kw.pop("f"), kw.pop("g")
+    # a budget below one workspace: the request is refused, not crashed
+    sv = P.Server(slots=2, mem_budget=1 << 20)
+    t, u, _ = sv.submit(tb, f, g, **kw)
+    with pytest.raises(P.WosError):
+        sv.poll(t)
+    sv.close()
+    # a budget for about one workspace: requests run one after another
+    small, _, sprobs = toolboxes[0]
+    sv = P.Server(slots=3, mem_budget=400 << 20)
+    ts = []
+    for k in range(6):
+        box, pr = (tb, probs[k % 3]) if k % 2 == 0 else (small, sprobs[k % 3])
+        kk = _kw(pr, "mixed")
+        ts.append(sv.submit(box, kk.pop("f"), kk.pop("g"), **kk)[0])
+    for t in ts:
+        sv.poll(t)
+    sv.close()

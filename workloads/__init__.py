@@ -264,3 +264,49 @@ def smooth_field(seed, dim, terms=8, max_freq=3.0, scale=0.5):
         return -np.cos(x @ w.T + ph) @ (a * (w * w).sum(axis=1))
 
     return val, grad, lap
+
+
+# ------------------------------------------------ served request problems
+
+
+def anisotropic_problem(seed, sites, bnodes, h=1e-5):
+    """Data of one served request, -div(A grad u) + b . grad u = f with
+    u = g on the boundary, on a 2-D domain (a manufactured solution):
+    A(x) = R(t(x)) diag(1, k(x)) R(t(x))^T with k = 1 + 99 s(x), s in [0, 1]
+    (anisotropy up to 1:100), b(x) = 0.8 (cos p(x), sin p(x)), and u_ex a
+    seeded sum of cosines; t, s and p are smooth seeded fields.  f is derived
+    from u_ex by central differences of the flux A grad u_ex (step h).
+    Returns dict(A (n,2,2), b (n,2), f (n,), g (p,), u (n,) = u_ex at the
+    sites)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    uex, ugrad, _ = smooth_field(int(rng.integers(1 << 30)), 2, terms=6, max_freq=2.5, scale=0.5)
+    wt, wk, wp = (rng.normal(0.0, 1.5, 2) for _ in range(3))
+    pt, pk, pp = rng.uniform(0, 2 * np.pi, 3)
+
+    def coef(x):
+        x = np.atleast_2d(x)
+        t = np.pi * np.sin(x @ wt + pt)
+        k = 1.0 + 99.0 * (0.5 + 0.5 * np.sin(x @ wk + pk))
+        c, sn = np.cos(t), np.sin(t)
+        R = np.stack([np.stack([c, -sn], -1), np.stack([sn, c], -1)], -2)
+        D = np.zeros(R.shape)
+        D[:, 0, 0] = 1.0
+        D[:, 1, 1] = k
+        A = R @ D @ np.transpose(R, (0, 2, 1))
+        ph = x @ wp + pp
+        b = 0.8 * np.stack([np.cos(ph), np.sin(ph)], 1)
+        return A, b
+
+    def flux(x):
+        A, _ = coef(x)
+        return np.einsum("nab,nb->na", A, ugrad(x))
+
+    x = np.atleast_2d(np.asarray(sites, dtype=np.float64))
+    A, b = coef(x)
+    div = np.zeros(len(x))
+    for a in range(2):
+        e = np.zeros(2)
+        e[a] = h
+        div += (flux(x + e)[:, a] - flux(x - e)[:, a]) / (2.0 * h)
+    f = -div + np.einsum("na,na->n", b, ugrad(x))
+    return dict(A=A, b=b, f=f, g=uex(bnodes), u=uex(x))
