@@ -16,7 +16,7 @@ namespace wos {
 
 namespace {
 
-constexpr int kVolBlock = 256;
+constexpr int kVolBlock = 1024;
 constexpr int kHistLdsMax = 8192;  // sites whose counts are binned in LDS (32 KiB, dynamic)
 
 #pragma clang fp contract(off)
@@ -224,7 +224,8 @@ int grid_for(size_t count, int block) {
 
 hipError_t launch_volume(const VolumeParams& P, hipStream_t stream) {
   if (P.nblocks <= 0) return hipSuccess;
-  // Two workgroups per CU, each thread looping over many points: the per-
+  // Two 1024-thread workgroups per CU (32 wavefronts to hide the latency of
+  // the record loads), each thread looping over many points: the per-
   // workgroup histogram flush (n atomics) is then paid only 512 times.
   int grid = (int)((P.nblocks + kVolBlock * 4 - 1) / (kVolBlock * 4));
   if (grid > 512) grid = 512;
