@@ -102,6 +102,13 @@ def tikhonov_solve(M, r, rcond):
     return np.linalg.solve(N + reg * np.eye(N.shape[0]), M.T @ r), reg
 
 
+def sym_reg_solve(M, r, rcond):
+    """Regularised solve of a symmetric positive semidefinite system:
+    (M + reg I)^{-1} r with reg = rcond max_j M_jj."""
+    reg = rcond * float(np.max(np.diag(M)))
+    return np.linalg.solve(M + reg * np.eye(M.shape[0]), r), reg
+
+
 def reconstruct(tb, q, g):
     """u = A q + H g~ and grad u (d, n)."""
     u = tb["A"] @ q + tb["H"] @ g
@@ -124,7 +131,11 @@ def apply_direct(tb, fbar, g):
     return reconstruct(tb, fbar, g)
 
 
-def newton(tb, lam, g, dFu, d2Fu, rcond=1e-3, tol=1e-8, max_iter=50, h0=None):
+def _sym_step(M, r, rcond, solver):
+    return tsvd_solve(M, r, rcond) if solver == "tsvd" else sym_reg_solve(M, r, rcond)[0]
+
+
+def newton(tb, lam, g, dFu, d2Fu, rcond=1e-3, tol=1e-8, max_iter=50, h0=None, solver="tsvd"):
     """Newton on grad J = 0 for F(x, u, p) = |p|^2/2 + G(x, u), with
     dFu(u) = dG/du and d2Fu(u) = d^2G/du^2 at the sites."""
     A, H = tb["A"], tb["H"]
@@ -141,22 +152,22 @@ def newton(tb, lam, g, dFu, d2Fu, rcond=1e-3, tol=1e-8, max_iter=50, h0=None):
         if gn <= tol * gnorm0 or it == max_iter:
             break
         hess = L0 + A.T @ ((lam * d2Fu(u))[:, None] * A)
-        h = h - tsvd_solve(hess, grad, rcond)
+        h = h - _sym_step(hess, grad, rcond, solver)
     u, gu = reconstruct(tb, h, g)
     return {"h": h, "u": u, "grad_u": gu, "iters": it, "grad_norm": gn, "grad_norm0": gnorm0}
 
 
-def newton_cubic(tb, lam, f, g, kappa=1.0, rcond=1e-3, tol=1e-8, max_iter=50):
+def newton_cubic(tb, lam, f, g, kappa=1.0, rcond=1e-3, tol=1e-8, max_iter=50, solver="tsvd"):
     """Newton for -Lap u + kappa u^3 = f (F = |p|^2/2 + kappa u^4/4 - f u),
     started at the solution of the problem without the cubic term."""
     A = tb["A"]
     L0, S0 = _grad_pairs(tb["B"], tb["K"], lam, None)
-    h0 = tsvd_solve(L0, A.T @ (lam * f) - S0 @ g, rcond)
+    h0 = _sym_step(L0, A.T @ (lam * f) - S0 @ g, rcond, solver)
     return newton(tb, lam, g, dFu=lambda u: kappa * u ** 3 - f, d2Fu=lambda u: 3.0 * kappa * u * u,
-                  rcond=rcond, tol=tol, max_iter=max_iter, h0=h0)
+                  rcond=rcond, tol=tol, max_iter=max_iter, h0=h0, solver=solver)
 
 
-def picard_quasilinear(tb, lam, f, g, rcond=1e-3, tol=1e-10, max_iter=100):
+def picard_quasilinear(tb, lam, f, g, rcond=1e-3, tol=1e-10, max_iter=100, solver="tsvd"):
     """Picard for -div((1+u^2) grad u) = f: A(x_i) = (1 + u_i^2) I, paper f = -f."""
     d, n, _ = tb["B"].shape
     u = np.zeros(n)
@@ -164,7 +175,7 @@ def picard_quasilinear(tb, lam, f, g, rcond=1e-3, tol=1e-10, max_iter=100):
     for it in range(1, max_iter + 1):
         a = 1.0 + u * u
         Acoef = a[:, None, None] * np.eye(d)[None]
-        res = solve_linear(tb, lam, -f, g, Acoef=Acoef, rcond=rcond)
+        res = solve_linear(tb, lam, -f, g, Acoef=Acoef, rcond=rcond, solver=solver)
         un = res["u"]
         du = np.sqrt(np.sum(lam * (un - u) ** 2))
         nu = np.sqrt(np.sum(lam * un ** 2))

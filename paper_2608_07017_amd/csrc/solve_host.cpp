@@ -227,6 +227,7 @@ wos_status ensure_tik(wos_toolbox* tb, SolveWork& w, bool mixed) {
     if ((s = walloc(w, &w.N32, m * m)) != WOS_OK) return s;
     if ((s = walloc(w, &w.v32, m)) != WOS_OK) return s;
     if ((s = walloc(w, &w.D32, dblocks)) != WOS_OK) return s;
+    if ((s = walloc(w, &w.L0_32, m * m)) != WOS_OK) return s;
     if ((s = walloc(w, &w.P32, m * 64)) != WOS_OK) return s;
   }
   return WOS_OK;
@@ -288,7 +289,7 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     SHIP(mfma_gemm_f32(true, false, m, m, n, 1.0f, (const float*)tb->d_A, m, w.R32 + (size_t)K * m, m, 1.0f,
                        w.Lam32, m, st));
     SHIP(mfma_gemm_f32(true, false, m, m, m, 1.0f, w.Lam32, m, w.Lam32, m, 0.0f, w.N32, m, st));
-    SHIP(launch_reg_from_diag(false, w.N32, m, m, rcond, w.regv, st));
+    SHIP(launch_reg_from_diag(false, w.N32, m, m, rcond * rcond, w.regv, st));
     SHIP(launch_add_diag(false, w.N32, m, m, w.regv, st));
     SHIP(cholesky_f32(w.N32, m, m, w.D32, w.P32, w.info, st));
     SHIP(tri_inverse_f32(w.N32, m, m, w.D32, w.Lam32, w.P32, st));  // X = L^{-1} over Lambda's storage
@@ -339,7 +340,7 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
                              w.Lam, m, st));
     }
     SHIP(mfma_gemm_f64(true, false, m, m, m, 1.0, w.Lam, m, w.Lam, m, 0.0, w.Hess, m, st));
-    SHIP(launch_reg_from_diag(true, w.Hess, m, m, rcond, w.regv, st));
+    SHIP(launch_reg_from_diag(true, w.Hess, m, m, rcond * rcond, w.regv, st));
     SHIP(launch_add_diag(true, w.Hess, m, m, w.regv, st));
     SHIP(cholesky_f64(w.Hess, m, m, w.D64, w.P64, w.info, st));
     SHIP(tri_inverse_f64(w.Hess, m, m, w.D64, w.Lam, w.P64, st));  // X = L^{-1} over Lambda's storage
@@ -353,13 +354,164 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
   SHIP(hipMemcpyAsync(&inf->reg, w.regv, sizeof(double), hipMemcpyDeviceToHost, st));
   return WOS_OK;
 }
+
+// Regularised solve of a symmetric positive semidefinite system H x = rhs:
+// x = (H + reg I)^{-1} rhs with reg = rcond max_j H_jj (the analogue, for a
+// symmetric matrix, of dropping the eigenvalues below rcond times the
+// largest).  H is formed by the caller in FP64 (w.Hess) or, mixed, in FP32
+// (w.N32); `applyH(x, out)` applies the exact H in FP64 (matrix-free) for
+// the refinement of the mixed route.
+template <typename F>
+wos_status sym_reg_solve(wos_toolbox* tb, SolveWork& w, bool mixed, double rcond, double tol, int maxit,
+                         const double* rhs, double* x, F applyH, wos_solve_info* inf, hipStream_t st) {
+  const int m = tb->m;
+  double* r = w.vec + 6 * w.vlen;
+  double* t = w.vec + 7 * w.vlen;
+  SHIP(hipMemsetAsync(w.info, 0, 2 * sizeof(int), st));
+  int hinfo = 0;
+  if (mixed) {
+    SHIP(launch_reg_from_diag(false, w.N32, m, m, rcond, w.regv, st));
+    SHIP(launch_add_diag(false, w.N32, m, m, w.regv, st));
+    SHIP(cholesky_f32(w.N32, m, m, w.D32, w.P32, w.info, st));
+    SHIP(tri_inverse_f32(w.N32, m, m, w.D32, w.Lam32, w.P32, st));
+    SHIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
+    SHIP(hipStreamSynchronize(st));
+    if (hinfo != 0) return sfail(WOS_ENOTCONV, "FP32 factorisation failed at column %d", hinfo - 1);
+    double rn0 = 0.0, rn = 0.0;
+    wos_status s;
+    if ((s = dev_dot(w, rhs, rhs, nullptr, m, &rn0, st)) != WOS_OK) return s;
+    rn0 = std::sqrt(rn0);
+    SHIP(hipMemsetAsync(x, 0, sizeof(double) * m, st));
+    SHIP(hipMemcpyAsync(r, rhs, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    int it = 0;
+    for (it = 1; it <= maxit; ++it) {
+      SHIP(launch_gemv_n_ld(false, w.Lam32, m, m, m, r, 1.0, 0.0, t, st));
+      SHIP(launch_gemv_t_ld(false, w.Lam32, m, m, m, t, 1.0, 1.0, x, st));
+      if ((s = applyH(x, t)) != WOS_OK) return s;
+      SHIP(launch_axpy_reg(m, rhs, nullptr, -1.0, t, r, st));
+      SHIP(launch_axpy_reg(m, r, w.regv, -1.0, x, r, st));
+      if ((s = dev_dot(w, r, r, nullptr, m, &rn, st)) != WOS_OK) return s;
+      rn = std::sqrt(rn);
+      if (rn <= tol * rn0) break;
+    }
+    inf->refine_iters = std::min(it, maxit);
+    inf->refine_residual = rn0 > 0 ? rn / rn0 : 0.0;
+  } else {
+    SHIP(launch_reg_from_diag(true, w.Hess, m, m, rcond, w.regv, st));
+    SHIP(launch_add_diag(true, w.Hess, m, m, w.regv, st));
+    SHIP(cholesky_f64(w.Hess, m, m, w.D64, w.P64, w.info, st));
+    SHIP(tri_inverse_f64(w.Hess, m, m, w.D64, w.Lam, w.P64, st));
+    SHIP(launch_gemv_n_ld(true, w.Lam, m, m, m, rhs, 1.0, 0.0, t, st));
+    SHIP(launch_gemv_t_ld(true, w.Lam, m, m, m, t, 1.0, 0.0, x, st));
+    SHIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
+    SHIP(hipStreamSynchronize(st));
+    if (hinfo != 0) return sfail(WOS_ENOTCONV, "matrix not positive definite at column %d", hinfo - 1);
+  }
+  SHIP(hipMemcpyAsync(&inf->reg, w.regv, sizeof(double), hipMemcpyDeviceToHost, st));
+  return WOS_OK;
+}
+
+// Newton for -Lap u + kappa u^3 = f with regularised steps (solver
+// TIKHONOV): the Hessian Lambda_0 + A^T diag(3 kappa lambda u^2) A is formed
+// explicitly (FP64, or FP32 in the mixed route) on the matrix cores, the
+// gradient and the refinement residuals are evaluated matrix-free in FP64.
+wos_status newton_tikhonov(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, double rcond, const double* f,
+                           const double* g, double* q, wos_solve_info* inf, hipStream_t st) {
+  const int n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
+  const int K = d * n;
+  const bool mixed = co->precision == WOS_SOLVE_MIXED && !tb->f64;
+  const double kappa = co->kappa;
+  const double tol = co->tol > 0 ? co->tol : 1e-8;
+  const int max_iter = co->max_iter > 0 ? co->max_iter : 50;
+  const double rtol = co->refine_tol > 0 ? co->refine_tol : 1e-10;
+  const int rmax = co->max_refine > 0 ? co->max_refine : 10;
+  wos_status s;
+  if ((s = ensure_tik(tb, w, mixed)) != WOS_OK) return s;
+  double* grad = w.vec + 0 * w.vlen;
+  double* uu = w.vec + 2 * w.vlen;
+  double* t1 = w.vec + 3 * w.vlen;
+  double* wts = w.vec + 4 * w.vlen;
+  double* tmp = w.vec + 5 * w.vlen;
+  double* sig0g = w.vec + 8 * w.vlen;
+  double* dlt = w.vec + 9 * w.vlen;
+  double* y1 = w.blk;
+  double* y2 = w.blk + (size_t)(d + 1) * n;
+  wos_coeffs co0{};  // A = I, b = c = 0: Lambda_0 and Sigma_0
+  // Lambda_0 explicit: L^T W0 L (the A rows carry no weight)
+  SHIP(launch_weight_rows_any(tb->f64, mixed, tb->d_A, tb->d_B, tb->d_H, tb->d_K, tb->d_lambda, nullptr, nullptr,
+                              nullptr, n, m, p, d, m, mixed ? (void*)w.R32 : (void*)w.R, st));
+  if (mixed)
+    SHIP(mfma_gemm_f32(true, false, m, m, K, 1.0f, (const float*)tb->d_B, m, w.R32, m, 0.0f, w.L0_32, m, st));
+  else if (tb->f64)
+    SHIP(mfma_gemm_f64(true, false, m, m, K, 1.0, (const double*)tb->d_B, m, w.R, m, 0.0, w.Lam0, m, st));
+  else
+    SHIP(mfma_gemm_f64_a32(true, false, m, m, K, 1.0, (const float*)tb->d_B, m, w.R, m, 0.0, w.Lam0, m, st));
+  auto apply_lam0 = [&](const double* x, double* out) { return apply_Lambda(tb, w, &co0, x, false, out, st); };
+  // Sigma_0 g = L^T W0 [K; H] g
+  SHIP(launch_gemv_n_ld(tb->f64, tb->d_K, d * n, p, p, g, 1.0, 0.0, y1, st));
+  SHIP(launch_gemv_n_ld(tb->f64, tb->d_H, n, p, p, g, 1.0, 0.0, y1 + (size_t)d * n, st));
+  SHIP(launch_apply_w(n, d, tb->d_lambda, nullptr, nullptr, nullptr, y1, false, nullptr, y2, st));
+  if ((s = apply_Lt(tb, y2, 1.0, 0.0, sig0g, st)) != WOS_OK) return s;
+  auto load_lam0 = [&]() -> wos_status {
+    if (mixed)
+      SHIP(hipMemcpyAsync(w.N32, w.L0_32, sizeof(float) * m * m, hipMemcpyDeviceToDevice, st));
+    else
+      SHIP(hipMemcpyAsync(w.Hess, w.Lam0, sizeof(double) * m * m, hipMemcpyDeviceToDevice, st));
+    return WOS_OK;
+  };
+  // h0: the problem without the cubic term, Lambda_0 h = A^T (lambda f) - Sigma_0 g
+  SHIP(launch_pointwise(n, tb->d_lambda, nullptr, f, 0.0, 0.0, 0.0, 0.0, -1.0, t1, st));
+  SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, t1, 1.0, 0.0, grad, st));
+  SHIP(launch_axpy_reg(m, grad, nullptr, -1.0, sig0g, grad, st));
+  if ((s = load_lam0()) != WOS_OK) return s;
+  if ((s = sym_reg_solve(tb, w, mixed, rcond, rtol, rmax, grad, q, apply_lam0, inf, st)) != WOS_OK) return s;
+  double gn0 = -1.0, gn = 0.0;
+  int it = 0;
+  for (it = 0; it <= max_iter; ++it) {
+    if ((s = reconstruct(tb, q, g, uu, nullptr, st)) != WOS_OK) return s;
+    // grad = A^T (lambda (kappa u^3 - f)) + Lambda_0 h + Sigma_0 g
+    SHIP(launch_pointwise(n, tb->d_lambda, uu, f, 0.0, 0.0, 0.0, kappa, 1.0, t1, st));
+    if ((s = apply_lam0(q, grad)) != WOS_OK) return s;
+    SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, t1, 1.0, 1.0, grad, st));
+    SHIP(launch_axpy_reg(m, grad, nullptr, 1.0, sig0g, grad, st));
+    if ((s = dev_dot(w, grad, grad, nullptr, m, &gn, st)) != WOS_OK) return s;
+    gn = std::sqrt(gn);
+    if (gn0 < 0) gn0 = gn;
+    if (gn <= tol * gn0 || it == max_iter) break;
+    // Hessian = Lambda_0 + A^T diag(wts) A, wts = 3 kappa lambda u^2
+    SHIP(launch_pointwise(n, tb->d_lambda, uu, nullptr, 0.0, 0.0, 3.0 * kappa, 0.0, 0.0, wts, st));
+    if ((s = load_lam0()) != WOS_OK) return s;
+    SHIP(launch_scale_rows(tb->f64, mixed, tb->d_A, n, m, wts, mixed ? (void*)w.R32 : (void*)w.R, st));
+    if (mixed)
+      SHIP(mfma_gemm_f32(true, false, m, m, n, 1.0f, (const float*)tb->d_A, m, w.R32, m, 1.0f, w.N32, m, st));
+    else if (tb->f64)
+      SHIP(mfma_gemm_f64(true, false, m, m, n, 1.0, (const double*)tb->d_A, m, w.R, m, 1.0, w.Hess, m, st));
+    else
+      SHIP(mfma_gemm_f64_a32(true, false, m, m, n, 1.0, (const float*)tb->d_A, m, w.R, m, 1.0, w.Hess, m, st));
+    auto apply_hess = [&](const double* x, double* out) -> wos_status {
+      wos_status s2 = apply_lam0(x, out);
+      if (s2 != WOS_OK) return s2;
+      SHIP(launch_gemv_n_ld(tb->f64, tb->d_A, n, m, m, x, 1.0, 0.0, tmp, st));
+      SHIP(launch_pointwise(n, wts, nullptr, tmp, 0.0, 0.0, 0.0, 0.0, -1.0, tmp, st));
+      SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, tmp, 1.0, 1.0, out, st));
+      return WOS_OK;
+    };
+    if ((s = sym_reg_solve(tb, w, mixed, rcond, rtol, rmax, grad, dlt, apply_hess, inf, st)) != WOS_OK) return s;
+    SHIP(launch_axpy_reg(m, q, nullptr, -1.0, dlt, q, st));
+  }
+  inf->iters = it;
+  inf->grad_norm = gn;
+  inf->grad_norm0 = gn0;
+  return WOS_OK;
+}
+
 }  // namespace
 
 namespace wos {
 
 void free_work(SolveWork& w) {
   void* ptrs[] = {w.R, w.Lam, w.Sig, w.Lam0, w.Sig0, w.Hess, w.G, w.V, w.E, w.rot, w.pq, w.vec, w.Ac, w.red,
-                  w.blk, w.regv, w.info, w.R32, w.Lam32, w.N32, w.v32, w.D64, w.D32, w.P64, w.P32};
+                  w.blk, w.regv, w.info, w.R32, w.Lam32, w.N32, w.v32, w.D64, w.D32, w.P64, w.P32, w.L0_32};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   w = SolveWork();
@@ -376,8 +528,6 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
     return sfail(WOS_EINVAL, "unknown solver %d", co->solver);
   if (co->precision != WOS_SOLVE_F64 && co->precision != WOS_SOLVE_MIXED)
     return sfail(WOS_EINVAL, "unknown solve precision %d", co->precision);
-  if (co->solver == WOS_SOLVER_TIKHONOV && co->kind != WOS_LINEAR)
-    return sfail(WOS_EINVAL, "the Tikhonov solver is available for linear problems");
   const int max_sweeps = co->max_sweeps > 0 ? co->max_sweeps : 40;
   wos_status s = ensure_work(tb, w);
   if (s != WOS_OK) return s;
@@ -398,6 +548,8 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
     if ((s = linear_rhs(tb, w, w.Sig, f, g, rhs, st)) != WOS_OK) return s;
     if ((s = tsvd_solve(tb, w, w.Lam, co->b == nullptr, rhs, rcond, max_sweeps, q, &tr, st)) != WOS_OK) return s;
     inf.iters = 1;
+  } else if (co->kind == WOS_SEMILINEAR_CUBIC && co->solver == WOS_SOLVER_TIKHONOV) {
+    if ((s = newton_tikhonov(tb, w, co, rcond, f, g, q, &inf, st)) != WOS_OK) return s;
   } else if (co->kind == WOS_SEMILINEAR_CUBIC) {
     // F = |p|^2/2 + kappa u^4/4 - f u; grad J = A^T(lam (kappa u^3 - f)) + Lam0 h + Sig0 g
     const double kappa = co->kappa;
@@ -443,9 +595,18 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
     double du = 0, nu = 0;
     for (it = 1; it <= max_iter; ++it) {
       SHIP(launch_picard_coef(n, d, uu, w.Ac, st));  // A(x_i) = (1 + u_i^2) I
-      if ((s = assemble(tb, w, w.Ac, nullptr, nullptr, w.Lam, w.Sig, st)) != WOS_OK) return s;
-      if ((s = linear_rhs(tb, w, w.Sig, fp, g, rhs, st)) != WOS_OK) return s;
-      if ((s = tsvd_solve(tb, w, w.Lam, true, rhs, rcond, max_sweeps, q, &tr, st)) != WOS_OK) return s;
+      if (co->solver == WOS_SOLVER_TIKHONOV) {
+        wos_coeffs cl = *co;
+        cl.kind = WOS_LINEAR;
+        cl.A = w.Ac;
+        cl.b = nullptr;
+        cl.c = nullptr;
+        if ((s = tikhonov_linear(tb, w, &cl, rcond, fp, g, q, &inf, st)) != WOS_OK) return s;
+      } else {
+        if ((s = assemble(tb, w, w.Ac, nullptr, nullptr, w.Lam, w.Sig, st)) != WOS_OK) return s;
+        if ((s = linear_rhs(tb, w, w.Sig, fp, g, rhs, st)) != WOS_OK) return s;
+        if ((s = tsvd_solve(tb, w, w.Lam, true, rhs, rcond, max_sweeps, q, &tr, st)) != WOS_OK) return s;
+      }
       if ((s = reconstruct(tb, q, g, t1, nullptr, st)) != WOS_OK) return s;
       // du = |u_new - u|_lam, nu = |u_new|_lam
       SHIP(launch_axpby(n, 1.0, t1, -1.0, uu, rhs, st));

@@ -121,9 +121,9 @@ __global__ void scale_kernel(int n, double beta, double* __restrict__ y) {
     y[i] = beta == 0.0 ? 0.0 : beta * y[i];
 }
 
-// out = rcond^2 * max_i N[i][i]; one workgroup
+// out = coef * max_i N[i][i]; one workgroup
 template <typename T>
-__global__ __launch_bounds__(256) void reg_from_diag_kernel(const T* __restrict__ N, int m, int ld, double rcond,
+__global__ __launch_bounds__(256) void reg_from_diag_kernel(const T* __restrict__ N, int m, int ld, double coef,
                                                             double* __restrict__ out) {
   __shared__ double s[256];
   double mx = 0.0;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void reg_from_diag_kernel(const T* __restrict_
     if ((int)threadIdx.x < h) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + h]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = rcond * rcond * s[0];
+  if (threadIdx.x == 0) out[0] = coef * s[0];
 }
 
 template <typename T>
@@ -161,7 +161,31 @@ __global__ void add_f32_kernel(int n, const float* __restrict__ d, double* __res
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += stride) q[i] += (double)d[i];
 }
 
+// Y (rows x cols, TO) = diag(w) X
+template <typename TI, typename TO>
+__global__ void scale_rows_kernel(const TI* __restrict__ X, int rows, int cols, const double* __restrict__ w,
+                                  TO* __restrict__ Y) {
+  const size_t total = (size_t)rows * cols;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride)
+    Y[e] = (TO)(w[e / cols] * (double)X[e]);
+}
+
 }  // namespace
+
+hipError_t launch_scale_rows(bool f64_in, bool f32_out, const void* X, int rows, int cols, const double* w, void* Y,
+                             hipStream_t st) {
+  const dim3 g(nblocks((size_t)rows * cols, 256)), b(256);
+  if (f64_in && !f32_out)
+    hipLaunchKernelGGL((scale_rows_kernel<double, double>), g, b, 0, st, (const double*)X, rows, cols, w, (double*)Y);
+  else if (f64_in && f32_out)
+    hipLaunchKernelGGL((scale_rows_kernel<double, float>), g, b, 0, st, (const double*)X, rows, cols, w, (float*)Y);
+  else if (!f64_in && !f32_out)
+    hipLaunchKernelGGL((scale_rows_kernel<float, double>), g, b, 0, st, (const float*)X, rows, cols, w, (double*)Y);
+  else
+    hipLaunchKernelGGL((scale_rows_kernel<float, float>), g, b, 0, st, (const float*)X, rows, cols, w, (float*)Y);
+  return hipGetLastError();
+}
 
 hipError_t launch_weight_rows_any(bool f64_in, bool f32_out, const void* A, const void* B, const void* H,
                                   const void* K, const double* lam, const double* Ac, const double* bc,
@@ -217,11 +241,11 @@ hipError_t launch_gemv_n_ld(bool f64, const void* X, int rows, int cols, int ld,
   return hipGetLastError();
 }
 
-hipError_t launch_reg_from_diag(bool f64, const void* N, int m, int ld, double rcond, double* out, hipStream_t st) {
+hipError_t launch_reg_from_diag(bool f64, const void* N, int m, int ld, double coef, double* out, hipStream_t st) {
   if (f64)
-    hipLaunchKernelGGL(reg_from_diag_kernel<double>, dim3(1), dim3(256), 0, st, (const double*)N, m, ld, rcond, out);
+    hipLaunchKernelGGL(reg_from_diag_kernel<double>, dim3(1), dim3(256), 0, st, (const double*)N, m, ld, coef, out);
   else
-    hipLaunchKernelGGL(reg_from_diag_kernel<float>, dim3(1), dim3(256), 0, st, (const float*)N, m, ld, rcond, out);
+    hipLaunchKernelGGL(reg_from_diag_kernel<float>, dim3(1), dim3(256), 0, st, (const float*)N, m, ld, coef, out);
   return hipGetLastError();
 }
 

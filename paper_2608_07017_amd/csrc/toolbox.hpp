@@ -60,6 +60,7 @@ struct SolveWork {
   float* D32 = nullptr;
   double* P64 = nullptr;    // one Cholesky panel, m x 64
   float* P32 = nullptr;
+  float* L0_32 = nullptr;   // Lambda_0 (A = I), FP32, for the mixed Newton route
   size_t bytes = 0;         // device memory held
 };
 

@@ -67,7 +67,11 @@ hipError_t launch_gemv_t_ld(bool f64, const void* X, int rows, int cols, int ld,
                             double beta, double* y, hipStream_t st);
 hipError_t launch_gemv_n_ld(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
                             double beta, double* y, hipStream_t st);
-hipError_t launch_reg_from_diag(bool f64, const void* N, int m, int ld, double rcond, double* out, hipStream_t st);
+// out = coef * max_i N[i][i]
+hipError_t launch_reg_from_diag(bool f64, const void* N, int m, int ld, double coef, double* out, hipStream_t st);
+// Y = diag(w) X (rows x cols)
+hipError_t launch_scale_rows(bool f64_in, bool f32_out, const void* X, int rows, int cols, const double* w, void* Y,
+                             hipStream_t st);
 hipError_t launch_add_diag(bool f64, void* N, int m, int ld, const double* reg, hipStream_t st);
 hipError_t launch_axpy_reg(int n, const double* x, const double* reg, double sign, const double* z, double* y,
                            hipStream_t st);

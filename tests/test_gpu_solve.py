@@ -252,3 +252,34 @@ def test_tikhonov_on_fp32_toolbox_matches_oracle(square_f32_tb, precision):
     else:
         tol = 1e-9
     assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < tol
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_newton_tikhonov_matches_oracle(square_f32_tb, precision):
+    tb, mats = square_f32_tb
+    lam = mats["lambda"]
+    x = tb.sites
+    ue, ge, le = W.smooth_field(7, 2, terms=4, max_freq=2.0, scale=0.5)
+    f = -le(x) + ue(x) ** 3
+    g = ue(tb.bnodes)
+    ref = OL.newton_cubic(mats, lam, f, g, kappa=1.0, rcond=1e-2, tol=1e-300, max_iter=5, solver="tikhonov")
+    u, gu, q, info = tb.solve(f, g, kind="semilinear_cubic", kappa=1.0, rcond=1e-2, tol=1e-300, max_iter=5,
+                              solver="tikhonov", precision=precision, refine_tol=1e-13, max_refine=30)
+    torch.cuda.synchronize()
+    _say("newton", precision, info)
+    assert info["iters"] == ref["iters"] == 5
+    assert np.isclose(info["grad_norm0"], ref["grad_norm0"], rtol=1e-6)
+    assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < (1e-9 if precision == "f64" else 1e-6)
+
+
+def test_picard_tikhonov_matches_oracle(disk_tb):
+    tb, mats = disk_tb
+    lam = mats["lambda"]
+    x = _rings(5)
+    f = 2.0 + x[:, 0]
+    g = 0.2 * W.circle_nodes(30)[:, 1]
+    ref = OL.picard_quasilinear(mats, lam, f, g, rcond=3e-2, tol=1e-300, max_iter=4, solver="tikhonov")
+    u, gu, q, info = tb.solve(f, g, kind="quasilinear", rcond=3e-2, tol=1e-300, max_iter=4, solver="tikhonov")
+    torch.cuda.synchronize()
+    assert info["iters"] == ref["iters"] == 4
+    assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < 1e-9

@@ -137,3 +137,27 @@ def test_tikhonov_tends_to_the_inverse_for_a_well_conditioned_matrix():
     r = rng.normal(size=12)
     q, _ = L.tikhonov_solve(M, r, 1e-7)
     assert np.allclose(q, np.linalg.solve(M, r), rtol=1e-9, atol=1e-11)
+
+
+def test_symmetric_regularised_solve_matches_eigen_filter():
+    rng = np.random.default_rng(14)
+    Q, _ = np.linalg.qr(rng.normal(size=(20, 20)))
+    e = np.logspace(1, -7, 20)
+    M = Q @ np.diag(e) @ Q.T
+    r = rng.normal(size=20)
+    x, reg = L.sym_reg_solve(M, r, 1e-3)
+    assert np.isclose(reg, 1e-3 * np.max(np.diag(M)))
+    assert np.allclose(x, Q @ ((Q.T @ r) / (e + reg)), rtol=1e-9, atol=1e-12)
+
+
+def test_regularised_newton_reaches_the_regularised_stationary_point():
+    # at convergence the step vanishes: grad J(h) = 0 up to the regularised
+    # solve, which for an invertible Hessian means grad J = 0
+    tb = _random_tb(10, 4, 2, 5)
+    tb["B"] *= 3
+    rng = np.random.default_rng(6)
+    lam = rng.random(10)
+    f = rng.normal(size=10)
+    g = rng.normal(size=4)
+    res = L.newton_cubic(tb, lam, f, g, kappa=0.5, rcond=1e-12, tol=1e-12, max_iter=60, solver="tikhonov")
+    assert res["grad_norm"] <= 1e-9 * res["grad_norm0"]
