@@ -13,7 +13,9 @@ equispaced boundary nodes, 1e4 walks per site, eps = 1e-4, FP32 walker.
 The line also carries "serving": solves/s and p50/p99 latency of a served
 stream of Dirichlet problems on resident L-shape toolboxes (256/1024/4096
 sites), mixed precision against FP64, with the L2 errors of both against
-the manufactured solutions.
+the manufactured solutions, and "newton_ball4096": the 3-D unit-ball
+toolbox build and a regularised Newton solve of -Lap u + u^3 = f, mixed
+precision against FP64.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-serving]
 
@@ -81,6 +83,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true", help="skip the served-solve stream")
+    ap.add_argument("--no-newton", action="store_true", help="skip the 3-D Newton run")
+    ap.add_argument("--newton-iters", type=int, default=10)
+    ap.add_argument("--newton-rcond", type=float, default=1e-2)
     ap.add_argument("--serve-requests", type=int, default=2000, help="open-loop requests (mixed precision)")
     ap.add_argument("--serve-saturation", type=int, default=300, help="requests of the saturation run")
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -197,6 +202,40 @@ def serving(a, torch, W, P):
     return out
 
 
+def newton_ball(a, torch, W, P):
+    """The 3-D unit ball toolbox (4096 sites, 1024 Fibonacci nodes, 1e4
+    walks/site, eps 1e-4, FP32) and Newton for -Lap u + u^3 = f with a seeded
+    manufactured solution, regularised steps in mixed precision and in FP64."""
+    cfg = W.config("ball4096")
+    x, z = cfg["sites"], cfg["bnodes"]
+    tb = P.Toolbox(cfg["domain"], x, z, cfg["walks"], cfg["eps"], seed=cfg["seed"], precision="f32")
+    tb.set_timing(True)
+    tb.build()
+    tb.build(seed=cfg["seed"] + 1)
+    t = tb.timings()
+    inf = tb.info()
+    lam = tb.export("lambda").cpu().numpy()
+    ue, _, le = W.smooth_field(2026, 3, terms=8, max_freq=3.0, scale=0.5)
+    f, g = -le(x) + ue(x) ** 3, ue(z)
+    nrm = float(np.sqrt(np.sum(lam * ue(x) ** 2)))
+    out = {"workload": "3D unit ball, 4096 sites, 1024 Fibonacci boundary nodes, 1e4 walks/site, eps 1e-4, FP32; "
+                       "-Lap u + u^3 = f, Newton (%d steps), Tikhonov rcond %g" % (a.newton_iters, a.newton_rcond),
+           "walker_ms": t["walker_ms"], "walk_steps_per_s": inf["walk_steps"] / (t["walker_ms"] * 1e-3)}
+    for prec in ("f64", "mixed"):
+        tb.solve(f, g, kind="semilinear_cubic", rcond=a.newton_rcond, tol=1e-300, max_iter=1, solver="tikhonov",
+                 precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, _, _, info = tb.solve(f, g, kind="semilinear_cubic", rcond=a.newton_rcond, tol=1e-300,
+                                 max_iter=a.newton_iters, solver="tikhonov", precision=prec, refine_tol=1e-8)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[prec] = {"seconds": dt, "grad_norm_rel": info["grad_norm"] / info["grad_norm0"],
+                     "rel_l2_error": float(np.sqrt(np.sum(lam * (u.cpu().numpy() - ue(x)) ** 2))) / nrm}
+    out["mixed_vs_f64"] = out["f64"]["seconds"] / out["mixed"]["seconds"]
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -277,6 +316,9 @@ def main():
         out["calibration_copy_bytes"] = src.numel() * 4
     if not a.no_serving:
         out["serving"] = serving(a, torch, W, P)
+    if not a.no_newton:
+        print("newton: ball4096", file=sys.stderr, flush=True)
+        out["newton_ball4096"] = newton_ball(a, torch, W, P)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_rows)
     print(json.dumps(out), flush=True)
