@@ -239,8 +239,8 @@ def newton_ball(a, torch, W, P):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: the toolbox build shards by sites across GPUs "
-              "(see DESIGN.md), which this build does not launch; use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: several GPUs would each build the rows of their own "
+              "share of the sites, and no multi-GPU launch is provided; use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads as W

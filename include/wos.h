@@ -94,6 +94,14 @@ typedef struct {
                                inputs, keeps the fastest for later builds, and
                                synchronises the stream once; 0: the size is chosen
                                by occupancy.  The results do not depend on it.     */
+  int32_t tally_in_hbm;     /* 1: the walker adds every tally straight into the
+                               toolbox in device memory (atomics, pre-scaled by
+                               1/N) instead of a site's rows in LDS; 0: only when
+                               a site's rows do not fit in LDS (about
+                               8 (1 + dim) n + 12 dim p bytes > 160 KiB).  In this
+                               mode the sums are in the toolbox precision and
+                               their order of addition is not fixed, so results
+                               agree with the LDS mode to rounding only.        */
 } wos_build_opts;
 
 typedef struct wos_toolbox wos_toolbox;
@@ -226,7 +234,8 @@ typedef struct {
  * linear elliptic PDEs" and Sec. "Euler-Lagrange boundary value problems"):
  * assembles Lambda, Sigma and the right-hand side of eq. linear_q from the
  * toolbox and the coefficients sampled at the sites, solves it with the
- * truncated SVD, and reconstructs u = A q + H g, grad u = B q + K g.
+ * chosen generalised inverse (coeffs->solver), and reconstructs
+ * u = A q + H g, grad u = B q + K g.
  *   f       device double (n): f(x_i) in the convention of `kind`
  *   g       device double (p): g(z_j)
  *   u       device double (n) output; grad_u device (d x n) or NULL;
@@ -239,6 +248,59 @@ typedef struct {
  * one toolbox.                                                               */
 wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* coeffs, const double* f, const double* g,
                      double* u, double* grad_u, double* q, wos_solve_info* info, void* stream);
+
+/* ---------------------------------------------------- solution operators
+ * For a LINEAR problem the map from the data (f, g) to the solution is
+ * linear (Sec. "Second order linear elliptic PDEs": q solves eq. linear_q,
+ * whose right-hand side is -A^T (lambda o f) - Sigma g, and u = A q + H g).
+ * An operator holds that map for one toolbox and one set of coefficients
+ * as dense matrices,
+ *   u      = U_f f + U_g g,           U = A Y [-A^T diag(lambda) | -Sigma] + [0 | H],
+ *   grad u = G_f f + G_g g (optional), with B and K in place of A and H,
+ * where Y = (Lambda^T Lambda + reg I)^{-1} Lambda^T is the Tikhonov inverse
+ * of wos_solve (solver TIKHONOV, same rcond and reg), formed once in FP64 on
+ * the matrix cores.  Each solve is then one pass over U (n x (n + p) values),
+ * and a batch of solves reads U once for all of them.                        */
+typedef struct wos_operator wos_operator;
+
+typedef struct {
+  int32_t want_grad;  /* 1: also hold G (d n x (n + p)) for grad u                 */
+  int32_t storage;    /* wos_precision of the stored matrices: WOS_F64, or WOS_F32
+                         (half the bytes per solve; products accumulate in FP64,
+                         relative change of u about 1e-7)                           */
+} wos_operator_opts;
+
+typedef struct {
+  int32_t n, p, dim, want_grad, storage;
+  double reg;          /* Tikhonov parameter used                               */
+  size_t device_bytes; /* held by the operator                                  */
+  double prep_ms;      /* device time of the preparation                        */
+} wos_operator_info;
+
+/* Prepares the operator of `coeffs` (kind LINEAR, solver TIKHONOV; the
+ * precision field is ignored: the preparation runs in FP64) on `stream` and
+ * synchronises it.  Temporary device memory of about
+ * 8 ((d+1) n (m+p) + 4 m (m+p)) bytes is allocated and freed.  The
+ * coefficient arrays are read during the call only; the toolbox must stay
+ * built and unchanged while the operator is used.
+ *   WOS_EINVAL: NULL argument, kind not LINEAR, toolbox not built;
+ *   WOS_ENOTIMPL: solver TSVD; WOS_ENOTCONV: normal matrix not positive
+ *   definite; WOS_ENOMEM: device memory.                                     */
+wos_status wos_operator_create(wos_toolbox* tb, const wos_coeffs* coeffs, const wos_operator_opts* opts,
+                               void* stream, wos_operator** out);
+
+/* Solves `nrhs` problems at once: for r < nrhs,
+ *   u[r] = U_f f[r] + U_g g[r],  grad_u[r] = G_f f[r] + G_g g[r].
+ *   f, g, u, grad_u: host arrays of nrhs device pointers to double vectors of
+ *   n, p, n and d x n values (grad_u may be NULL, or hold NULL entries; it
+ *   needs an operator with want_grad).  Outputs must not overlap inputs.
+ * Asynchronous on `stream`; nrhs in 1 .. 1024.                               */
+wos_status wos_operator_apply(const wos_operator* op, int32_t nrhs, const double* const* f,
+                              const double* const* g, double* const* u, double* const* grad_u, void* stream);
+
+wos_status wos_operator_get_info(const wos_operator* op, wos_operator_info* info);
+
+void wos_operator_free(wos_operator* op);
 
 /* ------------------------------------------------------------ serving
  * A request server over resident toolboxes.  Solves are queued in arrival
@@ -255,6 +317,7 @@ typedef struct wos_server wos_server;
 typedef struct {
   int32_t slots;      /* concurrent requests, 1 .. 16; 0 -> 4                  */
   size_t mem_budget;  /* device bytes for solve workspaces; 0 -> no limit     */
+  int32_t max_batch;  /* operator requests solved together, 1 .. 1024; 0 -> 64 */
 } wos_server_opts;
 
 wos_status wos_server_create(const wos_server_opts* opts, wos_server** out);
@@ -264,6 +327,13 @@ wos_status wos_server_create(const wos_server_opts* opts, wos_server** out);
  * is copied.  Returns at once with a ticket.                                  */
 wos_status wos_server_submit(wos_server* sv, wos_toolbox* tb, const wos_coeffs* coeffs, const double* f,
                              const double* g, double* u, double* grad_u, uint64_t* ticket);
+
+/* Queues one solve with a prepared operator.  Requests on the same operator
+ * that are queued together are solved as one batch (one pass over the
+ * operator for up to `max_batch` of them).  Buffers as for
+ * wos_server_submit; the operator must outlive its requests.                */
+wos_status wos_server_submit_op(wos_server* sv, const wos_operator* op, const double* f, const double* g,
+                                double* u, double* grad_u, uint64_t* ticket);
 
 /* Result of a request: WOS_EBUSY while it runs (block = 0), else its status
  * after it finished (block = 1 waits).  On completion fills *info and, if

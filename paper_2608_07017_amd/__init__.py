@@ -15,6 +15,7 @@ import numpy as np
 import torch
 
 from ._lib import (EXPORTS, KINDS, PRECISION, PROBLEMS, SOLVE_PRECISION, SOLVERS, WosBuildOpts, WosCoeffs,
+                   WosOperatorInfo, WosOperatorOpts,
                    WosDomain, WosError, WosServerOpts, WosSolveInfo, WosToolboxInfo, check, lib)
 
 __all__ = ["Toolbox", "Server", "build_toolbox", "WosError", "lib"]
@@ -50,7 +51,8 @@ class Toolbox:
     """A resident toolbox {x, z, A, B, H, K, lambda} on the current GPU."""
 
     def __init__(self, domain, sites, bnodes, walks, eps, seed=0, precision="f32", max_steps=0,
-                 fixed_M=0, volume_samples=0, walks_per_item=0, regen_threshold=0, autotune=True):
+                 fixed_M=0, volume_samples=0, walks_per_item=0, regen_threshold=0, autotune=True,
+                 tally_in_hbm=False):
         self.domain = domain
         self.sites = np.ascontiguousarray(np.asarray(sites, dtype=np.float64))
         self.bnodes = np.ascontiguousarray(np.asarray(bnodes, dtype=np.float64))
@@ -64,7 +66,8 @@ class Toolbox:
         opts = WosBuildOpts(walks_per_site=int(walks), eps=float(eps), max_steps=int(max_steps),
                             fixed_M=int(fixed_M), seed=self.seed, precision=PRECISION[precision],
                             volume_samples=int(volume_samples), walks_per_item=int(walks_per_item),
-                            regen_threshold=int(regen_threshold), autotune=1 if autotune else 0)
+                            regen_threshold=int(regen_threshold), autotune=1 if autotune else 0,
+                            tally_in_hbm=1 if tally_in_hbm else 0)
         h = ctypes.c_void_p()
         dp = ctypes.POINTER(ctypes.c_double)
         check(lib().wos_toolbox_create(ctypes.byref(dom), self.sites.ctypes.data_as(dp), self.n,
@@ -144,6 +147,12 @@ class Toolbox:
                               ctypes.byref(info), _stream_handle(stream)))
         return u, gu, q, {k: getattr(info, k) for k, _ in info._fields_}
 
+    def operator(self, A=None, b=None, c=None, rcond=1e-3, grad=False, storage="f64", stream=None):
+        """Prepare the solution operator of the linear problem with these
+        coefficients (include/wos.h, wos_operator_create): Tikhonov inverse
+        with `rcond`, stored in `storage` ("f64" or "f32")."""
+        return Operator(self, A, b, c, rcond, grad, storage, stream)
+
     def _coeffs(self, f, g, kind="linear", A=None, b=None, c=None, kappa=1.0, rcond=1e-3, tol=0.0, max_iter=0,
                 max_sweeps=0, solver="tsvd", precision="f64", max_refine=0, refine_tol=0.0):
         """Device copies of the problem data and the wos_coeffs struct."""
@@ -174,13 +183,64 @@ class Toolbox:
             pass
 
 
+class Operator:
+    """A prepared solution operator u = U_f f + U_g g (and grad u) of one
+    toolbox and one set of linear coefficients."""
+
+    def __init__(self, tb, A, b, c, rcond, grad, storage, stream):
+        zf = torch.zeros(tb.n, dtype=torch.float64, device="cuda")
+        zg = torch.zeros(tb.p, dtype=torch.float64, device="cuda")
+        _, _, A, b, c, co = tb._coeffs(zf, zg, "linear", A, b, c, rcond=rcond, solver="tikhonov")
+        opts = WosOperatorOpts(want_grad=1 if grad else 0, storage=PRECISION[storage])
+        self._h = ctypes.c_void_p()
+        check(lib().wos_operator_create(tb._h, ctypes.byref(co), ctypes.byref(opts), _stream_handle(stream),
+                                        ctypes.byref(self._h)))
+        self.tb = tb  # the toolbox must outlive the operator
+        self.n, self.p, self.dim, self.grad = tb.n, tb.p, tb.dim, bool(grad)
+
+    def info(self):
+        inf = WosOperatorInfo()
+        check(lib().wos_operator_get_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in inf._fields_}
+
+    def apply(self, f, g, grad=False, stream=None):
+        """f (nrhs, n) and g (nrhs, p), or single vectors; returns u (nrhs, n)
+        and grad_u (nrhs, d, n) or None, float64 on the device."""
+        dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+        f, g = dev(f), dev(g)
+        single = f.dim() == 1
+        f, g = f.reshape(-1, self.n), g.reshape(-1, self.p)
+        if f.shape[0] != g.shape[0]:
+            raise ValueError("f and g must hold the same number of right-hand sides")
+        k = f.shape[0]
+        u = torch.empty((k, self.n), dtype=torch.float64, device="cuda")
+        gu = torch.empty((k, self.dim, self.n), dtype=torch.float64, device="cuda") if grad else None
+        arr = lambda ts: (ctypes.c_void_p * k)(*[t.data_ptr() for t in ts])
+        check(lib().wos_operator_apply(self._h, k, arr(f), arr(g), arr(u), arr(gu) if grad else None,
+                                       _stream_handle(stream)))
+        if single:
+            return u[0], (gu[0] if grad else None)
+        return u, gu
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().wos_operator_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 class Server:
     """Request server over resident toolboxes (include/wos.h, wos_server_*):
     up to `slots` solves run concurrently, each on its own stream."""
 
-    def __init__(self, slots=4, mem_budget=0):
+    def __init__(self, slots=4, mem_budget=0, max_batch=0):
         self._h = ctypes.c_void_p()
-        opts = WosServerOpts(slots=int(slots), mem_budget=int(mem_budget))
+        opts = WosServerOpts(slots=int(slots), mem_budget=int(mem_budget), max_batch=int(max_batch))
         check(lib().wos_server_create(ctypes.byref(opts), ctypes.byref(self._h)))
         self._live = {}  # ticket -> tensors that must outlive the request
 
@@ -195,6 +255,21 @@ class Server:
         check(lib().wos_server_submit(self._h, tb._h, ctypes.byref(co), _dptr(f), _dptr(g), _dptr(u),
                                       _dptr(gu) if grad else ctypes.c_void_p(0), ctypes.byref(t)))
         self._live[t.value] = (f, g, A, b, c, u, gu)
+        return t.value, u, gu
+
+    def submit_op(self, op, f, g, u=None, grad=False):
+        """Queue a solve with a prepared operator; returns (ticket, u, grad_u)."""
+        dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+        f, g = dev(f), dev(g)
+        if f.numel() != op.n or g.numel() != op.p:
+            raise ValueError("f must have n entries and g p entries")
+        if u is None:
+            u = torch.empty(op.n, dtype=torch.float64, device="cuda")
+        gu = torch.empty((op.dim, op.n), dtype=torch.float64, device="cuda") if grad else None
+        t = ctypes.c_uint64()
+        check(lib().wos_server_submit_op(self._h, op._h, _dptr(f), _dptr(g), _dptr(u),
+                                         _dptr(gu) if grad else ctypes.c_void_p(0), ctypes.byref(t)))
+        self._live[t.value] = (op, f, g, u, gu)
         return t.value, u, gu
 
     def poll(self, ticket, block=True):

@@ -31,7 +31,8 @@ class WosBuildOpts(ctypes.Structure):
                 ("max_steps", ctypes.c_int32), ("fixed_M", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
                 ("volume_samples", ctypes.c_int64), ("walks_per_item", ctypes.c_int32),
-                ("regen_threshold", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("regen_threshold", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("tally_in_hbm", ctypes.c_int32)]
 
 
 class WosToolboxInfo(ctypes.Structure):
@@ -52,7 +53,17 @@ class WosCoeffs(ctypes.Structure):
 
 
 class WosServerOpts(ctypes.Structure):
-    _fields_ = [("slots", ctypes.c_int32), ("mem_budget", ctypes.c_size_t)]
+    _fields_ = [("slots", ctypes.c_int32), ("mem_budget", ctypes.c_size_t), ("max_batch", ctypes.c_int32)]
+
+
+class WosOperatorOpts(ctypes.Structure):
+    _fields_ = [("want_grad", ctypes.c_int32), ("storage", ctypes.c_int32)]
+
+
+class WosOperatorInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("p", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("want_grad", ctypes.c_int32), ("storage", ctypes.c_int32), ("reg", ctypes.c_double),
+                ("device_bytes", ctypes.c_size_t), ("prep_ms", ctypes.c_double)]
 
 
 class WosSolveInfo(ctypes.Structure):
@@ -89,6 +100,13 @@ SIGNATURES = {
     "wos_server_create": (ctypes.c_int, [ctypes.POINTER(WosServerOpts), ctypes.POINTER(_P)]),
     "wos_server_submit": (ctypes.c_int, [_P, _P, ctypes.POINTER(WosCoeffs), _P, _P, _P, _P,
                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "wos_operator_create": (ctypes.c_int, [_P, ctypes.POINTER(WosCoeffs), ctypes.POINTER(WosOperatorOpts), _P,
+                                           ctypes.POINTER(_P)]),
+    "wos_operator_apply": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                          ctypes.POINTER(_P), ctypes.POINTER(_P), _P]),
+    "wos_operator_get_info": (ctypes.c_int, [_P, ctypes.POINTER(WosOperatorInfo)]),
+    "wos_operator_free": (None, [_P]),
+    "wos_server_submit_op": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
     "wos_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(WosSolveInfo), _D]),
     "wos_server_pending": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "wos_server_destroy": (None, [_P]),

@@ -289,7 +289,7 @@ static wos_status zero_walker_outputs(wos_toolbox* tb, hipStream_t stream) {
   const size_t ts = tsize(tb);
   const size_t n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
   WOS_HIP(hipMemsetAsync(tb->d_stats, 0, 4 * 8, stream));
-  if (tb->items_per_site != 1) {
+  if (tb->items_per_site != 1 || tb->global_tally) {
     WOS_HIP(hipMemsetAsync(tb->d_A, 0, ts * n * m, stream));
     WOS_HIP(hipMemsetAsync(tb->d_B, 0, ts * d * n * m, stream));
     WOS_HIP(hipMemsetAsync(tb->d_K, 0, ts * d * n * p, stream));
@@ -323,6 +323,7 @@ static void fill_walker_params(const wos_toolbox* tb, uint32_t k0, uint32_t k1, 
   P.block_override = block;
   P.item_order = tb->d_item_order;
   P.direct_store = tb->items_per_site == 1 ? 1 : 0;
+  P.global_tally = tb->global_tally ? 1 : 0;
   P.acc_fixed = f64 ? 0 : tb->acc_fixed;  // FP64 toolboxes accumulate in FP64
   P.A = static_cast<T*>(tb->d_A);
   P.B = static_cast<T*>(tb->d_B);
@@ -440,11 +441,11 @@ wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_
   tb->regen_T = tb->opts.regen_threshold ? tb->opts.regen_threshold : 48;
 
   const int nseg = hd.kind == WOS_POLYGON ? dom->nvert : 0;
-  const size_t lds = walker_lds_bytes(d, n, p, nseg, tb->f64);
-  if (lds > 160 * 1024) {
-    delete tb;
-    return fail(WOS_ENOTIMPL, "site rows need %zu bytes of LDS (> 160 KiB); reduce n or p", lds);
-  }
+  // a site's rows are tallied in LDS when they fit, else straight into the
+  // toolbox in device memory
+  const size_t lds_rows = walker_lds_bytes(d, n, p, nseg, tb->f64);
+  tb->global_tally = opts->tally_in_hbm != 0 || lds_rows > 160 * 1024;
+  const size_t lds = tb->global_tally ? (tb->f64 ? 8 : 4) * (5 * (size_t)nseg + 4 * (size_t)n) : lds_rows;
 
   // work split: about one (site, chunk) item per workgroup slot of the chip
   const int64_t N = opts->walks_per_site;

@@ -174,4 +174,10 @@ hipError_t mfma_gemm_f64_a32(bool ta, bool tb, int M, int N, int K, double alpha
   return gemm_dispatch<double, float, double>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st);
 }
 
+// FP64 arithmetic on an FP32-stored right operand
+hipError_t mfma_gemm_f64_b32(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
+                             const float* B, int ldb, double beta, double* C, int ldc, hipStream_t st) {
+  return gemm_dispatch<double, double, float>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st);
+}
+
 }  // namespace wos

@@ -8,7 +8,10 @@
 // up to `slots` requests overlap on the device.  A worker keeps the
 // workspaces of the toolboxes it served; when a new one would exceed the
 // budget it first frees its own, and waits while other workers hold the
-// memory.  Each request records its submit, start and end times.
+// memory.  Requests on a prepared operator need no workspace; a worker that
+// takes one also takes the other queued requests on the same operator (up
+// to max_batch) and solves them with one batched application.  Each request
+// records its submit, start and end times.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -52,6 +55,7 @@ wos_status sv_fail(wos_status s, const char* fmt, ...) {
 struct Request {
   uint64_t id = 0;
   wos_toolbox* tb = nullptr;
+  const wos_operator* op = nullptr;  // operator request (tb unused)
   wos_coeffs co{};
   const double* f = nullptr;
   const double* g = nullptr;
@@ -82,6 +86,7 @@ size_t workspace_bytes(const wos_toolbox* tb) {
 struct wos_server {
   int device = 0;
   size_t budget = 0;  // 0: unlimited
+  int max_batch = 64;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Request*> queue;
@@ -115,6 +120,47 @@ void wos_server::worker_loop(int slot) {
     cv_work.wait(lk, [&] { return stop || !queue.empty(); });
     if (stop && queue.empty()) break;
     Request* r = queue.front();
+    if (r->op) {
+      // operator requests: take every queued one on this operator, up to max_batch
+      std::vector<Request*> batch;
+      for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < max_batch;) {
+        if ((*it)->op == r->op) {
+          batch.push_back(*it);
+          it = queue.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      if (!queue.empty()) cv_work.notify_one();
+      const double t_start = now_s();
+      for (Request* b : batch) b->t_start = t_start;
+      lk.unlock();
+      std::vector<const double*> fs, gs;
+      std::vector<double*> us, gus;
+      for (Request* b : batch) {
+        fs.push_back(b->f);
+        gs.push_back(b->g);
+        us.push_back(b->u);
+        gus.push_back(b->grad_u);
+      }
+      wos_status s = wos_operator_apply(r->op, (int32_t)batch.size(), fs.data(), gs.data(), us.data(), gus.data(), st);
+      std::string err = s == WOS_OK ? std::string() : std::string(wos_last_error());
+      if (s == WOS_OK && hipStreamSynchronize(st) != hipSuccess) {
+        s = WOS_EDEVICE;
+        err = "device error while applying an operator";
+      }
+      const double t_end = now_s();
+      lk.lock();
+      for (Request* b : batch) {
+        b->status = s;
+        b->error = err;
+        b->t_end = t_end;
+        b->info.iters = 1;
+        b->done = true;
+      }
+      cv_done.notify_all();
+      continue;
+    }
     // admission by memory
     if (ws.find(r->tb) == ws.end()) {
       const size_t need = workspace_bytes(r->tb);
@@ -189,6 +235,13 @@ wos_status wos_server_create(const wos_server_opts* opts, wos_server** out) {
     return sv_fail(WOS_EDEVICE, "no current HIP device");
   }
   sv->budget = opts ? opts->mem_budget : 0;
+  if (opts && opts->max_batch != 0) {
+    if (opts->max_batch < 1 || opts->max_batch > 1024) {
+      delete sv;
+      return sv_fail(WOS_EINVAL, "max_batch must be in [1, 1024]");
+    }
+    sv->max_batch = opts->max_batch;
+  }
   for (int i = 0; i < slots; ++i) sv->workers.emplace_back([sv, i] { sv->worker_loop(i); });
   *out = sv;
   return WOS_OK;
@@ -202,6 +255,26 @@ wos_status wos_server_submit(wos_server* sv, wos_toolbox* tb, const wos_coeffs* 
   if (!r) return sv_fail(WOS_ENOMEM, "out of host memory");
   r->tb = tb;
   r->co = *co;
+  r->f = f;
+  r->g = g;
+  r->u = u;
+  r->grad_u = grad_u;
+  r->t_submit = now_s();
+  std::lock_guard<std::mutex> g_(sv->mu);
+  r->id = sv->next_id++;
+  *ticket = r->id;
+  sv->queue.push_back(r.get());
+  sv->reqs.emplace(r->id, std::move(r));
+  sv->cv_work.notify_one();
+  return WOS_OK;
+}
+
+wos_status wos_server_submit_op(wos_server* sv, const wos_operator* op, const double* f, const double* g, double* u,
+                                double* grad_u, uint64_t* ticket) {
+  if (!sv || !op || !f || !g || !u || !ticket) return sv_fail(WOS_EINVAL, "NULL argument");
+  std::unique_ptr<Request> r(new (std::nothrow) Request());
+  if (!r) return sv_fail(WOS_ENOMEM, "out of host memory");
+  r->op = op;
   r->f = f;
   r->g = g;
   r->u = u;

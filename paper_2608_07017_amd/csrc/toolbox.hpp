@@ -81,6 +81,7 @@ struct wos_toolbox {
   int walker_block = 0;  // walker workgroup size (0: by occupancy, or tuned at the first build)
   bool autotune = false;
   int acc_fixed = 1;
+  bool global_tally = false;  // tallies by atomics into the toolbox (rows too large for LDS, or asked for)
   int* d_item_order = nullptr;
   std::vector<double> sites, bnodes;
   // device

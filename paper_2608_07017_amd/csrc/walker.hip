@@ -44,8 +44,9 @@ namespace {
 constexpr size_t kPtsLdsMax = 32 * 1024;
 constexpr size_t kLdsMax = 160 * 1024;
 
-// Tally accumulators in LDS.
-enum { kAccF64 = 0, kAccFixed = 1 };
+// Tally accumulators: FP64 or fixed point in LDS, or (rows too large for
+// LDS) atomics straight to the toolbox in HBM, pre-scaled by 1/N.
+enum { kAccF64 = 0, kAccFixed = 1, kAccGlobal = 2 };
 
 template <int ACC>
 struct Acc;
@@ -101,9 +102,22 @@ __device__ __forceinline__ int4 load_record(const GridDev<T>& g, const T* q) {
   return g.rec[(unsigned int)grid_cell<T, D>(g, q)];
 }
 
+template <>
+struct Acc<kAccGlobal> {};
+
+template <int ACC, typename T>
+struct AccWord {
+  using type = typename Acc<ACC>::word;
+};
+template <typename T>
+struct AccWord<kAccGlobal, T> {
+  using type = T;
+};
+
 template <typename T, int D, int KIND, bool PTS_LDS, int kBlock, int ACC>
 __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
-  using AW = typename Acc<ACC>::word;
+  constexpr bool GLOBAL = ACC == kAccGlobal;
+  using AW = typename AccWord<ACC, T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ unsigned int s_next;
   __shared__ unsigned long long s_steps, s_walks, s_capped;
@@ -118,17 +132,45 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   constexpr int PS = PtStride<D>::value;
 
   // LDS: the site's rows of A, B, K, the polygon edges, the site centres
-  // (when they fit) and the exit counts of H.
-  AW* sA = reinterpret_cast<AW*>(smem);
-  AW* sB = sA + m;
-  AW* sK = sB + (size_t)D * m;
-  T* sSeg = reinterpret_cast<T*>(sK + (size_t)D * p);
-  T* sPts = sSeg + 5 * P.nseg;
-  unsigned int* sH = reinterpret_cast<unsigned int*>(sPts + (PTS_LDS ? (size_t)PS * m : 0));
+  // (when they fit) and the exit counts of H.  In the global mode the rows
+  // are the site's rows of the toolbox itself (row a of B, K at stride
+  // n m, n p) and only the edges and centres are in LDS.
+  const size_t n_sites = (size_t)P.n;
+  AW *sA, *sB, *sK;
+  unsigned int* sH;
+  T *sSeg, *sPts;
+  size_t bstride, kstride;
+  if constexpr (GLOBAL) {
+    sA = P.A + (size_t)site * m;
+    sB = P.B + (size_t)site * m;
+    sK = P.K + (size_t)site * p;
+    sH = P.Hc + (size_t)site * p;
+    bstride = n_sites * m;
+    kstride = n_sites * p;
+    sSeg = reinterpret_cast<T*>(smem);
+    sPts = sSeg + 5 * P.nseg;
+  } else {
+    sA = reinterpret_cast<AW*>(smem);
+    sB = sA + m;
+    sK = sB + (size_t)D * m;
+    sSeg = reinterpret_cast<T*>(sK + (size_t)D * p);
+    sPts = sSeg + 5 * P.nseg;
+    sH = reinterpret_cast<unsigned int*>(sPts + (PTS_LDS ? (size_t)PS * m : 0));
+    bstride = m;
+    kstride = p;
+  }
+  auto add_tally = [&](AW* at, T v) {
+    if constexpr (GLOBAL)
+      atomicAdd(at, v * P.inv_N);
+    else
+      Acc<ACC>::add(at, v);
+  };
 
   const int tid = threadIdx.x;
-  for (int j = tid; j < (1 + D) * m + D * p; j += kBlock) sA[j] = AW(0);
-  for (int j = tid; j < p; j += kBlock) sH[j] = 0u;
+  if constexpr (!GLOBAL) {
+    for (int j = tid; j < (1 + D) * m + D * p; j += kBlock) sA[j] = AW(0);
+    for (int j = tid; j < p; j += kBlock) sH[j] = 0u;
+  }
   for (int j = tid; j < 5 * P.nseg; j += kBlock) sSeg[j] = P.segs[j];
   if constexpr (PTS_LDS)
     for (int j = tid; j < PS * m; j += kBlock) sPts[j] = P.gv.pts[j];
@@ -239,9 +281,9 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
         const T bw = r0 * poly;
         const int jb = grid_resolve<T, D>(P.gv, vpts, rb, qb);
 #pragma unroll
-        for (int a = 0; a < D; ++a) Acc<ACC>::add(&sB[a * m + jb], bw * Zs[a]);
+        for (int a = 0; a < D; ++a) add_tally(&sB[a * bstride + jb], bw * Zs[a]);
         const int j0 = grid_resolve<T, D>(P.gv, vpts, r0c, q0);
-        Acc<ACC>::add(&sA[j0], pomd * r0sq);
+        add_tally(&sA[j0], pomd * r0sq);
       }
       V += avail;
       n_walks += (unsigned long long)avail;
@@ -252,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
       const int j = grid_nearest<T, D>(P.gg, P.gg.pts, X);
       atomicAdd(&sH[j], 1u);
 #pragma unroll
-      for (int a = 0; a < D; ++a) Acc<ACC>::add(&sK[a * p + j], w[a]);
+      for (int a = 0; a < D; ++a) add_tally(&sK[a * kstride + j], w[a]);
       done = false;
     }
 
@@ -355,9 +397,9 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
         // A += t, B += t w at the cell of X_k + r Y, t = omega r^2 / d
         const T t = omd * r * r;
         const int j = grid_resolve<T, D>(P.gv, vpts, rec, q);
-        Acc<ACC>::add(&sA[j], t);
+        add_tally(&sA[j], t);
 #pragma unroll
-        for (int a = 0; a < D; ++a) Acc<ACC>::add(&sB[a * m + j], t * w[a]);
+        for (int a = 0; a < D; ++a) add_tally(&sB[a * bstride + j], t * w[a]);
       }
 #pragma unroll
       for (int a = 0; a < D; ++a) {
@@ -376,6 +418,15 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   atomicMax(&s_maxk, lane_maxk);
   __syncthreads();
 
+  if constexpr (GLOBAL) {
+    if (tid == 0) {
+      atomicAdd(&P.stats[0], s_steps);
+      atomicAdd(&P.stats[1], s_walks);
+      atomicAdd(&P.stats[2], s_capped);
+      atomicMax(&P.stats[3], (unsigned long long)s_maxk);
+    }
+    return;
+  } else {
   // ---- flush the site's rows, scaled by 1/N
   const double inv_N = (double)P.inv_N;
   const size_t n = (size_t)P.n;
@@ -419,6 +470,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
     atomicAdd(&P.stats[1], s_walks);
     atomicAdd(&P.stats[2], s_capped);
     atomicMax(&P.stats[3], (unsigned long long)s_maxk);
+  }
   }
 }
 
@@ -491,6 +543,11 @@ hipError_t launch_bs(const WalkerParams<T>& P, size_t lds, int items, hipStream_
 template <typename T, int D, int KIND>
 hipError_t launch_typed(const WalkerParams<T>& P, size_t lds, int items, hipStream_t stream) {
   const size_t pts = sizeof(T) * PtStride<D>::value * (size_t)P.m;
+  if (P.global_tally) {
+    const size_t lds_g = sizeof(T) * 5 * (size_t)P.nseg;
+    if (pts <= kPtsLdsMax) return launch_bs<T, D, KIND, true, kAccGlobal>(P, lds_g + pts, items, stream);
+    return launch_bs<T, D, KIND, false, kAccGlobal>(P, lds_g, items, stream);
+  }
   const bool pts_lds = pts <= kPtsLdsMax && lds + pts <= kLdsMax;
   if constexpr (std::is_same<T, float>::value) {
     if (P.acc_fixed) {

@@ -45,6 +45,8 @@ hipError_t mfma_gemm_f32(bool ta, bool tb, int M, int N, int K, float alpha, con
                          const float* B, int ldb, float beta, float* C, int ldc, hipStream_t st);
 hipError_t mfma_gemm_f64_a32(bool ta, bool tb, int M, int N, int K, double alpha, const float* A, int lda,
                              const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st);
+hipError_t mfma_gemm_f64_b32(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
+                             const float* B, int ldb, double beta, double* C, int ldc, hipStream_t st);
 
 // ---- Cholesky (chol.hip): in place, lower, row-major; info = first bad pivot + 1;
 // Dinv receives the inverses of the 64 x 64 diagonal factors (ceil(n/64) * 64 * 64);

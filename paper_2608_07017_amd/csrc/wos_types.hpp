@@ -60,6 +60,7 @@ struct WalkerParams {
   T inv_N;
   int regen_T;     // refill a wavefront's pool of prepared walks when this many slots are free
   int block_override;  // workgroup size chosen by the caller (0: by occupancy)
+  int global_tally;    // tallies by atomics to the toolbox in HBM (rows too large for LDS)
   const int* item_order;  // blockIdx -> item (longest expected work first)
   int direct_store;
   int acc_fixed;   // tally accumulators: 0 FP64, 1 64-bit fixed point

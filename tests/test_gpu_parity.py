@@ -136,6 +136,72 @@ def test_other_domains_fp64(name):
     _compare_f64(dom, sites, bn, 400, 1e-4, 17)
 
 
+# ------------------------------------------------ tallies straight to HBM
+
+
+@pytest.mark.parametrize("case", ["disk", "ragged", "cubeball"])
+def test_hbm_tally_mode_fp64(case):
+    """The walker mode that adds every tally into the toolbox in device memory
+    (used when a site's rows do not fit in LDS), forced on small cases: the
+    same walks, so exit counts exact and the matrices to rounding."""
+    if case == "disk":
+        c = W.config("disk64")
+        _compare_f64(c["domain"], c["sites"][:40], c["bnodes"], 500, c["eps"], c["seed"], tally_in_hbm=True)
+    elif case == "ragged":
+        dom = W.unit_disk()
+        sites = W.sample_sites(dom, 37, 5, 1e-3)
+        _compare_f64(dom, sites, W.circle_nodes(19), 333, 1e-3, 42, walks_per_item=100, tally_in_hbm=True)
+    else:
+        dom = W.cube_minus_ball()
+        bn = np.concatenate([W.cube_face_nodes(4), W.fibonacci_sphere(30, dom["center"], dom["radius"])])
+        sites = W.sample_sites(dom, 23, 11, 1e-3)
+        _compare_f64(dom, sites, bn, 300, 1e-4, 17, tally_in_hbm=True)
+
+
+def test_hbm_tally_fp32_matches_lds_tally():
+    """FP32 walker: the two tally modes run the same walks; exit counts equal,
+    the matrices equal to FP32 summation rounding."""
+    dom = W.unit_square()
+    sites = W.sample_sites(dom, 96, 21, 1e-3)
+    bn = W.square_nodes(16)
+    g1 = _export_all(_gpu_tb(dom, sites, bn, 3000, 1e-4, 5, precision="f32", volume_samples=1 << 14))
+    g2 = _export_all(_gpu_tb(dom, sites, bn, 3000, 1e-4, 5, precision="f32", volume_samples=1 << 14,
+                             tally_in_hbm=True))
+    assert np.array_equal(g1["Hcount"], g2["Hcount"])
+    for key in ("A", "B", "K"):
+        mass = np.abs(g1[key]).sum(axis=-1, keepdims=True)
+        assert np.all(np.abs(g1[key] - g2[key]) <= 1e-5 * mass), key
+
+
+def test_rows_beyond_lds_fp64_sampled():
+    """7000 sites in FP64: a site's rows of A and B need 168 000 bytes, more
+    than the 160 KiB of LDS, so the walker tallies into device memory.
+    Sampled rows against the oracle's walks of those sites."""
+    dom = W.unit_square()
+    n = 7000
+    sites = W.sample_sites(dom, n, 31, 1e-3)
+    bn = W.square_nodes(16)
+    walks, eps, seed = 40, 1e-3, 8
+    tb = _gpu_tb(dom, sites, bn, walks, eps, seed, precision="f64", volume_samples=1 << 12)
+    rows = np.array([0, 1, 2999, n // 2, n - 2, n - 1])
+    A = _np(tb.export("A")[rows])
+    B = _np(tb.export("B")[:, rows])
+    K = _np(tb.export("K")[:, rows])
+    Hc = _np(tb.export("Hcount")[rows]).astype(np.int64)
+    steps = 0
+    for r, i in enumerate(rows):
+        ev = site_events(dom, sites[i], int(i), np.arange(walks), eps, seed)
+        a, b, h, kk = bin_site(ev, sites, bn)
+        steps += int(ev.nsteps.sum())
+        assert np.array_equal(Hc[r], h.astype(np.int64))
+        sc = np.abs(a).max() / walks
+        assert np.allclose(A[r], a / walks, rtol=1e-10, atol=1e-12 * sc)
+        for d in range(2):
+            assert np.allclose(B[d, r], b[d] / walks, rtol=1e-10, atol=1e-12 * sc)
+            assert np.allclose(K[d, r], kk[d] / walks, rtol=1e-10, atol=1e-12)
+    assert tb.info()["walks"] == n * walks
+
+
 # ---------------------------------------------------------- FP32 walker
 
 
