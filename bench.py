@@ -93,6 +93,11 @@ def parse():
     ap.add_argument("--serve-rho", type=float, default=0.8)
     ap.add_argument("--serve-rcond", type=float, default=0.1)
     ap.add_argument("--serve-seed", type=int, default=7)
+    ap.add_argument("--serve-op-requests", type=int, default=20000,
+                    help="requests of each prepared-operator run")
+    ap.add_argument("--cubeball", action="store_true",
+                    help="also build the 3-D cube-minus-ball toolbox (32768 sites, 1e5 walks/site; about "
+                         "a minute) and solve the quasilinear problem on it by Picard")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy a MIB-sized device buffer 3 times (a known-size "
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -199,6 +204,85 @@ def serving(a, torch, W, P):
         out[prec] = {"saturation_solves_per_s": sat["solves_per_s"], "open_loop": dict(run(prec, nopen, rate), rho=a.serve_rho,
                                                                                      arrival_rate=rate)}
     out["mixed_vs_f64_saturation"] = out["mixed"]["saturation_solves_per_s"] / out["f64"]["saturation_solves_per_s"]
+
+    # the same requests against prepared solution operators (one per toolbox
+    # and problem), FP32 storage: queued requests on one operator are batched
+    print("serving: preparing operators", file=sys.stderr, flush=True)
+    ops, prep_ms, op_l2 = [], {}, {}
+    for tb, lam, pool in boxes:
+        row = []
+        for dev, uex in pool:
+            op = tb.operator(A=dev["A"], b=dev["b"], rcond=a.serve_rcond, storage="f32")
+            row.append(op)
+            prep_ms.setdefault(str(tb.n), []).append(op.info()["prep_ms"])
+            u, _ = op.apply(dev["f"], dev["g"])
+            op_l2.setdefault(str(tb.n), []).append(float(np.sqrt(np.sum(lam * (u.cpu().numpy() - uex) ** 2))))
+        ops.append(row)
+
+    def run_op(nreq, rate):
+        sv = P.Server(slots=a.serve_slots, max_batch=64)
+        picks = [(int(rng.integers(len(boxes))), int(rng.integers(a.serve_pool))) for _ in range(nreq)]
+        gaps = rng.exponential(1.0 / rate, nreq) if rate else np.zeros(nreq)
+        arrivals = np.cumsum(gaps)
+        tickets = []
+        t0 = time.perf_counter()
+        for (bi, pi), ta in zip(picks, arrivals):
+            while time.perf_counter() - t0 < ta:
+                pass
+            dev = boxes[bi][2][pi][0]
+            tickets.append(sv.submit_op(ops[bi][pi], dev["f"], dev["g"])[0])
+        times = [sv.poll(t)[1] for t in tickets]
+        sv.close()
+        first = min(t[0] for t in times)
+        last = max(t[2] for t in times)
+        lat = np.array([t[2] - t[0] for t in times]) * 1e3
+        return {"requests": nreq, "solves_per_s": nreq / (last - first), "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99))}
+
+    print("serving: operator saturation", file=sys.stderr, flush=True)
+    sat = run_op(a.serve_op_requests, 0.0)
+    print("serving: operator open loop", file=sys.stderr, flush=True)
+    rate = a.serve_rho * sat["solves_per_s"]
+    out["operator_f32"] = {"prep_ms": {k: float(np.mean(v)) for k, v in prep_ms.items()},
+                           "l2_error": {k: float(np.mean(v)) for k, v in op_l2.items()},
+                           "saturation_solves_per_s": sat["solves_per_s"],
+                           "open_loop": dict(run_op(a.serve_op_requests, rate), rho=a.serve_rho, arrival_rate=rate)}
+    return out
+
+
+def picard_cubeball(a, torch, W, P):
+    """The 3-D unit cube minus the ball of radius 0.3 (32768 sites, 8192
+    boundary nodes, 1e5 walks/site, eps 1e-5, FP32 tallies written straight to
+    HBM) and Picard for -div((1 + u^2) grad u) = f with a seeded manufactured
+    solution, Tikhonov steps in mixed precision and in FP64."""
+    cfg = W.config("cubeball32768")
+    x, z = cfg["sites"], cfg["bnodes"]
+    tb = P.Toolbox(cfg["domain"], x, z, cfg["walks"], cfg["eps"], seed=cfg["seed"], precision="f32", autotune=False)
+    tb.set_timing(True)
+    print("cubeball: build", file=sys.stderr, flush=True)
+    tb.build()
+    t = tb.timings()
+    inf = tb.info()
+    lam = tb.export("lambda").cpu().numpy()
+    ue, ge, le = W.smooth_field(2026, 3, terms=8, max_freq=2.0, scale=0.5)
+    u0, g0 = ue(x), ge(x)
+    f = -(1 + u0 ** 2) * le(x) - 2 * u0 * np.sum(g0 * g0, axis=1)
+    g = ue(z)
+    nrm = float(np.sqrt(np.sum(lam * u0 ** 2)))
+    out = {"workload": cfg["label"] + "; -div((1 + u^2) grad u) = f, Picard (3 steps), Tikhonov rcond 1e-2",
+           "walker_ms": t["walker_ms"], "walk_steps": inf["walk_steps"],
+           "walk_steps_per_s": inf["walk_steps"] / (t["walker_ms"] * 1e-3), "device_gib": inf["device_bytes"] / 2**30}
+    for prec in ("mixed", "f64"):
+        print("cubeball: picard", prec, file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, _, _, info = tb.solve(f, g, kind="quasilinear", rcond=1e-2, tol=1e-300, max_iter=3, solver="tikhonov",
+                                 precision=prec, refine_tol=1e-8)
+        torch.cuda.synchronize()
+        out[prec] = {"seconds": time.perf_counter() - t0,
+                     "rel_l2_error": float(np.sqrt(np.sum(lam * (u.cpu().numpy() - u0) ** 2))) / nrm}
+    out["mixed_vs_f64"] = out["f64"]["seconds"] / out["mixed"]["seconds"]
+    tb.free()
     return out
 
 
@@ -319,6 +403,8 @@ def main():
     if not a.no_newton:
         print("newton: ball4096", file=sys.stderr, flush=True)
         out["newton_ball4096"] = newton_ball(a, torch, W, P)
+    if a.cubeball:
+        out["picard_cubeball32768"] = picard_cubeball(a, torch, W, P)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_rows)
     print(json.dumps(out), flush=True)

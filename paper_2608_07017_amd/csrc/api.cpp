@@ -451,6 +451,11 @@ wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_
   const int64_t N = opts->walks_per_site;
   if (opts->walks_per_item > 0) {
     tb->walks_per_item = (int)std::min<int64_t>(opts->walks_per_item, N);
+  } else if (tb->global_tally) {
+    // tallies go to the toolbox in memory: split every site into items of
+    // a few walks per lane, dispatched site after site, so that the rows
+    // being written at any time are few and stay in the caches
+    tb->walks_per_item = (int)std::min<int64_t>(N, 4096);
   } else {
     const int bs = walker_block_size(lds);
     const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(160 * 1024 / std::max<size_t>(lds, 1), 2048 / bs));

@@ -3,16 +3,20 @@
 // equations of the solve path.
 //
 // Right-looking, panel width 64: the 64 x 64 diagonal block is factored by
-// one wavefront in LDS, which also inverts its factor (kept in Dinv, one
-// 64 x 64 block per panel); the panel below is then L21 = A21 L11^{-T}, an
-// MFMA GEMM with that inverse, and the trailing matrix is updated by the
-// MFMA GEMM (the full square; only its lower part is read later).  A
-// non-positive pivot is replaced by a tiny one and reported in `info`
-// (first failing column + 1), so a singular input never produces NaNs.
+// one wavefront in LDS (lane i updates row i; column j of the factor is
+// broadcast through its own LDS array for the rank-1 update), which also
+// inverts its factor (kept in Dinv, one 64 x 64 block per panel); the panel
+// below is then L21 = A21 L11^{-T}, an MFMA GEMM with that inverse, and the
+// trailing matrix is updated by the MFMA GEMM (the full square; only its
+// lower part is read later).  A non-positive pivot is replaced by a tiny one
+// and reported in `info` (first failing column + 1), so a singular input
+// never produces NaNs.
 //
 // The solves with the factor use its explicit inverse X = L^{-1}, built by
-// blocks from the diagonal inverses (two MFMA GEMMs per block row), so that
-// each solve (L L^T)^{-1} r = X^T (X r) is two matrix-vector products.
+// recursive halving, [L11 0; L21 L22]^{-1} = [X11 0; -X22 L21 X11 X22],
+// down to the diagonal inverses, so that most of its work is in large MFMA
+// GEMMs; each solve (L L^T)^{-1} r = X^T (X r) is then two matrix-vector
+// products.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,34 +40,38 @@ __device__ __forceinline__ double tiny_pivot<double>() { return 1e-300; }
 
 // Factor the diagonal block A[k0 .. k0+b)^2 in place (b <= NB) and write
 // the inverse of its factor to Dinv (NB x NB, row-major, zero above the
-// diagonal).  One wavefront; lane i owns row i.
+// diagonal).  One wavefront; lane i updates row i.  Column j of the factor
+// is copied to its own LDS array before the rank-1 update, so the update's
+// loads never wait on its stores.
 template <typename T>
 __global__ __launch_bounds__(64) void potrf_diag_kernel(T* __restrict__ A, int lda, int k0, int b,
                                                          T* __restrict__ Dinv, int* __restrict__ info) {
   __shared__ T s[NB][NB + 1];
+  __shared__ T col[NB];
   const int lane = threadIdx.x;
   for (int e = lane; e < NB * NB; e += 64) {
     const int i = e / NB, j = e % NB;
     s[i][j] = (i < b && j < b) ? A[(size_t)(k0 + i) * lda + k0 + j] : (i == j ? T(1) : T(0));
   }
   __syncthreads();
-  for (int j = 0; j < b; ++j) {
+  int bad = 0;
+  for (int j = 0; j < NB; ++j) {
     T d = s[j][j];
     if (!(d > T(0))) {
-      if (lane == 0 && *info == 0) *info = k0 + j + 1;
+      if (bad == 0 && j < b) bad = j + 1;
       d = tiny_pivot<T>();
     }
     d = dev_sqrt(d);
+    const T lij = lane > j ? s[lane][j] / d : (lane == j ? d : T(0));
+    col[lane] = lij;
     __syncthreads();
-    if (lane == j) s[j][j] = d;
-    if (lane > j && lane < b) s[lane][j] /= d;
-    __syncthreads();
-    if (lane > j && lane < b) {
-      const T lij = s[lane][j];
-      for (int c = j + 1; c <= lane; ++c) s[lane][c] -= lij * s[c][j];
-    }
+    s[lane][j] = lij;
+    // rank-1 update of row `lane` right of column j, up to the diagonal
+#pragma unroll 8
+    for (int c = j + 1; c <= lane; ++c) s[lane][c] -= lij * col[c];
     __syncthreads();
   }
+  if (lane == 0 && bad && *info == 0) *info = k0 + bad;
   // inverse of the lower factor, one column per lane kept in registers
   // (forward substitution with the factor's rows read from LDS)
   T xc[NB];
@@ -128,8 +136,8 @@ hipError_t potrf(T* A, int n, int lda, T* Dinv, T* work, int* info, hipStream_t 
 }
 
 // X = L^{-1} (lower, zeros above the diagonal) from the factor and the
-// inverses of its diagonal blocks: block row i is X_ii = Dinv_i and
-// X[i, 0:i] = -Dinv_i (L[i, 0:i] X[0:i, 0:i]), two MFMA GEMMs per block row.
+// inverses of its diagonal blocks, by recursive halving at multiples of NB:
+// X[h:, :h] = -X[h:, h:] (L[h:, :h] X[:h, :h]).
 template <typename T>
 __global__ void place_diag_inverse_kernel(const T* __restrict__ Dinv, int n, T* __restrict__ X, int ldx) {
   const int kb = blockIdx.x, k0 = kb * NB;
@@ -140,25 +148,42 @@ __global__ void place_diag_inverse_kernel(const T* __restrict__ Dinv, int n, T* 
 }
 
 template <typename T>
+hipError_t trtri_rec(const T* L, int lda, int n0, int n1, T* X, int ldx, T* work, hipStream_t st) {
+  const int nb = (n1 - n0 + NB - 1) / NB;
+  if (nb <= 1) return hipSuccess;  // diagonal block: placed beforehand
+  const int h = n0 + (nb / 2) * NB;
+  hipError_t e = trtri_rec<T>(L, lda, n0, h, X, ldx, work, st);
+  if (e != hipSuccess) return e;
+  e = trtri_rec<T>(L, lda, h, n1, X, ldx, work, st);
+  if (e != hipSuccess) return e;
+  const int r = n1 - h, c = h - n0;
+  // work (r x c) = L[h:n1, n0:h] X[n0:h, n0:h]
+  e = gemm_t<T>(false, false, r, c, c, T(1), L + (size_t)h * lda + n0, lda, X + (size_t)n0 * ldx + n0, ldx, T(0),
+                work, c, st);
+  if (e != hipSuccess) return e;
+  // X[h:n1, n0:h] = -X[h:n1, h:n1] work
+  return gemm_t<T>(false, false, r, c, r, T(-1), X + (size_t)h * ldx + h, ldx, work, c, T(0),
+                   X + (size_t)h * ldx + n0, ldx, st);
+}
+
+template <typename T>
 hipError_t trtri(const T* L, int n, int lda, const T* Dinv, T* X, int ldx, T* work, hipStream_t st) {
   hipError_t e = hipMemsetAsync(X, 0, sizeof(T) * (size_t)n * ldx, st);
   if (e != hipSuccess) return e;
   const int nb = (n + NB - 1) / NB;
   hipLaunchKernelGGL(place_diag_inverse_kernel<T>, dim3(nb), dim3(256), 0, st, Dinv, n, X, ldx);
-  for (int kb = 1; kb < nb; ++kb) {
-    const int k0 = kb * NB, b = min(NB, n - k0);
-    // work (b x k0) = L[k0.., 0:k0] X[0:k0, 0:k0]
-    e = gemm_t<T>(false, false, b, k0, k0, T(1), L + (size_t)k0 * lda, lda, X, ldx, T(0), work, k0, st);
-    if (e != hipSuccess) return e;
-    // X[k0.., 0:k0] = -Dinv_k work
-    e = gemm_t<T>(false, false, b, k0, b, T(-1), Dinv + (size_t)kb * NB * NB, NB, work, k0, T(0),
-                  X + (size_t)k0 * ldx, ldx, st);
-    if (e != hipSuccess) return e;
-  }
+  e = trtri_rec<T>(L, lda, 0, n, X, ldx, work, st);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
 }  // namespace
+
+size_t chol_work_elems(int n) {
+  const int nb = (n + NB - 1) / NB;
+  const size_t h = (size_t)(nb / 2) * NB;
+  return std::max<size_t>((size_t)n * NB, h * ((size_t)n - std::min<size_t>(h, n)));
+}
 
 hipError_t cholesky_f64(double* A, int n, int lda, double* Dinv, double* work, int* info, hipStream_t st) {
   return potrf<double>(A, n, lda, Dinv, work, info, st);

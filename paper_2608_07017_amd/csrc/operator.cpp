@@ -121,7 +121,7 @@ wos_status prepare(wos_operator* op, const wos_toolbox* tb, const wos_coeffs* co
   OTRY(t.get(&Y, (size_t)m * m));
   OTRY(t.get(&V, (size_t)m * np));
   OTRY(t.get(&Dinv, (size_t)((m + 63) / 64) * 64 * 64));
-  OTRY(t.get(&work, (size_t)m * 64));
+  OTRY(t.get(&work, chol_work_elems(m)));
   OTRY(t.get(&regv, 1));
   OTRY(t.get(&info, 2));
   OTRY(t.get(&U64, (size_t)op->rows * np));

@@ -216,7 +216,7 @@ wos_status ensure_tik(wos_toolbox* tb, SolveWork& w, bool mixed) {
   const size_t dblocks = ((m + 63) / 64) * 64 * 64;
   if (!w.blk) {
     if ((s = walloc(w, &w.D64, dblocks)) != WOS_OK) return s;
-    if ((s = walloc(w, &w.P64, m * 64)) != WOS_OK) return s;
+    if ((s = walloc(w, &w.P64, chol_work_elems(m))) != WOS_OK) return s;
     if ((s = walloc(w, &w.blk, 2 * (d + 1) * std::max<size_t>(n, 1))) != WOS_OK) return s;
     if ((s = walloc(w, &w.regv, 2)) != WOS_OK) return s;
     if ((s = walloc(w, &w.info, 2)) != WOS_OK) return s;
@@ -228,7 +228,7 @@ wos_status ensure_tik(wos_toolbox* tb, SolveWork& w, bool mixed) {
     if ((s = walloc(w, &w.v32, m)) != WOS_OK) return s;
     if ((s = walloc(w, &w.D32, dblocks)) != WOS_OK) return s;
     if ((s = walloc(w, &w.L0_32, m * m)) != WOS_OK) return s;
-    if ((s = walloc(w, &w.P32, m * 64)) != WOS_OK) return s;
+    if ((s = walloc(w, &w.P32, chol_work_elems(m))) != WOS_OK) return s;
   }
   return WOS_OK;
 }

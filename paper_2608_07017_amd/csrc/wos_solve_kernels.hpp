@@ -50,10 +50,12 @@ hipError_t mfma_gemm_f64_b32(bool ta, bool tb, int M, int N, int K, double alpha
 
 // ---- Cholesky (chol.hip): in place, lower, row-major; info = first bad pivot + 1;
 // Dinv receives the inverses of the 64 x 64 diagonal factors (ceil(n/64) * 64 * 64);
-// work holds one panel (n x 64)
+// work holds chol_work_elems(n) elements (one panel, and the largest
+// off-diagonal block of the triangular inverse)
+size_t chol_work_elems(int n);
 hipError_t cholesky_f64(double* A, int n, int lda, double* Dinv, double* work, int* info, hipStream_t st);
 hipError_t cholesky_f32(float* A, int n, int lda, float* Dinv, float* work, int* info, hipStream_t st);
-// X (n x n, ld n) = L^{-1}, lower with zeros above; work holds 64 x n
+// X (n x n, ld n) = L^{-1}, lower with zeros above; work as for the factorisation
 hipError_t tri_inverse_f64(const double* L, int n, int lda, const double* Dinv, double* X, double* work,
                            hipStream_t st);
 hipError_t tri_inverse_f32(const float* L, int n, int lda, const float* Dinv, float* X, float* work,

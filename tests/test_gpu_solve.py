@@ -255,6 +255,26 @@ def test_tikhonov_on_fp32_toolbox_matches_oracle(square_f32_tb, precision):
 
 
 @pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_tikhonov_many_panels_matches_oracle(precision):
+    """1100 sites: the Cholesky factorisation runs over 18 panels of 64 (the
+    last one ragged) and the triangular inverse recurses five levels."""
+    dom = W.unit_square()
+    sites = W.sample_sites(dom, 1100, 9, 1e-3)
+    tb, mats = _build(dom, sites, W.square_nodes(32), 400, 1e-3, precision="f32")
+    lam = mats["lambda"]
+    A, b, c = _tik_problem(sites, len(sites), 2)
+    f = np.sin(np.pi * sites[:, 0]) * (1 + sites[:, 1])
+    g = tb.bnodes[:, 0] ** 2 - tb.bnodes[:, 1] ** 2
+    ref = OL.solve_linear(mats, lam, f, g, Acoef=A, bcoef=b, ccoef=c, rcond=1e-2, solver="tikhonov")
+    u, gu, q, info = tb.solve(f, g, kind="linear", A=A, b=b, c=c, rcond=1e-2, solver="tikhonov",
+                              precision=precision, refine_tol=1e-13, max_refine=30)
+    torch.cuda.synchronize()
+    _say("many panels", precision, info)
+    assert info["fallback"] == 0
+    assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < (1e-9 if precision == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
 def test_newton_tikhonov_matches_oracle(square_f32_tb, precision):
     tb, mats = square_f32_tb
     lam = mats["lambda"]
