@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="square1024")
+    ap.add_argument("--walks", type=int, default=0, help="override the workload's walks per site (profiling runs)")
+    ap.add_argument("--no-autotune", action="store_true", help="workgroup size by occupancy, no timing pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true", help="skip the served-solve stream")
@@ -331,9 +333,12 @@ def main():
     import paper_2608_07017_amd as P
 
     cfg = W.config(a.workload)
+    if a.walks:
+        cfg["walks"] = a.walks
+        cfg["label"] = cfg["label"] + " (walks/site overridden: %d)" % a.walks
     prec = cfg["precision"]
     tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], cfg["walks"], cfg["eps"], seed=cfg["seed"],
-                   precision=prec)
+                   precision=prec, autotune=not a.no_autotune)
     bn = cfg["bnodes"]
     g = torch.tensor(bn[:, 0] ** 2 - bn[:, 1] ** 2, dtype=torch.float64, device="cuda")
     zero = torch.zeros(len(cfg["sites"]), dtype=torch.float64, device="cuda")

@@ -9,8 +9,11 @@
 // fixed point (2^-32 units, integer adds, so the sums do not depend on the
 // order of the atomics): on gfx950 both are several times faster than FP32
 // LDS atomics, which the tally rate would otherwise be bound by.  The
-// workgroup size (256 / 512 / 1024) is the smallest that fills a CU with
-// waves given the LDS each site's rows take.
+// workgroup size (256 / 448 / 512 / 1024) is chosen by occupancy, or timed
+// on the first build.  When a site's rows do not fit in LDS (or the caller
+// asks for it) the kernel adds every tally, pre-scaled by 1/N, straight
+// into the toolbox with device atomics instead (`kAccGlobal`); the walks
+// are the same.
 //
 // Lanes run walks back to back, so the long tail of walk lengths does not
 // idle a wavefront.  The loop advances in supersteps of four chain steps.
