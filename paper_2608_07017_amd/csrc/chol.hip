@@ -2,15 +2,15 @@
 // the triangular solves with L, in FP32 or FP64, for the regularised normal
 // equations of the solve path.
 //
-// Right-looking, panel width 64: the 64 x 64 diagonal block is factored by
-// one wavefront in LDS (lane i updates row i; column j of the factor is
-// broadcast through its own LDS array for the rank-1 update), which also
-// inverts its factor (kept in Dinv, one 64 x 64 block per panel); the panel
-// below is then L21 = A21 L11^{-T}, an MFMA GEMM with that inverse, and the
-// trailing matrix is updated by the MFMA GEMM (the full square; only its
-// lower part is read later).  A non-positive pivot is replaced by a tiny one
-// and reported in `info` (first failing column + 1), so a singular input
-// never produces NaNs.
+// Right-looking, panel width 64: the 64 x 64 diagonal block is factored in
+// LDS by four wavefronts (column j of the factor is broadcast through its
+// own LDS array for the rank-1 update, which the wavefronts split by
+// columns), and one of them inverts the factor (kept in Dinv, one 64 x 64
+// block per panel); the panel below is then L21 = A21 L11^{-T}, an MFMA
+// GEMM with that inverse, and the trailing matrix is updated by the MFMA
+// GEMM (the full square; only its lower part is read later).  A
+// non-positive pivot is replaced by a tiny one and reported in `info`
+// (first failing column + 1), so a singular input never produces NaNs.
 //
 // The solves with the factor use its explicit inverse X = L^{-1}, built by
 // recursive halving, [L11 0; L21 L22]^{-1} = [X11 0; -X22 L21 X11 X22],
@@ -40,51 +40,58 @@ __device__ __forceinline__ double tiny_pivot<double>() { return 1e-300; }
 
 // Factor the diagonal block A[k0 .. k0+b)^2 in place (b <= NB) and write
 // the inverse of its factor to Dinv (NB x NB, row-major, zero above the
-// diagonal).  One wavefront; lane i updates row i.  Column j of the factor
-// is copied to its own LDS array before the rank-1 update, so the update's
-// loads never wait on its stores.
+// diagonal).  Four wavefronts: for column j, wavefront 0 scales the column
+// into its own LDS array, then lane l of wavefront w updates row l at the
+// columns c = j+1+w, j+5+w, ... up to the diagonal (independent LDS
+// read-modify-writes).  Wavefront 0 then inverts the factor, one column per
+// lane in registers.
 template <typename T>
-__global__ __launch_bounds__(64) void potrf_diag_kernel(T* __restrict__ A, int lda, int k0, int b,
-                                                         T* __restrict__ Dinv, int* __restrict__ info) {
+__global__ __launch_bounds__(256) void potrf_diag_kernel(T* __restrict__ A, int lda, int k0, int b,
+                                                          T* __restrict__ Dinv, int* __restrict__ info) {
   __shared__ T s[NB][NB + 1];
   __shared__ T col[NB];
-  const int lane = threadIdx.x;
-  for (int e = lane; e < NB * NB; e += 64) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < NB * NB; e += 256) {
     const int i = e / NB, j = e % NB;
     s[i][j] = (i < b && j < b) ? A[(size_t)(k0 + i) * lda + k0 + j] : (i == j ? T(1) : T(0));
   }
   __syncthreads();
   int bad = 0;
   for (int j = 0; j < NB; ++j) {
-    T d = s[j][j];
-    if (!(d > T(0))) {
-      if (bad == 0 && j < b) bad = j + 1;
-      d = tiny_pivot<T>();
+    if (wave == 0) {
+      T d = s[j][j];
+      if (!(d > T(0))) {
+        if (bad == 0 && j < b) bad = j + 1;
+        d = tiny_pivot<T>();
+      }
+      d = dev_sqrt(d);
+      const T lij = lane > j ? s[lane][j] / d : (lane == j ? d : T(0));
+      col[lane] = lij;
+      s[lane][j] = lij;
     }
-    d = dev_sqrt(d);
-    const T lij = lane > j ? s[lane][j] / d : (lane == j ? d : T(0));
-    col[lane] = lij;
     __syncthreads();
-    s[lane][j] = lij;
-    // rank-1 update of row `lane` right of column j, up to the diagonal
-#pragma unroll 8
-    for (int c = j + 1; c <= lane; ++c) s[lane][c] -= lij * col[c];
+    const T lij = col[lane];
+#pragma unroll 4
+    for (int c = j + 1 + wave; c <= lane; c += 4) s[lane][c] -= lij * col[c];
     __syncthreads();
   }
-  if (lane == 0 && bad && *info == 0) *info = k0 + bad;
-  // inverse of the lower factor, one column per lane kept in registers
-  // (forward substitution with the factor's rows read from LDS)
-  T xc[NB];
+  if (tid == 0 && bad && *info == 0) *info = k0 + bad;
+  if (wave == 0) {
+    // inverse of the lower factor, one column per lane kept in registers
+    // (forward substitution with the factor's rows read from LDS)
+    T xc[NB];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    T v = (i == lane) ? T(1) : T(0);
+    for (int i = 0; i < NB; ++i) {
+      T v = (i == lane) ? T(1) : T(0);
 #pragma unroll
-    for (int t = 0; t < i; ++t) v -= s[i][t] * xc[t];
-    xc[i] = (i >= lane && i < b && lane < b) ? v / s[i][i] : T(0);
+      for (int t = 0; t < i; ++t) v -= s[i][t] * xc[t];
+      xc[i] = (i >= lane && i < b && lane < b) ? v / s[i][i] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) Dinv[i * NB + lane] = xc[i];
   }
-#pragma unroll
-  for (int i = 0; i < NB; ++i) Dinv[i * NB + lane] = xc[i];
-  for (int e = lane; e < b * b; e += 64) {
+  for (int e = tid; e < b * b; e += 256) {
     const int i = e / b, j = e % b;
     A[(size_t)(k0 + i) * lda + k0 + j] = (j <= i) ? s[i][j] : T(0);
   }
@@ -116,7 +123,7 @@ hipError_t potrf(T* A, int n, int lda, T* Dinv, T* work, int* info, hipStream_t 
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int b = min(NB, n - k0);
     T* Dk = Dinv + (size_t)(k0 / NB) * NB * NB;
-    hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(1), dim3(64), 0, st, A, lda, k0, b, Dk, info);
+    hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(1), dim3(256), 0, st, A, lda, k0, b, Dk, info);
     const int rest = n - k0 - b;
     if (rest > 0) {
       // panel: L21 = A21 L11^{-T} = A21 Dk^T into `work` (rest x b), then

@@ -17,6 +17,11 @@ namespace wos {
 // wave-uniform, so its schedule stays in scalar registers.
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1) {
+  // An empty volatile statement that takes the key in scalar registers: it
+  // keeps the compiler from hoisting all twenty round keys out of the walk
+  // loop (they would be spilled to VGPR lanes and read back every round);
+  // each round key is then one scalar add.
+  asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     // one 32x32->64 product each (a single multiply-add instruction)
