@@ -41,6 +41,7 @@ struct wos_operator {
   int n = 0, m = 0, p = 0, d = 0;
   bool grad = false, f32 = false;
   int rows = 0, cols = 0;  // U: rows = (grad ? d + 1 : 1) n, cols = n + p
+  int ld = 0;              // row stride of U: cols rounded up to a multiple of 4
   void* U = nullptr;
   double reg = 0.0;
   size_t bytes = 0;
@@ -124,7 +125,8 @@ wos_status prepare(wos_operator* op, const wos_toolbox* tb, const wos_coeffs* co
   OTRY(t.get(&work, chol_work_elems(m)));
   OTRY(t.get(&regv, 1));
   OTRY(t.get(&info, 2));
-  OTRY(t.get(&U64, (size_t)op->rows * np));
+  const size_t ldu = (size_t)op->ld;
+  OTRY(t.get(&U64, (size_t)op->rows * ldu));
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
   OHIP(hipEventCreate(&e0));
@@ -138,6 +140,7 @@ wos_status prepare(wos_operator* op, const wos_toolbox* tb, const wos_coeffs* co
   } eg{e0, e1};
   OHIP(hipEventRecord(e0, st));
   OHIP(hipMemsetAsync(info, 0, 2 * sizeof(int), st));
+  OHIP(hipMemsetAsync(U64, 0, sizeof(double) * (size_t)op->rows * ldu, st));  // zero row padding
 
   // [Lambda | S] = L^T W [L | K;H]
   OHIP(launch_weight_rows_any(f64, false, tb->d_A, tb->d_B, tb->d_H, tb->d_K, tb->d_lambda, co->A, co->b, co->c, n, m,
@@ -160,14 +163,14 @@ wos_status prepare(wos_operator* op, const wos_toolbox* tb, const wos_coeffs* co
   // U = [B; A] V + [0 | K; H]: gradient rows first, then the rows of u
   const int grad_rows = op->grad ? d * n : 0;
   if (op->grad) {
-    OHIP(gemm_tb_left(f64, false, d * n, (int)np, m, 1.0, tb->d_B, m, V, (int)np, 0.0, U64, (int)np, st));
-    OHIP(launch_add_block(U64 + n, d * n, p, (int)np, f64, tb->d_K, st));
+    OHIP(gemm_tb_left(f64, false, d * n, (int)np, m, 1.0, tb->d_B, m, V, (int)np, 0.0, U64, (int)ldu, st));
+    OHIP(launch_add_block(U64 + n, d * n, p, (int)ldu, f64, tb->d_K, st));
   }
-  double* Uu = U64 + (size_t)grad_rows * np;
-  OHIP(gemm_tb_left(f64, false, n, (int)np, m, 1.0, tb->d_A, m, V, (int)np, 0.0, Uu, (int)np, st));
-  OHIP(launch_add_block(Uu + n, n, p, (int)np, f64, tb->d_H, st));
+  double* Uu = U64 + (size_t)grad_rows * ldu;
+  OHIP(gemm_tb_left(f64, false, n, (int)np, m, 1.0, tb->d_A, m, V, (int)np, 0.0, Uu, (int)ldu, st));
+  OHIP(launch_add_block(Uu + n, n, p, (int)ldu, f64, tb->d_H, st));
 
-  const size_t count = (size_t)op->rows * np;
+  const size_t count = (size_t)op->rows * ldu;
   if (op->f32) {
     float* U32 = nullptr;
     OHIP(hipMalloc((void**)&U32, count * sizeof(float)));
@@ -225,6 +228,7 @@ wos_status wos_operator_create(wos_toolbox* tb, const wos_coeffs* co, const wos_
   op->f32 = storage == WOS_F32;
   op->rows = (int)rows;
   op->cols = tb->n + tb->p;
+  op->ld = (op->cols + 3) / 4 * 4;
   const wos_status s = prepare(op, tb, co, static_cast<hipStream_t>(stream));
   if (s != WOS_OK) {
     if (op->U) (void)hipFree(op->U);
@@ -247,10 +251,11 @@ wos_status wos_operator_apply(const wos_operator* op, int32_t nrhs, const double
   if (any_grad && !op->grad) return ofail(WOS_EINVAL, "gradient requested from an operator without want_grad");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int np = op->cols;
+  const size_t ldu = (size_t)op->ld;
   const int grad_rows = any_grad ? op->d * op->n : 0;
   const size_t skip = (op->grad && !any_grad) ? (size_t)op->d * op->n : 0;  // start of the rows of u
-  const void* U = op->f32 ? static_cast<const void*>(static_cast<const float*>(op->U) + skip * np)
-                          : static_cast<const void*>(static_cast<const double*>(op->U) + skip * np);
+  const void* U = op->f32 ? static_cast<const void*>(static_cast<const float*>(op->U) + skip * ldu)
+                          : static_cast<const void*>(static_cast<const double*>(op->U) + skip * ldu);
   const int rows = op->n + grad_rows;
   for (int r0 = 0; r0 < nrhs; r0 += kOpBatch) {
     const int nb = std::min(kOpBatch, nrhs - r0);
@@ -262,7 +267,7 @@ wos_status wos_operator_apply(const wos_operator* op, int32_t nrhs, const double
       bt.u[b] = u[r0 + b];
       bt.gu[b] = (any_grad && grad_u) ? grad_u[r0 + b] : nullptr;
     }
-    OHIP(launch_op_apply(op->f32, U, rows, np, np, op->n, grad_rows, nb, bt, st));
+    OHIP(launch_op_apply(op->f32, U, rows, np, (int)ldu, op->n, grad_rows, nb, bt, st));
   }
   return WOS_OK;
 }
