@@ -290,6 +290,45 @@ def test_square1024_fp32_full_size_sampled_rows():
     assert np.sqrt(np.mean((hg - exact) ** 2)) < 0.01
 
 
+def _export_rows(tb, rows):
+    """The sampled rows of every toolbox array, without copying whole
+    matrices to the host (the 3-D configurations hold gigabytes)."""
+    r = torch.as_tensor(rows, device="cuda")
+    out = {k: _np(tb.export(k).index_select(0, r)) for k in ("A", "H", "Hcount")}
+    out.update({k: _np(tb.export(k).index_select(1, r)) for k in ("B", "K")})
+    out["Hcount"] = out["Hcount"].astype(np.int64)
+    return out
+
+
+@pytest.mark.parametrize("name,rows,walks", [
+    ("lshape4096", [0, 1777, 4095], None),
+    ("ball4096", [0, 2048, 4095], None),
+    # the 3-D cube minus ball at its full site and node counts (tallies
+    # written straight to HBM); 500 walks per site keep the oracle's
+    # brute-force binning of the sampled rows short
+    ("cubeball32768", [0, 32767], 500),
+])
+def test_full_size_fp32_sampled_rows(name, rows, walks):
+    """The other configurations at their full sizes, in the launch shape the
+    benchmark uses; the oracle recomputes sampled rows from the same
+    streams, compared statistically as for the square."""
+    c = W.config(name)
+    N = walks or c["walks"]
+    tb = _gpu_tb(c["domain"], c["sites"], c["bnodes"], N, c["eps"], c["seed"], precision="f32")
+    info = tb.info()
+    assert info["walks"] == len(c["sites"]) * N
+    rows = np.array(rows)
+    g = _export_rows(tb, rows)
+    assert np.all(g["Hcount"].sum(axis=1) == N)
+    bn = c["bnodes"]
+    gb = bn[:, 0] ** 2 - bn[:, 1] ** 2          # harmonic in 2-D and 3-D
+    _say("oracle rows", name, rows.tolist())
+    ref = _oracle_rows_with_se(c["domain"], c["sites"], bn, N, c["eps"], c["seed"], rows, gb)
+    _check_f32_rows(g, ref, np.arange(len(rows)), gb)
+    del tb
+    torch.cuda.empty_cache()
+
+
 # ----------------------------------------------------------------- apply
 
 
