@@ -15,6 +15,7 @@
 // FP64, r = 0..3 (both checked on gfx950).
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <type_traits>
 
 #include "wos_solve_kernels.hpp"
@@ -136,10 +137,150 @@ __global__ __launch_bounds__(256) void mfma_gemm_kernel(int M, int N, int K, T a
       }
 }
 
+// C (M x N) = alpha A^T B + beta C for A (K x M) and B (K x N), both stored
+// K-major: the products of the solve (L^T R, Lambda^T Lambda, ...) are all
+// of this shape, and both slabs of a K step are then plain row segments.
+// A 256-thread workgroup owns a (32 WM) x (32 WN) tile of C, each wavefront
+// a (16 WM) x (16 WN) quarter of WM x WN MFMA blocks.  K advances in slabs
+// of 16: the next slab is loaded from global memory into registers while
+// the current one is multiplied out of LDS (two LDS buffers, one barrier
+// per slab), with 16-byte loads where rows are aligned.
+// PER consecutive elements from a 16-byte aligned address, in 16-byte loads
+template <typename T, typename S, int PER>
+__device__ __forceinline__ void load16(const S* src, T (&r)[PER]) {
+  if constexpr (std::is_same<S, float>::value) {
+#pragma unroll
+    for (int c = 0; c < PER / 4; ++c) {
+      const float4 q = reinterpret_cast<const float4*>(src)[c];
+      r[4 * c] = (T)q.x;
+      r[4 * c + 1] = (T)q.y;
+      r[4 * c + 2] = (T)q.z;
+      r[4 * c + 3] = (T)q.w;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < PER / 2; ++c) {
+      const double2 q = reinterpret_cast<const double2*>(src)[c];
+      r[2 * c] = (T)q.x;
+      r[2 * c + 1] = (T)q.y;
+    }
+  }
+}
+
+template <typename T, typename SA, typename SB, int WM, int WN>
+__global__ __launch_bounds__(256) void mfma_gemm_tn_kernel(int M, int N, int K, T alpha, const SA* __restrict__ A,
+                                                           int lda, const SB* __restrict__ B, int ldb, T beta,
+                                                           T* __restrict__ C, int ldc, int vec_a, int vec_b) {
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  constexpr int PA = BM * GK / 256, PB = BN * GK / 256;  // elements per thread per slab
+  __shared__ T sA[2][GK][BM + GPAD];
+  __shared__ T sB[2][GK][BN + GPAD];
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 16 * WM, wn = (wave & 1) * 16 * WN;
+  const int li = lane & 15, lk = lane >> 4;
+  // slab element ownership: thread t loads row k = t / 16 of the slab, the
+  // PA (PB) consecutive columns starting at (t % 16) * PA
+  const int lrow = tid >> 4, lcol_a = (tid & 15) * PA, lcol_b = (tid & 15) * PB;
+
+  T acc[WM][WN][4];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[a][b][r] = T(0);
+
+  T ra[PA], rb[PB];
+  auto load_slab = [&](int k0) {
+    const int gk = k0 + lrow;
+    {
+      const int gi = m0 + lcol_a;
+      const SA* src = A + (size_t)gk * lda + gi;
+      if (vec_a && gk < K && gi + PA <= M) {
+        load16<T, SA, PA>(src, ra);
+      } else {
+#pragma unroll
+        for (int e = 0; e < PA; ++e) ra[e] = (gk < K && gi + e < M) ? (T)src[e] : T(0);
+      }
+    }
+    {
+      const int gj = n0 + lcol_b;
+      const SB* src = B + (size_t)gk * ldb + gj;
+      if (vec_b && gk < K && gj + PB <= N) {
+        load16<T, SB, PB>(src, rb);
+      } else {
+#pragma unroll
+        for (int e = 0; e < PB; ++e) rb[e] = (gk < K && gj + e < N) ? (T)src[e] : T(0);
+      }
+    }
+  };
+  auto store_slab = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < PA; ++e) sA[buf][lrow][lcol_a + e] = ra[e];
+#pragma unroll
+    for (int e = 0; e < PB; ++e) sB[buf][lrow][lcol_b + e] = rb[e];
+  };
+
+  load_slab(0);
+  store_slab(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    const bool more = k0 + GK < K;
+    if (more) load_slab(k0 + GK);  // in flight during this slab's MFMAs
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 4) {
+      T av[WM], bv[WN];
+#pragma unroll
+      for (int a = 0; a < WM; ++a) av[a] = sA[buf][ks + lk][wm + 16 * a + li];
+#pragma unroll
+      for (int b = 0; b < WN; ++b) bv[b] = sB[buf][ks + lk][wn + 16 * b + li];
+#pragma unroll
+      for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b) mfma_16x16x4<T>(av[a], bv[b], acc[a][b]);
+    }
+    if (more) store_slab(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = m0 + wm + 16 * a + (std::is_same<T, double>::value ? lk + 4 * r : 4 * lk + r);
+        const int gj = n0 + wn + 16 * b + li;
+        if (gi < M && gj < N) {
+          T* dst = C + (size_t)gi * ldc + gj;
+          *dst = alpha * acc[a][b][r] + (beta == T(0) ? T(0) : beta * *dst);
+        }
+      }
+}
+
+// every row of a K-major operand starts on a 16-byte boundary
+template <typename S>
+bool rows_aligned(const S* X, int ld) {
+  return ((uintptr_t)X % 16) == 0 && ((size_t)ld * sizeof(S)) % 16 == 0;
+}
+
 template <typename T, typename SA, typename SB>
 hipError_t gemm_dispatch(bool ta, bool tb, int M, int N, int K, T alpha, const SA* A, int lda, const SB* B, int ldb,
                          T beta, T* C, int ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (ta && !tb) {
+    // FP32: 128 x 128 tiles; FP64: 64 x 64 (the accumulators and two LDS
+    // buffers of a larger FP64 tile would not fit)
+    constexpr int W = std::is_same<T, float>::value ? 4 : 2;
+    const dim3 grid2((N + 32 * W - 1) / (32 * W), (M + 32 * W - 1) / (32 * W));
+    const int va = rows_aligned(A, lda) ? 1 : 0, vb = rows_aligned(B, ldb) ? 1 : 0;
+    hipLaunchKernelGGL((mfma_gemm_tn_kernel<T, SA, SB, W, W>), grid2, dim3(256), 0, st, M, N, K, alpha, A, lda, B,
+                       ldb, beta, C, ldc, va, vb);
+    return hipGetLastError();
+  }
   const dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
   if (!ta && !tb)
     hipLaunchKernelGGL((mfma_gemm_kernel<T, SA, SB, false, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B,
