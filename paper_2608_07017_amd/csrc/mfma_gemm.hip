@@ -137,14 +137,13 @@ __global__ __launch_bounds__(256) void mfma_gemm_kernel(int M, int N, int K, T a
       }
 }
 
-// C (M x N) = alpha A^T B + beta C for A (K x M) and B (K x N), both stored
-// K-major: the products of the solve (L^T R, Lambda^T Lambda, ...) are all
-// of this shape, and both slabs of a K step are then plain row segments.
-// A 256-thread workgroup owns a (32 WM) x (32 WN) tile of C, each wavefront
-// a (16 WM) x (16 WN) quarter of WM x WN MFMA blocks.  K advances in slabs
-// of 16: the next slab is loaded from global memory into registers while
-// the current one is multiplied out of LDS (two LDS buffers, one barrier
-// per slab), with 16-byte loads where rows are aligned.
+// The pipelined kernel for larger products: a 256-thread workgroup owns a
+// (32 WM) x (32 WN) tile of C, each wavefront a (16 WM) x (16 WN) quarter
+// of WM x WN MFMA blocks.  K advances in slabs of 16: the next slab is
+// loaded from global memory into registers while the current one is
+// multiplied out of LDS (two LDS buffers, one barrier per slab), with
+// 16-byte loads wherever the stored rows are aligned, along M or N for a
+// K-major operand and along K otherwise.
 // PER consecutive elements from a 16-byte aligned address, in 16-byte loads
 template <typename T, typename S, int PER>
 __device__ __forceinline__ void load16(const S* src, T (&r)[PER]) {
@@ -167,10 +166,63 @@ __device__ __forceinline__ void load16(const S* src, T (&r)[PER]) {
   }
 }
 
-template <typename T, typename SA, typename SB, int WM, int WN>
-__global__ __launch_bounds__(256) void mfma_gemm_tn_kernel(int M, int N, int K, T alpha, const SA* __restrict__ A,
-                                                           int lda, const SB* __restrict__ B, int ldb, T beta,
-                                                           T* __restrict__ C, int ldc, int vec_a, int vec_b) {
+// One operand's share of a K slab: P consecutive elements of one stored
+// row.  K-major storage (op(A) = A^T with A K x M, or op(B) = B with B
+// K x N): thread t takes slab row k = t / (BX / P) and the P columns from
+// (t % (BX / P)) P.  Row-major storage along K (op(A) = A, op(B) = B^T):
+// thread t takes stored row x = t / (GK / P) and the P values of k from
+// (t % (GK / P)) P.  Out-of-range elements are zero.
+template <typename T, typename S, int BX, int P, bool KMAJOR>
+struct SlabPart {
+  int x, k;  // stored-row / column offsets of this thread within the slab
+  __device__ __forceinline__ SlabPart(int tid) {
+    if (KMAJOR) {
+      k = tid / (BX / P);
+      x = (tid % (BX / P)) * P;
+    } else {
+      x = tid / (GK / P);
+      k = (tid % (GK / P)) * P;
+    }
+  }
+  // load from X (ld) for the tile at x0 (extent X_ext) and slab k0 (of K)
+  __device__ __forceinline__ void load(const S* X, int ld, int x0, int xext, int k0, int K, int vec, T (&r)[P]) const {
+    if (KMAJOR) {
+      const int gk = k0 + k, gx = x0 + x;
+      const S* src = X + (size_t)gk * ld + gx;
+      if (vec && gk < K && gx + P <= xext) {
+        load16<T, S, P>(src, r);
+      } else {
+#pragma unroll
+        for (int e = 0; e < P; ++e) r[e] = (gk < K && gx + e < xext) ? (T)src[e] : T(0);
+      }
+    } else {
+      const int gx = x0 + x, gk = k0 + k;
+      const S* src = X + (size_t)gx * ld + gk;
+      if (vec && gx < xext && gk + P <= K) {
+        load16<T, S, P>(src, r);
+      } else {
+#pragma unroll
+        for (int e = 0; e < P; ++e) r[e] = (gx < xext && gk + e < K) ? (T)src[e] : T(0);
+      }
+    }
+  }
+  // store into the slab buffer s[k][x]
+  template <int LD>
+  __device__ __forceinline__ void store(T (*sl)[LD], const T (&r)[P]) const {
+    if (KMAJOR) {
+#pragma unroll
+      for (int e = 0; e < P; ++e) sl[k][x + e] = r[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < P; ++e) sl[k + e][x] = r[e];
+    }
+  }
+};
+
+template <typename T, typename SA, typename SB, bool TA, bool TB, int WM, int WN>
+__global__ __launch_bounds__(256) void mfma_gemm_pipe_kernel(int M, int N, int K, T alpha, const SA* __restrict__ A,
+                                                             int lda, const SB* __restrict__ B, int ldb, T beta,
+                                                             T* __restrict__ C, int ldc, int vec_a, int vec_b) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
   constexpr int PA = BM * GK / 256, PB = BN * GK / 256;  // elements per thread per slab
   __shared__ T sA[2][GK][BM + GPAD];
@@ -180,9 +232,8 @@ __global__ __launch_bounds__(256) void mfma_gemm_tn_kernel(int M, int N, int K, 
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 16 * WM, wn = (wave & 1) * 16 * WN;
   const int li = lane & 15, lk = lane >> 4;
-  // slab element ownership: thread t loads row k = t / 16 of the slab, the
-  // PA (PB) consecutive columns starting at (t % 16) * PA
-  const int lrow = tid >> 4, lcol_a = (tid & 15) * PA, lcol_b = (tid & 15) * PB;
+  const SlabPart<T, SA, BM, PA, TA> pa(tid);   // op(A) K-major iff A is stored transposed
+  const SlabPart<T, SB, BN, PB, !TB> pb(tid);  // op(B) K-major iff B is stored as is
 
   T acc[WM][WN][4];
 #pragma unroll
@@ -193,43 +244,18 @@ __global__ __launch_bounds__(256) void mfma_gemm_tn_kernel(int M, int N, int K, 
       for (int r = 0; r < 4; ++r) acc[a][b][r] = T(0);
 
   T ra[PA], rb[PB];
-  auto load_slab = [&](int k0) {
-    const int gk = k0 + lrow;
-    {
-      const int gi = m0 + lcol_a;
-      const SA* src = A + (size_t)gk * lda + gi;
-      if (vec_a && gk < K && gi + PA <= M) {
-        load16<T, SA, PA>(src, ra);
-      } else {
-#pragma unroll
-        for (int e = 0; e < PA; ++e) ra[e] = (gk < K && gi + e < M) ? (T)src[e] : T(0);
-      }
-    }
-    {
-      const int gj = n0 + lcol_b;
-      const SB* src = B + (size_t)gk * ldb + gj;
-      if (vec_b && gk < K && gj + PB <= N) {
-        load16<T, SB, PB>(src, rb);
-      } else {
-#pragma unroll
-        for (int e = 0; e < PB; ++e) rb[e] = (gk < K && gj + e < N) ? (T)src[e] : T(0);
-      }
-    }
-  };
-  auto store_slab = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < PA; ++e) sA[buf][lrow][lcol_a + e] = ra[e];
-#pragma unroll
-    for (int e = 0; e < PB; ++e) sB[buf][lrow][lcol_b + e] = rb[e];
-  };
-
-  load_slab(0);
-  store_slab(0);
+  pa.load(A, lda, m0, M, 0, K, vec_a, ra);
+  pb.load(B, ldb, n0, N, 0, K, vec_b, rb);
+  pa.store(sA[0], ra);
+  pb.store(sB[0], rb);
   __syncthreads();
   int buf = 0;
   for (int k0 = 0; k0 < K; k0 += GK) {
     const bool more = k0 + GK < K;
-    if (more) load_slab(k0 + GK);  // in flight during this slab's MFMAs
+    if (more) {  // in flight during this slab's MFMAs
+      pa.load(A, lda, m0, M, k0 + GK, K, vec_a, ra);
+      pb.load(B, ldb, n0, N, k0 + GK, K, vec_b, rb);
+    }
 #pragma unroll
     for (int ks = 0; ks < GK; ks += 4) {
       T av[WM], bv[WN];
@@ -242,7 +268,10 @@ __global__ __launch_bounds__(256) void mfma_gemm_tn_kernel(int M, int N, int K, 
 #pragma unroll
         for (int b = 0; b < WN; ++b) mfma_16x16x4<T>(av[a], bv[b], acc[a][b]);
     }
-    if (more) store_slab(buf ^ 1);
+    if (more) {
+      pa.store(sA[buf ^ 1], ra);
+      pb.store(sB[buf ^ 1], rb);
+    }
     __syncthreads();
     buf ^= 1;
   }
@@ -261,7 +290,7 @@ __global__ __launch_bounds__(256) void mfma_gemm_tn_kernel(int M, int N, int K, 
       }
 }
 
-// every row of a K-major operand starts on a 16-byte boundary
+// every stored row of an operand starts on a 16-byte boundary
 template <typename S>
 bool rows_aligned(const S* X, int ld) {
   return ((uintptr_t)X % 16) == 0 && ((size_t)ld * sizeof(S)) % 16 == 0;
@@ -271,14 +300,26 @@ template <typename T, typename SA, typename SB>
 hipError_t gemm_dispatch(bool ta, bool tb, int M, int N, int K, T alpha, const SA* A, int lda, const SB* B, int ldb,
                          T beta, T* C, int ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  if (ta && !tb) {
-    // FP32: 128 x 128 tiles; FP64: 64 x 64 (the accumulators and two LDS
-    // buffers of a larger FP64 tile would not fit)
-    constexpr int W = std::is_same<T, float>::value ? 4 : 2;
+  // large products: the pipelined kernel, FP32 128 x 128 tiles, FP64
+  // 64 x 64 (the accumulators and two LDS buffers of a larger FP64 tile
+  // would not fit); products with a side of 64 or less (Cholesky panels,
+  // the first levels of the triangular inverse) keep the 64 x 64 kernel
+  constexpr int W = std::is_same<T, float>::value ? 4 : 2;
+  if (M > 64 && N > 64 && K >= GK) {
     const dim3 grid2((N + 32 * W - 1) / (32 * W), (M + 32 * W - 1) / (32 * W));
     const int va = rows_aligned(A, lda) ? 1 : 0, vb = rows_aligned(B, ldb) ? 1 : 0;
-    hipLaunchKernelGGL((mfma_gemm_tn_kernel<T, SA, SB, W, W>), grid2, dim3(256), 0, st, M, N, K, alpha, A, lda, B,
-                       ldb, beta, C, ldc, va, vb);
+#define WOS_PIPE(TA_, TB_)                                                                                   \
+  hipLaunchKernelGGL((mfma_gemm_pipe_kernel<T, SA, SB, TA_, TB_, W, W>), grid2, dim3(256), 0, st, M, N, K, alpha, A, \
+                     lda, B, ldb, beta, C, ldc, va, vb)
+    if (ta && !tb)
+      WOS_PIPE(true, false);
+    else if (!ta && !tb)
+      WOS_PIPE(false, false);
+    else if (!ta && tb)
+      WOS_PIPE(false, true);
+    else
+      WOS_PIPE(true, true);
+#undef WOS_PIPE
     return hipGetLastError();
   }
   const dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
