@@ -3,10 +3,9 @@
 // equations of the solve path.
 //
 // Right-looking, panel width 64: the 64 x 64 diagonal block is factored in
-// LDS by four wavefronts (column j of the factor is broadcast through its
-// own LDS array for the rank-1 update, which the wavefronts split by
-// columns), and one of them inverts the factor (kept in Dinv, one 64 x 64
-// block per panel); the panel below is then L21 = A21 L11^{-T}, an MFMA
+// LDS by four wavefronts (itself blocked by panels of eight columns: one
+// wavefront factors a panel, all four apply its rank-8 update), and one of
+// them inverts the factor (kept in Dinv, one 64 x 64 block per panel); the panel below is then L21 = A21 L11^{-T}, an MFMA
 // GEMM with that inverse, and the trailing matrix is updated by the MFMA
 // GEMM (the full square; only its lower part is read later).  A
 // non-positive pivot is replaced by a tiny one and reported in `info`
@@ -40,16 +39,13 @@ __device__ __forceinline__ double tiny_pivot<double>() { return 1e-300; }
 
 // Factor the diagonal block A[k0 .. k0+b)^2 in place (b <= NB) and write
 // the inverse of its factor to Dinv (NB x NB, row-major, zero above the
-// diagonal).  Four wavefronts: for column j, wavefront 0 scales the column
-// into its own LDS array, then lane l of wavefront w updates row l at the
-// columns c = j+1+w, j+5+w, ... up to the diagonal (independent LDS
-// read-modify-writes).  Wavefront 0 then inverts the factor, one column per
-// lane in registers.
+// diagonal).  Four wavefronts, lane l owning row l: the factor is blocked
+// by panels of eight columns (see below), then wavefront 0 inverts it, one
+// column per lane in registers.
 template <typename T>
 __global__ __launch_bounds__(256) void potrf_diag_kernel(T* __restrict__ A, int lda, int k0, int b,
                                                           T* __restrict__ Dinv, int* __restrict__ info) {
   __shared__ T s[NB][NB + 1];
-  __shared__ T col[NB];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   for (int e = tid; e < NB * NB; e += 256) {
@@ -57,23 +53,40 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(T* __restrict__ A, int 
     s[i][j] = (i < b && j < b) ? A[(size_t)(k0 + i) * lda + k0 + j] : (i == j ? T(1) : T(0));
   }
   __syncthreads();
+  // blocked by panels of PW columns: wavefront 0 factors a panel (rows in
+  // lanes, columns in order, the panel's own updates inside the
+  // wavefront), then all wavefronts apply its rank-PW update to the
+  // columns right of it; two barriers per panel
+  constexpr int PW = 8;
   int bad = 0;
-  for (int j = 0; j < NB; ++j) {
+  for (int jb = 0; jb < NB; jb += PW) {
     if (wave == 0) {
-      T d = s[j][j];
-      if (!(d > T(0))) {
-        if (bad == 0 && j < b) bad = j + 1;
-        d = tiny_pivot<T>();
+      for (int t = 0; t < PW; ++t) {
+        const int j = jb + t;
+        T d = s[j][j];
+        if (!(d > T(0))) {
+          if (bad == 0 && j < b) bad = j + 1;
+          d = tiny_pivot<T>();
+        }
+        d = dev_sqrt(d);
+        const T lij = lane > j ? s[lane][j] / d : (lane == j ? d : T(0));
+        s[lane][j] = lij;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int c = j + 1; c < jb + PW; ++c)
+          if (lane >= c) s[lane][c] -= lij * s[c][j];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       }
-      d = dev_sqrt(d);
-      const T lij = lane > j ? s[lane][j] / d : (lane == j ? d : T(0));
-      col[lane] = lij;
-      s[lane][j] = lij;
     }
     __syncthreads();
-    const T lij = col[lane];
-#pragma unroll 4
-    for (int c = j + 1 + wave; c <= lane; c += 4) s[lane][c] -= lij * col[c];
+    T li[PW];
+#pragma unroll
+    for (int t = 0; t < PW; ++t) li[t] = s[lane][jb + t];
+    for (int c = jb + PW + wave; c <= lane; c += 4) {
+      T v = s[lane][c];
+#pragma unroll
+      for (int t = 0; t < PW; ++t) v -= li[t] * s[c][jb + t];
+      s[lane][c] = v;
+    }
     __syncthreads();
   }
   if (tid == 0 && bad && *info == 0) *info = k0 + bad;
