@@ -2,20 +2,19 @@
 // the triangular solves with L, in FP32 or FP64, for the regularised normal
 // equations of the solve path.
 //
-// Right-looking, panel width 64: the 64 x 64 diagonal block is factored in
-// LDS by four wavefronts (itself blocked by panels of eight columns: one
-// wavefront factors a panel, all four apply its rank-8 update), and one of
-// them inverts the factor (kept in Dinv, one 64 x 64 block per panel); the panel below is then L21 = A21 L11^{-T}, an MFMA
-// GEMM with that inverse, and the trailing matrix is updated by the MFMA
-// GEMM (the full square; only its lower part is read later).  A
-// non-positive pivot is replaced by a tiny one and reported in `info`
-// (first failing column + 1), so a singular input never produces NaNs.
+// Recursive: the block is halved at a multiple of 64 rows, the leading half
+// is factored and inverted, the off-diagonal block of the factor and the
+// Schur complement update are MFMA GEMMs (inner dimension half the block),
+// the trailing half is factored and inverted, and the off-diagonal block of
+// the inverse is two more GEMMs; 64 x 64 diagonal blocks are factored in
+// LDS by one workgroup of four wavefronts (itself blocked by panels of eight
+// columns: one wavefront factors a panel, all four apply its rank-8 update)
+// and inverted by one of them.  A non-positive pivot is replaced by a tiny
+// one and reported in `info` (first failing column + 1), so a singular
+// input never produces NaNs.
 //
-// The solves with the factor use its explicit inverse X = L^{-1}, built by
-// recursive halving, [L11 0; L21 L22]^{-1} = [X11 0; -X22 L21 X11 X22],
-// down to the diagonal inverses, so that most of its work is in large MFMA
-// GEMMs; each solve (L L^T)^{-1} r = X^T (X r) is then two matrix-vector
-// products.
+// The solves with the factor use its explicit inverse X = L^{-1}: each
+// solve (L L^T)^{-1} r = X^T (X r) is then two matrix-vector products.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,13 +37,13 @@ template <>
 __device__ __forceinline__ double tiny_pivot<double>() { return 1e-300; }
 
 // Factor the diagonal block A[k0 .. k0+b)^2 in place (b <= NB) and write
-// the inverse of its factor to Dinv (NB x NB, row-major, zero above the
+// the inverse of its factor to the same block of X (zero above the
 // diagonal).  Four wavefronts, lane l owning row l: the factor is blocked
 // by panels of eight columns (see below), then wavefront 0 inverts it, one
 // column per lane in registers.
 template <typename T>
 __global__ __launch_bounds__(256) void potrf_diag_kernel(T* __restrict__ A, int lda, int k0, int b,
-                                                          T* __restrict__ Dinv, int* __restrict__ info) {
+                                                          T* __restrict__ X, int ldx, int* __restrict__ info) {
   __shared__ T s[NB][NB + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -102,7 +101,8 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(T* __restrict__ A, int 
       xc[i] = (i >= lane && i < b && lane < b) ? v / s[i][i] : T(0);
     }
 #pragma unroll
-    for (int i = 0; i < NB; ++i) Dinv[i * NB + lane] = xc[i];
+    for (int i = 0; i < NB; ++i)
+      if (i < b && lane < b) X[(size_t)(k0 + i) * ldx + k0 + lane] = xc[i];
   }
   for (int e = tid; e < b * b; e += 256) {
     const int i = e / b, j = e % b;
@@ -124,75 +124,61 @@ hipError_t gemm_t<float>(bool ta, bool tb, int M, int N, int K, float alpha, con
   return mfma_gemm_f32(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st);
 }
 
+// dst (rows x cols, ldd) = src (rows x cols, lds)
 template <typename T>
-__global__ void copy_panel_kernel(const T* __restrict__ P, int rows, int b, T* __restrict__ A, int lda) {
-  const size_t total = (size_t)rows * b;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x)
-    A[(e / b) * lda + e % b] = P[e];
-}
-
-template <typename T>
-hipError_t potrf(T* A, int n, int lda, T* Dinv, T* work, int* info, hipStream_t st) {
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int b = min(NB, n - k0);
-    T* Dk = Dinv + (size_t)(k0 / NB) * NB * NB;
-    hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(1), dim3(256), 0, st, A, lda, k0, b, Dk, info);
-    const int rest = n - k0 - b;
-    if (rest > 0) {
-      // panel: L21 = A21 L11^{-T} = A21 Dk^T into `work` (rest x b), then
-      // the trailing update A22 -= L21 L21^T, then L21 back into A
-      T* A21 = A + (size_t)(k0 + b) * lda + k0;
-      hipError_t e = gemm_t<T>(false, true, rest, b, b, T(1), A21, lda, Dk, NB, T(0), work, b, st);
-      if (e != hipSuccess) return e;
-      T* A22 = A + (size_t)(k0 + b) * lda + k0 + b;
-      e = gemm_t<T>(false, true, rest, rest, b, T(-1), work, b, work, b, T(1), A22, lda, st);
-      if (e != hipSuccess) return e;
-      const size_t tot = (size_t)rest * b;
-      hipLaunchKernelGGL(copy_panel_kernel<T>, dim3((unsigned)std::min<size_t>((tot + 255) / 256, 4096)), dim3(256),
-                         0, st, work, rest, b, A21, lda);
-    }
-  }
-  return hipGetLastError();
-}
-
-// X = L^{-1} (lower, zeros above the diagonal) from the factor and the
-// inverses of its diagonal blocks, by recursive halving at multiples of NB:
-// X[h:, :h] = -X[h:, h:] (L[h:, :h] X[:h, :h]).
-template <typename T>
-__global__ void place_diag_inverse_kernel(const T* __restrict__ Dinv, int n, T* __restrict__ X, int ldx) {
-  const int kb = blockIdx.x, k0 = kb * NB;
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    const int i = e / NB, j = e % NB;
-    if (k0 + i < n && k0 + j < n) X[(size_t)(k0 + i) * ldx + k0 + j] = Dinv[(size_t)kb * NB * NB + e];
+__global__ void copy_block_kernel(const T* __restrict__ src, int lds, T* __restrict__ dst, int ldd, int rows,
+                                  int cols) {
+  const size_t total = (size_t)rows * cols;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = e / cols, j = e % cols;
+    dst[i * ldd + j] = src[i * lds + j];
   }
 }
 
+// Factor A[n0:n1, n0:n1] = L L^T in place and write X = L^{-1} to the same
+// block of X, by recursive halving at a multiple of NB:
+//   L11, X11 of the leading half;  L21 = A21 X11^T;  A22 -= L21 L21^T;
+//   L22, X22 of the trailing half;  X21 = -X22 (L21 X11);
+// the leaves are the one-workgroup diagonal kernel.  Apart from the leaves
+// every step is a GEMM whose inner dimension is half the block, so the
+// factorisation and the inverse run mostly as large MFMA products.
 template <typename T>
-hipError_t trtri_rec(const T* L, int lda, int n0, int n1, T* X, int ldx, T* work, hipStream_t st) {
+hipError_t chol_inv_rec(T* A, int lda, int n0, int n1, T* X, int ldx, T* work, int* info, hipStream_t st) {
   const int nb = (n1 - n0 + NB - 1) / NB;
-  if (nb <= 1) return hipSuccess;  // diagonal block: placed beforehand
+  if (nb <= 1) {
+    hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(1), dim3(256), 0, st, A, lda, n0, n1 - n0, X, ldx, info);
+    return hipGetLastError();
+  }
   const int h = n0 + (nb / 2) * NB;
-  hipError_t e = trtri_rec<T>(L, lda, n0, h, X, ldx, work, st);
-  if (e != hipSuccess) return e;
-  e = trtri_rec<T>(L, lda, h, n1, X, ldx, work, st);
-  if (e != hipSuccess) return e;
   const int r = n1 - h, c = h - n0;
-  // work (r x c) = L[h:n1, n0:h] X[n0:h, n0:h]
-  e = gemm_t<T>(false, false, r, c, c, T(1), L + (size_t)h * lda + n0, lda, X + (size_t)n0 * ldx + n0, ldx, T(0),
-                work, c, st);
+  T* A21 = A + (size_t)h * lda + n0;
+  T* A22 = A + (size_t)h * lda + h;
+  T* X11 = X + (size_t)n0 * ldx + n0;
+  T* X21 = X + (size_t)h * ldx + n0;
+  T* X22 = X + (size_t)h * ldx + h;
+  hipError_t e = chol_inv_rec<T>(A, lda, n0, h, X, ldx, work, info, st);
   if (e != hipSuccess) return e;
-  // X[h:n1, n0:h] = -X[h:n1, h:n1] work
-  return gemm_t<T>(false, false, r, c, r, T(-1), X + (size_t)h * ldx + h, ldx, work, c, T(0),
-                   X + (size_t)h * ldx + n0, ldx, st);
+  // L21 = A21 X11^T, kept in the (still unused) X21 block
+  e = gemm_t<T>(false, true, r, c, c, T(1), A21, lda, X11, ldx, T(0), X21, ldx, st);
+  if (e != hipSuccess) return e;
+  e = gemm_t<T>(false, true, r, r, c, T(-1), X21, ldx, X21, ldx, T(1), A22, lda, st);
+  if (e != hipSuccess) return e;
+  const size_t tot = (size_t)r * c;
+  hipLaunchKernelGGL(copy_block_kernel<T>, dim3((unsigned)std::min<size_t>((tot + 255) / 256, 4096)), dim3(256), 0,
+                     st, X21, ldx, A21, lda, r, c);
+  e = chol_inv_rec<T>(A, lda, h, n1, X, ldx, work, info, st);
+  if (e != hipSuccess) return e;
+  // X21 = -X22 (L21 X11)
+  e = gemm_t<T>(false, false, r, c, c, T(1), A21, lda, X11, ldx, T(0), work, c, st);
+  if (e != hipSuccess) return e;
+  return gemm_t<T>(false, false, r, c, r, T(-1), X22, ldx, work, c, T(0), X21, ldx, st);
 }
 
 template <typename T>
-hipError_t trtri(const T* L, int n, int lda, const T* Dinv, T* X, int ldx, T* work, hipStream_t st) {
-  hipError_t e = hipMemsetAsync(X, 0, sizeof(T) * (size_t)n * ldx, st);
+hipError_t chol_inv(T* A, int n, int lda, T* X, int ldx, T* work, int* info, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(X, 0, sizeof(T) * (size_t)n * ldx, st);  // the blocks above the diagonal
   if (e != hipSuccess) return e;
-  const int nb = (n + NB - 1) / NB;
-  hipLaunchKernelGGL(place_diag_inverse_kernel<T>, dim3(nb), dim3(256), 0, st, Dinv, n, X, ldx);
-  e = trtri_rec<T>(L, lda, 0, n, X, ldx, work, st);
+  e = chol_inv_rec<T>(A, lda, 0, n, X, ldx, work, info, st);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
@@ -205,19 +191,11 @@ size_t chol_work_elems(int n) {
   return std::max<size_t>((size_t)n * NB, h * ((size_t)n - std::min<size_t>(h, n)));
 }
 
-hipError_t cholesky_f64(double* A, int n, int lda, double* Dinv, double* work, int* info, hipStream_t st) {
-  return potrf<double>(A, n, lda, Dinv, work, info, st);
+hipError_t cholesky_inverse_f64(double* A, int n, int lda, double* X, double* work, int* info, hipStream_t st) {
+  return chol_inv<double>(A, n, lda, X, n, work, info, st);
 }
-hipError_t cholesky_f32(float* A, int n, int lda, float* Dinv, float* work, int* info, hipStream_t st) {
-  return potrf<float>(A, n, lda, Dinv, work, info, st);
-}
-hipError_t tri_inverse_f64(const double* L, int n, int lda, const double* Dinv, double* X, double* work,
-                           hipStream_t st) {
-  return trtri<double>(L, n, lda, Dinv, X, n, work, st);
-}
-hipError_t tri_inverse_f32(const float* L, int n, int lda, const float* Dinv, float* X, float* work,
-                           hipStream_t st) {
-  return trtri<float>(L, n, lda, Dinv, X, n, work, st);
+hipError_t cholesky_inverse_f32(float* A, int n, int lda, float* X, float* work, int* info, hipStream_t st) {
+  return chol_inv<float>(A, n, lda, X, n, work, info, st);
 }
 
 }  // namespace wos

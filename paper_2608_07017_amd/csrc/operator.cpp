@@ -112,7 +112,7 @@ wos_status prepare(wos_operator* op, const wos_toolbox* tb, const wos_coeffs* co
   const size_t mp = (size_t)m + p, np = (size_t)n + p;
   const double rcond = co->rcond > 0 ? co->rcond : 1e-3;
   Temps t;
-  double *R, *LS, *N, *X, *T1, *Y, *V, *Dinv, *work, *regv, *U64;
+  double *R, *LS, *N, *X, *T1, *Y, *V, *work, *regv, *U64;
   int* info;
   OTRY(t.get(&R, (size_t)(d + 1) * n * mp));
   OTRY(t.get(&LS, (size_t)m * mp));
@@ -121,7 +121,6 @@ wos_status prepare(wos_operator* op, const wos_toolbox* tb, const wos_coeffs* co
   OTRY(t.get(&T1, (size_t)m * m));
   OTRY(t.get(&Y, (size_t)m * m));
   OTRY(t.get(&V, (size_t)m * np));
-  OTRY(t.get(&Dinv, (size_t)((m + 63) / 64) * 64 * 64));
   OTRY(t.get(&work, chol_work_elems(m)));
   OTRY(t.get(&regv, 1));
   OTRY(t.get(&info, 2));
@@ -151,8 +150,7 @@ wos_status prepare(wos_operator* op, const wos_toolbox* tb, const wos_coeffs* co
   OHIP(mfma_gemm_f64(true, false, m, m, m, 1.0, LS, (int)mp, LS, (int)mp, 0.0, N, m, st));
   OHIP(launch_reg_from_diag(true, N, m, m, rcond * rcond, regv, st));
   OHIP(launch_add_diag(true, N, m, m, regv, st));
-  OHIP(cholesky_f64(N, m, m, Dinv, work, info, st));
-  OHIP(tri_inverse_f64(N, m, m, Dinv, X, work, st));
+  OHIP(cholesky_inverse_f64(N, m, m, X, work, info, st));
   // Y = X^T (X Lambda^T)
   OHIP(mfma_gemm_f64(false, true, m, m, m, 1.0, X, m, LS, (int)mp, 0.0, T1, m, st));
   OHIP(mfma_gemm_f64(true, false, m, m, m, 1.0, X, m, T1, m, 0.0, Y, m, st));

@@ -78,7 +78,7 @@ size_t workspace_bytes(const wos_toolbox* tb) {
   size_t b = 8 * ((d + 1) * n * (m + p) + 3 * m * m + 2 * m * p + 2 * M * M + 3 * M + 10 * vlen + n * d * d + 2);
   b += 8 * (2 * (d + 1) * n + 2) + 8;
   b += 4 * ((d + 1) * n * m + 3 * m * m + m);
-  b += 12 * ((m + 63) / 64) * 64 * 64 + 12 * chol_work_elems((int)m);
+  b += 12 * chol_work_elems((int)m);
   return b;
 }
 

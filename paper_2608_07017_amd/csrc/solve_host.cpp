@@ -213,9 +213,7 @@ wos_status dev_dot(SolveWork& w, const double* dx, const double* dy, const doubl
 wos_status ensure_tik(wos_toolbox* tb, SolveWork& w, bool mixed) {
   const size_t n = tb->n, m = tb->m, d = tb->dim;
   wos_status s;
-  const size_t dblocks = ((m + 63) / 64) * 64 * 64;
   if (!w.blk) {
-    if ((s = walloc(w, &w.D64, dblocks)) != WOS_OK) return s;
     if ((s = walloc(w, &w.P64, chol_work_elems(m))) != WOS_OK) return s;
     if ((s = walloc(w, &w.blk, 2 * (d + 1) * std::max<size_t>(n, 1))) != WOS_OK) return s;
     if ((s = walloc(w, &w.regv, 2)) != WOS_OK) return s;
@@ -226,7 +224,6 @@ wos_status ensure_tik(wos_toolbox* tb, SolveWork& w, bool mixed) {
     if ((s = walloc(w, &w.Lam32, m * m)) != WOS_OK) return s;
     if ((s = walloc(w, &w.N32, m * m)) != WOS_OK) return s;
     if ((s = walloc(w, &w.v32, m)) != WOS_OK) return s;
-    if ((s = walloc(w, &w.D32, dblocks)) != WOS_OK) return s;
     if ((s = walloc(w, &w.L0_32, m * m)) != WOS_OK) return s;
     if ((s = walloc(w, &w.P32, chol_work_elems(m))) != WOS_OK) return s;
   }
@@ -291,8 +288,7 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     SHIP(mfma_gemm_f32(true, false, m, m, m, 1.0f, w.Lam32, m, w.Lam32, m, 0.0f, w.N32, m, st));
     SHIP(launch_reg_from_diag(false, w.N32, m, m, rcond * rcond, w.regv, st));
     SHIP(launch_add_diag(false, w.N32, m, m, w.regv, st));
-    SHIP(cholesky_f32(w.N32, m, m, w.D32, w.P32, w.info, st));
-    SHIP(tri_inverse_f32(w.N32, m, m, w.D32, w.Lam32, w.P32, st));  // X = L^{-1} over Lambda's storage
+    SHIP(cholesky_inverse_f32(w.N32, m, m, w.Lam32, w.P32, w.info, st));  // X = L^{-1} over Lambda's storage
     int hinfo = 0;
     SHIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
     SHIP(hipStreamSynchronize(st));
@@ -342,8 +338,7 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     SHIP(mfma_gemm_f64(true, false, m, m, m, 1.0, w.Lam, m, w.Lam, m, 0.0, w.Hess, m, st));
     SHIP(launch_reg_from_diag(true, w.Hess, m, m, rcond * rcond, w.regv, st));
     SHIP(launch_add_diag(true, w.Hess, m, m, w.regv, st));
-    SHIP(cholesky_f64(w.Hess, m, m, w.D64, w.P64, w.info, st));
-    SHIP(tri_inverse_f64(w.Hess, m, m, w.D64, w.Lam, w.P64, st));  // X = L^{-1} over Lambda's storage
+    SHIP(cholesky_inverse_f64(w.Hess, m, m, w.Lam, w.P64, w.info, st));  // X = L^{-1} over Lambda's storage
     SHIP(launch_gemv_n_ld(true, w.Lam, m, m, m, c, 1.0, 0.0, t, st));
     SHIP(launch_gemv_t_ld(true, w.Lam, m, m, m, t, 1.0, 0.0, q, st));
     int hinfo = 0;
@@ -372,8 +367,7 @@ wos_status sym_reg_solve(wos_toolbox* tb, SolveWork& w, bool mixed, double rcond
   if (mixed) {
     SHIP(launch_reg_from_diag(false, w.N32, m, m, rcond, w.regv, st));
     SHIP(launch_add_diag(false, w.N32, m, m, w.regv, st));
-    SHIP(cholesky_f32(w.N32, m, m, w.D32, w.P32, w.info, st));
-    SHIP(tri_inverse_f32(w.N32, m, m, w.D32, w.Lam32, w.P32, st));
+    SHIP(cholesky_inverse_f32(w.N32, m, m, w.Lam32, w.P32, w.info, st));
     SHIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
     SHIP(hipStreamSynchronize(st));
     if (hinfo != 0) return sfail(WOS_ENOTCONV, "FP32 factorisation failed at column %d", hinfo - 1);
@@ -399,8 +393,7 @@ wos_status sym_reg_solve(wos_toolbox* tb, SolveWork& w, bool mixed, double rcond
   } else {
     SHIP(launch_reg_from_diag(true, w.Hess, m, m, rcond, w.regv, st));
     SHIP(launch_add_diag(true, w.Hess, m, m, w.regv, st));
-    SHIP(cholesky_f64(w.Hess, m, m, w.D64, w.P64, w.info, st));
-    SHIP(tri_inverse_f64(w.Hess, m, m, w.D64, w.Lam, w.P64, st));
+    SHIP(cholesky_inverse_f64(w.Hess, m, m, w.Lam, w.P64, w.info, st));
     SHIP(launch_gemv_n_ld(true, w.Lam, m, m, m, rhs, 1.0, 0.0, t, st));
     SHIP(launch_gemv_t_ld(true, w.Lam, m, m, m, t, 1.0, 0.0, x, st));
     SHIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -511,7 +504,7 @@ namespace wos {
 
 void free_work(SolveWork& w) {
   void* ptrs[] = {w.R, w.Lam, w.Sig, w.Lam0, w.Sig0, w.Hess, w.G, w.V, w.E, w.rot, w.pq, w.vec, w.Ac, w.red,
-                  w.blk, w.regv, w.info, w.R32, w.Lam32, w.N32, w.v32, w.D64, w.D32, w.P64, w.P32, w.L0_32};
+                  w.blk, w.regv, w.info, w.R32, w.Lam32, w.N32, w.v32, w.P64, w.P32, w.L0_32};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   w = SolveWork();

@@ -56,9 +56,7 @@ struct SolveWork {
   float* Lam32 = nullptr;   // m x m
   float* N32 = nullptr;     // m x m normal matrix / its factor
   float* v32 = nullptr;     // m
-  double* D64 = nullptr;    // inverses of the 64 x 64 diagonal Cholesky factors
-  float* D32 = nullptr;
-  double* P64 = nullptr;    // one Cholesky panel, m x 64
+  double* P64 = nullptr;    // Cholesky work (chol_work_elems(m))
   float* P32 = nullptr;
   float* L0_32 = nullptr;   // Lambda_0 (A = I), FP32, for the mixed Newton route
   size_t bytes = 0;         // device memory held

@@ -48,18 +48,13 @@ hipError_t mfma_gemm_f64_a32(bool ta, bool tb, int M, int N, int K, double alpha
 hipError_t mfma_gemm_f64_b32(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
                              const float* B, int ldb, double beta, double* C, int ldc, hipStream_t st);
 
-// ---- Cholesky (chol.hip): in place, lower, row-major; info = first bad pivot + 1;
-// Dinv receives the inverses of the 64 x 64 diagonal factors (ceil(n/64) * 64 * 64);
-// work holds chol_work_elems(n) elements (one panel, and the largest
-// off-diagonal block of the triangular inverse)
+// ---- Cholesky (chol.hip): A (n x n, lda, row-major, lower part read) is
+// overwritten by its factor L (lower); X (n x n, ld n) receives L^{-1}
+// (zeros above the diagonal); info = first bad pivot + 1; work holds
+// chol_work_elems(n) elements
 size_t chol_work_elems(int n);
-hipError_t cholesky_f64(double* A, int n, int lda, double* Dinv, double* work, int* info, hipStream_t st);
-hipError_t cholesky_f32(float* A, int n, int lda, float* Dinv, float* work, int* info, hipStream_t st);
-// X (n x n, ld n) = L^{-1}, lower with zeros above; work as for the factorisation
-hipError_t tri_inverse_f64(const double* L, int n, int lda, const double* Dinv, double* X, double* work,
-                           hipStream_t st);
-hipError_t tri_inverse_f32(const float* L, int n, int lda, const float* Dinv, float* X, float* work,
-                           hipStream_t st);
+hipError_t cholesky_inverse_f64(double* A, int n, int lda, double* X, double* work, int* info, hipStream_t st);
+hipError_t cholesky_inverse_f32(float* A, int n, int lda, float* X, float* work, int* info, hipStream_t st);
 
 // ---- regularised solve and matrix-free operator (tikhonov.hip)
 hipError_t launch_weight_rows_any(bool f64_in, bool f32_out, const void* A, const void* B, const void* H,
