@@ -300,25 +300,34 @@ template <typename T, typename SA, typename SB>
 hipError_t gemm_dispatch(bool ta, bool tb, int M, int N, int K, T alpha, const SA* A, int lda, const SB* B, int ldb,
                          T beta, T* C, int ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  // large products: the pipelined kernel, FP32 128 x 128 tiles, FP64
+  // larger products: the pipelined kernel, FP32 128 x 128 tiles, FP64
   // 64 x 64 (the accumulators and two LDS buffers of a larger FP64 tile
-  // would not fit); products with a side of 64 or less (Cholesky panels,
-  // the first levels of the triangular inverse) keep the 64 x 64 kernel
-  constexpr int W = std::is_same<T, float>::value ? 4 : 2;
+  // would not fit); products with a side of 64 or less (the lowest level
+  // of the recursive Cholesky) keep the 64 x 64 kernel
   if (M > 64 && N > 64 && K >= GK) {
-    const dim3 grid2((N + 32 * W - 1) / (32 * W), (M + 32 * W - 1) / (32 * W));
     const int va = rows_aligned(A, lda) ? 1 : 0, vb = rows_aligned(B, ldb) ? 1 : 0;
-#define WOS_PIPE(TA_, TB_)                                                                                   \
-  hipLaunchKernelGGL((mfma_gemm_pipe_kernel<T, SA, SB, TA_, TB_, W, W>), grid2, dim3(256), 0, st, M, N, K, alpha, A, \
-                     lda, B, ldb, beta, C, ldc, va, vb)
-    if (ta && !tb)
-      WOS_PIPE(true, false);
-    else if (!ta && !tb)
-      WOS_PIPE(false, false);
-    else if (!ta && tb)
-      WOS_PIPE(false, true);
-    else
-      WOS_PIPE(true, true);
+    // FP32 products too small to give 256 tiles of 128 x 128 take 64 x 64
+    // tiles, four times as many workgroups
+    const bool wide = std::is_same<T, float>::value && (size_t)((M + 127) / 128) * ((N + 127) / 128) >= 256;
+#define WOS_PIPE(W_, TA_, TB_)                                                                                  \
+  hipLaunchKernelGGL((mfma_gemm_pipe_kernel<T, SA, SB, TA_, TB_, W_, W_>),                                      \
+                     dim3((N + 32 * W_ - 1) / (32 * W_), (M + 32 * W_ - 1) / (32 * W_)), dim3(256), 0, st, M, N, K, \
+                     alpha, A, lda, B, ldb, beta, C, ldc, va, vb)
+#define WOS_PIPE_W(TA_, TB_) \
+  if (wide)                  \
+    WOS_PIPE(4, TA_, TB_);   \
+  else                       \
+    WOS_PIPE(2, TA_, TB_)
+    if (ta && !tb) {
+      WOS_PIPE_W(true, false);
+    } else if (!ta && !tb) {
+      WOS_PIPE_W(false, false);
+    } else if (!ta && tb) {
+      WOS_PIPE_W(false, true);
+    } else {
+      WOS_PIPE_W(true, true);
+    }
+#undef WOS_PIPE_W
 #undef WOS_PIPE
     return hipGetLastError();
   }
