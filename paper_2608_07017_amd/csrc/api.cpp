@@ -594,7 +594,17 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
     V.gv = view<double>(tb->gv, tb->d_sites_f64);
     V.n = n;
     V.dim = d;
-    V.npoints = tb->opts.volume_samples;
+    // stratified points: tiles^d equal tiles of the bounding box, tiles the
+    // largest power of two with at least 64 points per tile, and per tile
+    // the largest power of two of points that fits the requested number
+    const int64_t want = tb->opts.volume_samples;
+    int ts = 0, ps = 0;
+    while (((int64_t)1 << (d * (ts + 1))) * 64 <= want) ++ts;
+    while (((int64_t)1 << (ps + 1 + d * ts)) <= want) ++ps;
+    V.tile_shift = ts;
+    V.point_shift = ps;
+    V.inv_tiles = 1.0 / (double)((int64_t)1 << ts);
+    V.npoints = (int64_t)1 << (ps + d * ts);
     V.nblocks = d == 2 ? (V.npoints + 1) / 2 : V.npoints;
     V.k0 = k0;
     V.k1 = k1;

@@ -1,12 +1,17 @@
 // Cell weights lambda_i = |W_i| / |D| by uniform points, and the small
 // element-wise finishing kernels of a build.
 //
-// The volume points come from Philox tag 1 (counter (q mod 2^32, q >> 32,
-// 0, 1) for block q; two points per block in d = 2, one in d = 3), each
-// coordinate lo + (hi - lo) * u.  Everything here is FP64 with one rounding
-// per operation (no fused multiply-add), so the inside test and the nearest
-// site are decided exactly as a plain double-precision evaluation would:
-// the per-site counts are integers and reproducible bit for bit.
+// The volume points are stratified over the bounding box: tiles^d equal
+// tiles receive per_tile points each (both powers of two), point p in tile
+// p / per_tile (row-major, last axis fastest), so the lanes of a
+// wavefront share a tile and mostly a grid cell, and its grid-record loads
+// coalesce.  The uniforms come from Philox tag 1 (counter (q mod 2^32,
+// q >> 32, 0, 1) for block q; two points per block in d = 2, one in d = 3);
+// coordinate a is lo + (hi - lo) * ((c_a + u_a) / tiles) for tile index c_a.
+// Everything here is FP64 with one rounding per operation (no fused
+// multiply-add), so the inside test and the nearest site are decided
+// exactly as a plain double-precision evaluation would: the per-site counts
+// are integers and reproducible bit for bit.
 #include <hip/hip_runtime.h>
 
 #include "wos_device.hpp"
@@ -154,20 +159,29 @@ __global__ __launch_bounds__(kVolBlock) void volume_kernel(VolumeParams P) {
     int4 rec[PER];
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
+      // tile coordinates of point p = q PER + t
+      const int64_t p = q * PER + t;
+      const int64_t tile = p >> P.point_shift;
+      const int64_t tmask = ((int64_t)1 << P.tile_shift) - 1;
+      double c[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) c[a] = (double)((tile >> (P.tile_shift * (D - 1 - a))) & tmask);
+      double u[D];
       if constexpr (D == 2) {
-        const double u0 = u01<double>(t == 0 ? w.x : w.z);
-        const double u1 = u01<double>(t == 0 ? w.y : w.w);
-        const double p0 = ext[0] * u0, p1 = ext[1] * u1;
-        x[t][0] = P.dom.lo[0] + p0;
-        x[t][1] = P.dom.lo[1] + p1;
+        u[0] = u01<double>(t == 0 ? w.x : w.z);
+        u[1] = u01<double>(t == 0 ? w.y : w.w);
       } else {
-        const double p0 = ext[0] * u01<double>(w.x), p1 = ext[1] * u01<double>(w.y),
-                     p2 = ext[2] * u01<double>(w.z);
-        x[t][0] = P.dom.lo[0] + p0;
-        x[t][1] = P.dom.lo[1] + p1;
-        x[t][2] = P.dom.lo[2] + p2;
+        u[0] = u01<double>(w.x);
+        u[1] = u01<double>(w.y);
+        u[2] = u01<double>(w.z);
       }
-      ok[t] = (q * PER + t < P.npoints) && inside_exact<D, KIND>(P, x[t]);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const double f = (c[a] + u[a]) * P.inv_tiles;  // both steps exact
+        const double pa = ext[a] * f;
+        x[t][a] = P.dom.lo[a] + pa;
+      }
+      ok[t] = (p < P.npoints) && inside_exact<D, KIND>(P, x[t]);
       rec[t] = ok[t] ? P.gv.rec[cell_exact<D>(P.gv, x[t])] : make_int4(0, 0, 0, 0);
     }
 #pragma unroll

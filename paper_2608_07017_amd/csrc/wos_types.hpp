@@ -78,8 +78,11 @@ struct VolumeParams {
   GridDev<double> gv;
   int n;
   int dim;
-  int64_t npoints;      // candidate points
+  int64_t npoints;      // candidate points: per_tile * tiles^dim
   int64_t nblocks;      // Philox blocks
+  int tile_shift;       // log2(tiles per axis of the bounding box)
+  int point_shift;      // log2(points per tile)
+  double inv_tiles;     // 1 / tiles
   uint32_t k0, k1;
   unsigned long long* counts;  // n
   unsigned long long* inside;  // 1

@@ -2,7 +2,7 @@
 import numpy as np
 
 import workloads as W
-from oracle.volume import cell_weights, cell_counts, volume_points
+from oracle.volume import cell_weights, cell_counts, volume_points, volume_layout
 from oracle.geometry import inside
 
 
@@ -73,8 +73,31 @@ def test_disk_rejection_fraction():
 
 def test_point_stream_is_in_bbox_and_off_lattice():
     pts = volume_points(W.l_shape(), 9, 100001)
-    assert pts.shape == (100001, 2)
+    T, K = volume_layout(2, 100001)
+    assert (T, K) == (32, 64) and pts.shape == (K * T * T, 2)
     assert np.all(np.abs(pts) < 1)
     assert not np.any(pts == 0.0)
     kept = inside(W.l_shape(), pts).mean()
     assert abs(kept - 0.75) < 0.01
+
+
+def test_points_are_stratified_by_tile():
+    """Every tile of the bounding box receives exactly K points, uniform in
+    it: tile counts are exact, and within-tile offsets have mean 1/2 and
+    variance 1/12 (the uniform law's) to sampling precision."""
+    for dom, n in ((W.unit_square(), 1 << 14), (W.unit_ball(), 1 << 15)):
+        d = dom["dim"]
+        T, K = volume_layout(d, n)
+        assert K >= 64 and K * T ** d <= n < 2 * K * T ** d
+        pts = volume_points(dom, 3, n)
+        lo = -np.ones(d) if dom["kind"] == "ball" else np.zeros(d)
+        ext = 2.0 * np.ones(d) if dom["kind"] == "ball" else np.ones(d)
+        rel = (pts - lo) / ext * T
+        cell = np.floor(rel).astype(np.int64)
+        lin = np.ravel_multi_index(tuple(cell.T), (T,) * d)
+        assert np.array_equal(np.bincount(lin, minlength=T ** d), np.full(T ** d, K))
+        off = rel - cell
+        assert np.allclose(off.mean(axis=0), 0.5, atol=5 / np.sqrt(12 * len(off)))
+        assert np.allclose(off.var(axis=0), 1 / 12, atol=5 * np.sqrt(1 / 180 / len(off)))
+        # consecutive points share a tile: the first K points are all in tile 0
+        assert np.all(lin[:K] == 0) and np.all(lin[K:2 * K] == 1)
