@@ -7,9 +7,9 @@
 // Schur complement update are MFMA GEMMs (inner dimension half the block),
 // the trailing half is factored and inverted, and the off-diagonal block of
 // the inverse is two more GEMMs; 64 x 64 diagonal blocks are factored in
-// LDS by one workgroup of four wavefronts (itself blocked by panels of eight
-// columns: one wavefront factors a panel, all four apply its rank-8 update)
-// and inverted by one of them.  A non-positive pivot is replaced by a tiny
+// LDS by one workgroup of four wavefronts (panels of 16 columns factored in
+// one wavefront's registers, their updates and the inverse by 16 x 16 tiles
+// on the matrix cores).  A non-positive pivot is replaced by a tiny
 // one and reported in `info` (first failing column + 1), so a singular
 // input never produces NaNs.
 //
@@ -27,8 +27,22 @@ namespace {
 
 constexpr int NB = 64;
 
-__device__ __forceinline__ float dev_sqrt(float x) { return __builtin_sqrtf(x); }
-__device__ __forceinline__ double dev_sqrt(double x) { return sqrt(x); }
+// 1 / sqrt(x) for a positive normal x: the hardware estimate refined by
+// Newton steps y <- y (3/2 - (x/2) y^2) (one for FP32, two for FP64, each
+// at least doubling the correct bits), within a few ulp of the exact value.
+__device__ __forceinline__ float rsqrt_refined(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  const float h = 0.5f * x;
+  y = y * (1.5f - h * y * y);
+  return y;
+}
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * (1.5 - h * y * y);
+  y = y * (1.5 - h * y * y);
+  return y;
+}
 template <typename T>
 __device__ __forceinline__ T tiny_pivot();
 template <>
@@ -36,77 +50,196 @@ __device__ __forceinline__ float tiny_pivot<float>() { return 1e-30f; }
 template <>
 __device__ __forceinline__ double tiny_pivot<double>() { return 1e-300; }
 
+// Broadcast lane `src` (a constant) of v to the whole wavefront.
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 16 x 16 x 4 MFMA in the operand precision (layouts in mfma_gemm.hip:
+// A operand A[l % 16][l / 16], B operand B[l / 16][l % 16]).
+__device__ __forceinline__ void tile_mfma(float a, float b, float (&acc)[4]) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  v4f c = {acc[0], acc[1], acc[2], acc[3]};
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  for (int r = 0; r < 4; ++r) acc[r] = c[r];
+}
+__device__ __forceinline__ void tile_mfma(double a, double b, double (&acc)[4]) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  v4d c = {acc[0], acc[1], acc[2], acc[3]};
+  c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  for (int r = 0; r < 4; ++r) acc[r] = c[r];
+}
+// row of result r of lane l in a 16 x 16 MFMA tile (column l % 16)
+template <typename T>
+__device__ __forceinline__ int tile_row(int l, int r) {
+  return sizeof(T) == 8 ? (l >> 4) + 4 * r : 4 * (l >> 4) + r;
+}
+
+constexpr int TW = 16;  // tile side and panel width of the diagonal kernel
+
 // Factor the diagonal block A[k0 .. k0+b)^2 in place (b <= NB) and write
 // the inverse of its factor to the same block of X (zero above the
-// diagonal).  Four wavefronts, lane l owning row l: the factor is blocked
-// by panels of eight columns (see below), then wavefront 0 inverts it, one
-// column per lane in registers.
+// diagonal).  One workgroup of four wavefronts; the block is padded with
+// the identity to NB x NB in LDS.
+//
+// Factor, by panels of TW columns: wavefront 0 factors the panel with row
+// jb + l in lane l, the panel in registers and the pivots and multipliers
+// broadcast across lanes (no LDS round trip inside the panel); then the
+// TW x TW tiles right of and below the panel take the rank-TW update
+// C -= L_ip L_jp^T on the matrix cores (at most two tiles per wavefront).
+// Entries above the diagonal are left undefined and never read.
+//
+// Inverse X = L^{-1}, by tiles: the four diagonal tiles are inverted by
+// forward substitution (one wavefront each, one column per lane), then
+// each block row I of the off-diagonal tiles is X_IJ = -X_II sum_K L_IK X_KJ
+// (J <= K < I), the tiles of one block row in parallel.
 template <typename T>
 __global__ __launch_bounds__(256) void potrf_diag_kernel(T* __restrict__ A, int lda, int k0, int b,
                                                           T* __restrict__ X, int ldx, int* __restrict__ info) {
-  __shared__ T s[NB][NB + 1];
+  constexpr int NT = NB / TW;  // tiles per side
+  __shared__ T s[NB][NB + 1];  // the block, then its factor L (lower)
+  __shared__ T sx[NB][NB + 1];  // X = L^{-1}
+  __shared__ T st[4][TW][TW + 1];  // per-wavefront tile scratch
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
-    s[i][j] = (i < b && j < b) ? A[(size_t)(k0 + i) * lda + k0 + j] : (i == j ? T(1) : T(0));
+  const int li = lane & 15, lk = lane >> 4;
+  {
+    // all loads issued before the first LDS store (addresses clamped into
+    // the block, the padding selected afterwards)
+    T v[NB * NB / 256];
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+      const int e = tid + 256 * q;
+      const int i = min(e / NB, b - 1), j = min(e % NB, b - 1);
+      v[q] = A[(size_t)(k0 + i) * lda + k0 + j];
+    }
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+      const int e = tid + 256 * q;
+      const int i = e / NB, j = e % NB;
+      s[i][j] = (i < b && j < b) ? v[q] : (i == j ? T(1) : T(0));
+    }
   }
   __syncthreads();
-  // blocked by panels of PW columns: wavefront 0 factors a panel (rows in
-  // lanes, columns in order, the panel's own updates inside the
-  // wavefront), then all wavefronts apply its rank-PW update to the
-  // columns right of it; two barriers per panel
-  constexpr int PW = 8;
-  int bad = 0;
-  for (int jb = 0; jb < NB; jb += PW) {
+
+  int bad = 0;  // first non-positive pivot + 1 (wavefront 0)
+  for (int p = 0; p < NT; ++p) {
+    const int jb = p * TW;
     if (wave == 0) {
-      for (int t = 0; t < PW; ++t) {
-        const int j = jb + t;
-        T d = s[j][j];
-        if (!(d > T(0))) {
-          if (bad == 0 && j < b) bad = j + 1;
-          d = tiny_pivot<T>();
-        }
-        d = dev_sqrt(d);
-        const T lij = lane > j ? s[lane][j] / d : (lane == j ? d : T(0));
-        s[lane][j] = lij;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (int c = j + 1; c < jb + PW; ++c)
-          if (lane >= c) s[lane][c] -= lij * s[c][j];
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      const int row = jb + lane;
+      const bool live = row < NB;
+      T r[TW];
+#pragma unroll
+      for (int t = 0; t < TW; ++t) r[t] = live ? s[row][jb + t] : T(0);
+      // per column: pivot, scaled column, then the update of column t + 1
+      // (the next pivot's critical path) before the others; the
+      // scheduling barrier keeps the broadcasts of one column from being
+      // hoisted into the next (SGPR pressure)
+#pragma unroll
+      for (int t = 0; t < TW; ++t) {
+        T d = lane_bcast(r[t], t);
+        const bool ok = d > T(0);
+        bad = (!ok && bad == 0 && jb + t < b) ? jb + t + 1 : bad;
+        d = ok ? d : tiny_pivot<T>();
+        const T inv = rsqrt_refined(d);
+        const T l = lane > t ? r[t] * inv : (lane == t ? d * inv : T(0));
+        r[t] = l;
+        if (t + 1 < TW) r[t + 1] -= l * lane_bcast(l, t + 1);
+#pragma unroll
+        for (int c = t + 2; c < TW; ++c) r[c] -= l * lane_bcast(l, c);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (live) {
+#pragma unroll
+        for (int t = 0; t < TW; ++t) s[row][jb + t] = r[t];
       }
     }
     __syncthreads();
-    T li[PW];
+    // trailing tiles (I, J), p < J <= I < NT: wavefront w takes tiles
+    // w and w + 4 of that list
+    const int nrest = NT - 1 - p;
+    const int ntiles = nrest * (nrest + 1) / 2;
+    for (int k = wave; k < ntiles; k += 4) {
+      int J = p + 1, rem = k;
+      while (rem >= NT - J) {
+        rem -= NT - J;
+        ++J;
+      }
+      const int I = J + rem;
+      T acc[4];
 #pragma unroll
-    for (int t = 0; t < PW; ++t) li[t] = s[lane][jb + t];
-    for (int c = jb + PW + wave; c <= lane; c += 4) {
-      T v = s[lane][c];
+      for (int r = 0; r < 4; ++r) acc[r] = s[I * TW + tile_row<T>(lane, r)][J * TW + li];
 #pragma unroll
-      for (int t = 0; t < PW; ++t) v -= li[t] * s[c][jb + t];
-      s[lane][c] = v;
+      for (int q = 0; q < TW / 4; ++q) {
+        const T a = -s[I * TW + li][jb + 4 * q + lk];
+        const T bb = s[J * TW + li][jb + 4 * q + lk];
+        tile_mfma(a, bb, acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s[I * TW + tile_row<T>(lane, r)][J * TW + li] = acc[r];
     }
     __syncthreads();
   }
   if (tid == 0 && bad && *info == 0) *info = k0 + bad;
-  if (wave == 0) {
-    // inverse of the lower factor, one column per lane kept in registers
-    // (forward substitution with the factor's rows read from LDS)
-    T xc[NB];
+
+  // diagonal tiles of the inverse: wavefront I inverts L_II, column li in
+  // lanes li (the other lanes repeat the work of lane li)
+  {
+    // right-looking: row t of the column is final once the rows above it
+    // have been subtracted, then it is subtracted from the rows below
+    const int I = wave, o = I * TW;
+    const T invd = T(1) / s[o + li][o + li];
+    T xc[TW];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      T v = (i == lane) ? T(1) : T(0);
+    for (int i = 0; i < TW; ++i) xc[i] = (i == li) ? T(1) : T(0);
 #pragma unroll
-      for (int t = 0; t < i; ++t) v -= s[i][t] * xc[t];
-      xc[i] = (i >= lane && i < b && lane < b) ? v / s[i][i] : T(0);
+    for (int t = 0; t < TW; ++t) {
+      xc[t] *= lane_bcast(invd, t);
+#pragma unroll
+      for (int i = t + 1; i < TW; ++i) xc[i] -= s[o + i][o + t] * xc[t];
     }
+    if (lk == 0) {
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
-      if (i < b && lane < b) X[(size_t)(k0 + i) * ldx + k0 + lane] = xc[i];
+      for (int i = 0; i < TW; ++i) sx[o + i][o + li] = xc[i];
+    }
   }
-  for (int e = tid; e < b * b; e += 256) {
-    const int i = e / b, j = e % b;
-    A[(size_t)(k0 + i) * lda + k0 + j] = (j <= i) ? s[i][j] : T(0);
+  __syncthreads();
+  // block rows of the off-diagonal tiles
+  for (int I = 1; I < NT; ++I) {
+    if (wave < I) {
+      const int J = wave;
+      T acc[4] = {T(0), T(0), T(0), T(0)};
+      for (int K = J; K < I; ++K) {
+#pragma unroll
+        for (int q = 0; q < TW / 4; ++q)
+          tile_mfma(s[I * TW + li][K * TW + 4 * q + lk], sx[K * TW + 4 * q + lk][J * TW + li], acc);
+      }
+      T(*w)[TW + 1] = st[wave];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) w[tile_row<T>(lane, r)][li] = acc[r];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      T out[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int q = 0; q < TW / 4; ++q) tile_mfma(-sx[I * TW + li][I * TW + 4 * q + lk], w[4 * q + lk][li], out);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sx[I * TW + tile_row<T>(lane, r)][J * TW + li] = out[r];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < NB * NB / 256; ++q) {
+    const int e = tid + 256 * q;
+    const int i = e / NB, j = e % NB;
+    if (i < b && j < b) {
+      A[(size_t)(k0 + i) * lda + k0 + j] = (j <= i) ? s[i][j] : T(0);
+      X[(size_t)(k0 + i) * ldx + k0 + j] = (j <= i) ? sx[i][j] : T(0);
+    }
   }
 }
 
