@@ -83,52 +83,35 @@ __device__ __forceinline__ int tile_row(int l, int r) {
 
 constexpr int TW = 16;  // tile side and panel width of the diagonal kernel
 
-// Factor the diagonal block A[k0 .. k0+b)^2 in place (b <= NB) and write
-// the inverse of its factor to the same block of X (zero above the
-// diagonal).  One workgroup of four wavefronts; the block is padded with
-// the identity to NB x NB in LDS.
+template <typename T>
+using Blk = T[NB][NB + 1];  // one NB x NB block in LDS (rows padded)
+template <typename T>
+using Scr = T[4][TW][TW + 1];  // per-wavefront tile scratch
+
+// Factor the NB x NB block s (in LDS, padded with the identity beyond its
+// b x b part) as L L^T in place and write X = L^{-1} to sx; `bad` becomes
+// the first non-positive pivot + 1 (0 if none) among the first b columns.
+// Entries of s and sx above the diagonal are left undefined (those inside
+// the diagonal tiles of sx are zero).  All four wavefronts of the
+// workgroup call it; it ends with a barrier.
 //
 // Factor, by panels of TW columns: wavefront 0 factors the panel with row
 // jb + l in lane l, the panel in registers and the pivots and multipliers
 // broadcast across lanes (no LDS round trip inside the panel); then the
 // TW x TW tiles right of and below the panel take the rank-TW update
 // C -= L_ip L_jp^T on the matrix cores (at most two tiles per wavefront).
-// Entries above the diagonal are left undefined and never read.
 //
 // Inverse X = L^{-1}, by tiles: the four diagonal tiles are inverted by
 // forward substitution (one wavefront each, one column per lane), then
 // each block row I of the off-diagonal tiles is X_IJ = -X_II sum_K L_IK X_KJ
 // (J <= K < I), the tiles of one block row in parallel.
 template <typename T>
-__global__ __launch_bounds__(256) void potrf_diag_kernel(T* __restrict__ A, int lda, int k0, int b,
-                                                          T* __restrict__ X, int ldx, int* __restrict__ info) {
+__device__ void factor_inv_lds(Blk<T>& s, Blk<T>& sx, Scr<T>& st, int b, int& bad) {
   constexpr int NT = NB / TW;  // tiles per side
-  __shared__ T s[NB][NB + 1];  // the block, then its factor L (lower)
-  __shared__ T sx[NB][NB + 1];  // X = L^{-1}
-  __shared__ T st[4][TW][TW + 1];  // per-wavefront tile scratch
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  {
-    // all loads issued before the first LDS store (addresses clamped into
-    // the block, the padding selected afterwards)
-    T v[NB * NB / 256];
-#pragma unroll
-    for (int q = 0; q < NB * NB / 256; ++q) {
-      const int e = tid + 256 * q;
-      const int i = min(e / NB, b - 1), j = min(e % NB, b - 1);
-      v[q] = A[(size_t)(k0 + i) * lda + k0 + j];
-    }
-#pragma unroll
-    for (int q = 0; q < NB * NB / 256; ++q) {
-      const int e = tid + 256 * q;
-      const int i = e / NB, j = e % NB;
-      s[i][j] = (i < b && j < b) ? v[q] : (i == j ? T(1) : T(0));
-    }
-  }
-  __syncthreads();
-
-  int bad = 0;  // first non-positive pivot + 1 (wavefront 0)
+  bad = 0;
   for (int p = 0; p < NT; ++p) {
     const int jb = p * TW;
     if (wave == 0) {
@@ -186,8 +169,6 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(T* __restrict__ A, int 
     }
     __syncthreads();
   }
-  if (tid == 0 && bad && *info == 0) *info = k0 + bad;
-
   // diagonal tiles of the inverse: wavefront I inverts L_II, column li in
   // lanes li (the other lanes repeat the work of lane li)
   {
@@ -232,15 +213,149 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(T* __restrict__ A, int 
     }
     __syncthreads();
   }
+}
+
+// Load the rows x cols block of G at (r0, c0) into the NB x NB LDS block
+// s, padded with the identity (pad_identity) or zeros; every load is
+// issued before the first LDS store (addresses clamped into the block).
+template <typename T>
+__device__ void load_block(Blk<T>& s, const T* __restrict__ G, int ld, int r0, int c0, int rows, int cols,
+                           bool pad_identity) {
+  const int tid = threadIdx.x;
+  T v[NB * NB / 256];
+#pragma unroll
+  for (int q = 0; q < NB * NB / 256; ++q) {
+    const int e = tid + 256 * q;
+    const int i = min(e / NB, rows - 1), j = min(e % NB, cols - 1);
+    v[q] = G[(size_t)(r0 + i) * ld + c0 + j];
+  }
 #pragma unroll
   for (int q = 0; q < NB * NB / 256; ++q) {
     const int e = tid + 256 * q;
     const int i = e / NB, j = e % NB;
-    if (i < b && j < b) {
-      A[(size_t)(k0 + i) * lda + k0 + j] = (j <= i) ? s[i][j] : T(0);
-      X[(size_t)(k0 + i) * ldx + k0 + j] = (j <= i) ? sx[i][j] : T(0);
-    }
+    s[i][j] = (i < rows && j < cols) ? v[q] : ((pad_identity && i == j) ? T(1) : T(0));
   }
+}
+
+// Store the rows x cols part of the LDS block s to G at (r0, c0); with
+// `lower` the entries above the diagonal are stored as zeros.
+template <typename T>
+__device__ void store_block(const Blk<T>& s, T* __restrict__ G, int ld, int r0, int c0, int rows, int cols,
+                            bool lower) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < NB * NB / 256; ++q) {
+    const int e = tid + 256 * q;
+    const int i = e / NB, j = e % NB;
+    if (i < rows && j < cols) G[(size_t)(r0 + i) * ld + c0 + j] = (!lower || j <= i) ? s[i][j] : T(0);
+  }
+}
+
+// acc (the wavefront's 32 x 32 quadrant of an NB x NB product, 2 x 2 MFMA
+// tiles) += sum_k a(m, k) b(k, n) over k < NB, the operands read from LDS
+// through the accessors.  Quadrant of wavefront w: rows 32 (w / 2), columns
+// 32 (w % 2); tile (i, j) result r of lane l is element
+// (32 (w / 2) + 16 i + tile_row(l, r), 32 (w % 2) + 16 j + l % 16).
+template <typename T, typename FA, typename FB>
+__device__ __forceinline__ void lds_product(FA a, FB b, T (&acc)[2][2][4]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  for (int k = 0; k < NB; k += 4) {
+    T av[2], bv[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) av[i] = a(wm + 16 * i + li, k + lk);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bv[j] = b(k + lk, wn + 16 * j + li);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) tile_mfma(av[i], bv[j], acc[i][j]);
+  }
+}
+
+// Visit the elements of the wavefront's quadrant held in acc.
+template <typename T, typename F>
+__device__ __forceinline__ void quadrant_each(T (&acc)[2][2][4], F f) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) f(wm + 16 * i + tile_row<T>(lane, r), wn + 16 * j + li, acc[i][j][r]);
+}
+
+// Factor the diagonal block A[k0 .. k0+n)^2 (n <= 2 NB) in place and write
+// the inverse of its factor to the same block of X (whose part above the
+// diagonal the caller has zeroed), in one workgroup of four wavefronts
+// with the block in LDS: with halves 1 (the first NB rows) and 2,
+//   L11, X11 of block 11;  L21 = A21 X11^T;  A22 -= L21 L21^T;
+//   L22, X22 of block 22;  X21 = -X22 (L21 X11),
+// the four products on the matrix cores.  Only the lower triangle of A is
+// read; the part above the diagonal of the block is left as it was.
+template <typename T>
+__global__ __launch_bounds__(256) void potrf_node_kernel(T* __restrict__ A, int lda, int k0, int n,
+                                                          T* __restrict__ X, int ldx, int* __restrict__ info) {
+  __shared__ Blk<T> S0, S1, S2, S3;
+  __shared__ Scr<T> st;
+  const int b1 = min(n, NB), b2 = n - NB;
+  const int k1 = k0 + NB;
+  load_block(S0, A, lda, k0, k0, b1, b1, true);
+  __syncthreads();
+  int bad1 = 0, bad2 = 0;
+  factor_inv_lds(S0, S1, st, b1, bad1);
+  store_block(S0, A, lda, k0, k0, b1, b1, true);
+  store_block(S1, X, ldx, k0, k0, b1, b1, true);
+  if (b2 > 0) {
+    // L21 = A21 X11^T (X11 lower: entries above its diagonal read as 0)
+    load_block(S2, A, lda, k1, k0, b2, NB, false);
+    __syncthreads();
+    T acc[2][2][4] = {};
+    lds_product<T>([&](int m, int k) { return S2[m][k]; },
+                   [&](int k, int c) { return k <= c ? S1[c][k] : T(0); }, acc);
+    __syncthreads();  // S0 (L11) stored, S2 (A21) read
+    quadrant_each(acc, [&](int m, int c, T v) { S0[m][c] = v; });
+    __syncthreads();
+    store_block(S0, A, lda, k1, k0, b2, NB, false);
+    // A22 -= L21 L21^T, then L22, X22
+    load_block(S2, A, lda, k1, k1, b2, b2, true);
+    __syncthreads();
+    quadrant_each(acc, [&](int m, int c, T& v) { v = S2[m][c]; });
+    lds_product<T>([&](int m, int k) { return -S0[m][k]; }, [&](int k, int c) { return S0[c][k]; }, acc);
+    __syncthreads();
+    quadrant_each(acc, [&](int m, int c, T v) { S2[m][c] = v; });
+    __syncthreads();
+    factor_inv_lds(S2, S3, st, b2, bad2);
+    store_block(S2, A, lda, k1, k1, b2, b2, true);
+    store_block(S3, X, ldx, k1, k1, b2, b2, true);
+    // T = L21 X11 (into S1 once X11 is read), X21 = -X22 T
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] = T(0);
+    lds_product<T>([&](int m, int k) { return S0[m][k]; }, [&](int k, int c) { return k >= c ? S1[k][c] : T(0); },
+                   acc);
+    __syncthreads();  // S1 (X11) stored and read
+    quadrant_each(acc, [&](int m, int c, T v) { S1[m][c] = v; });
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] = T(0);
+    lds_product<T>([&](int m, int k) { return k <= m ? -S3[m][k] : T(0); }, [&](int k, int c) { return S1[k][c]; },
+                   acc);
+    quadrant_each(acc, [&](int m, int c, T v) {
+      if (m < b2) X[(size_t)(k1 + m) * ldx + k0 + c] = v;
+    });
+  }
+  if (threadIdx.x == 0 && *info == 0 && (bad1 || bad2)) *info = bad1 ? k0 + bad1 : k1 + bad2;
 }
 
 template <typename T>
@@ -269,20 +384,23 @@ __global__ void copy_block_kernel(const T* __restrict__ src, int lds, T* __restr
 }
 
 // Factor A[n0:n1, n0:n1] = L L^T in place and write X = L^{-1} to the same
-// block of X, by recursive halving at a multiple of NB:
+// block of X, by recursive halving at a multiple of LEAF:
 //   L11, X11 of the leading half;  L21 = A21 X11^T;  A22 -= L21 L21^T;
 //   L22, X22 of the trailing half;  X21 = -X22 (L21 X11);
-// the leaves are the one-workgroup diagonal kernel.  Apart from the leaves
-// every step is a GEMM whose inner dimension is half the block, so the
-// factorisation and the inverse run mostly as large MFMA products.
+// the leaves (at most LEAF = 2 NB rows) are the one-workgroup node kernel,
+// which takes the same steps inside LDS.  Apart from the leaves every step
+// is a GEMM whose inner dimension is half the block, so the factorisation
+// and the inverse run mostly as large MFMA products.
+constexpr int LEAF = 2 * NB;
+
 template <typename T>
 hipError_t chol_inv_rec(T* A, int lda, int n0, int n1, T* X, int ldx, T* work, int* info, hipStream_t st) {
-  const int nb = (n1 - n0 + NB - 1) / NB;
+  const int nb = (n1 - n0 + LEAF - 1) / LEAF;
   if (nb <= 1) {
-    hipLaunchKernelGGL(potrf_diag_kernel<T>, dim3(1), dim3(256), 0, st, A, lda, n0, n1 - n0, X, ldx, info);
+    hipLaunchKernelGGL(potrf_node_kernel<T>, dim3(1), dim3(256), 0, st, A, lda, n0, n1 - n0, X, ldx, info);
     return hipGetLastError();
   }
-  const int h = n0 + (nb / 2) * NB;
+  const int h = n0 + (nb / 2) * LEAF;
   const int r = n1 - h, c = h - n0;
   T* A21 = A + (size_t)h * lda + n0;
   T* A22 = A + (size_t)h * lda + h;
@@ -319,8 +437,9 @@ hipError_t chol_inv(T* A, int n, int lda, T* X, int ldx, T* work, int* info, hip
 }  // namespace
 
 size_t chol_work_elems(int n) {
-  const int nb = (n + NB - 1) / NB;
-  const size_t h = (size_t)(nb / 2) * NB;
+  // the largest r x c block of the recursion is the top level's
+  const int nb = (n + LEAF - 1) / LEAF;
+  const size_t h = (size_t)(nb / 2) * LEAF;
   return std::max<size_t>((size_t)n * NB, h * ((size_t)n - std::min<size_t>(h, n)));
 }
 
