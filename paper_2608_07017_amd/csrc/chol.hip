@@ -360,16 +360,18 @@ __global__ __launch_bounds__(256) void potrf_node_kernel(T* __restrict__ A, int 
 
 template <typename T>
 hipError_t gemm_t(bool ta, bool tb, int M, int N, int K, T alpha, const T* A, int lda, const T* B, int ldb, T beta,
-                  T* C, int ldc, hipStream_t st);
+                  T* C, int ldc, hipStream_t st, bool lower = false);
 template <>
 hipError_t gemm_t<double>(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
-                          const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st) {
-  return mfma_gemm_f64(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st);
+                          const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st, bool lower) {
+  return lower ? mfma_gemm_lower_f64(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st)
+               : mfma_gemm_f64(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st);
 }
 template <>
 hipError_t gemm_t<float>(bool ta, bool tb, int M, int N, int K, float alpha, const float* A, int lda,
-                         const float* B, int ldb, float beta, float* C, int ldc, hipStream_t st) {
-  return mfma_gemm_f32(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st);
+                         const float* B, int ldb, float beta, float* C, int ldc, hipStream_t st, bool lower) {
+  return lower ? mfma_gemm_lower_f32(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st)
+               : mfma_gemm_f32(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st);
 }
 
 // dst (rows x cols, ldd) = src (rows x cols, lds)
@@ -412,7 +414,7 @@ hipError_t chol_inv_rec(T* A, int lda, int n0, int n1, T* X, int ldx, T* work, i
   // L21 = A21 X11^T, kept in the (still unused) X21 block
   e = gemm_t<T>(false, true, r, c, c, T(1), A21, lda, X11, ldx, T(0), X21, ldx, st);
   if (e != hipSuccess) return e;
-  e = gemm_t<T>(false, true, r, r, c, T(-1), X21, ldx, X21, ldx, T(1), A22, lda, st);
+  e = gemm_t<T>(false, true, r, r, c, T(-1), X21, ldx, X21, ldx, T(1), A22, lda, st, true);  // lower part read
   if (e != hipSuccess) return e;
   const size_t tot = (size_t)r * c;
   hipLaunchKernelGGL(copy_block_kernel<T>, dim3((unsigned)std::min<size_t>((tot + 255) / 256, 4096)), dim3(256), 0,

@@ -64,10 +64,11 @@ __device__ __forceinline__ S op_at(const S* X, int ld, int r, int c) {
 template <typename T, typename SA, typename SB, bool TA, bool TB>
 __global__ __launch_bounds__(256) void mfma_gemm_kernel(int M, int N, int K, T alpha, const SA* __restrict__ A,
                                                         int lda, const SB* __restrict__ B, int ldb, T beta,
-                                                        T* __restrict__ C, int ldc) {
+                                                        T* __restrict__ C, int ldc, int lower) {
   __shared__ T sA[GK][GT + GPAD];  // sA[k][i] = op(A)[m0 + i][k0 + k]
   __shared__ T sB[GK][GT + GPAD];  // sB[k][j] = op(B)[k0 + k][n0 + j]
   const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  if (lower && n0 >= m0 + GT) return;  // tile above the diagonal
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;  // wavefront's quarter
@@ -222,12 +223,14 @@ struct SlabPart {
 template <typename T, typename SA, typename SB, bool TA, bool TB, int WM, int WN>
 __global__ __launch_bounds__(256) void mfma_gemm_pipe_kernel(int M, int N, int K, T alpha, const SA* __restrict__ A,
                                                              int lda, const SB* __restrict__ B, int ldb, T beta,
-                                                             T* __restrict__ C, int ldc, int vec_a, int vec_b) {
+                                                             T* __restrict__ C, int ldc, int vec_a, int vec_b,
+                                                             int lower) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
   constexpr int PA = BM * GK / 256, PB = BN * GK / 256;  // elements per thread per slab
   __shared__ T sA[2][GK][BM + GPAD];
   __shared__ T sB[2][GK][BN + GPAD];
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  if (lower && n0 >= m0 + BM) return;  // tile above the diagonal
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 16 * WM, wn = (wave & 1) * 16 * WN;
@@ -298,7 +301,8 @@ bool rows_aligned(const S* X, int ld) {
 
 template <typename T, typename SA, typename SB>
 hipError_t gemm_dispatch(bool ta, bool tb, int M, int N, int K, T alpha, const SA* A, int lda, const SB* B, int ldb,
-                         T beta, T* C, int ldc, hipStream_t st) {
+                         T beta, T* C, int ldc, hipStream_t st, bool lower = false) {
+  const int lo = lower ? 1 : 0;
   if (M <= 0 || N <= 0) return hipSuccess;
   // larger products: the pipelined kernel, FP32 128 x 128 tiles, FP64
   // 64 x 64 (the accumulators and two LDS buffers of a larger FP64 tile
@@ -312,7 +316,7 @@ hipError_t gemm_dispatch(bool ta, bool tb, int M, int N, int K, T alpha, const S
 #define WOS_PIPE(W_, TA_, TB_)                                                                                  \
   hipLaunchKernelGGL((mfma_gemm_pipe_kernel<T, SA, SB, TA_, TB_, W_, W_>),                                      \
                      dim3((N + 32 * W_ - 1) / (32 * W_), (M + 32 * W_ - 1) / (32 * W_)), dim3(256), 0, st, M, N, K, \
-                     alpha, A, lda, B, ldb, beta, C, ldc, va, vb)
+                     alpha, A, lda, B, ldb, beta, C, ldc, va, vb, lo)
 #define WOS_PIPE_W(TA_, TB_) \
   if (wide)                  \
     WOS_PIPE(4, TA_, TB_);   \
@@ -334,16 +338,16 @@ hipError_t gemm_dispatch(bool ta, bool tb, int M, int N, int K, T alpha, const S
   const dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
   if (!ta && !tb)
     hipLaunchKernelGGL((mfma_gemm_kernel<T, SA, SB, false, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B,
-                       ldb, beta, C, ldc);
+                       ldb, beta, C, ldc, lo);
   else if (ta && !tb)
     hipLaunchKernelGGL((mfma_gemm_kernel<T, SA, SB, true, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B,
-                       ldb, beta, C, ldc);
+                       ldb, beta, C, ldc, lo);
   else if (!ta && tb)
     hipLaunchKernelGGL((mfma_gemm_kernel<T, SA, SB, false, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B,
-                       ldb, beta, C, ldc);
+                       ldb, beta, C, ldc, lo);
   else
     hipLaunchKernelGGL((mfma_gemm_kernel<T, SA, SB, true, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B,
-                       ldb, beta, C, ldc);
+                       ldb, beta, C, ldc, lo);
   return hipGetLastError();
 }
 
@@ -357,6 +361,21 @@ hipError_t mfma_gemm_f64(bool ta, bool tb, int M, int N, int K, double alpha, co
 hipError_t mfma_gemm_f32(bool ta, bool tb, int M, int N, int K, float alpha, const float* A, int lda,
                          const float* B, int ldb, float beta, float* C, int ldc, hipStream_t st) {
   return gemm_dispatch<float, float, float>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st);
+}
+
+// Only the tiles of C that reach the diagonal or below (M == N; for
+// symmetric products whose upper triangle is never read)
+hipError_t mfma_gemm_lower_f64(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
+                               const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st) {
+  return gemm_dispatch<double, double, double>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st, true);
+}
+hipError_t mfma_gemm_lower_f32(bool ta, bool tb, int M, int N, int K, float alpha, const float* A, int lda,
+                               const float* B, int ldb, float beta, float* C, int ldc, hipStream_t st) {
+  return gemm_dispatch<float, float, float>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st, true);
+}
+hipError_t mfma_gemm_lower_f64_a32(bool ta, bool tb, int M, int N, int K, double alpha, const float* A, int lda,
+                                   const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st) {
+  return gemm_dispatch<double, float, double>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st, true);
 }
 
 // FP64 arithmetic on an FP32-stored left operand (the toolbox rows)

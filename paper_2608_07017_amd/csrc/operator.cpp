@@ -147,7 +147,7 @@ wos_status prepare(wos_operator* op, const wos_toolbox* tb, const wos_coeffs* co
   OHIP(gemm_tb_left(f64, true, m, (int)mp, d * n, 1.0, tb->d_B, m, R, (int)mp, 0.0, LS, (int)mp, st));
   OHIP(gemm_tb_left(f64, true, m, (int)mp, n, 1.0, tb->d_A, m, R + (size_t)d * n * mp, (int)mp, 1.0, LS, (int)mp, st));
   // N = Lambda^T Lambda + reg I, its factor and X = factor^{-1}
-  OHIP(mfma_gemm_f64(true, false, m, m, m, 1.0, LS, (int)mp, LS, (int)mp, 0.0, N, m, st));
+  OHIP(mfma_gemm_lower_f64(true, false, m, m, m, 1.0, LS, (int)mp, LS, (int)mp, 0.0, N, m, st));
   OHIP(launch_reg_from_diag(true, N, m, m, rcond * rcond, regv, st));
   OHIP(launch_add_diag(true, N, m, m, regv, st));
   OHIP(cholesky_inverse_f64(N, m, m, X, work, info, st));

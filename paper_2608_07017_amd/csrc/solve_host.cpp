@@ -285,7 +285,7 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     SHIP(mfma_gemm_f32(true, false, m, m, K, 1.0f, (const float*)tb->d_B, m, w.R32, m, 0.0f, w.Lam32, m, st));
     SHIP(mfma_gemm_f32(true, false, m, m, n, 1.0f, (const float*)tb->d_A, m, w.R32 + (size_t)K * m, m, 1.0f,
                        w.Lam32, m, st));
-    SHIP(mfma_gemm_f32(true, false, m, m, m, 1.0f, w.Lam32, m, w.Lam32, m, 0.0f, w.N32, m, st));
+    SHIP(mfma_gemm_lower_f32(true, false, m, m, m, 1.0f, w.Lam32, m, w.Lam32, m, 0.0f, w.N32, m, st));
     SHIP(launch_reg_from_diag(false, w.N32, m, m, rcond * rcond, w.regv, st));
     SHIP(launch_add_diag(false, w.N32, m, m, w.regv, st));
     SHIP(cholesky_inverse_f32(w.N32, m, m, w.Lam32, w.P32, w.info, st));  // X = L^{-1} over Lambda's storage
@@ -335,7 +335,7 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
       SHIP(mfma_gemm_f64_a32(true, false, m, m, n, 1.0, (const float*)tb->d_A, m, w.R + (size_t)K * m, m, 1.0,
                              w.Lam, m, st));
     }
-    SHIP(mfma_gemm_f64(true, false, m, m, m, 1.0, w.Lam, m, w.Lam, m, 0.0, w.Hess, m, st));
+    SHIP(mfma_gemm_lower_f64(true, false, m, m, m, 1.0, w.Lam, m, w.Lam, m, 0.0, w.Hess, m, st));
     SHIP(launch_reg_from_diag(true, w.Hess, m, m, rcond * rcond, w.regv, st));
     SHIP(launch_add_diag(true, w.Hess, m, m, w.regv, st));
     SHIP(cholesky_inverse_f64(w.Hess, m, m, w.Lam, w.P64, w.info, st));  // X = L^{-1} over Lambda's storage
@@ -430,15 +430,17 @@ wos_status newton_tikhonov(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
   double* y1 = w.blk;
   double* y2 = w.blk + (size_t)(d + 1) * n;
   wos_coeffs co0{};  // A = I, b = c = 0: Lambda_0 and Sigma_0
-  // Lambda_0 explicit: L^T W0 L (the A rows carry no weight)
+  // Lambda_0 explicit: L^T W0 L (the A rows carry no weight); only its
+  // lower triangle, as only the Cholesky of the Hessian reads it
   SHIP(launch_weight_rows_any(tb->f64, mixed, tb->d_A, tb->d_B, tb->d_H, tb->d_K, tb->d_lambda, nullptr, nullptr,
                               nullptr, n, m, p, d, m, mixed ? (void*)w.R32 : (void*)w.R, st));
   if (mixed)
-    SHIP(mfma_gemm_f32(true, false, m, m, K, 1.0f, (const float*)tb->d_B, m, w.R32, m, 0.0f, w.L0_32, m, st));
+    SHIP(mfma_gemm_lower_f32(true, false, m, m, K, 1.0f, (const float*)tb->d_B, m, w.R32, m, 0.0f, w.L0_32, m, st));
   else if (tb->f64)
-    SHIP(mfma_gemm_f64(true, false, m, m, K, 1.0, (const double*)tb->d_B, m, w.R, m, 0.0, w.Lam0, m, st));
+    SHIP(mfma_gemm_lower_f64(true, false, m, m, K, 1.0, (const double*)tb->d_B, m, w.R, m, 0.0, w.Lam0, m, st));
   else
-    SHIP(mfma_gemm_f64_a32(true, false, m, m, K, 1.0, (const float*)tb->d_B, m, w.R, m, 0.0, w.Lam0, m, st));
+    SHIP(mfma_gemm_lower_f64_a32(true, false, m, m, K, 1.0, (const float*)tb->d_B, m, w.R, m, 0.0, w.Lam0, m,
+                                 st));
   auto apply_lam0 = [&](const double* x, double* out) { return apply_Lambda(tb, w, &co0, x, false, out, st); };
   // Sigma_0 g = L^T W0 [K; H] g
   SHIP(launch_gemv_n_ld(tb->f64, tb->d_K, d * n, p, p, g, 1.0, 0.0, y1, st));
@@ -476,11 +478,11 @@ wos_status newton_tikhonov(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     if ((s = load_lam0()) != WOS_OK) return s;
     SHIP(launch_scale_rows(tb->f64, mixed, tb->d_A, n, m, wts, mixed ? (void*)w.R32 : (void*)w.R, st));
     if (mixed)
-      SHIP(mfma_gemm_f32(true, false, m, m, n, 1.0f, (const float*)tb->d_A, m, w.R32, m, 1.0f, w.N32, m, st));
+      SHIP(mfma_gemm_lower_f32(true, false, m, m, n, 1.0f, (const float*)tb->d_A, m, w.R32, m, 1.0f, w.N32, m, st));
     else if (tb->f64)
-      SHIP(mfma_gemm_f64(true, false, m, m, n, 1.0, (const double*)tb->d_A, m, w.R, m, 1.0, w.Hess, m, st));
+      SHIP(mfma_gemm_lower_f64(true, false, m, m, n, 1.0, (const double*)tb->d_A, m, w.R, m, 1.0, w.Hess, m, st));
     else
-      SHIP(mfma_gemm_f64_a32(true, false, m, m, n, 1.0, (const float*)tb->d_A, m, w.R, m, 1.0, w.Hess, m, st));
+      SHIP(mfma_gemm_lower_f64_a32(true, false, m, m, n, 1.0, (const float*)tb->d_A, m, w.R, m, 1.0, w.Hess, m, st));
     auto apply_hess = [&](const double* x, double* out) -> wos_status {
       wos_status s2 = apply_lam0(x, out);
       if (s2 != WOS_OK) return s2;

@@ -47,6 +47,15 @@ hipError_t mfma_gemm_f64_a32(bool ta, bool tb, int M, int N, int K, double alpha
                              const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st);
 hipError_t mfma_gemm_f64_b32(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
                              const float* B, int ldb, double beta, double* C, int ldc, hipStream_t st);
+// the same for a square C whose upper triangle is never read (symmetric
+// products): only the tiles that reach the diagonal or below are computed,
+// the rest of C is left as it was
+hipError_t mfma_gemm_lower_f64(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
+                               const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st);
+hipError_t mfma_gemm_lower_f32(bool ta, bool tb, int M, int N, int K, float alpha, const float* A, int lda,
+                               const float* B, int ldb, float beta, float* C, int ldc, hipStream_t st);
+hipError_t mfma_gemm_lower_f64_a32(bool ta, bool tb, int M, int N, int K, double alpha, const float* A, int lda,
+                                   const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st);
 
 // ---- Cholesky (chol.hip): A (n x n, lda, row-major, lower part read) is
 // overwritten by its factor L (lower); X (n x n, ld n) receives L^{-1}
