@@ -18,7 +18,11 @@ Nonlinear Elliptic Problems of Divergence-type"):
 * ``volume``    -- the cell weights lambda_i = |W_i| / |D|;
 * ``linalg``    -- assembly of Lambda, Sigma and the right-hand side
                    (eq. linear_q), the truncated-SVD solve, reconstruction,
-                   and the Newton / Picard outer loops.
+                   and the Newton / Picard outer loops;
+* ``euler_lagrange`` -- the discrete functional J of eq. gradJ for the
+                   p-Laplace energy, its gradient, and Adam (Sec.
+                   "Euler-Lagrange boundary value problems" and the
+                   appendix on the optimisation of J).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import it.  The product path (``paper_2608_07017_amd``)

@@ -1,0 +1,116 @@
+"""Euler-Lagrange route: minimisation of the discrete functional J (oracle).
+
+Test infrastructure (see the package header); never imported by the
+product path.
+
+Sec. "Euler-Lagrange boundary value problems": for an energy
+F(x, u, p) the problem is reduced to the unknown source fbar in R^m through
+u ~ U f + H g, with the toolbox estimators in place of the operators
+(eq. gradJ):
+
+    J(fbar) = sum_i lambda_i F(x_i, u_i, p_i),
+    u_i = [A fbar + H g~]_i,   p_i = B_i fbar + K_i g~,
+
+and its gradient (the boxed formula after eq. min_el_discrete)
+
+    grad J = A^T (lambda o dF/du) + sum_a B^(a)^T (lambda o dF/dp_a).
+
+The energy built here is the p-Laplace one of Sec. "Solving nonlinear
+elliptic PDEs" (eq. plaplace): F = |p|^P / P - f u, so dF/du = -f and
+dF/dp = |p|^(P-2) p (taken as 0 at p = 0, its limit for P > 1).
+
+The minimiser is Adam as restated in the appendix on the optimisation of
+J: m_j = beta1 m_{j-1} + (1 - beta1) grad, v_j = beta2 v_{j-1} +
+(1 - beta2) grad^2 (elementwise), alpha_j = alpha sqrt(1 - beta2^j) /
+(1 - beta1^j), fbar_j = fbar_{j-1} - alpha_j m_j / (sqrt(v_j) + eps), with
+m_0 = v_0 = 0 and the paper's beta1 = 0.9, beta2 = 0.999, eps = 1e-10.
+
+Readings (each listed in the design doc):
+* the stopping norm |grad J|_{2,V} = (sum_j lambda(V_j) [grad J]_j^2)^(1/2)
+  is taken with the normalised cell weights lambda_j = |V_j| / |D| (the
+  toolbox's V and W cells are the same Voronoi cells of the sites), i.e.
+  the paper's norm divided by sqrt(|D|);
+* the paper gives final gradient norms but no stopping rule: a run stops
+  after max_iter iterations or once the norm is at most tol.
+
+Pinned by tests/test_oracle_euler_lagrange.py: the gradient against central
+differences of J, Adam's first step (of length alpha in every coordinate,
+a closed form of the update), Adam on a separable quadratic against its
+known minimiser, the route at P = 2 against the linear system of
+eq. linear_q (the two routes of the paper coincide for the quadratic
+energy), and the disk's closed-form p-torsion solution at P = 2 against
+(1 - |x|^2) / 4.
+"""
+import numpy as np
+
+from .linalg import reconstruct
+
+
+def plaplace_energy_parts(tb, fbar, g, P, f):
+    """u, grad u (d, n), the energy density F_i and the weights
+    (dF/du, dF/dp) at the sites, for F = |p|^P / P - f u."""
+    u, gu = reconstruct(tb, fbar, g)
+    s = np.sum(gu * gu, axis=0)  # |p_i|^2
+    F = np.power(s, 0.5 * P) / P - f * u
+    c = np.where(s > 0.0, np.power(np.where(s > 0.0, s, 1.0), 0.5 * (P - 2.0)), 0.0)  # |p|^(P-2)
+    return u, gu, F, -f, c * gu
+
+
+def plaplace_J(tb, lam, fbar, g, P, f):
+    """J(fbar) = sum_i lambda_i (|p_i|^P / P - f_i u_i)   (eq. gradJ)."""
+    _, _, F, _, _ = plaplace_energy_parts(tb, fbar, g, P, f)
+    return float(np.sum(lam * F))
+
+
+def plaplace_grad(tb, lam, fbar, g, P, f):
+    """grad J = A^T (lambda o dF/du) + sum_a B^(a)^T (lambda o dF/dp_a)."""
+    _, _, _, dFu, dFp = plaplace_energy_parts(tb, fbar, g, P, f)
+    grad = tb["A"].T @ (lam * dFu)
+    for a in range(tb["B"].shape[0]):
+        grad = grad + tb["B"][a].T @ (lam * dFp[a])
+    return grad
+
+
+def grad_norm(lam, grad):
+    """(sum_j lambda_j grad_j^2)^(1/2) with the normalised cell weights."""
+    return float(np.sqrt(np.sum(lam * grad * grad)))
+
+
+def adam(grad_fn, f0, alpha, max_iter, beta1=0.9, beta2=0.999, eps=1e-10, tol=0.0, norm_fn=None,
+         check_every=1):
+    """Adam from f0 for at most max_iter iterations; with tol > 0 it stops
+    after iteration j (a multiple of check_every) once norm_fn(grad J(f_j))
+    <= tol.  Returns (f, iterations taken)."""
+    f = np.array(f0, dtype=np.float64)
+    m = np.zeros_like(f)
+    v = np.zeros_like(f)
+    j = 0
+    for j in range(1, max_iter + 1):
+        gr = grad_fn(f)
+        m = beta1 * m + (1.0 - beta1) * gr
+        v = beta2 * v + (1.0 - beta2) * gr * gr
+        aj = alpha * np.sqrt(1.0 - beta2 ** j) / (1.0 - beta1 ** j)
+        f = f - aj * m / (np.sqrt(v) + eps)
+        if tol > 0.0 and j % check_every == 0 and norm_fn(grad_fn(f)) <= tol:
+            break
+    return f, j
+
+
+def minimize_plaplace(tb, lam, f, g, P, alpha, max_iter, f0=1.0, tol=0.0, check_every=1):
+    """The p-Laplace route end to end: Adam from fbar_0 = f0 (a constant,
+    as in the paper's parameter table), then u, grad u, J and the norm."""
+    m = tb["A"].shape[1]
+    fb0 = np.full(m, float(f0))
+    fb, it = adam(lambda x: plaplace_grad(tb, lam, x, g, P, f), fb0, alpha, max_iter, tol=tol,
+                  norm_fn=lambda gr: grad_norm(lam, gr), check_every=check_every)
+    u, gu = reconstruct(tb, fb, g)
+    return {"fbar": fb, "u": u, "grad_u": gu, "iters": it, "J": plaplace_J(tb, lam, fb, g, P, f),
+            "grad_norm": grad_norm(lam, plaplace_grad(tb, lam, fb, g, P, f))}
+
+
+def plaplace_torsion_disk(x, P):
+    """The disk's p-torsion solution (-Lap_p u = 1, u = 0 on the circle),
+    Example "p-Torsion problem on unit disk":
+    u = (P-1)/P (1/2)^(1/(P-1)) (1 - |x|^(P/(P-1)))."""
+    r2 = np.sum(np.asarray(x, dtype=np.float64) ** 2, axis=-1)
+    return (P - 1.0) / P * 0.5 ** (1.0 / (P - 1.0)) * (1.0 - np.power(r2, P / (2.0 * P - 2.0)))

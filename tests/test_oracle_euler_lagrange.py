@@ -1,0 +1,134 @@
+"""Pins of the Euler-Lagrange route: J, its gradient, Adam, and the disk's
+p-torsion closed form."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import euler_lagrange as E
+from oracle import linalg as L
+from oracle.volume import cell_weights
+from oracle.walker import build_toolbox
+
+
+def _random_tb(n=10, p=4, d=2, seed=0):
+    rng = np.random.default_rng(seed)
+    return {"A": rng.random((n, n)), "B": rng.normal(size=(d, n, n)), "H": rng.random((n, p)),
+            "K": rng.normal(size=(d, n, p))}
+
+
+@pytest.mark.parametrize("P", [1.5, 2.0, 3.0, 5.0])
+def test_gradient_matches_central_differences_of_J(P):
+    tb = _random_tb(9, 4, 2, 1)
+    rng = np.random.default_rng(2)
+    lam = rng.random(9)
+    f = rng.normal(size=9)
+    g = rng.normal(size=4)
+    fb = rng.normal(size=9)
+    gr = E.plaplace_grad(tb, lam, fb, g, P, f)
+    h = 1e-6
+    fd = np.array([(E.plaplace_J(tb, lam, fb + h * e, g, P, f) - E.plaplace_J(tb, lam, fb - h * e, g, P, f)) / (2 * h)
+                   for e in np.eye(9)])
+    assert np.allclose(gr, fd, rtol=1e-6, atol=1e-7 * np.abs(fd).max())
+
+
+def test_quadratic_energy_gradient_is_the_linear_residual():
+    # P = 2: F = |p|^2/2 - f u, so grad J = Lambda0 fbar + Sigma0 g - A^T (lam f)
+    # with Lambda0 = sum_i lam_i B_i^T B_i (the regrouped sums of the linear
+    # route, coded separately)
+    tb = _random_tb(10, 4, 2, 3)
+    rng = np.random.default_rng(4)
+    lam, f, g, fb = rng.random(10), rng.normal(size=10), rng.normal(size=4), rng.normal(size=10)
+    L0, S0 = L._grad_pairs(tb["B"], tb["K"], lam, None)
+    ref = L0 @ fb + S0 @ g - tb["A"].T @ (lam * f)
+    assert np.allclose(E.plaplace_grad(tb, lam, fb, g, 2.0, f), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_adam_first_step_has_length_alpha():
+    # m1 = (1-b1) g, v1 = (1-b2) g^2, alpha_1 = alpha sqrt(1-b2)/(1-b1):
+    # the first step is alpha g / (|g| + eps / sqrt(1 - b2)) = alpha sign(g)
+    g0 = np.array([3.0, -0.5, 1e-3, -20.0])
+    f1, it = E.adam(lambda x: g0, np.zeros(4), 0.01, 1)
+    assert it == 1
+    assert np.allclose(f1, -0.01 * g0 / (np.abs(g0) + 1e-10 / np.sqrt(1 - 0.999)), rtol=1e-12, atol=0)
+    assert np.allclose(np.abs(f1), 0.01, rtol=1e-5)
+
+
+def test_adam_minimises_a_separable_quadratic():
+    c = np.array([1.0, 10.0, 0.1, 3.0])
+    t = np.array([0.5, -1.0, 2.0, 0.0])
+    f, it = E.adam(lambda x: c * (x - t), np.ones(4), 0.01, 20000)
+    assert np.allclose(f, t, atol=2e-3)
+
+
+def test_adam_route_at_P2_reaches_the_linear_solution():
+    # the two routes of the paper coincide for the quadratic energy: the
+    # minimiser of J solves Lambda0 fbar = A^T (lam f) - Sigma0 g
+    tb = _random_tb(8, 3, 2, 5)
+    rng = np.random.default_rng(6)
+    lam = 0.5 + rng.random(8)
+    f, g = rng.normal(size=8), rng.normal(size=3)
+    L0, S0 = L._grad_pairs(tb["B"], tb["K"], lam, None)
+    ref = np.linalg.solve(L0, tb["A"].T @ (lam * f) - S0 @ g)
+    out = E.minimize_plaplace(tb, lam, f, g, 2.0, alpha=0.01, max_iter=40000, f0=0.0)
+    assert np.allclose(out["fbar"], ref, atol=5e-3 * np.abs(ref).max())
+    assert out["grad_norm"] < 1e-3
+
+
+def test_adam_stops_at_the_tolerance():
+    tb = _random_tb(8, 3, 2, 7)
+    rng = np.random.default_rng(8)
+    lam = 0.5 + rng.random(8)
+    f, g = rng.normal(size=8), rng.normal(size=3)
+    out = E.minimize_plaplace(tb, lam, f, g, 2.0, alpha=0.01, max_iter=40000, f0=0.0, tol=1e-2, check_every=10)
+    assert out["iters"] < 40000 and out["iters"] % 10 == 0
+    assert out["grad_norm"] <= 1e-2
+
+
+@pytest.mark.parametrize("P", [1.5, 2.0, 3.0, 5.0, 10.0])
+def test_torsion_closed_form_solves_the_radial_p_laplace_equation(P):
+    # -Lap_p u = (1/r) d/dr (r |u'|^(P-2) u') = -1 for radial u, u(1) = 0;
+    # checked by central differences at interior radii
+    assert E.plaplace_torsion_disk(np.array([[1.0, 0.0]]), P)[0] == pytest.approx(0.0, abs=1e-15)
+    h = 1e-4
+
+    def u(r):
+        return E.plaplace_torsion_disk(np.stack([r, np.zeros_like(r)], -1), P)
+
+    def flux(r):
+        du = (u(r + h) - u(r - h)) / (2 * h)
+        return r * np.abs(du) ** (P - 2) * du
+
+    for r in (0.3, 0.5, 0.8):
+        r = np.array([r])
+        lap = (flux(r + h) - flux(r - h)) / (2 * h) / r
+        assert lap[0] == pytest.approx(-1.0, rel=1e-4)
+    x = np.random.default_rng(0).uniform(-0.7, 0.7, size=(5, 2))
+    if P == 2.0:
+        assert np.allclose(E.plaplace_torsion_disk(x, 2.0), (1 - (x**2).sum(1)) / 4, rtol=1e-14)
+
+
+def test_disk_torsion_end_to_end_early_stopped():
+    # The route on an oracle toolbox (the paper's ring layout, 5 rings,
+    # 1500 walks) with the paper's Adam parameters (fbar_0 = 1,
+    # alpha = 1e-3) reaches the p-torsion function after 2000 iterations
+    # (measured relative errors 0.055 at P = 2, 0.084 at P = 1.5).  Run on,
+    # Adam drifts to the exact minimiser of this Monte Carlo J, whose error
+    # is larger (0.66 at P = 2: the unregularised discrete problem with as
+    # many unknowns as cells is ill-posed in its oscillating directions).
+    dom = W.unit_disk()
+    K = 5
+    pts = []
+    for k in range(1, K + 1):
+        nk = 6 * k - 3
+        th = 2 * np.pi * np.arange(nk) / nk
+        pts.append(np.stack([(k - 0.5) / K * np.cos(th), (k - 0.5) / K * np.sin(th)], 1))
+    sites = np.concatenate(pts)
+    n = len(sites)
+    bn = W.circle_nodes(30)
+    tb = build_toolbox(dom, sites, bn, 1500, 1e-3, 8)
+    lam, _ = cell_weights(dom, sites, 2, 1 << 18)
+    for P, bound in ((2.0, 0.1), (1.5, 0.15)):
+        exact = E.plaplace_torsion_disk(sites, P)
+        out = E.minimize_plaplace(tb, lam, np.ones(n), np.zeros(30), P, alpha=1e-3, max_iter=2000, f0=1.0)
+        err = np.sqrt(np.sum(lam * (out["u"] - exact) ** 2)) / np.sqrt(np.sum(lam * exact**2))
+        assert err < bound
