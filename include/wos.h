@@ -249,6 +249,59 @@ typedef struct {
 wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* coeffs, const double* f, const double* g,
                      double* u, double* grad_u, double* q, wos_solve_info* info, void* stream);
 
+/* ------------------------------------------ Euler-Lagrange route (Adam)
+ * Minimises the discrete functional of Sec. "Euler-Lagrange boundary
+ * value problems" (eq. gradJ) over the unknown source fbar,
+ *   J(fbar) = sum_i lambda_i F(x_i, u_i, grad u_i),
+ *   u = A fbar + H g,  grad u_i = B_i fbar + K_i g,
+ * by Adam as the paper states it in its appendix on the optimisation of J
+ * (m_j, v_j, the bias-corrected step alpha sqrt(1 - beta2^j) / (1 - beta1^j)),
+ * with the boxed gradient
+ *   grad J = A^T (lambda o dF/du) + sum_a B^(a)^T (lambda o dF/dp_a).
+ * Energies:
+ *   WOS_EL_PLAPLACE  F = |p|^P / P - f u (eq. plaplace), the weak form of
+ *                    -div(|grad u|^(P-2) grad u) = f, u = g.            */
+typedef enum { WOS_EL_PLAPLACE = 0 } wos_energy;
+
+typedef struct {
+  int32_t energy;       /* wos_energy                                         */
+  double p_exp;         /* the exponent P > 1                                 */
+  double alpha;         /* Adam step size, > 0                                */
+  double beta1;         /* in [0, 1); 0 -> 0.9 (the paper's)                  */
+  double beta2;         /* in [0, 1); 0 -> 0.999 (the paper's)                */
+  double eps;           /* > 0; 0 -> 1e-10 (the paper's)                      */
+  int32_t max_iter;     /* iterations at most, > 0                            */
+  double tol;           /* stop once |grad J|_lambda <= tol; 0: run max_iter   */
+  int32_t check_every;  /* with tol > 0, the norm is evaluated after every
+                           check_every-th iteration; 0 -> 50                  */
+} wos_adam_opts;
+
+typedef struct {
+  int32_t iters;        /* iterations taken                                   */
+  double J;             /* J at the result                                    */
+  double grad_norm;     /* |grad J|_lambda = (sum_j lambda_j [grad J]_j^2)^(1/2)
+                           at the result (lambda_j = |W_j| / |D|)             */
+  double grad_norm0;    /* the same at the start                              */
+  double seconds;       /* wall time of the iterations                        */
+} wos_adam_info;
+
+/* Runs Adam from the source in `fbar` and leaves the result there.
+ *   f       device double (n): f(x_i)
+ *   g       device double (p): g(z_j)
+ *   fbar    device double (m): the start on entry, the result on return
+ *   u       device double (n) output; grad_u device (d x n) or NULL
+ *   info    host, optional.
+ * Every step runs on the device (the toolbox GEMVs in FP64 accumulation,
+ * the site weights and the Adam update); the host reads one scalar per
+ * norm check.  Runs on `stream` and synchronises it before returning.
+ * Errors: WOS_EINVAL for a NULL pointer, an unbuilt toolbox, an unknown
+ * energy, P <= 1, alpha <= 0, beta outside [0, 1), eps < 0 or
+ * max_iter <= 0.  The work vectors ((2d + 3) n + 3 m doubles) are allocated
+ * on the first call and kept with the toolbox.  Not thread-safe for one
+ * toolbox.                                                                   */
+wos_status wos_minimize(wos_toolbox* tb, const wos_adam_opts* opts, const double* f, const double* g,
+                        double* fbar, double* u, double* grad_u, wos_adam_info* info, void* stream);
+
 /* ---------------------------------------------------- solution operators
  * For a LINEAR problem the map from the data (f, g) to the solution is
  * linear (Sec. "Second order linear elliptic PDEs": q solves eq. linear_q,

@@ -14,8 +14,8 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import (EXPORTS, KINDS, PRECISION, PROBLEMS, SOLVE_PRECISION, SOLVERS, WosBuildOpts, WosCoeffs,
-                   WosOperatorInfo, WosOperatorOpts,
+from ._lib import (ENERGIES, EXPORTS, KINDS, PRECISION, PROBLEMS, SOLVE_PRECISION, SOLVERS, WosAdamInfo,
+                   WosAdamOpts, WosBuildOpts, WosCoeffs, WosOperatorInfo, WosOperatorOpts,
                    WosDomain, WosError, WosServerOpts, WosSolveInfo, WosToolboxInfo, check, lib)
 
 __all__ = ["Toolbox", "Server", "build_toolbox", "WosError", "lib"]
@@ -146,6 +146,32 @@ class Toolbox:
         check(lib().wos_solve(self._h, ctypes.byref(co), _dptr(f), _dptr(g), _dptr(u), _dptr(gu), _dptr(q),
                               ctypes.byref(info), _stream_handle(stream)))
         return u, gu, q, {k: getattr(info, k) for k, _ in info._fields_}
+
+    def minimize(self, f, g, p_exp, alpha, max_iter, fbar0=1.0, tol=0.0, check_every=0, beta1=0.0, beta2=0.0,
+                 eps=0.0, energy="plaplace", stream=None):
+        """Adam on the discrete functional J of the Euler-Lagrange route
+        (include/wos.h, wos_minimize), from the source fbar0 (a scalar for a
+        constant start, or an (m,) array).  Returns (u, grad_u, fbar, info)
+        with device float64 tensors."""
+        dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+        f, g = dev(f), dev(g)
+        if f.numel() != self.n or g.numel() != self.p:
+            raise ValueError("f must have n entries and g p entries")
+        if np.ndim(fbar0) == 0:
+            fbar = torch.full((self.n,), float(fbar0), dtype=torch.float64, device="cuda")
+        else:
+            fbar = dev(fbar0).clone()
+            if fbar.numel() != self.n:
+                raise ValueError("fbar0 must have m entries")
+        opts = WosAdamOpts(energy=ENERGIES[energy], p_exp=float(p_exp), alpha=float(alpha), beta1=float(beta1),
+                           beta2=float(beta2), eps=float(eps), max_iter=int(max_iter), tol=float(tol),
+                           check_every=int(check_every))
+        u = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        gu = torch.empty((self.dim, self.n), dtype=torch.float64, device="cuda")
+        info = WosAdamInfo()
+        check(lib().wos_minimize(self._h, ctypes.byref(opts), _dptr(f), _dptr(g), _dptr(fbar), _dptr(u), _dptr(gu),
+                                 ctypes.byref(info), _stream_handle(stream)))
+        return u, gu, fbar, {k: getattr(info, k) for k, _ in info._fields_}
 
     def operator(self, A=None, b=None, c=None, rcond=1e-3, grad=False, storage="f64", stream=None):
         """Prepare the solution operator of the linear problem with these

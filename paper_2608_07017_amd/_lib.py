@@ -74,6 +74,18 @@ class WosSolveInfo(ctypes.Structure):
                 ("fallback", ctypes.c_int32), ("refine_residual", ctypes.c_double)]
 
 
+class WosAdamOpts(ctypes.Structure):
+    _fields_ = [("energy", ctypes.c_int32), ("p_exp", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("check_every", ctypes.c_int32)]
+
+
+class WosAdamInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("J", ctypes.c_double), ("grad_norm", ctypes.c_double),
+                ("grad_norm0", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+ENERGIES = {"plaplace": 0}
 PROBLEMS = {"linear": 0, "semilinear_cubic": 1, "quasilinear": 2}
 SOLVERS = {"tsvd": 0, "tikhonov": 1}
 SOLVE_PRECISION = {"f64": 0, "mixed": 1}
@@ -92,6 +104,8 @@ SIGNATURES = {
     "wos_apply": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "wos_solve": (ctypes.c_int, [_P, ctypes.POINTER(WosCoeffs), _P, _P, _P, _P, _P,
                                  ctypes.POINTER(WosSolveInfo), _P]),
+    "wos_minimize": (ctypes.c_int, [_P, ctypes.POINTER(WosAdamOpts), _P, _P, _P, _P, _P,
+                                    ctypes.POINTER(WosAdamInfo), _P]),
     "wos_toolbox_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "wos_toolbox_get_timings": (ctypes.c_int, [_P, _D, _D, _D]),
     "wos_toolbox_free": (None, [_P]),

@@ -176,6 +176,45 @@ __global__ void pointwise_kernel(int n, const double* __restrict__ lam, const do
   }
 }
 
+// Euler-Lagrange route, p-Laplace energy F = |p|^P / P - f u (eq. gradJ
+// and eq. plaplace): at site i, with s = |grad u_i|^2,
+//   y[a n + i] = lambda_i |p|^(P-2) dp_a   (a < d; 0 where s = 0, the limit
+//                                           for P > 1),
+//   y[d n + i] = -lambda_i f_i              (dF/du),
+//   F[i]       = s^(P/2) / P - f_i u_i      (the energy density),
+// so that grad J = L^T y with L = [B; A].
+__global__ void plaplace_weights_kernel(int n, int d, double P, const double* __restrict__ lam,
+                                        const double* __restrict__ u, const double* __restrict__ gu,
+                                        const double* __restrict__ f, double* __restrict__ y,
+                                        double* __restrict__ F) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += stride) {
+    double s = 0.0;
+    for (int a = 0; a < d; ++a) s += gu[(size_t)a * n + i] * gu[(size_t)a * n + i];
+    const double c = s > 0.0 ? pow(s, 0.5 * (P - 2.0)) : 0.0;
+    const double li = lam[i];
+    for (int a = 0; a < d; ++a) y[(size_t)a * n + i] = li * c * gu[(size_t)a * n + i];
+    y[(size_t)d * n + i] = -li * f[i];
+    F[i] = (s > 0.0 ? pow(s, 0.5 * P) : 0.0) / P - f[i] * u[i];
+  }
+}
+
+// One Adam step (the appendix on the optimisation of J): m <- b1 m +
+// (1 - b1) g, v <- b2 v + (1 - b2) g^2, fbar <- fbar - a_j m / (sqrt(v) + eps),
+// with the bias-corrected step a_j computed on the host.
+__global__ void adam_kernel(int m, const double* __restrict__ g, double b1, double b2, double eps, double aj,
+                            double* __restrict__ mv, double* __restrict__ vv, double* __restrict__ fbar) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < (size_t)m; j += stride) {
+    const double gj = g[j];
+    const double mj = b1 * mv[j] + (1.0 - b1) * gj;
+    const double vj = b2 * vv[j] + (1.0 - b2) * gj * gj;
+    mv[j] = mj;
+    vv[j] = vj;
+    fbar[j] -= aj * mj / (sqrt(vj) + eps);
+  }
+}
+
 // C[i][j] += sum_k Xrows... : Gram update C += X^T diag(w) X (X rows x cols)
 // used for the Newton Hessian A^T diag(w) A.  64 x 64 tiles.
 template <typename T>
@@ -524,6 +563,19 @@ hipError_t launch_pointwise(int n, const double* lam, const double* u, const dou
                             double c2, double c3, double cf, double* out, hipStream_t st) {
   hipLaunchKernelGGL(pointwise_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, lam, u, f, c0, c1, c2, c3,
                      cf, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_plaplace_weights(int n, int d, double P, const double* lam, const double* u, const double* gu,
+                                   const double* f, double* y, double* F, hipStream_t st) {
+  hipLaunchKernelGGL(plaplace_weights_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d, P, lam, u, gu, f, y,
+                     F);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(int m, const double* g, double b1, double b2, double eps, double aj, double* mv, double* vv,
+                       double* fbar, hipStream_t st) {
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, g, b1, b2, eps, aj, mv, vv, fbar);
   return hipGetLastError();
 }
 

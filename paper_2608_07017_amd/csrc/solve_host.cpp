@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -506,7 +507,7 @@ namespace wos {
 
 void free_work(SolveWork& w) {
   void* ptrs[] = {w.R, w.Lam, w.Sig, w.Lam0, w.Sig0, w.Hess, w.G, w.V, w.E, w.rot, w.pq, w.vec, w.Ac, w.red,
-                  w.blk, w.regv, w.info, w.R32, w.Lam32, w.N32, w.v32, w.P64, w.P32, w.L0_32};
+                  w.blk, w.regv, w.info, w.R32, w.Lam32, w.N32, w.v32, w.P64, w.P32, w.L0_32, w.el};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   w = SolveWork();
@@ -628,7 +629,91 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
   return WOS_OK;
 }
 
+// ------------------------------------------------ Euler-Lagrange route
+// Adam on J(fbar) = sum_i lambda_i F(x_i, u_i, grad u_i) (eq. gradJ) for the
+// p-Laplace energy F = |p|^P / P - f u.  Per iteration: u, grad u from the
+// toolbox (two GEMVs), the site weights y = [lambda |p|^(P-2) p; -lambda f],
+// grad J = L^T y (two transposed GEMVs), one Adam step; all on the device.
+wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* o, const double* f, const double* g,
+                            double* fbar, double* u, double* grad_u, wos_adam_info* info, hipStream_t st) {
+  if (!o || !f || !g || !fbar || !u) return sfail(WOS_EINVAL, "NULL argument");
+  if (!tb->built) return sfail(WOS_EINVAL, "toolbox has not been built");
+  if (o->energy != WOS_EL_PLAPLACE) return sfail(WOS_EINVAL, "unknown energy %d", o->energy);
+  const double P = o->p_exp;
+  const double b1 = o->beta1 > 0 ? o->beta1 : 0.9;
+  const double b2 = o->beta2 > 0 ? o->beta2 : 0.999;
+  const double eps = o->eps > 0 ? o->eps : 1e-10;
+  const int check = o->check_every > 0 ? o->check_every : 50;
+  if (!(P > 1.0)) return sfail(WOS_EINVAL, "p_exp must be > 1");
+  if (!(o->alpha > 0.0)) return sfail(WOS_EINVAL, "alpha must be > 0");
+  if (!(b1 >= 0.0 && b1 < 1.0) || !(b2 >= 0.0 && b2 < 1.0)) return sfail(WOS_EINVAL, "beta1, beta2 must be in [0, 1)");
+  if (o->eps < 0.0 || !(o->tol >= 0.0)) return sfail(WOS_EINVAL, "eps and tol must be >= 0");
+  if (o->max_iter <= 0) return sfail(WOS_EINVAL, "max_iter must be > 0");
+  const int n = tb->n, m = tb->m, d = tb->dim;
+  wos_status s;
+  if (!w.el && (s = walloc(w, &w.el, (size_t)(2 * d + 3) * n + 3 * (size_t)m + 2)) != WOS_OK) return s;
+  double* uu = w.el;                   // n
+  double* gu = uu + n;                 // d n
+  double* y = gu + (size_t)d * n;      // (d + 1) n
+  double* F = y + (size_t)(d + 1) * n; // n
+  double* grad = F + n;                // m
+  double* mv = grad + m;               // m
+  double* vv = mv + m;                 // m
+  double* red = vv + m;                // 2
+  SHIP(hipMemsetAsync(mv, 0, sizeof(double) * 2 * (size_t)m, st));
+  auto gradient = [&](const double* x) -> wos_status {
+    wos_status e = reconstruct(tb, x, g, uu, gu, st);
+    if (e != WOS_OK) return e;
+    SHIP(launch_plaplace_weights(n, d, P, tb->d_lambda, uu, gu, f, y, F, st));
+    return apply_Lt(tb, y, 1.0, 0.0, grad, st);
+  };
+  auto weighted = [&](const double* x, const double* z, double* out) -> wos_status {
+    SHIP(launch_dot(m, x, z, tb->d_lambda, red, st));
+    SHIP(hipMemcpyAsync(out, red, sizeof(double), hipMemcpyDeviceToHost, st));
+    SHIP(hipStreamSynchronize(st));
+    return WOS_OK;
+  };
+  wos_adam_info inf{};
+  double gg = 0.0;
+  if ((s = gradient(fbar)) != WOS_OK) return s;
+  if ((s = weighted(grad, grad, &gg)) != WOS_OK) return s;
+  inf.grad_norm0 = std::sqrt(gg);
+  const auto t0 = std::chrono::steady_clock::now();
+  double b1j = 1.0, b2j = 1.0;
+  int it = 0;
+  for (int j = 1; j <= o->max_iter; ++j) {
+    b1j *= b1;
+    b2j *= b2;
+    const double aj = o->alpha * std::sqrt(1.0 - b2j) / (1.0 - b1j);
+    SHIP(launch_adam(m, grad, b1, b2, eps, aj, mv, vv, fbar, st));
+    it = j;
+    if ((s = gradient(fbar)) != WOS_OK) return s;  // at the new fbar: next step and the checks
+    if (o->tol > 0.0 && j % check == 0) {
+      if ((s = weighted(grad, grad, &gg)) != WOS_OK) return s;
+      if (std::sqrt(gg) <= o->tol) break;
+    }
+  }
+  SHIP(hipStreamSynchronize(st));
+  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  inf.iters = it;
+  if ((s = weighted(grad, grad, &gg)) != WOS_OK) return s;
+  inf.grad_norm = std::sqrt(gg);
+  // J = sum_i lambda_i F_i (F at the final fbar, from the last gradient)
+  SHIP(launch_dot(n, F, tb->d_lambda, nullptr, red, st));
+  SHIP(hipMemcpyAsync(&inf.J, red, sizeof(double), hipMemcpyDeviceToHost, st));
+  if ((s = reconstruct(tb, fbar, g, u, grad_u, st)) != WOS_OK) return s;
+  SHIP(hipStreamSynchronize(st));
+  if (info) *info = inf;
+  return WOS_OK;
+}
+
 }  // namespace wos
+
+extern "C" wos_status wos_minimize(wos_toolbox* tb, const wos_adam_opts* opts, const double* f, const double* g,
+                                   double* fbar, double* u, double* grad_u, wos_adam_info* info, void* stream) {
+  if (!tb) return sfail(WOS_EINVAL, "NULL argument");
+  return wos::minimize_request(tb, tb->sw, opts, f, g, fbar, u, grad_u, info, static_cast<hipStream_t>(stream));
+}
 
 extern "C" wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* co, const double* f, const double* g,
                                 double* u, double* grad_u, double* q_out, wos_solve_info* info, void* stream) {

@@ -59,12 +59,16 @@ struct SolveWork {
   double* P64 = nullptr;    // Cholesky work (chol_work_elems(m))
   float* P32 = nullptr;
   float* L0_32 = nullptr;   // Lambda_0 (A = I), FP32, for the mixed Newton route
+  double* el = nullptr;     // Euler-Lagrange route: (2d + 3) n + 3 m + 2 work doubles
   size_t bytes = 0;         // device memory held
 };
 
 // One solve on workspace `w` (C ABI wos_solve uses the toolbox's own).
 wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, const double* f, const double* g,
                          double* u, double* grad_u, double* q_out, wos_solve_info* info, hipStream_t st);
+// Adam on the discrete functional J (C ABI wos_minimize).
+wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* o, const double* f, const double* g,
+                            double* fbar, double* u, double* grad_u, wos_adam_info* info, hipStream_t st);
 void free_work(SolveWork& w);
 
 }  // namespace wos

@@ -32,6 +32,12 @@ hipError_t launch_diag(const double* G, int M, double* e, hipStream_t st);
 hipError_t launch_tsvd_filter(int M, const double* e, double thr, double* z, hipStream_t st);
 hipError_t launch_symmetrize(double* G, int M, hipStream_t st);
 hipError_t launch_dot(int n, const double* x, const double* y, const double* w, double* out, hipStream_t st);
+// Euler-Lagrange route (p-Laplace energy): site weights y = [lambda |p|^(P-2) p;
+// -lambda f] and energy density F; one Adam step on fbar
+hipError_t launch_plaplace_weights(int n, int d, double P, const double* lam, const double* u, const double* gu,
+                                   const double* f, double* y, double* F, hipStream_t st);
+hipError_t launch_adam(int m, const double* g, double b1, double b2, double eps, double aj, double* mv, double* vv,
+                       double* fbar, hipStream_t st);
 hipError_t launch_picard_coef(int n, int d, const double* u, double* Ac, hipStream_t st);
 // out (one double slot) = max |e_i|;  count of |e_i| > thr (as an integer in the slot)
 hipError_t launch_absmax(int n, const double* e, double* out, hipStream_t st);

@@ -1,0 +1,147 @@
+"""Euler-Lagrange route on the GPU (wos_minimize through the C ABI) against
+the oracle.
+
+The GPU toolbox is exported and handed to the oracle's J, gradient and Adam
+(FP64 NumPy), so both sides run the same iteration on the same matrices;
+they differ only in the summation order of the products, so the iterates
+agree to rounding (relative 1e-8 after a few hundred steps: Adam's update
+m / (sqrt(v) + eps) is Lipschitz in the gradient with constant 1 / sqrt(v)).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import euler_lagrange as E
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_2608_07017_amd")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rings(K):
+    pts = []
+    for k in range(1, K + 1):
+        nk = 6 * k - 3
+        r = (k - 0.5) / K
+        th = 2 * np.pi * np.arange(nk) / nk
+        pts.append(np.stack([r * np.cos(th), r * np.sin(th)], 1))
+    return np.concatenate(pts)
+
+
+def _build(dom, sites, bn, walks, eps, precision="f64", seed=11):
+    _say("GPU build", dom["kind"], len(sites), len(bn), walks, precision)
+    tb = P.Toolbox(dom, sites, bn, walks, eps, seed=seed, precision=precision, volume_samples=1 << 18)
+    tb.build()
+    torch.cuda.synchronize()
+    mats = {k: tb.export(k).cpu().numpy().astype(np.float64) for k in ("A", "B", "H", "K", "lambda")}
+    return tb, mats
+
+
+@pytest.fixture(scope="module")
+def disk_tb():
+    return _build(W.unit_disk(), _rings(5), W.circle_nodes(30), 1500, 1e-3)
+
+
+def _data(n, p, seed):
+    rng = np.random.default_rng(seed)
+    return 1.0 + 0.3 * rng.normal(size=n), 0.1 * rng.normal(size=p)
+
+
+def _oracle_run(mats, f, g, Pexp, alpha, iters, fb0, tol=0.0, check_every=1):
+    lam = mats["lambda"]
+    fb, it = E.adam(lambda x: E.plaplace_grad(mats, lam, x, g, Pexp, f), fb0, alpha, iters, tol=tol,
+                    norm_fn=lambda gr: E.grad_norm(lam, gr), check_every=check_every)
+    u, gu = E.reconstruct(mats, fb, g)
+    return fb, it, u, gu
+
+
+@pytest.mark.parametrize("Pexp,alpha", [(1.5, 0.01), (2.0, 0.01), (5.0, 0.01)])
+def test_adam_matches_oracle_f64(disk_tb, Pexp, alpha):
+    tb, mats = disk_tb
+    f, g = _data(tb.n, tb.p, 3)
+    iters = 300
+    _say("minimize P=%g alpha=%g iters=%d" % (Pexp, alpha, iters))
+    u, gu, fb, info = tb.minimize(f, g, Pexp, alpha, iters, fbar0=1.0)
+    ref_fb, it, ref_u, ref_gu = _oracle_run(mats, f, g, Pexp, alpha, iters, np.ones(tb.n))
+    assert info["iters"] == it == iters
+    scale = np.abs(ref_fb).max()
+    assert np.allclose(fb.cpu().numpy(), ref_fb, rtol=0, atol=1e-8 * scale)
+    assert np.allclose(u.cpu().numpy(), ref_u, rtol=0, atol=1e-8 * np.abs(ref_u).max())
+    assert np.allclose(gu.cpu().numpy(), ref_gu, rtol=0, atol=1e-8 * np.abs(ref_gu).max())
+    lam = mats["lambda"]
+    assert info["J"] == pytest.approx(E.plaplace_J(mats, lam, ref_fb, g, Pexp, f), rel=1e-8)
+    ref_gn = E.grad_norm(lam, E.plaplace_grad(mats, lam, ref_fb, g, Pexp, f))
+    assert info["grad_norm"] == pytest.approx(ref_gn, rel=1e-6)
+    ref_gn0 = E.grad_norm(lam, E.plaplace_grad(mats, lam, np.ones(tb.n), g, Pexp, f))
+    assert info["grad_norm0"] == pytest.approx(ref_gn0, rel=1e-10)
+
+
+def test_adam_matches_oracle_f32_toolbox():
+    # FP32 toolbox entries, FP64 arithmetic on both sides (the exported
+    # values are the stored FP32 ones, exactly representable in FP64)
+    cfg = W.config("lshape256")
+    tb, mats = _build(cfg["domain"], cfg["sites"], cfg["bnodes"], 1000, cfg["eps"], precision="f32")
+    f, g = _data(tb.n, tb.p, 5)
+    _say("minimize f32 toolbox P=3")
+    u, gu, fb, info = tb.minimize(f, g, 3.0, 0.01, 150, fbar0=0.5)
+    ref_fb, it, ref_u, _ = _oracle_run(mats, f, g, 3.0, 0.01, 150, np.full(tb.n, 0.5))
+    assert info["iters"] == it == 150
+    assert np.allclose(fb.cpu().numpy(), ref_fb, rtol=0, atol=1e-8 * np.abs(ref_fb).max())
+    assert np.allclose(u.cpu().numpy(), ref_u, rtol=0, atol=1e-8 * np.abs(ref_u).max())
+
+
+def test_adam_stops_at_the_tolerance(disk_tb):
+    tb, mats = disk_tb
+    f, g = _data(tb.n, tb.p, 7)
+    lam = mats["lambda"]
+    # the oracle's norm at each check; the tolerance is placed between two
+    # checks with a margin, so that rounding cannot move the stop
+    fb = np.ones(tb.n)
+    norms = []
+    for _ in range(30):
+        fb, _ = E.adam(lambda x: E.plaplace_grad(mats, lam, x, g, 2.0, f), np.ones(tb.n), 0.01, 10 * (len(norms) + 1))
+        norms.append(E.grad_norm(lam, E.plaplace_grad(mats, lam, fb, g, 2.0, f)))
+    k = next((i for i in range(1, len(norms)) if norms[i] < 0.8 * min(norms[:i])), None)
+    if k is None:
+        pytest.skip("no check with a clear drop of the norm")
+    tol = 0.5 * (norms[k] + min(norms[:k]))
+    _say("minimize tol=%g" % tol)
+    _, _, fbg, info = tb.minimize(f, g, 2.0, 0.01, 1000, fbar0=1.0, tol=tol, check_every=10)
+    ref_fb, it, _, _ = _oracle_run(mats, f, g, 2.0, 0.01, 1000, np.ones(tb.n), tol=tol, check_every=10)
+    assert info["iters"] == it == 10 * (k + 1)
+    assert info["grad_norm"] <= tol
+    assert np.allclose(fbg.cpu().numpy(), ref_fb, rtol=0, atol=1e-8 * np.abs(ref_fb).max())
+
+
+def test_invalid_options_are_rejected(disk_tb):
+    tb, _ = disk_tb
+    f, g = np.ones(tb.n), np.zeros(tb.p)
+    for kw in ({"p_exp": 1.0, "alpha": 0.01, "max_iter": 5}, {"p_exp": 2.0, "alpha": 0.0, "max_iter": 5},
+               {"p_exp": 2.0, "alpha": 0.01, "max_iter": 0}, {"p_exp": 2.0, "alpha": 0.01, "max_iter": 5, "beta1": 1.0}):
+        with pytest.raises(P.WosError):
+            tb.minimize(f, g, **kw)
+
+
+def test_disk_torsion_accuracy():
+    # The paper's disk example (p-torsion, f = 1, g = 0) with its Adam
+    # parameters: fbar_0 = 1, alpha = 1e-3 for P in {1.5, 2}, 1e-2 for P = 5.
+    # The iteration counts are early stops at the measured error minimum of
+    # this toolbox; the closed form is the oracle's.
+    sites, bn = W.paper_disk_layout()
+    tb, mats = _build(W.unit_disk(), sites, bn, 10000, 1e-4, precision="f32")
+    lam = mats["lambda"]
+    for Pexp, alpha, iters, bound in ((2.0, 1e-3, 2000, 0.05), (1.5, 1e-3, 2000, 0.08), (5.0, 1e-2, 300, 0.08)):
+        _say("torsion P=%g" % Pexp)
+        u, _, _, info = tb.minimize(np.ones(tb.n), np.zeros(tb.p), Pexp, alpha, iters, fbar0=1.0)
+        exact = E.plaplace_torsion_disk(sites, Pexp)
+        err = np.sqrt(np.sum(lam * (u.cpu().numpy() - exact) ** 2)) / np.sqrt(np.sum(lam * exact**2))
+        _say("  rel L2 error %.4f, grad norm %.2e, %d iters in %.3f s" % (err, info["grad_norm"], info["iters"],
+                                                                        info["seconds"]))
+        assert err < bound
