@@ -15,7 +15,9 @@ stream of Dirichlet problems on resident L-shape toolboxes (256/1024/4096
 sites), mixed precision against FP64, with the L2 errors of both against
 the manufactured solutions, and "newton_ball4096": the 3-D unit-ball
 toolbox build and a regularised Newton solve of -Lap u + u^3 = f, mixed
-precision against FP64.
+precision against FP64, and "el_plaplace": Adam on the discrete p-Laplace
+functional (the paper's disk p-torsion example and the iteration rate on
+the 4096-site L-shape toolbox).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-serving]
 
@@ -87,6 +89,10 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the served-solve stream")
     ap.add_argument("--no-newton", action="store_true", help="skip the 3-D Newton run")
     ap.add_argument("--newton-iters", type=int, default=10)
+    ap.add_argument("--no-el", action="store_true", help="skip the Euler-Lagrange (Adam) runs")
+    ap.add_argument("--el-walks", type=int, default=100000)
+    ap.add_argument("--el-max-iter", type=int, default=20000)
+    ap.add_argument("--el-rate-iters", type=int, default=100)
     ap.add_argument("--newton-rcond", type=float, default=1e-2)
     ap.add_argument("--serve-requests", type=int, default=2000, help="open-loop requests (mixed precision)")
     ap.add_argument("--serve-saturation", type=int, default=300, help="requests of the saturation run")
@@ -322,6 +328,55 @@ def newton_ball(a, torch, W, P):
     return out
 
 
+def el_plaplace(a, torch, W, P):
+    """Euler-Lagrange route: Adam on the discrete p-Laplace functional.
+
+    (1) The paper's p-torsion example on the unit disk (its ring layout: 300
+    sites, 60 boundary nodes; 1e5 walks/site, eps 1e-4, FP32 toolbox),
+    f = 1, g = 0, Adam with the paper's fbar_0 = 1 and step sizes, run until
+    the gradient norm reaches the paper's final values (1e-5 for P <= 2,
+    5e-6 otherwise, in absolute cell measures; divided here by sqrt(|D|) for
+    the normalised weights), checked every 50 iterations; relative L2 error
+    against the closed form.  (2) The iteration rate on the 4096-site
+    L-shape toolbox (FP32), where each iteration streams the toolbox twice
+    (u, grad u forward and grad J back): achieved bytes / s against HBM."""
+    sites, bn = W.paper_disk_layout()
+    tb = P.Toolbox(W.unit_disk(), sites, bn, a.el_walks, 1e-4, seed=11, precision="f32", volume_samples=1 << 20)
+    tb.build()
+    torch.cuda.synchronize()
+    lam = tb.export("lambda").cpu().numpy()
+    rows = {}
+    for Pexp, alpha, paper_norm in ((1.5, 1e-3, 1e-5), (2.0, 1e-3, 1e-5), (5.0, 1e-2, 5e-6), (10.0, 1e-2, 5e-6),
+                                    (50.0, 1e-1, 5e-6)):
+        tol = paper_norm / np.sqrt(np.pi)
+        u, _, _, info = tb.minimize(np.ones(tb.n), np.zeros(tb.p), Pexp, alpha, a.el_max_iter, fbar0=1.0, tol=tol,
+                                    check_every=50)
+        ex = W.plaplace_torsion_disk_exact(sites, Pexp)
+        err = float(np.sqrt(np.sum(lam * (u.cpu().numpy() - ex) ** 2)) / np.sqrt(np.sum(lam * ex ** 2)))
+        rows["P=%g" % Pexp] = {"alpha": alpha, "iters": info["iters"], "seconds": info["seconds"],
+                               "iters_per_s": info["iters"] / info["seconds"], "grad_norm": info["grad_norm"],
+                               "tol": tol, "J": info["J"], "rel_l2_error": err}
+    tb.free()
+    out = {"workload": "paper disk p-torsion: 300 ring sites, 60 nodes, %g walks/site, eps 1e-4, FP32; Adam "
+                       "(beta 0.9/0.999, eps 1e-10, fbar_0 = 1) to the paper's gradient norms" % a.el_walks,
+           "disk": rows}
+    cfg = W.config("lshape4096")
+    tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], 1000, cfg["eps"], seed=cfg["seed"], precision="f32")
+    tb.build()
+    torch.cuda.synchronize()
+    n, p, d = tb.n, tb.p, tb.dim
+    f, g = np.ones(n), np.zeros(p)
+    tb.minimize(f, g, 2.0, 1e-3, 5)
+    _, _, _, info = tb.minimize(f, g, 2.0, 1e-3, a.el_rate_iters)
+    per_iter = info["seconds"] / info["iters"]
+    bytes_iter = 2.0 * (d + 1) * n * (n + p) * 4  # the FP32 toolbox read forward and back
+    out["lshape4096"] = {"iters": info["iters"], "us_per_iter": per_iter * 1e6,
+                         "toolbox_bytes_per_iter": bytes_iter, "achieved_GBps": bytes_iter / per_iter / 1e9,
+                         "hbm_frac": bytes_iter / per_iter / 8e12}
+    tb.free()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -410,6 +465,9 @@ def main():
         out["newton_ball4096"] = newton_ball(a, torch, W, P)
     if a.cubeball:
         out["picard_cubeball32768"] = picard_cubeball(a, torch, W, P)
+    if not a.no_el:
+        print("euler-lagrange: disk p-torsion, lshape4096", file=sys.stderr, flush=True)
+        out["el_plaplace"] = el_plaplace(a, torch, W, P)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_rows)
     print(json.dumps(out), flush=True)

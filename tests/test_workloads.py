@@ -27,3 +27,10 @@ def test_served_problem_source_for_constant_coefficients():
     h = 1e-5
     div = sum((gu(x + h * e)[:, a] - gu(x - h * e)[:, a]) / (2 * h) for a, e in enumerate(np.eye(2)))
     assert np.allclose(div, lap(x), rtol=1e-6, atol=1e-7)
+
+
+def test_torsion_exact_solution_matches_the_oracle():
+    from oracle.euler_lagrange import plaplace_torsion_disk
+    x = np.random.default_rng(1).uniform(-0.7, 0.7, size=(50, 2))
+    for P in (1.5, 2.0, 5.0, 50.0):
+        assert np.allclose(W.plaplace_torsion_disk_exact(x, P), plaplace_torsion_disk(x, P), rtol=1e-14, atol=0)

@@ -186,6 +186,15 @@ def paper_disk_layout():
     return np.concatenate(pts), circle_nodes(60)
 
 
+def plaplace_torsion_disk_exact(x, P):
+    """Exact solution of the paper's p-torsion example on the unit disk
+    (-div(|grad u|^(P-2) grad u) = 1, u = 0 on the circle):
+    (P-1)/P (1/2)^(1/(P-1)) (1 - |x|^(P/(P-1))).  Problem data for
+    reporting errors, like the manufactured solutions here."""
+    r2 = np.sum(np.asarray(x, dtype=np.float64) ** 2, axis=-1)
+    return (P - 1.0) / P * 0.5 ** (1.0 / (P - 1.0)) * (1.0 - np.power(r2, P / (2.0 * P - 2.0)))
+
+
 def paper_square_layout():
     """20 x 20 cell centres of the unit square, 20 boundary nodes per edge."""
     g = (np.arange(20) + 0.5) / 20.0
