@@ -338,8 +338,9 @@ def el_plaplace(a, torch, W, P):
     5e-6 otherwise, in absolute cell measures; divided here by sqrt(|D|) for
     the normalised weights), checked every 50 iterations; relative L2 error
     against the closed form.  (2) The iteration rate on the 4096-site
-    L-shape toolbox (FP32), where each iteration streams the toolbox twice
-    (u, grad u forward and grad J back): achieved bytes / s against HBM."""
+    L-shape toolbox (FP32), where each iteration streams B twice (grad u
+    forward, grad J back; the A and K terms are constants of the
+    iteration): achieved bytes / s against HBM."""
     sites, bn = W.paper_disk_layout()
     tb = P.Toolbox(W.unit_disk(), sites, bn, a.el_walks, 1e-4, seed=11, precision="f32", volume_samples=1 << 20)
     tb.build()
@@ -369,9 +370,11 @@ def el_plaplace(a, torch, W, P):
     tb.minimize(f, g, 2.0, 1e-3, 5)
     _, _, _, info = tb.minimize(f, g, 2.0, 1e-3, a.el_rate_iters)
     per_iter = info["seconds"] / info["iters"]
-    bytes_iter = 2.0 * (d + 1) * n * (n + p) * 4  # the FP32 toolbox read forward and back
+    # an iteration streams B (d n x m, FP32) twice: B fbar, then B^T yB; the
+    # A and K terms of the gradient are constants of the iteration
+    bytes_iter = 2.0 * d * n * n * 4
     out["lshape4096"] = {"iters": info["iters"], "us_per_iter": per_iter * 1e6,
-                         "toolbox_bytes_per_iter": bytes_iter, "achieved_GBps": bytes_iter / per_iter / 1e9,
+                         "B_bytes_per_iter": bytes_iter, "achieved_GBps": bytes_iter / per_iter / 1e9,
                          "hbm_frac": bytes_iter / per_iter / 8e12}
     tb.free()
     return out

@@ -293,10 +293,12 @@ typedef struct {
  *   info    host, optional.
  * Every step runs on the device (the toolbox GEMVs in FP64 accumulation,
  * the site weights and the Adam update); the host reads one scalar per
- * norm check.  Runs on `stream` and synchronises it before returning.
+ * norm check.  As dF/du = -f does not depend on u, A^T (lambda o f) and
+ * K g are formed once and an iteration streams only B (forward and
+ * transposed); u and J are formed at the end.  Runs on `stream` and synchronises it before returning.
  * Errors: WOS_EINVAL for a NULL pointer, an unbuilt toolbox, an unknown
  * energy, P <= 1, alpha <= 0, beta outside [0, 1), eps < 0 or
- * max_iter <= 0.  The work vectors ((2d + 3) n + 3 m doubles) are allocated
+ * max_iter <= 0.  The work vectors ((3d + 3) n + 3 m doubles) are allocated
  * on the first call and kept with the toolbox.  Not thread-safe for one
  * toolbox.                                                                   */
 wos_status wos_minimize(wos_toolbox* tb, const wos_adam_opts* opts, const double* f, const double* g,

@@ -199,11 +199,33 @@ __global__ void plaplace_weights_kernel(int n, int d, double P, const double* __
   }
 }
 
+// The gradient part of the same weights, for an energy whose dF/du does not
+// depend on u: yB[a n + i] = lambda_i |p|^(P-2) p_a with p = gB + kg (gB =
+// B fbar, kg = K g fixed over the iteration).
+__global__ void plaplace_wb_kernel(int n, int d, double P, const double* __restrict__ lam,
+                                   const double* __restrict__ gB, const double* __restrict__ kg,
+                                   double* __restrict__ yB) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += stride) {
+    double pa[3] = {0.0, 0.0, 0.0};
+    double s = 0.0;
+    for (int a = 0; a < d; ++a) {
+      pa[a] = gB[(size_t)a * n + i] + (kg ? kg[(size_t)a * n + i] : 0.0);
+      s += pa[a] * pa[a];
+    }
+    const double c = s > 0.0 ? lam[i] * pow(s, 0.5 * (P - 2.0)) : 0.0;
+    for (int a = 0; a < d; ++a) yB[(size_t)a * n + i] = c * pa[a];
+  }
+}
+
 // One Adam step (the appendix on the optimisation of J): m <- b1 m +
 // (1 - b1) g, v <- b2 v + (1 - b2) g^2, fbar <- fbar - a_j m / (sqrt(v) + eps),
-// with the bias-corrected step a_j computed on the host.
-__global__ void adam_kernel(int m, const double* __restrict__ g, double b1, double b2, double eps, double aj,
-                            double* __restrict__ mv, double* __restrict__ vv, double* __restrict__ fbar) {
+// with the bias-corrected step a_j computed on the host.  With `reset`,
+// g is then set to it (the constant part of the next gradient, onto which
+// the next one is accumulated).
+__global__ void adam_kernel(int m, double* __restrict__ g, double b1, double b2, double eps, double aj,
+                            double* __restrict__ mv, double* __restrict__ vv, double* __restrict__ fbar,
+                            const double* __restrict__ reset) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < (size_t)m; j += stride) {
     const double gj = g[j];
@@ -212,6 +234,7 @@ __global__ void adam_kernel(int m, const double* __restrict__ g, double b1, doub
     mv[j] = mj;
     vv[j] = vj;
     fbar[j] -= aj * mj / (sqrt(vj) + eps);
+    if (reset) g[j] = reset[j];
   }
 }
 
@@ -573,9 +596,17 @@ hipError_t launch_plaplace_weights(int n, int d, double P, const double* lam, co
   return hipGetLastError();
 }
 
-hipError_t launch_adam(int m, const double* g, double b1, double b2, double eps, double aj, double* mv, double* vv,
-                       double* fbar, hipStream_t st) {
-  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, g, b1, b2, eps, aj, mv, vv, fbar);
+hipError_t launch_plaplace_wb(int n, int d, double P, const double* lam, const double* gB, const double* kg,
+                              double* yB, hipStream_t st) {
+  if (d < 1 || d > 3) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(plaplace_wb_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d, P, lam, gB, kg, yB);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(int m, double* g, double b1, double b2, double eps, double aj, double* mv, double* vv,
+                       double* fbar, const double* reset, hipStream_t st) {
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, g, b1, b2, eps, aj, mv, vv, fbar,
+                     reset);
   return hipGetLastError();
 }
 

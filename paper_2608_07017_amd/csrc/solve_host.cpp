@@ -631,9 +631,12 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
 
 // ------------------------------------------------ Euler-Lagrange route
 // Adam on J(fbar) = sum_i lambda_i F(x_i, u_i, grad u_i) (eq. gradJ) for the
-// p-Laplace energy F = |p|^P / P - f u.  Per iteration: u, grad u from the
-// toolbox (two GEMVs), the site weights y = [lambda |p|^(P-2) p; -lambda f],
-// grad J = L^T y (two transposed GEMVs), one Adam step; all on the device.
+// p-Laplace energy F = |p|^P / P - f u.  Its dF/du = -f does not depend on
+// u, so grad J = c + B^T yB with the constant c = A^T (-lambda o f) and
+// yB = lambda |p|^(P-2) p, p = B fbar + K g (K g fixed too).  An iteration
+// therefore streams B twice (B fbar, then B^T yB accumulated onto c) and
+// nothing else: four kernels, all on the device.  u = A fbar + H g and J
+// are formed once at the end.
 wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* o, const double* f, const double* g,
                             double* fbar, double* u, double* grad_u, wos_adam_info* info, hipStream_t st) {
   if (!o || !f || !g || !fbar || !u) return sfail(WOS_EINVAL, "NULL argument");
@@ -649,23 +652,34 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
   if (!(b1 >= 0.0 && b1 < 1.0) || !(b2 >= 0.0 && b2 < 1.0)) return sfail(WOS_EINVAL, "beta1, beta2 must be in [0, 1)");
   if (o->eps < 0.0 || !(o->tol >= 0.0)) return sfail(WOS_EINVAL, "eps and tol must be >= 0");
   if (o->max_iter <= 0) return sfail(WOS_EINVAL, "max_iter must be > 0");
-  const int n = tb->n, m = tb->m, d = tb->dim;
+  const int n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
   wos_status s;
-  if (!w.el && (s = walloc(w, &w.el, (size_t)(2 * d + 3) * n + 3 * (size_t)m + 2)) != WOS_OK) return s;
-  double* uu = w.el;                   // n
-  double* gu = uu + n;                 // d n
-  double* y = gu + (size_t)d * n;      // (d + 1) n
-  double* F = y + (size_t)(d + 1) * n; // n
-  double* grad = F + n;                // m
-  double* mv = grad + m;               // m
-  double* vv = mv + m;                 // m
-  double* red = vv + m;                // 2
+  if (!w.el && (s = walloc(w, &w.el, (size_t)(3 * d + 3) * n + 3 * (size_t)m + 2)) != WOS_OK) return s;
+  double* cvec = w.el;                  // m (= n): c = A^T (-lambda o f)
+  double* gB = cvec + m;                // d n: B fbar (at the end: grad u when the caller passes none)
+  double* yB = gB + (size_t)d * n;      // (d + 1) n: the B weights, then -lambda f; at the end all weights
+  double* yA = yB + (size_t)d * n;      //   its last n
+  double* kgv = yB + (size_t)(d + 1) * n;  // d n: K g
+  double* F = kgv + (size_t)d * n;      // n: the energy density at the end
+  double* grad = F + n;                 // m
+  double* mv = grad + m;                // m
+  double* vv = mv + m;                  // m
+  double* red = vv + m;                 // 2
   SHIP(hipMemsetAsync(mv, 0, sizeof(double) * 2 * (size_t)m, st));
+  // constants of the iteration: c = A^T (-lambda o f) and K g
+  SHIP(launch_pointwise(n, tb->d_lambda, nullptr, f, 0.0, 0.0, 0.0, 0.0, 1.0, yA, st));  // -lambda f
+  SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, yA, 1.0, 0.0, cvec, st));
+  if (p > 0)
+    SHIP(launch_gemv_n_ld(tb->f64, tb->d_K, d * n, p, p, g, 1.0, 0.0, kgv, st));
+  else
+    SHIP(hipMemsetAsync(kgv, 0, sizeof(double) * (size_t)d * n, st));
+  SHIP(hipMemcpyAsync(grad, cvec, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+  // grad += B^T yB(x)  (grad holds c on entry)
   auto gradient = [&](const double* x) -> wos_status {
-    wos_status e = reconstruct(tb, x, g, uu, gu, st);
-    if (e != WOS_OK) return e;
-    SHIP(launch_plaplace_weights(n, d, P, tb->d_lambda, uu, gu, f, y, F, st));
-    return apply_Lt(tb, y, 1.0, 0.0, grad, st);
+    SHIP(launch_gemv_n_ld(tb->f64, tb->d_B, d * n, m, m, x, 1.0, 0.0, gB, st));
+    SHIP(launch_plaplace_wb(n, d, P, tb->d_lambda, gB, kgv, yB, st));
+    SHIP(launch_gemv_t_acc(tb->f64, tb->d_B, d * n, m, m, yB, 1.0, grad, st));
+    return WOS_OK;
   };
   auto weighted = [&](const double* x, const double* z, double* out) -> wos_status {
     SHIP(launch_dot(m, x, z, tb->d_lambda, red, st));
@@ -685,7 +699,7 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
     b1j *= b1;
     b2j *= b2;
     const double aj = o->alpha * std::sqrt(1.0 - b2j) / (1.0 - b1j);
-    SHIP(launch_adam(m, grad, b1, b2, eps, aj, mv, vv, fbar, st));
+    SHIP(launch_adam(m, grad, b1, b2, eps, aj, mv, vv, fbar, cvec, st));  // grad <- c afterwards
     it = j;
     if ((s = gradient(fbar)) != WOS_OK) return s;  // at the new fbar: next step and the checks
     if (o->tol > 0.0 && j % check == 0) {
@@ -698,10 +712,11 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
   inf.iters = it;
   if ((s = weighted(grad, grad, &gg)) != WOS_OK) return s;
   inf.grad_norm = std::sqrt(gg);
-  // J = sum_i lambda_i F_i (F at the final fbar, from the last gradient)
+  // u, grad u and J = sum_i lambda_i F_i at the result
+  if ((s = reconstruct(tb, fbar, g, u, grad_u ? grad_u : gB, st)) != WOS_OK) return s;
+  SHIP(launch_plaplace_weights(n, d, P, tb->d_lambda, u, grad_u ? grad_u : gB, f, yB, F, st));
   SHIP(launch_dot(n, F, tb->d_lambda, nullptr, red, st));
   SHIP(hipMemcpyAsync(&inf.J, red, sizeof(double), hipMemcpyDeviceToHost, st));
-  if ((s = reconstruct(tb, fbar, g, u, grad_u, st)) != WOS_OK) return s;
   SHIP(hipStreamSynchronize(st));
   if (info) *info = inf;
   return WOS_OK;

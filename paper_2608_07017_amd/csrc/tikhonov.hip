@@ -12,6 +12,8 @@
 // (row block a, then site i).
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 #include "wos_solve_kernels.hpp"
 
 namespace wos {
@@ -113,6 +115,102 @@ __global__ __launch_bounds__(256) void gemv_n_ld_kernel(const T* __restrict__ X,
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if (lane == 0) y[row] = alpha * acc + (beta == 0.0 ? 0.0 : beta * y[row]);
+}
+
+// 16-byte loads of four consecutive FP32 elements
+__device__ __forceinline__ void load4(const float* p, double (&x)[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  x[0] = q.x;
+  x[1] = q.y;
+  x[2] = q.z;
+  x[3] = q.w;
+}
+
+// y[j] += alpha sum_r X[r][j] v[r] for an FP32 X with rows aligned to 16
+// bytes and cols % 4 == 0: lane l of wavefront w takes columns
+// c0 + 4l .. c0 + 4l + 3 of rows r0 + w, r0 + w + 4, ... (16-byte loads, the
+// wavefront reading 1 KB of one row at a time, four rows in flight); the
+// four wavefronts' sums
+// are added in LDS and each column gets one atomic per block of T4_ROWS rows.
+constexpr int T4_ROWS = 512;
+__global__ __launch_bounds__(256) void gemv_t4_kernel(const float* __restrict__ X, int rows, int cols, int ld,
+                                                      const double* __restrict__ v, double alpha,
+                                                      double* __restrict__ y) {
+  __shared__ double part[3][64][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.x * 256 + 4 * lane;
+  const int r0 = blockIdx.y * T4_ROWS, r1 = min(rows, r0 + T4_ROWS);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (c < cols) {
+    int r = r0 + wave;
+    for (; r + 12 < r1; r += 16) {  // four rows in flight per lane
+      double xa[4], xb[4], xc[4], xd[4];
+      load4(X + (size_t)r * ld + c, xa);
+      load4(X + (size_t)(r + 4) * ld + c, xb);
+      load4(X + (size_t)(r + 8) * ld + c, xc);
+      load4(X + (size_t)(r + 12) * ld + c, xd);
+      const double va = v[r], vb = v[r + 4], vc = v[r + 8], vd = v[r + 12];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = fma(xd[q], vd, fma(xc[q], vc, fma(xb[q], vb, fma(xa[q], va, acc[q]))));
+    }
+    for (; r < r1; r += 4) {
+      double xa[4];
+      load4(X + (size_t)r * ld + c, xa);
+      const double va = v[r];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = fma(xa[q], va, acc[q]);
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[wave - 1][lane][q] = acc[q];
+  }
+  __syncthreads();
+  if (wave == 0 && c < cols) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double t = acc[q] + part[0][lane][q] + part[1][lane][q] + part[2][lane][q];
+      if (t != 0.0) atomicAdd(&y[c + q], alpha * t);
+    }
+  }
+}
+
+// y[i] = alpha sum_j X[i][j] v[j] + beta y[i] for an FP32 X with rows
+// aligned to 16 bytes and cols % 4 == 0: one wavefront per row, 16-byte
+// loads (each lane four consecutive elements, the wavefront 1 KB at a time)
+__global__ __launch_bounds__(256) void gemv_n4_kernel(const float* __restrict__ X, int rows, int cols, int ld,
+                                                      const double* __restrict__ v, double alpha, double beta,
+                                                      double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const float* xr = X + (size_t)row * ld;
+  double acc = 0.0, acc2 = 0.0;
+  int j = 4 * lane;
+  for (; j + 256 < cols; j += 512) {  // two loads in flight per lane
+    double xa[4], xb[4];
+    load4(xr + j, xa);
+    load4(xr + j + 256, xb);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc = fma(xa[q], v[j + q], acc);
+      acc2 = fma(xb[q], v[j + 256 + q], acc2);
+    }
+  }
+  if (j < cols) {
+    double xa[4];
+    load4(xr + j, xa);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc = fma(xa[q], v[j + q], acc);
+  }
+  acc += acc2;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) y[row] = alpha * acc + (beta == 0.0 ? 0.0 : beta * y[row]);
+}
+
+bool rows16(const void* X, int ld, int cols) {
+  return ((uintptr_t)X % 16) == 0 && (ld % 4) == 0 && (cols % 4) == 0;
 }
 
 __global__ void scale_kernel(int n, double beta, double* __restrict__ y) {
@@ -218,6 +316,30 @@ hipError_t launch_gemv_t_ld(bool f64, const void* X, int rows, int cols, int ld,
                             double beta, double* y, hipStream_t st) {
   hipLaunchKernelGGL(scale_kernel, dim3(nblocks(cols, 256)), dim3(256), 0, st, cols, beta, y);
   if (rows <= 0) return hipGetLastError();
+  if (!f64 && rows16(X, ld, cols)) {
+    const dim3 g4((cols + 255) / 256, (rows + T4_ROWS - 1) / T4_ROWS);
+    hipLaunchKernelGGL(gemv_t4_kernel, g4, dim3(256), 0, st, (const float*)X, rows, cols, ld, v, alpha, y);
+    return hipGetLastError();
+  }
+  const int chunk = 128;
+  const dim3 g((cols + 255) / 256, (rows + chunk - 1) / chunk);
+  if (f64)
+    hipLaunchKernelGGL(gemv_t_split_kernel<double>, g, dim3(256), 0, st, (const double*)X, rows, cols, ld, v, alpha, y,
+                       chunk);
+  else
+    hipLaunchKernelGGL(gemv_t_split_kernel<float>, g, dim3(256), 0, st, (const float*)X, rows, cols, ld, v, alpha, y,
+                       chunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_t_acc(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
+                             double* y, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  if (!f64 && rows16(X, ld, cols)) {
+    const dim3 g4((cols + 255) / 256, (rows + T4_ROWS - 1) / T4_ROWS);
+    hipLaunchKernelGGL(gemv_t4_kernel, g4, dim3(256), 0, st, (const float*)X, rows, cols, ld, v, alpha, y);
+    return hipGetLastError();
+  }
   const int chunk = 128;
   const dim3 g((cols + 255) / 256, (rows + chunk - 1) / chunk);
   if (f64)
@@ -232,7 +354,10 @@ hipError_t launch_gemv_t_ld(bool f64, const void* X, int rows, int cols, int ld,
 hipError_t launch_gemv_n_ld(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
                             double beta, double* y, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  if (f64)
+  if (!f64 && rows16(X, ld, cols))
+    hipLaunchKernelGGL(gemv_n4_kernel, dim3((rows + 3) / 4), dim3(256), 0, st, (const float*)X, rows, cols, ld, v,
+                       alpha, beta, y);
+  else if (f64)
     hipLaunchKernelGGL(gemv_n_ld_kernel<double>, dim3((rows + 3) / 4), dim3(256), 0, st, (const double*)X, rows, cols,
                        ld, v, alpha, beta, y);
   else

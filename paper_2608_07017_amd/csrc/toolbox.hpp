@@ -59,7 +59,7 @@ struct SolveWork {
   double* P64 = nullptr;    // Cholesky work (chol_work_elems(m))
   float* P32 = nullptr;
   float* L0_32 = nullptr;   // Lambda_0 (A = I), FP32, for the mixed Newton route
-  double* el = nullptr;     // Euler-Lagrange route: (2d + 3) n + 3 m + 2 work doubles
+  double* el = nullptr;     // Euler-Lagrange route: (3d + 3) n + 3 m + 2 work doubles
   size_t bytes = 0;         // device memory held
 };
 

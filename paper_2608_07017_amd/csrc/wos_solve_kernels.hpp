@@ -36,8 +36,10 @@ hipError_t launch_dot(int n, const double* x, const double* y, const double* w, 
 // -lambda f] and energy density F; one Adam step on fbar
 hipError_t launch_plaplace_weights(int n, int d, double P, const double* lam, const double* u, const double* gu,
                                    const double* f, double* y, double* F, hipStream_t st);
-hipError_t launch_adam(int m, const double* g, double b1, double b2, double eps, double aj, double* mv, double* vv,
-                       double* fbar, hipStream_t st);
+hipError_t launch_plaplace_wb(int n, int d, double P, const double* lam, const double* gB, const double* kg,
+                              double* yB, hipStream_t st);
+hipError_t launch_adam(int m, double* g, double b1, double b2, double eps, double aj, double* mv, double* vv,
+                       double* fbar, const double* reset, hipStream_t st);
 hipError_t launch_picard_coef(int n, int d, const double* u, double* Ac, hipStream_t st);
 // out (one double slot) = max |e_i|;  count of |e_i| > thr (as an integer in the slot)
 hipError_t launch_absmax(int n, const double* e, double* out, hipStream_t st);
@@ -77,6 +79,9 @@ hipError_t launch_weight_rows_any(bool f64_in, bool f32_out, const void* A, cons
                                   const double* cc, int n, int m, int p, int d, int cols, void* R, hipStream_t st);
 hipError_t launch_apply_w(int n, int d, const double* lam, const double* Ac, const double* bc, const double* cc,
                           const double* y, bool trans, const double* f, double* z, hipStream_t st);
+// y += alpha X^T v (no scaling of y first)
+hipError_t launch_gemv_t_acc(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
+                             double* y, hipStream_t st);
 hipError_t launch_gemv_t_ld(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
                             double beta, double* y, hipStream_t st);
 hipError_t launch_gemv_n_ld(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
