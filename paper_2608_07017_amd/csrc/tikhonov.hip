@@ -131,15 +131,14 @@ __device__ __forceinline__ void load4(const float* p, double (&x)[4]) {
 // c0 + 4l .. c0 + 4l + 3 of rows r0 + w, r0 + w + 4, ... (16-byte loads, the
 // wavefront reading 1 KB of one row at a time, four rows in flight); the
 // four wavefronts' sums
-// are added in LDS and each column gets one atomic per block of T4_ROWS rows.
-constexpr int T4_ROWS = 512;
+// are added in LDS and each column gets one atomic per block of `rpb` rows.
 __global__ __launch_bounds__(256) void gemv_t4_kernel(const float* __restrict__ X, int rows, int cols, int ld,
                                                       const double* __restrict__ v, double alpha,
-                                                      double* __restrict__ y) {
+                                                      double* __restrict__ y, int rpb) {
   __shared__ double part[3][64][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = blockIdx.x * 256 + 4 * lane;
-  const int r0 = blockIdx.y * T4_ROWS, r1 = min(rows, r0 + T4_ROWS);
+  const int r0 = blockIdx.y * rpb, r1 = min(rows, r0 + rpb);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (c < cols) {
     int r = r0 + wave;
@@ -211,6 +210,18 @@ __global__ __launch_bounds__(256) void gemv_n4_kernel(const float* __restrict__ 
 
 bool rows16(const void* X, int ld, int cols) {
   return ((uintptr_t)X % 16) == 0 && (ld % 4) == 0 && (cols % 4) == 0;
+}
+
+// Rows per block of gemv_t4_kernel: 512 when that still gives 256 blocks
+// (fewer atomics per column measured faster than more blocks), otherwise
+// halved down to 32 so that small products are not a few long loops.
+void launch_gemv_t4(const float* X, int rows, int cols, int ld, const double* v, double alpha, double* y,
+                    hipStream_t st) {
+  const int cb = (cols + 255) / 256;
+  int rpb = 512;
+  while (rpb > 32 && (size_t)cb * ((rows + rpb - 1) / rpb) < 256) rpb /= 2;
+  const dim3 g4(cb, (rows + rpb - 1) / rpb);
+  hipLaunchKernelGGL(gemv_t4_kernel, g4, dim3(256), 0, st, X, rows, cols, ld, v, alpha, y, rpb);
 }
 
 __global__ void scale_kernel(int n, double beta, double* __restrict__ y) {
@@ -317,8 +328,7 @@ hipError_t launch_gemv_t_ld(bool f64, const void* X, int rows, int cols, int ld,
   hipLaunchKernelGGL(scale_kernel, dim3(nblocks(cols, 256)), dim3(256), 0, st, cols, beta, y);
   if (rows <= 0) return hipGetLastError();
   if (!f64 && rows16(X, ld, cols)) {
-    const dim3 g4((cols + 255) / 256, (rows + T4_ROWS - 1) / T4_ROWS);
-    hipLaunchKernelGGL(gemv_t4_kernel, g4, dim3(256), 0, st, (const float*)X, rows, cols, ld, v, alpha, y);
+    launch_gemv_t4((const float*)X, rows, cols, ld, v, alpha, y, st);
     return hipGetLastError();
   }
   const int chunk = 128;
@@ -336,8 +346,7 @@ hipError_t launch_gemv_t_acc(bool f64, const void* X, int rows, int cols, int ld
                              double* y, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   if (!f64 && rows16(X, ld, cols)) {
-    const dim3 g4((cols + 255) / 256, (rows + T4_ROWS - 1) / T4_ROWS);
-    hipLaunchKernelGGL(gemv_t4_kernel, g4, dim3(256), 0, st, (const float*)X, rows, cols, ld, v, alpha, y);
+    launch_gemv_t4((const float*)X, rows, cols, ld, v, alpha, y, st);
     return hipGetLastError();
   }
   const int chunk = 128;
