@@ -33,13 +33,17 @@ Readings (each listed in the design doc):
 * the paper gives final gradient norms but no stopping rule: a run stops
   after max_iter iterations or once the norm is at most tol.
 
+``interpolate`` evaluates a solution off the sites, piecewise constant on
+the cells or with the first-order correction <grad u_i, x - x_i>.
+
 Pinned by tests/test_oracle_euler_lagrange.py: the gradient against central
 differences of J, Adam's first step (of length alpha in every coordinate,
 a closed form of the update), Adam on a separable quadratic against its
 known minimiser, the route at P = 2 against the linear system of
 eq. linear_q (the two routes of the paper coincide for the quadratic
 energy), and the disk's closed-form p-torsion solution at P = 2 against
-(1 - |x|^2) / 4.
+(1 - |x|^2) / 4; the interpolation reproduces affine fields exactly and
+returns u_i at the sites.
 """
 import numpy as np
 
@@ -106,6 +110,21 @@ def minimize_plaplace(tb, lam, f, g, P, alpha, max_iter, f0=1.0, tol=0.0, check_
     u, gu = reconstruct(tb, fb, g)
     return {"fbar": fb, "u": u, "grad_u": gu, "iters": it, "J": plaplace_J(tb, lam, fb, g, P, f),
             "grad_norm": grad_norm(lam, plaplace_grad(tb, lam, fb, g, P, f))}
+
+
+def interpolate(sites, u, grad_u, x):
+    """Evaluation off the sites (the approximations after eq.
+    min_el_discrete): for x in the cell W_i of its nearest site x_i,
+    u(x) ~ u_i + <grad u_i, x - x_i> (the gradient-enhanced form), or u_i
+    when grad_u is None (piecewise constant).  Returns (values, i)."""
+    from .voronoi import nearest
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    i = nearest(sites, x)
+    v = np.asarray(u, dtype=np.float64)[i].copy()
+    if grad_u is not None:
+        gu = np.asarray(grad_u, dtype=np.float64)
+        v += np.sum(gu[:, i].T * (x - np.asarray(sites, dtype=np.float64)[i]), axis=1)
+    return v, i
 
 
 def plaplace_torsion_disk(x, P):

@@ -132,3 +132,24 @@ def test_disk_torsion_end_to_end_early_stopped():
         out = E.minimize_plaplace(tb, lam, np.ones(n), np.zeros(30), P, alpha=1e-3, max_iter=2000, f0=1.0)
         err = np.sqrt(np.sum(lam * (out["u"] - exact) ** 2)) / np.sqrt(np.sum(lam * exact**2))
         assert err < bound
+
+
+def test_interpolation_reproduces_affine_fields():
+    # u(x) = a.x + b with its exact gradient at the sites: the
+    # gradient-enhanced form is exact everywhere, whatever the cells
+    rng = np.random.default_rng(9)
+    for d in (2, 3):
+        sites = rng.uniform(-1, 1, size=(50, d))
+        a, b = rng.normal(size=d), 0.7
+        u = sites @ a + b
+        gu = np.tile(a[:, None], (1, 50))
+        x = rng.uniform(-1, 1, size=(400, d))
+        v, i = E.interpolate(sites, u, gu, x)
+        assert np.allclose(v, x @ a + b, rtol=0, atol=1e-13)
+        # without the gradient: the value of the nearest site (brute force)
+        v0, i0 = E.interpolate(sites, u, None, x)
+        d2 = ((x[:, None, :] - sites[None, :, :]) ** 2).sum(2)
+        assert np.array_equal(i0, np.argmin(d2, axis=1)) and np.array_equal(v0, u[i0])
+        # at the sites themselves: u_i
+        vs, isite = E.interpolate(sites, u, gu, sites)
+        assert np.array_equal(isite, np.arange(50)) and np.allclose(vs, u, rtol=0, atol=1e-14)
