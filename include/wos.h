@@ -249,6 +249,23 @@ typedef struct {
 wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* coeffs, const double* f, const double* g,
                      double* u, double* grad_u, double* q, wos_solve_info* info, void* stream);
 
+/* Evaluation off the sites (the approximations of u on the partition after
+ * eq. min_el_discrete in Sec. "Euler-Lagrange boundary value problems"):
+ * each point x_k is binned to its nearest site x_i (the Voronoi cell W_i,
+ * through the same grid the walks are binned by, in the toolbox
+ * precision) and
+ *   out[k] = u_i + <grad u_i, x_k - x_i>   with grad_u (gradient-enhanced),
+ *   out[k] = u_i                            with grad_u NULL (piecewise constant).
+ *   u       device double (n); grad_u device double (d x n) or NULL
+ *   x       device double (npts x d), points of D; the nearest site is exact
+ *           on the domain's bounding box (outside it a point is binned by
+ *           the nearest grid cell)
+ *   out     device double (npts); site device int32 (npts) or NULL: i
+ * Asynchronous on `stream`.  Errors: WOS_EINVAL for NULL arguments or
+ * npts < 0.                                                                  */
+wos_status wos_interpolate(const wos_toolbox* tb, const double* u, const double* grad_u, const double* x,
+                           int64_t npts, double* out, int32_t* site, void* stream);
+
 /* ------------------------------------------ Euler-Lagrange route (Adam)
  * Minimises the discrete functional of Sec. "Euler-Lagrange boundary
  * value problems" (eq. gradJ) over the unknown source fbar,

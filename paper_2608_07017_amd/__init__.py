@@ -147,6 +147,25 @@ class Toolbox:
                               ctypes.byref(info), _stream_handle(stream)))
         return u, gu, q, {k: getattr(info, k) for k, _ in info._fields_}
 
+    def interpolate(self, u, x, grad_u=None, stream=None):
+        """u at arbitrary points x (npts, d) of the domain (include/wos.h,
+        wos_interpolate): the nearest site's value, plus <grad u_i, x - x_i>
+        when grad_u (d, n) is given.  Returns (values, site indices) as
+        device tensors."""
+        dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+        u, x = dev(u), dev(x)
+        if u.numel() != self.n or (x.numel() and x.shape[-1] != self.dim):
+            raise ValueError("u must have n entries and x shape (npts, d)")
+        gu = None if grad_u is None else dev(grad_u)
+        if gu is not None and gu.numel() != self.dim * self.n:
+            raise ValueError("grad_u must have d x n entries")
+        npts = x.numel() // self.dim
+        out = torch.empty(npts, dtype=torch.float64, device="cuda")
+        site = torch.empty(npts, dtype=torch.int32, device="cuda")
+        check(lib().wos_interpolate(self._h, _dptr(u), _dptr(gu) if gu is not None else ctypes.c_void_p(0),
+                                    _dptr(x), npts, _dptr(out), _dptr(site), _stream_handle(stream)))
+        return out, site
+
     def minimize(self, f, g, p_exp, alpha, max_iter, fbar0=1.0, tol=0.0, check_every=0, beta1=0.0, beta2=0.0,
                  eps=0.0, energy="plaplace", stream=None):
         """Adam on the discrete functional J of the Euler-Lagrange route

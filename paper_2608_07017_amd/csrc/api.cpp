@@ -770,6 +770,23 @@ wos_status wos_apply(const wos_toolbox* tb, const double* fbar, const double* g,
   return WOS_OK;
 }
 
+wos_status wos_interpolate(const wos_toolbox* tb, const double* u, const double* grad_u, const double* x,
+                           int64_t npts, double* out, int32_t* site, void* stream_) {
+  g_err.clear();
+  if (!tb || !u || (npts > 0 && (!x || !out))) return fail(WOS_EINVAL, "NULL argument");
+  if (npts < 0) return fail(WOS_EINVAL, "npts must be >= 0");
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  if (tb->f64)
+    WOS_HIP(launch_interpolate<double>(tb->dim, view<double>(tb->gv, tb->d_sites_f64),
+                                       static_cast<const double*>(tb->d_sites_f64), u, grad_u, tb->n, x, npts, out,
+                                       site, stream));
+  else
+    WOS_HIP(launch_interpolate<float>(tb->dim, view<float>(tb->gv, tb->d_sites_f32),
+                                      static_cast<const double*>(tb->d_sites_f64), u, grad_u, tb->n, x, npts, out,
+                                      site, stream));
+  return WOS_OK;
+}
+
 void wos_toolbox_free(wos_toolbox* tb) {
   if (!tb) return;
   if (tb->built && tb->last_stream) (void)hipStreamSynchronize(tb->last_stream);

@@ -30,4 +30,11 @@ hipError_t launch_apply_f64(const double* M, int rows, int cols_m, const double*
                             const double* N, int cols_n, const double* y, double* out, int batch,
                             hipStream_t stream);
 
+// out[k] = u[i] (+ <gu[:, i], x_k - y_i> when gu is given), i the nearest
+// site of x_k by the site grid g; site[k] = i when site is given.
+template <typename T>
+hipError_t launch_interpolate(int dim, const GridDev<T>& g, const double* sites64, const double* u,
+                              const double* gu, int n, const double* x, int64_t npts, double* out, int* site,
+                              hipStream_t st);
+
 }  // namespace wos

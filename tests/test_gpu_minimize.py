@@ -145,3 +145,50 @@ def test_disk_torsion_accuracy():
         _say("  rel L2 error %.4f, grad norm %.2e, %d iters in %.3f s" % (err, info["grad_norm"], info["iters"],
                                                                         info["seconds"]))
         assert err < bound
+
+
+def _disk_points(k, seed):
+    rng = np.random.default_rng(seed)
+    r = np.sqrt(rng.uniform(0, 1, k)) * 0.999
+    th = rng.uniform(0, 2 * np.pi, k)
+    return np.stack([r * np.cos(th), r * np.sin(th)], 1)
+
+
+def test_interpolation_matches_oracle_f64(disk_tb):
+    # nearest sites bit-exact against the brute-force map (FP64 lookups,
+    # random points: no exact ties), values to rounding
+    tb, _ = disk_tb
+    sites = _rings(5)
+    rng = np.random.default_rng(12)
+    u, gu = rng.normal(size=tb.n), rng.normal(size=(2, tb.n))
+    x = np.concatenate([_disk_points(20000, 13), sites, [[0.0, 0.0]]])
+    _say("interpolate %d points" % len(x))
+    v, i = tb.interpolate(u, x, gu)
+    ref_v, ref_i = E.interpolate(sites, u, gu, x)
+    assert np.array_equal(i.cpu().numpy(), ref_i)
+    assert np.allclose(v.cpu().numpy(), ref_v, rtol=0, atol=1e-13 * np.abs(ref_v).max())
+    v0, _ = tb.interpolate(u, x)
+    assert np.array_equal(v0.cpu().numpy(), u[ref_i])
+
+
+def test_interpolation_reproduces_affine_fields_f32_toolbox():
+    # FP32 lookups: an index may differ from the FP64 brute force only at a
+    # near-tie; the affine field is reproduced whichever site is taken
+    cfg = W.config("lshape256")
+    tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], 100, cfg["eps"], seed=cfg["seed"], precision="f32")
+    sites = cfg["sites"]
+    rng = np.random.default_rng(14)
+    x = rng.uniform(-1, 1, size=(30000, 2))
+    x = x[~((x[:, 0] >= 0) & (x[:, 1] < 0))]  # the L-shape
+    a, b = np.array([0.3, -1.7]), 0.25
+    u, gu = sites @ a + b, np.tile(a[:, None], (1, tb.n))
+    _say("interpolate f32 %d points" % len(x))
+    v, i = tb.interpolate(u, x, gu)
+    v, i = v.cpu().numpy(), i.cpu().numpy()
+    assert np.allclose(v, x @ a + b, rtol=0, atol=1e-12)
+    _, ref_i = E.interpolate(sites, u, None, x)
+    bad = np.nonzero(i != ref_i)[0]
+    d_gpu = ((x[bad] - sites[i[bad]]) ** 2).sum(1)
+    d_ref = ((x[bad] - sites[ref_i[bad]]) ** 2).sum(1)
+    assert np.all(d_gpu - d_ref <= 1e-6 * d_ref + 1e-12), "a non-tie was binned to another site"
+    assert len(bad) < 1e-3 * len(x)
