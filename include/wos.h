@@ -161,6 +161,22 @@ typedef enum {
 wos_status wos_toolbox_export(const wos_toolbox* tb, int32_t what, void* dst, size_t bytes,
                               int32_t dst_is_device, void* stream);
 
+/* Per-estimator (M, N) (Sec. "Laplacian Operator Toolbox: Pseudocode
+ * algorithms": the WoS steps M and the samples N may differ between the
+ * estimators A, B, H and K).  Build a second toolbox `src` on the same
+ * domain, sites and boundary nodes, with its own walks, fixed_M, eps and
+ * seed, then copy the estimators named in `mask` from it into `dst`:
+ *   WOS_TAKE_A = 1, WOS_TAKE_B = 2, WOS_TAKE_H = 4 (with the exit counts),
+ *   WOS_TAKE_K = 8.
+ * Each estimator of dst is then the one of the toolbox it came from
+ * (B^(j) and K^(j) move with all their components j).  Both toolboxes must
+ * be built, with the same precision, dimension, domain, sites and nodes
+ * (compared exactly).  Device-to-device copies ordered on `stream`.
+ * Errors: WOS_EINVAL for a NULL argument, an unbuilt toolbox, a mismatch,
+ * or mask outside 1..15.                                                      */
+enum { WOS_TAKE_A = 1, WOS_TAKE_B = 2, WOS_TAKE_H = 4, WOS_TAKE_K = 8 };
+wos_status wos_toolbox_take(wos_toolbox* dst, const wos_toolbox* src, uint32_t mask, void* stream);
+
 /* Direct application with a known source (Sec. "Matrix estimators" and the
  * boxed reconstruction):  u = A fbar + H g,  grad_u = B fbar + K g,
  * i.e. the solution of -(1/2) Lap u = f, u = g with fbar_j = f(y_j).

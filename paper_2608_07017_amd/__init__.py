@@ -147,6 +147,17 @@ class Toolbox:
                               ctypes.byref(info), _stream_handle(stream)))
         return u, gu, q, {k: getattr(info, k) for k, _ in info._fields_}
 
+    def take(self, other, estimators, stream=None):
+        """Copy the estimators named in `estimators` (any of "A", "B", "H",
+        "K") from `other`, a toolbox built on the same domain, sites and
+        nodes with its own walks, fixed_M, eps and seed (include/wos.h,
+        wos_toolbox_take): per-estimator (M, N)."""
+        bits = {"A": 1, "B": 2, "H": 4, "K": 8}
+        mask = 0
+        for e in estimators:
+            mask |= bits[e]
+        check(lib().wos_toolbox_take(self._h, other._h, mask, _stream_handle(stream)))
+
     def interpolate(self, u, x, grad_u=None, stream=None):
         """u at arbitrary points x (npts, d) of the domain (include/wos.h,
         wos_interpolate): the nearest site's value, plus <grad u_i, x - x_i>

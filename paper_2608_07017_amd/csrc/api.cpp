@@ -770,6 +770,31 @@ wos_status wos_apply(const wos_toolbox* tb, const double* fbar, const double* g,
   return WOS_OK;
 }
 
+wos_status wos_toolbox_take(wos_toolbox* dst, const wos_toolbox* src, uint32_t mask, void* stream_) {
+  g_err.clear();
+  if (!dst || !src) return fail(WOS_EINVAL, "NULL argument");
+  if (mask < 1 || mask > 15) return fail(WOS_EINVAL, "mask must be in 1..15");
+  if (!dst->built || !src->built) return fail(WOS_EINVAL, "both toolboxes must be built");
+  const HostDomain &a = dst->dom, &b = src->dom;
+  bool same = dst->f64 == src->f64 && dst->dim == src->dim && dst->n == src->n && dst->m == src->m &&
+              dst->p == src->p && a.kind == b.kind && a.dim == b.dim && a.rad == b.rad && a.verts == b.verts &&
+              dst->sites == src->sites && dst->bnodes == src->bnodes;
+  for (int k = 0; k < 3; ++k) same = same && a.c[k] == b.c[k] && a.lo[k] == b.lo[k] && a.hi[k] == b.hi[k];
+  if (!same) return fail(WOS_EINVAL, "toolboxes differ in precision, domain, sites or boundary nodes");
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  const size_t ts = tsize(dst), n = dst->n, m = dst->m, p = dst->p, d = dst->dim;
+  if (mask & WOS_TAKE_A) WOS_HIP(hipMemcpyAsync(dst->d_A, src->d_A, ts * n * m, hipMemcpyDeviceToDevice, stream));
+  if (mask & WOS_TAKE_B)
+    WOS_HIP(hipMemcpyAsync(dst->d_B, src->d_B, ts * d * n * m, hipMemcpyDeviceToDevice, stream));
+  if (mask & WOS_TAKE_H) {
+    WOS_HIP(hipMemcpyAsync(dst->d_H, src->d_H, ts * n * p, hipMemcpyDeviceToDevice, stream));
+    WOS_HIP(hipMemcpyAsync(dst->d_Hc, src->d_Hc, 4 * n * p, hipMemcpyDeviceToDevice, stream));
+  }
+  if (mask & WOS_TAKE_K)
+    WOS_HIP(hipMemcpyAsync(dst->d_K, src->d_K, ts * d * n * p, hipMemcpyDeviceToDevice, stream));
+  return WOS_OK;
+}
+
 wos_status wos_interpolate(const wos_toolbox* tb, const double* u, const double* grad_u, const double* x,
                            int64_t npts, double* out, int32_t* site, void* stream_) {
   g_err.clear();

@@ -116,6 +116,32 @@ def test_paper_fixed_M_mode():
     _compare_f64(W.unit_square(), sites[::13], bn, 200, 0.0, 3, fixed_M=30)
 
 
+def test_per_estimator_walks_and_steps():
+    """Per-estimator (M, N): A and B from 200 walks of 30 steps (seed 3),
+    H and K from 500 walks of 60 steps (seed 8), combined by copying the
+    second toolbox's H and K into the first; each must match the oracle
+    build with its own (M, N, seed)."""
+    sites, bn = W.paper_square_layout()
+    s = sites[::13]
+    dom = W.unit_square()
+    tb1 = _gpu_tb(dom, s, bn, 200, 0.0, 3, precision="f64", volume_samples=1 << 12, fixed_M=30)
+    tb2 = _gpu_tb(dom, s, bn, 500, 0.0, 8, precision="f64", volume_samples=1 << 12, fixed_M=60)
+    tb1.take(tb2, "HK")
+    g = _export_all(tb1)
+    ref_ab = oracle_build(dom, s, bn, 200, 0.0, 3, fixed_M=30)
+    ref_hk = oracle_build(dom, s, bn, 500, 0.0, 8, fixed_M=60)
+    for key, ref in (("A", ref_ab), ("B", ref_ab), ("K", ref_hk)):
+        scale = np.abs(ref[key]).max()
+        assert np.allclose(g[key], ref[key], rtol=1e-10, atol=1e-12 * scale), key
+    assert np.array_equal(g["Hcount"], ref_hk["Hcount"])
+    assert np.allclose(g["H"], ref_hk["H"], rtol=1e-15, atol=0)
+    # the source toolbox is unchanged, and a toolbox on other sites is refused
+    assert np.array_equal(_export_all(tb2)["Hcount"], ref_hk["Hcount"])
+    tb3 = _gpu_tb(dom, sites[1::13], bn, 10, 0.0, 3, precision="f64", volume_samples=1 << 12, fixed_M=5)
+    with pytest.raises(P.WosError):
+        tb1.take(tb3, "A")
+
+
 def test_step_cap_counts():
     dom = W.unit_disk()
     sites = W.sample_sites(dom, 9, 8, 1e-2)
