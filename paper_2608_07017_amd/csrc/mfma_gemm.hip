@@ -312,7 +312,11 @@ hipError_t gemm_dispatch(bool ta, bool tb, int M, int N, int K, T alpha, const S
     const int va = rows_aligned(A, lda) ? 1 : 0, vb = rows_aligned(B, ldb) ? 1 : 0;
     // FP32 products too small to give 256 tiles of 128 x 128 take 64 x 64
     // tiles, four times as many workgroups
-    const bool wide = std::is_same<T, float>::value && (size_t)((M + 127) / 128) * ((N + 127) / 128) >= 256;
+    // (in the lower-triangle mode the 128 x 128 tiles that remain must
+    // still fill the chip four times over, else the last round runs
+    // mostly empty)
+    const size_t t128 = (size_t)((M + 127) / 128) * ((N + 127) / 128);
+    const bool wide = std::is_same<T, float>::value && (lower ? (t128 + (M + 127) / 128) / 2 >= 1024 : t128 >= 256);
 #define WOS_PIPE(W_, TA_, TB_)                                                                                  \
   hipLaunchKernelGGL((mfma_gemm_pipe_kernel<T, SA, SB, TA_, TB_, W_, W_>),                                      \
                      dim3((N + 32 * W_ - 1) / (32 * W_), (M + 32 * W_ - 1) / (32 * W_)), dim3(256), 0, st, M, N, K, \
