@@ -34,12 +34,19 @@ Walks are simulated together as arrays (the paper's Rem.
 "implementation_tips" (ii) vectorises over walks); each walk's arithmetic
 is exactly the steps above.
 
+The V cells (the columns of A and B) may be a partition of their own
+(Rem. after the definition of the partitions: W_n and V_m chosen
+independently); with ``vcentres`` the tally points are binned to those
+centres, the walks themselves are unchanged.
+
 Pinned by tests/test_oracle_walker.py: E tau = (1-|x|^2)/d and its
 gradient on the unit disk and ball (eps bias bounded by 2 eps / d), the
 closed forms U[x_1] and grad U[x_1], the harmonic extension and its
 gradient for harmonic boundary data, the disk's harmonic measure of an arc,
 H row sums equal to 1, and the binned matrices against the same walks'
-pointwise estimators on piecewise-constant data.
+pointwise estimators on piecewise-constant data; with a separate V
+partition, the row sums unchanged and the columns permuted with the
+centres.
 """
 import numpy as np
 
@@ -159,21 +166,25 @@ def bin_site(ev, sites, bnodes, m=None, p=None):
 
 
 def build_toolbox(dom, sites, bnodes, walks, eps, seed, max_steps=DEFAULT_MAX_STEPS,
-                  fixed_M=0, rows=None):
+                  fixed_M=0, rows=None, vcentres=None):
     """The toolbox A (n,m), B (d,n,m), H (n,p), K (d,n,p) of eq. LOT.
 
-    Centres: W-centres = V-centres = ``sites`` (n = m), Gamma-centres =
+    Centres: W-centres = ``sites`` (the walks' starting points, n rows),
+    V-centres = ``vcentres`` (the cells the tally points are binned to, m
+    columns; the same as ``sites`` when None, n = m), Gamma-centres =
     ``bnodes``.  ``rows`` restricts the output to a subset of sites (rows
     are independent: each (site, walk) pair has its own random stream).
     """
     sites = np.asarray(sites, dtype=np.float64)
     bnodes = np.asarray(bnodes, dtype=np.float64)
+    vc = sites if vcentres is None else np.asarray(vcentres, dtype=np.float64)
     n, d = sites.shape
+    m = len(vc)
     p = len(bnodes)
     rows = np.arange(n) if rows is None else np.asarray(rows)
     nr = len(rows)
-    A = np.zeros((nr, n))
-    B = np.zeros((d, nr, n))
+    A = np.zeros((nr, m))
+    B = np.zeros((d, nr, m))
     Hc = np.zeros((nr, p), dtype=np.int64)
     K = np.zeros((d, nr, p))
     steps = np.zeros(nr, dtype=np.int64)
@@ -181,7 +192,7 @@ def build_toolbox(dom, sites, bnodes, walks, eps, seed, max_steps=DEFAULT_MAX_ST
     capped = np.zeros(nr, dtype=np.int64)
     for row, i in enumerate(rows):
         ev = site_events(dom, sites[i], int(i), np.arange(walks), eps, seed, max_steps, fixed_M)
-        a_row, b_rows, h_row, k_rows = bin_site(ev, sites, bnodes)
+        a_row, b_rows, h_row, k_rows = bin_site(ev, vc, bnodes)
         A[row] = a_row / walks
         B[:, row] = b_rows / walks
         Hc[row] = h_row

@@ -117,3 +117,24 @@ def test_walk_length_statistics_disk():
     ev1 = site_events(DISK, np.array([0.3, 0.1]), 0, np.arange(20000), 1e-2, 3)
     ev2 = site_events(DISK, np.array([0.3, 0.1]), 0, np.arange(20000), 1e-4, 3)
     assert 2.0 < ev2.nsteps.mean() - ev1.nsteps.mean() < 8.0
+
+
+def test_separate_v_partition_moves_only_the_columns():
+    # Binning the same walks to another V partition (W != V) changes which
+    # column a tally lands in, never the tally: row sums of A and B (and H, K,
+    # which are binned to the boundary cells) are those of the W = V build,
+    # and permuting the V centres permutes the columns exactly.
+    import workloads as W
+    dom = W.unit_disk()
+    sites = W.sample_sites(dom, 6, 21, 1e-3)
+    bn = W.circle_nodes(9)
+    vc = W.sample_sites(dom, 11, 22, 1e-3)
+    same = build_toolbox(dom, sites, bn, 150, 1e-3, 5)
+    wv = build_toolbox(dom, sites, bn, 150, 1e-3, 5, vcentres=vc)
+    assert wv["A"].shape == (6, 11) and wv["B"].shape == (2, 6, 11)
+    assert np.allclose(wv["A"].sum(1), same["A"].sum(1), rtol=1e-12)
+    assert np.allclose(wv["B"].sum(2), same["B"].sum(2), rtol=1e-12, atol=1e-14)
+    assert np.array_equal(wv["Hcount"], same["Hcount"]) and np.array_equal(wv["K"], same["K"])
+    perm = np.random.default_rng(3).permutation(11)
+    wp = build_toolbox(dom, sites, bn, 150, 1e-3, 5, vcentres=vc[perm])
+    assert np.array_equal(wp["A"], wv["A"][:, perm]) and np.array_equal(wp["B"], wv["B"][:, :, perm])
