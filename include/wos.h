@@ -142,6 +142,21 @@ typedef struct {
   size_t device_bytes;      /* device memory held by the toolbox           */
 } wos_toolbox_info;
 
+/* As wos_toolbox_create, with a V partition of its own (the remark after
+ * the definition of the partitions in Sec. "Matrix estimators": W_n and V_m
+ * may be chosen independently, W discretising the image of the smoothing
+ * operators and V their domain).  The walks start at the n W centres
+ * `sites` (and lambda_i = |W_i| / |D| is over their cells); the tally
+ * points are binned to the m V centres `vcentres` (host, m x d, inside D),
+ * so A is n x m and B d x n x m; |V_j| / |D| is computed with lambda
+ * (WOS_EXPORT_LAMBDA_V).  With vcentres NULL (m ignored) this is
+ * wos_toolbox_create.  Supported on a toolbox with n != m: builds, apply,
+ * export, take, interpolate, LINEAR solves and wos_minimize; the nonlinear
+ * solve kinds and the operators return WOS_EINVAL.                          */
+wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int32_t n, const double* vcentres,
+                                 int32_t m, const double* bnodes, int32_t p, const wos_build_opts* opts,
+                                 wos_toolbox** out);
+
 /* Fills *info.  Synchronises the toolbox's last build stream.                  */
 wos_status wos_toolbox_get_info(const wos_toolbox* tb, wos_toolbox_info* info);
 
@@ -152,7 +167,8 @@ typedef enum {
   WOS_EXPORT_K = 3,       /* d x n x p,  toolbox precision             */
   WOS_EXPORT_HCOUNT = 4,  /* n x p,      uint32 exit counts            */
   WOS_EXPORT_LAMBDA = 5,  /* n,          double lambda_i               */
-  WOS_EXPORT_VCOUNT = 6   /* n,          uint64 volume-point counts    */
+  WOS_EXPORT_VCOUNT = 6,  /* n,          uint64 volume-point counts    */
+  WOS_EXPORT_LAMBDA_V = 7 /* m,          double |V_j| / |D| (= lambda when V = W) */
 } wos_export_what;
 
 /* Copies one toolbox array into dst (device if dst_is_device, else host),
@@ -312,8 +328,8 @@ typedef struct {
 typedef struct {
   int32_t iters;        /* iterations taken                                   */
   double J;             /* J at the result                                    */
-  double grad_norm;     /* |grad J|_lambda = (sum_j lambda_j [grad J]_j^2)^(1/2)
-                           at the result (lambda_j = |W_j| / |D|)             */
+  double grad_norm;     /* |grad J|_V = (sum_j |V_j| / |D| [grad J]_j^2)^(1/2)
+                           at the result                                      */
   double grad_norm0;    /* the same at the start                              */
   double seconds;       /* wall time of the iterations                        */
 } wos_adam_info;
@@ -331,7 +347,7 @@ typedef struct {
  * transposed); u and J are formed at the end.  Runs on `stream` and synchronises it before returning.
  * Errors: WOS_EINVAL for a NULL pointer, an unbuilt toolbox, an unknown
  * energy, P <= 1, alpha <= 0, beta outside [0, 1), eps < 0 or
- * max_iter <= 0.  The work vectors ((3d + 3) n + 3 m doubles) are allocated
+ * max_iter <= 0.  The work vectors ((3d + 2) n + 4 m doubles) are allocated
  * on the first call and kept with the toolbox.  Not thread-safe for one
  * toolbox.                                                                   */
 wos_status wos_minimize(wos_toolbox* tb, const wos_adam_opts* opts, const double* f, const double* g,

@@ -52,12 +52,17 @@ class Toolbox:
 
     def __init__(self, domain, sites, bnodes, walks, eps, seed=0, precision="f32", max_steps=0,
                  fixed_M=0, volume_samples=0, walks_per_item=0, regen_threshold=0, autotune=True,
-                 tally_in_hbm=False):
+                 tally_in_hbm=False, vcentres=None):
+        """`sites` are the W centres (the walks start there, n rows); with
+        `vcentres` the tally points are binned to a V partition of its own
+        (m columns; include/wos.h, wos_toolbox_create_wv), else V = W."""
         self.domain = domain
         self.sites = np.ascontiguousarray(np.asarray(sites, dtype=np.float64))
+        self.vcentres = None if vcentres is None else np.ascontiguousarray(np.asarray(vcentres, dtype=np.float64))
         self.bnodes = np.ascontiguousarray(np.asarray(bnodes, dtype=np.float64))
         self.dim = int(domain["dim"])
         self.n = self.sites.shape[0]
+        self.m = self.n if self.vcentres is None else self.vcentres.shape[0]
         self.p = self.bnodes.shape[0]
         self.seed = int(seed)
         self.precision = precision
@@ -70,9 +75,17 @@ class Toolbox:
                             tally_in_hbm=1 if tally_in_hbm else 0)
         h = ctypes.c_void_p()
         dp = ctypes.POINTER(ctypes.c_double)
-        check(lib().wos_toolbox_create(ctypes.byref(dom), self.sites.ctypes.data_as(dp), self.n,
-                                       self.bnodes.ctypes.data_as(dp), self.p, ctypes.byref(opts),
-                                       ctypes.byref(h)))
+        if self.vcentres is None:
+            check(lib().wos_toolbox_create(ctypes.byref(dom), self.sites.ctypes.data_as(dp), self.n,
+                                           self.bnodes.ctypes.data_as(dp), self.p, ctypes.byref(opts),
+                                           ctypes.byref(h)))
+        else:
+            if self.vcentres.ndim != 2 or self.vcentres.shape[1] != self.dim:
+                raise ValueError("vcentres must have shape (m, d)")
+            check(lib().wos_toolbox_create_wv(ctypes.byref(dom), self.sites.ctypes.data_as(dp), self.n,
+                                              self.vcentres.ctypes.data_as(dp), self.m,
+                                              self.bnodes.ctypes.data_as(dp), self.p, ctypes.byref(opts),
+                                              ctypes.byref(h)))
         del keep
         self._h = h
         self.dtype = torch.float64 if precision == "f64" else torch.float32
@@ -100,10 +113,11 @@ class Toolbox:
 
     # ------------------------------------------------------------- export
     def _shape(self, what):
-        n, p, d = self.n, self.p, self.dim
-        return {"A": ((n, n), self.dtype), "B": ((d, n, n), self.dtype), "H": ((n, p), self.dtype),
+        n, m, p, d = self.n, self.m, self.p, self.dim
+        return {"A": ((n, m), self.dtype), "B": ((d, n, m), self.dtype), "H": ((n, p), self.dtype),
                 "K": ((d, n, p), self.dtype), "Hcount": ((n, p), torch.int32),
-                "lambda": ((n,), torch.float64), "vcount": ((n,), torch.int64)}[what]
+                "lambda": ((n,), torch.float64), "vcount": ((n,), torch.int64),
+                "lambda_v": ((m,), torch.float64)}[what]
 
     def export(self, what, stream=None):
         """A copy of one toolbox array as a device tensor (Hcount as int32
@@ -119,8 +133,8 @@ class Toolbox:
         """u = A fbar + H g and grad u = B fbar + K g (device float64)."""
         fbar = torch.as_tensor(fbar, dtype=torch.float64, device="cuda").contiguous()
         g = torch.as_tensor(g, dtype=torch.float64, device="cuda").contiguous()
-        if fbar.numel() != self.n or g.numel() != self.p:
-            raise ValueError("fbar must have n entries and g p entries")
+        if fbar.numel() != self.m or g.numel() != self.p:
+            raise ValueError("fbar must have m entries and g p entries")
         u = torch.empty(self.n, dtype=torch.float64, device="cuda")
         gu = torch.empty((self.dim, self.n), dtype=torch.float64, device="cuda") if grad else None
         check(lib().wos_apply(self._h, _dptr(fbar), _dptr(g), _dptr(u),
@@ -141,7 +155,7 @@ class Toolbox:
                                          precision, max_refine, refine_tol)
         u = torch.empty(self.n, dtype=torch.float64, device="cuda")
         gu = torch.empty((self.dim, self.n), dtype=torch.float64, device="cuda")
-        q = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        q = torch.empty(self.m, dtype=torch.float64, device="cuda")
         info = WosSolveInfo()
         check(lib().wos_solve(self._h, ctypes.byref(co), _dptr(f), _dptr(g), _dptr(u), _dptr(gu), _dptr(q),
                               ctypes.byref(info), _stream_handle(stream)))
@@ -188,10 +202,10 @@ class Toolbox:
         if f.numel() != self.n or g.numel() != self.p:
             raise ValueError("f must have n entries and g p entries")
         if np.ndim(fbar0) == 0:
-            fbar = torch.full((self.n,), float(fbar0), dtype=torch.float64, device="cuda")
+            fbar = torch.full((self.m,), float(fbar0), dtype=torch.float64, device="cuda")
         else:
             fbar = dev(fbar0).clone()
-            if fbar.numel() != self.n:
+            if fbar.numel() != self.m:
                 raise ValueError("fbar0 must have m entries")
         opts = WosAdamOpts(energy=ENERGIES[energy], p_exp=float(p_exp), alpha=float(alpha), beta1=float(beta1),
                            beta2=float(beta2), eps=float(eps), max_iter=int(max_iter), tol=float(tol),

@@ -16,7 +16,7 @@ STATUS = {0: "WOS_OK", -1: "WOS_EINVAL", -2: "WOS_EDOMAIN", -3: "WOS_ENOMEM", -4
           -5: "WOS_ENOTCONV", -6: "WOS_EBUSY", -7: "WOS_ENOTIMPL"}
 KINDS = {"ball": 1, "box": 2, "polygon": 3, "box_minus_ball": 4}
 PRECISION = {"f32": 0, "f64": 1}
-EXPORTS = {"A": 0, "B": 1, "H": 2, "K": 3, "Hcount": 4, "lambda": 5, "vcount": 6}
+EXPORTS = {"A": 0, "B": 1, "H": 2, "K": 3, "Hcount": 4, "lambda": 5, "vcount": 6, "lambda_v": 7}
 
 
 class WosDomain(ctypes.Structure):
@@ -96,6 +96,8 @@ _D = ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
     "wos_toolbox_create": (ctypes.c_int, [ctypes.POINTER(WosDomain), _D, ctypes.c_int32, _D, ctypes.c_int32,
                                           ctypes.POINTER(WosBuildOpts), ctypes.POINTER(_P)]),
+    "wos_toolbox_create_wv": (ctypes.c_int, [ctypes.POINTER(WosDomain), _D, ctypes.c_int32, _D, ctypes.c_int32, _D,
+                                             ctypes.c_int32, ctypes.POINTER(WosBuildOpts), ctypes.POINTER(_P)]),
     "wos_toolbox_build": (ctypes.c_int, [_P, ctypes.c_uint64, _P]),
     "wos_build_toolbox": (ctypes.c_int, [ctypes.POINTER(WosDomain), _D, ctypes.c_int32, _D, ctypes.c_int32,
                                          ctypes.POINTER(WosBuildOpts), _P, ctypes.POINTER(_P)]),

@@ -267,6 +267,11 @@ void release(wos_toolbox* tb) {
                   tb->d_item_order};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  if (tb->wv) {  // the V-side arrays are separate allocations only with a V partition of their own
+    void* vptrs[] = {tb->gw.rec, tb->gw.list, tb->d_vsites_f32, tb->d_vsites_f64, tb->d_lambda_v, tb->d_vcount_v};
+    for (void* q : vptrs)
+      if (q) (void)hipFree(q);
+  }
 }
 
 bool finite3(const double* v, int k) {
@@ -305,7 +310,7 @@ static void fill_walker_params(const wos_toolbox* tb, uint32_t k0, uint32_t k1, 
   P.segs = static_cast<const T*>(tb->d_segs);
   P.nseg = (int)tb->dom.verts.size() / 2;
   P.sites = static_cast<const T*>(f64 ? tb->d_sites_f64 : tb->d_sites_f32);
-  P.gv = view<T>(tb->gv, f64 ? tb->d_sites_f64 : tb->d_sites_f32);
+  P.gv = view<T>(tb->gv, f64 ? tb->d_vsites_f64 : tb->d_vsites_f32);
   P.gg = view<T>(tb->gg, tb->d_bnodes);
   P.n = tb->n;
   P.m = tb->m;
@@ -355,12 +360,21 @@ const char* wos_version(void) { return "libwos 0.1 (gfx950)"; }
 wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_t n,
                               const double* bnodes, int32_t p, const wos_build_opts* opts,
                               wos_toolbox** out) {
+  return wos_toolbox_create_wv(dom, sites, n, nullptr, 0, bnodes, p, opts, out);
+}
+
+wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int32_t n, const double* vcentres,
+                                 int32_t m, const double* bnodes, int32_t p, const wos_build_opts* opts,
+                                 wos_toolbox** out) {
   g_err.clear();
   if (!out) return fail(WOS_EINVAL, "out is NULL");
   *out = nullptr;
   if (!dom || !sites || !bnodes || !opts) return fail(WOS_EINVAL, "NULL argument");
   if (dom->dim != 2 && dom->dim != 3) return fail(WOS_EINVAL, "dim must be 2 or 3");
   if (n < 1 || p < 1) return fail(WOS_EINVAL, "need n >= 1 and p >= 1 (n=%d, p=%d)", n, p);
+  const bool wv = vcentres != nullptr;
+  if (!wv) m = n;
+  if (m < 1) return fail(WOS_EINVAL, "need m >= 1 V centres (m=%d)", m);
   if (opts->walks_per_site < 1 || opts->walks_per_site > (int64_t)INT32_MAX)
     return fail(WOS_EINVAL, "walks_per_site must be in [1, 2^31)");
   if (opts->fixed_M < 0) return fail(WOS_EINVAL, "fixed_M must be >= 0");
@@ -425,16 +439,25 @@ wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_
   }
   for (int j = 0; j < p; ++j)
     if (!finite3(bnodes + (size_t)j * d, d)) return fail(WOS_EINVAL, "boundary node %d is not finite", j);
+  if (wv)
+    for (int j = 0; j < m; ++j) {
+      const double* y = vcentres + (size_t)j * d;
+      if (!finite3(y, d)) return fail(WOS_EINVAL, "V centre %d is not finite", j);
+      if (!host_inside(hd, y)) return fail(WOS_EDOMAIN, "V centre %d is not inside the domain", j);
+    }
 
   wos_toolbox* tb = new (std::nothrow) wos_toolbox();
   if (!tb) return fail(WOS_ENOMEM, "host allocation failed");
   tb->dom = hd;
   tb->opts = *opts;
   tb->dim = d;
-  tb->n = tb->m = n;
+  tb->n = n;
+  tb->m = m;
   tb->p = p;
+  tb->wv = wv;
   tb->f64 = opts->precision == WOS_F64;
   tb->sites.assign(sites, sites + (size_t)n * d);
+  tb->vsites.assign(wv ? vcentres : sites, (wv ? vcentres : sites) + (size_t)m * d);
   tb->bnodes.assign(bnodes, bnodes + (size_t)p * d);
   if (tb->opts.max_steps == 0) tb->opts.max_steps = kDefaultMaxSteps;
   if (tb->opts.volume_samples == 0) tb->opts.volume_samples = (int64_t)1 << 24;
@@ -443,9 +466,9 @@ wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_
   const int nseg = hd.kind == WOS_POLYGON ? dom->nvert : 0;
   // a site's rows are tallied in LDS when they fit, else straight into the
   // toolbox in device memory
-  const size_t lds_rows = walker_lds_bytes(d, n, p, nseg, tb->f64);
+  const size_t lds_rows = walker_lds_bytes(d, m, p, nseg, tb->f64);
   tb->global_tally = opts->tally_in_hbm != 0 || lds_rows > 160 * 1024;
-  const size_t lds = tb->global_tally ? (tb->f64 ? 8 : 4) * (5 * (size_t)nseg + 4 * (size_t)n) : lds_rows;
+  const size_t lds = tb->global_tally ? (tb->f64 ? 8 : 4) * (5 * (size_t)nseg + 4 * (size_t)m) : lds_rows;
 
   // work split: about one (site, chunk) item per workgroup slot of the chip
   const int64_t N = opts->walks_per_site;
@@ -482,8 +505,10 @@ wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_
   host_bbox(hd, lo, hi);
   double vol = 1;
   for (int a = 0; a < d; ++a) vol *= (hi[a] - lo[a]);
-  const double sp_v = std::pow(vol / n, 1.0 / d);
-  GridHost gvh = build_grid(sites, n, d, lo, hi, sp_v / (d == 2 ? 8.0 : 4.0), 1 << 24);
+  const double sp_v = std::pow(vol / m, 1.0 / d);
+  GridHost gvh = build_grid(tb->vsites.data(), m, d, lo, hi, sp_v / (d == 2 ? 8.0 : 4.0), 1 << 24);
+  GridHost gwh;
+  if (wv) gwh = build_grid(sites, n, d, lo, hi, std::pow(vol / n, 1.0 / d) / (d == 2 ? 8.0 : 4.0), 1 << 24);
   const double bm = host_boundary_measure(hd);
   const double sp_b = d == 2 ? bm / p : std::sqrt(bm / p);
   GridHost ggh = build_grid(bnodes, p, d, lo, hi, sp_b / 4.0, 1 << 23);
@@ -516,11 +541,24 @@ wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_
   }
   TRY(upload_grid(tb, gvh, &tb->gv));
   TRY(upload_grid(tb, ggh, &tb->gg));
+  if (wv)
+    TRY(upload_grid(tb, gwh, &tb->gw));
+  else
+    tb->gw = tb->gv;
   {
     auto s32 = padded<float>(tb->sites, n, d);
     auto s64 = padded<double>(tb->sites, n, d);
     TRY(upload(tb, &tb->d_sites_f32, s32.data(), s32.size() * 4));
     TRY(upload(tb, &tb->d_sites_f64, s64.data(), s64.size() * 8));
+    if (wv) {
+      auto v32 = padded<float>(tb->vsites, m, d);
+      auto v64 = padded<double>(tb->vsites, m, d);
+      TRY(upload(tb, &tb->d_vsites_f32, v32.data(), v32.size() * 4));
+      TRY(upload(tb, &tb->d_vsites_f64, v64.data(), v64.size() * 8));
+    } else {
+      tb->d_vsites_f32 = tb->d_sites_f32;
+      tb->d_vsites_f64 = tb->d_sites_f64;
+    }
     if (tb->f64) {
       auto b = padded<double>(tb->bnodes, p, d);
       TRY(upload(tb, &tb->d_bnodes, b.data(), b.size() * 8));
@@ -552,14 +590,21 @@ wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_
     TRY(upload(tb, (void**)&tb->d_verts, v.data(), v.size() * 8));
   }
   const size_t ts = tsize(tb);
-  TRY(dev_alloc(tb, &tb->d_A, ts * (size_t)n * n));
-  TRY(dev_alloc(tb, &tb->d_B, ts * (size_t)d * n * n));
+  TRY(dev_alloc(tb, &tb->d_A, ts * (size_t)n * m));
+  TRY(dev_alloc(tb, &tb->d_B, ts * (size_t)d * n * m));
   TRY(dev_alloc(tb, &tb->d_K, ts * (size_t)d * n * p));
   TRY(dev_alloc(tb, &tb->d_H, ts * (size_t)n * p));
   TRY(dev_alloc(tb, (void**)&tb->d_Hc, 4 * (size_t)n * p));
   TRY(dev_alloc(tb, (void**)&tb->d_vcount, 8 * (size_t)n));
   TRY(dev_alloc(tb, (void**)&tb->d_stats, 8 * 8));
   TRY(dev_alloc(tb, (void**)&tb->d_lambda, 8 * (size_t)n));
+  if (wv) {
+    TRY(dev_alloc(tb, (void**)&tb->d_vcount_v, 8 * (size_t)m));
+    TRY(dev_alloc(tb, (void**)&tb->d_lambda_v, 8 * (size_t)m));
+  } else {
+    tb->d_vcount_v = tb->d_vcount;
+    tb->d_lambda_v = tb->d_lambda;
+  }
 #undef TRY
   *out = tb;
   return WOS_OK;
@@ -591,7 +636,7 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
     host_bbox(tb->dom, V.dom.lo, V.dom.hi);  // points are drawn in the bounding box
     V.verts = tb->d_verts;
     V.nvert = (int)tb->dom.verts.size() / 2;
-    V.gv = view<double>(tb->gv, tb->d_sites_f64);
+    V.gv = view<double>(tb->gw, tb->d_sites_f64);
     V.n = n;
     V.dim = d;
     // stratified points: tiles^d equal tiles of the bounding box, tiles the
@@ -612,6 +657,16 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
     V.inside = tb->d_stats + 4;
     WOS_HIP(launch_volume(V, stream));
     WOS_HIP(launch_lambda(tb->d_vcount, n, tb->d_lambda, stream));
+    if (tb->wv) {
+      // the same points binned to the V centres: |V_j| / |D|
+      WOS_HIP(hipMemsetAsync(tb->d_vcount_v, 0, 8 * (size_t)m, stream));
+      V.gv = view<double>(tb->gv, tb->d_vsites_f64);
+      V.n = m;
+      V.counts = tb->d_vcount_v;
+      V.inside = tb->d_stats + 5;
+      WOS_HIP(launch_volume(V, stream));
+      WOS_HIP(launch_lambda(tb->d_vcount_v, m, tb->d_lambda_v, stream));
+    }
   }
   if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[1], stream));
 
@@ -737,6 +792,7 @@ wos_status wos_toolbox_export(const wos_toolbox* tb, int32_t what, void* dst, si
     case WOS_EXPORT_HCOUNT: src = tb->d_Hc; want = 4 * n * p; break;
     case WOS_EXPORT_LAMBDA: src = tb->d_lambda; want = 8 * n; break;
     case WOS_EXPORT_VCOUNT: src = tb->d_vcount; want = 8 * n; break;
+    case WOS_EXPORT_LAMBDA_V: src = tb->d_lambda_v; want = 8 * m; break;
     default: return fail(WOS_EINVAL, "unknown export %d", what);
   }
   if (bytes != want) return fail(WOS_EINVAL, "export %d needs %zu bytes, got %zu", what, want, bytes);
@@ -778,7 +834,7 @@ wos_status wos_toolbox_take(wos_toolbox* dst, const wos_toolbox* src, uint32_t m
   const HostDomain &a = dst->dom, &b = src->dom;
   bool same = dst->f64 == src->f64 && dst->dim == src->dim && dst->n == src->n && dst->m == src->m &&
               dst->p == src->p && a.kind == b.kind && a.dim == b.dim && a.rad == b.rad && a.verts == b.verts &&
-              dst->sites == src->sites && dst->bnodes == src->bnodes;
+              dst->sites == src->sites && dst->vsites == src->vsites && dst->bnodes == src->bnodes;
   for (int k = 0; k < 3; ++k) same = same && a.c[k] == b.c[k] && a.lo[k] == b.lo[k] && a.hi[k] == b.hi[k];
   if (!same) return fail(WOS_EINVAL, "toolboxes differ in precision, domain, sites or boundary nodes");
   hipStream_t stream = static_cast<hipStream_t>(stream_);
@@ -802,11 +858,11 @@ wos_status wos_interpolate(const wos_toolbox* tb, const double* u, const double*
   if (npts < 0) return fail(WOS_EINVAL, "npts must be >= 0");
   hipStream_t stream = static_cast<hipStream_t>(stream_);
   if (tb->f64)
-    WOS_HIP(launch_interpolate<double>(tb->dim, view<double>(tb->gv, tb->d_sites_f64),
+    WOS_HIP(launch_interpolate<double>(tb->dim, view<double>(tb->gw, tb->d_sites_f64),
                                        static_cast<const double*>(tb->d_sites_f64), u, grad_u, tb->n, x, npts, out,
                                        site, stream));
   else
-    WOS_HIP(launch_interpolate<float>(tb->dim, view<float>(tb->gv, tb->d_sites_f32),
+    WOS_HIP(launch_interpolate<float>(tb->dim, view<float>(tb->gw, tb->d_sites_f32),
                                       static_cast<const double*>(tb->d_sites_f64), u, grad_u, tb->n, x, npts, out,
                                       site, stream));
   return WOS_OK;

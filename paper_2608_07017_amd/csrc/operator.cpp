@@ -205,6 +205,7 @@ wos_status wos_operator_create(wos_toolbox* tb, const wos_coeffs* co, const wos_
   *out = nullptr;
   if (!tb || !co) return ofail(WOS_EINVAL, "NULL argument");
   if (!tb->built) return ofail(WOS_EINVAL, "toolbox has not been built");
+  if (tb->n != tb->m) return ofail(WOS_EINVAL, "operators need V = W (n == m)");
   if (co->kind != WOS_LINEAR) return ofail(WOS_EINVAL, "operators exist for LINEAR problems only");
   if (co->solver != WOS_SOLVER_TIKHONOV)
     return ofail(WOS_ENOTIMPL, "operators are prepared with the Tikhonov solver only");

@@ -518,6 +518,8 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
                          double* u, double* grad_u, double* q_out, wos_solve_info* info, hipStream_t st) {
   if (!tb || !co || !f || !g || !u) return sfail(WOS_EINVAL, "NULL argument");
   if (!tb->built) return sfail(WOS_EINVAL, "toolbox has not been built");
+  if (tb->n != tb->m && co->kind != WOS_LINEAR)
+    return sfail(WOS_EINVAL, "only LINEAR solves are supported on a toolbox with a separate V partition");
   const double rcond = co->rcond > 0 ? co->rcond : 1e-3;
   if (!(rcond < 1.0)) return sfail(WOS_EINVAL, "rcond must be in (0, 1)");
   if (co->solver != WOS_SOLVER_TSVD && co->solver != WOS_SOLVER_TIKHONOV)
@@ -654,7 +656,7 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
   if (o->max_iter <= 0) return sfail(WOS_EINVAL, "max_iter must be > 0");
   const int n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
   wos_status s;
-  if (!w.el && (s = walloc(w, &w.el, (size_t)(3 * d + 3) * n + 3 * (size_t)m + 2)) != WOS_OK) return s;
+  if (!w.el && (s = walloc(w, &w.el, (size_t)(3 * d + 2) * n + 4 * (size_t)m + 2)) != WOS_OK) return s;
   double* cvec = w.el;                  // m (= n): c = A^T (-lambda o f)
   double* gB = cvec + m;                // d n: B fbar (at the end: grad u when the caller passes none)
   double* yB = gB + (size_t)d * n;      // (d + 1) n: the B weights, then -lambda f; at the end all weights
@@ -682,7 +684,7 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
     return WOS_OK;
   };
   auto weighted = [&](const double* x, const double* z, double* out) -> wos_status {
-    SHIP(launch_dot(m, x, z, tb->d_lambda, red, st));
+    SHIP(launch_dot(m, x, z, tb->d_lambda_v, red, st));  // the V cells' measures
     SHIP(hipMemcpyAsync(out, red, sizeof(double), hipMemcpyDeviceToHost, st));
     SHIP(hipStreamSynchronize(st));
     return WOS_OK;

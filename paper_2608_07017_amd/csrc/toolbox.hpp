@@ -59,7 +59,7 @@ struct SolveWork {
   double* P64 = nullptr;    // Cholesky work (chol_work_elems(m))
   float* P32 = nullptr;
   float* L0_32 = nullptr;   // Lambda_0 (A = I), FP32, for the mixed Newton route
-  double* el = nullptr;     // Euler-Lagrange route: (3d + 3) n + 3 m + 2 work doubles
+  double* el = nullptr;     // Euler-Lagrange route: (3d + 2) n + 4 m + 2 work doubles
   size_t bytes = 0;         // device memory held
 };
 
@@ -85,11 +85,15 @@ struct wos_toolbox {
   int acc_fixed = 1;
   bool global_tally = false;  // tallies by atomics into the toolbox (rows too large for LDS, or asked for)
   int* d_item_order = nullptr;
-  std::vector<double> sites, bnodes;
+  std::vector<double> sites, vsites, bnodes;  // W centres (n), V centres (m), boundary nodes (p)
+  bool wv = false;  // separate V partition (else V = W and the V arrays alias the W ones)
   // device
-  wos::DevGrid gv, gg;
-  void* d_sites_f32 = nullptr;   // padded centres
+  wos::DevGrid gv, gg;           // nearest V centre (the walker's tallies), nearest boundary node
+  wos::DevGrid gw;               // nearest W centre (cell weights, evaluation off the sites)
+  void* d_sites_f32 = nullptr;   // padded W centres
   void* d_sites_f64 = nullptr;
+  void* d_vsites_f32 = nullptr;  // padded V centres
+  void* d_vsites_f64 = nullptr;
   void* d_bnodes = nullptr;      // toolbox precision, padded
   void* d_segs = nullptr;        // toolbox precision, 5 per edge
   double* d_verts = nullptr;
@@ -100,7 +104,9 @@ struct wos_toolbox {
   uint32_t* d_Hc = nullptr;
   unsigned long long* d_vcount = nullptr;
   unsigned long long* d_stats = nullptr;  // [0..3] walker, [4] volume inside
-  double* d_lambda = nullptr;
+  double* d_lambda = nullptr;          // lambda_i = |W_i| / |D| (n)
+  double* d_lambda_v = nullptr;        // |V_j| / |D| (m)
+  unsigned long long* d_vcount_v = nullptr;
   size_t bytes = 0;
   hipStream_t last_stream = nullptr;
   bool built = false;

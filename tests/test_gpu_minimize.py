@@ -192,3 +192,45 @@ def test_interpolation_reproduces_affine_fields_f32_toolbox():
     d_ref = ((x[bad] - sites[ref_i[bad]]) ** 2).sum(1)
     assert np.all(d_gpu - d_ref <= 1e-6 * d_ref + 1e-12), "a non-tie was binned to another site"
     assert len(bad) < 1e-3 * len(x)
+
+
+def test_separate_v_partition_solve_adam_interpolate():
+    """W != V (40 W centres, 61 V centres, FP64): the linear TSVD solve, Adam
+    (with |V_j| / |D| as the norm's weights) and the evaluation off the
+    sites (binned to the W cells) against the oracle on the exported
+    toolbox."""
+    from oracle import linalg as OL
+    dom = W.unit_disk()
+    sites = W.sample_sites(dom, 40, 31, 1e-3)
+    vc = W.sample_sites(dom, 61, 32, 1e-3)
+    bn = W.circle_nodes(30)
+    _say("GPU build W != V: n=40 m=61")
+    tb = P.Toolbox(dom, sites, bn, 300, 1e-3, seed=13, precision="f64", volume_samples=1 << 16, vcentres=vc)
+    tb.build()
+    torch.cuda.synchronize()
+    mats = {k: tb.export(k).cpu().numpy().astype(np.float64) for k in ("A", "B", "H", "K", "lambda", "lambda_v")}
+    lam, lam_v = mats["lambda"], mats["lambda_v"]
+    f, g = _data(40, 30, 17)
+    # linear: -Lap u = f (paper's sign), TSVD with a threshold away from every singular value
+    Lam, _ = OL.assemble(mats, lam)
+    s_ = np.linalg.svd(Lam, compute_uv=False)
+    rc = next((c for c in (1e-3, 2e-3, 5e-3, 1e-2, 3e-2) if np.min(np.abs(s_ - c * s_[0])) > 1e-4 * c * s_[0]), None)
+    if rc is not None:
+        ref = OL.solve_linear(mats, lam, -f, g, rcond=rc)
+        u, gu, q, info = tb.solve(-f, g, kind="linear", rcond=rc)
+        assert q.numel() == 61
+        assert np.allclose(u.cpu().numpy(), ref["u"], rtol=0, atol=1e-9 * np.abs(ref["u"]).max())
+    # Adam
+    _say("minimize W != V")
+    u, gu, fb, info = tb.minimize(f, g, 3.0, 0.01, 200, fbar0=1.0)
+    ref_fb, it = E.adam(lambda x: E.plaplace_grad(mats, lam, x, g, 3.0, f), np.ones(61), 0.01, 200)
+    assert fb.numel() == 61 and info["iters"] == it == 200
+    assert np.allclose(fb.cpu().numpy(), ref_fb, rtol=0, atol=1e-8 * np.abs(ref_fb).max())
+    ref_gn = E.grad_norm(lam_v, E.plaplace_grad(mats, lam, ref_fb, g, 3.0, f))
+    assert info["grad_norm"] == pytest.approx(ref_gn, rel=1e-6)
+    # evaluation off the sites: the W cells
+    x = _disk_points(5000, 19)
+    v, i = tb.interpolate(u, x, gu)
+    ref_v, ref_i = E.interpolate(sites, u.cpu().numpy(), gu.cpu().numpy(), x)
+    assert np.array_equal(i.cpu().numpy(), ref_i)
+    assert np.allclose(v.cpu().numpy(), ref_v, rtol=0, atol=1e-13 * np.abs(ref_v).max())

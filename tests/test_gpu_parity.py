@@ -142,6 +142,40 @@ def test_per_estimator_walks_and_steps():
         tb1.take(tb3, "A")
 
 
+@pytest.mark.parametrize("m", [25, 61])
+def test_separate_v_partition_fp64(m):
+    """W != V: 40 W centres (the walks' starts), m V centres (coarser and
+    finer), FP64.  The matrices against the oracle's build on the same V
+    centres, exit counts exactly; lambda over W and |V_j| / |D| over V both
+    bit-exact against the oracle's binning of the same volume stream."""
+    dom = W.unit_disk()
+    sites = W.sample_sites(dom, 40, 31, 1e-3)
+    vc = W.sample_sites(dom, m, 32, 1e-3)
+    bn = W.circle_nodes(30)
+    npts = 1 << 14
+    _say("GPU build W != V: n=40 m=%d" % m)
+    tb = P.Toolbox(dom, sites, bn, 300, 1e-3, seed=13, precision="f64", volume_samples=npts, vcentres=vc)
+    tb.build()
+    torch.cuda.synchronize()
+    g = _export_all(tb)
+    assert g["A"].shape == (40, m) and g["B"].shape == (2, 40, m)
+    ref = oracle_build(dom, sites, bn, 300, 1e-3, 13, vcentres=vc)
+    assert np.array_equal(g["Hcount"], ref["Hcount"])
+    for key in ("A", "B", "K"):
+        scale = np.abs(ref[key]).max()
+        assert np.allclose(g[key], ref[key], rtol=1e-10, atol=1e-12 * scale), key
+    cw = cell_counts(dom, sites, 13, npts)
+    cv = cell_counts(dom, vc, 13, npts)
+    assert np.array_equal(g["vcount"].astype(np.int64), cw)
+    assert np.allclose(g["lambda"], cw / cw.sum(), rtol=1e-15, atol=0)
+    assert np.allclose(_np(tb.export("lambda_v")), cv / cv.sum(), rtol=1e-15, atol=0)
+    # routes not supported with n != m are refused
+    with pytest.raises(P.WosError):
+        tb.solve(np.ones(40), np.zeros(30), kind="semilinear_cubic")
+    with pytest.raises(P.WosError):
+        tb.operator()
+
+
 def test_step_cap_counts():
     dom = W.unit_disk()
     sites = W.sample_sites(dom, 9, 8, 1e-2)
