@@ -361,6 +361,28 @@ def el_plaplace(a, torch, W, P):
     out = {"workload": "paper disk p-torsion: 300 ring sites, 60 nodes, %g walks/site, eps 1e-4, FP32; Adam "
                        "(beta 0.9/0.999, eps 1e-10, fbar_0 = 1) to the paper's gradient norms" % a.el_walks,
            "disk": rows}
+    # run on to 20000 iterations (near the minimiser of J): with W = V the
+    # minimiser is far from the closed form; with a finer W partition (1200
+    # ring sites) for the same 300 V cells it is not
+    wfine = []
+    for k in range(1, 21):
+        th = 2 * np.pi * np.arange(6 * k - 3) / (6 * k - 3)
+        wfine.append(np.stack([(k - 0.5) / 20 * np.cos(th), (k - 0.5) / 20 * np.sin(th)], 1))
+    wfine = np.concatenate(wfine)
+    conv = {}
+    for label, wsites, vc in (("W=V=300", sites, None), ("W=1200,V=300", wfine, sites)):
+        tb = P.Toolbox(W.unit_disk(), wsites, bn, a.el_walks, 1e-4, seed=11, precision="f32",
+                       volume_samples=1 << 20, vcentres=vc)
+        tb.build()
+        lam = tb.export("lambda").cpu().numpy()
+        conv[label] = {}
+        for Pexp, alpha in ((1.5, 1e-3), (2.0, 1e-3), (5.0, 1e-2)):
+            u, _, _, info = tb.minimize(np.ones(tb.n), np.zeros(tb.p), Pexp, alpha, 20000, fbar0=1.0)
+            ex = W.plaplace_torsion_disk_exact(wsites, Pexp)
+            conv[label]["P=%g" % Pexp] = float(np.sqrt(np.sum(lam * (u.cpu().numpy() - ex) ** 2))
+                                               / np.sqrt(np.sum(lam * ex ** 2)))
+        tb.free()
+    out["disk_20000_iters_rel_l2_error"] = conv
     cfg = W.config("lshape4096")
     tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], 1000, cfg["eps"], seed=cfg["seed"], precision="f32")
     tb.build()
