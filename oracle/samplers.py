@@ -7,6 +7,10 @@ Prop. "removing singularities" and Rem. "MC_no_singular":
   - d = 2 (part (i.1)): R = median of three uniforms ~ Beta(2,2), Y = R Z,
     and every A/B tally is re-weighted by omega = -(2/3) ln R / (1 - R)
     (the ratio of the radial law of f_Y, -4 t ln t, to Beta(2,2), 6t(1-t));
+  - d = 2, the exact law (also part (i.1)): R = exp((1 + W_{-1}(-U/e))/2)
+    with the lower branch of the Lambert W function, weight 1, U the
+    first of the same three uniforms (``lambert_radius``; the paper uses
+    the median representation for want of a Lambert W in its framework);
   - d = 3 (part (i.2)): R = median of three uniforms ~ Beta(2,2) and
     Y = R^{1/(d-2)} Z = R Z has exactly the law f_Y (omega = 1).  The
     paper's general statement "U_(2) ~ Beta(2/(d-2), 2)" holds only for
@@ -21,14 +25,28 @@ Prop. "removing singularities" and Rem. "MC_no_singular":
 
 Pinned by tests/test_oracle_samplers.py: the CDF of Beta(2,2), the law of
 S (CDF 2t - t^2), E[omega] = 1 and E[omega R^2] = 1/4 (the radial moments
-of f_Y), the first two moments of the sphere directions, and the ball-term
-identity integrated in closed form.
+of f_Y), the first two moments of the sphere directions, the ball-term
+identity integrated in closed form, and the Lambert radius against the
+radial distribution function r^2 (1 - 2 ln r) of f_Y.
 """
 import numpy as np
 
 
 def median3(u1, u2, u3):
     return np.median(np.stack([u1, u2, u3]), axis=0)
+
+
+def lambert_radius(u):
+    """The exact radial law of Y in d = 2 (Prop. "removing singularities"
+    (i.1)): R = exp((1 + W_{-1}(-U/e)) / 2), W_{-1} the lower real branch of
+    the Lambert W function (scipy's lambertw, branch -1); used with weight 1."""
+    from scipy.special import lambertw
+    u = np.asarray(u, dtype=np.float64)
+    w = lambertw(-u / np.e, -1).real
+    # at the branch point y = -1/e (u = 1) W_{-1} = -1 by definition; scipy
+    # returns NaN for the rounded -1/e itself
+    w = np.where(np.isnan(w), -1.0, w)
+    return np.exp(0.5 * (1.0 + w))
 
 
 def omega(R, dim):

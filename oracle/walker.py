@@ -6,7 +6,10 @@ refined form of Rem. "MC_no_singular" (samplers in ``oracle.samplers``).
 For site x = x_i and walk l, with r0 = r(x):
 
 1. per-walk draws: R ~ Beta(2,2), Z, Zs, U1 uniform on the sphere, S;
-   Y = R Z; omega (d = 2 only, else 1); w = (d / r0) U1 (the factor
+   Y = R Z; omega (d = 2 only, else 1) -- or, with sampler="lambert" in
+   d = 2, R from the exact radial law (the Lambert W form of Prop.
+   "removing singularities" (i.1), from the first of the same uniforms)
+   and omega = 1; w = (d / r0) U1 (the factor
    (X_1 - x) d / r0^2 of eqs. Estimator_B and Estimator_K);
 2. ball term of eq. Estimator_B, refined: tally r0 * sum_{k<d} S^k * Zs
    into B at the cell of x + r0 S Zs;
@@ -52,7 +55,7 @@ import numpy as np
 
 from .geometry import distance
 from .philox import walk_block, step_uniforms
-from .samplers import median3, omega, s_of_u, ball_weight_poly, sphere
+from .samplers import median3, omega, s_of_u, ball_weight_poly, sphere, lambert_radius
 from .voronoi import nearest
 
 DEFAULT_MAX_STEPS = 10000
@@ -70,7 +73,7 @@ class SiteEvents:
     """
 
 
-def site_events(dom, x, i, walks, eps, seed, max_steps=DEFAULT_MAX_STEPS, fixed_M=0):
+def site_events(dom, x, i, walks, eps, seed, max_steps=DEFAULT_MAX_STEPS, fixed_M=0, sampler="median3"):
     d = dom["dim"]
     x = np.asarray(x, dtype=np.float64).reshape(d)
     l = np.asarray(walks, dtype=np.int64)
@@ -80,7 +83,10 @@ def site_events(dom, x, i, walks, eps, seed, max_steps=DEFAULT_MAX_STEPS, fixed_
         raise ValueError("site outside the domain")
 
     b0 = walk_block(seed, l, i, 0)
-    R = median3(b0[0], b0[1], b0[2])
+    exact = sampler == "lambert"
+    if exact and d != 2:
+        raise ValueError("the Lambert W sampler is for d = 2")
+    R = lambert_radius(b0[0]) if exact else median3(b0[0], b0[1], b0[2])
     S = s_of_u(b0[3])
     b1 = walk_block(seed, l, i, 1)
     if d == 2:
@@ -92,7 +98,7 @@ def site_events(dom, x, i, walks, eps, seed, max_steps=DEFAULT_MAX_STEPS, fixed_
         Z = sphere(3, [b1[0], b1[1]])
         Zs = sphere(3, [b1[2], b1[3]])
         U1 = sphere(3, [b2[0], b2[1]])
-    om = omega(R, d)
+    om = np.ones_like(R) if exact else omega(R, d)
     Y = R[:, None] * Z
     w = (d / r0) * U1
 
@@ -166,7 +172,7 @@ def bin_site(ev, sites, bnodes, m=None, p=None):
 
 
 def build_toolbox(dom, sites, bnodes, walks, eps, seed, max_steps=DEFAULT_MAX_STEPS,
-                  fixed_M=0, rows=None, vcentres=None):
+                  fixed_M=0, rows=None, vcentres=None, sampler="median3"):
     """The toolbox A (n,m), B (d,n,m), H (n,p), K (d,n,p) of eq. LOT.
 
     Centres: W-centres = ``sites`` (the walks' starting points, n rows),
@@ -191,7 +197,7 @@ def build_toolbox(dom, sites, bnodes, walks, eps, seed, max_steps=DEFAULT_MAX_ST
     maxk = np.zeros(nr, dtype=np.int64)
     capped = np.zeros(nr, dtype=np.int64)
     for row, i in enumerate(rows):
-        ev = site_events(dom, sites[i], int(i), np.arange(walks), eps, seed, max_steps, fixed_M)
+        ev = site_events(dom, sites[i], int(i), np.arange(walks), eps, seed, max_steps, fixed_M, sampler)
         a_row, b_rows, h_row, k_rows = bin_site(ev, vc, bnodes)
         A[row] = a_row / walks
         B[:, row] = b_rows / walks
@@ -205,7 +211,7 @@ def build_toolbox(dom, sites, bnodes, walks, eps, seed, max_steps=DEFAULT_MAX_ST
 
 
 def pointwise(dom, x, i, walks, eps, seed, f=None, g=None, max_steps=DEFAULT_MAX_STEPS,
-              fixed_M=0):
+              fixed_M=0, sampler="median3"):
     """The pointwise estimators of Sec. "Monte Carlo estimators" in their
     refined form: U^f (eq. u MC), grad U^f (eq. gradu U MC), H^g (eq. H MC),
     grad H^g (eq. dh MC), each with its per-walk standard error.
@@ -213,7 +219,7 @@ def pointwise(dom, x, i, walks, eps, seed, f=None, g=None, max_steps=DEFAULT_MAX
     f: callable on points (k,d) -> (k,); g: callable on points -> (k,).
     Returns a dict of means and standard errors.
     """
-    ev = site_events(dom, x, i, np.arange(walks), eps, seed, max_steps, fixed_M)
+    ev = site_events(dom, x, i, np.arange(walks), eps, seed, max_steps, fixed_M, sampler)
     N = walks
     d = dom["dim"]
     out = {"r0": ev.r0, "nsteps": ev.nsteps}

@@ -4,6 +4,9 @@ import numpy as np
 from scipy import stats
 
 from oracle.philox import walk_block
+import pytest
+
+from oracle import samplers as S
 from oracle.samplers import median3, omega, s_of_u, sphere, ball_weight_poly
 
 N = 400_000
@@ -73,3 +76,15 @@ def test_ball_term_identity_linear_f():
         Z = sphere(d, Zu)
         val = (d / 2) * ball_weight_poly(S, d) * S * Z[:, 0] * Z[:, 0]
         assert abs(val.mean() - lhs) < 6 * val.std() / np.sqrt(N)
+
+
+def test_lambert_radius_has_the_green_radial_law():
+    # the radial law of f_Y in d = 2 has the density -4 r ln r and the
+    # distribution function F(r) = r^2 (1 - 2 ln r); R = exp((1 + W_{-1}(-u/e))/2)
+    # must satisfy F(R) = u exactly (up to rounding), with R(1) = 1
+    u = np.concatenate([np.linspace(1e-9, 1.0, 2001), [1e-300, 0.5]])
+    R = S.lambert_radius(u)
+    assert np.all((R > 0) & (R <= 1.0))
+    F = R**2 * (1.0 - 2.0 * np.log(R))
+    assert np.allclose(F, u, rtol=1e-11, atol=1e-15)
+    assert S.lambert_radius(1.0) == pytest.approx(1.0, abs=1e-7)

@@ -138,3 +138,17 @@ def test_separate_v_partition_moves_only_the_columns():
     perm = np.random.default_rng(3).permutation(11)
     wp = build_toolbox(dom, sites, bn, 150, 1e-3, 5, vcentres=vc[perm])
     assert np.array_equal(wp["A"], wv["A"][:, perm]) and np.array_equal(wp["B"], wv["B"][:, :, perm])
+
+
+@pytest.mark.parametrize("x", [[0.3, -0.5], [0.0, 0.0]])
+def test_exact_radius_sampler_closed_forms(x):
+    # the exact radial law (weight 1) gives the same estimators: exit time,
+    # its gradient, and the linear source on the disk
+    x = np.array(x)
+    o = pointwise(DISK, x, 3, 60000, 1e-4, 11, f=lambda p: np.ones(len(p)), sampler="lambert")
+    assert _close(o["U"], o["U_se"], (1 - x @ x) / 2 - 1e-4 / 2, 1e-4 / 2)
+    assert _close(o["gradU"], o["gradU_se"], -x, 2e-4)
+    o = pointwise(DISK, x, 5, 80000, 1e-4, 12, f=lambda p: p[:, 0], sampler="lambert")
+    q = 1 - x @ x
+    assert _close(o["U"], o["U_se"], x[0] * q / 4, 1e-4)
+    assert _close(o["gradU"], o["gradU_se"], (q * np.eye(2)[0] - 2 * x[0] * x) / 4, 1e-4)
