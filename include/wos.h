@@ -102,7 +102,19 @@ typedef struct {
                                mode the sums are in the toolbox precision and
                                their order of addition is not fixed, so results
                                agree with the LDS mode to rounding only.        */
+  int32_t sampler;          /* radial law of Y (the ball-Green density, eq. density
+                               Green), d = 2: WOS_SAMPLER_MEDIAN3 (0) R the median
+                               of three uniforms (Beta(2,2)) with the weight
+                               omega(R) = -(2/3) ln R / (1 - R) (Prop. "removing
+                               singularities" (i.1), the representation the paper
+                               uses); WOS_SAMPLER_LAMBERT (1) the exact law,
+                               R = exp((1 + W_{-1}(-U/e)) / 2) with the lower
+                               branch of the Lambert W function and weight 1 (the
+                               same proposition), U the first of the same three
+                               uniforms.  d = 3 supports only 0.                  */
 } wos_build_opts;
+
+enum { WOS_SAMPLER_MEDIAN3 = 0, WOS_SAMPLER_LAMBERT = 1 };
 
 typedef struct wos_toolbox wos_toolbox;
 

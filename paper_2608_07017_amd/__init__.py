@@ -52,7 +52,7 @@ class Toolbox:
 
     def __init__(self, domain, sites, bnodes, walks, eps, seed=0, precision="f32", max_steps=0,
                  fixed_M=0, volume_samples=0, walks_per_item=0, regen_threshold=0, autotune=True,
-                 tally_in_hbm=False, vcentres=None):
+                 tally_in_hbm=False, vcentres=None, sampler="median3"):
         """`sites` are the W centres (the walks start there, n rows); with
         `vcentres` the tally points are binned to a V partition of its own
         (m columns; include/wos.h, wos_toolbox_create_wv), else V = W."""
@@ -72,7 +72,8 @@ class Toolbox:
                             fixed_M=int(fixed_M), seed=self.seed, precision=PRECISION[precision],
                             volume_samples=int(volume_samples), walks_per_item=int(walks_per_item),
                             regen_threshold=int(regen_threshold), autotune=1 if autotune else 0,
-                            tally_in_hbm=1 if tally_in_hbm else 0)
+                            tally_in_hbm=1 if tally_in_hbm else 0,
+                            sampler={"median3": 0, "lambert": 1}[sampler])
         h = ctypes.c_void_p()
         dp = ctypes.POINTER(ctypes.c_double)
         if self.vcentres is None:

@@ -32,7 +32,7 @@ class WosBuildOpts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
                 ("volume_samples", ctypes.c_int64), ("walks_per_item", ctypes.c_int32),
                 ("regen_threshold", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("tally_in_hbm", ctypes.c_int32)]
+                ("tally_in_hbm", ctypes.c_int32), ("sampler", ctypes.c_int32)]
 
 
 class WosToolboxInfo(ctypes.Structure):

@@ -329,6 +329,7 @@ static void fill_walker_params(const wos_toolbox* tb, uint32_t k0, uint32_t k1, 
   P.item_order = tb->d_item_order;
   P.direct_store = tb->items_per_site == 1 ? 1 : 0;
   P.global_tally = tb->global_tally ? 1 : 0;
+  P.exact_radius = tb->opts.sampler == WOS_SAMPLER_LAMBERT ? 1 : 0;
   P.acc_fixed = f64 ? 0 : tb->acc_fixed;  // FP64 toolboxes accumulate in FP64
   P.A = static_cast<T*>(tb->d_A);
   P.B = static_cast<T*>(tb->d_B);
@@ -387,6 +388,10 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
   if (opts->regen_threshold < 0 || opts->regen_threshold > 64)
     return fail(WOS_EINVAL, "regen_threshold must be in [0, 64]");
   if (opts->walks_per_item < 0) return fail(WOS_EINVAL, "walks_per_item must be >= 0");
+  if (opts->sampler != WOS_SAMPLER_MEDIAN3 && opts->sampler != WOS_SAMPLER_LAMBERT)
+    return fail(WOS_EINVAL, "unknown sampler %d", opts->sampler);
+  if (opts->sampler == WOS_SAMPLER_LAMBERT && dom->dim != 2)
+    return fail(WOS_EINVAL, "the Lambert W sampler is for d = 2");
 
   HostDomain hd;
   hd.kind = dom->kind;

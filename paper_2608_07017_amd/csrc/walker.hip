@@ -117,8 +117,15 @@ struct AccWord<kAccGlobal, T> {
   using type = T;
 };
 
+// KIND carries the domain kind in its low four bits and, in bit 4
+// (kExactRadius), the d = 2 exact radial sampler, so that the default
+// kernels hold none of the sampler's code.
+constexpr int kExactRadius = 16;
+
 template <typename T, int D, int KIND, bool PTS_LDS, int kBlock, int ACC>
 __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
+  constexpr int GEO = KIND & 15;
+  constexpr bool EXACT = D == 2 && (KIND & kExactRadius) != 0;
   constexpr bool GLOBAL = ACC == kAccGlobal;
   using AW = typename AccWord<ACC, T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -190,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   T x[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) x[a] = P.sites[(size_t)site * PS + a];
-  const T r0 = boundary_distance<T, D, KIND>(P.dom, x, sSeg, P.nseg);
+  const T r0 = boundary_distance<T, D, GEO>(P.dom, x, sSeg, P.nseg);
   const T d_over_r0 = T(D) / r0;
   const T r0sq = r0 * r0;
 
@@ -250,7 +257,13 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
         const uint4 b0 = philox(pl, (uint32_t)site, 0u, kTagWalk, P.k0, P.k1);
         const uint4 b1 = philox(pl, (uint32_t)site, 1u, kTagWalk, P.k0, P.k1);
         const T u1 = u01<T>(b0.x), u2 = u01<T>(b0.y), u3 = u01<T>(b0.z);
-        const T R = fmax(fmin(u1, u2), fmin(fmax(u1, u2), u3));  // median of three
+        // median of three (Beta(2,2), reweighted by omega), or in d = 2 the
+        // exact radial law from the first uniform
+        T R;
+        if constexpr (EXACT)
+          R = radius_exact2<T>(u1);
+        else
+          R = fmax(fmin(u1, u2), fmin(fmax(u1, u2), u3));
         const T S = T(1) - dsqrt(u01<T>(b0.w));
         T Z[D], Zs[D];
         T om;
@@ -258,7 +271,10 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
           dir2(u01<T>(b1.x), Z);
           dir2(u01<T>(b1.y), Zs);
           dir2(u01<T>(b1.z), pU1);
-          om = omega2<T>(R);
+          if constexpr (EXACT)
+            om = T(1);
+          else
+            om = omega2<T>(R);
         } else {
           const uint4 b2 = philox(pl, (uint32_t)site, 2u, kTagWalk, P.k0, P.k1);
           dir3(u01<T>(b1.x), u01<T>(b1.y), Z);
@@ -327,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
         l = tl;
         k = 1;
         active = true;
-        r = step_distance<T, D, KIND>(P, X, sSeg);
+        r = step_distance<T, D, GEO>(P, X, sSeg);
 #pragma unroll
         for (int a = 0; a < D; ++a) q[a] = X[a] + r * Y[a];
         rec = load_record<T, D>(P.gv, q);
@@ -392,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
       T Xn[D], qn[D];
 #pragma unroll
       for (int a = 0; a < D; ++a) Xn[a] = X[a] + r * U[a];
-      const T rn = step_distance<T, D, KIND>(P, Xn, sSeg);
+      const T rn = step_distance<T, D, GEO>(P, Xn, sSeg);
 #pragma unroll
       for (int a = 0; a < D; ++a) qn[a] = Xn[a] + rn * Y[a];
       const int4 recn = load_record<T, D>(P.gv, qn);
@@ -567,9 +583,15 @@ hipError_t dispatch(const WalkerParams<T>& P, int dim, int kind, size_t lds, int
                     hipStream_t stream) {
   if (dim == 2) {
     switch (kind) {
-      case WOS_BALL: return launch_typed<T, 2, WOS_BALL>(P, lds, items, stream);
-      case WOS_BOX: return launch_typed<T, 2, WOS_BOX>(P, lds, items, stream);
-      case WOS_POLYGON: return launch_typed<T, 2, WOS_POLYGON>(P, lds, items, stream);
+      case WOS_BALL:
+        return P.exact_radius ? launch_typed<T, 2, WOS_BALL | kExactRadius>(P, lds, items, stream)
+                              : launch_typed<T, 2, WOS_BALL>(P, lds, items, stream);
+      case WOS_BOX:
+        return P.exact_radius ? launch_typed<T, 2, WOS_BOX | kExactRadius>(P, lds, items, stream)
+                              : launch_typed<T, 2, WOS_BOX>(P, lds, items, stream);
+      case WOS_POLYGON:
+        return P.exact_radius ? launch_typed<T, 2, WOS_POLYGON | kExactRadius>(P, lds, items, stream)
+                              : launch_typed<T, 2, WOS_POLYGON>(P, lds, items, stream);
       default: return hipErrorInvalidValue;
     }
   }

@@ -87,6 +87,41 @@ __device__ __forceinline__ T omega2(T R) {
   return T(-2.0 / 3.0) * lr / (T(1) - R);
 }
 
+// W_{-1}(y), y in [-1/e, 0): the lower real branch of the Lambert W function
+// (w e^w = y, w <= -1).  Start from the series at the branch point,
+// w = -1 + p - p^2/3 + 11 p^3/72 with p = -sqrt(2 (1 + e y)), when y is near
+// -1/e, else from the expansion w = L1 - L2 + L2/L1 (L1 = ln(-y),
+// L2 = ln(-L1)); then Halley's iteration on w e^w - y (cubic convergence:
+// three steps reach the working precision from either start).
+template <typename T>
+__device__ __forceinline__ T lambert_wm1(T y) {
+  const T q = fmax(T(0), T(2) * (T(1) + T(2.718281828459045) * y));
+  T w;
+  if (q < T(0.5)) {
+    const T p = -sqrt(q);
+    w = T(-1) + p * (T(1) + p * (T(-1.0 / 3.0) + p * T(11.0 / 72.0)));
+  } else {
+    const T l1 = log(-y), l2 = log(-l1);
+    w = l1 - l2 + l2 / l1;
+  }
+  for (int k = 0; k < 3; ++k) {
+    const T ew = exp(w);
+    const T f = w * ew - y;
+    const T wp1 = w + T(1);
+    if (f == T(0) || wp1 == T(0)) break;
+    w -= f / (ew * wp1 - (w + T(2)) * f / (T(2) * wp1));
+  }
+  return w;
+}
+
+// The exact radial law of Y in d = 2 (Prop. "removing singularities" (i.1)):
+// R = exp((1 + W_{-1}(-u/e)) / 2), whose distribution function
+// r^2 (1 - 2 ln r) equals u.
+template <typename T>
+__device__ __forceinline__ T radius_exact2(T u) {
+  return exp(T(0.5) * (T(1) + lambert_wm1<T>(-u * T(0.36787944117144233))));
+}
+
 // ------------------------------------------------------------- geometry
 // r(x): distance to the boundary (eq. r), specialised per domain kind.
 // Polygon edges are read from LDS: (ax, ay, ex, ey, 1/|e|^2) per edge.

@@ -61,6 +61,7 @@ struct WalkerParams {
   int regen_T;     // refill a wavefront's pool of prepared walks when this many slots are free
   int block_override;  // workgroup size chosen by the caller (0: by occupancy)
   int global_tally;    // tallies by atomics to the toolbox in HBM (rows too large for LDS)
+  int exact_radius;    // d = 2: R from the exact radial law (Lambert W), weight 1
   const int* item_order;  // blockIdx -> item (longest expected work first)
   int direct_store;
   int acc_fixed;   // tally accumulators: 0 FP64, 1 64-bit fixed point

@@ -176,6 +176,34 @@ def test_separate_v_partition_fp64(m):
         tb.operator()
 
 
+def test_lambert_sampler_fp64():
+    """The exact d = 2 radial sampler (Lambert W): A, B against the oracle's
+    build with the same sampler (scipy's W_{-1} there, Halley's iteration on
+    the GPU); the walks do not depend on the sampler, so the exit counts
+    equal the default build's.  Refused in 3-D."""
+    dom = W.unit_disk()
+    sites = W.sample_sites(dom, 37, 5, 1e-3)
+    bn = W.circle_nodes(19)
+    tb, g, _ = _compare_f64_sampler(dom, sites, bn)
+    with pytest.raises(P.WosError):
+        P.Toolbox(W.unit_ball(), W.sample_sites(W.unit_ball(), 3, 1, 1e-3), W.fibonacci_sphere(8), 10, 1e-3,
+                  precision="f64", sampler="lambert")
+
+
+def _compare_f64_sampler(dom, sites, bn):
+    tb = _gpu_tb(dom, sites, bn, 333, 1e-3, 42, precision="f64", volume_samples=1 << 12, sampler="lambert")
+    g = _export_all(tb)
+    ref = oracle_build(dom, sites, bn, 333, 1e-3, 42, sampler="lambert")
+    base = oracle_build(dom, sites, bn, 333, 1e-3, 42)
+    assert np.array_equal(g["Hcount"], ref["Hcount"]) and np.array_equal(ref["Hcount"], base["Hcount"])
+    for key in ("A", "B", "K"):
+        scale = np.abs(ref[key]).max()
+        assert np.allclose(g[key], ref[key], rtol=1e-10, atol=1e-12 * scale), key
+    # the estimators change (another sampler), their row sums agree in mean
+    assert not np.allclose(g["A"], base["A"])
+    return tb, g, ref
+
+
 def test_step_cap_counts():
     dom = W.unit_disk()
     sites = W.sample_sites(dom, 9, 8, 1e-2)
