@@ -17,7 +17,9 @@ the manufactured solutions, and "newton_ball4096": the 3-D unit-ball
 toolbox build and a regularised Newton solve of -Lap u + u^3 = f, mixed
 precision against FP64, and "el_plaplace": Adam on the discrete p-Laplace
 functional (the paper's disk p-torsion example and the iteration rate on
-the 4096-site L-shape toolbox).
+the 4096-site L-shape toolbox), and "el_energies": the minimal surface and
+semilinear energies (closed-form solutions on the unit square, the paper's
+minimal surface data on the disk, and the semilinear iteration rate).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-serving]
 
@@ -402,6 +404,84 @@ def el_plaplace(a, torch, W, P):
     return out
 
 
+def el_energies(a, torch, W, P):
+    """The other energies of the Euler-Lagrange route.  (1) Minimal surface
+    on the unit square with Scherk's boundary values, u = ln(cos k(y - 1/2)
+    / cos k(x - 1/2)) / k at k = 2.5, against that closed form (the harmonic
+    function with the same boundary values is reported beside it); (2) the
+    semilinear Lap u + u^2 = f with u* = sin(pi x) sin(pi y) against u*.
+    Both on W = 64 x 64, V = 32 x 32 cell centres, 160 boundary nodes,
+    el_walks walks/site, FP32, Adam run to a gradient norm of 1e-9 (checked
+    every 100 iterations).  (3) The paper's minimal surface example on the
+    disk (g = 0.3 sin 5 phi; no closed form: J is the graph's area over
+    |D|) and its semilinear example with s = 800 on its 20 x 20 square
+    layout, with its Adam parameters (fbar_0 = 1, alpha 0.01 and 1) to its
+    final gradient norm 1e-6.  (4) The semilinear iteration rate on the 4096-site L-shape
+    toolbox, which streams A and B twice each."""
+    def grid(k):
+        t = (np.arange(k) + 0.5) / k
+        return np.stack(np.meshgrid(t, t, indexing="ij"), -1).reshape(-1, 2)
+    sw, sv, bn = grid(64), grid(32), W.square_nodes(40)
+    tb = P.Toolbox(W.unit_square(), sw, bn, a.el_walks, 1e-4, seed=17, precision="f32", volume_samples=1 << 20,
+                   vcentres=sv)
+    tb.build()
+    torch.cuda.synchronize()
+    lam = tb.export("lambda").cpu().numpy()
+    H = tb.export("H").cpu().numpy().astype(np.float64)
+    err = lambda u, ex: float(np.sqrt(np.sum(lam * (u - ex) ** 2) / np.sum(lam * ex ** 2)))
+    k = 2.5
+    scherk = lambda x: np.log(np.cos(k * (x[:, 1] - 0.5)) / np.cos(k * (x[:, 0] - 0.5))) / k
+    out = {"workload": "unit square, W = 64 x 64, V = 32 x 32 cell centres, 160 boundary nodes, %g walks/site, "
+                       "eps 1e-4, FP32; Adam to |grad J| <= 1e-9" % a.el_walks}
+    u, _, _, info = tb.minimize(np.zeros(tb.n), scherk(bn), 0.0, 0.01, a.el_max_iter, fbar0=0.0,
+                                energy="minimal_surface", tol=1e-9, check_every=100)
+    out["minimal_surface_scherk"] = {"k": k, "alpha": 0.01, "iters": info["iters"], "seconds": info["seconds"],
+                                     "grad_norm": info["grad_norm"],
+                                     "rel_l2_error": err(u.cpu().numpy(), scherk(sw)),
+                                     "harmonic_rel_l2_error": err(H @ scherk(bn), scherk(sw))}
+    ex = np.sin(np.pi * sw[:, 0]) * np.sin(np.pi * sw[:, 1])
+    u, _, _, info = tb.minimize(-2 * np.pi ** 2 * ex + ex ** 2, np.zeros(tb.p), 0.0, 0.1, a.el_max_iter,
+                                fbar0=0.0, energy="semilinear", tol=1e-9, check_every=100)
+    out["semilinear_sin"] = {"alpha": 0.1, "iters": info["iters"], "seconds": info["seconds"],
+                             "grad_norm": info["grad_norm"], "rel_l2_error": err(u.cpu().numpy(), ex)}
+    tb.free()
+    sites, bnd = W.paper_disk_layout()
+    tb = P.Toolbox(W.unit_disk(), sites, bnd, a.el_walks, 1e-4, seed=11, precision="f32", volume_samples=1 << 20)
+    tb.build()
+    phi = np.arctan2(bnd[:, 1], bnd[:, 0])
+    u, _, _, info = tb.minimize(np.zeros(tb.n), 0.3 * np.sin(5 * phi), 0.0, 0.01, a.el_max_iter, fbar0=1.0,
+                                energy="minimal_surface", tol=1e-6 / np.sqrt(np.pi), check_every=50)
+    out["minimal_surface_disk_paper"] = {"alpha": 0.01, "fbar0": 1.0, "iters": info["iters"],
+                                         "seconds": info["seconds"], "grad_norm": info["grad_norm"],
+                                         "J_area_over_D": info["J"], "u_range": [float(u.min()), float(u.max())]}
+    tb.free()
+    sites, bnd = W.paper_square_layout()
+    tb = P.Toolbox(W.unit_square(), sites, bnd, a.el_walks, 1e-4, seed=11, precision="f32", volume_samples=1 << 20)
+    tb.build()
+    f = 800.0 * np.sin(np.pi * sites[:, 0]) * np.sin(np.pi * sites[:, 1])
+    u, _, _, info = tb.minimize(f, np.zeros(tb.p), 0.0, 1.0, a.el_max_iter, fbar0=1.0, energy="semilinear",
+                                tol=1e-6, check_every=50)
+    out["semilinear_s800_square_paper"] = {"alpha": 1.0, "fbar0": 1.0, "iters": info["iters"],
+                                           "seconds": info["seconds"], "grad_norm": info["grad_norm"],
+                                           "J": info["J"], "u_range": [float(u.min()), float(u.max())]}
+    tb.free()
+    cfg = W.config("lshape4096")
+    tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], 1000, cfg["eps"], seed=cfg["seed"], precision="f32")
+    tb.build()
+    torch.cuda.synchronize()
+    n, d = tb.n, tb.dim
+    f, g = np.ones(n), np.zeros(tb.p)
+    tb.minimize(f, g, 0.0, 1e-3, 5, fbar0=0.0, energy="semilinear")
+    _, _, _, info = tb.minimize(f, g, 0.0, 1e-3, a.el_rate_iters, fbar0=0.0, energy="semilinear")
+    per_iter = info["seconds"] / info["iters"]
+    bytes_iter = 2.0 * (d + 1) * n * n * 4  # A and B (FP32), forward and transposed
+    out["lshape4096_semilinear"] = {"iters": info["iters"], "us_per_iter": per_iter * 1e6,
+                                    "AB_bytes_per_iter": bytes_iter, "achieved_GBps": bytes_iter / per_iter / 1e9,
+                                    "hbm_frac": bytes_iter / per_iter / 8e12}
+    tb.free()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -493,6 +573,8 @@ def main():
     if not a.no_el:
         print("euler-lagrange: disk p-torsion, lshape4096", file=sys.stderr, flush=True)
         out["el_plaplace"] = el_plaplace(a, torch, W, P)
+        print("euler-lagrange: minimal surface, semilinear", file=sys.stderr, flush=True)
+        out["el_energies"] = el_energies(a, torch, W, P)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_rows)
     print(json.dumps(out), flush=True)

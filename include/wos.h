@@ -320,13 +320,23 @@ wos_status wos_interpolate(const wos_toolbox* tb, const double* u, const double*
  * with the boxed gradient
  *   grad J = A^T (lambda o dF/du) + sum_a B^(a)^T (lambda o dF/dp_a).
  * Energies:
- *   WOS_EL_PLAPLACE  F = |p|^P / P - f u (eq. plaplace), the weak form of
- *                    -div(|grad u|^(P-2) grad u) = f, u = g.            */
-typedef enum { WOS_EL_PLAPLACE = 0 } wos_energy;
+ *   WOS_EL_PLAPLACE         F = |p|^P / P - f u (eq. plaplace), the weak
+ *                           form of -div(|grad u|^(P-2) grad u) = f, u = g;
+ *   WOS_EL_MINIMAL_SURFACE  F = sqrt(1 + |p|^2) - f u (the minimal surface
+ *                           example, f = 0 there): the graph of least area
+ *                           over D with boundary values g;
+ *   WOS_EL_SEMILINEAR       F = |p|^2 / 2 - u^3 / 3 + f u (the semilinear
+ *                           example): Lap u + u^2 = f, u = g.  Its dF/du
+ *                           depends on u, so an iteration streams A as well
+ *                           as B (twice each), and J is unbounded below:
+ *                           Adam finds a local minimiser, if any, near the
+ *                           start.
+ * p_exp is read for WOS_EL_PLAPLACE only.                                  */
+typedef enum { WOS_EL_PLAPLACE = 0, WOS_EL_MINIMAL_SURFACE = 1, WOS_EL_SEMILINEAR = 2 } wos_energy;
 
 typedef struct {
   int32_t energy;       /* wos_energy                                         */
-  double p_exp;         /* the exponent P > 1                                 */
+  double p_exp;         /* the exponent P > 1 (WOS_EL_PLAPLACE)               */
   double alpha;         /* Adam step size, > 0                                */
   double beta1;         /* in [0, 1); 0 -> 0.9 (the paper's)                  */
   double beta2;         /* in [0, 1); 0 -> 0.999 (the paper's)                */
@@ -354,12 +364,14 @@ typedef struct {
  *   info    host, optional.
  * Every step runs on the device (the toolbox GEMVs in FP64 accumulation,
  * the site weights and the Adam update); the host reads one scalar per
- * norm check.  As dF/du = -f does not depend on u, A^T (lambda o f) and
- * K g are formed once and an iteration streams only B (forward and
- * transposed); u and J are formed at the end.  Runs on `stream` and synchronises it before returning.
+ * norm check.  Where dF/du = -f does not depend on u (p-Laplace, minimal
+ * surface), A^T (lambda o f) and K g are formed once and an iteration
+ * streams only B (forward and transposed); for the semilinear energy it
+ * streams A too, with H g formed once.  u and J are formed at the end.
+ * Runs on `stream` and synchronises it before returning.
  * Errors: WOS_EINVAL for a NULL pointer, an unbuilt toolbox, an unknown
- * energy, P <= 1, alpha <= 0, beta outside [0, 1), eps < 0 or
- * max_iter <= 0.  The work vectors ((3d + 2) n + 4 m doubles) are allocated
+ * energy, P <= 1 (WOS_EL_PLAPLACE), alpha <= 0, beta outside [0, 1), eps < 0 or
+ * max_iter <= 0.  The work vectors ((3d + 4) n + 4 m doubles) are allocated
  * on the first call and kept with the toolbox.  Not thread-safe for one
  * toolbox.                                                                   */
 wos_status wos_minimize(wos_toolbox* tb, const wos_adam_opts* opts, const double* f, const double* g,

@@ -15,9 +15,12 @@ and its gradient (the boxed formula after eq. min_el_discrete)
 
     grad J = A^T (lambda o dF/du) + sum_a B^(a)^T (lambda o dF/dp_a).
 
-The energy built here is the p-Laplace one of Sec. "Solving nonlinear
-elliptic PDEs" (eq. plaplace): F = |p|^P / P - f u, so dF/du = -f and
-dF/dp = |p|^(P-2) p (taken as 0 at p = 0, its limit for P > 1).
+The energies built here are those of the paper's nonlinear examples: the
+p-Laplace one of Sec. "Solving nonlinear elliptic PDEs" (eq. plaplace),
+F = |p|^P / P - f u, so dF/du = -f and dF/dp = |p|^(P-2) p (taken as 0 at
+p = 0, its limit for P > 1); the minimal surface one, F = sqrt(1 + |p|^2)
+- f u (f = 0 in the paper); and the semilinear one of the Breuer-McKenna-
+Plum example, F = |p|^2 / 2 - u^3 / 3 + f u (Lap u + u^2 = f).
 
 The minimiser is Adam as restated in the appendix on the optimisation of
 J: m_j = beta1 m_{j-1} + (1 - beta1) grad, v_j = beta2 v_{j-1} +
@@ -50,14 +53,50 @@ import numpy as np
 from .linalg import reconstruct
 
 
-def plaplace_energy_parts(tb, fbar, g, P, f):
+ENERGIES = ("plaplace", "minimal_surface", "semilinear")
+
+
+def energy_parts(energy, tb, fbar, g, P, f):
     """u, grad u (d, n), the energy density F_i and the weights
-    (dF/du, dF/dp) at the sites, for F = |p|^P / P - f u."""
+    (dF/du, dF/dp) at the sites for the energies of the paper's examples:
+    "plaplace"         F = |p|^P / P - f u                (eq. plaplace)
+    "minimal_surface"  F = sqrt(1 + |p|^2) - f u          (Example "minimal
+                                                           surface", f = 0)
+    "semilinear"       F = |p|^2 / 2 - u^3 / 3 + f u      (Example
+                                                           "semilinear": Lap u + u^2 = f)
+    (P is used by "plaplace" only)."""
     u, gu = reconstruct(tb, fbar, g)
     s = np.sum(gu * gu, axis=0)  # |p_i|^2
-    F = np.power(s, 0.5 * P) / P - f * u
-    c = np.where(s > 0.0, np.power(np.where(s > 0.0, s, 1.0), 0.5 * (P - 2.0)), 0.0)  # |p|^(P-2)
-    return u, gu, F, -f, c * gu
+    if energy == "plaplace":
+        F = np.power(s, 0.5 * P) / P - f * u
+        c = np.where(s > 0.0, np.power(np.where(s > 0.0, s, 1.0), 0.5 * (P - 2.0)), 0.0)  # |p|^(P-2)
+        return u, gu, F, -f, c * gu
+    if energy == "minimal_surface":
+        q = np.sqrt(1.0 + s)
+        return u, gu, q - f * u, -f, gu / q
+    if energy == "semilinear":
+        return u, gu, 0.5 * s - u ** 3 / 3.0 + f * u, f - u * u, gu
+    raise ValueError("unknown energy %r" % energy)
+
+
+def plaplace_energy_parts(tb, fbar, g, P, f):
+    """The parts of energy_parts for F = |p|^P / P - f u."""
+    return energy_parts("plaplace", tb, fbar, g, P, f)
+
+
+def energy_J(energy, tb, lam, fbar, g, P, f):
+    """J(fbar) = sum_i lambda_i F_i   (eq. gradJ)."""
+    _, _, F, _, _ = energy_parts(energy, tb, fbar, g, P, f)
+    return float(np.sum(lam * F))
+
+
+def energy_grad(energy, tb, lam, fbar, g, P, f):
+    """grad J = A^T (lambda o dF/du) + sum_a B^(a)^T (lambda o dF/dp_a)."""
+    _, _, _, dFu, dFp = energy_parts(energy, tb, fbar, g, P, f)
+    grad = tb["A"].T @ (lam * dFu)
+    for a in range(tb["B"].shape[0]):
+        grad = grad + tb["B"][a].T @ (lam * dFp[a])
+    return grad
 
 
 def plaplace_J(tb, lam, fbar, g, P, f):
@@ -98,6 +137,18 @@ def adam(grad_fn, f0, alpha, max_iter, beta1=0.9, beta2=0.999, eps=1e-10, tol=0.
         if tol > 0.0 and j % check_every == 0 and norm_fn(grad_fn(f)) <= tol:
             break
     return f, j
+
+
+def minimize_energy(energy, tb, lam, f, g, P, alpha, max_iter, f0=1.0, tol=0.0, check_every=1, lam_v=None):
+    """Adam on J for any of the energies, from a constant fbar_0 = f0; the
+    stopping norm uses lam_v (the V cells' measures; lam when None)."""
+    m = tb["A"].shape[1]
+    lv = lam if lam_v is None else lam_v
+    fb, it = adam(lambda x: energy_grad(energy, tb, lam, x, g, P, f), np.full(m, float(f0)), alpha, max_iter,
+                  tol=tol, norm_fn=lambda gr: grad_norm(lv, gr), check_every=check_every)
+    u, gu = reconstruct(tb, fb, g)
+    return {"fbar": fb, "u": u, "grad_u": gu, "iters": it, "J": energy_J(energy, tb, lam, fb, g, P, f),
+            "grad_norm": grad_norm(lv, energy_grad(energy, tb, lam, fb, g, P, f))}
 
 
 def minimize_plaplace(tb, lam, f, g, P, alpha, max_iter, f0=1.0, tol=0.0, check_every=1):

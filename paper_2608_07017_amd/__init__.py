@@ -196,8 +196,9 @@ class Toolbox:
                  eps=0.0, energy="plaplace", stream=None):
         """Adam on the discrete functional J of the Euler-Lagrange route
         (include/wos.h, wos_minimize), from the source fbar0 (a scalar for a
-        constant start, or an (m,) array).  Returns (u, grad_u, fbar, info)
-        with device float64 tensors."""
+        constant start, or an (m,) array); energy is "plaplace" (exponent
+        p_exp), "minimal_surface" or "semilinear" (p_exp unused).  Returns
+        (u, grad_u, fbar, info) with device float64 tensors."""
         dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
         f, g = dev(f), dev(g)
         if f.numel() != self.n or g.numel() != self.p:

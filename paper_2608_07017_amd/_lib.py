@@ -85,7 +85,7 @@ class WosAdamInfo(ctypes.Structure):
                 ("grad_norm0", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
-ENERGIES = {"plaplace": 0}
+ENERGIES = {"plaplace": 0, "minimal_surface": 1, "semilinear": 2}
 PROBLEMS = {"linear": 0, "semilinear_cubic": 1, "quasilinear": 2}
 SOLVERS = {"tsvd": 0, "tikhonov": 1}
 SOLVE_PRECISION = {"f64": 0, "mixed": 1}

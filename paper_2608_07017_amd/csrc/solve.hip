@@ -176,35 +176,62 @@ __global__ void pointwise_kernel(int n, const double* __restrict__ lam, const do
   }
 }
 
-// Euler-Lagrange route, p-Laplace energy F = |p|^P / P - f u (eq. gradJ
-// and eq. plaplace): at site i, with s = |grad u_i|^2,
-//   y[a n + i] = lambda_i |p|^(P-2) dp_a   (a < d; 0 where s = 0, the limit
-//                                           for P > 1),
-//   y[d n + i] = -lambda_i f_i              (dF/du),
-//   F[i]       = s^(P/2) / P - f_i u_i      (the energy density),
-// so that grad J = L^T y with L = [B; A].
-__global__ void plaplace_weights_kernel(int n, int d, double P, const double* __restrict__ lam,
-                                        const double* __restrict__ u, const double* __restrict__ gu,
-                                        const double* __restrict__ f, double* __restrict__ y,
-                                        double* __restrict__ F) {
+// Euler-Lagrange route (eq. gradJ): the site weights of grad J = L^T y,
+// L = [B; A], for the energies of the paper's nonlinear examples, with
+// s = |p_i|^2, p_i = grad u_i:
+//   kind 0, p-Laplace (eq. plaplace)   F = s^(P/2) / P - f u,
+//           dF/dp = s^((P-2)/2) p (0 where s = 0, the limit for P > 1),
+//           dF/du = -f;
+//   kind 1, minimal surface            F = sqrt(1 + s) - f u,
+//           dF/dp = p / sqrt(1 + s), dF/du = -f;
+//   kind 2, semilinear (Lap u + u^2 = f) F = s / 2 - u^3 / 3 + f u,
+//           dF/dp = p, dF/du = f - u^2.
+// dF/dp weight factor c(s) with dF/dp = c p:
+__device__ inline double energy_cp(int kind, double P, double s) {
+  if (kind == 1) return 1.0 / sqrt(1.0 + s);
+  if (kind == 2) return 1.0;
+  return s > 0.0 ? pow(s, 0.5 * (P - 2.0)) : 0.0;
+}
+
+// All weights and the density at the result:
+//   y[a n + i] = lambda_i c(s) p_a   (a < d),
+//   y[d n + i] = lambda_i dF/du,
+//   F[i]       = F(u_i, p_i).
+__global__ void energy_weights_kernel(int kind, int n, int d, double P, const double* __restrict__ lam,
+                                      const double* __restrict__ u, const double* __restrict__ gu,
+                                      const double* __restrict__ f, double* __restrict__ y,
+                                      double* __restrict__ F) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += stride) {
     double s = 0.0;
     for (int a = 0; a < d; ++a) s += gu[(size_t)a * n + i] * gu[(size_t)a * n + i];
-    const double c = s > 0.0 ? pow(s, 0.5 * (P - 2.0)) : 0.0;
-    const double li = lam[i];
+    const double c = energy_cp(kind, P, s);
+    const double li = lam[i], ui = u[i], fi = f[i];
     for (int a = 0; a < d; ++a) y[(size_t)a * n + i] = li * c * gu[(size_t)a * n + i];
-    y[(size_t)d * n + i] = -li * f[i];
-    F[i] = (s > 0.0 ? pow(s, 0.5 * P) : 0.0) / P - f[i] * u[i];
+    double Fi;
+    if (kind == 1) {
+      y[(size_t)d * n + i] = -li * fi;
+      Fi = sqrt(1.0 + s) - fi * ui;
+    } else if (kind == 2) {
+      y[(size_t)d * n + i] = li * (fi - ui * ui);
+      Fi = 0.5 * s - ui * ui * ui / 3.0 + fi * ui;
+    } else {
+      y[(size_t)d * n + i] = -li * fi;
+      Fi = (s > 0.0 ? pow(s, 0.5 * P) : 0.0) / P - fi * ui;
+    }
+    F[i] = Fi;
   }
 }
 
-// The gradient part of the same weights, for an energy whose dF/du does not
-// depend on u: yB[a n + i] = lambda_i |p|^(P-2) p_a with p = gB + kg (gB =
-// B fbar, kg = K g fixed over the iteration).
-__global__ void plaplace_wb_kernel(int n, int d, double P, const double* __restrict__ lam,
-                                   const double* __restrict__ gB, const double* __restrict__ kg,
-                                   double* __restrict__ yB) {
+// The weights inside the iteration: yB[a n + i] = lambda_i c(s) p_a with
+// p = gB + kg (gB = B fbar, kg = K g fixed over the iteration); with uA
+// (= A fbar) given, also yA[i] = lambda_i (f_i - u_i^2), u = uA + hg (hg =
+// H g), the u-dependent dF/du of the semilinear energy.
+__global__ void energy_wb_kernel(int kind, int n, int d, double P, const double* __restrict__ lam,
+                                 const double* __restrict__ gB, const double* __restrict__ kg,
+                                 double* __restrict__ yB, const double* __restrict__ uA,
+                                 const double* __restrict__ hg, const double* __restrict__ f,
+                                 double* __restrict__ yA) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += stride) {
     double pa[3] = {0.0, 0.0, 0.0};
@@ -213,8 +240,13 @@ __global__ void plaplace_wb_kernel(int n, int d, double P, const double* __restr
       pa[a] = gB[(size_t)a * n + i] + (kg ? kg[(size_t)a * n + i] : 0.0);
       s += pa[a] * pa[a];
     }
-    const double c = s > 0.0 ? lam[i] * pow(s, 0.5 * (P - 2.0)) : 0.0;
+    const double li = lam[i];
+    const double c = li * energy_cp(kind, P, s);
     for (int a = 0; a < d; ++a) yB[(size_t)a * n + i] = c * pa[a];
+    if (uA) {
+      const double ui = uA[i] + (hg ? hg[i] : 0.0);
+      yA[i] = li * (f[i] - ui * ui);
+    }
   }
 }
 
@@ -589,17 +621,20 @@ hipError_t launch_pointwise(int n, const double* lam, const double* u, const dou
   return hipGetLastError();
 }
 
-hipError_t launch_plaplace_weights(int n, int d, double P, const double* lam, const double* u, const double* gu,
-                                   const double* f, double* y, double* F, hipStream_t st) {
-  hipLaunchKernelGGL(plaplace_weights_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d, P, lam, u, gu, f, y,
-                     F);
+hipError_t launch_energy_weights(int kind, int n, int d, double P, const double* lam, const double* u,
+                                 const double* gu, const double* f, double* y, double* F, hipStream_t st) {
+  if (d < 1 || d > 3) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(energy_weights_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, kind, n, d, P, lam, u, gu, f,
+                     y, F);
   return hipGetLastError();
 }
 
-hipError_t launch_plaplace_wb(int n, int d, double P, const double* lam, const double* gB, const double* kg,
-                              double* yB, hipStream_t st) {
+hipError_t launch_energy_wb(int kind, int n, int d, double P, const double* lam, const double* gB, const double* kg,
+                            double* yB, const double* uA, const double* hg, const double* f, double* yA,
+                            hipStream_t st) {
   if (d < 1 || d > 3) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(plaplace_wb_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d, P, lam, gB, kg, yB);
+  hipLaunchKernelGGL(energy_wb_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, kind, n, d, P, lam, gB, kg, yB, uA,
+                     hg, f, yA);
   return hipGetLastError();
 }
 

@@ -632,31 +632,37 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
 }
 
 // ------------------------------------------------ Euler-Lagrange route
-// Adam on J(fbar) = sum_i lambda_i F(x_i, u_i, grad u_i) (eq. gradJ) for the
-// p-Laplace energy F = |p|^P / P - f u.  Its dF/du = -f does not depend on
+// Adam on J(fbar) = sum_i lambda_i F(x_i, u_i, grad u_i) (eq. gradJ).  For
+// the p-Laplace and minimal surface energies dF/du = -f does not depend on
 // u, so grad J = c + B^T yB with the constant c = A^T (-lambda o f) and
-// yB = lambda |p|^(P-2) p, p = B fbar + K g (K g fixed too).  An iteration
+// yB = lambda dF/dp(p), p = B fbar + K g (K g fixed too).  An iteration
 // therefore streams B twice (B fbar, then B^T yB accumulated onto c) and
-// nothing else: four kernels, all on the device.  u = A fbar + H g and J
-// are formed once at the end.
+// nothing else: four kernels, all on the device.  The semilinear energy's
+// dF/du = f - u^2 does depend on u: its iteration also forms u = A fbar +
+// H g (H g fixed) and accumulates A^T (lambda o dF/du), so it streams A
+// twice as well, c being 0.  u = A fbar + H g and J are formed once at the
+// end.
 wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* o, const double* f, const double* g,
                             double* fbar, double* u, double* grad_u, wos_adam_info* info, hipStream_t st) {
   if (!o || !f || !g || !fbar || !u) return sfail(WOS_EINVAL, "NULL argument");
   if (!tb->built) return sfail(WOS_EINVAL, "toolbox has not been built");
-  if (o->energy != WOS_EL_PLAPLACE) return sfail(WOS_EINVAL, "unknown energy %d", o->energy);
-  const double P = o->p_exp;
+  const int kind = o->energy;
+  if (kind != WOS_EL_PLAPLACE && kind != WOS_EL_MINIMAL_SURFACE && kind != WOS_EL_SEMILINEAR)
+    return sfail(WOS_EINVAL, "unknown energy %d", kind);
+  const bool uterm = kind == WOS_EL_SEMILINEAR;  // dF/du depends on u
+  const double P = kind == WOS_EL_PLAPLACE ? o->p_exp : 2.0;
   const double b1 = o->beta1 > 0 ? o->beta1 : 0.9;
   const double b2 = o->beta2 > 0 ? o->beta2 : 0.999;
   const double eps = o->eps > 0 ? o->eps : 1e-10;
   const int check = o->check_every > 0 ? o->check_every : 50;
-  if (!(P > 1.0)) return sfail(WOS_EINVAL, "p_exp must be > 1");
+  if (kind == WOS_EL_PLAPLACE && !(P > 1.0)) return sfail(WOS_EINVAL, "p_exp must be > 1");
   if (!(o->alpha > 0.0)) return sfail(WOS_EINVAL, "alpha must be > 0");
   if (!(b1 >= 0.0 && b1 < 1.0) || !(b2 >= 0.0 && b2 < 1.0)) return sfail(WOS_EINVAL, "beta1, beta2 must be in [0, 1)");
   if (o->eps < 0.0 || !(o->tol >= 0.0)) return sfail(WOS_EINVAL, "eps and tol must be >= 0");
   if (o->max_iter <= 0) return sfail(WOS_EINVAL, "max_iter must be > 0");
   const int n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
   wos_status s;
-  if (!w.el && (s = walloc(w, &w.el, (size_t)(3 * d + 2) * n + 4 * (size_t)m + 2)) != WOS_OK) return s;
+  if (!w.el && (s = walloc(w, &w.el, (size_t)(3 * d + 4) * n + 4 * (size_t)m + 2)) != WOS_OK) return s;
   double* cvec = w.el;                  // m (= n): c = A^T (-lambda o f)
   double* gB = cvec + m;                // d n: B fbar (at the end: grad u when the caller passes none)
   double* yB = gB + (size_t)d * n;      // (d + 1) n: the B weights, then -lambda f; at the end all weights
@@ -667,20 +673,33 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
   double* mv = grad + m;                // m
   double* vv = mv + m;                  // m
   double* red = vv + m;                 // 2
+  double* hg = red + 2;                 // n: H g (semilinear)
+  double* uA = hg + n;                  // n: A fbar (semilinear)
   SHIP(hipMemsetAsync(mv, 0, sizeof(double) * 2 * (size_t)m, st));
-  // constants of the iteration: c = A^T (-lambda o f) and K g
-  SHIP(launch_pointwise(n, tb->d_lambda, nullptr, f, 0.0, 0.0, 0.0, 0.0, 1.0, yA, st));  // -lambda f
-  SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, yA, 1.0, 0.0, cvec, st));
+  // constants of the iteration: c = A^T (-lambda o f) (0 for the semilinear
+  // energy), K g, and H g when u enters dF/du
+  if (uterm) {
+    SHIP(hipMemsetAsync(cvec, 0, sizeof(double) * m, st));
+    if (p > 0)
+      SHIP(launch_gemv_n_ld(tb->f64, tb->d_H, n, p, p, g, 1.0, 0.0, hg, st));
+    else
+      SHIP(hipMemsetAsync(hg, 0, sizeof(double) * n, st));
+  } else {
+    SHIP(launch_pointwise(n, tb->d_lambda, nullptr, f, 0.0, 0.0, 0.0, 0.0, 1.0, yA, st));  // -lambda f
+    SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, yA, 1.0, 0.0, cvec, st));
+  }
   if (p > 0)
     SHIP(launch_gemv_n_ld(tb->f64, tb->d_K, d * n, p, p, g, 1.0, 0.0, kgv, st));
   else
     SHIP(hipMemsetAsync(kgv, 0, sizeof(double) * (size_t)d * n, st));
   SHIP(hipMemcpyAsync(grad, cvec, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
-  // grad += B^T yB(x)  (grad holds c on entry)
+  // grad += B^T yB(x) (+ A^T yA(x))  (grad holds c on entry)
   auto gradient = [&](const double* x) -> wos_status {
     SHIP(launch_gemv_n_ld(tb->f64, tb->d_B, d * n, m, m, x, 1.0, 0.0, gB, st));
-    SHIP(launch_plaplace_wb(n, d, P, tb->d_lambda, gB, kgv, yB, st));
+    if (uterm) SHIP(launch_gemv_n_ld(tb->f64, tb->d_A, n, m, m, x, 1.0, 0.0, uA, st));
+    SHIP(launch_energy_wb(kind, n, d, P, tb->d_lambda, gB, kgv, yB, uterm ? uA : nullptr, hg, f, yA, st));
     SHIP(launch_gemv_t_acc(tb->f64, tb->d_B, d * n, m, m, yB, 1.0, grad, st));
+    if (uterm) SHIP(launch_gemv_t_acc(tb->f64, tb->d_A, n, m, m, yA, 1.0, grad, st));
     return WOS_OK;
   };
   auto weighted = [&](const double* x, const double* z, double* out) -> wos_status {
@@ -716,7 +735,7 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
   inf.grad_norm = std::sqrt(gg);
   // u, grad u and J = sum_i lambda_i F_i at the result
   if ((s = reconstruct(tb, fbar, g, u, grad_u ? grad_u : gB, st)) != WOS_OK) return s;
-  SHIP(launch_plaplace_weights(n, d, P, tb->d_lambda, u, grad_u ? grad_u : gB, f, yB, F, st));
+  SHIP(launch_energy_weights(kind, n, d, P, tb->d_lambda, u, grad_u ? grad_u : gB, f, yB, F, st));
   SHIP(launch_dot(n, F, tb->d_lambda, nullptr, red, st));
   SHIP(hipMemcpyAsync(&inf.J, red, sizeof(double), hipMemcpyDeviceToHost, st));
   SHIP(hipStreamSynchronize(st));

@@ -32,12 +32,15 @@ hipError_t launch_diag(const double* G, int M, double* e, hipStream_t st);
 hipError_t launch_tsvd_filter(int M, const double* e, double thr, double* z, hipStream_t st);
 hipError_t launch_symmetrize(double* G, int M, hipStream_t st);
 hipError_t launch_dot(int n, const double* x, const double* y, const double* w, double* out, hipStream_t st);
-// Euler-Lagrange route (p-Laplace energy): site weights y = [lambda |p|^(P-2) p;
-// -lambda f] and energy density F; one Adam step on fbar
-hipError_t launch_plaplace_weights(int n, int d, double P, const double* lam, const double* u, const double* gu,
-                                   const double* f, double* y, double* F, hipStream_t st);
-hipError_t launch_plaplace_wb(int n, int d, double P, const double* lam, const double* gB, const double* kg,
-                              double* yB, hipStream_t st);
+// Euler-Lagrange route, energy kind 0 p-Laplace, 1 minimal surface,
+// 2 semilinear: all site weights y = [lambda dF/dp; lambda dF/du] and the
+// energy density F at a result; the weights inside the iteration (yB from
+// p = gB + kg, and with uA non-NULL yA from u = uA + hg); one Adam step
+hipError_t launch_energy_weights(int kind, int n, int d, double P, const double* lam, const double* u,
+                                 const double* gu, const double* f, double* y, double* F, hipStream_t st);
+hipError_t launch_energy_wb(int kind, int n, int d, double P, const double* lam, const double* gB, const double* kg,
+                            double* yB, const double* uA, const double* hg, const double* f, double* yA,
+                            hipStream_t st);
 hipError_t launch_adam(int m, double* g, double b1, double b2, double eps, double aj, double* mv, double* vv,
                        double* fbar, const double* reset, hipStream_t st);
 hipError_t launch_picard_coef(int n, int d, const double* u, double* Ac, hipStream_t st);

@@ -7,6 +7,7 @@ they differ only in the summation order of the products, so the iterates
 agree to rounding (relative 1e-8 after a few hundred steps: Adam's update
 m / (sqrt(v) + eps) is Lipschitz in the gradient with constant 1 / sqrt(v)).
 """
+import ctypes
 import sys
 
 import numpy as np
@@ -234,3 +235,98 @@ def test_separate_v_partition_solve_adam_interpolate():
     ref_v, ref_i = E.interpolate(sites, u.cpu().numpy(), gu.cpu().numpy(), x)
     assert np.array_equal(i.cpu().numpy(), ref_i)
     assert np.allclose(v.cpu().numpy(), ref_v, rtol=0, atol=1e-13 * np.abs(ref_v).max())
+
+
+@pytest.mark.parametrize("energy", ["minimal_surface", "semilinear"])
+def test_other_energies_match_oracle_f64(disk_tb, energy):
+    # the same 300 Adam iterations on both sides; the semilinear energy
+    # also streams A each iteration (its dF/du = f - u^2)
+    tb, mats = disk_tb
+    f, g = _data(tb.n, tb.p, 23)
+    lam = mats["lambda"]
+    _say("minimize %s 300 iters" % energy)
+    u, gu, fb, info = tb.minimize(f, g, 0.0, 0.01, 300, fbar0=0.0, energy=energy)
+    ref = E.minimize_energy(energy, mats, lam, f, g, 0.0, 0.01, 300, f0=0.0)
+    assert info["iters"] == ref["iters"] == 300
+    assert np.allclose(fb.cpu().numpy(), ref["fbar"], rtol=0, atol=1e-8 * np.abs(ref["fbar"]).max())
+    assert np.allclose(u.cpu().numpy(), ref["u"], rtol=0, atol=1e-8 * np.abs(ref["u"]).max())
+    assert np.allclose(gu.cpu().numpy(), ref["grad_u"], rtol=0, atol=1e-8 * np.abs(ref["grad_u"]).max())
+    assert info["J"] == pytest.approx(ref["J"], rel=1e-8, abs=1e-10)
+    assert info["grad_norm"] == pytest.approx(ref["grad_norm"], rel=1e-6)
+
+
+def _square_wv(nw, nv, walks, seed):
+    """The unit square with W = nw x nw and V = nv x nv cell centres (FP32
+    toolbox), 40 boundary nodes per edge."""
+    def grid(k):
+        t = (np.arange(k) + 0.5) / k
+        return np.stack(np.meshgrid(t, t, indexing="ij"), -1).reshape(-1, 2)
+    sw, sv, bn = grid(nw), grid(nv), W.square_nodes(40)
+    _say("GPU build square W=%d V=%d walks=%d" % (nw * nw, nv * nv, walks))
+    tb = P.Toolbox(W.unit_square(), sw, bn, walks, 1e-4, seed=seed, precision="f32", volume_samples=1 << 20,
+                   vcentres=sv)
+    tb.build()
+    torch.cuda.synchronize()
+    return tb, sw, bn, {k: tb.export(k).cpu().numpy().astype(np.float64) for k in ("H", "lambda")}
+
+
+def test_minimal_surface_scherk_square():
+    # Scherk's surface u = ln(cos k(y - 1/2) / cos k(x - 1/2)) / k (k < pi)
+    # has zero mean curvature: with its boundary values it is the minimal
+    # surface over the square.  At k = 2.5 the harmonic function with the
+    # same boundary values is 0.16 away from it in relative L2, so reaching
+    # it shows the nonlinear term at work, not just the boundary fit.
+    k = 2.5
+    scherk = lambda x: np.log(np.cos(k * (x[:, 1] - 0.5)) / np.cos(k * (x[:, 0] - 0.5))) / k
+    tb, sw, bn, mats = _square_wv(32, 16, 20000, 41)
+    lam = mats["lambda"]
+    g = scherk(bn)
+    ex = scherk(sw)
+    err = lambda u: np.sqrt(np.sum(lam * (u - ex) ** 2) / np.sum(lam * ex**2))
+    _say("minimize minimal_surface Scherk k=%g" % k)
+    u, _, _, info = tb.minimize(np.zeros(tb.n), g, 0.0, 0.01, 6000, fbar0=0.0, energy="minimal_surface", tol=1e-9,
+                                check_every=100)
+    e_ms, e_h = err(u.cpu().numpy()), err(mats["H"] @ g)
+    _say("  rel L2 error %.4f (harmonic %.4f), grad norm %.2e, %d iters in %.3f s"
+         % (e_ms, e_h, info["grad_norm"], info["iters"], info["seconds"]))
+    assert e_h > 0.1
+    assert e_ms < 0.06 and e_ms < 0.4 * e_h
+
+
+def test_semilinear_manufactured_square():
+    # Lap u + u^2 = f with u* = sin(pi x) sin(pi y): f = -2 pi^2 u* + u*^2,
+    # u* = 0 on the boundary.  u* is a local minimiser of J (the second
+    # variation -Lap - 2 u* is positive: 2 max u* = 2 < 2 pi^2), which Adam
+    # reaches from fbar = 0.
+    us = lambda x: np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1])
+    tb, sw, bn, mats = _square_wv(32, 16, 20000, 43)
+    lam = mats["lambda"]
+    ex = us(sw)
+    f = -2 * np.pi**2 * ex + ex**2
+    _say("minimize semilinear manufactured")
+    u, _, _, info = tb.minimize(f, np.zeros(tb.p), 0.0, 0.1, 6000, fbar0=0.0, energy="semilinear", tol=1e-8,
+                                check_every=100)
+    e = np.sqrt(np.sum(lam * (u.cpu().numpy() - ex) ** 2) / np.sum(lam * ex**2))
+    _say("  rel L2 error %.4f, grad norm %.2e, %d iters in %.3f s" % (e, info["grad_norm"], info["iters"],
+                                                                     info["seconds"]))
+    assert e < 0.04
+
+
+def test_energy_options(disk_tb):
+    # p_exp is ignored by the energies without an exponent; an unknown
+    # energy code is refused
+    from paper_2608_07017_amd import _lib
+    tb, _ = disk_tb
+    f, g = np.ones(tb.n), np.zeros(tb.p)
+    for energy in ("minimal_surface", "semilinear"):
+        _, _, _, info = tb.minimize(f, g, 0.0, 0.01, 3, fbar0=0.0, energy=energy)
+        assert info["iters"] == 3
+    opts = _lib.WosAdamOpts(energy=7, p_exp=2.0, alpha=0.01, max_iter=3)
+    fd = torch.ones(tb.n, dtype=torch.float64, device="cuda")
+    gd = torch.zeros(tb.p, dtype=torch.float64, device="cuda")
+    fb = torch.zeros(tb.m, dtype=torch.float64, device="cuda")
+    u = torch.empty(tb.n, dtype=torch.float64, device="cuda")
+    st = _lib.lib().wos_minimize(tb._h, ctypes.byref(opts), ctypes.c_void_p(fd.data_ptr()),
+                                 ctypes.c_void_p(gd.data_ptr()), ctypes.c_void_p(fb.data_ptr()),
+                                 ctypes.c_void_p(u.data_ptr()), None, None, None)
+    assert st != 0

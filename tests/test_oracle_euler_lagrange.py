@@ -153,3 +153,43 @@ def test_interpolation_reproduces_affine_fields():
         # at the sites themselves: u_i
         vs, isite = E.interpolate(sites, u, gu, sites)
         assert np.array_equal(isite, np.arange(50)) and np.allclose(vs, u, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("energy", ["minimal_surface", "semilinear"])
+def test_other_energies_gradient_matches_central_differences(energy):
+    tb = _random_tb(9, 4, 2, 21)
+    tb["A"] *= 0.3  # keeps u moderate for the cubic
+    rng = np.random.default_rng(22)
+    lam, f, g, fb = rng.random(9), rng.normal(size=9), rng.normal(size=4), 0.5 * rng.normal(size=9)
+    gr = E.energy_grad(energy, tb, lam, fb, g, 0.0, f)
+    h = 1e-6
+    fd = np.array([(E.energy_J(energy, tb, lam, fb + h * e, g, 0.0, f)
+                    - E.energy_J(energy, tb, lam, fb - h * e, g, 0.0, f)) / (2 * h) for e in np.eye(9)])
+    assert np.allclose(gr, fd, rtol=1e-6, atol=1e-7 * np.abs(fd).max())
+
+
+def test_semilinear_gradient_is_the_regrouped_residual():
+    # F = |p|^2/2 - u^3/3 + f u: grad J = Lambda0 fbar + Sigma0 g + A^T (lam (f - u^2))
+    tb = _random_tb(10, 4, 2, 23)
+    rng = np.random.default_rng(24)
+    lam, f, g, fb = rng.random(10), rng.normal(size=10), rng.normal(size=4), rng.normal(size=10)
+    L0, S0 = L._grad_pairs(tb["B"], tb["K"], lam, None)
+    u = tb["A"] @ fb + tb["H"] @ g
+    ref = L0 @ fb + S0 @ g + tb["A"].T @ (lam * (f - u * u))
+    assert np.allclose(E.energy_grad("semilinear", tb, lam, fb, g, 0.0, f), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_minimal_surface_of_small_slope_is_the_quadratic_energy():
+    # sqrt(1 + |p|^2) = 1 + |p|^2/2 + O(|p|^4): for tiny data the gradients
+    # of the two energies agree to the fourth order
+    tb = _random_tb(8, 3, 2, 25)
+    rng = np.random.default_rng(26)
+    lam, g, fb = rng.random(8), 1e-4 * rng.normal(size=3), 1e-4 * rng.normal(size=8)
+    f = np.zeros(8)
+    a = E.energy_grad("minimal_surface", tb, lam, fb, g, 0.0, f)
+    b = E.energy_grad("plaplace", tb, lam, fb, g, 2.0, f)
+    _, gu = L.reconstruct(tb, fb, g)
+    s = float(np.max(np.sum(gu * gu, axis=0)))  # the gap is O(|p|^2) relative
+    assert s < 1e-5
+    assert np.allclose(a, b, rtol=0, atol=s * np.abs(b).max() * 8)
+    assert not np.allclose(a, b, rtol=0, atol=1e-3 * s * np.abs(b).max())  # but not zero
