@@ -36,6 +36,13 @@ Readings (each listed in the design doc):
 * the paper gives final gradient norms but no stopping rule: a run stops
   after max_iter iterations or once the norm is at most tol.
 
+Saddle points (the semilinear example's several solutions) are searched
+by p-HiSD, ``phisd``, with M = A (n = m) as the paper takes it; its
+initial directions are the eigenvectors of the k smallest eigenvalues of
+the Hessian at fbar_0 (``semilinear_hessian``).  Reading: with M not
+symmetric the M-orthonormalisation uses x^T M y with the left factor as in
+the projections v v^T M.
+
 ``interpolate`` evaluates a solution off the sites, piecewise constant on
 the cells or with the first-order correction <grad u_i, x - x_i>.
 
@@ -161,6 +168,65 @@ def minimize_plaplace(tb, lam, f, g, P, alpha, max_iter, f0=1.0, tol=0.0, check_
     u, gu = reconstruct(tb, fb, g)
     return {"fbar": fb, "u": u, "grad_u": gu, "iters": it, "J": plaplace_J(tb, lam, fb, g, P, f),
             "grad_norm": grad_norm(lam, plaplace_grad(tb, lam, fb, g, P, f))}
+
+
+def semilinear_hessian(tb, lam, fbar, g):
+    """The Hessian of J for F = |p|^2 / 2 - u^3 / 3 + f u:
+    H = sum_a B^(a)^T diag(lambda) B^(a) + A^T diag(lambda (-2 u)) A
+    (d2F/dp2 = I, d2F/du2 = -2u, no mixed term)."""
+    u, _ = reconstruct(tb, fbar, g)
+    H = tb["A"].T @ ((lam * (-2.0 * u))[:, None] * tb["A"])
+    for a in range(tb["B"].shape[0]):
+        H = H + tb["B"][a].T @ (lam[:, None] * tb["B"][a])
+    return H
+
+
+def m_orthonormalize(V, M):
+    """Gram-Schmidt of the columns v_1..v_k of V in the form <x, y>_M =
+    x^T M y (the form of the projections v v^T M of p-HiSD):
+    v_i <- v_i - sum_{l<i} <v_l, v_i>_M v_l, then v_i / <v_i, v_i>_M^(1/2)."""
+    V = np.array(V, dtype=np.float64)
+    for i in range(V.shape[1]):
+        for l in range(i):
+            V[:, i] -= (V[:, l] @ (M @ V[:, i])) * V[:, l]
+        V[:, i] /= np.sqrt(V[:, i] @ (M @ V[:, i]))
+    return V
+
+
+def phisd(grad_fn, f0, V0, M, eta, tau, max_iter, tol=0.0, norm_fn=None, check_every=1):
+    """Preconditioned high-index saddle dynamics (p-HiSD), as the paper
+    states it in its appendix on the optimisation of J: from fbar_0 and k
+    directions V^(0) (M-orthonormalised first), for j >= 1
+      fbar_j = fbar_{j-1} - eta R M^-1 grad J(fbar_{j-1}),
+               R = I - 2 sum_i v_i v_i^T M,
+      v_i   <- v_i - tau P_i M^-1 H(fbar_j) v_i,
+               P_i = I - v_i v_i^T M - 2 sum_{l<i} v_l v_l^T M,
+    all with the previous V, then V M-orthonormalised; H(fbar) v is the
+    central difference (grad J(fbar + h v) - grad J(fbar - h v)) / (2h),
+    h = 1e-6 max(1, |fbar|_2).  With tol > 0 the run stops after iteration
+    j (a multiple of check_every) once norm_fn(grad J(fbar_j)) <= tol.
+    Returns (fbar, V, iterations taken)."""
+    f = np.array(f0, dtype=np.float64)
+    V = m_orthonormalize(V0, M)
+    k = V.shape[1]
+    j = 0
+    for j in range(1, max_iter + 1):
+        w = np.linalg.solve(M, grad_fn(f))
+        Rw = w - 2.0 * sum(V[:, i] * (V[:, i] @ (M @ w)) for i in range(k))
+        f = f - eta * Rw
+        h = 1e-6 * max(1.0, float(np.linalg.norm(f)))
+        Vn = V.copy()
+        for i in range(k):
+            Hv = (grad_fn(f + h * V[:, i]) - grad_fn(f - h * V[:, i])) / (2.0 * h)
+            y = np.linalg.solve(M, Hv)
+            Py = y - V[:, i] * (V[:, i] @ (M @ y))
+            for l in range(i):
+                Py = Py - 2.0 * V[:, l] * (V[:, l] @ (M @ y))
+            Vn[:, i] = V[:, i] - tau * Py
+        V = m_orthonormalize(Vn, M)
+        if tol > 0.0 and j % check_every == 0 and norm_fn(grad_fn(f)) <= tol:
+            break
+    return f, V, j
 
 
 def interpolate(sites, u, grad_u, x):

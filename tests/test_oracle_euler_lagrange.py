@@ -193,3 +193,76 @@ def test_minimal_surface_of_small_slope_is_the_quadratic_energy():
     assert s < 1e-5
     assert np.allclose(a, b, rtol=0, atol=s * np.abs(b).max() * 8)
     assert not np.allclose(a, b, rtol=0, atol=1e-3 * s * np.abs(b).max())  # but not zero
+
+
+def _saddle_quadratic(m, negs, seed):
+    # J = 1/2 x^T H x - b^T x with H = Q diag(e) Q^T, `negs` negative
+    # eigenvalues: the unique critical point is H^-1 b, a saddle of index negs
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.normal(size=(m, m)))
+    e = np.concatenate([-(1.0 + np.arange(negs)), 1.0 + rng.random(m - negs) * 3])
+    H = (Q * e) @ Q.T
+    b = rng.normal(size=m)
+    return H, b, Q, e
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_phisd_finds_the_saddle_of_a_quadratic_and_its_unstable_space(k):
+    # M = I: the fixed point is the critical point H^-1 b, and V spans the
+    # eigenvectors of the k negative eigenvalues (the unstable directions)
+    H, b, Q, e = _saddle_quadratic(8, k, 31)
+    rng = np.random.default_rng(32)
+    V0 = Q[:, :k] + 0.3 * rng.normal(size=(8, k))
+    f, V, it = E.phisd(lambda x: H @ x - b, rng.normal(size=8), V0, np.eye(8), 0.1, 0.1, 3000)
+    assert np.allclose(f, np.linalg.solve(H, b), atol=1e-8)
+    proj = Q[:, :k] @ (Q[:, :k].T @ V)  # V lies in span(Q[:, :k])
+    assert np.allclose(proj, V, atol=1e-6)
+    assert np.allclose(V.T @ V, np.eye(k), atol=1e-10)
+
+
+def test_phisd_with_a_preconditioner_reaches_the_same_saddle():
+    # an SPD M changes the path, not the critical point; the directions are
+    # M-orthonormal at every step
+    H, b, Q, e = _saddle_quadratic(8, 1, 33)
+    rng = np.random.default_rng(34)
+    G = rng.normal(size=(8, 8))
+    M = G @ G.T / 8 + np.eye(8)
+    f, V, it = E.phisd(lambda x: H @ x - b, np.zeros(8), Q[:, :1] + 0.2 * rng.normal(size=(8, 1)), M, 0.05, 0.05,
+                       4000)
+    assert np.allclose(f, np.linalg.solve(H, b), atol=1e-8)
+    assert np.allclose(V.T @ M @ V, np.eye(1), atol=1e-10)
+
+
+def test_phisd_stops_at_the_tolerance():
+    H, b, Q, e = _saddle_quadratic(6, 1, 35)
+    f, V, it = E.phisd(lambda x: H @ x - b, np.zeros(6), Q[:, :1] + 0.1, np.eye(6), 0.1, 0.1, 5000, tol=1e-6,
+                       norm_fn=np.linalg.norm, check_every=10)
+    assert it < 5000 and it % 10 == 0 and np.linalg.norm(H @ f - b) <= 1e-6
+
+
+def test_m_orthonormalize_nonsymmetric_form():
+    # x^T M y with M not symmetric: v_l^T M v_i = 0 for l < i and 1 for l = i
+    rng = np.random.default_rng(36)
+    M = np.eye(7) + 0.2 * rng.normal(size=(7, 7))
+    M = M @ M.T + 0.3 * (rng.normal(size=(7, 7)) - rng.normal(size=(7, 7)))
+    V = E.m_orthonormalize(rng.normal(size=(7, 3)), M)
+    G = V.T @ M @ V
+    assert np.allclose(np.diag(G), 1.0, atol=1e-12)
+    assert np.allclose(np.triu(G, 1), 0.0, atol=1e-12)
+    # M = I: the QR factor (up to column signs)
+    X = rng.normal(size=(7, 3))
+    Qr, _ = np.linalg.qr(X)
+    assert np.allclose(np.abs(E.m_orthonormalize(X, np.eye(7))), np.abs(Qr), atol=1e-12)
+
+
+def test_semilinear_hessian_matches_differences_of_the_gradient():
+    tb = _random_tb(9, 4, 2, 37)
+    tb["A"] *= 0.3
+    rng = np.random.default_rng(38)
+    lam, f, g, fb = rng.random(9), rng.normal(size=9), rng.normal(size=4), rng.normal(size=9)
+    H = E.semilinear_hessian(tb, lam, fb, g)
+    h = 1e-5
+    fd = np.stack([(E.energy_grad("semilinear", tb, lam, fb + h * e, g, 0, f)
+                    - E.energy_grad("semilinear", tb, lam, fb - h * e, g, 0, f)) / (2 * h) for e in np.eye(9)], 1)
+    assert np.allclose(H, fd, rtol=1e-7, atol=1e-8 * np.abs(H).max())
+    assert np.allclose(H, H.T, atol=1e-12 * np.abs(H).max())
