@@ -95,6 +95,7 @@ def parse():
     ap.add_argument("--el-walks", type=int, default=100000)
     ap.add_argument("--el-max-iter", type=int, default=20000)
     ap.add_argument("--el-rate-iters", type=int, default=100)
+    ap.add_argument("--el-conv-iters", type=int, default=20000)
     ap.add_argument("--newton-rcond", type=float, default=1e-2)
     ap.add_argument("--serve-requests", type=int, default=2000, help="open-loop requests (mixed precision)")
     ap.add_argument("--serve-saturation", type=int, default=300, help="requests of the saturation run")
@@ -379,12 +380,12 @@ def el_plaplace(a, torch, W, P):
         lam = tb.export("lambda").cpu().numpy()
         conv[label] = {}
         for Pexp, alpha in ((1.5, 1e-3), (2.0, 1e-3), (5.0, 1e-2)):
-            u, _, _, info = tb.minimize(np.ones(tb.n), np.zeros(tb.p), Pexp, alpha, 20000, fbar0=1.0)
+            u, _, _, info = tb.minimize(np.ones(tb.n), np.zeros(tb.p), Pexp, alpha, a.el_conv_iters, fbar0=1.0)
             ex = W.plaplace_torsion_disk_exact(wsites, Pexp)
             conv[label]["P=%g" % Pexp] = float(np.sqrt(np.sum(lam * (u.cpu().numpy() - ex) ** 2))
                                                / np.sqrt(np.sum(lam * ex ** 2)))
         tb.free()
-    out["disk_20000_iters_rel_l2_error"] = conv
+    out["disk_%d_iters_rel_l2_error" % a.el_conv_iters] = conv
     cfg = W.config("lshape4096")
     tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], 1000, cfg["eps"], seed=cfg["seed"], precision="f32")
     tb.build()
@@ -410,7 +411,7 @@ def el_energies(a, torch, W, P):
     / cos k(x - 1/2)) / k at k = 2.5, against that closed form (the harmonic
     function with the same boundary values is reported beside it); (2) the
     semilinear Lap u + u^2 = f with u* = sin(pi x) sin(pi y) against u*.
-    Both on W = 64 x 64, V = 32 x 32 cell centres, 160 boundary nodes,
+    Both on W = 48 x 48, V = 24 x 24 cell centres, 160 boundary nodes,
     el_walks walks/site, FP32, Adam run to a gradient norm of 1e-9 (checked
     every 100 iterations).  (3) The paper's minimal surface example on the
     disk (g = 0.3 sin 5 phi; no closed form: J is the graph's area over
@@ -421,7 +422,7 @@ def el_energies(a, torch, W, P):
     def grid(k):
         t = (np.arange(k) + 0.5) / k
         return np.stack(np.meshgrid(t, t, indexing="ij"), -1).reshape(-1, 2)
-    sw, sv, bn = grid(64), grid(32), W.square_nodes(40)
+    sw, sv, bn = grid(48), grid(24), W.square_nodes(40)
     tb = P.Toolbox(W.unit_square(), sw, bn, a.el_walks, 1e-4, seed=17, precision="f32", volume_samples=1 << 20,
                    vcentres=sv)
     tb.build()
@@ -431,7 +432,7 @@ def el_energies(a, torch, W, P):
     err = lambda u, ex: float(np.sqrt(np.sum(lam * (u - ex) ** 2) / np.sum(lam * ex ** 2)))
     k = 2.5
     scherk = lambda x: np.log(np.cos(k * (x[:, 1] - 0.5)) / np.cos(k * (x[:, 0] - 0.5))) / k
-    out = {"workload": "unit square, W = 64 x 64, V = 32 x 32 cell centres, 160 boundary nodes, %g walks/site, "
+    out = {"workload": "unit square, W = 48 x 48, V = 24 x 24 cell centres, 160 boundary nodes, %g walks/site, "
                        "eps 1e-4, FP32; Adam to |grad J| <= 1e-9" % a.el_walks}
     u, _, _, info = tb.minimize(np.zeros(tb.n), scherk(bn), 0.0, 0.01, a.el_max_iter, fbar0=0.0,
                                 energy="minimal_surface", tol=1e-9, check_every=100)
