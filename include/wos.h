@@ -377,6 +377,71 @@ typedef struct {
 wos_status wos_minimize(wos_toolbox* tb, const wos_adam_opts* opts, const double* f, const double* g,
                         double* fbar, double* u, double* grad_u, wos_adam_info* info, void* stream);
 
+/* --------------------------------------------- saddle search (p-HiSD)
+ * Critical points of J other than minima (the semilinear example's
+ * several solutions) by preconditioned high-index saddle dynamics, as the
+ * paper states it in its appendix on the optimisation of J: with k
+ * directions v_1..v_k,
+ *   fbar <- fbar - eta R M^-1 grad J(fbar),   R = I - 2 sum_i v_i v_i^T M,
+ *   v_i  <- v_i - tau P_i M^-1 H(fbar) v_i,
+ *           P_i = I - v_i v_i^T M - 2 sum_{l<i} v_l v_l^T M,
+ * then V is M-orthonormalised (Gram-Schmidt in x^T M y, in the order
+ * v_1..v_k).  H(fbar) v is the central difference of grad J with step
+ * h = 1e-6 max(1, |fbar|_2).  M is the identity or, as the paper takes it
+ * for the semilinear example, the toolbox matrix A (then n = m); its
+ * inverse is formed once by the Newton-Schulz iteration X <- X + X (I - A X)
+ * from X_0 = A^T / |A|_F^2 on the FP64 matrix cores.                       */
+typedef enum { WOS_HISD_PRECOND_IDENTITY = 0, WOS_HISD_PRECOND_A = 1 } wos_hisd_precond;
+typedef enum { WOS_HISD_INIT_GIVEN = 0, WOS_HISD_INIT_HESSIAN = 1 } wos_hisd_init;
+
+typedef struct {
+  int32_t energy;       /* wos_energy                                          */
+  double p_exp;         /* P (WOS_EL_PLAPLACE)                                 */
+  int32_t k;            /* the index searched for, 1..8                        */
+  double eta;           /* step of fbar, > 0                                   */
+  double tau;           /* step of the directions, > 0                         */
+  int32_t max_iter;     /* iterations at most, > 0                             */
+  double tol;           /* stop once |grad J|_V <= tol; 0: run max_iter        */
+  int32_t check_every;  /* with tol > 0; 0 -> 50                               */
+  int32_t precond;      /* wos_hisd_precond                                    */
+  int32_t init;         /* wos_hisd_init: the caller's directions, or the
+                           eigenvectors of the k smallest eigenvalues of the
+                           Hessian of J at the start (the paper's choice; the
+                           semilinear energy only)                            */
+} wos_hisd_opts;
+
+typedef struct {
+  int32_t iters;        /* iterations taken                                    */
+  double J;             /* J at the result                                     */
+  double grad_norm;     /* |grad J|_V at the result                            */
+  double grad_norm0;    /* the same at the start                               */
+  double seconds;       /* wall time of the iterations                         */
+  int32_t ns_iters;     /* Newton-Schulz iterations (WOS_HISD_PRECOND_A)       */
+  double ns_residual;   /* |I - A X|_F of the inverse used                     */
+} wos_hisd_info;
+
+/* Runs p-HiSD from the source in `fbar` and leaves the result there.
+ *   f, g    device double (n), (p): the data, as for wos_minimize
+ *   fbar    device double (m): the start on entry, the result on return
+ *   V       device double (k x m, direction i at V + i m): with
+ *           WOS_HISD_INIT_GIVEN the initial directions on entry (any
+ *           linearly independent set); the final directions on return
+ *   u       device double (n) output; grad_u device (d x n) or NULL
+ *   info    host, optional.
+ * An iteration evaluates grad J 2k + 1 times (each streams B, and A for the
+ * semilinear energy, twice) and applies M^-1 k + 1 times (FP64 GEMVs).
+ * Runs on `stream` and synchronises it before returning.
+ * Errors: WOS_EINVAL for a NULL pointer, an unbuilt toolbox, an unknown
+ * energy or option, k outside 1..8 or above m, eta or tau <= 0,
+ * max_iter <= 0, WOS_HISD_PRECOND_A with n != m or m > 16384,
+ * WOS_HISD_INIT_HESSIAN with another energy than WOS_EL_SEMILINEAR, and
+ * directions that are not M-independent (a non-positive x^T M x in the
+ * Gram-Schmidt pass).  Work memory (3 m^2 + 76 m doubles, plus the solver's
+ * work for WOS_HISD_INIT_HESSIAN) is kept with the toolbox.  Not
+ * thread-safe for one toolbox.                                              */
+wos_status wos_saddle(wos_toolbox* tb, const wos_hisd_opts* opts, const double* f, const double* g, double* fbar,
+                      double* V, double* u, double* grad_u, wos_hisd_info* info, void* stream);
+
 /* ---------------------------------------------------- solution operators
  * For a LINEAR problem the map from the data (f, g) to the solution is
  * linear (Sec. "Second order linear elliptic PDEs": q solves eq. linear_q,

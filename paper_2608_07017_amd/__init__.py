@@ -14,8 +14,8 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import (ENERGIES, EXPORTS, KINDS, PRECISION, PROBLEMS, SOLVE_PRECISION, SOLVERS, WosAdamInfo,
-                   WosAdamOpts, WosBuildOpts, WosCoeffs, WosOperatorInfo, WosOperatorOpts,
+from ._lib import (ENERGIES, EXPORTS, HISD_INIT, HISD_PRECOND, KINDS, PRECISION, PROBLEMS, SOLVE_PRECISION, SOLVERS,
+                   WosAdamInfo, WosAdamOpts, WosHisdInfo, WosHisdOpts, WosBuildOpts, WosCoeffs, WosOperatorInfo, WosOperatorOpts,
                    WosDomain, WosError, WosServerOpts, WosSolveInfo, WosToolboxInfo, check, lib)
 
 __all__ = ["Toolbox", "Server", "build_toolbox", "WosError", "lib"]
@@ -218,6 +218,41 @@ class Toolbox:
         check(lib().wos_minimize(self._h, ctypes.byref(opts), _dptr(f), _dptr(g), _dptr(fbar), _dptr(u), _dptr(gu),
                                  ctypes.byref(info), _stream_handle(stream)))
         return u, gu, fbar, {k: getattr(info, k) for k, _ in info._fields_}
+
+    def saddle(self, f, g, k, eta, tau, max_iter, fbar0=1.0, V0=None, precond="A", energy="semilinear", p_exp=0.0,
+               tol=0.0, check_every=0, stream=None):
+        """p-HiSD saddle search on J (include/wos.h, wos_saddle) from the
+        source fbar0 (scalar or (m,) array) with k directions: V0 (k, m) if
+        given, else the eigenvectors of the k smallest eigenvalues of the
+        Hessian at fbar0.  precond is "A" (the paper's M = A) or "identity".
+        Returns (u, grad_u, fbar, V, info) with device float64 tensors."""
+        dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+        f, g = dev(f), dev(g)
+        if f.numel() != self.n or g.numel() != self.p:
+            raise ValueError("f must have n entries and g p entries")
+        if np.ndim(fbar0) == 0:
+            fbar = torch.full((self.m,), float(fbar0), dtype=torch.float64, device="cuda")
+        else:
+            fbar = dev(fbar0).clone()
+            if fbar.numel() != self.m:
+                raise ValueError("fbar0 must have m entries")
+        if not 1 <= int(k) <= 8:
+            raise ValueError("k must be in 1..8")
+        if V0 is None:
+            V = torch.zeros((int(k), self.m), dtype=torch.float64, device="cuda")
+        else:
+            V = dev(V0).clone()
+            if tuple(V.shape) != (int(k), self.m):
+                raise ValueError("V0 must have shape (k, m)")
+        opts = WosHisdOpts(energy=ENERGIES[energy], p_exp=float(p_exp), k=int(k), eta=float(eta), tau=float(tau),
+                           max_iter=int(max_iter), tol=float(tol), check_every=int(check_every),
+                           precond=HISD_PRECOND[precond], init=HISD_INIT["given" if V0 is not None else "hessian"])
+        u = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        gu = torch.empty((self.dim, self.n), dtype=torch.float64, device="cuda")
+        info = WosHisdInfo()
+        check(lib().wos_saddle(self._h, ctypes.byref(opts), _dptr(f), _dptr(g), _dptr(fbar), _dptr(V), _dptr(u),
+                               _dptr(gu), ctypes.byref(info), _stream_handle(stream)))
+        return u, gu, fbar, V, {k_: getattr(info, k_) for k_, _ in info._fields_}
 
     def operator(self, A=None, b=None, c=None, rcond=1e-3, grad=False, storage="f64", stream=None):
         """Prepare the solution operator of the linear problem with these

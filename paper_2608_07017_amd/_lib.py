@@ -85,7 +85,22 @@ class WosAdamInfo(ctypes.Structure):
                 ("grad_norm0", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
+class WosHisdOpts(ctypes.Structure):
+    _fields_ = [("energy", ctypes.c_int32), ("p_exp", ctypes.c_double), ("k", ctypes.c_int32),
+                ("eta", ctypes.c_double), ("tau", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("init", ctypes.c_int32)]
+
+
+class WosHisdInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("J", ctypes.c_double), ("grad_norm", ctypes.c_double),
+                ("grad_norm0", ctypes.c_double), ("seconds", ctypes.c_double), ("ns_iters", ctypes.c_int32),
+                ("ns_residual", ctypes.c_double)]
+
+
 ENERGIES = {"plaplace": 0, "minimal_surface": 1, "semilinear": 2}
+HISD_PRECOND = {"identity": 0, "A": 1}
+HISD_INIT = {"given": 0, "hessian": 1}
 PROBLEMS = {"linear": 0, "semilinear_cubic": 1, "quasilinear": 2}
 SOLVERS = {"tsvd": 0, "tikhonov": 1}
 SOLVE_PRECISION = {"f64": 0, "mixed": 1}
@@ -110,6 +125,8 @@ SIGNATURES = {
     "wos_toolbox_take": (ctypes.c_int, [_P, _P, ctypes.c_uint32, _P]),
     "wos_minimize": (ctypes.c_int, [_P, ctypes.POINTER(WosAdamOpts), _P, _P, _P, _P, _P,
                                     ctypes.POINTER(WosAdamInfo), _P]),
+    "wos_saddle": (ctypes.c_int, [_P, ctypes.POINTER(WosHisdOpts), _P, _P, _P, _P, _P, _P,
+                                  ctypes.POINTER(WosHisdInfo), _P]),
     "wos_toolbox_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "wos_toolbox_get_timings": (ctypes.c_int, [_P, _D, _D, _D]),
     "wos_toolbox_free": (None, [_P]),

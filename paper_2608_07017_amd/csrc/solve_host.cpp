@@ -106,6 +106,26 @@ struct TsvdResult {
   double smax = 0, smin_kept = 0;
 };
 
+// Eigen-decomposition of the symmetric M x M matrix in w.G by cyclic Jacobi
+// sweeps until the off-diagonal mass is below (1e-15)^2 of the diagonal's:
+// eigenvalues to w.E, eigenvectors to the columns of w.V.
+wos_status jacobi_eig(SolveWork& w, int max_sweeps, int* sweeps_out, hipStream_t st) {
+  const int M = w.M;
+  SHIP(launch_set_identity(w.V, M, st));
+  double host2[2] = {0, 0};
+  int sweeps = 0;
+  for (; sweeps < max_sweeps; ++sweeps) {
+    SHIP(launch_offnorm(w.G, M, w.red, st));
+    SHIP(hipMemcpyAsync(host2, w.red, sizeof host2, hipMemcpyDeviceToHost, st));
+    SHIP(hipStreamSynchronize(st));
+    if (!(host2[0] > 1e-30 * host2[1]) || host2[1] == 0.0) break;
+    for (int rd = 0; rd < M - 1; ++rd) SHIP(launch_jacobi_round(w.G, w.V, M, rd, w.rot, w.pq, st));
+  }
+  SHIP(launch_diag(w.G, M, w.E, st));
+  *sweeps_out = sweeps;
+  return WOS_OK;
+}
+
 // q (m) = TSVD(Mat) r (m), Mat m x m; `symmetric` selects the eigen route.
 wos_status tsvd_solve(wos_toolbox* tb, SolveWork& w, const double* Mat, bool symmetric, const double* r,
                       double rcond, int max_sweeps, double* q, TsvdResult* res, hipStream_t st) {
@@ -125,18 +145,9 @@ wos_status tsvd_solve(wos_toolbox* tb, SolveWork& w, const double* Mat, bool sym
     SHIP(launch_pad_copy(Gm, m, m, w.G, M, st));
     SHIP(launch_gemv_t(true, Mat, m, m, r, 1.0, 0.0, rr, st));
   }
-  SHIP(launch_set_identity(w.V, M, st));
-  // Jacobi sweeps until the off-diagonal mass is below (1e-15)^2 of the diagonal's
-  double host2[2] = {0, 0};
   int sweeps = 0;
-  for (; sweeps < max_sweeps; ++sweeps) {
-    SHIP(launch_offnorm(w.G, M, w.red, st));
-    SHIP(hipMemcpyAsync(host2, w.red, sizeof host2, hipMemcpyDeviceToHost, st));
-    SHIP(hipStreamSynchronize(st));
-    if (!(host2[0] > 1e-30 * host2[1]) || host2[1] == 0.0) break;
-    for (int rd = 0; rd < M - 1; ++rd) SHIP(launch_jacobi_round(w.G, w.V, M, rd, w.rot, w.pq, st));
-  }
-  SHIP(launch_diag(w.G, M, w.E, st));
+  wos_status s;
+  if ((s = jacobi_eig(w, max_sweeps, &sweeps, st)) != WOS_OK) return s;
   double emax = 0.0;
   SHIP(launch_absmax(M, w.E, w.red, st));
   SHIP(hipMemcpyAsync(&emax, w.red, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -507,7 +518,8 @@ namespace wos {
 
 void free_work(SolveWork& w) {
   void* ptrs[] = {w.R, w.Lam, w.Sig, w.Lam0, w.Sig0, w.Hess, w.G, w.V, w.E, w.rot, w.pq, w.vec, w.Ac, w.red,
-                  w.blk, w.regv, w.info, w.R32, w.Lam32, w.N32, w.v32, w.P64, w.P32, w.L0_32, w.el};
+                  w.blk, w.regv, w.info, w.R32, w.Lam32, w.N32, w.v32, w.P64, w.P32, w.L0_32, w.el, w.hs,
+                  w.hs_bad};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   w = SolveWork();
@@ -632,6 +644,77 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
 }
 
 // ------------------------------------------------ Euler-Lagrange route
+// grad J for one energy, its constant parts formed once (`setup`):
+// c = A^T (-lambda o f) when dF/du = -f (else 0), K g, and H g when u
+// enters dF/du.  `acc` adds B^T yB(x) (+ A^T yA(x)) onto `out`, which
+// holds c; `eval` first sets out = c.
+struct ElGrad {
+  wos_toolbox* tb = nullptr;
+  int kind = 0;
+  double P = 2.0;
+  bool uterm = false;
+  const double* f = nullptr;
+  double* cvec = nullptr;  // m
+  double* gB = nullptr;    // d n
+  double* yB = nullptr;    // (d + 1) n: the B weights, then yA
+  double* yA = nullptr;
+  double* kgv = nullptr;   // d n
+  double* hg = nullptr;    // n
+  double* uA = nullptr;    // n
+  hipStream_t st = nullptr;
+
+  // carves m + (3d + 3) n doubles from `base`; returns the first one after
+  double* carve(double* base) {
+    const size_t n = tb->n, m = tb->m, d = tb->dim;
+    cvec = base;
+    gB = cvec + m;
+    yB = gB + d * n;
+    yA = yB + d * n;
+    kgv = yA + n;
+    hg = kgv + d * n;
+    uA = hg + n;
+    return uA + n;
+  }
+  wos_status setup(const double* g) {
+    const int n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
+    if (uterm) {
+      SHIP(hipMemsetAsync(cvec, 0, sizeof(double) * m, st));
+      if (p > 0)
+        SHIP(launch_gemv_n_ld(tb->f64, tb->d_H, n, p, p, g, 1.0, 0.0, hg, st));
+      else
+        SHIP(hipMemsetAsync(hg, 0, sizeof(double) * n, st));
+    } else {
+      SHIP(launch_pointwise(n, tb->d_lambda, nullptr, f, 0.0, 0.0, 0.0, 0.0, 1.0, yA, st));  // -lambda f
+      SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, yA, 1.0, 0.0, cvec, st));
+    }
+    if (p > 0)
+      SHIP(launch_gemv_n_ld(tb->f64, tb->d_K, d * n, p, p, g, 1.0, 0.0, kgv, st));
+    else
+      SHIP(hipMemsetAsync(kgv, 0, sizeof(double) * (size_t)d * n, st));
+    return WOS_OK;
+  }
+  wos_status acc(const double* x, double* out) {
+    const int n = tb->n, m = tb->m, d = tb->dim;
+    SHIP(launch_gemv_n_ld(tb->f64, tb->d_B, d * n, m, m, x, 1.0, 0.0, gB, st));
+    if (uterm) SHIP(launch_gemv_n_ld(tb->f64, tb->d_A, n, m, m, x, 1.0, 0.0, uA, st));
+    SHIP(launch_energy_wb(kind, n, d, P, tb->d_lambda, gB, kgv, yB, uterm ? uA : nullptr, hg, f, yA, st));
+    SHIP(launch_gemv_t_acc(tb->f64, tb->d_B, d * n, m, m, yB, 1.0, out, st));
+    if (uterm) SHIP(launch_gemv_t_acc(tb->f64, tb->d_A, n, m, m, yA, 1.0, out, st));
+    return WOS_OK;
+  }
+  wos_status eval(const double* x, double* out) {
+    SHIP(hipMemcpyAsync(out, cvec, sizeof(double) * tb->m, hipMemcpyDeviceToDevice, st));
+    return acc(x, out);
+  }
+};
+
+wos_status check_energy(int kind, double p_exp) {
+  if (kind != WOS_EL_PLAPLACE && kind != WOS_EL_MINIMAL_SURFACE && kind != WOS_EL_SEMILINEAR)
+    return sfail(WOS_EINVAL, "unknown energy %d", kind);
+  if (kind == WOS_EL_PLAPLACE && !(p_exp > 1.0)) return sfail(WOS_EINVAL, "p_exp must be > 1");
+  return WOS_OK;
+}
+
 // Adam on J(fbar) = sum_i lambda_i F(x_i, u_i, grad u_i) (eq. gradJ).  For
 // the p-Laplace and minimal surface energies dF/du = -f does not depend on
 // u, so grad J = c + B^T yB with the constant c = A^T (-lambda o f) and
@@ -647,61 +730,39 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
   if (!o || !f || !g || !fbar || !u) return sfail(WOS_EINVAL, "NULL argument");
   if (!tb->built) return sfail(WOS_EINVAL, "toolbox has not been built");
   const int kind = o->energy;
-  if (kind != WOS_EL_PLAPLACE && kind != WOS_EL_MINIMAL_SURFACE && kind != WOS_EL_SEMILINEAR)
-    return sfail(WOS_EINVAL, "unknown energy %d", kind);
-  const bool uterm = kind == WOS_EL_SEMILINEAR;  // dF/du depends on u
+  wos_status s;
+  if ((s = check_energy(kind, o->p_exp)) != WOS_OK) return s;
   const double P = kind == WOS_EL_PLAPLACE ? o->p_exp : 2.0;
   const double b1 = o->beta1 > 0 ? o->beta1 : 0.9;
   const double b2 = o->beta2 > 0 ? o->beta2 : 0.999;
   const double eps = o->eps > 0 ? o->eps : 1e-10;
   const int check = o->check_every > 0 ? o->check_every : 50;
-  if (kind == WOS_EL_PLAPLACE && !(P > 1.0)) return sfail(WOS_EINVAL, "p_exp must be > 1");
   if (!(o->alpha > 0.0)) return sfail(WOS_EINVAL, "alpha must be > 0");
   if (!(b1 >= 0.0 && b1 < 1.0) || !(b2 >= 0.0 && b2 < 1.0)) return sfail(WOS_EINVAL, "beta1, beta2 must be in [0, 1)");
   if (o->eps < 0.0 || !(o->tol >= 0.0)) return sfail(WOS_EINVAL, "eps and tol must be >= 0");
   if (o->max_iter <= 0) return sfail(WOS_EINVAL, "max_iter must be > 0");
-  const int n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
-  wos_status s;
+  const int n = tb->n, m = tb->m, d = tb->dim;
   if (!w.el && (s = walloc(w, &w.el, (size_t)(3 * d + 4) * n + 4 * (size_t)m + 2)) != WOS_OK) return s;
-  double* cvec = w.el;                  // m (= n): c = A^T (-lambda o f)
-  double* gB = cvec + m;                // d n: B fbar (at the end: grad u when the caller passes none)
-  double* yB = gB + (size_t)d * n;      // (d + 1) n: the B weights, then -lambda f; at the end all weights
-  double* yA = yB + (size_t)d * n;      //   its last n
-  double* kgv = yB + (size_t)(d + 1) * n;  // d n: K g
-  double* F = kgv + (size_t)d * n;      // n: the energy density at the end
+  ElGrad eg;
+  eg.tb = tb;
+  eg.kind = kind;
+  eg.P = P;
+  eg.uterm = kind == WOS_EL_SEMILINEAR;  // dF/du depends on u
+  eg.f = f;
+  eg.st = st;
+  double* F = eg.carve(w.el);           // n: the energy density at the end
   double* grad = F + n;                 // m
   double* mv = grad + m;                // m
   double* vv = mv + m;                  // m
   double* red = vv + m;                 // 2
-  double* hg = red + 2;                 // n: H g (semilinear)
-  double* uA = hg + n;                  // n: A fbar (semilinear)
+  double* gB = eg.gB;                   // at the end: grad u when the caller passes none
+  double* yB = eg.yB;                   // at the end: all weights
+  double* cvec = eg.cvec;
   SHIP(hipMemsetAsync(mv, 0, sizeof(double) * 2 * (size_t)m, st));
-  // constants of the iteration: c = A^T (-lambda o f) (0 for the semilinear
-  // energy), K g, and H g when u enters dF/du
-  if (uterm) {
-    SHIP(hipMemsetAsync(cvec, 0, sizeof(double) * m, st));
-    if (p > 0)
-      SHIP(launch_gemv_n_ld(tb->f64, tb->d_H, n, p, p, g, 1.0, 0.0, hg, st));
-    else
-      SHIP(hipMemsetAsync(hg, 0, sizeof(double) * n, st));
-  } else {
-    SHIP(launch_pointwise(n, tb->d_lambda, nullptr, f, 0.0, 0.0, 0.0, 0.0, 1.0, yA, st));  // -lambda f
-    SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, yA, 1.0, 0.0, cvec, st));
-  }
-  if (p > 0)
-    SHIP(launch_gemv_n_ld(tb->f64, tb->d_K, d * n, p, p, g, 1.0, 0.0, kgv, st));
-  else
-    SHIP(hipMemsetAsync(kgv, 0, sizeof(double) * (size_t)d * n, st));
+  if ((s = eg.setup(g)) != WOS_OK) return s;
   SHIP(hipMemcpyAsync(grad, cvec, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
   // grad += B^T yB(x) (+ A^T yA(x))  (grad holds c on entry)
-  auto gradient = [&](const double* x) -> wos_status {
-    SHIP(launch_gemv_n_ld(tb->f64, tb->d_B, d * n, m, m, x, 1.0, 0.0, gB, st));
-    if (uterm) SHIP(launch_gemv_n_ld(tb->f64, tb->d_A, n, m, m, x, 1.0, 0.0, uA, st));
-    SHIP(launch_energy_wb(kind, n, d, P, tb->d_lambda, gB, kgv, yB, uterm ? uA : nullptr, hg, f, yA, st));
-    SHIP(launch_gemv_t_acc(tb->f64, tb->d_B, d * n, m, m, yB, 1.0, grad, st));
-    if (uterm) SHIP(launch_gemv_t_acc(tb->f64, tb->d_A, n, m, m, yA, 1.0, grad, st));
-    return WOS_OK;
-  };
+  auto gradient = [&](const double* x) -> wos_status { return eg.acc(x, grad); };
   auto weighted = [&](const double* x, const double* z, double* out) -> wos_status {
     SHIP(launch_dot(m, x, z, tb->d_lambda_v, red, st));  // the V cells' measures
     SHIP(hipMemcpyAsync(out, red, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -743,7 +804,205 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
   return WOS_OK;
 }
 
+// ------------------------------------------------ saddle search (p-HiSD)
+// The inverse X ~ A^-1 (m x m, FP64) by Newton-Schulz: X_0 = A^T / |A|_F^2
+// (so that I - A X_0 has its spectrum in [0, 1)), then X <- X + X D with
+// D = I - A X, whose residual squares at each step (I - A X' = D^2).  Stops
+// once |D|_F <= 1e-13 sqrt(m), or when it no longer falls (rounding), or
+// after 100 steps.
+static wos_status ns_inverse(wos_toolbox* tb, double* X, double* Y, double* D, double* red, int* iters,
+                             double* resid, hipStream_t st) {
+  const int m = tb->m;
+  const size_t mm = (size_t)m * m;
+  SHIP(launch_transpose_to_f64(tb->f64, tb->d_A, m, X, st));
+  double nf2 = 0.0;
+  SHIP(launch_dot((int)mm, X, X, nullptr, red, st));
+  SHIP(hipMemcpyAsync(&nf2, red, sizeof(double), hipMemcpyDeviceToHost, st));
+  SHIP(hipStreamSynchronize(st));
+  if (!(nf2 > 0.0) || !std::isfinite(nf2)) return sfail(WOS_EINVAL, "p-HiSD: A is zero or not finite");
+  SHIP(launch_axpby((int)mm, 1.0 / nf2, X, 0.0, nullptr, X, st));
+  double prev = INFINITY, r2 = 0.0;
+  int it = 0;
+  for (; it < 100; ++it) {
+    // D = I - A X
+    if (tb->f64)
+      SHIP(mfma_gemm_f64(false, false, m, m, m, 1.0, static_cast<const double*>(tb->d_A), m, X, m, 0.0, D, m, st));
+    else
+      SHIP(mfma_gemm_f64_a32(false, false, m, m, m, 1.0, static_cast<const float*>(tb->d_A), m, X, m, 0.0, D, m,
+                             st));
+    SHIP(launch_identity_minus(m, D, st));
+    SHIP(launch_dot((int)mm, D, D, nullptr, red, st));
+    SHIP(hipMemcpyAsync(&r2, red, sizeof(double), hipMemcpyDeviceToHost, st));
+    SHIP(hipStreamSynchronize(st));
+    if (!std::isfinite(r2)) return sfail(WOS_EINVAL, "p-HiSD: the inverse of A diverged");
+    if (r2 <= 1e-26 * m || (prev < 1e-6 && r2 > 0.25 * prev)) break;
+    prev = r2;
+    // X <- X + X D  (into Y, then swapped back by copy)
+    SHIP(hipMemcpyAsync(Y, X, sizeof(double) * mm, hipMemcpyDeviceToDevice, st));
+    SHIP(mfma_gemm_f64(false, false, m, m, m, 1.0, X, m, D, m, 1.0, Y, m, st));
+    SHIP(hipMemcpyAsync(X, Y, sizeof(double) * mm, hipMemcpyDeviceToDevice, st));
+  }
+  *iters = it;
+  *resid = std::sqrt(r2);
+  return WOS_OK;
+}
+
+wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o, const double* f, const double* g,
+                          double* fbar, double* V, double* u, double* grad_u, wos_hisd_info* info, hipStream_t st) {
+  if (!o || !f || !g || !fbar || !V || !u) return sfail(WOS_EINVAL, "NULL argument");
+  if (!tb->built) return sfail(WOS_EINVAL, "toolbox has not been built");
+  const int kind = o->energy;
+  wos_status s;
+  if ((s = check_energy(kind, o->p_exp)) != WOS_OK) return s;
+  const int n = tb->n, m = tb->m, d = tb->dim, k = o->k;
+  if (k < 1 || k > 8 || k > m) return sfail(WOS_EINVAL, "k must be in 1..min(8, m)");
+  if (!(o->eta > 0.0) || !(o->tau > 0.0)) return sfail(WOS_EINVAL, "eta and tau must be > 0");
+  if (o->max_iter <= 0) return sfail(WOS_EINVAL, "max_iter must be > 0");
+  if (!(o->tol >= 0.0)) return sfail(WOS_EINVAL, "tol must be >= 0");
+  if (o->precond != WOS_HISD_PRECOND_IDENTITY && o->precond != WOS_HISD_PRECOND_A)
+    return sfail(WOS_EINVAL, "unknown preconditioner %d", o->precond);
+  if (o->init != WOS_HISD_INIT_GIVEN && o->init != WOS_HISD_INIT_HESSIAN)
+    return sfail(WOS_EINVAL, "unknown initialisation %d", o->init);
+  const bool useA = o->precond == WOS_HISD_PRECOND_A;
+  if (useA && (n != m || m > 16384)) return sfail(WOS_EINVAL, "the preconditioner A needs n = m <= 16384");
+  if (o->init == WOS_HISD_INIT_HESSIAN && kind != WOS_EL_SEMILINEAR)
+    return sfail(WOS_EINVAL, "the Hessian initialisation is provided for the semilinear energy only");
+  const int check = o->check_every > 0 ? o->check_every : 50;
+  const double P = kind == WOS_EL_PLAPLACE ? o->p_exp : 2.0;
+  const size_t mm = (size_t)m * m;
+  if (!w.el && (s = walloc(w, &w.el, (size_t)(3 * d + 4) * n + 4 * (size_t)m + 2)) != WOS_OK) return s;
+  const size_t hs_len = 3 * mm + 76 * (size_t)m + 8;
+  if (!w.hs && (s = walloc(w, &w.hs, hs_len)) != WOS_OK) return s;
+  if (!w.hs_bad && (s = walloc(w, &w.hs_bad, 1)) != WOS_OK) return s;
+  ElGrad eg;
+  eg.tb = tb;
+  eg.kind = kind;
+  eg.P = P;
+  eg.uterm = kind == WOS_EL_SEMILINEAR;
+  eg.f = f;
+  eg.st = st;
+  double* F = eg.carve(w.el);  // n
+  double* red = F + n;         // 2 (the Adam route's slots are not used here)
+  double* Minv = w.hs;         // m^2
+  double* Y2 = Minv + mm;      // m^2 (Newton-Schulz)
+  double* D = Y2 + mm;         // m^2 (Newton-Schulz)
+  double* Vc = D + mm;         // 8 m: the directions
+  double* Vn = Vc + 8 * (size_t)m;   // 8 m
+  double* MV = Vn + 8 * (size_t)m;   // 8 m: M V
+  double* HV = MV + 8 * (size_t)m;   // 8 m
+  double* Yv = HV + 8 * (size_t)m;   // 8 m: M^-1 H V
+  double* Xs = Yv + 8 * (size_t)m;   // 16 m: fbar +- h v_i
+  double* Gs = Xs + 16 * (size_t)m;  // 16 m: their gradients
+  double* gr = Gs + 16 * (size_t)m;  // m
+  double* wv = gr + m;               // m: M^-1 grad J
+  double* hbuf = wv + m;             // 8: the difference step h (device)
+  if ((size_t)(hbuf + 8 - w.hs) > hs_len) return sfail(WOS_EINVAL, "p-HiSD: work layout");
+  wos_hisd_info inf{};
+  if ((s = eg.setup(g)) != WOS_OK) return s;
+  if (useA && (s = ns_inverse(tb, Minv, Y2, D, red, &inf.ns_iters, &inf.ns_residual, st)) != WOS_OK) return s;
+  // y = M^-1 x, and M x, for one vector
+  auto minv = [&](const double* x, double* y) -> wos_status {
+    if (useA)
+      SHIP(launch_gemv_n(true, Minv, m, m, x, 1.0, 0.0, y, st));
+    else
+      SHIP(hipMemcpyAsync(y, x, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    return WOS_OK;
+  };
+  auto mult = [&](const double* x, double* y) -> wos_status {
+    if (useA)
+      SHIP(launch_gemv_n_ld(tb->f64, tb->d_A, m, m, m, x, 1.0, 0.0, y, st));
+    else
+      SHIP(hipMemcpyAsync(y, x, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    return WOS_OK;
+  };
+  auto orthonormalise = [&](double* Vx) -> wos_status {
+    for (int i = 0; i < k; ++i)
+      if ((s = mult(Vx + (size_t)i * m, MV + (size_t)i * m)) != WOS_OK) return s;
+    SHIP(hipMemsetAsync(w.hs_bad, 0, sizeof(int), st));
+    SHIP(launch_hisd_gs(m, k, Vx, MV, w.hs_bad, st));
+    int bad = 0;
+    SHIP(hipMemcpyAsync(&bad, w.hs_bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    SHIP(hipStreamSynchronize(st));
+    if (bad) return sfail(WOS_EINVAL, "p-HiSD: the directions are not M-independent");
+    return WOS_OK;
+  };
+  auto weighted_norm = [&](const double* x, double* out) -> wos_status {
+    SHIP(launch_dot(m, x, x, tb->d_lambda_v, red, st));
+    SHIP(hipMemcpyAsync(out, red, sizeof(double), hipMemcpyDeviceToHost, st));
+    SHIP(hipStreamSynchronize(st));
+    *out = std::sqrt(*out);
+    return WOS_OK;
+  };
+  // the initial directions
+  if (o->init == WOS_HISD_INIT_HESSIAN) {
+    // H = Lambda_0 + A^T diag(lambda (-2 u)) A at fbar, u = A fbar + H g;
+    // its k lowest eigenvectors
+    if ((s = ensure_work(tb, w)) != WOS_OK) return s;
+    if ((s = assemble(tb, w, nullptr, nullptr, nullptr, w.Lam0, w.Sig0, st)) != WOS_OK) return s;
+    double* uu = w.vec;                 // n
+    double* t2 = w.vec + w.vlen;        // n
+    if ((s = reconstruct(tb, fbar, g, uu, nullptr, st)) != WOS_OK) return s;
+    SHIP(launch_pointwise(n, tb->d_lambda, uu, nullptr, 0.0, -2.0, 0.0, 0.0, 0.0, t2, st));  // -2 lambda u
+    SHIP(hipMemcpyAsync(w.Hess, w.Lam0, sizeof(double) * mm, hipMemcpyDeviceToDevice, st));
+    SHIP(launch_gram(tb->f64, tb->d_A, n, m, t2, w.Hess, st));
+    SHIP(launch_pad_copy(w.Hess, m, m, w.G, w.M, st));
+    SHIP(launch_symmetrize(w.G, w.M, st));
+    int sweeps = 0;
+    if ((s = jacobi_eig(w, 60, &sweeps, st)) != WOS_OK) return s;
+    SHIP(launch_hisd_select(w.M, m, k, w.E, w.V, Vc, st));
+  } else {
+    SHIP(hipMemcpyAsync(Vc, V, sizeof(double) * k * (size_t)m, hipMemcpyDeviceToDevice, st));
+  }
+  if ((s = orthonormalise(Vc)) != WOS_OK) return s;
+  double gn = 0.0;
+  if ((s = eg.eval(fbar, gr)) != WOS_OK) return s;
+  if ((s = weighted_norm(gr, &inf.grad_norm0)) != WOS_OK) return s;
+  const auto t0 = std::chrono::steady_clock::now();
+  int it = 0;
+  for (int j = 1; j <= o->max_iter; ++j) {
+    // fbar_j = fbar_{j-1} - eta R M^-1 grad J(fbar_{j-1})  (gr holds the gradient)
+    if ((s = minv(gr, wv)) != WOS_OK) return s;
+    SHIP(launch_hisd_fbar(m, k, Vc, gr, wv, o->eta, fbar, hbuf, st));
+    // H(fbar_j) v_i by central differences
+    SHIP(launch_hisd_shift(m, k, fbar, Vc, hbuf, Xs, st));
+    for (int i = 0; i < 2 * k; ++i)
+      if ((s = eg.eval(Xs + (size_t)i * m, Gs + (size_t)i * m)) != WOS_OK) return s;
+    SHIP(launch_hisd_hv(m, k, Gs, hbuf, HV, st));
+    for (int i = 0; i < k; ++i)
+      if ((s = minv(HV + (size_t)i * m, Yv + (size_t)i * m)) != WOS_OK) return s;
+    SHIP(launch_hisd_v(m, k, Vc, HV, Yv, o->tau, Vn, st));
+    if ((s = orthonormalise(Vn)) != WOS_OK) return s;
+    std::swap(Vc, Vn);
+    it = j;
+    if ((s = eg.eval(fbar, gr)) != WOS_OK) return s;  // at fbar_j: the next step and the checks
+    if (o->tol > 0.0 && j % check == 0) {
+      if ((s = weighted_norm(gr, &gn)) != WOS_OK) return s;
+      if (gn <= o->tol) break;
+    }
+  }
+  SHIP(hipStreamSynchronize(st));
+  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  inf.iters = it;
+  if ((s = weighted_norm(gr, &inf.grad_norm)) != WOS_OK) return s;
+  SHIP(hipMemcpyAsync(V, Vc, sizeof(double) * k * (size_t)m, hipMemcpyDeviceToDevice, st));
+  // u, grad u and J at the result
+  if ((s = reconstruct(tb, fbar, g, u, grad_u ? grad_u : eg.gB, st)) != WOS_OK) return s;
+  SHIP(launch_energy_weights(kind, n, d, P, tb->d_lambda, u, grad_u ? grad_u : eg.gB, f, eg.yB, F, st));
+  SHIP(launch_dot(n, F, tb->d_lambda, nullptr, red, st));
+  SHIP(hipMemcpyAsync(&inf.J, red, sizeof(double), hipMemcpyDeviceToHost, st));
+  SHIP(hipStreamSynchronize(st));
+  if (info) *info = inf;
+  return WOS_OK;
+}
+
 }  // namespace wos
+
+extern "C" wos_status wos_saddle(wos_toolbox* tb, const wos_hisd_opts* opts, const double* f, const double* g,
+                                 double* fbar, double* V, double* u, double* grad_u, wos_hisd_info* info,
+                                 void* stream) {
+  if (!tb) return sfail(WOS_EINVAL, "NULL argument");
+  return wos::saddle_request(tb, tb->sw, opts, f, g, fbar, V, u, grad_u, info, static_cast<hipStream_t>(stream));
+}
 
 extern "C" wos_status wos_minimize(wos_toolbox* tb, const wos_adam_opts* opts, const double* f, const double* g,
                                    double* fbar, double* u, double* grad_u, wos_adam_info* info, void* stream) {

@@ -59,7 +59,9 @@ struct SolveWork {
   double* P64 = nullptr;    // Cholesky work (chol_work_elems(m))
   float* P32 = nullptr;
   float* L0_32 = nullptr;   // Lambda_0 (A = I), FP32, for the mixed Newton route
-  double* el = nullptr;     // Euler-Lagrange route: (3d + 2) n + 4 m + 2 work doubles
+  double* el = nullptr;     // Euler-Lagrange route: (3d + 4) n + 4 m + 2 work doubles
+  double* hs = nullptr;     // p-HiSD: 3 m^2 + 76 m + 8 work doubles
+  int* hs_bad = nullptr;    // p-HiSD: Gram-Schmidt status (device)
   size_t bytes = 0;         // device memory held
 };
 
@@ -69,6 +71,9 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
 // Adam on the discrete functional J (C ABI wos_minimize).
 wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* o, const double* f, const double* g,
                             double* fbar, double* u, double* grad_u, wos_adam_info* info, hipStream_t st);
+// p-HiSD saddle search on J (C ABI wos_saddle).
+wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o, const double* f, const double* g,
+                          double* fbar, double* V, double* u, double* grad_u, wos_hisd_info* info, hipStream_t st);
 void free_work(SolveWork& w);
 
 }  // namespace wos

@@ -98,6 +98,19 @@ hipError_t launch_add_diag(bool f64, void* N, int m, int ld, const double* reg, 
 hipError_t launch_axpy_reg(int n, const double* x, const double* reg, double sign, const double* z, double* y,
                            hipStream_t st);
 hipError_t launch_to_f32(int n, const double* x, float* y, hipStream_t st);
+// ---- p-HiSD (phisd.hip): k <= 8 directions stored as V[i m + j]
+hipError_t launch_hisd_fbar(int m, int k, const double* V, const double* gr, const double* w, double eta, double* fbar,
+                            double* h, hipStream_t st);
+hipError_t launch_hisd_shift(int m, int k, const double* fbar, const double* V, const double* h, double* X,
+                             hipStream_t st);
+hipError_t launch_hisd_hv(int m, int k, const double* G, const double* h, double* HV, hipStream_t st);
+hipError_t launch_hisd_v(int m, int k, const double* V, const double* HV, const double* Y, double tau, double* Vn,
+                         hipStream_t st);
+hipError_t launch_hisd_gs(int m, int k, double* V, double* MV, int* bad, hipStream_t st);
+hipError_t launch_hisd_select(int Mp, int m, int k, const double* e, const double* Evec, double* Vout,
+                              hipStream_t st);
+hipError_t launch_transpose_to_f64(bool f64, const void* A, int m, double* X, hipStream_t st);
+hipError_t launch_identity_minus(int m, double* D, hipStream_t st);
 hipError_t launch_add_f32(int n, const float* dlt, double* q, hipStream_t st);
 
 }  // namespace wos

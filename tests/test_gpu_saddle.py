@@ -1,0 +1,142 @@
+"""p-HiSD saddle search on the GPU (wos_saddle through the C ABI) against
+the oracle's p-HiSD on the exported toolbox.
+
+Both sides run the same iteration on the same matrices.  They differ in
+the summation order, in M^-1 (Newton-Schulz on the GPU, an LU solve in the
+oracle; both to rounding times the condition of A) and in the rounding of
+the central differences (relative eps |grad J| / h, h = 1e-6 |fbar|), so
+iterates after a few steps agree to about 1e-7 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import euler_lagrange as E
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_2608_07017_amd")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rings(K):
+    pts = []
+    for k in range(1, K + 1):
+        nk = 6 * k - 3
+        r = (k - 0.5) / K
+        th = 2 * np.pi * np.arange(nk) / nk
+        pts.append(np.stack([r * np.cos(th), r * np.sin(th)], 1))
+    return np.concatenate(pts)
+
+
+@pytest.fixture(scope="module")
+def ring_tb():
+    _say("GPU build disk rings 5, 1500 walks, FP64")
+    tb = P.Toolbox(W.unit_disk(), _rings(5), W.circle_nodes(30), 1500, 1e-3, seed=11, precision="f64",
+                   volume_samples=1 << 18)
+    tb.build()
+    torch.cuda.synchronize()
+    mats = {k: tb.export(k).cpu().numpy().astype(np.float64) for k in ("A", "B", "H", "K", "lambda")}
+    return tb, mats
+
+
+def _problem(n, p, seed):
+    rng = np.random.default_rng(seed)
+    return 2.0 + rng.normal(size=n), 0.1 * rng.normal(size=p)
+
+
+@pytest.mark.parametrize("precond,eta,tau", [("A", 0.5, 0.5), ("identity", 20.0, 20.0)])
+def test_saddle_given_directions_matches_oracle(ring_tb, precond, eta, tau):
+    tb, mats = ring_tb
+    lam = mats["lambda"]
+    f, g = _problem(tb.n, tb.p, 5)
+    rng = np.random.default_rng(6)
+    V0 = rng.normal(size=(2, tb.m))
+    fb0 = 1.0 + 0.1 * rng.normal(size=tb.m)
+    iters = 12
+    _say("saddle precond=%s k=2 iters=%d" % (precond, iters))
+    u, gu, fb, V, info = tb.saddle(f, g, 2, eta, tau, iters, fbar0=fb0, V0=V0, precond=precond)
+    M = mats["A"] if precond == "A" else np.eye(tb.m)
+    gr = lambda x: E.energy_grad("semilinear", mats, lam, x, g, 0.0, f)
+    ref_fb, ref_V, it = E.phisd(gr, fb0, V0.T, M, eta, tau, iters)
+    assert info["iters"] == it == iters
+    fb, V = fb.cpu().numpy(), V.cpu().numpy()
+    assert np.abs(fb - ref_fb).max() <= 1e-7 * np.abs(ref_fb).max()
+    assert np.abs(V.T - ref_V).max() <= 1e-6 * np.abs(ref_V).max()
+    ref_u, ref_gu = E.reconstruct(mats, ref_fb, g)
+    assert np.abs(u.cpu().numpy() - ref_u).max() <= 1e-7 * np.abs(ref_u).max()
+    assert info["grad_norm"] == pytest.approx(E.grad_norm(lam, gr(ref_fb)), rel=1e-5)
+    assert info["grad_norm0"] == pytest.approx(E.grad_norm(lam, gr(fb0)), rel=1e-10)
+    assert info["J"] == pytest.approx(E.energy_J("semilinear", mats, lam, ref_fb, g, 0.0, f), rel=1e-7)
+    if precond == "A":
+        assert info["ns_iters"] > 0 and info["ns_residual"] < 1e-8
+        # the directions are M-orthonormal in the Gram-Schmidt sense
+        G = V @ M @ V.T
+        assert np.allclose(np.diag(G), 1.0, atol=1e-9) and abs(G[0, 1]) < 1e-9
+
+
+def test_saddle_hessian_initialisation_matches_oracle(ring_tb):
+    # the directions start as the eigenvectors of the k smallest eigenvalues
+    # of the Hessian at fbar_0; fbar's update is invariant to their signs and
+    # V is compared up to them.  The eigenvalue gaps are checked first.
+    tb, mats = ring_tb
+    lam = mats["lambda"]
+    f, g = _problem(tb.n, tb.p, 7)
+    fb0 = np.full(tb.m, 30.0)
+    H0 = E.semilinear_hessian(mats, lam, fb0, g)
+    ev, evec = np.linalg.eigh(0.5 * (H0 + H0.T))
+    k = 2
+    gaps = np.diff(ev[: k + 1])
+    assert gaps.min() > 1e-6 * np.abs(ev).max(), "near-degenerate eigenvalues: the test needs other data"
+    _say("saddle hessian init k=%d" % k)
+    for iters in (1, 6):
+        _, _, fb, V, info = tb.saddle(f, g, k, 0.5, 0.5, iters, fbar0=fb0, precond="A")
+        gr = lambda x: E.energy_grad("semilinear", mats, lam, x, g, 0.0, f)
+        ref_fb, ref_V, _ = E.phisd(gr, fb0, evec[:, :k], mats["A"], 0.5, 0.5, iters)
+        fb, V = fb.cpu().numpy(), V.cpu().numpy().T
+        assert np.abs(fb - ref_fb).max() <= 1e-6 * np.abs(ref_fb).max()
+        sgn = np.sign(np.sum(V * ref_V, axis=0))
+        assert np.abs(V * sgn - ref_V).max() <= 1e-5 * np.abs(ref_V).max()
+
+
+def test_saddle_stops_at_the_tolerance(ring_tb):
+    # with a tolerance that every norm meets, the run ends at the first
+    # check (iteration check_every)
+    tb, mats = ring_tb
+    f, g = _problem(tb.n, tb.p, 9)
+    _, _, _, _, info = tb.saddle(f, g, 1, 0.5, 0.5, 400, fbar0=1.0, V0=np.ones((1, tb.m)), precond="A",
+                                 energy="semilinear", tol=1e30, check_every=7)
+    assert info["iters"] == 7
+
+
+def test_saddle_invalid_options(ring_tb):
+    tb, _ = ring_tb
+    f, g = np.ones(tb.n), np.zeros(tb.p)
+    with pytest.raises(ValueError):
+        tb.saddle(f, g, 0, 1.0, 1.0, 5)
+    for kw in ({"k": 1, "eta": 0.0, "tau": 1.0, "max_iter": 5}, {"k": 1, "eta": 1.0, "tau": 0.0, "max_iter": 5},
+               {"k": 1, "eta": 1.0, "tau": 1.0, "max_iter": 0},
+               {"k": 1, "eta": 1.0, "tau": 1.0, "max_iter": 5, "energy": "plaplace", "p_exp": 2.0}):
+        with pytest.raises(P.WosError):
+            tb.saddle(f, g, **kw)
+    # dependent directions
+    with pytest.raises(P.WosError):
+        tb.saddle(f, g, 2, 1.0, 1.0, 5, V0=np.ones((2, tb.m)), precond="identity")
+
+
+def test_saddle_preconditioner_needs_square_toolbox():
+    dom = W.unit_disk()
+    tb = P.Toolbox(dom, W.sample_sites(dom, 30, 3, 1e-3), W.circle_nodes(20), 100, 1e-3, seed=3, precision="f64",
+                   volume_samples=1 << 14, vcentres=W.sample_sites(dom, 20, 4, 1e-3))
+    tb.build()
+    f, g = np.ones(30), np.zeros(20)
+    with pytest.raises(P.WosError):
+        tb.saddle(f, g, 1, 1.0, 1.0, 5, V0=np.ones((1, 20)), precond="A")
+    _, _, fb, V, info = tb.saddle(f, g, 1, 1.0, 1.0, 3, V0=np.ones((1, 20)), precond="identity")
+    assert info["iters"] == 3 and fb.numel() == 20
