@@ -96,6 +96,7 @@ def parse():
     ap.add_argument("--el-max-iter", type=int, default=20000)
     ap.add_argument("--el-rate-iters", type=int, default=100)
     ap.add_argument("--el-conv-iters", type=int, default=20000)
+    ap.add_argument("--hisd-max-iter", type=int, default=40000)
     ap.add_argument("--newton-rcond", type=float, default=1e-2)
     ap.add_argument("--serve-requests", type=int, default=2000, help="open-loop requests (mixed precision)")
     ap.add_argument("--serve-saturation", type=int, default=300, help="requests of the saturation run")
@@ -417,7 +418,8 @@ def el_energies(a, torch, W, P):
     disk (g = 0.3 sin 5 phi; no closed form: J is the graph's area over
     |D|) and its semilinear example with s = 800 on its 20 x 20 square
     layout, with its Adam parameters (fbar_0 = 1, alpha 0.01 and 1) to its
-    final gradient norm 1e-6.  (4) The semilinear iteration rate on the 4096-site L-shape
+    final gradient norm 1e-6, and that example's index-1 and index-2 saddle
+    points by p-HiSD with its parameters.  (4) The semilinear iteration rate on the 4096-site L-shape
     toolbox, which streams A and B twice each."""
     def grid(k):
         t = (np.arange(k) + 0.5) / k
@@ -465,6 +467,15 @@ def el_energies(a, torch, W, P):
     out["semilinear_s800_square_paper"] = {"alpha": 1.0, "fbar0": 1.0, "iters": info["iters"],
                                            "seconds": info["seconds"], "grad_norm": info["grad_norm"],
                                            "J": info["J"], "u_range": [float(u.min()), float(u.max())]}
+    # the same example's saddle points by p-HiSD with the paper's parameters
+    # (M = A, fbar_0 = 1000, eta = 20, tau = 10, directions from the Hessian)
+    for k in (1, 2):
+        u, _, _, _, info = tb.saddle(f, np.zeros(tb.p), k, 20.0, 10.0, a.hisd_max_iter, fbar0=1000.0, precond="A",
+                                     tol=1e-6, check_every=50)
+        out["semilinear_s800_phisd_k%d" % k] = {
+            "iters": info["iters"], "seconds": info["seconds"], "ms_per_iter": 1e3 * info["seconds"] / info["iters"],
+            "grad_norm": info["grad_norm"], "J": info["J"], "u_range": [float(u.min()), float(u.max())],
+            "newton_schulz_iters": info["ns_iters"], "newton_schulz_residual": info["ns_residual"]}
     tb.free()
     cfg = W.config("lshape4096")
     tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], 1000, cfg["eps"], seed=cfg["seed"], precision="f32")

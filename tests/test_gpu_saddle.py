@@ -140,3 +140,35 @@ def test_saddle_preconditioner_needs_square_toolbox():
         tb.saddle(f, g, 1, 1.0, 1.0, 5, V0=np.ones((1, 20)), precond="A")
     _, _, fb, V, info = tb.saddle(f, g, 1, 1.0, 1.0, 3, V0=np.ones((1, 20)), precond="identity")
     assert info["iters"] == 3 and fb.numel() == 20
+
+
+def test_saddle_paper_semilinear_s800_index1():
+    # The paper's example Lap u + u^2 = 800 sin(pi x) sin(pi y), u = 0 on
+    # the unit square, on its 20 x 20 layout (1e5 walks/site, FP64), with
+    # its p-HiSD parameters (M = A, fbar_0 = 1000, eta = 20, tau = 10,
+    # directions from the Hessian) and k = 1, run to its final gradient norm
+    # 1e-6.  The result is a critical point whose Hessian (the oracle's, on
+    # the exported toolbox) has exactly one negative eigenvalue, unlike the
+    # minimum Adam reaches.
+    sites, bn = W.paper_square_layout()
+    _say("GPU build paper square, 1e5 walks")
+    tb = P.Toolbox(W.unit_square(), sites, bn, 100000, 1e-4, seed=11, precision="f64", volume_samples=1 << 20)
+    tb.build()
+    torch.cuda.synchronize()
+    mats = {k: tb.export(k).cpu().numpy().astype(np.float64) for k in ("A", "B", "H", "K", "lambda")}
+    lam = mats["lambda"]
+    f = 800.0 * np.sin(np.pi * sites[:, 0]) * np.sin(np.pi * sites[:, 1])
+    g = np.zeros(tb.p)
+    _say("saddle s=800 k=1")
+    u, _, fb, _, info = tb.saddle(f, g, 1, 20.0, 10.0, 20000, fbar0=1000.0, precond="A", tol=1e-6, check_every=50)
+    _say("  %d iters, grad norm %.2e, J %.4g, %.2f s" % (info["iters"], info["grad_norm"], info["J"], info["seconds"]))
+    assert info["iters"] < 20000 and info["grad_norm"] <= 1e-6
+    fb = fb.cpu().numpy()
+    gr = E.energy_grad("semilinear", mats, lam, fb, g, 0.0, f)
+    assert E.grad_norm(lam, gr) == pytest.approx(info["grad_norm"], rel=1e-6)
+    Hf = E.semilinear_hessian(mats, lam, fb, g)
+    ev = np.linalg.eigvalsh(0.5 * (Hf + Hf.T))
+    assert np.sum(ev < 0) == 1
+    _, _, fmin, _ = tb.minimize(f, g, 0.0, 1.0, 30000, fbar0=1.0, energy="semilinear", tol=1e-6, check_every=50)
+    Hm = E.semilinear_hessian(mats, lam, fmin.cpu().numpy(), g)
+    assert np.sum(np.linalg.eigvalsh(0.5 * (Hm + Hm.T)) < 0) == 0
