@@ -358,7 +358,6 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     SHIP(hipStreamSynchronize(st));
     if (hinfo != 0) return sfail(WOS_ENOTCONV, "normal matrix not positive definite at column %d", hinfo - 1);
   }
-  SHIP(hipMemcpyAsync(&inf->reg, w.regv, sizeof(double), hipMemcpyDeviceToHost, st));
   return WOS_OK;
 }
 
@@ -412,7 +411,6 @@ wos_status sym_reg_solve(wos_toolbox* tb, SolveWork& w, bool mixed, double rcond
     SHIP(hipStreamSynchronize(st));
     if (hinfo != 0) return sfail(WOS_ENOTCONV, "matrix not positive definite at column %d", hinfo - 1);
   }
-  SHIP(hipMemcpyAsync(&inf->reg, w.regv, sizeof(double), hipMemcpyDeviceToHost, st));
   return WOS_OK;
 }
 
@@ -632,6 +630,10 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
   }
   if ((s = reconstruct(tb, q, g, u, grad_u, st)) != WOS_OK) return s;
   if (q_out) SHIP(hipMemcpyAsync(q_out, q, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+  // the regularisation parameter of the last Tikhonov solve, read at the
+  // final synchronisation (no copy into `inf` is left pending on a return)
+  if (co->solver == WOS_SOLVER_TIKHONOV && w.regv)
+    SHIP(hipMemcpyAsync(&inf.reg, w.regv, sizeof(double), hipMemcpyDeviceToHost, st));
   SHIP(hipStreamSynchronize(st));
   if (co->solver == WOS_SOLVER_TSVD) {
     inf.rank = tr.rank;
@@ -915,17 +917,22 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
       SHIP(hipMemcpyAsync(y, x, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
     return WOS_OK;
   };
+  // the Gram-Schmidt flag is sticky: cleared once, read (with a
+  // synchronisation) after the first pass, at the norm checks and at the end
   auto orthonormalise = [&](double* Vx) -> wos_status {
     for (int i = 0; i < k; ++i)
       if ((s = mult(Vx + (size_t)i * m, MV + (size_t)i * m)) != WOS_OK) return s;
-    SHIP(hipMemsetAsync(w.hs_bad, 0, sizeof(int), st));
     SHIP(launch_hisd_gs(m, k, Vx, MV, w.hs_bad, st));
+    return WOS_OK;
+  };
+  auto check_bad = [&]() -> wos_status {
     int bad = 0;
     SHIP(hipMemcpyAsync(&bad, w.hs_bad, sizeof(int), hipMemcpyDeviceToHost, st));
     SHIP(hipStreamSynchronize(st));
     if (bad) return sfail(WOS_EINVAL, "p-HiSD: the directions are not M-independent");
     return WOS_OK;
   };
+  SHIP(hipMemsetAsync(w.hs_bad, 0, sizeof(int), st));
   auto weighted_norm = [&](const double* x, double* out) -> wos_status {
     SHIP(launch_dot(m, x, x, tb->d_lambda_v, red, st));
     SHIP(hipMemcpyAsync(out, red, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -954,6 +961,7 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
     SHIP(hipMemcpyAsync(Vc, V, sizeof(double) * k * (size_t)m, hipMemcpyDeviceToDevice, st));
   }
   if ((s = orthonormalise(Vc)) != WOS_OK) return s;
+  if ((s = check_bad()) != WOS_OK) return s;
   double gn = 0.0;
   if ((s = eg.eval(fbar, gr)) != WOS_OK) return s;
   if ((s = weighted_norm(gr, &inf.grad_norm0)) != WOS_OK) return s;
@@ -976,6 +984,7 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
     it = j;
     if ((s = eg.eval(fbar, gr)) != WOS_OK) return s;  // at fbar_j: the next step and the checks
     if (o->tol > 0.0 && j % check == 0) {
+      if ((s = check_bad()) != WOS_OK) return s;
       if ((s = weighted_norm(gr, &gn)) != WOS_OK) return s;
       if (gn <= o->tol) break;
     }
@@ -983,6 +992,7 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   SHIP(hipStreamSynchronize(st));
   inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   inf.iters = it;
+  if ((s = check_bad()) != WOS_OK) return s;
   if ((s = weighted_norm(gr, &inf.grad_norm)) != WOS_OK) return s;
   SHIP(hipMemcpyAsync(V, Vc, sizeof(double) * k * (size_t)m, hipMemcpyDeviceToDevice, st));
   // u, grad u and J at the result
