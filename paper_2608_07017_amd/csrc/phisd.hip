@@ -52,7 +52,8 @@ __global__ __launch_bounds__(kHisdThreads) void hisd_fbar_kernel(int m, int k, c
   if (threadIdx.x == 0) h[0] = 1e-6 * fmax(1.0, sqrt(ss));
 }
 
-// X[(2i) m + j] = fbar_j + h v_ij, X[(2i + 1) m + j] = fbar_j - h v_ij.
+// X[(2i) m + j] = fbar_j + h v_ij, X[(2i + 1) m + j] = fbar_j - h v_ij,
+// and X[2k m + j] = fbar_j (the point itself, last).
 __global__ void hisd_shift_kernel(int m, int k, const double* __restrict__ fbar, const double* __restrict__ V,
                                   const double* __restrict__ h, double* __restrict__ X) {
   const double hh = h[0];
@@ -62,6 +63,7 @@ __global__ void hisd_shift_kernel(int m, int k, const double* __restrict__ fbar,
     const double v = V[t];
     X[2 * i * m + j] = fbar[j] + hh * v;
     X[(2 * i + 1) * m + j] = fbar[j] - hh * v;
+    if (i == 0) X[2 * (size_t)k * m + j] = fbar[j];
   }
 }
 
@@ -210,6 +212,13 @@ __global__ void identity_minus_kernel(int m, double* __restrict__ D) {
   }
 }
 
+// Y[t m + j] = c[j] for t < nv.
+__global__ void hisd_broadcast_kernel(int m, int nv, const double* __restrict__ c, double* __restrict__ Y) {
+  const size_t total = (size_t)nv * m;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x)
+    Y[t] = c[t % m];
+}
+
 unsigned grid_for(size_t n) {
   const size_t b = (n + 255) / 256;
   return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
@@ -262,6 +271,11 @@ hipError_t launch_transpose_to_f64(bool f64, const void* A, int m, double* X, hi
   else
     hipLaunchKernelGGL(transpose_to_f64_kernel<float>, dim3(grid_for((size_t)m * m)), dim3(256), 0, st,
                        (const float*)A, m, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_hisd_broadcast(int m, int nv, const double* c, double* Y, hipStream_t st) {
+  hipLaunchKernelGGL(hisd_broadcast_kernel, dim3(grid_for((size_t)nv * m)), dim3(256), 0, st, m, nv, c, Y);
   return hipGetLastError();
 }
 

@@ -226,12 +226,18 @@ __global__ void energy_weights_kernel(int kind, int n, int d, double P, const do
 // The weights inside the iteration: yB[a n + i] = lambda_i c(s) p_a with
 // p = gB + kg (gB = B fbar, kg = K g fixed over the iteration); with uA
 // (= A fbar) given, also yA[i] = lambda_i (f_i - u_i^2), u = uA + hg (hg =
-// H g), the u-dependent dF/du of the semilinear energy.
+// H g), the u-dependent dF/du of the semilinear energy.  Several points
+// at once: point blockIdx.y reads gB + y sg and uA + y su and writes
+// yB + y sy and yA + y sy.
 __global__ void energy_wb_kernel(int kind, int n, int d, double P, const double* __restrict__ lam,
                                  const double* __restrict__ gB, const double* __restrict__ kg,
                                  double* __restrict__ yB, const double* __restrict__ uA,
                                  const double* __restrict__ hg, const double* __restrict__ f,
-                                 double* __restrict__ yA) {
+                                 double* __restrict__ yA, size_t sg, size_t su, size_t sy) {
+  gB += blockIdx.y * sg;
+  yB += blockIdx.y * sy;
+  yA += blockIdx.y * sy;
+  if (uA) uA += blockIdx.y * su;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += stride) {
     double pa[3] = {0.0, 0.0, 0.0};
@@ -634,7 +640,18 @@ hipError_t launch_energy_wb(int kind, int n, int d, double P, const double* lam,
                             hipStream_t st) {
   if (d < 1 || d > 3) return hipErrorInvalidValue;
   hipLaunchKernelGGL(energy_wb_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, kind, n, d, P, lam, gB, kg, yB, uA,
-                     hg, f, yA);
+                     hg, f, yA, (size_t)0, (size_t)0, (size_t)0);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_wb_batch(int kind, int n, int d, double P, const double* lam, const double* GB,
+                                  const double* kg, double* YB, const double* UA, const double* hg, const double* f,
+                                  int nv, hipStream_t st) {
+  if (d < 1 || d > 3 || nv < 1 || nv > 65535) return hipErrorInvalidValue;
+  const size_t dn = (size_t)d * n;
+  // point t: gB = GB + t dn, uA = UA + t n, yB = YB + t (d + 1) n, yA = yB + d n
+  hipLaunchKernelGGL(energy_wb_kernel, dim3(blocks_for(n, 256), nv), dim3(256), 0, st, kind, n, d, P, lam, GB, kg, YB,
+                     UA, hg, f, YB + dn, dn, (size_t)n, dn + n);
   return hipGetLastError();
 }
 

@@ -517,7 +517,7 @@ namespace wos {
 void free_work(SolveWork& w) {
   void* ptrs[] = {w.R, w.Lam, w.Sig, w.Lam0, w.Sig0, w.Hess, w.G, w.V, w.E, w.rot, w.pq, w.vec, w.Ac, w.red,
                   w.blk, w.regv, w.info, w.R32, w.Lam32, w.N32, w.v32, w.P64, w.P32, w.L0_32, w.el, w.hs,
-                  w.hs_bad};
+                  w.hs_bad, w.hsb};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   w = SolveWork();
@@ -708,6 +708,34 @@ struct ElGrad {
     SHIP(hipMemcpyAsync(out, cvec, sizeof(double) * tb->m, hipMemcpyDeviceToDevice, st));
     return acc(x, out);
   }
+  // whether eval_batch reads the toolbox once for nv points (FP32 rows of
+  // 16 bytes, nv odd in 3..17); otherwise it evaluates one point at a time
+  bool batchable(int nv) const { return !tb->f64 && tb->m % 4 == 0 && nv >= 3 && nv <= 17 && (nv & 1); }
+  // out[t] = grad J(x[t]) for nv points stored one after another (m each);
+  // scratch holds nv (2d + 2) n doubles
+  wos_status eval_batch(const double* x, double* out, int nv, double* scratch) {
+    const int n = tb->n, m = tb->m, d = tb->dim;
+    if (!batchable(nv)) {
+      for (int t = 0; t < nv; ++t) {
+        wos_status s = eval(x + (size_t)t * m, out + (size_t)t * m);
+        if (s != WOS_OK) return s;
+      }
+      return WOS_OK;
+    }
+    const size_t dn = (size_t)d * n;
+    double* GB = scratch;                   // nv d n
+    double* UA = GB + (size_t)nv * dn;      // nv n
+    double* YB = UA + (size_t)nv * n;       // nv (d + 1) n
+    const float* Bf = static_cast<const float*>(tb->d_B);
+    const float* Af = static_cast<const float*>(tb->d_A);
+    SHIP(launch_gemv_n4_batch(Bf, d * n, m, m, x, m, nv, GB, (int)dn, st));
+    if (uterm) SHIP(launch_gemv_n4_batch(Af, n, m, m, x, m, nv, UA, n, st));
+    SHIP(launch_energy_wb_batch(kind, n, d, P, tb->d_lambda, GB, kgv, YB, uterm ? UA : nullptr, hg, f, nv, st));
+    SHIP(launch_hisd_broadcast(m, nv, cvec, out, st));
+    SHIP(launch_gemv_t4_batch(Bf, d * n, m, m, YB, (int)(dn + n), nv, out, m, st));
+    if (uterm) SHIP(launch_gemv_t4_batch(Af, n, m, m, YB + dn, (int)(dn + n), nv, out, m, st));
+    return WOS_OK;
+  }
 };
 
 wos_status check_energy(int kind, double p_exp) {
@@ -893,12 +921,14 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   double* MV = Vn + 8 * (size_t)m;   // 8 m: M V
   double* HV = MV + 8 * (size_t)m;   // 8 m
   double* Yv = HV + 8 * (size_t)m;   // 8 m: M^-1 H V
-  double* Xs = Yv + 8 * (size_t)m;   // 16 m: fbar +- h v_i
-  double* Gs = Xs + 16 * (size_t)m;  // 16 m: their gradients
-  double* gr = Gs + 16 * (size_t)m;  // m
-  double* wv = gr + m;               // m: M^-1 grad J
+  double* Xs = Yv + 8 * (size_t)m;   // 17 m: fbar +- h v_i, then fbar
+  double* Gs = Xs + 17 * (size_t)m;  // 17 m: their gradients
+  double* gr0 = Gs + 17 * (size_t)m; // m: the gradient at the start
+  double* wv = gr0 + m;              // m: M^-1 grad J
   double* hbuf = wv + m;             // 8: the difference step h (device)
   if ((size_t)(hbuf + 8 - w.hs) > hs_len) return sfail(WOS_EINVAL, "p-HiSD: work layout");
+  const int nv = 2 * k + 1;  // the points of one iteration's gradients
+  if (eg.batchable(nv) && !w.hsb && (s = walloc(w, &w.hsb, 17 * (size_t)(2 * d + 2) * n)) != WOS_OK) return s;
   wos_hisd_info inf{};
   if ((s = eg.setup(g)) != WOS_OK) return s;
   if (useA && (s = ns_inverse(tb, Minv, Y2, D, red, &inf.ns_iters, &inf.ns_residual, st)) != WOS_OK) return s;
@@ -963,7 +993,8 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   if ((s = orthonormalise(Vc)) != WOS_OK) return s;
   if ((s = check_bad()) != WOS_OK) return s;
   double gn = 0.0;
-  if ((s = eg.eval(fbar, gr)) != WOS_OK) return s;
+  const double* gr = gr0;  // grad J at the current fbar
+  if ((s = eg.eval(fbar, gr0)) != WOS_OK) return s;
   if ((s = weighted_norm(gr, &inf.grad_norm0)) != WOS_OK) return s;
   const auto t0 = std::chrono::steady_clock::now();
   int it = 0;
@@ -971,10 +1002,12 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
     // fbar_j = fbar_{j-1} - eta R M^-1 grad J(fbar_{j-1})  (gr holds the gradient)
     if ((s = minv(gr, wv)) != WOS_OK) return s;
     SHIP(launch_hisd_fbar(m, k, Vc, gr, wv, o->eta, fbar, hbuf, st));
-    // H(fbar_j) v_i by central differences
+    // the 2k + 1 gradients at fbar_j +- h v_i and fbar_j (one pass over the
+    // toolbox when batchable): H(fbar_j) v_i by central differences, and
+    // grad J(fbar_j) for the next step and the checks
     SHIP(launch_hisd_shift(m, k, fbar, Vc, hbuf, Xs, st));
-    for (int i = 0; i < 2 * k; ++i)
-      if ((s = eg.eval(Xs + (size_t)i * m, Gs + (size_t)i * m)) != WOS_OK) return s;
+    if ((s = eg.eval_batch(Xs, Gs, nv, w.hsb)) != WOS_OK) return s;
+    gr = Gs + 2 * (size_t)k * m;
     SHIP(launch_hisd_hv(m, k, Gs, hbuf, HV, st));
     for (int i = 0; i < k; ++i)
       if ((s = minv(HV + (size_t)i * m, Yv + (size_t)i * m)) != WOS_OK) return s;
@@ -982,7 +1015,6 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
     if ((s = orthonormalise(Vn)) != WOS_OK) return s;
     std::swap(Vc, Vn);
     it = j;
-    if ((s = eg.eval(fbar, gr)) != WOS_OK) return s;  // at fbar_j: the next step and the checks
     if (o->tol > 0.0 && j % check == 0) {
       if ((s = check_bad()) != WOS_OK) return s;
       if ((s = weighted_norm(gr, &gn)) != WOS_OK) return s;

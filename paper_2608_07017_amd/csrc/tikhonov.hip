@@ -208,6 +208,84 @@ __global__ __launch_bounds__(256) void gemv_n4_kernel(const float* __restrict__ 
   if (lane == 0) y[row] = alpha * acc + (beta == 0.0 ? 0.0 : beta * y[row]);
 }
 
+// The same two products for NV vectors at once (NV odd, 3..17: the 2k + 1
+// points of a saddle-search iteration), so that X is read once for all:
+// vector t is V + t vs, its result Y + t ys.
+// Y[t][i] = sum_j X[i][j] V[t][j]; one wavefront per row.
+template <int NV>
+__global__ __launch_bounds__(256) void gemv_n4b_kernel(const float* __restrict__ X, int rows, int cols, int ld,
+                                                       const double* __restrict__ V, int vs, double* __restrict__ Y,
+                                                       int ys) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const float* xr = X + (size_t)row * ld;
+  double acc[NV];
+#pragma unroll
+  for (int t = 0; t < NV; ++t) acc[t] = 0.0;
+  for (int j = 4 * lane; j < cols; j += 256) {
+    double xa[4];
+    load4(xr + j, xa);
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+      const double* vt = V + (size_t)t * vs + j;
+      acc[t] = fma(xa[3], vt[3], fma(xa[2], vt[2], fma(xa[1], vt[1], fma(xa[0], vt[0], acc[t]))));
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NV; ++t) {
+    double a = acc[t];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+    if (lane == 0) Y[(size_t)t * ys + row] = a;
+  }
+}
+
+// Y[t][j] += sum_i X[i][j] V[t][i]: the layout of gemv_t4_kernel, the four
+// wavefronts' sums added in LDS one vector at a time.
+template <int NV>
+__global__ __launch_bounds__(256) void gemv_t4b_kernel(const float* __restrict__ X, int rows, int cols, int ld,
+                                                       const double* __restrict__ V, int vs, double* __restrict__ Y,
+                                                       int ys, int rpb) {
+  __shared__ double part[3][64][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.x * 256 + 4 * lane;
+  const int r0 = blockIdx.y * rpb, r1 = min(rows, r0 + rpb);
+  double acc[NV][4];
+#pragma unroll
+  for (int t = 0; t < NV; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[t][q] = 0.0;
+  if (c < cols) {
+    for (int r = r0 + wave; r < r1; r += 4) {
+      double xa[4];
+      load4(X + (size_t)r * ld + c, xa);
+#pragma unroll
+      for (int t = 0; t < NV; ++t) {
+        const double vt = V[(size_t)t * vs + r];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[t][q] = fma(xa[q], vt, acc[t][q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NV; ++t) {
+    if (wave > 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) part[wave - 1][lane][q] = acc[t][q];
+    }
+    __syncthreads();
+    if (wave == 0 && c < cols) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double s = acc[t][q] + part[0][lane][q] + part[1][lane][q] + part[2][lane][q];
+        if (s != 0.0) atomicAdd(&Y[(size_t)t * ys + c + q], s);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 bool rows16(const void* X, int ld, int cols) {
   return ((uintptr_t)X % 16) == 0 && (ld % 4) == 0 && (cols % 4) == 0;
 }
@@ -374,6 +452,48 @@ hipError_t launch_gemv_n_ld(bool f64, const void* X, int rows, int cols, int ld,
                        ld, v, alpha, beta, y);
   return hipGetLastError();
 }
+
+#define WOS_NV_CASES(M_) M_(3) M_(5) M_(7) M_(9) M_(11) M_(13) M_(15) M_(17)
+
+hipError_t launch_gemv_n4_batch(const float* X, int rows, int cols, int ld, const double* V, int vs, int nv,
+                                double* Y, int ys, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  if (!rows16(X, ld, cols)) return hipErrorInvalidValue;
+  const dim3 g((rows + 3) / 4);
+  switch (nv) {
+#define WOS_CASE(N_)                                                                                           \
+  case N_:                                                                                                     \
+    hipLaunchKernelGGL(gemv_n4b_kernel<N_>, g, dim3(256), 0, st, X, rows, cols, ld, V, vs, Y, ys);             \
+    break;
+    WOS_NV_CASES(WOS_CASE)
+#undef WOS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_t4_batch(const float* X, int rows, int cols, int ld, const double* V, int vs, int nv,
+                                double* Y, int ys, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  if (!rows16(X, ld, cols)) return hipErrorInvalidValue;
+  const int cb = (cols + 255) / 256;
+  int rpb = 512;
+  while (rpb > 32 && (size_t)cb * ((rows + rpb - 1) / rpb) < 256) rpb /= 2;
+  const dim3 g(cb, (rows + rpb - 1) / rpb);
+  switch (nv) {
+#define WOS_CASE(N_)                                                                                           \
+  case N_:                                                                                                     \
+    hipLaunchKernelGGL(gemv_t4b_kernel<N_>, g, dim3(256), 0, st, X, rows, cols, ld, V, vs, Y, ys, rpb);        \
+    break;
+    WOS_NV_CASES(WOS_CASE)
+#undef WOS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+#undef WOS_NV_CASES
 
 hipError_t launch_reg_from_diag(bool f64, const void* N, int m, int ld, double coef, double* out, hipStream_t st) {
   if (f64)

@@ -62,6 +62,7 @@ struct SolveWork {
   double* el = nullptr;     // Euler-Lagrange route: (3d + 4) n + 4 m + 2 work doubles
   double* hs = nullptr;     // p-HiSD: 3 m^2 + 76 m + 8 work doubles
   int* hs_bad = nullptr;    // p-HiSD: Gram-Schmidt status (device)
+  double* hsb = nullptr;    // p-HiSD, batched gradients: 17 (2d + 2) n doubles
   size_t bytes = 0;         // device memory held
 };
 

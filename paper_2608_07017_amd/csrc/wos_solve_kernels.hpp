@@ -41,6 +41,17 @@ hipError_t launch_energy_weights(int kind, int n, int d, double P, const double*
 hipError_t launch_energy_wb(int kind, int n, int d, double P, const double* lam, const double* gB, const double* kg,
                             double* yB, const double* uA, const double* hg, const double* f, double* yA,
                             hipStream_t st);
+// the weights at nv points: point t reads GB + t d n (and UA + t n) and
+// writes YB + t (d + 1) n (the B weights, then the A weights)
+hipError_t launch_energy_wb_batch(int kind, int n, int d, double P, const double* lam, const double* GB,
+                                  const double* kg, double* YB, const double* UA, const double* hg, const double* f,
+                                  int nv, hipStream_t st);
+// FP32 X with 16-byte rows, nv odd in 3..17 (else hipErrorInvalidValue):
+// Y[t] = X V[t] and Y[t] += X^T V[t], X read once for all nv vectors
+hipError_t launch_gemv_n4_batch(const float* X, int rows, int cols, int ld, const double* V, int vs, int nv,
+                                double* Y, int ys, hipStream_t st);
+hipError_t launch_gemv_t4_batch(const float* X, int rows, int cols, int ld, const double* V, int vs, int nv,
+                                double* Y, int ys, hipStream_t st);
 hipError_t launch_adam(int m, double* g, double b1, double b2, double eps, double aj, double* mv, double* vv,
                        double* fbar, const double* reset, hipStream_t st);
 hipError_t launch_picard_coef(int n, int d, const double* u, double* Ac, hipStream_t st);
@@ -111,6 +122,8 @@ hipError_t launch_hisd_select(int Mp, int m, int k, const double* e, const doubl
                               hipStream_t st);
 hipError_t launch_transpose_to_f64(bool f64, const void* A, int m, double* X, hipStream_t st);
 hipError_t launch_identity_minus(int m, double* D, hipStream_t st);
+// Y[t] = c for t < nv (m-vectors, stride m)
+hipError_t launch_hisd_broadcast(int m, int nv, const double* c, double* Y, hipStream_t st);
 hipError_t launch_add_f32(int n, const float* dlt, double* q, hipStream_t st);
 
 }  // namespace wos

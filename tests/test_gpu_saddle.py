@@ -172,3 +172,30 @@ def test_saddle_paper_semilinear_s800_index1():
     _, _, fmin, _ = tb.minimize(f, g, 0.0, 1.0, 30000, fbar0=1.0, energy="semilinear", tol=1e-6, check_every=50)
     Hm = E.semilinear_hessian(mats, lam, fmin.cpu().numpy(), g)
     assert np.sum(np.linalg.eigvalsh(0.5 * (Hm + Hm.T)) < 0) == 0
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_saddle_fp32_toolbox_batched_gradients_match_oracle(k):
+    # An FP32 toolbox with m % 4 == 0 (4 rings, 48 sites) takes the batched
+    # gradients: the 2k + 1 points of an iteration in one pass over A and B.
+    # The exported FP32 entries are exact in FP64, so the oracle runs on the
+    # same matrices.
+    _say("GPU build disk rings 4, FP32; saddle k=%d" % k)
+    tb = P.Toolbox(W.unit_disk(), _rings(4), W.circle_nodes(24), 1500, 1e-3, seed=12, precision="f32",
+                   volume_samples=1 << 18)
+    tb.build()
+    torch.cuda.synchronize()
+    mats = {key: tb.export(key).cpu().numpy().astype(np.float64) for key in ("A", "B", "H", "K", "lambda")}
+    lam = mats["lambda"]
+    assert tb.m % 4 == 0
+    f, g = _problem(tb.n, tb.p, 15)
+    rng = np.random.default_rng(16)
+    V0 = rng.normal(size=(k, tb.m))
+    fb0 = 1.0 + 0.1 * rng.normal(size=tb.m)
+    u, _, fb, V, info = tb.saddle(f, g, k, 0.5, 0.5, 10, fbar0=fb0, V0=V0, precond="A")
+    gr = lambda x: E.energy_grad("semilinear", mats, lam, x, g, 0.0, f)
+    ref_fb, ref_V, _ = E.phisd(gr, fb0, V0.T, mats["A"], 0.5, 0.5, 10)
+    fb, V = fb.cpu().numpy(), V.cpu().numpy()
+    assert np.abs(fb - ref_fb).max() <= 1e-7 * np.abs(ref_fb).max()
+    assert np.abs(V.T - ref_V).max() <= 1e-6 * np.abs(ref_V).max()
+    assert info["grad_norm"] == pytest.approx(E.grad_norm(lam, gr(ref_fb)), rel=1e-5)
