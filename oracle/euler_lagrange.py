@@ -20,7 +20,10 @@ p-Laplace one of Sec. "Solving nonlinear elliptic PDEs" (eq. plaplace),
 F = |p|^P / P - f u, so dF/du = -f and dF/dp = |p|^(P-2) p (taken as 0 at
 p = 0, its limit for P > 1); the minimal surface one, F = sqrt(1 + |p|^2)
 - f u (f = 0 in the paper); and the semilinear one of the Breuer-McKenna-
-Plum example, F = |p|^2 / 2 - u^3 / 3 + f u (Lap u + u^2 = f).
+Plum example, F = |p|^2 / 2 - u^3 / 3 + f u (Lap u + u^2 = f); and the
+weighted quadratic one of the example "elliptic div min", F = w (p.A p / 2
++ c u^2 / 2 - f u) with w = exp(-phi), whose Euler-Lagrange equation is
+-div(A grad u) + (A grad phi).grad u + c u = f.
 
 The minimiser is Adam as restated in the appendix on the optimisation of
 J: m_j = beta1 m_{j-1} + (1 - beta1) grad, v_j = beta2 v_{j-1} +
@@ -60,10 +63,10 @@ import numpy as np
 from .linalg import reconstruct
 
 
-ENERGIES = ("plaplace", "minimal_surface", "semilinear")
+ENERGIES = ("plaplace", "minimal_surface", "semilinear", "elliptic")
 
 
-def energy_parts(energy, tb, fbar, g, P, f):
+def energy_parts(energy, tb, fbar, g, P, f, coef=None):
     """u, grad u (d, n), the energy density F_i and the weights
     (dF/du, dF/dp) at the sites for the energies of the paper's examples:
     "plaplace"         F = |p|^P / P - f u                (eq. plaplace)
@@ -71,7 +74,11 @@ def energy_parts(energy, tb, fbar, g, P, f):
                                                            surface", f = 0)
     "semilinear"       F = |p|^2 / 2 - u^3 / 3 + f u      (Example
                                                            "semilinear": Lap u + u^2 = f)
-    (P is used by "plaplace" only)."""
+    "elliptic"         F = w (p.A p / 2 + c u^2 / 2 - f u) (Example
+                       "elliptic div min", w = exp(-phi): -div(A grad u)
+                       + (A grad phi).grad u + c u = f)
+    (P is used by "plaplace" only; coef = {"A": (n, d, d), "c": (n,),
+    "w": (n,)} by "elliptic", each optional: identity, 0, 1)."""
     u, gu = reconstruct(tb, fbar, g)
     s = np.sum(gu * gu, axis=0)  # |p_i|^2
     if energy == "plaplace":
@@ -83,6 +90,16 @@ def energy_parts(energy, tb, fbar, g, P, f):
         return u, gu, q - f * u, -f, gu / q
     if energy == "semilinear":
         return u, gu, 0.5 * s - u ** 3 / 3.0 + f * u, f - u * u, gu
+    if energy == "elliptic":
+        coef = coef or {}
+        n, d = u.shape[0], gu.shape[0]
+        w = np.asarray(coef["w"], dtype=np.float64) if coef.get("w") is not None else np.ones(n)
+        c = np.asarray(coef["c"], dtype=np.float64) if coef.get("c") is not None else np.zeros(n)
+        Ac = (np.asarray(coef["A"], dtype=np.float64) if coef.get("A") is not None
+              else np.broadcast_to(np.eye(d), (n, d, d)))
+        Ap = np.einsum("nab,bn->an", Ac, gu)  # A_i p_i
+        F = w * (0.5 * np.sum(gu * Ap, axis=0) + 0.5 * c * u * u - f * u)
+        return u, gu, F, w * (c * u - f), w * Ap
     raise ValueError("unknown energy %r" % energy)
 
 
@@ -91,15 +108,15 @@ def plaplace_energy_parts(tb, fbar, g, P, f):
     return energy_parts("plaplace", tb, fbar, g, P, f)
 
 
-def energy_J(energy, tb, lam, fbar, g, P, f):
+def energy_J(energy, tb, lam, fbar, g, P, f, coef=None):
     """J(fbar) = sum_i lambda_i F_i   (eq. gradJ)."""
-    _, _, F, _, _ = energy_parts(energy, tb, fbar, g, P, f)
+    _, _, F, _, _ = energy_parts(energy, tb, fbar, g, P, f, coef)
     return float(np.sum(lam * F))
 
 
-def energy_grad(energy, tb, lam, fbar, g, P, f):
+def energy_grad(energy, tb, lam, fbar, g, P, f, coef=None):
     """grad J = A^T (lambda o dF/du) + sum_a B^(a)^T (lambda o dF/dp_a)."""
-    _, _, _, dFu, dFp = energy_parts(energy, tb, fbar, g, P, f)
+    _, _, _, dFu, dFp = energy_parts(energy, tb, fbar, g, P, f, coef)
     grad = tb["A"].T @ (lam * dFu)
     for a in range(tb["B"].shape[0]):
         grad = grad + tb["B"][a].T @ (lam * dFp[a])
@@ -146,16 +163,17 @@ def adam(grad_fn, f0, alpha, max_iter, beta1=0.9, beta2=0.999, eps=1e-10, tol=0.
     return f, j
 
 
-def minimize_energy(energy, tb, lam, f, g, P, alpha, max_iter, f0=1.0, tol=0.0, check_every=1, lam_v=None):
+def minimize_energy(energy, tb, lam, f, g, P, alpha, max_iter, f0=1.0, tol=0.0, check_every=1, lam_v=None,
+                    coef=None):
     """Adam on J for any of the energies, from a constant fbar_0 = f0; the
     stopping norm uses lam_v (the V cells' measures; lam when None)."""
     m = tb["A"].shape[1]
     lv = lam if lam_v is None else lam_v
-    fb, it = adam(lambda x: energy_grad(energy, tb, lam, x, g, P, f), np.full(m, float(f0)), alpha, max_iter,
+    fb, it = adam(lambda x: energy_grad(energy, tb, lam, x, g, P, f, coef), np.full(m, float(f0)), alpha, max_iter,
                   tol=tol, norm_fn=lambda gr: grad_norm(lv, gr), check_every=check_every)
     u, gu = reconstruct(tb, fb, g)
-    return {"fbar": fb, "u": u, "grad_u": gu, "iters": it, "J": energy_J(energy, tb, lam, fb, g, P, f),
-            "grad_norm": grad_norm(lv, energy_grad(energy, tb, lam, fb, g, P, f))}
+    return {"fbar": fb, "u": u, "grad_u": gu, "iters": it, "J": energy_J(energy, tb, lam, fb, g, P, f, coef),
+            "grad_norm": grad_norm(lv, energy_grad(energy, tb, lam, fb, g, P, f, coef))}
 
 
 def minimize_plaplace(tb, lam, f, g, P, alpha, max_iter, f0=1.0, tol=0.0, check_every=1):

@@ -266,3 +266,61 @@ def test_semilinear_hessian_matches_differences_of_the_gradient():
                     - E.energy_grad("semilinear", tb, lam, fb - h * e, g, 0, f)) / (2 * h) for e in np.eye(9)], 1)
     assert np.allclose(H, fd, rtol=1e-7, atol=1e-8 * np.abs(H).max())
     assert np.allclose(H, H.T, atol=1e-12 * np.abs(H).max())
+
+
+def _elliptic_coef(n, d, seed):
+    rng = np.random.default_rng(seed)
+    G = rng.normal(size=(n, d, d))
+    return {"A": np.einsum("nab,ncb->nac", G, G) + np.eye(d), "c": rng.random(n), "w": 0.5 + rng.random(n)}
+
+
+def test_elliptic_gradient_matches_central_differences():
+    tb = _random_tb(9, 4, 2, 41)
+    rng = np.random.default_rng(42)
+    lam, f, g, fb = rng.random(9), rng.normal(size=9), rng.normal(size=4), rng.normal(size=9)
+    co = _elliptic_coef(9, 2, 43)
+    gr = E.energy_grad("elliptic", tb, lam, fb, g, 0.0, f, co)
+    h = 1e-6
+    fd = np.array([(E.energy_J("elliptic", tb, lam, fb + h * e, g, 0.0, f, co)
+                    - E.energy_J("elliptic", tb, lam, fb - h * e, g, 0.0, f, co)) / (2 * h) for e in np.eye(9)])
+    assert np.allclose(gr, fd, rtol=1e-6, atol=1e-7 * np.abs(fd).max())
+
+
+def test_elliptic_gradient_is_the_linear_system_with_weighted_coefficients():
+    # the energy is quadratic: grad J = Lambda fbar + Sigma g - A^T (lam w f)
+    # with the linear route's Lambda, Sigma for the coefficients (w A, b = 0,
+    # w c) (eq. linear_q, assembled by the oracle's linear algebra)
+    tb = _random_tb(10, 4, 2, 44)
+    rng = np.random.default_rng(45)
+    lam, f, g, fb = rng.random(10), rng.normal(size=10), rng.normal(size=4), rng.normal(size=10)
+    co = _elliptic_coef(10, 2, 46)
+    Lm, Sg = L.assemble(tb, lam, co["w"][:, None, None] * co["A"], None, co["w"] * co["c"])
+    ref = Lm @ fb + Sg @ g - tb["A"].T @ (lam * co["w"] * f)
+    assert np.allclose(E.energy_grad("elliptic", tb, lam, fb, g, 0.0, f, co), ref, rtol=1e-12, atol=1e-12)
+    # and with no coefficients it is the Dirichlet energy with source: the
+    # P = 2 p-Laplace gradient
+    assert np.allclose(E.energy_grad("elliptic", tb, lam, fb, g, 0.0, f),
+                       E.energy_grad("plaplace", tb, lam, fb, g, 2.0, f), rtol=1e-12, atol=1e-12)
+
+
+def test_elliptic_example_solution_satisfies_its_equation():
+    # the manufactured data of the example: f = -div(A grad u) + (A grad phi).grad u
+    # + c u checked by central differences of the flux A grad u
+    x = np.array([[0.3, -0.2], [-0.5, 0.4], [0.1, 0.7]])
+    u, gu, f = W.elliptic_divmin_disk(x)
+    h = 1e-4
+
+    def flux(y):
+        _, gy, _ = W.elliptic_divmin_disk(y)
+        Ay = np.stack([[np.ones(len(y)), y[:, 0] * y[:, 1]], [y[:, 0] * y[:, 1], np.ones(len(y))]]).transpose(2, 0, 1)
+        return np.einsum("nab,nb->na", Ay, gy)
+
+    div = sum((flux(x + h * e)[:, a] - flux(x - h * e)[:, a]) / (2 * h) for a, e in enumerate(np.eye(2)))
+    Agphi = np.stack([x[:, 0] + x[:, 0] * x[:, 1] ** 2, x[:, 0] ** 2 * x[:, 1] + x[:, 1]], 1)
+    assert np.allclose(-div + np.sum(Agphi * gu, 1) + u, f, rtol=1e-6, atol=1e-7)
+    # u vanishes on the circle; gradient by differences
+    th = np.linspace(0, 2 * np.pi, 7)
+    assert np.allclose(W.elliptic_divmin_disk(np.stack([np.cos(th), np.sin(th)], 1))[0], 0.0, atol=1e-15)
+    gfd = np.stack([(W.elliptic_divmin_disk(x + h * e)[0] - W.elliptic_divmin_disk(x - h * e)[0]) / (2 * h)
+                    for e in np.eye(2)], 1)
+    assert np.allclose(gu, gfd, rtol=1e-7, atol=2e-7)  # O(h^2) truncation of the differences

@@ -195,6 +195,39 @@ def plaplace_torsion_disk_exact(x, P):
     return (P - 1.0) / P * 0.5 ** (1.0 / (P - 1.0)) * (1.0 - np.power(r2, P / (2.0 * P - 2.0)))
 
 
+def elliptic_divmin_disk(x):
+    """The example "elliptic div min" on the unit disk: A = [[1, xy], [xy, 1]],
+    phi = (x^2 + y^2) / 2, c = 1, u = (1 - x^2 - y^2)(x^3 - 3 x y^2) (0 on
+    the circle).  Returns u, grad u (n, 2) and f = -div(A grad u) +
+    (A grad phi).grad u + c u, by hand-differentiated closed forms.  Problem
+    data, like the manufactured solutions here."""
+    x = np.asarray(x, dtype=np.float64)
+    X, Y = x[:, 0], x[:, 1]
+    s = 1.0 - X * X - Y * Y
+    h = X ** 3 - 3 * X * Y * Y
+    hx, hy = 3 * X * X - 3 * Y * Y, -6 * X * Y
+    hxx, hxy, hyy = 6 * X, -6 * Y, -6 * X
+    sx, sy = -2 * X, -2 * Y
+    u = s * h
+    ux, uy = s * hx + h * sx, s * hy + h * sy
+    uxx = -2 * h + 2 * sx * hx + s * hxx
+    uyy = -2 * h + 2 * sy * hy + s * hyy
+    uxy = sx * hy + sy * hx + s * hxy
+    div = uxx + uyy + 2 * X * Y * uxy + X * ux + Y * uy  # div(A grad u)
+    agx, agy = X + X * Y * Y, X * X * Y + Y            # A grad phi
+    f = -div + agx * ux + agy * uy + u
+    return u, np.stack([ux, uy], 1), f
+
+
+def elliptic_divmin_coef(x):
+    """The example's coefficient fields at the sites: A (n, 2, 2), c (n,)
+    and the weight w = exp(-phi) (n,)."""
+    x = np.asarray(x, dtype=np.float64)
+    xy = x[:, 0] * x[:, 1]
+    A = np.stack([np.stack([np.ones_like(xy), xy], -1), np.stack([xy, np.ones_like(xy)], -1)], -2)
+    return A, np.ones(len(x)), np.exp(-0.5 * np.sum(x * x, axis=1))
+
+
 def paper_square_layout():
     """20 x 20 cell centres of the unit square, 20 boundary nodes per edge."""
     g = (np.arange(20) + 0.5) / 20.0
