@@ -419,7 +419,8 @@ def el_energies(a, torch, W, P):
     |D|) and its semilinear example with s = 800 on its 20 x 20 square
     layout, with its Adam parameters (fbar_0 = 1, alpha 0.01 and 1) to its
     final gradient norm 1e-6, and that example's index-1 and index-2 saddle
-    points by p-HiSD with its parameters.  (4) The semilinear iteration rate on the 4096-site L-shape
+    points by p-HiSD with its parameters; and its example "elliptic div
+    min" on the disk layout against the closed form.  (4) The semilinear iteration rate on the 4096-site L-shape
     toolbox, which streams A and B twice each."""
     def grid(k):
         t = (np.arange(k) + 0.5) / k
@@ -457,6 +458,38 @@ def el_energies(a, torch, W, P):
     out["minimal_surface_disk_paper"] = {"alpha": 0.01, "fbar0": 1.0, "iters": info["iters"],
                                          "seconds": info["seconds"], "grad_norm": info["grad_norm"],
                                          "J_area_over_D": info["J"], "u_range": [float(u.min()), float(u.max())]}
+    tb.free()
+    # the example "elliptic div min" on the disk layout, with its Adam
+    # parameters (fbar_0 = 0.1, alpha = 0.01) to its final norm 1e-4
+    sites, bnd = W.paper_disk_layout()
+    tb = P.Toolbox(W.unit_disk(), sites, bnd, a.el_walks, 1e-4, seed=11, precision="f32", volume_samples=1 << 20)
+    tb.build()
+    lam = tb.export("lambda").cpu().numpy()
+    ue, _, fe = W.elliptic_divmin_disk(sites)
+    cA, cc, cw = W.elliptic_divmin_coef(sites)
+    u, _, _, info = tb.minimize(fe, np.zeros(tb.p), 0.0, 0.01, a.el_max_iter, fbar0=0.1, energy="elliptic",
+                                coef_A=cA, coef_c=cc, coef_w=cw, tol=1e-4 / np.sqrt(np.pi), check_every=50)
+    out["elliptic_divmin_disk_paper"] = {
+        "alpha": 0.01, "fbar0": 0.1, "iters": info["iters"], "seconds": info["seconds"],
+        "grad_norm": info["grad_norm"],
+        "rel_l2_error": float(np.sqrt(np.sum(lam * (u.cpu().numpy() - ue) ** 2) / np.sum(lam * ue ** 2)))}
+    tb.free()
+    # the same with a finer W partition (1200 ring sites) for the paper's 300
+    # V cells, run to el_conv_iters iterations (near the minimiser of J)
+    wfine = np.concatenate([np.stack([(k - 0.5) / 20 * np.cos(2 * np.pi * np.arange(6 * k - 3) / (6 * k - 3)),
+                                      (k - 0.5) / 20 * np.sin(2 * np.pi * np.arange(6 * k - 3) / (6 * k - 3))], 1)
+                            for k in range(1, 21)])
+    tb = P.Toolbox(W.unit_disk(), wfine, bnd, a.el_walks, 1e-4, seed=11, precision="f32", volume_samples=1 << 20,
+                   vcentres=sites)
+    tb.build()
+    lam = tb.export("lambda").cpu().numpy()
+    ue, _, fe = W.elliptic_divmin_disk(wfine)
+    cA, cc, cw = W.elliptic_divmin_coef(wfine)
+    u, _, _, info = tb.minimize(fe, np.zeros(tb.p), 0.0, 0.01, a.el_conv_iters, fbar0=0.1, energy="elliptic",
+                                coef_A=cA, coef_c=cc, coef_w=cw)
+    out["elliptic_divmin_disk_W1200_V300"] = {
+        "iters": info["iters"], "seconds": info["seconds"], "grad_norm": info["grad_norm"],
+        "rel_l2_error": float(np.sqrt(np.sum(lam * (u.cpu().numpy() - ue) ** 2) / np.sum(lam * ue ** 2)))}
     tb.free()
     sites, bnd = W.paper_square_layout()
     tb = P.Toolbox(W.unit_square(), sites, bnd, a.el_walks, 1e-4, seed=11, precision="f32", volume_samples=1 << 20)

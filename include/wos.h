@@ -331,8 +331,19 @@ wos_status wos_interpolate(const wos_toolbox* tb, const double* u, const double*
  *                           as B (twice each), and J is unbounded below:
  *                           Adam finds a local minimiser, if any, near the
  *                           start.
+ *   WOS_EL_ELLIPTIC         F = w (p.A p / 2 + c u^2 / 2 - f u) (the example
+ *                           "elliptic div min", w = exp(-phi)): the weak
+ *                           form of -div(A grad u) + (A grad phi).grad u
+ *                           + c u = f, u = g, with per-site coefficient
+ *                           fields w, A, c (wos_adam_opts); an iteration
+ *                           streams A and B.
  * p_exp is read for WOS_EL_PLAPLACE only.                                  */
-typedef enum { WOS_EL_PLAPLACE = 0, WOS_EL_MINIMAL_SURFACE = 1, WOS_EL_SEMILINEAR = 2 } wos_energy;
+typedef enum {
+  WOS_EL_PLAPLACE = 0,
+  WOS_EL_MINIMAL_SURFACE = 1,
+  WOS_EL_SEMILINEAR = 2,
+  WOS_EL_ELLIPTIC = 3
+} wos_energy;
 
 typedef struct {
   int32_t energy;       /* wos_energy                                         */
@@ -345,6 +356,10 @@ typedef struct {
   double tol;           /* stop once |grad J|_lambda <= tol; 0: run max_iter   */
   int32_t check_every;  /* with tol > 0, the norm is evaluated after every
                            check_every-th iteration; 0 -> 50                  */
+  /* WOS_EL_ELLIPTIC: device, per site, each NULL for its default         */
+  const double* coef_A; /* n x d x d, row-major (NULL: the identity)          */
+  const double* coef_c; /* n (NULL: 0)                                        */
+  const double* coef_w; /* n (NULL: 1)                                        */
 } wos_adam_opts;
 
 typedef struct {
@@ -366,8 +381,8 @@ typedef struct {
  * the site weights and the Adam update); the host reads one scalar per
  * norm check.  Where dF/du = -f does not depend on u (p-Laplace, minimal
  * surface), A^T (lambda o f) and K g are formed once and an iteration
- * streams only B (forward and transposed); for the semilinear energy it
- * streams A too, with H g formed once.  u and J are formed at the end.
+ * streams only B (forward and transposed); for the semilinear and elliptic
+ * energies it streams A too, with H g formed once.  u and J are formed at the end.
  * Runs on `stream` and synchronises it before returning.
  * Errors: WOS_EINVAL for a NULL pointer, an unbuilt toolbox, an unknown
  * energy, P <= 1 (WOS_EL_PLAPLACE), alpha <= 0, beta outside [0, 1), eps < 0 or

@@ -77,7 +77,8 @@ class WosSolveInfo(ctypes.Structure):
 class WosAdamOpts(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_int32), ("p_exp", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("check_every", ctypes.c_int32)]
+                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("check_every", ctypes.c_int32),
+                ("coef_A", ctypes.c_void_p), ("coef_c", ctypes.c_void_p), ("coef_w", ctypes.c_void_p)]
 
 
 class WosAdamInfo(ctypes.Structure):
@@ -98,7 +99,7 @@ class WosHisdInfo(ctypes.Structure):
                 ("ns_residual", ctypes.c_double)]
 
 
-ENERGIES = {"plaplace": 0, "minimal_surface": 1, "semilinear": 2}
+ENERGIES = {"plaplace": 0, "minimal_surface": 1, "semilinear": 2, "elliptic": 3}
 HISD_PRECOND = {"identity": 0, "A": 1}
 HISD_INIT = {"given": 0, "hessian": 1}
 PROBLEMS = {"linear": 0, "semilinear_cubic": 1, "quasilinear": 2}

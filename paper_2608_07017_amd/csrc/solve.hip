@@ -185,7 +185,11 @@ __global__ void pointwise_kernel(int n, const double* __restrict__ lam, const do
 //   kind 1, minimal surface            F = sqrt(1 + s) - f u,
 //           dF/dp = p / sqrt(1 + s), dF/du = -f;
 //   kind 2, semilinear (Lap u + u^2 = f) F = s / 2 - u^3 / 3 + f u,
-//           dF/dp = p, dF/du = f - u^2.
+//           dF/dp = p, dF/du = f - u^2;
+//   kind 3, weighted quadratic ("elliptic div min")
+//           F = w (p.A p / 2 + c u^2 / 2 - f u), dF/dp = w A p,
+//           dF/du = w (c u - f), with per-site w, A (d x d, row-major) and
+//           c, each optional (1, I, 0).
 // dF/dp weight factor c(s) with dF/dp = c p:
 __device__ inline double energy_cp(int kind, double P, double s) {
   if (kind == 1) return 1.0 / sqrt(1.0 + s);
@@ -197,12 +201,36 @@ __device__ inline double energy_cp(int kind, double P, double s) {
 //   y[a n + i] = lambda_i c(s) p_a   (a < d),
 //   y[d n + i] = lambda_i dF/du,
 //   F[i]       = F(u_i, p_i).
+// w A p for kind 3 at site i (pa: d components)
+__device__ inline void weighted_Ap(int d, size_t i, const double* pa, const double* cA, double wi, double* q) {
+  for (int a = 0; a < d; ++a) {
+    double t = 0.0;
+    for (int b = 0; b < d; ++b) t += (cA ? cA[(i * d + a) * d + b] : (a == b ? 1.0 : 0.0)) * pa[b];
+    q[a] = wi * t;
+  }
+}
+
 __global__ void energy_weights_kernel(int kind, int n, int d, double P, const double* __restrict__ lam,
                                       const double* __restrict__ u, const double* __restrict__ gu,
                                       const double* __restrict__ f, double* __restrict__ y,
-                                      double* __restrict__ F) {
+                                      double* __restrict__ F, const double* __restrict__ cA,
+                                      const double* __restrict__ cc, const double* __restrict__ cw) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += stride) {
+    if (kind == 3) {
+      double pa[3] = {0.0, 0.0, 0.0}, q[3];
+      for (int a = 0; a < d; ++a) pa[a] = gu[(size_t)a * n + i];
+      const double wi = cw ? cw[i] : 1.0, ci = cc ? cc[i] : 0.0, li = lam[i], ui = u[i], fi = f[i];
+      weighted_Ap(d, i, pa, cA, wi, q);
+      double pq = 0.0;
+      for (int a = 0; a < d; ++a) {
+        y[(size_t)a * n + i] = li * q[a];
+        pq += pa[a] * q[a];
+      }
+      y[(size_t)d * n + i] = li * wi * (ci * ui - fi);
+      F[i] = 0.5 * pq + wi * (0.5 * ci * ui * ui - fi * ui);
+      continue;
+    }
     double s = 0.0;
     for (int a = 0; a < d; ++a) s += gu[(size_t)a * n + i] * gu[(size_t)a * n + i];
     const double c = energy_cp(kind, P, s);
@@ -233,7 +261,9 @@ __global__ void energy_wb_kernel(int kind, int n, int d, double P, const double*
                                  const double* __restrict__ gB, const double* __restrict__ kg,
                                  double* __restrict__ yB, const double* __restrict__ uA,
                                  const double* __restrict__ hg, const double* __restrict__ f,
-                                 double* __restrict__ yA, size_t sg, size_t su, size_t sy) {
+                                 double* __restrict__ yA, size_t sg, size_t su, size_t sy,
+                                 const double* __restrict__ cA, const double* __restrict__ cc,
+                                 const double* __restrict__ cw) {
   gB += blockIdx.y * sg;
   yB += blockIdx.y * sy;
   yA += blockIdx.y * sy;
@@ -247,6 +277,17 @@ __global__ void energy_wb_kernel(int kind, int n, int d, double P, const double*
       s += pa[a] * pa[a];
     }
     const double li = lam[i];
+    if (kind == 3) {
+      const double wi = cw ? cw[i] : 1.0;
+      double q[3];
+      weighted_Ap(d, i, pa, cA, wi, q);
+      for (int a = 0; a < d; ++a) yB[(size_t)a * n + i] = li * q[a];
+      if (uA) {
+        const double ui = uA[i] + (hg ? hg[i] : 0.0);
+        yA[i] = li * wi * ((cc ? cc[i] : 0.0) * ui - f[i]);
+      }
+      continue;
+    }
     const double c = li * energy_cp(kind, P, s);
     for (int a = 0; a < d; ++a) yB[(size_t)a * n + i] = c * pa[a];
     if (uA) {
@@ -628,30 +669,31 @@ hipError_t launch_pointwise(int n, const double* lam, const double* u, const dou
 }
 
 hipError_t launch_energy_weights(int kind, int n, int d, double P, const double* lam, const double* u,
-                                 const double* gu, const double* f, double* y, double* F, hipStream_t st) {
+                                 const double* gu, const double* f, double* y, double* F, const EnergyCoef& co,
+                                 hipStream_t st) {
   if (d < 1 || d > 3) return hipErrorInvalidValue;
   hipLaunchKernelGGL(energy_weights_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, kind, n, d, P, lam, u, gu, f,
-                     y, F);
+                     y, F, co.A, co.c, co.w);
   return hipGetLastError();
 }
 
 hipError_t launch_energy_wb(int kind, int n, int d, double P, const double* lam, const double* gB, const double* kg,
                             double* yB, const double* uA, const double* hg, const double* f, double* yA,
-                            hipStream_t st) {
+                            const EnergyCoef& co, hipStream_t st) {
   if (d < 1 || d > 3) return hipErrorInvalidValue;
   hipLaunchKernelGGL(energy_wb_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, kind, n, d, P, lam, gB, kg, yB, uA,
-                     hg, f, yA, (size_t)0, (size_t)0, (size_t)0);
+                     hg, f, yA, (size_t)0, (size_t)0, (size_t)0, co.A, co.c, co.w);
   return hipGetLastError();
 }
 
 hipError_t launch_energy_wb_batch(int kind, int n, int d, double P, const double* lam, const double* GB,
                                   const double* kg, double* YB, const double* UA, const double* hg, const double* f,
-                                  int nv, hipStream_t st) {
+                                  int nv, const EnergyCoef& co, hipStream_t st) {
   if (d < 1 || d > 3 || nv < 1 || nv > 65535) return hipErrorInvalidValue;
   const size_t dn = (size_t)d * n;
   // point t: gB = GB + t dn, uA = UA + t n, yB = YB + t (d + 1) n, yA = yB + d n
   hipLaunchKernelGGL(energy_wb_kernel, dim3(blocks_for(n, 256), nv), dim3(256), 0, st, kind, n, d, P, lam, GB, kg, YB,
-                     UA, hg, f, YB + dn, dn, (size_t)n, dn + n);
+                     UA, hg, f, YB + dn, dn, (size_t)n, dn + n, co.A, co.c, co.w);
   return hipGetLastError();
 }
 

@@ -656,6 +656,7 @@ struct ElGrad {
   double P = 2.0;
   bool uterm = false;
   const double* f = nullptr;
+  EnergyCoef co;           // kind 3 coefficients
   double* cvec = nullptr;  // m
   double* gB = nullptr;    // d n
   double* yB = nullptr;    // (d + 1) n: the B weights, then yA
@@ -699,7 +700,7 @@ struct ElGrad {
     const int n = tb->n, m = tb->m, d = tb->dim;
     SHIP(launch_gemv_n_ld(tb->f64, tb->d_B, d * n, m, m, x, 1.0, 0.0, gB, st));
     if (uterm) SHIP(launch_gemv_n_ld(tb->f64, tb->d_A, n, m, m, x, 1.0, 0.0, uA, st));
-    SHIP(launch_energy_wb(kind, n, d, P, tb->d_lambda, gB, kgv, yB, uterm ? uA : nullptr, hg, f, yA, st));
+    SHIP(launch_energy_wb(kind, n, d, P, tb->d_lambda, gB, kgv, yB, uterm ? uA : nullptr, hg, f, yA, co, st));
     SHIP(launch_gemv_t_acc(tb->f64, tb->d_B, d * n, m, m, yB, 1.0, out, st));
     if (uterm) SHIP(launch_gemv_t_acc(tb->f64, tb->d_A, n, m, m, yA, 1.0, out, st));
     return WOS_OK;
@@ -730,7 +731,7 @@ struct ElGrad {
     const float* Af = static_cast<const float*>(tb->d_A);
     SHIP(launch_gemv_n4_batch(Bf, d * n, m, m, x, m, nv, GB, (int)dn, st));
     if (uterm) SHIP(launch_gemv_n4_batch(Af, n, m, m, x, m, nv, UA, n, st));
-    SHIP(launch_energy_wb_batch(kind, n, d, P, tb->d_lambda, GB, kgv, YB, uterm ? UA : nullptr, hg, f, nv, st));
+    SHIP(launch_energy_wb_batch(kind, n, d, P, tb->d_lambda, GB, kgv, YB, uterm ? UA : nullptr, hg, f, nv, co, st));
     SHIP(launch_hisd_broadcast(m, nv, cvec, out, st));
     SHIP(launch_gemv_t4_batch(Bf, d * n, m, m, YB, (int)(dn + n), nv, out, m, st));
     if (uterm) SHIP(launch_gemv_t4_batch(Af, n, m, m, YB + dn, (int)(dn + n), nv, out, m, st));
@@ -739,7 +740,8 @@ struct ElGrad {
 };
 
 wos_status check_energy(int kind, double p_exp) {
-  if (kind != WOS_EL_PLAPLACE && kind != WOS_EL_MINIMAL_SURFACE && kind != WOS_EL_SEMILINEAR)
+  if (kind != WOS_EL_PLAPLACE && kind != WOS_EL_MINIMAL_SURFACE && kind != WOS_EL_SEMILINEAR &&
+      kind != WOS_EL_ELLIPTIC)
     return sfail(WOS_EINVAL, "unknown energy %d", kind);
   if (kind == WOS_EL_PLAPLACE && !(p_exp > 1.0)) return sfail(WOS_EINVAL, "p_exp must be > 1");
   return WOS_OK;
@@ -777,9 +779,12 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
   eg.tb = tb;
   eg.kind = kind;
   eg.P = P;
-  eg.uterm = kind == WOS_EL_SEMILINEAR;  // dF/du depends on u
+  eg.uterm = kind == WOS_EL_SEMILINEAR || kind == WOS_EL_ELLIPTIC;  // dF/du depends on u
   eg.f = f;
   eg.st = st;
+  eg.co.A = o->coef_A;
+  eg.co.c = o->coef_c;
+  eg.co.w = o->coef_w;
   double* F = eg.carve(w.el);           // n: the energy density at the end
   double* grad = F + n;                 // m
   double* mv = grad + m;                // m
@@ -826,7 +831,7 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
   inf.grad_norm = std::sqrt(gg);
   // u, grad u and J = sum_i lambda_i F_i at the result
   if ((s = reconstruct(tb, fbar, g, u, grad_u ? grad_u : gB, st)) != WOS_OK) return s;
-  SHIP(launch_energy_weights(kind, n, d, P, tb->d_lambda, u, grad_u ? grad_u : gB, f, yB, F, st));
+  SHIP(launch_energy_weights(kind, n, d, P, tb->d_lambda, u, grad_u ? grad_u : gB, f, yB, F, eg.co, st));
   SHIP(launch_dot(n, F, tb->d_lambda, nullptr, red, st));
   SHIP(hipMemcpyAsync(&inf.J, red, sizeof(double), hipMemcpyDeviceToHost, st));
   SHIP(hipStreamSynchronize(st));
@@ -908,7 +913,7 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   eg.tb = tb;
   eg.kind = kind;
   eg.P = P;
-  eg.uterm = kind == WOS_EL_SEMILINEAR;
+  eg.uterm = kind == WOS_EL_SEMILINEAR || kind == WOS_EL_ELLIPTIC;
   eg.f = f;
   eg.st = st;
   double* F = eg.carve(w.el);  // n
@@ -1029,7 +1034,7 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   SHIP(hipMemcpyAsync(V, Vc, sizeof(double) * k * (size_t)m, hipMemcpyDeviceToDevice, st));
   // u, grad u and J at the result
   if ((s = reconstruct(tb, fbar, g, u, grad_u ? grad_u : eg.gB, st)) != WOS_OK) return s;
-  SHIP(launch_energy_weights(kind, n, d, P, tb->d_lambda, u, grad_u ? grad_u : eg.gB, f, eg.yB, F, st));
+  SHIP(launch_energy_weights(kind, n, d, P, tb->d_lambda, u, grad_u ? grad_u : eg.gB, f, eg.yB, F, eg.co, st));
   SHIP(launch_dot(n, F, tb->d_lambda, nullptr, red, st));
   SHIP(hipMemcpyAsync(&inf.J, red, sizeof(double), hipMemcpyDeviceToHost, st));
   SHIP(hipStreamSynchronize(st));

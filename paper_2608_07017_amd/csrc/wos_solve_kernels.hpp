@@ -33,19 +33,27 @@ hipError_t launch_tsvd_filter(int M, const double* e, double thr, double* z, hip
 hipError_t launch_symmetrize(double* G, int M, hipStream_t st);
 hipError_t launch_dot(int n, const double* x, const double* y, const double* w, double* out, hipStream_t st);
 // Euler-Lagrange route, energy kind 0 p-Laplace, 1 minimal surface,
-// 2 semilinear: all site weights y = [lambda dF/dp; lambda dF/du] and the
-// energy density F at a result; the weights inside the iteration (yB from
+// 2 semilinear, 3 weighted quadratic (coefficients `co`): all site weights
+// y = [lambda dF/dp; lambda dF/du] and the energy density F at a result; the weights inside the iteration (yB from
 // p = gB + kg, and with uA non-NULL yA from u = uA + hg); one Adam step
+// per-site coefficients of energy kind 3 (device, each NULL for 1, I, 0):
+// w (n), A (n x d x d), c (n)
+struct EnergyCoef {
+  const double* A = nullptr;
+  const double* c = nullptr;
+  const double* w = nullptr;
+};
 hipError_t launch_energy_weights(int kind, int n, int d, double P, const double* lam, const double* u,
-                                 const double* gu, const double* f, double* y, double* F, hipStream_t st);
+                                 const double* gu, const double* f, double* y, double* F, const EnergyCoef& co,
+                                 hipStream_t st);
 hipError_t launch_energy_wb(int kind, int n, int d, double P, const double* lam, const double* gB, const double* kg,
                             double* yB, const double* uA, const double* hg, const double* f, double* yA,
-                            hipStream_t st);
+                            const EnergyCoef& co, hipStream_t st);
 // the weights at nv points: point t reads GB + t d n (and UA + t n) and
 // writes YB + t (d + 1) n (the B weights, then the A weights)
 hipError_t launch_energy_wb_batch(int kind, int n, int d, double P, const double* lam, const double* GB,
                                   const double* kg, double* YB, const double* UA, const double* hg, const double* f,
-                                  int nv, hipStream_t st);
+                                  int nv, const EnergyCoef& co, hipStream_t st);
 // FP32 X with 16-byte rows, nv odd in 3..17 (else hipErrorInvalidValue):
 // Y[t] = X V[t] and Y[t] += X^T V[t], X read once for all nv vectors
 hipError_t launch_gemv_n4_batch(const float* X, int rows, int cols, int ld, const double* V, int vs, int nv,
