@@ -419,7 +419,7 @@ def el_energies(a, torch, W, P):
     |D|) and its semilinear example with s = 800 on its 20 x 20 square
     layout, with its Adam parameters (fbar_0 = 1, alpha 0.01 and 1) to its
     final gradient norm 1e-6, and that example's index-1 and index-2 saddle
-    points by p-HiSD with its parameters; and its example "elliptic div
+    points by p-HiSD with its parameters (k = 1, 2, 3); and its example "elliptic div
     min" on the disk layout against the closed form.  (4) The semilinear iteration rate on the 4096-site L-shape
     toolbox, which streams A and B twice each."""
     def grid(k):
@@ -502,7 +502,7 @@ def el_energies(a, torch, W, P):
                                            "J": info["J"], "u_range": [float(u.min()), float(u.max())]}
     # the same example's saddle points by p-HiSD with the paper's parameters
     # (M = A, fbar_0 = 1000, eta = 20, tau = 10, directions from the Hessian)
-    for k in (1, 2):
+    for k in (1, 2, 3):
         u, _, _, _, info = tb.saddle(f, np.zeros(tb.p), k, 20.0, 10.0, a.hisd_max_iter, fbar0=1000.0, precond="A",
                                      tol=1e-6, check_every=50)
         out["semilinear_s800_phisd_k%d" % k] = {

@@ -199,3 +199,38 @@ def test_saddle_fp32_toolbox_batched_gradients_match_oracle(k):
     assert np.abs(fb - ref_fb).max() <= 1e-7 * np.abs(ref_fb).max()
     assert np.abs(V.T - ref_V).max() <= 1e-6 * np.abs(ref_V).max()
     assert info["grad_norm"] == pytest.approx(E.grad_norm(lam, gr(ref_fb)), rel=1e-5)
+
+
+def test_saddle_paper_s800_four_distinct_solutions():
+    # The paper finds at least four essentially distinct solutions of
+    # Lap u + u^2 = 800 sin(pi x) sin(pi y): here Adam's minimum (Hessian
+    # index 0) and p-HiSD's saddles for k = 1, 2, 3 (index k), all at the
+    # paper's final norm, on an FP32 toolbox of its 20 x 20 layout (1e5
+    # walks/site) with its parameters.  Solutions of different index are
+    # not images of each other under the square's symmetries.
+    sites, bn = W.paper_square_layout()
+    _say("GPU build paper square, 1e5 walks, FP32")
+    tb = P.Toolbox(W.unit_square(), sites, bn, 100000, 1e-4, seed=11, precision="f32", volume_samples=1 << 20)
+    tb.build()
+    torch.cuda.synchronize()
+    mats = {key: tb.export(key).cpu().numpy().astype(np.float64) for key in ("A", "B", "H", "K", "lambda")}
+    lam = mats["lambda"]
+    f = 800.0 * np.sin(np.pi * sites[:, 0]) * np.sin(np.pi * sites[:, 1])
+    g = np.zeros(tb.p)
+    us = []
+    _, _, fb, info = tb.minimize(f, g, 0.0, 1.0, 40000, fbar0=1.0, energy="semilinear", tol=1e-6, check_every=50)
+    sols = [(0, fb.cpu().numpy(), info)]
+    for k in (1, 2, 3):
+        _say("saddle s=800 k=%d" % k)
+        _, _, fb, _, info = tb.saddle(f, g, k, 20.0, 10.0, 40000, fbar0=1000.0, precond="A", tol=1e-6,
+                                      check_every=50)
+        sols.append((k, fb.cpu().numpy(), info))
+    for k, fb, info in sols:
+        _say("  index %d: %d iters, grad norm %.2e, J %.5g" % (k, info["iters"], info["grad_norm"], info["J"]))
+        assert info["iters"] < 40000 and info["grad_norm"] <= 1e-6
+        Hf = E.semilinear_hessian(mats, lam, fb, g)
+        assert np.sum(np.linalg.eigvalsh(0.5 * (Hf + Hf.T)) < 0) == k
+        us.append(mats["A"] @ fb)
+    for a in range(4):
+        for b in range(a):
+            assert np.linalg.norm(us[a] - us[b]) > 0.1 * max(np.linalg.norm(us[a]), np.linalg.norm(us[b]))
