@@ -906,8 +906,21 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   const double P = kind == WOS_EL_PLAPLACE ? o->p_exp : 2.0;
   const size_t mm = (size_t)m * m;
   if (!w.el && (s = walloc(w, &w.el, (size_t)(3 * d + 4) * n + 4 * (size_t)m + 2)) != WOS_OK) return s;
-  const size_t hs_len = 3 * mm + 76 * (size_t)m + 8;
-  if (!w.hs && (s = walloc(w, &w.hs, hs_len)) != WOS_OK) return s;
+  // the three m x m Newton-Schulz matrices only with M = A; the buffer
+  // grows when a later call needs more
+  const size_t nmat = useA ? 3 * mm : 0;
+  const size_t hs_len = nmat + 76 * (size_t)m + 8;
+  if (w.hs_cap < hs_len) {
+    if (w.hs) {
+      SHIP(hipStreamSynchronize(st));
+      SHIP(hipFree(w.hs));
+      w.bytes -= w.hs_cap * sizeof(double);
+      w.hs = nullptr;
+      w.hs_cap = 0;
+    }
+    if ((s = walloc(w, &w.hs, hs_len)) != WOS_OK) return s;
+    w.hs_cap = hs_len;
+  }
   if (!w.hs_bad && (s = walloc(w, &w.hs_bad, 1)) != WOS_OK) return s;
   ElGrad eg;
   eg.tb = tb;
@@ -918,10 +931,10 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   eg.st = st;
   double* F = eg.carve(w.el);  // n
   double* red = F + n;         // 2 (the Adam route's slots are not used here)
-  double* Minv = w.hs;         // m^2
+  double* Minv = w.hs;         // m^2 (M = A)
   double* Y2 = Minv + mm;      // m^2 (Newton-Schulz)
   double* D = Y2 + mm;         // m^2 (Newton-Schulz)
-  double* Vc = D + mm;         // 8 m: the directions
+  double* Vc = w.hs + nmat;    // 8 m: the directions
   double* Vn = Vc + 8 * (size_t)m;   // 8 m
   double* MV = Vn + 8 * (size_t)m;   // 8 m: M V
   double* HV = MV + 8 * (size_t)m;   // 8 m
