@@ -131,7 +131,7 @@ wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_
 
 /* Queues one complete toolbox build on `stream`: the cell weights lambda_i,
  * the walks of Alg. "WoS-LOT" for all (site, walk) pairs, and the
- * normalisation by N.  `seed` replaces opts.seed for this build.  Previous
+ * normalisation by N.  `seed` replaces opts.seed for this call.  Previous
  * contents are overwritten.  Asynchronous.                                      */
 wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream);
 

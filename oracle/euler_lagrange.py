@@ -31,7 +31,7 @@ J: m_j = beta1 m_{j-1} + (1 - beta1) grad, v_j = beta2 v_{j-1} +
 (1 - beta1^j), fbar_j = fbar_{j-1} - alpha_j m_j / (sqrt(v_j) + eps), with
 m_0 = v_0 = 0 and the paper's beta1 = 0.9, beta2 = 0.999, eps = 1e-10.
 
-Readings (each listed in the design doc):
+Readings:
 * the stopping norm |grad J|_{2,V} = (sum_j lambda(V_j) [grad J]_j^2)^(1/2)
   is taken with the normalised cell weights lambda_j = |V_j| / |D| (the
   toolbox's V and W cells are the same Voronoi cells of the sites), i.e.

@@ -15,7 +15,7 @@ lambda_i <B_{.ij}, b(x_i)>, K^b likewise, H^c_{ij} = lambda_i c_i H_{ij};
 then u = A q + H g~ and grad u_i = B_i q + K_i g~ (the boxed
 reconstruction; Sec. "Euler-Lagrange" for the gradient).
 
-Readings taken here (each listed in the design doc):
+Readings taken here:
 * the right-hand side term "A^lambda f~" is dimensionally (n x m)(n,) and is
   read as (A^lambda)^T f~ = A^T (lambda o f~), which is what the derivation
   above it produces (sum_i lambda_i f(x_i) [A phi]_i);

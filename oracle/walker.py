@@ -23,7 +23,7 @@ For site x = x_i and walk l, with r0 = r(x):
    cell (eqs. Estimator_H, Estimator_K);
 7. divide by N.
 
-Readings of the paper taken here (each also listed in the design doc):
+Readings of the paper taken here:
 * the paper runs a fixed number M of steps; the default here stops at the
   first k >= 1 with r(X_k) < eps (``fixed_M > 0`` gives the paper's rule:
   exactly M chain tallies, terminal point X_{M+1} as in Alg. "WoS-LOT");

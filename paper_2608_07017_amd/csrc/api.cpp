@@ -676,7 +676,7 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
   if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[1], stream));
 
   // walker; on the first build with autotuning, every supported workgroup
-  // size is timed on this build's own inputs first and the fastest is kept
+  // size is timed on the toolbox's own inputs first and the fastest is kept
   // (the tallies are exact fixed-point sums, so the result does not depend
   // on the choice)
   if (tb->autotune && tb->walker_block == 0) {
