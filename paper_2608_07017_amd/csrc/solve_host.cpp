@@ -709,9 +709,10 @@ struct ElGrad {
     SHIP(hipMemcpyAsync(out, cvec, sizeof(double) * tb->m, hipMemcpyDeviceToDevice, st));
     return acc(x, out);
   }
-  // whether eval_batch reads the toolbox once for nv points (FP32 rows of
-  // 16 bytes, nv odd in 3..17); otherwise it evaluates one point at a time
-  bool batchable(int nv) const { return !tb->f64 && tb->m % 4 == 0 && nv >= 3 && nv <= 17 && (nv & 1); }
+  // whether eval_batch reads the toolbox once for nv points (nv odd in
+  // 3..17: the 2k + 1 points of a saddle-search iteration); otherwise it
+  // evaluates one point at a time
+  static bool batchable(int nv) { return nv >= 3 && nv <= 17 && (nv & 1); }
   // out[t] = grad J(x[t]) for nv points stored one after another (m each);
   // scratch holds nv (2d + 2) n doubles
   wos_status eval_batch(const double* x, double* out, int nv, double* scratch) {
@@ -727,14 +728,12 @@ struct ElGrad {
     double* GB = scratch;                   // nv d n
     double* UA = GB + (size_t)nv * dn;      // nv n
     double* YB = UA + (size_t)nv * n;       // nv (d + 1) n
-    const float* Bf = static_cast<const float*>(tb->d_B);
-    const float* Af = static_cast<const float*>(tb->d_A);
-    SHIP(launch_gemv_n4_batch(Bf, d * n, m, m, x, m, nv, GB, (int)dn, st));
-    if (uterm) SHIP(launch_gemv_n4_batch(Af, n, m, m, x, m, nv, UA, n, st));
+    SHIP(launch_gemv_batch(tb->f64, false, tb->d_B, d * n, m, m, x, m, nv, GB, (int)dn, st));
+    if (uterm) SHIP(launch_gemv_batch(tb->f64, false, tb->d_A, n, m, m, x, m, nv, UA, n, st));
     SHIP(launch_energy_wb_batch(kind, n, d, P, tb->d_lambda, GB, kgv, YB, uterm ? UA : nullptr, hg, f, nv, co, st));
     SHIP(launch_hisd_broadcast(m, nv, cvec, out, st));
-    SHIP(launch_gemv_t4_batch(Bf, d * n, m, m, YB, (int)(dn + n), nv, out, m, st));
-    if (uterm) SHIP(launch_gemv_t4_batch(Af, n, m, m, YB + dn, (int)(dn + n), nv, out, m, st));
+    SHIP(launch_gemv_batch(tb->f64, true, tb->d_B, d * n, m, m, YB, (int)(dn + n), nv, out, m, st));
+    if (uterm) SHIP(launch_gemv_batch(tb->f64, true, tb->d_A, n, m, m, YB + dn, (int)(dn + n), nv, out, m, st));
     return WOS_OK;
   }
 };

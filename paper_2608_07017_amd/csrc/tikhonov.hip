@@ -286,6 +286,55 @@ __global__ __launch_bounds__(256) void gemv_t4b_kernel(const float* __restrict__
   }
 }
 
+// The same two batched products for any row layout and either precision:
+// one wavefront per row (forward), one thread per column (transposed,
+// coalesced across the workgroup, `rpb` rows per block, one atomic per
+// column and vector per block).
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void gemv_nb_kernel(const T* __restrict__ X, int rows, int cols, int ld,
+                                                      const double* __restrict__ V, int vs, double* __restrict__ Y,
+                                                      int ys) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const T* xr = X + (size_t)row * ld;
+  double acc[NV];
+#pragma unroll
+  for (int t = 0; t < NV; ++t) acc[t] = 0.0;
+  for (int j = lane; j < cols; j += 64) {
+    const double x = (double)xr[j];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) acc[t] = fma(x, V[(size_t)t * vs + j], acc[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < NV; ++t) {
+    double a = acc[t];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+    if (lane == 0) Y[(size_t)t * ys + row] = a;
+  }
+}
+
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void gemv_tb_kernel(const T* __restrict__ X, int rows, int cols, int ld,
+                                                      const double* __restrict__ V, int vs, double* __restrict__ Y,
+                                                      int ys, int rpb) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= cols) return;
+  const int r0 = blockIdx.y * rpb, r1 = min(rows, r0 + rpb);
+  double acc[NV];
+#pragma unroll
+  for (int t = 0; t < NV; ++t) acc[t] = 0.0;
+  for (int r = r0; r < r1; ++r) {
+    const double x = (double)X[(size_t)r * ld + c];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) acc[t] = fma(x, V[(size_t)t * vs + r], acc[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < NV; ++t)
+    if (acc[t] != 0.0) atomicAdd(&Y[(size_t)t * ys + c], acc[t]);
+}
+
 bool rows16(const void* X, int ld, int cols) {
   return ((uintptr_t)X % 16) == 0 && (ld % 4) == 0 && (cols % 4) == 0;
 }
@@ -471,6 +520,50 @@ hipError_t launch_gemv_n4_batch(const float* X, int rows, int cols, int ld, cons
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gemv_batch_generic(bool trans, const T* X, int rows, int cols, int ld, const double* V, int vs, int nv,
+                              double* Y, int ys, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  if (!trans) {
+    const dim3 g((rows + 3) / 4);
+    switch (nv) {
+#define WOS_CASE(N_)                                                                                 \
+  case N_:                                                                                           \
+    hipLaunchKernelGGL((gemv_nb_kernel<T, N_>), g, dim3(256), 0, st, X, rows, cols, ld, V, vs, Y, ys); \
+    break;
+      WOS_NV_CASES(WOS_CASE)
+#undef WOS_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  } else {
+    const int cb = (cols + 255) / 256;
+    int rpb = 512;
+    while (rpb > 16 && (size_t)cb * ((rows + rpb - 1) / rpb) < 256) rpb /= 2;
+    const dim3 g(cb, (rows + rpb - 1) / rpb);
+    switch (nv) {
+#define WOS_CASE(N_)                                                                                          \
+  case N_:                                                                                                    \
+    hipLaunchKernelGGL((gemv_tb_kernel<T, N_>), g, dim3(256), 0, st, X, rows, cols, ld, V, vs, Y, ys, rpb);     \
+    break;
+      WOS_NV_CASES(WOS_CASE)
+#undef WOS_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_batch(bool f64, bool trans, const void* X, int rows, int cols, int ld, const double* V, int vs,
+                             int nv, double* Y, int ys, hipStream_t st) {
+  if (!f64 && rows16(X, ld, cols))
+    return trans ? launch_gemv_t4_batch((const float*)X, rows, cols, ld, V, vs, nv, Y, ys, st)
+                 : launch_gemv_n4_batch((const float*)X, rows, cols, ld, V, vs, nv, Y, ys, st);
+  if (f64) return gemv_batch_generic<double>(trans, (const double*)X, rows, cols, ld, V, vs, nv, Y, ys, st);
+  return gemv_batch_generic<float>(trans, (const float*)X, rows, cols, ld, V, vs, nv, Y, ys, st);
 }
 
 hipError_t launch_gemv_t4_batch(const float* X, int rows, int cols, int ld, const double* V, int vs, int nv,

@@ -60,6 +60,10 @@ hipError_t launch_gemv_n4_batch(const float* X, int rows, int cols, int ld, cons
                                 double* Y, int ys, hipStream_t st);
 hipError_t launch_gemv_t4_batch(const float* X, int rows, int cols, int ld, const double* V, int vs, int nv,
                                 double* Y, int ys, hipStream_t st);
+// the same for any toolbox storage (FP32 rows of 16 bytes take the 4-wide
+// kernels above): Y[t] = X V[t] (trans false) or Y[t] += X^T V[t]
+hipError_t launch_gemv_batch(bool f64, bool trans, const void* X, int rows, int cols, int ld, const double* V, int vs,
+                             int nv, double* Y, int ys, hipStream_t st);
 hipError_t launch_adam(int m, double* g, double b1, double b2, double eps, double aj, double* mv, double* vv,
                        double* fbar, const double* reset, hipStream_t st);
 hipError_t launch_picard_coef(int n, int d, const double* u, double* Ac, hipStream_t st);

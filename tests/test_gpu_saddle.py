@@ -176,20 +176,21 @@ def test_saddle_paper_semilinear_s800_index1():
     assert np.sum(np.linalg.eigvalsh(0.5 * (Hm + Hm.T)) < 0) == 0
 
 
-@pytest.mark.parametrize("k", [1, 2, 4])
-def test_saddle_fp32_toolbox_batched_gradients_match_oracle(k):
-    # An FP32 toolbox with m % 4 == 0 (4 rings, 48 sites) takes the batched
-    # gradients: the 2k + 1 points of an iteration in one pass over A and B.
-    # The exported FP32 entries are exact in FP64, so the oracle runs on the
-    # same matrices.
-    _say("GPU build disk rings 4, FP32; saddle k=%d" % k)
-    tb = P.Toolbox(W.unit_disk(), _rings(4), W.circle_nodes(24), 1500, 1e-3, seed=12, precision="f32",
+@pytest.mark.parametrize("rings,k", [(4, 1), (4, 2), (4, 4), (5, 2)])
+def test_saddle_fp32_toolbox_batched_gradients_match_oracle(rings, k):
+    # FP32 toolboxes take the batched gradients (the 2k + 1 points of an
+    # iteration in one pass over A and B): with m % 4 == 0 (4 rings, 48
+    # sites) the 4-wide kernels, otherwise (5 rings, 75 sites) the generic
+    # ones; the FP64 tests above take the generic FP64 ones.  The exported
+    # FP32 entries are exact in FP64, so the oracle runs on the same
+    # matrices.
+    _say("GPU build disk rings %d, FP32; saddle k=%d" % (rings, k))
+    tb = P.Toolbox(W.unit_disk(), _rings(rings), W.circle_nodes(24), 1500, 1e-3, seed=12, precision="f32",
                    volume_samples=1 << 18)
     tb.build()
     torch.cuda.synchronize()
     mats = {key: tb.export(key).cpu().numpy().astype(np.float64) for key in ("A", "B", "H", "K", "lambda")}
     lam = mats["lambda"]
-    assert tb.m % 4 == 0
     f, g = _problem(tb.n, tb.p, 15)
     rng = np.random.default_rng(16)
     V0 = rng.normal(size=(k, tb.m))
