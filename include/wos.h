@@ -443,8 +443,9 @@ typedef struct {
  *           linearly independent set); the final directions on return
  *   u       device double (n) output; grad_u device (d x n) or NULL
  *   info    host, optional.
- * An iteration evaluates grad J 2k + 1 times (each streams B, and A for the
- * semilinear energy, twice) and applies M^-1 k + 1 times (FP64 GEMVs).
+ * An iteration evaluates grad J at 2k + 1 points in one batched pass over
+ * B (and A when dF/du depends on u), forward and transposed, and applies
+ * M^-1 k + 1 times (FP64 GEMVs).
  * Runs on `stream` and synchronises it before returning.
  * Errors: WOS_EINVAL for a NULL pointer, an unbuilt toolbox, an unknown
  * energy or option, k outside 1..8 or above m, eta or tau <= 0,
