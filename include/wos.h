@@ -452,7 +452,7 @@ typedef struct {
  * max_iter <= 0, WOS_HISD_PRECOND_A with n != m or m > 16384,
  * WOS_HISD_INIT_HESSIAN with another energy than WOS_EL_SEMILINEAR, and
  * directions that are not M-independent (a non-positive x^T M x in the
- * Gram-Schmidt pass).  Work memory (76 m doubles, 3 m^2 more with
+ * Gram-Schmidt pass).  Work memory (78 m doubles, 3 m^2 more with
  * WOS_HISD_PRECOND_A, plus the solver's work for WOS_HISD_INIT_HESSIAN) is
  * kept with the toolbox and grows when a call needs more.  Not thread-safe
  * for one toolbox.                                                          */

@@ -67,14 +67,16 @@ __global__ void hisd_shift_kernel(int m, int k, const double* __restrict__ fbar,
   }
 }
 
-// HV_i = (G[2i] - G[2i + 1]) / (2h): the central difference of grad J.
+// HV_i = (G[2i] - G[2i + 1]) / (2h) for i < k, the central difference of
+// grad J; and HV_k = G[2k], grad J at the point itself, so that one batched
+// product with M^-1 serves both.
 __global__ void hisd_hv_kernel(int m, int k, const double* __restrict__ G, const double* __restrict__ h,
                                double* __restrict__ HV) {
   const double inv = 0.5 / h[0];
-  const size_t total = (size_t)k * m;
+  const size_t total = (size_t)(k + 1) * m;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
     const size_t i = t / m, j = t % m;
-    HV[t] = (G[2 * i * m + j] - G[(2 * i + 1) * m + j]) * inv;
+    HV[t] = i < (size_t)k ? (G[2 * i * m + j] - G[(2 * i + 1) * m + j]) * inv : G[2 * (size_t)k * m + j];
   }
 }
 
@@ -240,7 +242,7 @@ hipError_t launch_hisd_shift(int m, int k, const double* fbar, const double* V, 
 }
 
 hipError_t launch_hisd_hv(int m, int k, const double* G, const double* h, double* HV, hipStream_t st) {
-  hipLaunchKernelGGL(hisd_hv_kernel, dim3(grid_for((size_t)k * m)), dim3(256), 0, st, m, k, G, h, HV);
+  hipLaunchKernelGGL(hisd_hv_kernel, dim3(grid_for((size_t)(k + 1) * m)), dim3(256), 0, st, m, k, G, h, HV);
   return hipGetLastError();
 }
 

@@ -908,7 +908,7 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   // the three m x m Newton-Schulz matrices only with M = A; the buffer
   // grows when a later call needs more
   const size_t nmat = useA ? 3 * mm : 0;
-  const size_t hs_len = nmat + 76 * (size_t)m + 8;
+  const size_t hs_len = nmat + 78 * (size_t)m + 8;
   if (w.hs_cap < hs_len) {
     if (w.hs) {
       SHIP(hipStreamSynchronize(st));
@@ -936,9 +936,9 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   double* Vc = w.hs + nmat;    // 8 m: the directions
   double* Vn = Vc + 8 * (size_t)m;   // 8 m
   double* MV = Vn + 8 * (size_t)m;   // 8 m: M V
-  double* HV = MV + 8 * (size_t)m;   // 8 m
-  double* Yv = HV + 8 * (size_t)m;   // 8 m: M^-1 H V
-  double* Xs = Yv + 8 * (size_t)m;   // 17 m: fbar +- h v_i, then fbar
+  double* HV = MV + 8 * (size_t)m;   // 9 m: H v_i, then grad J
+  double* Yv = HV + 9 * (size_t)m;   // 9 m: M^-1 of them
+  double* Xs = Yv + 9 * (size_t)m;   // 17 m: fbar +- h v_i, then fbar
   double* Gs = Xs + 17 * (size_t)m;  // 17 m: their gradients
   double* gr0 = Gs + 17 * (size_t)m; // m: the gradient at the start
   double* wv = gr0 + m;              // m: M^-1 grad J
@@ -955,6 +955,14 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
       SHIP(launch_gemv_n(true, Minv, m, m, x, 1.0, 0.0, y, st));
     else
       SHIP(hipMemcpyAsync(y, x, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    return WOS_OK;
+  };
+  // Y[t] = M^-1 X[t] for nv vectors: one pass over M^-1
+  auto minv_batch = [&](const double* X, int nvec, double* Y) -> wos_status {
+    if (useA)
+      SHIP(launch_gemv_batch(true, false, Minv, m, m, m, X, m, nvec, Y, m, st));
+    else
+      SHIP(hipMemcpyAsync(Y, X, sizeof(double) * nvec * (size_t)m, hipMemcpyDeviceToDevice, st));
     return WOS_OK;
   };
   auto mult = [&](const double* x, double* y) -> wos_status {
@@ -1011,23 +1019,27 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   if ((s = check_bad()) != WOS_OK) return s;
   double gn = 0.0;
   const double* gr = gr0;  // grad J at the current fbar
+  const double* wcur = wv;  // M^-1 of it
   if ((s = eg.eval(fbar, gr0)) != WOS_OK) return s;
+  if ((s = minv(gr0, wv)) != WOS_OK) return s;
   if ((s = weighted_norm(gr, &inf.grad_norm0)) != WOS_OK) return s;
   const auto t0 = std::chrono::steady_clock::now();
   int it = 0;
   for (int j = 1; j <= o->max_iter; ++j) {
-    // fbar_j = fbar_{j-1} - eta R M^-1 grad J(fbar_{j-1})  (gr holds the gradient)
-    if ((s = minv(gr, wv)) != WOS_OK) return s;
-    SHIP(launch_hisd_fbar(m, k, Vc, gr, wv, o->eta, fbar, hbuf, st));
+    // fbar_j = fbar_{j-1} - eta R M^-1 grad J(fbar_{j-1})  (gr holds the
+    // gradient, wcur its product with M^-1)
+    SHIP(launch_hisd_fbar(m, k, Vc, gr, wcur, o->eta, fbar, hbuf, st));
     // the 2k + 1 gradients at fbar_j +- h v_i and fbar_j (one pass over the
     // toolbox when batchable): H(fbar_j) v_i by central differences, and
     // grad J(fbar_j) for the next step and the checks
     SHIP(launch_hisd_shift(m, k, fbar, Vc, hbuf, Xs, st));
     if ((s = eg.eval_batch(Xs, Gs, nv, w.hsb)) != WOS_OK) return s;
     gr = Gs + 2 * (size_t)k * m;
+    // H v_i and grad J(fbar_j), then M^-1 of all k + 1 in one pass: y_i for
+    // the directions, and the next step's M^-1 grad J
     SHIP(launch_hisd_hv(m, k, Gs, hbuf, HV, st));
-    for (int i = 0; i < k; ++i)
-      if ((s = minv(HV + (size_t)i * m, Yv + (size_t)i * m)) != WOS_OK) return s;
+    if ((s = minv_batch(HV, k + 1, Yv)) != WOS_OK) return s;
+    wcur = Yv + (size_t)k * m;
     SHIP(launch_hisd_v(m, k, Vc, HV, Yv, o->tau, Vn, st));
     if ((s = orthonormalise(Vn)) != WOS_OK) return s;
     std::swap(Vc, Vn);

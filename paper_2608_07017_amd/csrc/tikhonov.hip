@@ -503,6 +503,8 @@ hipError_t launch_gemv_n_ld(bool f64, const void* X, int rows, int cols, int ld,
 }
 
 #define WOS_NV_CASES(M_) M_(3) M_(5) M_(7) M_(9) M_(11) M_(13) M_(15) M_(17)
+#define WOS_NV_ALL(M_) \
+  M_(1) M_(2) M_(3) M_(4) M_(5) M_(6) M_(7) M_(8) M_(9) M_(10) M_(11) M_(12) M_(13) M_(14) M_(15) M_(16) M_(17)
 
 hipError_t launch_gemv_n4_batch(const float* X, int rows, int cols, int ld, const double* V, int vs, int nv,
                                 double* Y, int ys, hipStream_t st) {
@@ -533,7 +535,7 @@ hipError_t gemv_batch_generic(bool trans, const T* X, int rows, int cols, int ld
   case N_:                                                                                           \
     hipLaunchKernelGGL((gemv_nb_kernel<T, N_>), g, dim3(256), 0, st, X, rows, cols, ld, V, vs, Y, ys); \
     break;
-      WOS_NV_CASES(WOS_CASE)
+      WOS_NV_ALL(WOS_CASE)
 #undef WOS_CASE
       default:
         return hipErrorInvalidValue;
@@ -559,7 +561,8 @@ hipError_t gemv_batch_generic(bool trans, const T* X, int rows, int cols, int ld
 
 hipError_t launch_gemv_batch(bool f64, bool trans, const void* X, int rows, int cols, int ld, const double* V, int vs,
                              int nv, double* Y, int ys, hipStream_t st) {
-  if (!f64 && rows16(X, ld, cols))
+  const bool odd = nv >= 3 && nv <= 17 && (nv & 1);  // the 4-wide kernels' counts
+  if (!f64 && odd && rows16(X, ld, cols))
     return trans ? launch_gemv_t4_batch((const float*)X, rows, cols, ld, V, vs, nv, Y, ys, st)
                  : launch_gemv_n4_batch((const float*)X, rows, cols, ld, V, vs, nv, Y, ys, st);
   if (f64) return gemv_batch_generic<double>(trans, (const double*)X, rows, cols, ld, V, vs, nv, Y, ys, st);
@@ -587,6 +590,7 @@ hipError_t launch_gemv_t4_batch(const float* X, int rows, int cols, int ld, cons
   return hipGetLastError();
 }
 #undef WOS_NV_CASES
+#undef WOS_NV_ALL
 
 hipError_t launch_reg_from_diag(bool f64, const void* N, int m, int ld, double coef, double* out, hipStream_t st) {
   if (f64)

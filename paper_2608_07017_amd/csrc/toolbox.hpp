@@ -60,7 +60,7 @@ struct SolveWork {
   float* P32 = nullptr;
   float* L0_32 = nullptr;   // Lambda_0 (A = I), FP32, for the mixed Newton route
   double* el = nullptr;     // Euler-Lagrange route: (3d + 4) n + 4 m + 2 work doubles
-  double* hs = nullptr;     // p-HiSD: 76 m + 8 work doubles (+ 3 m^2 with M = A)
+  double* hs = nullptr;     // p-HiSD: 78 m + 8 work doubles (+ 3 m^2 with M = A)
   size_t hs_cap = 0;        // doubles held at hs
   int* hs_bad = nullptr;    // p-HiSD: Gram-Schmidt status (device)
   double* hsb = nullptr;    // p-HiSD, batched gradients: 17 (2d + 2) n doubles

@@ -60,8 +60,9 @@ hipError_t launch_gemv_n4_batch(const float* X, int rows, int cols, int ld, cons
                                 double* Y, int ys, hipStream_t st);
 hipError_t launch_gemv_t4_batch(const float* X, int rows, int cols, int ld, const double* V, int vs, int nv,
                                 double* Y, int ys, hipStream_t st);
-// the same for any toolbox storage (FP32 rows of 16 bytes take the 4-wide
-// kernels above): Y[t] = X V[t] (trans false) or Y[t] += X^T V[t]
+// the same for any storage (FP32 rows of 16 bytes take the 4-wide kernels
+// above): Y[t] = X V[t] (trans false; nv in 1..17) or Y[t] += X^T V[t]
+// (trans true; nv odd in 3..17)
 hipError_t launch_gemv_batch(bool f64, bool trans, const void* X, int rows, int cols, int ld, const double* V, int vs,
                              int nv, double* Y, int ys, hipStream_t st);
 hipError_t launch_adam(int m, double* g, double b1, double b2, double eps, double aj, double* mv, double* vv,
@@ -126,6 +127,7 @@ hipError_t launch_hisd_fbar(int m, int k, const double* V, const double* gr, con
                             double* h, hipStream_t st);
 hipError_t launch_hisd_shift(int m, int k, const double* fbar, const double* V, const double* h, double* X,
                              hipStream_t st);
+// HV (k + 1 vectors): the k central differences, then G[2k] copied
 hipError_t launch_hisd_hv(int m, int k, const double* G, const double* h, double* HV, hipStream_t st);
 hipError_t launch_hisd_v(int m, int k, const double* V, const double* HV, const double* Y, double tau, double* Vn,
                          hipStream_t st);
