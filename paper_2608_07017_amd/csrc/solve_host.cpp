@@ -975,8 +975,12 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   // the Gram-Schmidt flag is sticky: cleared once, read (with a
   // synchronisation) after the first pass, at the norm checks and at the end
   auto orthonormalise = [&](double* Vx) -> wos_status {
-    for (int i = 0; i < k; ++i)
-      if ((s = mult(Vx + (size_t)i * m, MV + (size_t)i * m)) != WOS_OK) return s;
+    if (useA && k >= 2) {  // M V in one pass over A
+      SHIP(launch_gemv_batch(tb->f64, false, tb->d_A, m, m, m, Vx, m, k, MV, m, st));
+    } else {
+      for (int i = 0; i < k; ++i)
+        if ((s = mult(Vx + (size_t)i * m, MV + (size_t)i * m)) != WOS_OK) return s;
+    }
     SHIP(launch_hisd_gs(m, k, Vx, MV, w.hs_bad, st));
     return WOS_OK;
   };
