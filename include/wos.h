@@ -452,7 +452,8 @@ typedef struct {
  * max_iter <= 0, WOS_HISD_PRECOND_A with n != m or m > 16384,
  * WOS_HISD_INIT_HESSIAN with another energy than WOS_EL_SEMILINEAR, and
  * directions that are not M-independent (a non-positive x^T M x in the
- * Gram-Schmidt pass).  Work memory (78 m doubles, 3 m^2 more with
+ * Gram-Schmidt pass); WOS_ENOTCONV when the Newton-Schulz inverse of A
+ * stops above |I - A X|_F = 1e-6 sqrt(m) (A too ill-conditioned).  Work memory (78 m doubles, 3 m^2 more with
  * WOS_HISD_PRECOND_A, plus the solver's work for WOS_HISD_INIT_HESSIAN) is
  * kept with the toolbox and grows when a call needs more.  Not thread-safe
  * for one toolbox.                                                          */

@@ -948,7 +948,13 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   if (eg.batchable(nv) && !w.hsb && (s = walloc(w, &w.hsb, 17 * (size_t)(2 * d + 2) * n)) != WOS_OK) return s;
   wos_hisd_info inf{};
   if ((s = eg.setup(g)) != WOS_OK) return s;
-  if (useA && (s = ns_inverse(tb, Minv, Y2, D, red, &inf.ns_iters, &inf.ns_residual, st)) != WOS_OK) return s;
+  if (useA) {
+    if ((s = ns_inverse(tb, Minv, Y2, D, red, &inf.ns_iters, &inf.ns_residual, st)) != WOS_OK) return s;
+    // the GPU update uses v^T grad J for v^T M (M^-1 grad J): M^-1 must be
+    // an inverse to well below the iteration's own accuracy
+    if (!(inf.ns_residual <= 1e-6 * std::sqrt((double)m)))
+      return sfail(WOS_ENOTCONV, "p-HiSD: the Newton-Schulz inverse of A reached only |I - A X|_F = %g", inf.ns_residual);
+  }
   // y = M^-1 x, and M x, for one vector
   auto minv = [&](const double* x, double* y) -> wos_status {
     if (useA)
