@@ -445,15 +445,17 @@ typedef struct {
  *   info    host, optional.
  * An iteration evaluates grad J at 2k + 1 points in one batched pass over
  * B (and A when dF/du depends on u), forward and transposed, and applies
- * M^-1 k + 1 times (FP64 GEMVs).
+ * M^-1 to k + 1 vectors in one pass over it (FP64).
  * Runs on `stream` and synchronises it before returning.
  * Errors: WOS_EINVAL for a NULL pointer, an unbuilt toolbox, an unknown
- * energy or option, k outside 1..8 or above m, eta or tau <= 0,
- * max_iter <= 0, WOS_HISD_PRECOND_A with n != m or m > 16384,
- * WOS_HISD_INIT_HESSIAN with another energy than WOS_EL_SEMILINEAR, and
- * directions that are not M-independent (a non-positive x^T M x in the
- * Gram-Schmidt pass); WOS_ENOTCONV when the Newton-Schulz inverse of A
- * stops above |I - A X|_F = 1e-6 sqrt(m) (A too ill-conditioned).  Work memory (78 m doubles, 3 m^2 more with
+ * energy or option, WOS_EL_ELLIPTIC (a convex energy: no saddle points),
+ * k outside 1..8 or above m, eta or tau <= 0, max_iter <= 0,
+ * WOS_HISD_PRECOND_A with n != m or m > 16384, WOS_HISD_INIT_HESSIAN with
+ * another energy than WOS_EL_SEMILINEAR, and directions that are not
+ * M-independent (x^T M x not positive, or below 1e-24 of its value before
+ * the Gram-Schmidt projections); WOS_ENOTCONV when the Newton-Schulz
+ * inverse of A stops above |I - A X|_F = 1e-6 sqrt(m) (A too
+ * ill-conditioned).  Work memory (78 m doubles, 3 m^2 more with
  * WOS_HISD_PRECOND_A, plus the solver's work for WOS_HISD_INIT_HESSIAN) is
  * kept with the toolbox and grows when a call needs more.  Not thread-safe
  * for one toolbox.                                                          */

@@ -888,6 +888,7 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   const int kind = o->energy;
   wos_status s;
   if ((s = check_energy(kind, o->p_exp)) != WOS_OK) return s;
+  if (kind == WOS_EL_ELLIPTIC) return sfail(WOS_EINVAL, "p-HiSD: the weighted quadratic energy has no saddle points");
   const int n = tb->n, m = tb->m, d = tb->dim, k = o->k;
   if (k < 1 || k > 8 || k > m) return sfail(WOS_EINVAL, "k must be in 1..min(8, m)");
   if (!(o->eta > 0.0) || !(o->tau > 0.0)) return sfail(WOS_EINVAL, "eta and tau must be > 0");

@@ -124,7 +124,8 @@ def test_saddle_invalid_options(ring_tb):
         tb.saddle(f, g, 0, 1.0, 1.0, 5)
     for kw in ({"k": 1, "eta": 0.0, "tau": 1.0, "max_iter": 5}, {"k": 1, "eta": 1.0, "tau": 0.0, "max_iter": 5},
                {"k": 1, "eta": 1.0, "tau": 1.0, "max_iter": 0},
-               {"k": 1, "eta": 1.0, "tau": 1.0, "max_iter": 5, "energy": "plaplace", "p_exp": 2.0}):
+               {"k": 1, "eta": 1.0, "tau": 1.0, "max_iter": 5, "energy": "plaplace", "p_exp": 2.0},
+               {"k": 1, "eta": 1.0, "tau": 1.0, "max_iter": 5, "energy": "elliptic", "V0": np.ones((1, tb.m))}):
         with pytest.raises(P.WosError):
             tb.saddle(f, g, **kw)
     # dependent directions
