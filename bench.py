@@ -419,7 +419,7 @@ def el_energies(a, torch, W, P):
     |D|) and its semilinear example with s = 800 on its 20 x 20 square
     layout, with its Adam parameters (fbar_0 = 1, alpha 0.01 and 1) to its
     final gradient norm 1e-6, and that example's index-1 and index-2 saddle
-    points by p-HiSD with its parameters (k = 1, 2, 3); and its example "elliptic div
+    points by p-HiSD with its parameters (k = 1, 2, 3), also at s = 8000; and its example "elliptic div
     min" on the disk layout against the closed form.  (4) The semilinear iteration rate on the 4096-site L-shape
     toolbox, which streams A and B twice each."""
     def grid(k):
@@ -509,6 +509,20 @@ def el_energies(a, torch, W, P):
             "iters": info["iters"], "seconds": info["seconds"], "ms_per_iter": 1e3 * info["seconds"] / info["iters"],
             "grad_norm": info["grad_norm"], "J": info["J"], "u_range": [float(u.min()), float(u.max())],
             "newton_schulz_iters": info["ns_iters"], "newton_schulz_residual": info["ns_residual"]}
+    # s = 8000 with the paper's parameters for it: Adam with alpha = 10, and
+    # p-HiSD as above
+    f = 8000.0 * np.sin(np.pi * sites[:, 0]) * np.sin(np.pi * sites[:, 1])
+    u, _, _, info = tb.minimize(f, np.zeros(tb.p), 0.0, 10.0, a.el_max_iter * 3, fbar0=1.0, energy="semilinear",
+                                tol=1e-6, check_every=50)
+    out["semilinear_s8000_adam"] = {"alpha": 10.0, "iters": info["iters"], "seconds": info["seconds"],
+                                    "grad_norm": info["grad_norm"], "J": info["J"],
+                                    "u_range": [float(u.min()), float(u.max())]}
+    for k in (1, 2, 3):
+        u, _, _, _, info = tb.saddle(f, np.zeros(tb.p), k, 20.0, 10.0, a.hisd_max_iter, fbar0=1000.0, precond="A",
+                                     tol=1e-6, check_every=50)
+        out["semilinear_s8000_phisd_k%d" % k] = {
+            "iters": info["iters"], "seconds": info["seconds"], "grad_norm": info["grad_norm"], "J": info["J"],
+            "u_range": [float(u.min()), float(u.max())]}
     tb.free()
     cfg = W.config("lshape4096")
     tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], 1000, cfg["eps"], seed=cfg["seed"], precision="f32")
