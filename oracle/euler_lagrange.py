@@ -49,14 +49,27 @@ the projections v v^T M.
 ``interpolate`` evaluates a solution off the sites, piecewise constant on
 the cells or with the first-order correction <grad u_i, x - x_i>.
 
-Pinned by tests/test_oracle_euler_lagrange.py: the gradient against central
-differences of J, Adam's first step (of length alpha in every coordinate,
-a closed form of the update), Adam on a separable quadratic against its
-known minimiser, the route at P = 2 against the linear system of
-eq. linear_q (the two routes of the paper coincide for the quadratic
-energy), and the disk's closed-form p-torsion solution at P = 2 against
-(1 - |x|^2) / 4; the interpolation reproduces affine fields exactly and
-returns u_i at the sites.
+Pinned by tests/test_oracle_euler_lagrange.py:
+* the gradient of every energy against central differences of J;
+* the semilinear gradient against the regrouped sums Lambda0 fbar +
+  Sigma0 g + A^T (lambda (f - u^2));
+* the weighted quadratic gradient against the linear system of
+  eq. linear_q with the coefficients (w A, 0, w c);
+* the minimal surface gradient at small slope against the quadratic one;
+* Adam's first step (of length alpha in every coordinate, a closed form of
+  the update), and Adam on a separable quadratic against its known
+  minimiser;
+* the route at P = 2 against the linear system of eq. linear_q (the two
+  routes of the paper coincide for the quadratic energy);
+* the disk's closed-form p-torsion solution against the radial p-Laplace
+  equation, and at P = 2 against (1 - |x|^2) / 4;
+* p-HiSD on quadratics with a known saddle: the fixed point H^-1 b, with
+  the directions spanning the unstable eigenvectors (M = I and an SPD M);
+* the M-orthonormalisation for a non-symmetric M, and the QR factor for
+  M = I;
+* the semilinear Hessian against differences of the gradient;
+* the interpolation, which reproduces affine fields exactly and returns
+  u_i at the sites.
 """
 import numpy as np
 
