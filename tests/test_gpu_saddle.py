@@ -238,3 +238,24 @@ def test_saddle_paper_s800_four_distinct_solutions():
     for a in range(4):
         for b in range(a):
             assert np.linalg.norm(us[a] - us[b]) > 0.1 * max(np.linalg.norm(us[a]), np.linalg.norm(us[b]))
+
+
+@pytest.mark.parametrize("energy,p_exp", [("plaplace", 3.0), ("minimal_surface", 0.0)])
+def test_saddle_other_energies_match_oracle(ring_tb, energy, p_exp):
+    # the batched weights for the energies whose dF/du is constant (their c
+    # term is broadcast before the transposed products): 8 iterations, k = 2,
+    # M = A, against the oracle's p-HiSD
+    tb, mats = ring_tb
+    lam = mats["lambda"]
+    f, g = _problem(tb.n, tb.p, 21)
+    rng = np.random.default_rng(22)
+    V0 = rng.normal(size=(2, tb.m))
+    fb0 = 1.0 + 0.1 * rng.normal(size=tb.m)
+    _say("saddle %s k=2" % energy)
+    _, _, fb, V, info = tb.saddle(f, g, 2, 0.5, 0.5, 8, fbar0=fb0, V0=V0, precond="A", energy=energy, p_exp=p_exp)
+    gr = lambda x: E.energy_grad(energy, mats, lam, x, g, p_exp, f)
+    ref_fb, ref_V, _ = E.phisd(gr, fb0, V0.T, mats["A"], 0.5, 0.5, 8)
+    fb, V = fb.cpu().numpy(), V.cpu().numpy()
+    assert np.abs(fb - ref_fb).max() <= 1e-7 * np.abs(ref_fb).max()
+    assert np.abs(V.T - ref_V).max() <= 1e-6 * np.abs(ref_V).max()
+    assert info["grad_norm"] == pytest.approx(E.grad_norm(lam, gr(ref_fb)), rel=1e-5)
