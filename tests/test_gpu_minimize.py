@@ -401,3 +401,35 @@ def test_elliptic_divmin_finer_w_partition_converges():
     _say("  rel L2 error %.4f, grad norm %.2e, %d iters" % (err, info["grad_norm"], info["iters"]))
     assert info["grad_norm"] <= 1e-9
     assert err < 0.04
+
+
+@pytest.mark.parametrize("energy", ["semilinear", "elliptic"])
+def test_u_dependent_energies_separate_v_partition(energy):
+    # n = 40 W sites, m = 61 V cells (FP64): the u-term (A fbar, A^T yA)
+    # with a rectangular A, 150 Adam iterations against the oracle, the
+    # norm with the V cells' measures
+    dom = W.unit_disk()
+    sites = W.sample_sites(dom, 40, 51, 1e-3)
+    vc = W.sample_sites(dom, 61, 52, 1e-3)
+    _say("GPU build W != V (40, 61); minimize %s" % energy)
+    tb = P.Toolbox(dom, sites, W.circle_nodes(30), 300, 1e-3, seed=14, precision="f64", volume_samples=1 << 16,
+                   vcentres=vc)
+    tb.build()
+    torch.cuda.synchronize()
+    mats = {k: tb.export(k).cpu().numpy().astype(np.float64) for k in ("A", "B", "H", "K", "lambda", "lambda_v")}
+    f, g = _data(40, 30, 53)
+    rng = np.random.default_rng(54)
+    co = None
+    kw = {}
+    if energy == "elliptic":
+        G = rng.normal(size=(40, 2, 2))
+        co = {"A": np.einsum("nab,ncb->nac", G, G) + np.eye(2), "c": rng.random(40), "w": 0.5 + rng.random(40)}
+        kw = {"coef_A": co["A"], "coef_c": co["c"], "coef_w": co["w"]}
+    u, _, fb, info = tb.minimize(f, g, 0.0, 0.01, 150, fbar0=0.1, energy=energy, **kw)
+    ref = E.minimize_energy(energy, mats, mats["lambda"], f, g, 0.0, 0.01, 150, f0=0.1, lam_v=mats["lambda_v"],
+                            coef=co)
+    assert fb.numel() == 61
+    assert np.allclose(fb.cpu().numpy(), ref["fbar"], rtol=0, atol=1e-8 * np.abs(ref["fbar"]).max())
+    assert np.allclose(u.cpu().numpy(), ref["u"], rtol=0, atol=1e-8 * np.abs(ref["u"]).max())
+    assert info["grad_norm"] == pytest.approx(ref["grad_norm"], rel=1e-6)
+    assert info["J"] == pytest.approx(ref["J"], rel=1e-8, abs=1e-10)
