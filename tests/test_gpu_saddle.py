@@ -143,6 +143,18 @@ def test_saddle_preconditioner_needs_square_toolbox():
         tb.saddle(f, g, 1, 1.0, 1.0, 5, V0=np.ones((1, 20)), precond="A")
     _, _, fb, V, info = tb.saddle(f, g, 1, 1.0, 1.0, 3, V0=np.ones((1, 20)), precond="identity")
     assert info["iters"] == 3 and fb.numel() == 20
+    # with M = I the batched gradients run over the rectangular A and B
+    # (n = 30 sites, m = 20 cells): against the oracle, k = 2
+    mats = {key: tb.export(key).cpu().numpy().astype(np.float64) for key in ("A", "B", "H", "K", "lambda")}
+    lam = mats["lambda"]
+    f2, g2 = _problem(30, 20, 25)
+    rng = np.random.default_rng(26)
+    V0 = rng.normal(size=(2, 20))
+    _, _, fb, V, info = tb.saddle(f2, g2, 2, 20.0, 20.0, 6, fbar0=1.0, V0=V0, precond="identity")
+    gr = lambda x: E.energy_grad("semilinear", mats, lam, x, g2, 0.0, f2)
+    ref_fb, ref_V, _ = E.phisd(gr, np.ones(20), V0.T, np.eye(20), 20.0, 20.0, 6)
+    assert np.abs(fb.cpu().numpy() - ref_fb).max() <= 1e-7 * np.abs(ref_fb).max()
+    assert np.abs(V.cpu().numpy().T - ref_V).max() <= 1e-6 * np.abs(ref_V).max()
 
 
 def test_saddle_paper_semilinear_s800_index1():
