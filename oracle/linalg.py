@@ -38,8 +38,9 @@ discrete functional J of eq. gradJ):
 Pinned by tests/test_oracle_linalg.py: the regrouped sums against the
 literal per-cell sums, the TSVD against numpy's SVD pseudo-inverse, the
 Newton iteration on the quadratic energy against the linear system (the two
-routes of the paper coincide), and end-to-end errors against manufactured
-solutions on the unit disk.
+routes of the paper coincide), end-to-end errors against manufactured
+solutions on the unit disk, and the Picard fixed point against the
+Kirchhoff transform w = u + u^3/3 of the same problem (a linear solve for w).
 """
 import numpy as np
 

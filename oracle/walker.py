@@ -42,6 +42,15 @@ The V cells (the columns of A and B) may be a partition of their own
 independently); with ``vcentres`` the tally points are binned to those
 centres, the walks themselves are unchanged.
 
+Pinned by tests/test_oracle_green_pins.py: every entry of A and B of a
+row against the disk's and the ball's Green function integrated over the
+Voronoi cells (and its gradient in x), the pointwise estimators of
+non-harmonic defining functions (U(-Lap phi / 2) = phi and its gradient)
+on the disk, ball, square, L-shape and cube minus ball, the harmonic
+extension of |y| on the disk with its gradient, and the square's torsion
+function; tests/test_oracle_mutations.py checks that these pins fail for
+copies of this file with one plausible mistake planted (tally point,
+k = 0 point, ball term, omega, signs, terminal point, K weight).
 Pinned by tests/test_oracle_walker.py: E tau = (1-|x|^2)/d and its
 gradient on the unit disk and ball (eps bias bounded by 2 eps / d), the
 closed forms U[x_1] and grad U[x_1], the harmonic extension and its

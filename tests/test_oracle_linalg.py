@@ -161,3 +161,46 @@ def test_regularised_newton_reaches_the_regularised_stationary_point():
     g = rng.normal(size=4)
     res = L.newton_cubic(tb, lam, f, g, kappa=0.5, rcond=1e-12, tol=1e-12, max_iter=60, solver="tikhonov")
     assert res["grad_norm"] <= 1e-9 * res["grad_norm0"]
+
+
+def _kirchhoff_inverse(w):
+    """The real root u of u + u^3 / 3 = w (Cardano: u^3 + 3 u - 3 w = 0)."""
+    s = np.sqrt(2.25 * w * w + 1.0)
+    return np.cbrt(1.5 * w + s) + np.cbrt(1.5 * w - s)
+
+
+def test_t16_picard_agrees_with_the_kirchhoff_transform():
+    # -div((1 + u^2) grad u) = f becomes -Lap w = f for w = u + u^3/3
+    # (grad w = (1 + u^2) grad u), with w = g + g^3/3 on the boundary: a
+    # second, linear route to the same solution.  On one toolbox the Picard
+    # fixed point and the transformed linear solve agree to within their
+    # discretisation error against the manufactured solution, while dropping
+    # the coefficient (a = 1) does not.
+    dom = W.unit_disk()
+    sites = _rings(5)
+    n = len(sites)
+    bn = W.circle_nodes(30)
+    tb = build_toolbox(dom, sites, bn, 1500, 1e-3, 8)
+    lam, _ = cell_weights(dom, sites, 2, 1 << 18)
+
+    def uex(x):
+        return 0.8 + 0.6 * x[:, 0] - 0.5 * x[:, 1] + 0.4 * x[:, 0] * x[:, 1]
+
+    def grad(x):
+        return np.stack([0.6 + 0.4 * x[:, 1], -0.5 + 0.4 * x[:, 0]], 1)
+
+    # u_ex is harmonic, so f = -(1 + u^2) Lap u - 2 u |grad u|^2 = -2 u |grad u|^2
+    f = -2.0 * uex(sites) * np.sum(grad(sites) ** 2, 1)
+    g = uex(bn)
+    pic = L.picard_quasilinear(tb, lam, f, g, rcond=3e-2, tol=1e-12)
+    w = L.solve_linear(tb, lam, -f, g + g ** 3 / 3, rcond=3e-2)["u"]
+    u_k = _kirchhoff_inverse(w)
+    assert np.allclose(u_k + u_k ** 3 / 3, w, rtol=1e-13, atol=1e-13)
+    nrm = lambda v: np.sqrt(np.sum(lam * v * v))
+    ue = uex(sites)
+    err_p, err_k = nrm(pic["u"] - ue), nrm(u_k - ue)
+    gap = nrm(pic["u"] - u_k)
+    assert err_p < 0.05 * nrm(ue) and err_k < 0.05 * nrm(ue)
+    assert gap <= max(err_p, err_k)
+    lin = L.solve_linear(tb, lam, -f, g, rcond=3e-2)["u"]    # the coefficient dropped
+    assert nrm(lin - u_k) > 3 * max(err_p, err_k)
