@@ -94,14 +94,28 @@ typedef struct {
                                inputs, keeps the fastest for later builds, and
                                synchronises the stream once; 0: the size is chosen
                                by occupancy.  The results do not depend on it.     */
-  int32_t tally_in_hbm;     /* 1: the walker adds every tally straight into the
-                               toolbox in device memory (atomics, pre-scaled by
-                               1/N) instead of a site's rows in LDS; 0: only when
-                               a site's rows do not fit in LDS (about
-                               8 (1 + dim) n + 12 dim p bytes > 160 KiB).  In this
-                               mode the sums are in the toolbox precision and
-                               their order of addition is not fixed, so results
-                               agree with the LDS mode to rounding only.        */
+  int32_t tally_mode;       /* where the walker sums a site's tallies (wos_tally_mode):
+                               AUTO (0): LDS_ROWS when a site's rows fit in LDS
+                               (about 8 (1 + dim) m + 12 dim p bytes <= 160 KiB),
+                               else WINDOW for an FP32 toolbox with m, p <= 40960,
+                               else HBM.
+                               LDS_ROWS (1): the whole rows of A, B, H, K in LDS,
+                               written to the toolbox once per work item.
+                               WINDOW (2, FP32): the V cells and the boundary
+                               cells are numbered along a Morton curve in pages
+                               of 64; each site keeps the pages nearest to it
+                               (window_pages, window_bpages) in LDS and adds the
+                               tallies that fall elsewhere straight into the
+                               toolbox (device atomics); the columns are put back
+                               in the caller's order at the end of the build.
+                               HBM (3): every tally straight into the toolbox by
+                               device atomics, pre-scaled by 1/N.
+                               Outside LDS_ROWS the sums are in the toolbox
+                               precision and their order of addition is not
+                               fixed, so results agree with LDS_ROWS to rounding
+                               only; in WINDOW mode ties between equidistant
+                               centres go to the lower Morton rank instead of
+                               the lower index.                                 */
   int32_t sampler;          /* radial law of Y (the ball-Green density, eq. density
                                Green), d = 2: WOS_SAMPLER_MEDIAN3 (0) R the median
                                of three uniforms (Beta(2,2)) with the weight
@@ -112,7 +126,49 @@ typedef struct {
                                branch of the Lambert W function and weight 1 (the
                                same proposition), U the first of the same three
                                uniforms.  d = 3 supports only 0.                  */
+  int32_t walker_block;     /* walker workgroup size: 0 automatic (occupancy, or the
+                               autotuned size), or 256, 448, 512, 1024           */
+  int32_t tally_acc;        /* LDS_ROWS accumulators of an FP32 toolbox: 0 automatic
+                               (exact 64-bit fixed point in 2^-32 units, unless the
+                               bound of wos_build_plan.fixed_bound reaches 1/2,
+                               then FP64), 1 fixed point (WOS_EINVAL when the bound
+                               reaches 1/2), 2 FP64.  FP64 toolboxes always
+                               accumulate in FP64.                               */
+  int32_t window_pages;     /* WINDOW: pages of V cells per site in LDS (0: as many
+                               as fit 78 KiB with the boundary pages, i.e. two
+                               workgroups per compute unit)                      */
+  int32_t window_bpages;    /* WINDOW: pages of boundary cells per site in LDS
+                               (0: min(16, all))                                 */
 } wos_build_opts;
+
+enum { WOS_TALLY_AUTO = 0, WOS_TALLY_LDS_ROWS = 1, WOS_TALLY_WINDOW = 2, WOS_TALLY_HBM = 3 };
+enum { WOS_ACC_AUTO = 0, WOS_ACC_FIXED = 1, WOS_ACC_F64 = 2 };
+
+/* The decisions wos_toolbox_create takes for given inputs, computed on the
+ * host only (no device call), for callers that size or check a build before
+ * making it.  Arguments as for wos_toolbox_create_wv (vcentres NULL: V = W).
+ * fixed_bound is the largest per-item sum of |tally| that any fixed-point
+ * word can receive, as a fraction of the fixed-point range 2^31: the K sums
+ * are bounded by N_item d / r0 (|w| = d / r0 per walk), the B sums by
+ * 4 N_item (d / r0) R^2 / d and the A sums by 4 N_item omega_max R^2 / d
+ * (R the half diagonal of the bounding box, R^2 / d a bound on the mean
+ * exit time, 4 a margin for its fluctuation over the item's walks,
+ * omega_max = 12 the largest d = 2 weight with 24-bit uniforms, 1 in 3-D),
+ * r0 the smallest distance of a site to the boundary.                        */
+typedef struct {
+  int32_t tally_mode;       /* the mode used (never AUTO)                         */
+  int32_t tally_acc;        /* LDS_ROWS: WOS_ACC_FIXED or WOS_ACC_F64             */
+  int32_t walks_per_item;   /* walks one workgroup takes per site                 */
+  int32_t items_per_site;
+  int32_t window_pages;     /* WINDOW: V pages per site held in LDS              */
+  int32_t window_bpages;    /* WINDOW: boundary pages per site held in LDS       */
+  int64_t lds_bytes;        /* LDS of one walker workgroup                        */
+  double fixed_bound;       /* see above; fixed point is used only below 1/2      */
+} wos_build_plan;
+
+wos_status wos_toolbox_plan(const wos_domain* dom, const double* sites, int32_t n, const double* vcentres,
+                            int32_t m, const double* bnodes, int32_t p, const wos_build_opts* opts,
+                            wos_build_plan* out);
 
 enum { WOS_SAMPLER_MEDIAN3 = 0, WOS_SAMPLER_LAMBERT = 1 };
 
@@ -349,8 +405,8 @@ typedef struct {
   int32_t energy;       /* wos_energy                                         */
   double p_exp;         /* the exponent P > 1 (WOS_EL_PLAPLACE)               */
   double alpha;         /* Adam step size, > 0                                */
-  double beta1;         /* in [0, 1); 0 -> 0.9 (the paper's)                  */
-  double beta2;         /* in [0, 1); 0 -> 0.999 (the paper's)                */
+  double beta1;         /* in [0, 1); negative -> 0.9 (the paper's)           */
+  double beta2;         /* in [0, 1); negative -> 0.999 (the paper's)         */
   double eps;           /* > 0; 0 -> 1e-10 (the paper's)                      */
   int32_t max_iter;     /* iterations at most, > 0                            */
   double tol;           /* stop once |grad J|_lambda <= tol; 0: run max_iter   */
@@ -385,7 +441,7 @@ typedef struct {
  * energies it streams A too, with H g formed once.  u and J are formed at the end.
  * Runs on `stream` and synchronises it before returning.
  * Errors: WOS_EINVAL for a NULL pointer, an unbuilt toolbox, an unknown
- * energy, P <= 1 (WOS_EL_PLAPLACE), alpha <= 0, beta outside [0, 1), eps < 0 or
+ * energy, P <= 1 (WOS_EL_PLAPLACE), alpha <= 0, beta >= 1, eps < 0 or
  * max_iter <= 0.  The work vectors ((3d + 4) n + 4 m doubles) are allocated
  * on the first call and kept with the toolbox.  Not thread-safe for one
  * toolbox.                                                                   */

@@ -15,10 +15,11 @@ import numpy as np
 import torch
 
 from ._lib import (ENERGIES, EXPORTS, HISD_INIT, HISD_PRECOND, KINDS, PRECISION, PROBLEMS, SOLVE_PRECISION, SOLVERS,
-                   WosAdamInfo, WosAdamOpts, WosHisdInfo, WosHisdOpts, WosBuildOpts, WosCoeffs, WosOperatorInfo, WosOperatorOpts,
-                   WosDomain, WosError, WosServerOpts, WosSolveInfo, WosToolboxInfo, check, lib)
+                   TALLY_ACC, TALLY_MODES, WosAdamInfo, WosAdamOpts, WosBuildPlan, WosHisdInfo, WosHisdOpts,
+                   WosBuildOpts, WosCoeffs, WosOperatorInfo, WosOperatorOpts, WosDomain, WosError, WosServerOpts,
+                   WosSolveInfo, WosToolboxInfo, check, lib)
 
-__all__ = ["Toolbox", "Server", "build_toolbox", "WosError", "lib"]
+__all__ = ["Toolbox", "Server", "build_toolbox", "build_plan", "WosError", "lib"]
 
 
 def _stream_handle(stream=None):
@@ -47,15 +48,53 @@ def _dptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def build_opts(walks, eps, seed=0, precision="f32", max_steps=0, fixed_M=0, volume_samples=0, walks_per_item=0,
+               regen_threshold=0, autotune=True, tally="auto", sampler="median3", walker_block=0, tally_acc="auto",
+               window_pages=0, window_bpages=0):
+    """The wos_build_opts structure of include/wos.h."""
+    return WosBuildOpts(walks_per_site=int(walks), eps=float(eps), max_steps=int(max_steps),
+                        fixed_M=int(fixed_M), seed=int(seed), precision=PRECISION[precision],
+                        volume_samples=int(volume_samples), walks_per_item=int(walks_per_item),
+                        regen_threshold=int(regen_threshold), autotune=1 if autotune else 0,
+                        tally_mode=TALLY_MODES[tally], sampler={"median3": 0, "lambert": 1}[sampler],
+                        walker_block=int(walker_block), tally_acc=TALLY_ACC[tally_acc],
+                        window_pages=int(window_pages), window_bpages=int(window_bpages))
+
+
+def build_plan(domain, sites, bnodes, walks, eps, vcentres=None, **kw):
+    """The host decisions of a build (include/wos.h, wos_toolbox_plan), without
+    touching the GPU: tally mode, accumulators, work split, window, LDS bytes
+    and the fixed-point bound."""
+    sites = np.ascontiguousarray(np.asarray(sites, dtype=np.float64))
+    bnodes = np.ascontiguousarray(np.asarray(bnodes, dtype=np.float64))
+    vc = None if vcentres is None else np.ascontiguousarray(np.asarray(vcentres, dtype=np.float64))
+    dom, keep = _domain_struct(domain)
+    opts = build_opts(walks, eps, **kw)
+    plan = WosBuildPlan()
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().wos_toolbox_plan(ctypes.byref(dom), sites.ctypes.data_as(dp), sites.shape[0],
+                                 vc.ctypes.data_as(dp) if vc is not None else None,
+                                 0 if vc is None else vc.shape[0], bnodes.ctypes.data_as(dp), bnodes.shape[0],
+                                 ctypes.byref(opts), ctypes.byref(plan)))
+    del keep
+    out = {f: getattr(plan, f) for f, _ in plan._fields_}
+    out["tally_mode"] = {v: k for k, v in TALLY_MODES.items()}[out["tally_mode"]]
+    out["tally_acc"] = {v: k for k, v in TALLY_ACC.items()}[out["tally_acc"]]
+    return out
+
+
 class Toolbox:
     """A resident toolbox {x, z, A, B, H, K, lambda} on the current GPU."""
 
     def __init__(self, domain, sites, bnodes, walks, eps, seed=0, precision="f32", max_steps=0,
                  fixed_M=0, volume_samples=0, walks_per_item=0, regen_threshold=0, autotune=True,
-                 tally_in_hbm=False, vcentres=None, sampler="median3"):
+                 tally="auto", vcentres=None, sampler="median3", walker_block=0, tally_acc="auto",
+                 window_pages=0, window_bpages=0):
         """`sites` are the W centres (the walks start there, n rows); with
         `vcentres` the tally points are binned to a V partition of its own
-        (m columns; include/wos.h, wos_toolbox_create_wv), else V = W."""
+        (m columns; include/wos.h, wos_toolbox_create_wv), else V = W.
+        `tally` is the walker's tally mode ("auto", "lds_rows", "window",
+        "hbm"; include/wos.h, wos_build_opts.tally_mode)."""
         self.domain = domain
         self.sites = np.ascontiguousarray(np.asarray(sites, dtype=np.float64))
         self.vcentres = None if vcentres is None else np.ascontiguousarray(np.asarray(vcentres, dtype=np.float64))
@@ -68,12 +107,9 @@ class Toolbox:
         self.precision = precision
         self.walks = int(walks)
         dom, keep = _domain_struct(domain)
-        opts = WosBuildOpts(walks_per_site=int(walks), eps=float(eps), max_steps=int(max_steps),
-                            fixed_M=int(fixed_M), seed=self.seed, precision=PRECISION[precision],
-                            volume_samples=int(volume_samples), walks_per_item=int(walks_per_item),
-                            regen_threshold=int(regen_threshold), autotune=1 if autotune else 0,
-                            tally_in_hbm=1 if tally_in_hbm else 0,
-                            sampler={"median3": 0, "lambert": 1}[sampler])
+        opts = build_opts(walks, eps, seed, precision, max_steps, fixed_M, volume_samples, walks_per_item,
+                          regen_threshold, autotune, tally, sampler, walker_block, tally_acc, window_pages,
+                          window_bpages)
         h = ctypes.c_void_p()
         dp = ctypes.POINTER(ctypes.c_double)
         if self.vcentres is None:
@@ -192,7 +228,7 @@ class Toolbox:
                                     _dptr(x), npts, _dptr(out), _dptr(site), _stream_handle(stream)))
         return out, site
 
-    def minimize(self, f, g, p_exp, alpha, max_iter, fbar0=1.0, tol=0.0, check_every=0, beta1=0.0, beta2=0.0,
+    def minimize(self, f, g, p_exp, alpha, max_iter, fbar0=1.0, tol=0.0, check_every=0, beta1=-1.0, beta2=-1.0,
                  eps=0.0, energy="plaplace", coef_A=None, coef_c=None, coef_w=None, stream=None):
         """Adam on the discrete functional J of the Euler-Lagrange route
         (include/wos.h, wos_minimize), from the source fbar0 (a scalar for a

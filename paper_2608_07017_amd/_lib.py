@@ -32,7 +32,20 @@ class WosBuildOpts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
                 ("volume_samples", ctypes.c_int64), ("walks_per_item", ctypes.c_int32),
                 ("regen_threshold", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("tally_in_hbm", ctypes.c_int32), ("sampler", ctypes.c_int32)]
+                ("tally_mode", ctypes.c_int32), ("sampler", ctypes.c_int32),
+                ("walker_block", ctypes.c_int32), ("tally_acc", ctypes.c_int32),
+                ("window_pages", ctypes.c_int32), ("window_bpages", ctypes.c_int32)]
+
+
+class WosBuildPlan(ctypes.Structure):
+    _fields_ = [("tally_mode", ctypes.c_int32), ("tally_acc", ctypes.c_int32),
+                ("walks_per_item", ctypes.c_int32), ("items_per_site", ctypes.c_int32),
+                ("window_pages", ctypes.c_int32), ("window_bpages", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int64), ("fixed_bound", ctypes.c_double)]
+
+
+TALLY_MODES = {"auto": 0, "lds_rows": 1, "window": 2, "hbm": 3}
+TALLY_ACC = {"auto": 0, "fixed": 1, "f64": 2}
 
 
 class WosToolboxInfo(ctypes.Structure):
@@ -114,6 +127,8 @@ SIGNATURES = {
                                           ctypes.POINTER(WosBuildOpts), ctypes.POINTER(_P)]),
     "wos_toolbox_create_wv": (ctypes.c_int, [ctypes.POINTER(WosDomain), _D, ctypes.c_int32, _D, ctypes.c_int32, _D,
                                              ctypes.c_int32, ctypes.POINTER(WosBuildOpts), ctypes.POINTER(_P)]),
+    "wos_toolbox_plan": (ctypes.c_int, [ctypes.POINTER(WosDomain), _D, ctypes.c_int32, _D, ctypes.c_int32, _D,
+                                        ctypes.c_int32, ctypes.POINTER(WosBuildOpts), ctypes.POINTER(WosBuildPlan)]),
     "wos_toolbox_build": (ctypes.c_int, [_P, ctypes.c_uint64, _P]),
     "wos_build_toolbox": (ctypes.c_int, [ctypes.POINTER(WosDomain), _D, ctypes.c_int32, _D, ctypes.c_int32,
                                          ctypes.POINTER(WosBuildOpts), _P, ctypes.POINTER(_P)]),

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -14,6 +15,7 @@
 #include <vector>
 
 #include "grid.hpp"
+#include "window.hpp"
 #include "toolbox.hpp"
 #include "wos_kernels.hpp"
 
@@ -264,7 +266,8 @@ void release(wos_toolbox* tb) {
   void* ptrs[] = {tb->gv.rec, tb->gv.list, tb->gg.rec, tb->gg.list, tb->d_sites_f32,
                   tb->d_sites_f64, tb->d_bnodes, tb->d_segs, tb->d_verts, tb->d_A, tb->d_B,
                   tb->d_K, tb->d_H, tb->d_Hc, tb->d_vcount, tb->d_stats, tb->d_lambda,
-                  tb->d_item_order};
+                  tb->d_item_order, tb->gv_r.rec, tb->gv_r.list, tb->gg_r.rec, tb->gg_r.list,
+                  tb->d_vsites_r, tb->d_bnodes_r, tb->d_vrank, tb->d_brank, tb->d_win};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (tb->wv) {  // the V-side arrays are separate allocations only with a V partition of their own
@@ -288,94 +291,20 @@ bool finite3(const double* v, int k) {
     if (s_ != WOS_OK) return s_;      \
   } while (0)
 
-// Zero what a walker launch accumulates into: its statistics and, when
-// sites are split over several items (atomic flushes), the tallies.
-static wos_status zero_walker_outputs(wos_toolbox* tb, hipStream_t stream) {
-  const size_t ts = tsize(tb);
-  const size_t n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
-  WOS_HIP(hipMemsetAsync(tb->d_stats, 0, 4 * 8, stream));
-  if (tb->items_per_site != 1 || tb->global_tally) {
-    WOS_HIP(hipMemsetAsync(tb->d_A, 0, ts * n * m, stream));
-    WOS_HIP(hipMemsetAsync(tb->d_B, 0, ts * d * n * m, stream));
-    WOS_HIP(hipMemsetAsync(tb->d_K, 0, ts * d * n * p, stream));
-    WOS_HIP(hipMemsetAsync(tb->d_Hc, 0, 4 * n * p, stream));
-  }
-  return WOS_OK;
-}
+namespace {
 
-template <typename T>
-static void fill_walker_params(const wos_toolbox* tb, uint32_t k0, uint32_t k1, int block, WalkerParams<T>& P) {
-  const bool f64 = std::is_same<T, double>::value;
-  P.dom = to_dev<T>(tb->dom);
-  P.segs = static_cast<const T*>(tb->d_segs);
-  P.nseg = (int)tb->dom.verts.size() / 2;
-  P.sites = static_cast<const T*>(f64 ? tb->d_sites_f64 : tb->d_sites_f32);
-  P.gv = view<T>(tb->gv, f64 ? tb->d_vsites_f64 : tb->d_vsites_f32);
-  P.gg = view<T>(tb->gg, tb->d_bnodes);
-  P.n = tb->n;
-  P.m = tb->m;
-  P.p = tb->p;
-  P.walks = tb->opts.walks_per_site;
-  P.walks_per_item = tb->walks_per_item;
-  P.items_per_site = tb->items_per_site;
-  P.eps = (T)tb->opts.eps;
-  P.max_steps = tb->opts.max_steps;
-  P.fixed_M = tb->opts.fixed_M;
-  P.k0 = k0;
-  P.k1 = k1;
-  P.inv_N = (T)(1.0 / (double)tb->opts.walks_per_site);
-  P.regen_T = tb->regen_T;
-  P.block_override = block;
-  P.item_order = tb->d_item_order;
-  P.direct_store = tb->items_per_site == 1 ? 1 : 0;
-  P.global_tally = tb->global_tally ? 1 : 0;
-  P.exact_radius = tb->opts.sampler == WOS_SAMPLER_LAMBERT ? 1 : 0;
-  P.acc_fixed = f64 ? 0 : tb->acc_fixed;  // FP64 toolboxes accumulate in FP64
-  P.A = static_cast<T*>(tb->d_A);
-  P.B = static_cast<T*>(tb->d_B);
-  P.Hc = tb->d_Hc;
-  P.K = static_cast<T*>(tb->d_K);
-  P.stats = tb->d_stats;
-}
+std::atomic<uint64_t> g_next_uid{1};
 
-static wos_status launch_walker(const wos_toolbox* tb, uint32_t k0, uint32_t k1, int block, hipStream_t stream) {
-  const int items = tb->items_per_site * tb->n;
-  if (tb->f64) {
-    WalkerParams<double> P{};
-    fill_walker_params<double>(tb, k0, k1, block, P);
-    WOS_HIP(launch_walker_f64(P, tb->dim, tb->dom.kind, items, stream));
-  } else {
-    WalkerParams<float> P{};
-    fill_walker_params<float>(tb, k0, k1, block, P);
-    WOS_HIP(launch_walker_f32(P, tb->dim, tb->dom.kind, items, stream));
-  }
-  return WOS_OK;
-}
-
-extern "C" {
-
-const char* wos_last_error(void) { return g_err.c_str(); }
-
-const char* wos_version(void) { return "libwos 0.1 (gfx950)"; }
-
-wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_t n,
-                              const double* bnodes, int32_t p, const wos_build_opts* opts,
-                              wos_toolbox** out) {
-  return wos_toolbox_create_wv(dom, sites, n, nullptr, 0, bnodes, p, opts, out);
-}
-
-wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int32_t n, const double* vcentres,
-                                 int32_t m, const double* bnodes, int32_t p, const wos_build_opts* opts,
-                                 wos_toolbox** out) {
-  g_err.clear();
-  if (!out) return fail(WOS_EINVAL, "out is NULL");
-  *out = nullptr;
+// Validation shared by wos_toolbox_create_wv and wos_toolbox_plan: fills the
+// host domain and the column count (*m = n without a V partition).
+wos_status validate_inputs(const wos_domain* dom, const double* sites, int32_t n, const double* vcentres,
+                           int32_t* m, const double* bnodes, int32_t p, const wos_build_opts* opts, HostDomain* out) {
   if (!dom || !sites || !bnodes || !opts) return fail(WOS_EINVAL, "NULL argument");
   if (dom->dim != 2 && dom->dim != 3) return fail(WOS_EINVAL, "dim must be 2 or 3");
   if (n < 1 || p < 1) return fail(WOS_EINVAL, "need n >= 1 and p >= 1 (n=%d, p=%d)", n, p);
   const bool wv = vcentres != nullptr;
-  if (!wv) m = n;
-  if (m < 1) return fail(WOS_EINVAL, "need m >= 1 V centres (m=%d)", m);
+  if (!wv) *m = n;
+  if (*m < 1) return fail(WOS_EINVAL, "need m >= 1 V centres (m=%d)", *m);
   if (opts->walks_per_site < 1 || opts->walks_per_site > (int64_t)INT32_MAX)
     return fail(WOS_EINVAL, "walks_per_site must be in [1, 2^31)");
   if (opts->fixed_M < 0) return fail(WOS_EINVAL, "fixed_M must be >= 0");
@@ -392,8 +321,17 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
     return fail(WOS_EINVAL, "unknown sampler %d", opts->sampler);
   if (opts->sampler == WOS_SAMPLER_LAMBERT && dom->dim != 2)
     return fail(WOS_EINVAL, "the Lambert W sampler is for d = 2");
+  if (opts->tally_mode < WOS_TALLY_AUTO || opts->tally_mode > WOS_TALLY_HBM)
+    return fail(WOS_EINVAL, "unknown tally_mode %d", opts->tally_mode);
+  if (opts->tally_acc < WOS_ACC_AUTO || opts->tally_acc > WOS_ACC_F64)
+    return fail(WOS_EINVAL, "unknown tally_acc %d", opts->tally_acc);
+  if (opts->walker_block != 0 && opts->walker_block != 256 && opts->walker_block != 448 &&
+      opts->walker_block != 512 && opts->walker_block != 1024)
+    return fail(WOS_EINVAL, "walker_block must be 0, 256, 448, 512 or 1024");
+  if (opts->window_pages < 0 || opts->window_pages > 255 || opts->window_bpages < 0 || opts->window_bpages > 255)
+    return fail(WOS_EINVAL, "window_pages and window_bpages must be in [0, 255]");
 
-  HostDomain hd;
+  HostDomain& hd = *out;
   hd.kind = dom->kind;
   hd.dim = dom->dim;
   for (int a = 0; a < 3; ++a) {
@@ -445,14 +383,242 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
   for (int j = 0; j < p; ++j)
     if (!finite3(bnodes + (size_t)j * d, d)) return fail(WOS_EINVAL, "boundary node %d is not finite", j);
   if (wv)
-    for (int j = 0; j < m; ++j) {
+    for (int j = 0; j < *m; ++j) {
       const double* y = vcentres + (size_t)j * d;
       if (!finite3(y, d)) return fail(WOS_EINVAL, "V centre %d is not finite", j);
       if (!host_inside(hd, y)) return fail(WOS_EDOMAIN, "V centre %d is not inside the domain", j);
     }
+  return WOS_OK;
+}
+
+// The host decisions of a build: tally mode, accumulators, work split and
+// window size.
+struct Plan {
+  int mode = WOS_TALLY_LDS_ROWS, acc = WOS_ACC_FIXED;
+  int wpi = 1, ips = 1, pc = 0, pb = 0;
+  size_t lds = 0;
+  double fixed_bound = 0;
+};
+
+constexpr size_t kLdsBytes = 160 * 1024;
+constexpr size_t kWindowBudget = 78 * 1024;  // two walker workgroups per compute unit
+
+wos_status make_plan(const HostDomain& hd, const double* sites, int n, int m, int p, const wos_build_opts* o,
+                     Plan* pl) {
+  const int d = hd.dim;
+  const bool f64 = o->precision == WOS_F64;
+  const int nseg = hd.kind == WOS_POLYGON ? (int)hd.verts.size() / 2 : 0;
+  const size_t lds_rows = walker_lds_bytes(d, m, p, nseg, f64);
+  const bool rows_fit = lds_rows <= kLdsBytes;
+  const bool win_ok = !f64 && (size_t)m <= permute_max_cols() && (size_t)p <= permute_max_cols();
+  int mode = o->tally_mode;
+  if (mode == WOS_TALLY_AUTO) mode = rows_fit ? WOS_TALLY_LDS_ROWS : win_ok ? WOS_TALLY_WINDOW : WOS_TALLY_HBM;
+  if (mode == WOS_TALLY_LDS_ROWS && !rows_fit)
+    return fail(WOS_EINVAL, "tally_mode LDS_ROWS: a site's rows take %zu bytes of LDS (at most %zu)", lds_rows,
+                kLdsBytes);
+  if (mode == WOS_TALLY_WINDOW && !win_ok)
+    return fail(WOS_EINVAL, "tally_mode WINDOW needs an FP32 toolbox with m, p <= %zu", permute_max_cols());
+  pl->mode = mode;
+
+  const int npv = (m + kPage - 1) / kPage, npb = (p + kPage - 1) / kPage;
+  size_t lds = 0;
+  if (mode == WOS_TALLY_WINDOW) {
+    int pb = o->window_bpages > 0 ? o->window_bpages : 16;
+    pb = std::max(1, std::min(pb, npb));
+    int pc = o->window_pages;
+    if (pc <= 0) {
+      const size_t per_page = 4 * (size_t)(1 + d) * kPage;
+      const size_t fixed = walker_window_lds_bytes(d, 0, pb, npv, npb, nseg) + 2 * 255;
+      pc = fixed < kWindowBudget ? (int)((kWindowBudget - fixed) / per_page) : 1;
+    }
+    pc = std::max(1, std::min(pc, std::min(npv, 255)));
+    pl->pc = pc;
+    pl->pb = pb;
+    lds = walker_window_lds_bytes(d, pc, pb, npv, npb, nseg);
+    if (lds > kLdsBytes)
+      return fail(WOS_EINVAL, "window of %d + %d pages takes %zu bytes of LDS (at most %zu)", pc, pb, lds, kLdsBytes);
+  } else if (mode == WOS_TALLY_HBM) {
+    lds = (f64 ? 8 : 4) * (5 * (size_t)nseg);
+  } else {
+    lds = lds_rows;
+  }
+  pl->lds = lds;
+
+  // work split: about one (site, chunk) item per workgroup slot of the chip
+  const int64_t N = o->walks_per_site;
+  int64_t wpi;
+  if (o->walks_per_item > 0) {
+    wpi = std::min<int64_t>(o->walks_per_item, N);
+  } else if (mode == WOS_TALLY_HBM) {
+    // every tally goes to the toolbox in memory: split every site into items
+    // of a few walks per lane, dispatched site after site, so that the rows
+    // being written at any time are few and stay in the caches
+    wpi = std::min<int64_t>(N, 4096);
+  } else {
+    const int bs = walker_block_size(lds);
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(kLdsBytes / std::max<size_t>(lds, 1), 2048 / bs));
+    const int64_t slots = 256 * per_cu;
+    const int64_t ips = std::max<int64_t>(1, 2 * slots / n);
+    const int64_t floor_w = std::min<int64_t>(N, 4 * (int64_t)bs);  // >= 4 walks per lane
+    wpi = std::max<int64_t>((N + ips - 1) / ips, floor_w);
+  }
+  pl->wpi = (int)wpi;
+  pl->ips = (int)((N + wpi - 1) / wpi);
+  if ((int64_t)pl->ips * n > (int64_t)INT32_MAX) return fail(WOS_EINVAL, "too many work items");
+
+  // bound on the per-item sums a fixed-point word receives (see wos.h)
+  double lo[3], hi[3];
+  host_bbox(hd, lo, hi);
+  double R2 = 0;
+  for (int a = 0; a < d; ++a) R2 += 0.25 * (hi[a] - lo[a]) * (hi[a] - lo[a]);
+  double r0min = 1e300;
+  for (int i = 0; i < n; ++i) r0min = std::min(r0min, host_distance(hd, sites + (size_t)i * d));
+  const double om_max = (d == 2 && o->sampler == WOS_SAMPLER_MEDIAN3) ? 12.0 : 1.0;
+  const double Ni = (double)wpi;
+  const double bK = Ni * d / r0min;
+  const double bB = 4.0 * Ni * (d / r0min) * R2 / d;
+  const double bA = 4.0 * Ni * om_max * R2 / d;
+  pl->fixed_bound = std::max(bK, std::max(bB, bA)) / 2147483648.0;
+  if (f64 || mode != WOS_TALLY_LDS_ROWS) {
+    pl->acc = f64 ? WOS_ACC_F64 : WOS_ACC_AUTO;
+  } else if (o->tally_acc == WOS_ACC_F64) {
+    pl->acc = WOS_ACC_F64;
+  } else if (pl->fixed_bound >= 0.5) {
+    if (o->tally_acc == WOS_ACC_FIXED)
+      return fail(WOS_EINVAL, "fixed-point tallies could overflow (bound %.3g of the range)", pl->fixed_bound);
+    pl->acc = WOS_ACC_F64;
+  } else {
+    pl->acc = WOS_ACC_FIXED;
+  }
+  return WOS_OK;
+}
+
+}  // namespace
+
+// Zero what a walker launch accumulates into: its statistics and, when
+// sites are split over several items (atomic flushes), the tallies.
+static wos_status zero_walker_outputs(wos_toolbox* tb, hipStream_t stream) {
+  const size_t ts = tsize(tb);
+  const size_t n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
+  WOS_HIP(hipMemsetAsync(tb->d_stats, 0, 4 * 8, stream));
+  if (tb->items_per_site != 1 || tb->global_tally) {
+    WOS_HIP(hipMemsetAsync(tb->d_A, 0, ts * n * m, stream));
+    WOS_HIP(hipMemsetAsync(tb->d_B, 0, ts * d * n * m, stream));
+    WOS_HIP(hipMemsetAsync(tb->d_K, 0, ts * d * n * p, stream));
+    WOS_HIP(hipMemsetAsync(tb->d_Hc, 0, 4 * n * p, stream));
+  }
+  return WOS_OK;
+}
+
+template <typename T>
+static void fill_walker_params(const wos_toolbox* tb, uint32_t k0, uint32_t k1, int block, WalkerParams<T>& P) {
+  const bool f64 = std::is_same<T, double>::value;
+  P.dom = to_dev<T>(tb->dom);
+  P.segs = static_cast<const T*>(tb->d_segs);
+  P.nseg = (int)tb->dom.verts.size() / 2;
+  P.sites = static_cast<const T*>(f64 ? tb->d_sites_f64 : tb->d_sites_f32);
+  P.gv = view<T>(tb->gv, f64 ? tb->d_vsites_f64 : tb->d_vsites_f32);
+  P.gg = view<T>(tb->gg, tb->d_bnodes);
+  P.n = tb->n;
+  P.m = tb->m;
+  P.p = tb->p;
+  P.walks = tb->opts.walks_per_site;
+  P.walks_per_item = tb->walks_per_item;
+  P.items_per_site = tb->items_per_site;
+  P.eps = (T)tb->opts.eps;
+  P.max_steps = tb->opts.max_steps;
+  P.fixed_M = tb->opts.fixed_M;
+  P.k0 = k0;
+  P.k1 = k1;
+  P.inv_N = (T)(1.0 / (double)tb->opts.walks_per_site);
+  P.regen_T = tb->regen_T;
+  P.block_override = block;
+  P.item_order = tb->d_item_order;
+  P.direct_store = tb->items_per_site == 1 ? 1 : 0;
+  P.global_tally = tb->global_tally ? 1 : 0;
+  P.window = tb->tally_mode == WOS_TALLY_WINDOW ? 1 : 0;
+  if (P.window) {
+    // the walker's columns are Morton ranks: grids over the ranked centres
+    P.gv = view<T>(tb->gv_r, tb->d_vsites_r);
+    P.gg = view<T>(tb->gg_r, tb->d_bnodes_r);
+    P.win = tb->d_win;
+    P.win_pc = tb->win_pc;
+    P.win_pb = tb->win_pb;
+    P.npv = (tb->m + kPage - 1) / kPage;
+    P.npb = (tb->p + kPage - 1) / kPage;
+  }
+  P.exact_radius = tb->opts.sampler == WOS_SAMPLER_LAMBERT ? 1 : 0;
+  P.acc_fixed = f64 ? 0 : tb->acc_fixed;  // FP64 toolboxes accumulate in FP64
+  P.A = static_cast<T*>(tb->d_A);
+  P.B = static_cast<T*>(tb->d_B);
+  P.Hc = tb->d_Hc;
+  P.K = static_cast<T*>(tb->d_K);
+  P.stats = tb->d_stats;
+}
+
+static wos_status launch_walker(const wos_toolbox* tb, uint32_t k0, uint32_t k1, int block, hipStream_t stream) {
+  const int items = tb->items_per_site * tb->n;
+  if (tb->f64) {
+    WalkerParams<double> P{};
+    fill_walker_params<double>(tb, k0, k1, block, P);
+    WOS_HIP(launch_walker_f64(P, tb->dim, tb->dom.kind, items, stream));
+  } else {
+    WalkerParams<float> P{};
+    fill_walker_params<float>(tb, k0, k1, block, P);
+    WOS_HIP(launch_walker_f32(P, tb->dim, tb->dom.kind, items, stream));
+  }
+  return WOS_OK;
+}
+
+extern "C" {
+
+const char* wos_last_error(void) { return g_err.c_str(); }
+
+const char* wos_version(void) { return "libwos 0.1 (gfx950)"; }
+
+wos_status wos_toolbox_create(const wos_domain* dom, const double* sites, int32_t n,
+                              const double* bnodes, int32_t p, const wos_build_opts* opts,
+                              wos_toolbox** out) {
+  return wos_toolbox_create_wv(dom, sites, n, nullptr, 0, bnodes, p, opts, out);
+}
+
+wos_status wos_toolbox_plan(const wos_domain* dom, const double* sites, int32_t n, const double* vcentres,
+                            int32_t m, const double* bnodes, int32_t p, const wos_build_opts* opts,
+                            wos_build_plan* out) {
+  g_err.clear();
+  if (!out) return fail(WOS_EINVAL, "out is NULL");
+  std::memset(out, 0, sizeof *out);
+  HostDomain hd;
+  WOS_TRY(validate_inputs(dom, sites, n, vcentres, &m, bnodes, p, opts, &hd));
+  Plan pl;
+  WOS_TRY(make_plan(hd, sites, n, m, p, opts, &pl));
+  out->tally_mode = pl.mode;
+  out->tally_acc = pl.acc;
+  out->walks_per_item = pl.wpi;
+  out->items_per_site = pl.ips;
+  out->window_pages = pl.pc;
+  out->window_bpages = pl.pb;
+  out->lds_bytes = (int64_t)pl.lds;
+  out->fixed_bound = pl.fixed_bound;
+  return WOS_OK;
+}
+
+wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int32_t n, const double* vcentres,
+                                 int32_t m, const double* bnodes, int32_t p, const wos_build_opts* opts,
+                                 wos_toolbox** out) {
+  g_err.clear();
+  if (!out) return fail(WOS_EINVAL, "out is NULL");
+  *out = nullptr;
+  HostDomain hd;
+  WOS_TRY(validate_inputs(dom, sites, n, vcentres, &m, bnodes, p, opts, &hd));
+  Plan pl;
+  WOS_TRY(make_plan(hd, sites, n, m, p, opts, &pl));
+  const bool wv = vcentres != nullptr;
+  const int d = dom->dim;
 
   wos_toolbox* tb = new (std::nothrow) wos_toolbox();
   if (!tb) return fail(WOS_ENOMEM, "host allocation failed");
+  tb->uid = g_next_uid.fetch_add(1);
   tb->dom = hd;
   tb->opts = *opts;
   tb->dim = d;
@@ -467,51 +633,24 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
   if (tb->opts.max_steps == 0) tb->opts.max_steps = kDefaultMaxSteps;
   if (tb->opts.volume_samples == 0) tb->opts.volume_samples = (int64_t)1 << 24;
   tb->regen_T = tb->opts.regen_threshold ? tb->opts.regen_threshold : 48;
-
+  tb->tally_mode = pl.mode;
+  tb->global_tally = pl.mode == WOS_TALLY_HBM || pl.mode == WOS_TALLY_WINDOW;
+  tb->acc_fixed = pl.acc == WOS_ACC_FIXED ? 1 : 0;
+  tb->walks_per_item = pl.wpi;
+  tb->items_per_site = pl.ips;
+  tb->win_pc = pl.pc;
+  tb->win_pb = pl.pb;
+  tb->autotune = opts->autotune != 0;
+  tb->walker_block = opts->walker_block;
   const int nseg = hd.kind == WOS_POLYGON ? dom->nvert : 0;
-  // a site's rows are tallied in LDS when they fit, else straight into the
-  // toolbox in device memory
-  const size_t lds_rows = walker_lds_bytes(d, m, p, nseg, tb->f64);
-  tb->global_tally = opts->tally_in_hbm != 0 || lds_rows > 160 * 1024;
-  const size_t lds = tb->global_tally ? (tb->f64 ? 8 : 4) * (5 * (size_t)nseg + 4 * (size_t)m) : lds_rows;
-
-  // work split: about one (site, chunk) item per workgroup slot of the chip
-  const int64_t N = opts->walks_per_site;
-  if (opts->walks_per_item > 0) {
-    tb->walks_per_item = (int)std::min<int64_t>(opts->walks_per_item, N);
-  } else if (tb->global_tally) {
-    // tallies go to the toolbox in memory: split every site into items of
-    // a few walks per lane, dispatched site after site, so that the rows
-    // being written at any time are few and stay in the caches
-    tb->walks_per_item = (int)std::min<int64_t>(N, 4096);
-  } else {
-    const int bs = walker_block_size(lds);
-    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(160 * 1024 / std::max<size_t>(lds, 1), 2048 / bs));
-    const int64_t slots = 256 * per_cu;
-    const int64_t ips = std::max<int64_t>(1, 2 * slots / n);
-    const int64_t floor_w = std::min<int64_t>(N, 4 * (int64_t)bs);  // >= 4 walks per lane
-    tb->walks_per_item = (int)std::max<int64_t>((N + ips - 1) / ips, floor_w);
-  }
-  {
-    tb->autotune = opts->autotune != 0;
-    const char* wb = std::getenv("WOS_WALKER_BLOCK");  // fixed workgroup size, for tuning studies
-    if (wb) tb->walker_block = std::atoi(wb);
-    const char* e = std::getenv("WOS_TALLY");
-    tb->acc_fixed = (e && std::strcmp(e, "f64") == 0) ? 0 : 1;
-  }
-  tb->items_per_site = (int)((N + tb->walks_per_item - 1) / tb->walks_per_item);
-  if ((int64_t)tb->items_per_site * n > (int64_t)INT32_MAX) {
-    delete tb;
-    return fail(WOS_EINVAL, "too many work items");
-  }
 
   // nearest-centre grids
   double lo[3], hi[3];
   host_bbox(hd, lo, hi);
   double vol = 1;
   for (int a = 0; a < d; ++a) vol *= (hi[a] - lo[a]);
-  const double sp_v = std::pow(vol / m, 1.0 / d);
-  GridHost gvh = build_grid(tb->vsites.data(), m, d, lo, hi, sp_v / (d == 2 ? 8.0 : 4.0), 1 << 24);
+  const double h_v = std::pow(vol / m, 1.0 / d) / (d == 2 ? 8.0 : 4.0);
+  GridHost gvh = build_grid(tb->vsites.data(), m, d, lo, hi, h_v, 1 << 24);
   GridHost gwh;
   if (wv) gwh = build_grid(sites, n, d, lo, hi, std::pow(vol / n, 1.0 / d) / (d == 2 ? 8.0 : 4.0), 1 << 24);
   const double bm = host_boundary_measure(hd);
@@ -529,19 +668,35 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
     }                   \
   } while (0)
   {
-    // items in order of decreasing expected work: walks from sites far from
-    // the boundary take more steps
-    std::vector<int> site_rank(n);
-    std::vector<double> r0(n);
-    for (int i = 0; i < n; ++i) {
-      site_rank[i] = i;
-      r0[i] = host_distance(hd, sites + (size_t)i * d);
-    }
-    std::stable_sort(site_rank.begin(), site_rank.end(), [&](int a, int b) { return r0[a] > r0[b]; });
     std::vector<int> order;
     order.reserve((size_t)n * tb->items_per_site);
-    for (int i : site_rank)
-      for (int c = 0; c < tb->items_per_site; ++c) order.push_back(i * tb->items_per_site + c);
+    if (pl.mode == WOS_TALLY_WINDOW) {
+      // items of sites in Morton order, in eight contiguous runs dealt to
+      // the workgroup slots round-robin (workgroup b runs on accelerator
+      // die b mod 8, so each die walks one compact part of the domain and
+      // its L2 holds that part's grid records and toolbox rows)
+      std::vector<int> so = morton_order(sites, n, d, lo, hi);
+      std::vector<int> items;
+      items.reserve(order.capacity());
+      for (int i : so)
+        for (int c = 0; c < tb->items_per_site; ++c) items.push_back(i * tb->items_per_site + c);
+      const size_t T = items.size(), run = (T + 7) / 8;
+      for (size_t k = 0; k < run; ++k)
+        for (size_t x = 0; x < 8; ++x)
+          if (x * run + k < T && k < run) order.push_back(items[x * run + k]);
+    } else {
+      // items in order of decreasing expected work: walks from sites far
+      // from the boundary take more steps
+      std::vector<int> site_rank(n);
+      std::vector<double> r0(n);
+      for (int i = 0; i < n; ++i) {
+        site_rank[i] = i;
+        r0[i] = host_distance(hd, sites + (size_t)i * d);
+      }
+      std::stable_sort(site_rank.begin(), site_rank.end(), [&](int a, int b) { return r0[a] > r0[b]; });
+      for (int i : site_rank)
+        for (int c = 0; c < tb->items_per_site; ++c) order.push_back(i * tb->items_per_site + c);
+    }
     TRY(upload(tb, (void**)&tb->d_item_order, order.data(), order.size() * sizeof(int)));
   }
   TRY(upload_grid(tb, gvh, &tb->gv));
@@ -571,6 +726,43 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
       auto b = padded<float>(tb->bnodes, p, d);
       TRY(upload(tb, &tb->d_bnodes, b.data(), b.size() * 4));
     }
+  }
+  if (pl.mode == WOS_TALLY_WINDOW) {
+    // V centres and boundary nodes ranked along a Morton curve, their grids
+    // (records hold ranks), the caller index -> rank maps for the final
+    // permutation, and each site's nearest pages
+    const std::vector<int> vo = morton_order(tb->vsites.data(), m, d, lo, hi);
+    const std::vector<int> bo = morton_order(bnodes, p, d, lo, hi);
+    std::vector<double> vs((size_t)m * d), bs((size_t)p * d);
+    std::vector<int> vr(m), br(p);
+    for (int r = 0; r < m; ++r) {
+      vr[vo[r]] = r;
+      for (int a = 0; a < d; ++a) vs[(size_t)r * d + a] = tb->vsites[(size_t)vo[r] * d + a];
+    }
+    for (int r = 0; r < p; ++r) {
+      br[bo[r]] = r;
+      for (int a = 0; a < d; ++a) bs[(size_t)r * d + a] = bnodes[(size_t)bo[r] * d + a];
+    }
+    GridHost gvr = build_grid(vs.data(), m, d, lo, hi, h_v, 1 << 24);
+    GridHost ggr = build_grid(bs.data(), p, d, lo, hi, sp_b / 4.0, 1 << 23);
+    TRY(upload_grid(tb, gvr, &tb->gv_r));
+    TRY(upload_grid(tb, ggr, &tb->gg_r));
+    auto v32 = padded<float>(vs, m, d);
+    auto b32 = padded<float>(bs, p, d);
+    TRY(upload(tb, &tb->d_vsites_r, v32.data(), v32.size() * 4));
+    TRY(upload(tb, &tb->d_bnodes_r, b32.data(), b32.size() * 4));
+    TRY(upload(tb, (void**)&tb->d_vrank, vr.data(), vr.size() * sizeof(int)));
+    TRY(upload(tb, (void**)&tb->d_brank, br.data(), br.size() * sizeof(int)));
+    const std::vector<uint16_t> pv = nearest_pages(sites, n, vs.data(), m, d, pl.pc);
+    const std::vector<uint16_t> pg = nearest_pages(sites, n, bs.data(), p, d, pl.pb);
+    std::vector<uint16_t> win((size_t)n * (pl.pc + pl.pb));
+    for (int i = 0; i < n; ++i) {
+      std::copy(pv.begin() + (size_t)i * pl.pc, pv.begin() + (size_t)(i + 1) * pl.pc,
+                win.begin() + (size_t)i * (pl.pc + pl.pb));
+      std::copy(pg.begin() + (size_t)i * pl.pb, pg.begin() + (size_t)(i + 1) * pl.pb,
+                win.begin() + (size_t)i * (pl.pc + pl.pb) + pl.pc);
+    }
+    TRY(upload(tb, (void**)&tb->d_win, win.data(), win.size() * sizeof(uint16_t)));
   }
   {
     std::vector<double> seg(5 * std::max(nseg, 1), 0.0);
@@ -621,12 +813,15 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
   hipStream_t stream = static_cast<hipStream_t>(stream_);
   const int d = tb->dim, n = tb->n, m = tb->m, p = tb->p;
   const size_t ts = tsize(tb);
-  const bool direct = tb->items_per_site == 1;
+  // the walker adds into the toolbox (rather than storing its rows) when a
+  // site is split over several items or its tallies reach the toolbox by
+  // device atomics
+  const bool accumulate = tb->items_per_site != 1 || tb->global_tally;
   const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFull), k1 = (uint32_t)(seed >> 32);
 
   WOS_HIP(hipMemsetAsync(tb->d_stats, 0, 8 * 8, stream));
   WOS_HIP(hipMemsetAsync(tb->d_vcount, 0, 8 * (size_t)n, stream));
-  if (!direct) {
+  if (accumulate) {
     WOS_HIP(hipMemsetAsync(tb->d_A, 0, ts * (size_t)n * m, stream));
     WOS_HIP(hipMemsetAsync(tb->d_B, 0, ts * (size_t)d * n * m, stream));
     WOS_HIP(hipMemsetAsync(tb->d_K, 0, ts * (size_t)d * n * p, stream));
@@ -703,6 +898,13 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
   }
   WOS_TRY(launch_walker(tb, k0, k1, tb->walker_block, stream));
   if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[2], stream));
+  if (tb->tally_mode == WOS_TALLY_WINDOW) {
+    // columns from Morton ranks back to the caller's order
+    WOS_HIP(launch_permute_cols(tb->d_A, n, m, tb->d_vrank, stream));
+    WOS_HIP(launch_permute_cols(tb->d_B, d * n, m, tb->d_vrank, stream));
+    WOS_HIP(launch_permute_cols(tb->d_K, d * n, p, tb->d_brank, stream));
+    WOS_HIP(launch_permute_cols(tb->d_Hc, n, p, tb->d_brank, stream));
+  }
   if (tb->f64)
     WOS_HIP(launch_h_from_counts_f64(tb->d_Hc, (size_t)n * p, 1.0 / (double)tb->opts.walks_per_site,
                                      static_cast<double*>(tb->d_H), stream));

@@ -56,6 +56,7 @@ wos_status sv_fail(wos_status s, const char* fmt, ...) {
 struct Request {
   uint64_t id = 0;
   wos_toolbox* tb = nullptr;
+  uint64_t tb_uid = 0;               // the toolbox's unique id (workspace caches key on it)
   const wos_operator* op = nullptr;  // operator request (tb unused)
   wos_coeffs co{};
   const double* f = nullptr;
@@ -106,7 +107,9 @@ void wos_server::worker_loop(int slot) {
   (void)hipSetDevice(device);
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
-  std::map<wos_toolbox*, std::pair<SolveWork, size_t>> ws;  // workspace and its reserved bytes
+  // workspace and its reserved bytes, by toolbox id (not by address: a freed
+  // toolbox's address can be reused by a new one of another shape)
+  std::map<uint64_t, std::pair<SolveWork, size_t>> ws;
   auto evict_all = [&](std::unique_lock<std::mutex>& lk) {
     (void)lk;
     for (auto& kv : ws) {
@@ -163,7 +166,7 @@ void wos_server::worker_loop(int slot) {
       continue;
     }
     // admission by memory
-    if (ws.find(r->tb) == ws.end()) {
+    if (ws.find(r->tb_uid) == ws.end()) {
       const size_t need = workspace_bytes(r->tb);
       if (budget && reserved + need > budget) evict_all(lk);
       bool gave_up = false;
@@ -189,12 +192,12 @@ void wos_server::worker_loop(int slot) {
         continue;
       }
       reserved += need;
-      ws[r->tb] = std::make_pair(SolveWork(), need);
+      ws[r->tb_uid] = std::make_pair(SolveWork(), need);
     } else {
       queue.pop_front();
     }
     if (!queue.empty()) cv_work.notify_one();
-    SolveWork& w = ws[r->tb].first;
+    SolveWork& w = ws[r->tb_uid].first;
     r->t_start = now_s();
     lk.unlock();
     wos_status s = solve_request(r->tb, w, &r->co, r->f, r->g, r->u, r->grad_u, nullptr, &r->info, st);
@@ -255,6 +258,7 @@ wos_status wos_server_submit(wos_server* sv, wos_toolbox* tb, const wos_coeffs* 
   std::unique_ptr<Request> r(new (std::nothrow) Request());
   if (!r) return sv_fail(WOS_ENOMEM, "out of host memory");
   r->tb = tb;
+  r->tb_uid = tb->uid;
   r->co = *co;
   r->f = f;
   r->g = g;

@@ -62,7 +62,19 @@ wos_status walloc(SolveWork& w, P** p, size_t count) {
   return WOS_OK;
 }
 
+// A workspace is sized for one toolbox shape; one that was sized for another
+// shape (a server slot that served another toolbox) is emptied first, and
+// every buffer is then allocated again on demand.
+void fit_work(wos_toolbox* tb, SolveWork& w) {
+  if (w.bytes > 0 && (w.n != tb->n || w.m != tb->m || w.p != tb->p || w.d != tb->dim)) free_work(w);
+  w.n = tb->n;
+  w.m = tb->m;
+  w.p = tb->p;
+  w.d = tb->dim;
+}
+
 wos_status ensure_work(wos_toolbox* tb, SolveWork& w) {
+  fit_work(tb, w);
   if (w.ready) return WOS_OK;
   const size_t n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
   w.M = (int)(m + (m & 1));
@@ -528,6 +540,7 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
                          double* u, double* grad_u, double* q_out, wos_solve_info* info, hipStream_t st) {
   if (!tb || !co || !f || !g || !u) return sfail(WOS_EINVAL, "NULL argument");
   if (!tb->built) return sfail(WOS_EINVAL, "toolbox has not been built");
+  fit_work(tb, w);
   if (tb->n != tb->m && co->kind != WOS_LINEAR)
     return sfail(WOS_EINVAL, "only LINEAR solves are supported on a toolbox with a separate V partition");
   const double rcond = co->rcond > 0 ? co->rcond : 1e-3;
@@ -760,12 +773,14 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
                             double* fbar, double* u, double* grad_u, wos_adam_info* info, hipStream_t st) {
   if (!o || !f || !g || !fbar || !u) return sfail(WOS_EINVAL, "NULL argument");
   if (!tb->built) return sfail(WOS_EINVAL, "toolbox has not been built");
+  fit_work(tb, w);
   const int kind = o->energy;
   wos_status s;
   if ((s = check_energy(kind, o->p_exp)) != WOS_OK) return s;
   const double P = kind == WOS_EL_PLAPLACE ? o->p_exp : 2.0;
-  const double b1 = o->beta1 > 0 ? o->beta1 : 0.9;
-  const double b2 = o->beta2 > 0 ? o->beta2 : 0.999;
+  // a negative beta asks for the paper's value; 0 is a valid choice
+  const double b1 = o->beta1 < 0 ? 0.9 : o->beta1;
+  const double b2 = o->beta2 < 0 ? 0.999 : o->beta2;
   const double eps = o->eps > 0 ? o->eps : 1e-10;
   const int check = o->check_every > 0 ? o->check_every : 50;
   if (!(o->alpha > 0.0)) return sfail(WOS_EINVAL, "alpha must be > 0");
@@ -885,6 +900,7 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
                           double* fbar, double* V, double* u, double* grad_u, wos_hisd_info* info, hipStream_t st) {
   if (!o || !f || !g || !fbar || !V || !u) return sfail(WOS_EINVAL, "NULL argument");
   if (!tb->built) return sfail(WOS_EINVAL, "toolbox has not been built");
+  fit_work(tb, w);
   const int kind = o->energy;
   wos_status s;
   if ((s = check_energy(kind, o->p_exp)) != WOS_OK) return s;

@@ -32,6 +32,7 @@ struct DevGrid {
 // toolbox (sizes depend only on n, m, p, d).
 struct SolveWork {
   bool ready = false;
+  int n = 0, m = 0, p = 0, d = 0;  // the toolbox shape the buffers were sized for
   int M = 0;  // m rounded up to even (Jacobi pairs)
   double* R = nullptr;      // (d+1) n x (m+p) weighted rows
   double* Lam = nullptr;    // m x m
@@ -81,6 +82,7 @@ void free_work(SolveWork& w);
 }  // namespace wos
 
 struct wos_toolbox {
+  uint64_t uid = 0;  // unique per toolbox object of the process (workspace caches key on it)
   wos::SolveWork sw;
   wos::HostDomain dom;
   wos_build_opts opts{};
@@ -90,8 +92,18 @@ struct wos_toolbox {
   int walker_block = 0;  // walker workgroup size (0: by occupancy, or tuned at the first build)
   bool autotune = false;
   int acc_fixed = 1;
-  bool global_tally = false;  // tallies by atomics into the toolbox (rows too large for LDS, or asked for)
+  int tally_mode = WOS_TALLY_LDS_ROWS;  // wos_tally_mode in use (never AUTO)
+  bool global_tally = false;  // HBM or WINDOW: tallies reach the toolbox by device atomics
   int* d_item_order = nullptr;
+  // windowed tally mode: V centres and boundary nodes ranked along a Morton
+  // curve (the walker's columns are ranks until the final permutation)
+  int win_pc = 0, win_pb = 0;    // pages of V cells / boundary cells per site in LDS
+  wos::DevGrid gv_r, gg_r;       // grids over the ranked V centres / boundary nodes
+  void* d_vsites_r = nullptr;    // ranked V centres, FP32, padded
+  void* d_bnodes_r = nullptr;    // ranked boundary nodes, FP32, padded
+  int* d_vrank = nullptr;        // caller column j -> rank
+  int* d_brank = nullptr;        // caller boundary node j -> rank
+  uint16_t* d_win = nullptr;     // n x (win_pc + win_pb) page lists
   std::vector<double> sites, vsites, bnodes;  // W centres (n), V centres (m), boundary nodes (p)
   bool wv = false;  // separate V partition (else V = W and the V arrays alias the W ones)
   // device

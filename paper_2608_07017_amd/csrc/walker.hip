@@ -48,8 +48,12 @@ constexpr size_t kPtsLdsMax = 32 * 1024;
 constexpr size_t kLdsMax = 160 * 1024;
 
 // Tally accumulators: FP64 or fixed point in LDS, or (rows too large for
-// LDS) atomics straight to the toolbox in HBM, pre-scaled by 1/N.
-enum { kAccF64 = 0, kAccFixed = 1, kAccGlobal = 2 };
+// LDS) atomics straight to the toolbox in HBM, pre-scaled by 1/N, or the
+// windowed mode: FP32 LDS sums for the pages of cells listed for the site,
+// device atomics (pre-scaled) for the cells outside them.
+enum { kAccF64 = 0, kAccFixed = 1, kAccGlobal = 2, kAccWindow = 3 };
+constexpr int kPageCells = 64;     // cells per page (consecutive Morton ranks)
+constexpr unsigned char kNoSlot = 0xFF;
 
 template <int ACC>
 struct Acc;
@@ -107,6 +111,8 @@ __device__ __forceinline__ int4 load_record(const GridDev<T>& g, const T* q) {
 
 template <>
 struct Acc<kAccGlobal> {};
+template <>
+struct Acc<kAccWindow> {};
 
 template <int ACC, typename T>
 struct AccWord {
@@ -114,6 +120,10 @@ struct AccWord {
 };
 template <typename T>
 struct AccWord<kAccGlobal, T> {
+  using type = T;
+};
+template <typename T>
+struct AccWord<kAccWindow, T> {
   using type = T;
 };
 
@@ -127,6 +137,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   constexpr int GEO = KIND & 15;
   constexpr bool EXACT = D == 2 && (KIND & kExactRadius) != 0;
   constexpr bool GLOBAL = ACC == kAccGlobal;
+  constexpr bool WINDOW = ACC == kAccWindow;
   using AW = typename AccWord<ACC, T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ unsigned int s_next;
@@ -144,13 +155,39 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   // LDS: the site's rows of A, B, K, the polygon edges, the site centres
   // (when they fit) and the exit counts of H.  In the global mode the rows
   // are the site's rows of the toolbox itself (row a of B, K at stride
-  // n m, n p) and only the edges and centres are in LDS.
+  // n m, n p) and only the edges and centres are in LDS.  In the windowed
+  // mode LDS holds the listed pages of the rows (slot (s, c) for cell
+  // 64 page_s + c), the page lists and the page -> slot tables; the rows in
+  // the toolbox receive the rest.
   const size_t n_sites = (size_t)P.n;
   AW *sA, *sB, *sK;
   unsigned int* sH;
   T *sSeg, *sPts;
   size_t bstride, kstride;
-  if constexpr (GLOBAL) {
+  // windowed mode only
+  T *gA = nullptr, *gB = nullptr, *gK = nullptr;
+  unsigned int* gH = nullptr;
+  unsigned short* wl = nullptr;   // the site's page list (V pages, then boundary pages)
+  unsigned char *tV = nullptr, *tG = nullptr;
+  const int pc = P.win_pc, pb = P.win_pb;
+  if constexpr (WINDOW) {
+    const size_t vs = (size_t)pc * kPageCells, gs = (size_t)pb * kPageCells;
+    sA = reinterpret_cast<AW*>(smem);
+    sB = sA + vs;
+    sK = sB + (size_t)D * vs;
+    sH = reinterpret_cast<unsigned int*>(sK + (size_t)D * gs);
+    sSeg = reinterpret_cast<T*>(sH + gs);
+    sPts = sSeg + 5 * P.nseg;
+    wl = reinterpret_cast<unsigned short*>(sPts + (PTS_LDS ? (size_t)PS * m : 0));
+    tV = reinterpret_cast<unsigned char*>(wl + pc + pb);
+    tG = tV + P.npv;
+    bstride = vs;
+    kstride = gs;
+    gA = P.A + (size_t)site * m;
+    gB = P.B + (size_t)site * m;
+    gK = P.K + (size_t)site * p;
+    gH = P.Hc + (size_t)site * p;
+  } else if constexpr (GLOBAL) {
     sA = P.A + (size_t)site * m;
     sB = P.B + (size_t)site * m;
     sK = P.K + (size_t)site * p;
@@ -172,12 +209,89 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   auto add_tally = [&](AW* at, T v) {
     if constexpr (GLOBAL)
       atomicAdd(at, v * P.inv_N);
-    else
+    else if constexpr (!WINDOW)
       Acc<ACC>::add(at, v);
+  };
+  // Tallies by cell: j a V cell (A, B) or a boundary cell (H, K).
+  const size_t gbs = n_sites * m, gks = n_sites * p;  // toolbox strides of B, K rows
+  auto tally_A = [&](int j, T v) {
+    if constexpr (WINDOW) {
+      const unsigned int sl = tV[j >> 6];
+      if (sl != kNoSlot)
+        atomicAdd(&sA[(sl << 6) | (j & 63)], v);
+      else
+        atomicAdd(&gA[j], v * P.inv_N);
+    } else {
+      add_tally(&sA[j], v);
+    }
+  };
+  auto tally_B = [&](int j, const T* v) {
+    if constexpr (WINDOW) {
+      const unsigned int sl = tV[j >> 6];
+      if (sl != kNoSlot) {
+        const int c = (sl << 6) | (j & 63);
+#pragma unroll
+        for (int a = 0; a < D; ++a) atomicAdd(&sB[a * bstride + c], v[a]);
+      } else {
+#pragma unroll
+        for (int a = 0; a < D; ++a) atomicAdd(&gB[a * gbs + j], v[a] * P.inv_N);
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < D; ++a) add_tally(&sB[a * bstride + j], v[a]);
+    }
+  };
+  auto tally_AB = [&](int j, T t, const T* wv) {
+    if constexpr (WINDOW) {
+      const unsigned int sl = tV[j >> 6];
+      if (sl != kNoSlot) {
+        const int c = (sl << 6) | (j & 63);
+        atomicAdd(&sA[c], t);
+#pragma unroll
+        for (int a = 0; a < D; ++a) atomicAdd(&sB[a * bstride + c], t * wv[a]);
+      } else {
+        const T ts = t * P.inv_N;
+        atomicAdd(&gA[j], ts);
+#pragma unroll
+        for (int a = 0; a < D; ++a) atomicAdd(&gB[a * gbs + j], ts * wv[a]);
+      }
+    } else {
+      add_tally(&sA[j], t);
+#pragma unroll
+      for (int a = 0; a < D; ++a) add_tally(&sB[a * bstride + j], t * wv[a]);
+    }
+  };
+  auto tally_HK = [&](int j, const T* wv) {
+    if constexpr (WINDOW) {
+      const unsigned int sl = tG[j >> 6];
+      if (sl != kNoSlot) {
+        const int c = (sl << 6) | (j & 63);
+        atomicAdd(&sH[c], 1u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) atomicAdd(&sK[a * kstride + c], wv[a]);
+      } else {
+        atomicAdd(&gH[j], 1u);
+#pragma unroll
+        for (int a = 0; a < D; ++a) atomicAdd(&gK[a * gks + j], wv[a] * P.inv_N);
+      }
+    } else {
+      atomicAdd(&sH[j], 1u);
+#pragma unroll
+      for (int a = 0; a < D; ++a) add_tally(&sK[a * kstride + j], wv[a]);
+    }
   };
 
   const int tid = threadIdx.x;
-  if constexpr (!GLOBAL) {
+  if constexpr (WINDOW) {
+    const int cells = (pc + pb) * kPageCells;
+    for (int j = tid; j < (1 + D) * cells; j += kBlock) sA[j] = T(0);  // sH's zero bits included
+    const unsigned short* lst = P.win + (size_t)site * (pc + pb);
+    for (int j = tid; j < pc + pb; j += kBlock) wl[j] = lst[j];
+    for (int j = tid; j < P.npv + P.npb; j += kBlock) tV[j] = kNoSlot;
+    __syncthreads();
+    for (int j = tid; j < pc; j += kBlock) tV[wl[j]] = (unsigned char)j;
+    for (int j = tid; j < pb; j += kBlock) tG[wl[pc + j]] = (unsigned char)j;
+  } else if constexpr (!GLOBAL) {
     for (int j = tid; j < (1 + D) * m + D * p; j += kBlock) sA[j] = AW(0);
     for (int j = tid; j < p; j += kBlock) sH[j] = 0u;
   }
@@ -299,10 +413,12 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
         if constexpr (D == 3) poly += S * S;
         const T bw = r0 * poly;
         const int jb = grid_resolve<T, D>(P.gv, vpts, rb, qb);
+        T bt[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) add_tally(&sB[a * bstride + jb], bw * Zs[a]);
+        for (int a = 0; a < D; ++a) bt[a] = bw * Zs[a];
+        tally_B(jb, bt);
         const int j0 = grid_resolve<T, D>(P.gv, vpts, r0c, q0);
-        add_tally(&sA[j0], pomd * r0sq);
+        tally_A(j0, pomd * r0sq);
       }
       V += avail;
       n_walks += (unsigned long long)avail;
@@ -311,9 +427,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
     // ---- terminal tallies of the walks that stopped (eqs. Estimator_H, _K)
     if (done) {
       const int j = grid_nearest<T, D>(P.gg, P.gg.pts, X);
-      atomicAdd(&sH[j], 1u);
-#pragma unroll
-      for (int a = 0; a < D; ++a) add_tally(&sK[a * kstride + j], w[a]);
+      tally_HK(j, w);
       done = false;
     }
 
@@ -416,9 +530,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
         // A += t, B += t w at the cell of X_k + r Y, t = omega r^2 / d
         const T t = omd * r * r;
         const int j = grid_resolve<T, D>(P.gv, vpts, rec, q);
-        add_tally(&sA[j], t);
-#pragma unroll
-        for (int a = 0; a < D; ++a) add_tally(&sB[a * bstride + j], t * w[a]);
+        tally_AB(j, t, w);
       }
 #pragma unroll
       for (int a = 0; a < D; ++a) {
@@ -437,7 +549,35 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   atomicMax(&s_maxk, lane_maxk);
   __syncthreads();
 
-  if constexpr (GLOBAL) {
+  if constexpr (GLOBAL || WINDOW) {
+    if constexpr (WINDOW) {
+      // the window's sums, scaled by 1/N, onto the toolbox rows
+      const T inv_N = P.inv_N;
+      for (int c = tid; c < pc * kPageCells; c += kBlock) {
+        const int j = ((int)wl[c >> 6] << 6) | (c & 63);
+        if (j < m) {
+          const T va = sA[c];
+          if (va != T(0)) atomicAdd(&gA[j], va * inv_N);
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            const T vb = sB[a * bstride + c];
+            if (vb != T(0)) atomicAdd(&gB[a * gbs + j], vb * inv_N);
+          }
+        }
+      }
+      for (int c = tid; c < pb * kPageCells; c += kBlock) {
+        const int j = ((int)wl[pc + (c >> 6)] << 6) | (c & 63);
+        if (j < p) {
+          const unsigned int h = sH[c];
+          if (h) atomicAdd(&gH[j], h);
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            const T vk = sK[a * kstride + c];
+            if (vk != T(0)) atomicAdd(&gK[a * gks + j], vk * inv_N);
+          }
+        }
+      }
+    }
     if (tid == 0) {
       atomicAdd(&P.stats[0], s_steps);
       atomicAdd(&P.stats[1], s_walks);
@@ -562,6 +702,14 @@ hipError_t launch_bs(const WalkerParams<T>& P, size_t lds, int items, hipStream_
 template <typename T, int D, int KIND>
 hipError_t launch_typed(const WalkerParams<T>& P, size_t lds, int items, hipStream_t stream) {
   const size_t pts = sizeof(T) * PtStride<D>::value * (size_t)P.m;
+  if constexpr (std::is_same<T, float>::value) {
+    if (P.window) {
+      const size_t lds_w = walker_window_lds_bytes(D, P.win_pc, P.win_pb, P.npv, P.npb, P.nseg);
+      if (pts <= kPtsLdsMax && lds_w + pts <= kLdsMax)
+        return launch_bs<T, D, KIND, true, kAccWindow>(P, lds_w + pts, items, stream);
+      return launch_bs<T, D, KIND, false, kAccWindow>(P, lds_w, items, stream);
+    }
+  }
   if (P.global_tally) {
     const size_t lds_g = sizeof(T) * 5 * (size_t)P.nseg;
     if (pts <= kPtsLdsMax) return launch_bs<T, D, KIND, true, kAccGlobal>(P, lds_g + pts, items, stream);
@@ -604,6 +752,13 @@ hipError_t dispatch(const WalkerParams<T>& P, int dim, int kind, size_t lds, int
 }
 
 }  // namespace
+
+size_t walker_window_lds_bytes(int dim, int pc, int pb, int npv, int npb, int nseg) {
+  // FP32 sums of A, B, K and the counts of H for the listed pages, the edges,
+  // the page lists (2 bytes each) and the page -> slot tables (1 byte each)
+  return 4 * (size_t)(1 + dim) * kPageCells * (size_t)(pc + pb) + 4 * 5 * (size_t)nseg + 2 * (size_t)(pc + pb) +
+         (size_t)(npv + npb);
+}
 
 size_t walker_lds_bytes(int dim, int m, int p, int nseg, bool f64) {
   const size_t t = f64 ? 8 : 4;

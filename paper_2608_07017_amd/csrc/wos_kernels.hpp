@@ -8,11 +8,17 @@
 namespace wos {
 
 size_t walker_lds_bytes(int dim, int m, int p, int nseg, bool f64);
+size_t walker_window_lds_bytes(int dim, int pc, int pb, int npv, int npb, int nseg);
 int walker_block_size(size_t lds);
 hipError_t launch_walker_f32(const WalkerParams<float>& P, int dim, int kind, int items,
                              hipStream_t stream);
 hipError_t launch_walker_f64(const WalkerParams<double>& P, int dim, int kind, int items,
                              hipStream_t stream);
+
+// X (rows x cols, 4-byte elements, row-major) <- X[:, rank] in place;
+// cols <= permute_max_cols().
+size_t permute_max_cols();
+hipError_t launch_permute_cols(void* X, int rows, int cols, const int* rank, hipStream_t st);
 
 hipError_t launch_volume(const VolumeParams& P, hipStream_t stream);
 hipError_t launch_lambda(const unsigned long long* counts, int n, double* lambda,

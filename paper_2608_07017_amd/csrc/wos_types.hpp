@@ -65,6 +65,10 @@ struct WalkerParams {
   const int* item_order;  // blockIdx -> item (longest expected work first)
   int direct_store;
   int acc_fixed;   // tally accumulators: 0 FP64, 1 64-bit fixed point
+  int window;      // windowed tallies: columns are Morton ranks, pages listed per site
+  const uint16_t* win;  // n x (win_pc + win_pb): a site's V pages, then its boundary pages
+  int win_pc, win_pb;   // pages held in LDS per site
+  int npv, npb;         // pages of the ranked V centres / boundary nodes
   T* A;
   T* B;
   uint32_t* Hc;

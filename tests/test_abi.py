@@ -71,3 +71,41 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", os.path.join(ROOT, "no_such_libwos.so"))
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+_STRUCTS = ["wos_domain", "wos_build_opts", "wos_build_plan", "wos_toolbox_info", "wos_coeffs", "wos_solve_info",
+            "wos_adam_opts", "wos_adam_info", "wos_hisd_opts", "wos_hisd_info", "wos_operator_opts",
+            "wos_operator_info", "wos_server_opts"]
+
+
+def _ctypes_struct(name):
+    from paper_2608_07017_amd import _lib
+    cname = "Wos" + "".join(w.capitalize() for w in name.split("_")[1:])
+    return getattr(_lib, cname)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # sizeof and every field offset, from the C compiler on the header and
+    # from the binding's ctypes structures
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "wos.h"', "int main(void) {"]
+    for name in _STRUCTS:
+        st = _ctypes_struct(name)
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
+        for f, _ in st._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, f, name, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            name, field, val = ln.split()
+            got[(name, field)] = int(val)
+    for name in _STRUCTS:
+        st = _ctypes_struct(name)
+        assert got[(name, "size")] == ctypes.sizeof(st), name
+        for f, _ in st._fields_:
+            assert got[(name, f)] == getattr(st, f).offset, (name, f)

@@ -234,16 +234,16 @@ def test_hbm_tally_mode_fp64(case):
     same walks, so exit counts exact and the matrices to rounding."""
     if case == "disk":
         c = W.config("disk64")
-        _compare_f64(c["domain"], c["sites"][:40], c["bnodes"], 500, c["eps"], c["seed"], tally_in_hbm=True)
+        _compare_f64(c["domain"], c["sites"][:40], c["bnodes"], 500, c["eps"], c["seed"], tally="hbm")
     elif case == "ragged":
         dom = W.unit_disk()
         sites = W.sample_sites(dom, 37, 5, 1e-3)
-        _compare_f64(dom, sites, W.circle_nodes(19), 333, 1e-3, 42, walks_per_item=100, tally_in_hbm=True)
+        _compare_f64(dom, sites, W.circle_nodes(19), 333, 1e-3, 42, walks_per_item=100, tally="hbm")
     else:
         dom = W.cube_minus_ball()
         bn = np.concatenate([W.cube_face_nodes(4), W.fibonacci_sphere(30, dom["center"], dom["radius"])])
         sites = W.sample_sites(dom, 23, 11, 1e-3)
-        _compare_f64(dom, sites, bn, 300, 1e-4, 17, tally_in_hbm=True)
+        _compare_f64(dom, sites, bn, 300, 1e-4, 17, tally="hbm")
 
 
 def test_hbm_tally_fp32_matches_lds_tally():
@@ -254,11 +254,68 @@ def test_hbm_tally_fp32_matches_lds_tally():
     bn = W.square_nodes(16)
     g1 = _export_all(_gpu_tb(dom, sites, bn, 3000, 1e-4, 5, precision="f32", volume_samples=1 << 14))
     g2 = _export_all(_gpu_tb(dom, sites, bn, 3000, 1e-4, 5, precision="f32", volume_samples=1 << 14,
-                             tally_in_hbm=True))
+                             tally="hbm"))
     assert np.array_equal(g1["Hcount"], g2["Hcount"])
     for key in ("A", "B", "K"):
         mass = np.abs(g1[key]).sum(axis=-1, keepdims=True)
         assert np.all(np.abs(g1[key] - g2[key]) <= 1e-5 * mass), key
+
+
+@pytest.mark.parametrize("case", ["square", "lshape", "ball", "cubeball"])
+def test_window_tally_fp32_matches_lds_rows(case):
+    """The windowed tally mode (V cells and boundary cells ranked along a
+    Morton curve, a few pages per site in LDS, the rest by device atomics,
+    columns put back in the caller's order) forced with small windows, so
+    that both paths carry many tallies, against the LDS-row mode on the same
+    walks: exit counts equal, the matrices equal to FP32 summation rounding,
+    the walk statistics identical."""
+    dom = {"square": W.unit_square(), "lshape": W.l_shape(), "ball": W.unit_ball(),
+           "cubeball": W.cube_minus_ball()}[case]
+    d = dom["dim"]
+    sites = W.sample_sites(dom, 333, 23, 1e-3)          # 6 pages, the last one ragged
+    if case == "square":
+        bn = W.square_nodes(40)
+    elif case == "lshape":
+        bn = W.polygon_nodes(dom["verts"], 150)
+    elif case == "ball":
+        bn = W.fibonacci_sphere(150)
+    else:
+        bn = np.concatenate([W.cube_face_nodes(4), W.fibonacci_sphere(54, dom["center"], dom["radius"])])
+    kw = dict(precision="f32", volume_samples=1 << 12)
+    t1 = _gpu_tb(dom, sites, bn, 2000, 1e-4, 13, **kw)
+    t2 = _gpu_tb(dom, sites, bn, 2000, 1e-4, 13, tally="window", window_pages=2, window_bpages=1, **kw)
+    i1, i2 = t1.info(), t2.info()
+    for k in ("walks", "walk_steps", "max_walk_steps", "capped_walks"):
+        assert i1[k] == i2[k], k
+    g1, g2 = _export_all(t1), _export_all(t2)
+    _same_walks_fp32(g1, g2, len(sites) * 2000)
+    # a second build on the same toolbox (the accumulators start from zero again)
+    t2.build(seed=13)
+    torch.cuda.synchronize()
+    g3 = _export_all(t2)
+    assert np.array_equal(g3["Hcount"].sum(1), g2["Hcount"].sum(1))
+    _same_walks_fp32(g3, g2, len(sites) * 2000)
+
+
+def _same_walks_fp32(g1, g2, walks):
+    """Two FP32 toolboxes of the same walks whose binning visits tied
+    centres in another order: every exit counted once in both, a walk binned
+    to the other of two equidistant nodes at most about once per 1e5 walks
+    (exact FP32 ties), and otherwise the matrices equal to summation
+    rounding."""
+    h1, h2 = g1["Hcount"], g2["Hcount"]
+    assert np.array_equal(h1.sum(1), h2.sum(1))
+    moved = np.abs(h1 - h2).sum()
+    assert moved <= 2 * max(4, 1e-5 * walks), moved
+    tied = h1 != h2                                     # entries a tie moved an exit into or out of
+    for key in ("A", "B"):
+        mass = np.abs(g1[key]).sum(axis=-1, keepdims=True)
+        assert np.all(np.abs(g1[key] - g2[key]) <= 1e-5 * mass), key
+    mass = np.abs(g1["K"]).sum(axis=-1, keepdims=True)
+    ok = np.abs(g1["K"] - g2["K"]) <= 1e-5 * mass
+    assert np.all(ok | tied[None]), "K"
+    # the row sums of K hold every exit's weight in both
+    assert np.allclose(g1["K"].sum(-1), g2["K"].sum(-1), rtol=1e-5, atol=1e-5 * mass[..., 0].max())
 
 
 def test_rows_beyond_lds_fp64_sampled():

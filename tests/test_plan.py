@@ -1,0 +1,88 @@
+"""Host decisions of a build (wos_toolbox_plan): tally mode, accumulators,
+work split, windows, and the fixed-point overflow guard.  Host only: no
+device call is made."""
+import numpy as np
+import pytest
+
+import workloads as W
+import paper_2608_07017_amd as P
+
+
+def _plan(name, **kw):
+    c = W.config(name)
+    kw.setdefault("precision", c["precision"])
+    return P.build_plan(c["domain"], c["sites"], c["bnodes"], c["walks"], c["eps"], **kw)
+
+
+def test_workload_plans():
+    # rows in LDS while they fit, the windowed mode for the 32768-site box
+    # minus ball (its rows take 640 KB), two walker workgroups per compute unit
+    assert _plan("square1024")["tally_mode"] == "lds_rows"
+    assert _plan("ball4096")["tally_mode"] == "lds_rows"
+    cb = _plan("cubeball32768")
+    assert cb["tally_mode"] == "window"
+    assert cb["window_bpages"] == 16 and 40 <= cb["window_pages"] <= 255
+    assert cb["lds_bytes"] <= 78 * 1024
+    assert cb["items_per_site"] * cb["walks_per_item"] >= 100000
+
+
+def test_window_size_options():
+    pl = _plan("cubeball32768", window_pages=100, window_bpages=24)
+    assert pl["window_pages"] == 100 and pl["window_bpages"] == 24
+    # 4 (1 + d) 64 bytes per page plus tables and lists
+    assert pl["lds_bytes"] == 4 * 4 * 64 * 124 + 2 * 124 + 512 + 128
+    with pytest.raises(P.WosError):   # more than LDS holds
+        _plan("cubeball32768", window_pages=255, window_bpages=255)
+
+
+def test_forced_modes_and_their_limits():
+    assert _plan("square1024", tally="window")["tally_mode"] == "window"
+    assert _plan("square1024", tally="hbm")["tally_mode"] == "hbm"
+    with pytest.raises(P.WosError):
+        _plan("cubeball32768", tally="lds_rows")
+    with pytest.raises(P.WosError):
+        _plan("disk64", tally="window")          # FP64 toolbox
+    with pytest.raises(P.WosError):
+        _plan("square1024", walker_block=300)
+
+
+def _near_boundary_case(r0, walks, **kw):
+    dom = W.unit_square()
+    sites = np.array([[0.5, 0.5], [r0, 0.5]])
+    return P.build_plan(dom, sites, W.square_nodes(4), walks, 1e-9, walks_per_item=walks, **kw)
+
+
+def test_fixed_point_bound_formula():
+    # K: N d / r0, B: 4 N (d / r0) R^2 / d, A: 4 N omega_max R^2 / d, with
+    # R^2 = 1/2 (half diagonal of the unit square) and omega_max = 12 in 2-D
+    N, r0 = 1000, 1e-3
+    pl = _near_boundary_case(r0, N)
+    bK = N * 2 / r0
+    bB = 4 * N * (2 / r0) * 0.5 / 2
+    bA = 4 * N * 12 * 0.5 / 2
+    assert np.isclose(pl["fixed_bound"], max(bK, bB, bA) / 2 ** 31, rtol=1e-12)
+    assert pl["tally_acc"] == "fixed"
+
+
+def test_fixed_point_overflow_guard():
+    # a site 1e-6 from the boundary with 1e5 walks in one item: a K sum can
+    # reach 2e11 > 2^31, so the automatic choice is FP64 and forcing fixed
+    # point is refused
+    pl = _near_boundary_case(1e-6, 100000)
+    assert pl["fixed_bound"] >= 0.5
+    assert pl["tally_acc"] == "f64"
+    assert _near_boundary_case(1e-6, 100000, tally_acc="f64")["tally_acc"] == "f64"
+    with pytest.raises(P.WosError):
+        _near_boundary_case(1e-6, 100000, tally_acc="fixed")
+    # smaller items bring the bound back into range
+    small = P.build_plan(W.unit_square(), np.array([[0.5, 0.5], [1e-6, 0.5]]), W.square_nodes(4), 100000, 1e-9,
+                         walks_per_item=100)
+    assert small["fixed_bound"] < 0.5 and small["tally_acc"] == "fixed"
+
+
+def test_plan_rejects_bad_inputs():
+    dom = W.unit_disk()
+    with pytest.raises(P.WosError):
+        P.build_plan(dom, np.array([[2.0, 0.0]]), W.circle_nodes(8), 10, 1e-3)   # site outside
+    with pytest.raises(P.WosError):
+        P.build_plan(dom, np.array([[0.1, 0.0]]), W.circle_nodes(8), 10, 1e-3, window_pages=300)
