@@ -7,21 +7,23 @@ application to the boundary data g = x^2 - y^2 (u = A 0 + H g,
 grad u = B 0 + K g).  Each step uses a new seed.  `value` is walk-steps per
 second over the whole step, inputs resident in HBM.
 
-Workload (default): 2-D unit square, 1024 uniform interior sites, 256
-equispaced boundary nodes, 1e4 walks per site, eps = 1e-4, FP32 walker.
+Workload (default): the largest single-GPU configuration, the 3-D unit cube
+minus the ball of radius 0.3 about its centre: 32768 uniform interior sites,
+8192 boundary nodes (6936 face-cell midpoints on the cube, 1256 Fibonacci
+points on the sphere), 1e5 walks per site, eps = 1e-5, FP32 walker (its rows
+exceed LDS: the windowed tally mode).
 
-The line also carries "serving": solves/s and p50/p99 latency of a served
-stream of Dirichlet problems on resident L-shape toolboxes (256/1024/4096
-sites), mixed precision against FP64, with the L2 errors of both against
-the manufactured solutions, and "newton_ball4096": the 3-D unit-ball
-toolbox build and a regularised Newton solve of -Lap u + u^3 = f, mixed
-precision against FP64, and "el_plaplace": Adam on the discrete p-Laplace
-functional (the paper's disk p-torsion example and the iteration rate on
-the 4096-site L-shape toolbox), and "el_energies": the minimal surface and
-semilinear energies (closed-form solutions on the unit square, the paper's
-minimal surface data on the disk, and the semilinear iteration rate).
+The line also carries "serving": solves/s and p50/p99 latency of served
+streams of Dirichlet problems on resident L-shape toolboxes (256/1024/4096
+sites), every request with its own seeded coefficients, mixed precision
+against FP64, with the L2 errors of both against the manufactured
+solutions, and "newton_ball4096": the 3-D unit-ball toolbox build and a
+regularised Newton solve of -Lap u + u^3 = f, mixed precision against FP64,
+and "el_plaplace": Adam on the discrete p-Laplace functional (the paper's
+disk p-torsion example), and "el_energies": the paper's semilinear example
+(Adam and p-HiSD saddle points) and its example "elliptic div min".
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-serving]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-serving]
 
 Prints one JSON line.
 """
@@ -30,6 +32,7 @@ import hashlib
 import json
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -81,13 +84,18 @@ def measured_traffic(workload):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="square1024")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cubeball32768")
     ap.add_argument("--walks", type=int, default=0, help="override the workload's walks per site (profiling runs)")
     ap.add_argument("--no-autotune", action="store_true", help="workgroup size by occupancy, no timing pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=3)
+    ap.add_argument("--cpu-walks", type=int, default=0,
+                    help="walks of the oracle's sample per site (0: sized for about 5 s per site)")
+    ap.add_argument("--cpu-procs", type=int, default=0, help="processes of the all-core oracle run (0: the CPU share)")
+    ap.add_argument("--no-cpu-solves", action="store_true", help="skip the numpy FP64 solve baseline")
+    ap.add_argument("--probe", action="store_true", help="also report the VALU issue-rate probe")
+    ap.add_argument("--minimal-surface", action="store_true", help="also run the minimal surface energies")
     ap.add_argument("--no-serving", action="store_true", help="skip the served-solve stream")
     ap.add_argument("--no-newton", action="store_true", help="skip the 3-D Newton run")
     ap.add_argument("--newton-iters", type=int, default=10)
@@ -98,11 +106,12 @@ def parse():
     ap.add_argument("--el-conv-iters", type=int, default=20000)
     ap.add_argument("--hisd-max-iter", type=int, default=40000)
     ap.add_argument("--newton-rcond", type=float, default=1e-2)
-    ap.add_argument("--serve-requests", type=int, default=2000, help="open-loop requests (mixed precision)")
-    ap.add_argument("--serve-saturation", type=int, default=300, help="requests of the saturation run")
+    ap.add_argument("--serve-requests", type=int, default=10000, help="requests of each open-loop mixed run")
+    ap.add_argument("--serve-saturation", type=int, default=2000, help="requests of the saturation run")
+    ap.add_argument("--serve-f64-requests", type=int, default=2000, help="requests of the FP64 open-loop run")
     ap.add_argument("--serve-slots", type=int, default=8)
-    ap.add_argument("--serve-pool", type=int, default=4, help="problems per toolbox")
-    ap.add_argument("--serve-rho", type=float, default=0.8)
+    ap.add_argument("--serve-problems", type=int, default=400, help="distinct seeded problems per toolbox")
+    ap.add_argument("--serve-rho", default="0.5,0.8,0.95")
     ap.add_argument("--serve-rcond", type=float, default=0.1)
     ap.add_argument("--serve-seed", type=int, default=7)
     ap.add_argument("--serve-op-requests", type=int, default=20000,
@@ -123,68 +132,143 @@ def geometry_key(name):
     return "square"
 
 
-def cpu_baseline(cfg, rows):
-    """The oracle, as it stands, on a bounded sample: `rows` whole sites of the
-    same workload (all N walks each).  Rate in walk-steps/s."""
+def _oracle_site_sample(job):
+    """One bounded sample of the oracle (run in a child process): `walks`
+    walks of site i of the named workload, binned.  Returns (walk-steps, s)."""
+    name, i, walks = job
+    import workloads as W
     from oracle.walker import site_events, bin_site
+    c = W.config(name)
     t0 = time.perf_counter()
-    steps = 0
-    for i in range(rows):
-        ev = site_events(cfg["domain"], cfg["sites"][i], i, np.arange(cfg["walks"]), cfg["eps"], cfg["seed"])
-        bin_site(ev, cfg["sites"], cfg["bnodes"])
-        steps += int(ev.nsteps.sum())
-    dt = time.perf_counter() - t0
-    return {"value": steps / dt, "unit": "walk-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%d of %d sites x %d walks (%d walk-steps, %.1f s), FP64 NumPy, one thread"
-                      % (rows, len(cfg["sites"]), cfg["walks"], steps, dt)}
+    ev = site_events(c["domain"], c["sites"][i], i, np.arange(walks), c["eps"], c["seed"])
+    bin_site(ev, c["sites"], c["bnodes"])
+    return int(ev.nsteps.sum()), time.perf_counter() - t0
+
+
+def _host_cpu():
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = os.cpu_count() or 1
+    return model, os.cpu_count(), share
+
+
+def cpu_baseline(name, walks, procs):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    `walks` walks of whole sites (the oracle's rate per walk-step does not
+    depend on the sample size), once in one process (one thread: NumPy's
+    element-wise kernels), then `procs` sites at once in as many processes.
+    Rates in walk-steps/s."""
+    import multiprocessing as mp
+    model, ncpu, share = _host_cpu()
+    steps1, dt1 = _oracle_site_sample((name, 0, walks))
+    ctx = mp.get_context("spawn")
+    jobs = [(name, 1 + k, walks) for k in range(procs)]
+    t0 = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_oracle_site_sample, jobs)
+    dtn = time.perf_counter() - t0
+    stepsn = sum(r[0] for r in res)
+    return {"value": stepsn / dtn, "unit": "walk-steps/s", "cores": procs, "kind": "oracle",
+            "sample": "%d sites x %d walks of the same workload in %d processes (%d walk-steps, %.1f s wall); FP64 "
+                      "NumPy oracle, brute-force nearest centre" % (procs, walks, procs, stepsn, dtn),
+            "single_thread": {"value": steps1 / dt1, "sample": "1 site x %d walks (%d walk-steps, %.1f s)"
+                                                               % (walks, steps1, dt1)},
+            "host": {"lscpu_model": model, "os_cpu_count": ncpu, "affinity": share}}
+
+
+def cpu_solve_baseline():
+    """numpy/LAPACK FP64 solves of eq. linear_q by the oracle (Tikhonov,
+    the generalised inverse the served route uses) on toolboxes of the
+    served sizes (d = 2, p = n / 4; random matrices: the time does not depend
+    on their values), BLAS threads as the environment sets them."""
+    from oracle import linalg as OL
+    rng = np.random.default_rng(3)
+    out = {"threads": os.environ.get("OMP_NUM_THREADS", "default")}
+    for n, reps in ((256, 10), (1024, 3), (4096, 1)):
+        p, d = n // 4, 2
+        tb = {"A": rng.random((n, n)), "B": rng.normal(size=(d, n, n)), "H": rng.random((n, p)),
+              "K": rng.normal(size=(d, n, p))}
+        lam = rng.random(n) / n
+        M = rng.normal(size=(n, d, d))
+        Ac = M @ M.transpose(0, 2, 1) + np.eye(d)
+        bc = rng.normal(size=(n, d))
+        f, g = rng.normal(size=n), rng.normal(size=p)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            OL.solve_linear(tb, lam, f, g, Acoef=Ac, bcoef=bc, rcond=0.1, solver="tikhonov")
+        dt = (time.perf_counter() - t0) / reps
+        out[str(n)] = {"solves_per_s": 1.0 / dt, "ms_per_solve": 1e3 * dt}
+    return out
 
 
 SERVE_SIZES = (256, 1024, 4096)
 
 
 def serving(a, torch, W, P):
-    """Served stream on resident L-shape toolboxes: -div(A grad u) + b . grad u = f
+    """Served streams on resident L-shape toolboxes: -div(A grad u) + b . grad u = f
     with A anisotropic (up to 1:100) and b smooth, solved by the Tikhonov route
-    in mixed precision and in FP64.  Saturation rate (all requests queued at
-    once), then Poisson arrivals at rho times that rate; latency = finish - arrival."""
+    in mixed precision and in FP64.  Every request carries its own seeded
+    coefficient fields and data (serve_problems distinct problems per
+    toolbox; nothing is cached between requests).  Saturation rate (all
+    requests queued at once), then Poisson arrivals at rho times that rate
+    for each rho; latency = finish - arrival.  Every mixed result is checked
+    against its problem's FP64 plain solve: L2 error against u_ex within
+    1.01 times the FP64 one plus 1e-6.  The prepared-operator route is
+    reported for a stream that shares coefficients (one set per toolbox, a
+    new right-hand side per request)."""
     rng = np.random.default_rng(a.serve_seed)
+    rhos = [float(r) for r in str(a.serve_rho).split(",")]
     boxes = []
+    print("serving: toolboxes and %d problems per toolbox" % a.serve_problems, file=sys.stderr, flush=True)
     for n in SERVE_SIZES:
         cfg = W.config("lshape%d" % n)
         tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], cfg["walks"], cfg["eps"], seed=cfg["seed"],
                        precision="f32")
         tb.build()
-        lam = tb.export("lambda").cpu().numpy()
-        pool = []
-        for k in range(a.serve_pool):
-            pr = W.anisotropic_problem(a.serve_seed * 1000 + 10 * n + k, cfg["sites"], cfg["bnodes"])
+        lam = torch.as_tensor(tb.export("lambda"), dtype=torch.float64)
+        probs = []
+        for k in range(a.serve_problems):
+            pr = W.anisotropic_problem(a.serve_seed * 100000 + 1000 * (n // 256) + k, cfg["sites"], cfg["bnodes"])
             dev = {key: torch.as_tensor(v, dtype=torch.float64, device="cuda").contiguous()
-                   for key, v in (("f", -pr["f"]), ("g", pr["g"]), ("A", pr["A"]), ("b", -pr["b"]))}
-            pool.append((dev, pr["u"]))
-        boxes.append((tb, lam, pool))
+                   for key, v in (("f", -pr["f"]), ("g", pr["g"]), ("A", pr["A"]), ("b", -pr["b"]), ("u", pr["u"]))}
+            probs.append(dev)
+        boxes.append((tb, lam, probs))
     torch.cuda.synchronize()
 
     def kw(dev, prec):
         return dict(kind="linear", A=dev["A"], b=dev["b"], rcond=a.serve_rcond, solver="tikhonov", precision=prec,
                     refine_tol=1e-8)
 
-    # accuracy against the manufactured solutions, both precisions
-    l2 = {}
-    ok = True
-    for tb, lam, pool in boxes:
-        e = {"f64": [], "mixed": []}
-        for dev, uex in pool:
-            for prec in ("f64", "mixed"):
-                u, _, _, info = tb.solve(dev["f"], dev["g"], **kw(dev, prec))
-                e[prec].append(float(np.sqrt(np.sum(lam * (u.cpu().numpy() - uex) ** 2))))
-            ok = ok and e["mixed"][-1] <= 1.01 * e["f64"][-1] + 1e-6
-        l2[str(tb.n)] = {p: float(np.mean(v)) for p, v in e.items()}
+    def l2(lam, u, dev):
+        return float(torch.sqrt(torch.sum(lam * (u - dev["u"]) ** 2)))
 
-    def run(prec, nreq, rate):
+    # the FP64 plain solve of every problem: its L2 error is the bar each
+    # served mixed result must reach
+    print("serving: FP64 reference solves", file=sys.stderr, flush=True)
+    sv = P.Server(slots=a.serve_slots)
+    pend = [[sv.submit(tb, dev["f"], dev["g"], **kw(dev, "f64")) for dev in probs] for tb, _, probs in boxes]
+    ref_err = []
+    for (tb, lam, probs), row in zip(boxes, pend):
+        ref_err.append([])
+        for dev, (tk, u, _) in zip(probs, row):
+            sv.poll(tk)
+            ref_err[-1].append(l2(lam, u, dev))
+    sv.close()
+
+    def run(prec, nreq, rate, check=False):
         sv = P.Server(slots=a.serve_slots)
-        for tb, lam, pool in boxes:  # warm every workspace
-            sv.poll(sv.submit(tb, pool[0][0]["f"], pool[0][0]["g"], **kw(pool[0][0], prec))[0])
-        picks = [(int(rng.integers(len(boxes))), int(rng.integers(a.serve_pool))) for _ in range(nreq)]
+        for tb, lam, probs in boxes:  # warm every workspace
+            sv.poll(sv.submit(tb, probs[0]["f"], probs[0]["g"], **kw(probs[0], prec))[0])
+        picks = [(int(rng.integers(len(boxes))), int(rng.integers(a.serve_problems))) for _ in range(nreq)]
         gaps = rng.exponential(1.0 / rate, nreq) if rate else np.zeros(nreq)
         arrivals = np.cumsum(gaps)
         tickets = []
@@ -192,48 +276,70 @@ def serving(a, torch, W, P):
         for (bi, pi), ta in zip(picks, arrivals):
             while time.perf_counter() - t0 < ta:
                 pass
-            tb, lam, pool = boxes[bi]
-            dev = pool[pi][0]
-            tickets.append(sv.submit(tb, dev["f"], dev["g"], **kw(dev, prec))[0])
-        times = [sv.poll(t)[1] for t in tickets]
+            tb, lam, probs = boxes[bi]
+            dev = probs[pi]
+            tk, u, _ = sv.submit(tb, dev["f"], dev["g"], **kw(dev, prec))
+            tickets.append((tk, u))
+        res = [sv.poll(tk) for tk, _ in tickets]
         sv.close()
+        times = [r[1] for r in res]
         first = min(t[0] for t in times)
         last = max(t[2] for t in times)
         lat = np.array([t[2] - t[0] for t in times]) * 1e3
-        return {"requests": nreq, "solves_per_s": nreq / (last - first), "p50_ms": float(np.percentile(lat, 50)),
-                "p99_ms": float(np.percentile(lat, 99))}
+        out = {"requests": nreq, "solves_per_s": nreq / (last - first), "p50_ms": float(np.percentile(lat, 50)),
+               "p99_ms": float(np.percentile(lat, 99))}
+        if check:
+            ok = 0
+            for (bi, pi), (_, u) in zip(picks, tickets):
+                tb, lam, probs = boxes[bi]
+                ok += l2(lam, u, probs[pi]) <= 1.01 * ref_err[bi][pi] + 1e-6
+            out["at_fp64_l2_error"] = ok / nreq
+        return out
 
     out = {"workload": "L-shape toolboxes of %s sites (n/4 boundary nodes, 1e4 walks/site, eps 1e-4, FP32), "
-                       "requests uniform over them: -div(A grad u) + b.grad u = f, A seeded smooth SPD with "
-                       "anisotropy up to 1:100, |b| <= 0.8, manufactured u; Tikhonov rcond %g"
-                       % ("/".join(map(str, SERVE_SIZES)), a.serve_rcond),
-           "slots": a.serve_slots, "l2_error": l2, "mixed_at_fp64_l2_error": bool(ok)}
-    for prec, nopen in (("mixed", a.serve_requests), ("f64", max(100, a.serve_requests // 4))):
-        print("serving: %s saturation" % prec, file=sys.stderr, flush=True)
-        sat = run(prec, a.serve_saturation, 0.0)
-        print("serving: %s open loop" % prec, file=sys.stderr, flush=True)
-        rate = a.serve_rho * sat["solves_per_s"]
-        out[prec] = {"saturation_solves_per_s": sat["solves_per_s"], "open_loop": dict(run(prec, nopen, rate), rho=a.serve_rho,
-                                                                                     arrival_rate=rate)}
-    out["mixed_vs_f64_saturation"] = out["mixed"]["saturation_solves_per_s"] / out["f64"]["saturation_solves_per_s"]
+                       "requests uniform over them and over %d seeded problems per toolbox: -div(A grad u) + "
+                       "b.grad u = f, A smooth SPD with anisotropy up to 1:100, |b| <= 0.8, manufactured u; "
+                       "Tikhonov rcond %g" % ("/".join(map(str, SERVE_SIZES)), a.serve_problems, a.serve_rcond),
+           "slots": a.serve_slots,
+           "l2_error_f64": {str(tb.n): float(np.mean(e)) for (tb, _, _), e in zip(boxes, ref_err)}}
+    print("serving: mixed saturation", file=sys.stderr, flush=True)
+    sat = run("mixed", a.serve_saturation, 0.0, check=True)
+    out["mixed"] = {"saturation": sat, "open_loop": []}
+    for rho in rhos:
+        print("serving: mixed open loop rho %g" % rho, file=sys.stderr, flush=True)
+        rate = rho * sat["solves_per_s"]
+        out["mixed"]["open_loop"].append(dict(run("mixed", a.serve_requests, rate, check=True), rho=rho,
+                                              arrival_rate=rate))
+    print("serving: FP64 saturation and open loop", file=sys.stderr, flush=True)
+    sat64 = run("f64", max(200, a.serve_saturation // 4), 0.0)
+    rho = 0.8
+    out["f64"] = {"saturation": sat64,
+                  "open_loop": [dict(run("f64", a.serve_f64_requests, rho * sat64["solves_per_s"]), rho=rho,
+                                     arrival_rate=rho * sat64["solves_per_s"])]}
+    out["mixed_vs_f64_saturation"] = sat["solves_per_s"] / sat64["solves_per_s"]
+    out["mixed_at_fp64_l2_error"] = min([sat["at_fp64_l2_error"]] +
+                                        [r["at_fp64_l2_error"] for r in out["mixed"]["open_loop"]])
 
-    # the same requests against prepared solution operators (one per toolbox
-    # and problem), FP32 storage: queued requests on one operator are batched
+    # a stream that shares coefficients: one prepared solution operator per
+    # toolbox (FP32 storage), a new right-hand side per request; queued
+    # requests on one operator are batched
     print("serving: preparing operators", file=sys.stderr, flush=True)
     ops, prep_ms, op_l2 = [], {}, {}
-    for tb, lam, pool in boxes:
-        row = []
-        for dev, uex in pool:
-            op = tb.operator(A=dev["A"], b=dev["b"], rcond=a.serve_rcond, storage="f32")
-            row.append(op)
-            prep_ms.setdefault(str(tb.n), []).append(op.info()["prep_ms"])
-            u, _ = op.apply(dev["f"], dev["g"])
-            op_l2.setdefault(str(tb.n), []).append(float(np.sqrt(np.sum(lam * (u.cpu().numpy() - uex) ** 2))))
-        ops.append(row)
+    for tb, lam, probs in boxes:
+        dev = probs[0]
+        op = tb.operator(A=dev["A"], b=dev["b"], rcond=a.serve_rcond, storage="f32")
+        ops.append(op)
+        prep_ms[str(tb.n)] = op.info()["prep_ms"]
+        u, _ = op.apply(dev["f"], dev["g"])
+        op_l2[str(tb.n)] = l2(lam, u, dev)
+    rhs = []
+    for (tb, lam, probs) in boxes:
+        rhs.append([(torch.randn(tb.n, dtype=torch.float64, device="cuda"),
+                     torch.randn(tb.p, dtype=torch.float64, device="cuda")) for _ in range(64)])
 
     def run_op(nreq, rate):
         sv = P.Server(slots=a.serve_slots, max_batch=64)
-        picks = [(int(rng.integers(len(boxes))), int(rng.integers(a.serve_pool))) for _ in range(nreq)]
+        picks = [(int(rng.integers(len(boxes))), int(rng.integers(64))) for _ in range(nreq)]
         gaps = rng.exponential(1.0 / rate, nreq) if rate else np.zeros(nreq)
         arrivals = np.cumsum(gaps)
         tickets = []
@@ -241,8 +347,8 @@ def serving(a, torch, W, P):
         for (bi, pi), ta in zip(picks, arrivals):
             while time.perf_counter() - t0 < ta:
                 pass
-            dev = boxes[bi][2][pi][0]
-            tickets.append(sv.submit_op(ops[bi][pi], dev["f"], dev["g"])[0])
+            f, g = rhs[bi][pi]
+            tickets.append(sv.submit_op(ops[bi], f, g)[0])
         times = [sv.poll(t)[1] for t in tickets]
         sv.close()
         first = min(t[0] for t in times)
@@ -253,12 +359,14 @@ def serving(a, torch, W, P):
 
     print("serving: operator saturation", file=sys.stderr, flush=True)
     sat = run_op(a.serve_op_requests, 0.0)
-    print("serving: operator open loop", file=sys.stderr, flush=True)
-    rate = a.serve_rho * sat["solves_per_s"]
-    out["operator_f32"] = {"prep_ms": {k: float(np.mean(v)) for k, v in prep_ms.items()},
-                           "l2_error": {k: float(np.mean(v)) for k, v in op_l2.items()},
-                           "saturation_solves_per_s": sat["solves_per_s"],
-                           "open_loop": dict(run_op(a.serve_op_requests, rate), rho=a.serve_rho, arrival_rate=rate)}
+    rate = 0.8 * sat["solves_per_s"]
+    out["operator_f32_shared_coefficients"] = {
+        "prep_ms": prep_ms, "l2_error": op_l2, "saturation_solves_per_s": sat["solves_per_s"],
+        "open_loop": dict(run_op(a.serve_op_requests, rate), rho=0.8, arrival_rate=rate)}
+    for op in ops:
+        op.free()
+    for tb, _, _ in boxes:
+        tb.free()
     return out
 
 
@@ -317,17 +425,25 @@ def newton_ball(a, torch, W, P):
     out = {"workload": "3D unit ball, 4096 sites, 1024 Fibonacci boundary nodes, 1e4 walks/site, eps 1e-4, FP32; "
                        "-Lap u + u^3 = f, Newton (%d steps), Tikhonov rcond %g" % (a.newton_iters, a.newton_rcond),
            "walker_ms": t["walker_ms"], "walk_steps_per_s": inf["walk_steps"] / (t["walker_ms"] * 1e-3)}
+    us = {}
     for prec in ("f64", "mixed"):
         tb.solve(f, g, kind="semilinear_cubic", rcond=a.newton_rcond, tol=1e-300, max_iter=1, solver="tikhonov",
                  precision=prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         u, _, _, info = tb.solve(f, g, kind="semilinear_cubic", rcond=a.newton_rcond, tol=1e-300,
-                                 max_iter=a.newton_iters, solver="tikhonov", precision=prec, refine_tol=1e-8)
+                                 max_iter=a.newton_iters, solver="tikhonov", precision=prec, refine_tol=1e-10,
+                                 max_refine=30)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        us[prec] = u.cpu().numpy()
         out[prec] = {"seconds": dt, "grad_norm_rel": info["grad_norm"] / info["grad_norm0"],
-                     "rel_l2_error": float(np.sqrt(np.sum(lam * (u.cpu().numpy() - ue(x)) ** 2))) / nrm}
+                     "refine_converged": info["refine_converged"],
+                     "rel_l2_error": float(np.sqrt(np.sum(lam * (us[prec] - ue(x)) ** 2))) / nrm}
+    # the mixed route's result against the FP64 route's (same regularised
+    # system; the survey's bar for this configuration is 1e-8)
+    out["mixed_vs_f64_rel_diff_u"] = float(np.sqrt(np.sum(lam * (us["mixed"] - us["f64"]) ** 2)
+                                               / np.sum(lam * us["f64"] ** 2)))
     out["mixed_vs_f64"] = out["f64"]["seconds"] / out["mixed"]["seconds"]
     return out
 
@@ -425,40 +541,41 @@ def el_energies(a, torch, W, P):
     def grid(k):
         t = (np.arange(k) + 0.5) / k
         return np.stack(np.meshgrid(t, t, indexing="ij"), -1).reshape(-1, 2)
-    sw, sv, bn = grid(48), grid(24), W.square_nodes(40)
-    tb = P.Toolbox(W.unit_square(), sw, bn, a.el_walks, 1e-4, seed=17, precision="f32", volume_samples=1 << 20,
-                   vcentres=sv)
-    tb.build()
-    torch.cuda.synchronize()
-    lam = tb.export("lambda").cpu().numpy()
-    H = tb.export("H").cpu().numpy().astype(np.float64)
-    err = lambda u, ex: float(np.sqrt(np.sum(lam * (u - ex) ** 2) / np.sum(lam * ex ** 2)))
-    k = 2.5
-    scherk = lambda x: np.log(np.cos(k * (x[:, 1] - 0.5)) / np.cos(k * (x[:, 0] - 0.5))) / k
-    out = {"workload": "unit square, W = 48 x 48, V = 24 x 24 cell centres, 160 boundary nodes, %g walks/site, "
-                       "eps 1e-4, FP32; Adam to |grad J| <= 1e-9" % a.el_walks}
-    u, _, _, info = tb.minimize(np.zeros(tb.n), scherk(bn), 0.0, 0.01, a.el_max_iter, fbar0=0.0,
-                                energy="minimal_surface", tol=1e-9, check_every=100)
-    out["minimal_surface_scherk"] = {"k": k, "alpha": 0.01, "iters": info["iters"], "seconds": info["seconds"],
-                                     "grad_norm": info["grad_norm"],
-                                     "rel_l2_error": err(u.cpu().numpy(), scherk(sw)),
-                                     "harmonic_rel_l2_error": err(H @ scherk(bn), scherk(sw))}
-    ex = np.sin(np.pi * sw[:, 0]) * np.sin(np.pi * sw[:, 1])
-    u, _, _, info = tb.minimize(-2 * np.pi ** 2 * ex + ex ** 2, np.zeros(tb.p), 0.0, 0.1, a.el_max_iter,
-                                fbar0=0.0, energy="semilinear", tol=1e-9, check_every=100)
-    out["semilinear_sin"] = {"alpha": 0.1, "iters": info["iters"], "seconds": info["seconds"],
-                             "grad_norm": info["grad_norm"], "rel_l2_error": err(u.cpu().numpy(), ex)}
-    tb.free()
-    sites, bnd = W.paper_disk_layout()
-    tb = P.Toolbox(W.unit_disk(), sites, bnd, a.el_walks, 1e-4, seed=11, precision="f32", volume_samples=1 << 20)
-    tb.build()
-    phi = np.arctan2(bnd[:, 1], bnd[:, 0])
-    u, _, _, info = tb.minimize(np.zeros(tb.n), 0.3 * np.sin(5 * phi), 0.0, 0.01, a.el_max_iter, fbar0=1.0,
-                                energy="minimal_surface", tol=1e-6 / np.sqrt(np.pi), check_every=50)
-    out["minimal_surface_disk_paper"] = {"alpha": 0.01, "fbar0": 1.0, "iters": info["iters"],
-                                         "seconds": info["seconds"], "grad_norm": info["grad_norm"],
-                                         "J_area_over_D": info["J"], "u_range": [float(u.min()), float(u.max())]}
-    tb.free()
+    out = {"workload": "the paper's examples: semilinear (s = 800, 8000) on its 20 x 20 square layout, Adam and "
+                       "p-HiSD; elliptic div min on its disk layout; %g walks/site, eps 1e-4, FP32" % a.el_walks}
+    if a.minimal_surface:
+        sw, sv, bn = grid(48), grid(24), W.square_nodes(40)
+        tb = P.Toolbox(W.unit_square(), sw, bn, a.el_walks, 1e-4, seed=17, precision="f32", volume_samples=1 << 20,
+                       vcentres=sv)
+        tb.build()
+        torch.cuda.synchronize()
+        lam = tb.export("lambda").cpu().numpy()
+        H = tb.export("H").cpu().numpy().astype(np.float64)
+        err = lambda u, ex: float(np.sqrt(np.sum(lam * (u - ex) ** 2) / np.sum(lam * ex ** 2)))
+        k = 2.5
+        scherk = lambda x: np.log(np.cos(k * (x[:, 1] - 0.5)) / np.cos(k * (x[:, 0] - 0.5))) / k
+        u, _, _, info = tb.minimize(np.zeros(tb.n), scherk(bn), 0.0, 0.01, a.el_max_iter, fbar0=0.0,
+                                    energy="minimal_surface", tol=1e-9, check_every=100)
+        out["minimal_surface_scherk"] = {"k": k, "alpha": 0.01, "iters": info["iters"], "seconds": info["seconds"],
+                                         "grad_norm": info["grad_norm"],
+                                         "rel_l2_error": err(u.cpu().numpy(), scherk(sw)),
+                                         "harmonic_rel_l2_error": err(H @ scherk(bn), scherk(sw))}
+        ex = np.sin(np.pi * sw[:, 0]) * np.sin(np.pi * sw[:, 1])
+        u, _, _, info = tb.minimize(-2 * np.pi ** 2 * ex + ex ** 2, np.zeros(tb.p), 0.0, 0.1, a.el_max_iter,
+                                    fbar0=0.0, energy="semilinear", tol=1e-9, check_every=100)
+        out["semilinear_sin"] = {"alpha": 0.1, "iters": info["iters"], "seconds": info["seconds"],
+                                 "grad_norm": info["grad_norm"], "rel_l2_error": err(u.cpu().numpy(), ex)}
+        tb.free()
+        sites, bnd = W.paper_disk_layout()
+        tb = P.Toolbox(W.unit_disk(), sites, bnd, a.el_walks, 1e-4, seed=11, precision="f32", volume_samples=1 << 20)
+        tb.build()
+        phi = np.arctan2(bnd[:, 1], bnd[:, 0])
+        u, _, _, info = tb.minimize(np.zeros(tb.n), 0.3 * np.sin(5 * phi), 0.0, 0.01, a.el_max_iter, fbar0=1.0,
+                                    energy="minimal_surface", tol=1e-6 / np.sqrt(np.pi), check_every=50)
+        out["minimal_surface_disk_paper"] = {"alpha": 0.01, "fbar0": 1.0, "iters": info["iters"],
+                                             "seconds": info["seconds"], "grad_norm": info["grad_norm"],
+                                             "J_area_over_D": info["J"], "u_range": [float(u.min()), float(u.max())]}
+        tb.free()
     # the example "elliptic div min" on the disk layout, with its Adam
     # parameters (fbar_0 = 0.1, alpha = 0.01) to its final norm 1e-4
     sites, bnd = W.paper_disk_layout()
@@ -556,44 +673,48 @@ def main():
         cfg["walks"] = a.walks
         cfg["label"] = cfg["label"] + " (walks/site overridden: %d)" % a.walks
     prec = cfg["precision"]
+    print("headline: creating the %s toolbox" % a.workload, file=sys.stderr, flush=True)
     tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], cfg["walks"], cfg["eps"], seed=cfg["seed"],
                    precision=prec, autotune=not a.no_autotune)
+    plan = P.build_plan(cfg["domain"], cfg["sites"], cfg["bnodes"], cfg["walks"], cfg["eps"], precision=prec)
     bn = cfg["bnodes"]
     g = torch.tensor(bn[:, 0] ** 2 - bn[:, 1] ** 2, dtype=torch.float64, device="cuda")
     zero = torch.zeros(len(cfg["sites"]), dtype=torch.float64, device="cuda")
+    # HIP events around the walker launch on its own stream (the library's
+    # timing records), read after each step
+    tb.set_timing(True)
 
     def step(k):
         tb.build(seed=cfg["seed"] + 1000 + k)
         return tb.apply(zero, g)
 
     for k in range(a.warmup):
+        print("headline: warm-up step %d" % k, file=sys.stderr, flush=True)
         step(k)
     torch.cuda.synchronize()
+    kernel_ms, finalize_ms, walk_steps, walks = [], [], [], []
     t0 = time.perf_counter()
-    for k in range(a.steps):
-        step(a.warmup + k)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    # walk-steps of the timed builds: every build is a different seed, so the
-    # counts differ slightly; re-run the per-step statistics pass after timing
-    tb.set_timing(True)
-    kernel_ms = []
-    walk_steps = []
-    walks = []
     for k in range(a.steps):
         step(a.warmup + k)
         t = tb.timings()
         inf = tb.info()
         kernel_ms.append(t["walker_ms"])
+        finalize_ms.append(t["finalize_ms"])
         walk_steps.append(inf["walk_steps"])
         walks.append(inf["walks"])
+        print("headline: step %d walker %.1f ms" % (k, t["walker_ms"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
     total_steps = float(np.sum(walk_steps))
     elapsed = t1 - t0
     value = total_steps / elapsed
-    u, gu = step(0)
+    u, gu = step(a.warmup + a.steps)
     torch.cuda.synchronize()
     exact = cfg["sites"][:, 0] ** 2 - cfg["sites"][:, 1] ** 2
     herr = float(np.sqrt(np.mean((u.cpu().numpy() - exact) ** 2)))
+    tb.free()
+    del tb
+    torch.cuda.empty_cache()
 
     c_step, c_walk = WALKER_BUDGET[geometry_key(a.workload)]
     mean_steps = total_steps / a.steps
@@ -610,11 +731,15 @@ def main():
                    "walks_per_site": cfg["walks"], "eps": cfg["eps"], "seed": cfg["seed"]},
         "walker": {"kernel_ms": float(np.mean(kernel_ms)), "walk_steps_per_s": mean_steps / walker_s,
                    "walk_steps_per_build": mean_steps, "walks_per_build": mean_walks,
-                   "harmonic_extension_rms_err": herr},
+                   "column_permutation_ms": float(np.mean(finalize_ms)),
+                   "tally_mode": plan["tally_mode"], "window_pages": plan["window_pages"],
+                   "window_bpages": plan["window_bpages"], "harmonic_extension_rms_err": herr},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
                      "frac": achieved / peak, "traffic": measured_traffic(a.workload),
                      "budget": {"per_walk_step": c_step, "per_walk": c_walk}},
     }
+    if a.probe:
+        out["valu_probe_lane_ops_per_s"] = {op: P.probe_valu(op) for op in P.PROBE_OPS}
     if a.calibrate_copy > 0:
         src = torch.ones(a.calibrate_copy * (1 << 20) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -632,10 +757,17 @@ def main():
     if not a.no_el:
         print("euler-lagrange: disk p-torsion, lshape4096", file=sys.stderr, flush=True)
         out["el_plaplace"] = el_plaplace(a, torch, W, P)
-        print("euler-lagrange: minimal surface, semilinear", file=sys.stderr, flush=True)
+        print("euler-lagrange: semilinear and elliptic examples", file=sys.stderr, flush=True)
         out["el_energies"] = el_energies(a, torch, W, P)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_rows)
+        print("cpu baseline: the oracle", file=sys.stderr, flush=True)
+        _, _, share = _host_cpu()
+        procs = a.cpu_procs or max(1, min(16, share))
+        walks = a.cpu_walks or (512 if len(cfg["sites"]) > 8192 else min(cfg["walks"], 4000))
+        out["cpu_baseline"] = cpu_baseline(a.workload, walks, procs)
+        if not a.no_cpu_solves:
+            print("cpu baseline: numpy solves", file=sys.stderr, flush=True)
+            out["cpu_baseline"]["solves"] = cpu_solve_baseline()
     print(json.dumps(out), flush=True)
 
 

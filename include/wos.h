@@ -91,9 +91,11 @@ typedef struct {
                                that trigger a refill; 0 -> 48 (1 .. 64)           */
   int32_t autotune;         /* 1: the first build times the walker at each supported
                                workgroup size (256, 448, 512, 1024) on its own
-                               inputs, keeps the fastest for later builds, and
-                               synchronises the stream once; 0: the size is chosen
-                               by occupancy.  The results do not depend on it.     */
+                               inputs (the first 4096 work items of the launch),
+                               keeps the fastest for later builds, and synchronises
+                               the stream once; 0: the size is chosen by occupancy.
+                               With fixed-point LDS sums the results do not depend
+                               on it (with FP32 or FP64 sums, to rounding only).  */
   int32_t tally_mode;       /* where the walker sums a site's tallies (wos_tally_mode):
                                AUTO (0): LDS_ROWS when a site's rows fit in LDS
                                (about 8 (1 + dim) m + 12 dim p bytes <= 160 KiB),
@@ -293,7 +295,10 @@ typedef enum {
                           formed and factored in FP32 on the matrix cores, then
                           iterative refinement with FP64 residuals of the exact
                           system (matrix-free) to refine_tol; falls back to FP64 when
-                          the FP32 factorisation fails                                 */
+                          the FP32 factorisation fails.  The regularisation
+                          parameter is the FP64 route's (from exact FP64 columns
+                          of Lambda, or the exact FP64 diagonal of the Newton
+                          Hessian), so both routes solve the same system.       */
 } wos_solve_precision;
 
 typedef struct {
@@ -328,6 +333,9 @@ typedef struct {
   int32_t refine_iters;   /* MIXED: refinement steps taken                       */
   int32_t fallback;       /* MIXED: 1 when the request was solved in FP64        */
   double refine_residual; /* MIXED: final |r| / |Lambda^T rhs|                    */
+  int32_t refine_converged; /* MIXED: 1 when every refinement reached refine_tol
+                             (else it stopped at max_refine; the result is the
+                             last iterate); 1 for FP64 solves                    */
 } wos_solve_info;
 
 /* Solves a Dirichlet problem on the toolbox's domain (Sec. "Second order
@@ -627,6 +635,22 @@ wos_status wos_toolbox_get_timings(const wos_toolbox* tb, double* ms_walker, dou
                                    double* ms_finalize);
 
 void wos_toolbox_free(wos_toolbox* tb);
+
+/* Issue-rate probe of the vector ALU (the peak of the walker's roofline, which
+ * is bound by plain lane arithmetic): every lane of 32 workgroups of 256
+ * threads per compute unit runs eight independent chains of `iters`
+ * instructions of one kind, timed with HIP events on `stream` (synchronised):
+ *   WOS_PROBE_FMA_F32       v_fma_f32 (non-packed FP32 fused multiply-add)
+ *   WOS_PROBE_ADD_U32       32-bit integer add
+ *   WOS_PROBE_SIN_F32       the hardware sine (a transcendental)
+ *   WOS_PROBE_MUL_U32       32-bit integer multiply (low half)
+ *   WOS_PROBE_MUL_WIDE_U32  32 x 32 -> 64 multiply, both halves (as in Philox)
+ * *lane_ops_per_s receives instructions x lanes per second.  Allocates and
+ * frees a small device buffer.  Errors: WOS_EINVAL for an unknown op,
+ * iters < 1 or NULL; WOS_EDEVICE, WOS_ENOMEM.                                  */
+enum { WOS_PROBE_FMA_F32 = 0, WOS_PROBE_ADD_U32 = 1, WOS_PROBE_SIN_F32 = 2, WOS_PROBE_MUL_U32 = 3,
+       WOS_PROBE_MUL_WIDE_U32 = 4 };
+wos_status wos_probe_valu(int32_t op, int32_t iters, double* lane_ops_per_s, void* stream);
 
 /* Message for the last failing call of this thread ("" if none).             */
 const char* wos_last_error(void);

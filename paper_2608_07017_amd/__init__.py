@@ -83,6 +83,17 @@ def build_plan(domain, sites, bnodes, walks, eps, vcentres=None, **kw):
     return out
 
 
+PROBE_OPS = {"fma_f32": 0, "add_u32": 1, "sin_f32": 2, "mul_u32": 3, "mul_wide_u32": 4}
+
+
+def probe_valu(op, iters=4096, stream=None):
+    """Lane operations per second of one vector ALU instruction kind over the
+    whole GPU (include/wos.h, wos_probe_valu)."""
+    rate = ctypes.c_double()
+    check(lib().wos_probe_valu(PROBE_OPS[op], int(iters), ctypes.byref(rate), _stream_handle(stream)))
+    return rate.value
+
+
 class Toolbox:
     """A resident toolbox {x, z, A, B, H, K, lambda} on the current GPU."""
 

@@ -84,7 +84,8 @@ class WosSolveInfo(ctypes.Structure):
                 ("sigma_max", ctypes.c_double), ("sigma_threshold", ctypes.c_double),
                 ("grad_norm", ctypes.c_double), ("grad_norm0", ctypes.c_double),
                 ("update_norm", ctypes.c_double), ("reg", ctypes.c_double), ("refine_iters", ctypes.c_int32),
-                ("fallback", ctypes.c_int32), ("refine_residual", ctypes.c_double)]
+                ("fallback", ctypes.c_int32), ("refine_residual", ctypes.c_double),
+                ("refine_converged", ctypes.c_int32)]
 
 
 class WosAdamOpts(ctypes.Structure):
@@ -161,6 +162,7 @@ SIGNATURES = {
     "wos_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(WosSolveInfo), _D]),
     "wos_server_pending": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "wos_server_destroy": (None, [_P]),
+    "wos_probe_valu": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _D, _P]),
 }
 
 

@@ -556,8 +556,12 @@ static void fill_walker_params(const wos_toolbox* tb, uint32_t k0, uint32_t k1, 
   P.stats = tb->d_stats;
 }
 
-static wos_status launch_walker(const wos_toolbox* tb, uint32_t k0, uint32_t k1, int block, hipStream_t stream) {
-  const int items = tb->items_per_site * tb->n;
+// max_items > 0 launches only the first max_items items of the order (the
+// autotuner's timing runs)
+static wos_status launch_walker(const wos_toolbox* tb, uint32_t k0, uint32_t k1, int block, hipStream_t stream,
+                                int max_items = 0) {
+  int items = tb->items_per_site * tb->n;
+  if (max_items > 0) items = std::min(items, max_items);
   if (tb->f64) {
     WalkerParams<double> P{};
     fill_walker_params<double>(tb, k0, k1, block, P);
@@ -871,9 +875,10 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
   if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[1], stream));
 
   // walker; on the first build with autotuning, every supported workgroup
-  // size is timed on the toolbox's own inputs first and the fastest is kept
-  // (the tallies are exact fixed-point sums, so the result does not depend
-  // on the choice)
+  // size is timed on the toolbox's own inputs first (on the first 4096 items
+  // of the launch order: several waves of workgroups over the whole chip)
+  // and the fastest is kept; the timing runs' tallies are cleared before
+  // the real launch
   if (tb->autotune && tb->walker_block == 0) {
     static const int kCandidates[] = {256, 448, 512, 1024};
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -884,7 +889,7 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
     for (int bs : kCandidates) {
       WOS_TRY(zero_walker_outputs(tb, stream));
       WOS_HIP(hipEventRecord(t0, stream));
-      WOS_TRY(launch_walker(tb, k0, k1, bs, stream));
+      WOS_TRY(launch_walker(tb, k0, k1, bs, stream, 4096));
       WOS_HIP(hipEventRecord(t1, stream));
       WOS_HIP(hipEventSynchronize(t1));
       float ms = 0.0f;

@@ -80,6 +80,8 @@ size_t workspace_bytes(const wos_toolbox* tb) {
   b += 8 * (2 * (d + 1) * n + 2) + 8;
   b += 4 * ((d + 1) * n * m + 3 * m * m + m);
   b += 12 * chol_work_elems((int)m);
+  b += 8 * ((size_t)kColsqChunks + 2) * m;  // exact column norms of the mixed route
+  b += 8 * gemv_part_elems((int)std::max(m, p), 1);  // partial sums of the transposed products
   return b;
 }
 

@@ -549,20 +549,20 @@ __global__ void symmetrize_kernel(double* __restrict__ G, int M) {
   }
 }
 
-// out[0] = sum_i w_i x_i y_i (w = 1 when null); out[0] must be zeroed
-__global__ void dot_kernel(int n, const double* __restrict__ x, const double* __restrict__ y,
-                           const double* __restrict__ w, double* __restrict__ out) {
-  __shared__ double sh[256];
+// out[0] = sum_i w_i x_i y_i (w = 1 when null): one workgroup, a fixed
+// order of additions (the value does not depend on the schedule)
+__global__ __launch_bounds__(1024) void dot_kernel(int n, const double* __restrict__ x, const double* __restrict__ y,
+                                                   const double* __restrict__ w, double* __restrict__ out) {
+  __shared__ double sh[1024];
   double s = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    s += (w ? w[i] : 1.0) * x[i] * y[i];
+  for (int i = threadIdx.x; i < n; i += 1024) s += (w ? w[i] : 1.0) * x[i] * y[i];
   sh[threadIdx.x] = s;
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
+  for (int h = 512; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(out, sh[0]);
+  if (threadIdx.x == 0) out[0] = sh[0];
 }
 
 // out[0] = max_i |e_i| (as the bit pattern of a non-negative double, which
@@ -756,12 +756,7 @@ hipError_t launch_symmetrize(double* G, int M, hipStream_t st) {
 }
 
 hipError_t launch_dot(int n, const double* x, const double* y, const double* w, double* out, hipStream_t st) {
-  hipError_t e = hipMemsetAsync(out, 0, sizeof(double), st);
-  if (e != hipSuccess) return e;
-  int g = (n + 255) / 256;
-  if (g > 256) g = 256;
-  if (g < 1) g = 1;
-  hipLaunchKernelGGL(dot_kernel, dim3(g), dim3(256), 0, st, n, x, y, w, out);
+  hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(1024), 0, st, n, x, y, w, out);
   return hipGetLastError();
 }
 

@@ -73,6 +73,27 @@ void fit_work(wos_toolbox* tb, SolveWork& w) {
   w.d = tb->dim;
 }
 
+// The partial-sum buffer of the transposed products for up to nv vectors
+// of max(m, p) columns.  Grown only before a request's first launch that
+// needs more (the stream is synchronised first, as queued work may still
+// read the old buffer).
+wos_status ensure_part(wos_toolbox* tb, SolveWork& w, int nv, hipStream_t st) {
+  const size_t need = gemv_part_elems(std::max(tb->m, tb->p), nv);
+  if (w.part_cap >= need) return WOS_OK;
+  if (w.fixed) return sfail(WOS_ENOMEM, "the fixed workspace holds no room for %zu partial sums", need);
+  if (w.part) {
+    SHIP(hipStreamSynchronize(st));
+    (void)hipFree(w.part);
+    w.bytes -= w.part_cap * sizeof(double);
+    w.part = nullptr;
+    w.part_cap = 0;
+  }
+  wos_status s = walloc(w, &w.part, need);
+  if (s != WOS_OK) return s;
+  w.part_cap = need;
+  return WOS_OK;
+}
+
 wos_status ensure_work(wos_toolbox* tb, SolveWork& w) {
   fit_work(tb, w);
   if (w.ready) return WOS_OK;
@@ -237,6 +258,10 @@ wos_status dev_dot(SolveWork& w, const double* dx, const double* dy, const doubl
 wos_status ensure_tik(wos_toolbox* tb, SolveWork& w, bool mixed) {
   const size_t n = tb->n, m = tb->m, d = tb->dim;
   wos_status s;
+  if (mixed && !w.colp) {
+    if ((s = walloc(w, &w.colp, (size_t)kColsqChunks * m)) != WOS_OK) return s;
+    if ((s = walloc(w, &w.cn, 2 * m)) != WOS_OK) return s;
+  }
   if (!w.blk) {
     if ((s = walloc(w, &w.P64, chol_work_elems(m))) != WOS_OK) return s;
     if ((s = walloc(w, &w.blk, 2 * (d + 1) * std::max<size_t>(n, 1))) != WOS_OK) return s;
@@ -262,10 +287,11 @@ wos_status apply_L(wos_toolbox* tb, const double* x, double* y, hipStream_t st) 
   return WOS_OK;
 }
 // x (m) = alpha L^T y + beta x
-wos_status apply_Lt(wos_toolbox* tb, const double* y, double alpha, double beta, double* x, hipStream_t st) {
+wos_status apply_Lt(wos_toolbox* tb, SolveWork& w, const double* y, double alpha, double beta, double* x,
+                    hipStream_t st) {
   const int n = tb->n, m = tb->m, d = tb->dim;
-  SHIP(launch_gemv_t_ld(tb->f64, tb->d_B, d * n, m, m, y, alpha, beta, x, st));
-  SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, y + (size_t)d * n, alpha, 1.0, x, st));
+  SHIP(launch_gemv_t_ld(tb->f64, tb->d_B, d * n, m, m, y, alpha, beta, x, w.part, st));
+  SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, y + (size_t)d * n, alpha, 1.0, x, w.part, st));
   return WOS_OK;
 }
 // out = Lambda x (trans = false) or Lambda^T x, Lambda = L^T W L
@@ -277,7 +303,42 @@ wos_status apply_Lambda(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, con
   wos_status s;
   if ((s = apply_L(tb, x, y1, st)) != WOS_OK) return s;
   SHIP(launch_apply_w(n, d, tb->d_lambda, co->A, co->b, co->c, y1, trans, nullptr, y2, st));
-  return apply_Lt(tb, y2, 1.0, 0.0, out, st);
+  return apply_Lt(tb, w, y2, 1.0, 0.0, out, st);
+}
+
+// The regularisation parameter of the mixed route, rcond^2 max_j
+// |Lambda e_j|^2, equal to the FP64 route's (read there from the diagonal of
+// its FP64 normal matrix), so that FP64 refinement converges to the same
+// regularised system: the column norms of the FP32 Lambda (accumulated in
+// FP64) pick the candidates within 1e-5 of the largest (at most 16, largest
+// first), and those columns are formed again in FP64, matrix-free.  e and col
+// are m-vectors of work.
+wos_status mixed_tikhonov_reg(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, double rcond, double* e,
+                              double* col, hipStream_t st) {
+  const int m = tb->m;
+  SHIP(launch_colsq(false, w.Lam32, m, m, m, nullptr, 1, false, w.colp, w.cn, st));
+  std::vector<double> cn(m);
+  SHIP(hipMemcpyAsync(cn.data(), w.cn, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+  SHIP(hipStreamSynchronize(st));
+  const double mx = *std::max_element(cn.begin(), cn.end());
+  std::vector<std::pair<double, int>> cand;
+  for (int j = 0; j < m; ++j)
+    if (cn[j] >= (1.0 - 1e-5) * mx) cand.push_back({cn[j], j});
+  std::sort(cand.begin(), cand.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+    return a.first > b.first || (a.first == b.first && a.second < b.second);
+  });
+  if (cand.size() > 16) cand.resize(16);
+  double best = 0.0;
+  wos_status s;
+  for (const auto& c : cand) {
+    SHIP(launch_unit_vector(m, c.second, e, st));
+    if ((s = apply_Lambda(tb, w, co, e, false, col, st)) != WOS_OK) return s;
+    double nn = 0.0;
+    if ((s = dev_dot(w, col, col, nullptr, m, &nn, st)) != WOS_OK) return s;
+    best = std::max(best, nn);
+  }
+  SHIP(launch_set_scalar(w.regv, rcond * rcond * best, st));
+  return WOS_OK;
 }
 
 wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, double rcond, const double* f,
@@ -298,7 +359,7 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
   SHIP(launch_gemv_n_ld(tb->f64, tb->d_K, d * n, p, p, g, 1.0, 0.0, y1, st));
   SHIP(launch_gemv_n_ld(tb->f64, tb->d_H, n, p, p, g, 1.0, 0.0, y1 + (size_t)d * n, st));
   SHIP(launch_apply_w(n, d, tb->d_lambda, co->A, co->b, co->c, y1, false, f, y2, st));
-  if ((s = apply_Lt(tb, y2, -1.0, 0.0, rhs, st)) != WOS_OK) return s;
+  if ((s = apply_Lt(tb, w, y2, -1.0, 0.0, rhs, st)) != WOS_OK) return s;
   if ((s = apply_Lambda(tb, w, co, rhs, true, c, st)) != WOS_OK) return s;
   SHIP(hipMemsetAsync(w.info, 0, 2 * sizeof(int), st));
 
@@ -310,7 +371,7 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     SHIP(mfma_gemm_f32(true, false, m, m, n, 1.0f, (const float*)tb->d_A, m, w.R32 + (size_t)K * m, m, 1.0f,
                        w.Lam32, m, st));
     SHIP(mfma_gemm_lower_f32(true, false, m, m, m, 1.0f, w.Lam32, m, w.Lam32, m, 0.0f, w.N32, m, st));
-    SHIP(launch_reg_from_diag(false, w.N32, m, m, rcond * rcond, w.regv, st));
+    if ((s = mixed_tikhonov_reg(tb, w, co, rcond, r, t, st)) != WOS_OK) return s;
     SHIP(launch_add_diag(false, w.N32, m, m, w.regv, st));
     SHIP(cholesky_inverse_f32(w.N32, m, m, w.Lam32, w.P32, w.info, st));  // X = L^{-1} over Lambda's storage
     int hinfo = 0;
@@ -334,7 +395,7 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     for (it = 1; it <= maxit; ++it) {
       // q += X^T (X r): the FP32 factor's inverse applied with FP64 accumulation
       SHIP(launch_gemv_n_ld(false, w.Lam32, m, m, m, r, 1.0, 0.0, t, st));
-      SHIP(launch_gemv_t_ld(false, w.Lam32, m, m, m, t, 1.0, 1.0, q, st));
+      SHIP(launch_gemv_t_ld(false, w.Lam32, m, m, m, t, 1.0, 1.0, q, w.part, st));
       // r = c - Lambda^T Lambda q - reg q   (FP64)
       if ((s = apply_Lambda(tb, w, co, q, false, t, st)) != WOS_OK) return s;
       if ((s = apply_Lambda(tb, w, co, t, true, r, st)) != WOS_OK) return s;
@@ -346,6 +407,7 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     }
     inf->refine_iters = std::min(it, maxit);
     inf->refine_residual = cn > 0 ? rn / cn : 0.0;
+    if (!(rn <= tol * cn)) inf->refine_converged = 0;
   } else {
     // FP64: Lambda = L^T R (R = W L in FP64), N = Lambda^T Lambda + reg I
     SHIP(launch_weight_rows_any(tb->f64, false, tb->d_A, tb->d_B, tb->d_H, tb->d_K, tb->d_lambda, co->A, co->b,
@@ -364,7 +426,7 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     SHIP(launch_add_diag(true, w.Hess, m, m, w.regv, st));
     SHIP(cholesky_inverse_f64(w.Hess, m, m, w.Lam, w.P64, w.info, st));  // X = L^{-1} over Lambda's storage
     SHIP(launch_gemv_n_ld(true, w.Lam, m, m, m, c, 1.0, 0.0, t, st));
-    SHIP(launch_gemv_t_ld(true, w.Lam, m, m, m, t, 1.0, 0.0, q, st));
+    SHIP(launch_gemv_t_ld(true, w.Lam, m, m, m, t, 1.0, 0.0, q, w.part, st));
     int hinfo = 0;
     SHIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
     SHIP(hipStreamSynchronize(st));
@@ -381,14 +443,16 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
 // the refinement of the mixed route.
 template <typename F>
 wos_status sym_reg_solve(wos_toolbox* tb, SolveWork& w, bool mixed, double rcond, double tol, int maxit,
-                         const double* rhs, double* x, F applyH, wos_solve_info* inf, hipStream_t st) {
+                         const double* rhs, double* x, F applyH, const double* diag, wos_solve_info* inf,
+                         hipStream_t st) {
   const int m = tb->m;
   double* r = w.vec + 6 * w.vlen;
   double* t = w.vec + 7 * w.vlen;
   SHIP(hipMemsetAsync(w.info, 0, 2 * sizeof(int), st));
   int hinfo = 0;
   if (mixed) {
-    SHIP(launch_reg_from_diag(false, w.N32, m, m, rcond, w.regv, st));
+    // reg from the exact FP64 diagonal of H (as the FP64 route reads it)
+    SHIP(launch_reg_from_vec(diag, m, rcond, w.regv, st));
     SHIP(launch_add_diag(false, w.N32, m, m, w.regv, st));
     SHIP(cholesky_inverse_f32(w.N32, m, m, w.Lam32, w.P32, w.info, st));
     SHIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -403,7 +467,7 @@ wos_status sym_reg_solve(wos_toolbox* tb, SolveWork& w, bool mixed, double rcond
     int it = 0;
     for (it = 1; it <= maxit; ++it) {
       SHIP(launch_gemv_n_ld(false, w.Lam32, m, m, m, r, 1.0, 0.0, t, st));
-      SHIP(launch_gemv_t_ld(false, w.Lam32, m, m, m, t, 1.0, 1.0, x, st));
+      SHIP(launch_gemv_t_ld(false, w.Lam32, m, m, m, t, 1.0, 1.0, x, w.part, st));
       if ((s = applyH(x, t)) != WOS_OK) return s;
       SHIP(launch_axpy_reg(m, rhs, nullptr, -1.0, t, r, st));
       SHIP(launch_axpy_reg(m, r, w.regv, -1.0, x, r, st));
@@ -413,12 +477,13 @@ wos_status sym_reg_solve(wos_toolbox* tb, SolveWork& w, bool mixed, double rcond
     }
     inf->refine_iters = std::min(it, maxit);
     inf->refine_residual = rn0 > 0 ? rn / rn0 : 0.0;
+    if (!(rn <= tol * rn0)) inf->refine_converged = 0;
   } else {
     SHIP(launch_reg_from_diag(true, w.Hess, m, m, rcond, w.regv, st));
     SHIP(launch_add_diag(true, w.Hess, m, m, w.regv, st));
     SHIP(cholesky_inverse_f64(w.Hess, m, m, w.Lam, w.P64, w.info, st));
     SHIP(launch_gemv_n_ld(true, w.Lam, m, m, m, rhs, 1.0, 0.0, t, st));
-    SHIP(launch_gemv_t_ld(true, w.Lam, m, m, m, t, 1.0, 0.0, x, st));
+    SHIP(launch_gemv_t_ld(true, w.Lam, m, m, m, t, 1.0, 0.0, x, w.part, st));
     SHIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
     SHIP(hipStreamSynchronize(st));
     if (hinfo != 0) return sfail(WOS_ENOTCONV, "matrix not positive definite at column %d", hinfo - 1);
@@ -468,7 +533,7 @@ wos_status newton_tikhonov(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
   SHIP(launch_gemv_n_ld(tb->f64, tb->d_K, d * n, p, p, g, 1.0, 0.0, y1, st));
   SHIP(launch_gemv_n_ld(tb->f64, tb->d_H, n, p, p, g, 1.0, 0.0, y1 + (size_t)d * n, st));
   SHIP(launch_apply_w(n, d, tb->d_lambda, nullptr, nullptr, nullptr, y1, false, nullptr, y2, st));
-  if ((s = apply_Lt(tb, y2, 1.0, 0.0, sig0g, st)) != WOS_OK) return s;
+  if ((s = apply_Lt(tb, w, y2, 1.0, 0.0, sig0g, st)) != WOS_OK) return s;
   auto load_lam0 = [&]() -> wos_status {
     if (mixed)
       SHIP(hipMemcpyAsync(w.N32, w.L0_32, sizeof(float) * m * m, hipMemcpyDeviceToDevice, st));
@@ -478,10 +543,15 @@ wos_status newton_tikhonov(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
   };
   // h0: the problem without the cubic term, Lambda_0 h = A^T (lambda f) - Sigma_0 g
   SHIP(launch_pointwise(n, tb->d_lambda, nullptr, f, 0.0, 0.0, 0.0, 0.0, -1.0, t1, st));
-  SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, t1, 1.0, 0.0, grad, st));
+  SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, t1, 1.0, 0.0, grad, w.part, st));
   SHIP(launch_axpy_reg(m, grad, nullptr, -1.0, sig0g, grad, st));
   if ((s = load_lam0()) != WOS_OK) return s;
-  if ((s = sym_reg_solve(tb, w, mixed, rcond, rtol, rmax, grad, q, apply_lam0, inf, st)) != WOS_OK) return s;
+  // mixed: the exact FP64 diagonal of Lambda_0, sum_a sum_i lambda_i B^(a)_ij^2
+  double* diag0 = mixed ? w.cn : nullptr;
+  double* diagH = mixed ? w.cn + m : nullptr;
+  if (mixed)
+    SHIP(launch_colsq(tb->f64, tb->d_B, d * n, m, m, tb->d_lambda, n, false, w.colp, diag0, st));
+  if ((s = sym_reg_solve(tb, w, mixed, rcond, rtol, rmax, grad, q, apply_lam0, diag0, inf, st)) != WOS_OK) return s;
   double gn0 = -1.0, gn = 0.0;
   int it = 0;
   for (it = 0; it <= max_iter; ++it) {
@@ -489,7 +559,7 @@ wos_status newton_tikhonov(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
     // grad = A^T (lambda (kappa u^3 - f)) + Lambda_0 h + Sigma_0 g
     SHIP(launch_pointwise(n, tb->d_lambda, uu, f, 0.0, 0.0, 0.0, kappa, 1.0, t1, st));
     if ((s = apply_lam0(q, grad)) != WOS_OK) return s;
-    SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, t1, 1.0, 1.0, grad, st));
+    SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, t1, 1.0, 1.0, grad, w.part, st));
     SHIP(launch_axpy_reg(m, grad, nullptr, 1.0, sig0g, grad, st));
     if ((s = dev_dot(w, grad, grad, nullptr, m, &gn, st)) != WOS_OK) return s;
     gn = std::sqrt(gn);
@@ -510,10 +580,16 @@ wos_status newton_tikhonov(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
       if (s2 != WOS_OK) return s2;
       SHIP(launch_gemv_n_ld(tb->f64, tb->d_A, n, m, m, x, 1.0, 0.0, tmp, st));
       SHIP(launch_pointwise(n, wts, nullptr, tmp, 0.0, 0.0, 0.0, 0.0, -1.0, tmp, st));
-      SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, tmp, 1.0, 1.0, out, st));
+      SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, tmp, 1.0, 1.0, out, w.part, st));
       return WOS_OK;
     };
-    if ((s = sym_reg_solve(tb, w, mixed, rcond, rtol, rmax, grad, dlt, apply_hess, inf, st)) != WOS_OK) return s;
+    if (mixed) {
+      // the Hessian's exact diagonal: Lambda_0's plus sum_i wts_i A_ij^2
+      SHIP(hipMemcpyAsync(diagH, diag0, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+      SHIP(launch_colsq(tb->f64, tb->d_A, n, m, m, wts, n, true, w.colp, diagH, st));
+    }
+    if ((s = sym_reg_solve(tb, w, mixed, rcond, rtol, rmax, grad, dlt, apply_hess, diagH, inf, st)) != WOS_OK)
+      return s;
     SHIP(launch_axpy_reg(m, q, nullptr, -1.0, dlt, q, st));
   }
   inf->iters = it;
@@ -528,10 +604,11 @@ namespace wos {
 
 void free_work(SolveWork& w) {
   void* ptrs[] = {w.R, w.Lam, w.Sig, w.Lam0, w.Sig0, w.Hess, w.G, w.V, w.E, w.rot, w.pq, w.vec, w.Ac, w.red,
-                  w.blk, w.regv, w.info, w.R32, w.Lam32, w.N32, w.v32, w.P64, w.P32, w.L0_32, w.el, w.hs,
-                  w.hs_bad, w.hsb};
-  for (void* q : ptrs)
-    if (q) (void)hipFree(q);
+                  w.blk, w.regv, w.colp, w.cn, w.info, w.R32, w.Lam32, w.N32, w.v32, w.P64, w.P32, w.L0_32, w.el, w.hs,
+                  w.hs_bad, w.hsb, w.part};
+  if (!w.fixed)
+    for (void* q : ptrs)
+      if (q) (void)hipFree(q);
   w = SolveWork();
 }
 
@@ -552,6 +629,7 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
   const int max_sweeps = co->max_sweeps > 0 ? co->max_sweeps : 40;
   wos_status s = ensure_work(tb, w);
   if (s != WOS_OK) return s;
+  if ((s = ensure_part(tb, w, 1, st)) != WOS_OK) return s;
   const int n = tb->n, m = tb->m, d = tb->dim;
   double* rhs = w.vec + 0 * w.vlen;
   double* q = w.vec + 1 * w.vlen;
@@ -559,6 +637,7 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
   double* t1 = w.vec + 3 * w.vlen;
   double* t2 = w.vec + 4 * w.vlen;
   wos_solve_info inf{};
+  inf.refine_converged = 1;
   TsvdResult tr;
 
   if (co->kind == WOS_LINEAR && co->solver == WOS_SOLVER_TIKHONOV) {
@@ -677,6 +756,7 @@ struct ElGrad {
   double* kgv = nullptr;   // d n
   double* hg = nullptr;    // n
   double* uA = nullptr;    // n
+  double* part = nullptr;  // partial sums of the transposed products
   hipStream_t st = nullptr;
 
   // carves m + (3d + 3) n doubles from `base`; returns the first one after
@@ -701,7 +781,7 @@ struct ElGrad {
         SHIP(hipMemsetAsync(hg, 0, sizeof(double) * n, st));
     } else {
       SHIP(launch_pointwise(n, tb->d_lambda, nullptr, f, 0.0, 0.0, 0.0, 0.0, 1.0, yA, st));  // -lambda f
-      SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, yA, 1.0, 0.0, cvec, st));
+      SHIP(launch_gemv_t_ld(tb->f64, tb->d_A, n, m, m, yA, 1.0, 0.0, cvec, part, st));
     }
     if (p > 0)
       SHIP(launch_gemv_n_ld(tb->f64, tb->d_K, d * n, p, p, g, 1.0, 0.0, kgv, st));
@@ -714,8 +794,8 @@ struct ElGrad {
     SHIP(launch_gemv_n_ld(tb->f64, tb->d_B, d * n, m, m, x, 1.0, 0.0, gB, st));
     if (uterm) SHIP(launch_gemv_n_ld(tb->f64, tb->d_A, n, m, m, x, 1.0, 0.0, uA, st));
     SHIP(launch_energy_wb(kind, n, d, P, tb->d_lambda, gB, kgv, yB, uterm ? uA : nullptr, hg, f, yA, co, st));
-    SHIP(launch_gemv_t_acc(tb->f64, tb->d_B, d * n, m, m, yB, 1.0, out, st));
-    if (uterm) SHIP(launch_gemv_t_acc(tb->f64, tb->d_A, n, m, m, yA, 1.0, out, st));
+    SHIP(launch_gemv_t_acc(tb->f64, tb->d_B, d * n, m, m, yB, 1.0, out, part, st));
+    if (uterm) SHIP(launch_gemv_t_acc(tb->f64, tb->d_A, n, m, m, yA, 1.0, out, part, st));
     return WOS_OK;
   }
   wos_status eval(const double* x, double* out) {
@@ -741,12 +821,12 @@ struct ElGrad {
     double* GB = scratch;                   // nv d n
     double* UA = GB + (size_t)nv * dn;      // nv n
     double* YB = UA + (size_t)nv * n;       // nv (d + 1) n
-    SHIP(launch_gemv_batch(tb->f64, false, tb->d_B, d * n, m, m, x, m, nv, GB, (int)dn, st));
-    if (uterm) SHIP(launch_gemv_batch(tb->f64, false, tb->d_A, n, m, m, x, m, nv, UA, n, st));
+    SHIP(launch_gemv_batch(tb->f64, false, tb->d_B, d * n, m, m, x, m, nv, GB, (int)dn, part, st));
+    if (uterm) SHIP(launch_gemv_batch(tb->f64, false, tb->d_A, n, m, m, x, m, nv, UA, n, part, st));
     SHIP(launch_energy_wb_batch(kind, n, d, P, tb->d_lambda, GB, kgv, YB, uterm ? UA : nullptr, hg, f, nv, co, st));
     SHIP(launch_hisd_broadcast(m, nv, cvec, out, st));
-    SHIP(launch_gemv_batch(tb->f64, true, tb->d_B, d * n, m, m, YB, (int)(dn + n), nv, out, m, st));
-    if (uterm) SHIP(launch_gemv_batch(tb->f64, true, tb->d_A, n, m, m, YB + dn, (int)(dn + n), nv, out, m, st));
+    SHIP(launch_gemv_batch(tb->f64, true, tb->d_B, d * n, m, m, YB, (int)(dn + n), nv, out, m, part, st));
+    if (uterm) SHIP(launch_gemv_batch(tb->f64, true, tb->d_A, n, m, m, YB + dn, (int)(dn + n), nv, out, m, part, st));
     return WOS_OK;
   }
 };
@@ -789,12 +869,14 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
   if (o->max_iter <= 0) return sfail(WOS_EINVAL, "max_iter must be > 0");
   const int n = tb->n, m = tb->m, d = tb->dim;
   if (!w.el && (s = walloc(w, &w.el, (size_t)(3 * d + 4) * n + 4 * (size_t)m + 2)) != WOS_OK) return s;
+  if ((s = ensure_part(tb, w, 1, st)) != WOS_OK) return s;
   ElGrad eg;
   eg.tb = tb;
   eg.kind = kind;
   eg.P = P;
   eg.uterm = kind == WOS_EL_SEMILINEAR || kind == WOS_EL_ELLIPTIC;  // dF/du depends on u
   eg.f = f;
+  eg.part = w.part;
   eg.st = st;
   eg.co.A = o->coef_A;
   eg.co.c = o->coef_c;
@@ -938,12 +1020,14 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
     w.hs_cap = hs_len;
   }
   if (!w.hs_bad && (s = walloc(w, &w.hs_bad, 1)) != WOS_OK) return s;
+  if ((s = ensure_part(tb, w, std::min(17, 2 * k + 1), st)) != WOS_OK) return s;
   ElGrad eg;
   eg.tb = tb;
   eg.kind = kind;
   eg.P = P;
   eg.uterm = kind == WOS_EL_SEMILINEAR || kind == WOS_EL_ELLIPTIC;
   eg.f = f;
+  eg.part = w.part;
   eg.st = st;
   double* F = eg.carve(w.el);  // n
   double* red = F + n;         // 2 (the Adam route's slots are not used here)
@@ -983,7 +1067,7 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   // Y[t] = M^-1 X[t] for nv vectors: one pass over M^-1
   auto minv_batch = [&](const double* X, int nvec, double* Y) -> wos_status {
     if (useA)
-      SHIP(launch_gemv_batch(true, false, Minv, m, m, m, X, m, nvec, Y, m, st));
+      SHIP(launch_gemv_batch(true, false, Minv, m, m, m, X, m, nvec, Y, m, w.part, st));
     else
       SHIP(hipMemcpyAsync(Y, X, sizeof(double) * nvec * (size_t)m, hipMemcpyDeviceToDevice, st));
     return WOS_OK;
@@ -999,7 +1083,7 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   // synchronisation) after the first pass, at the norm checks and at the end
   auto orthonormalise = [&](double* Vx) -> wos_status {
     if (useA && k >= 2) {  // M V in one pass over A
-      SHIP(launch_gemv_batch(tb->f64, false, tb->d_A, m, m, m, Vx, m, k, MV, m, st));
+      SHIP(launch_gemv_batch(tb->f64, false, tb->d_A, m, m, m, Vx, m, k, MV, m, w.part, st));
     } else {
       for (int i = 0; i < k; ++i)
         if ((s = mult(Vx + (size_t)i * m, MV + (size_t)i * m)) != WOS_OK) return s;

@@ -12,6 +12,7 @@
 // (row block a, then site i).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "wos_solve_kernels.hpp"
@@ -89,17 +90,33 @@ __global__ void apply_w_kernel(int n, int d, const double* __restrict__ lam, con
   }
 }
 
-// y[j] += alpha sum_{r in chunk} X[r][j] v[r]  (y pre-scaled by the caller)
+// Transposed products y = X^T v over row blocks are summed deterministically:
+// block b writes its column sums to part[b][:], then gemv_reduce_kernel adds
+// the blocks in order (the result does not depend on the schedule).
+//
+// part[blockIdx.y][j] = sum_{r in chunk} X[r][j] v[r]
 template <typename T>
 __global__ __launch_bounds__(256) void gemv_t_split_kernel(const T* __restrict__ X, int rows, int cols, int ld,
-                                                           const double* __restrict__ v, double alpha,
-                                                           double* __restrict__ y, int chunk) {
+                                                           const double* __restrict__ v, double* __restrict__ part,
+                                                           int chunk) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= cols) return;
   const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
   double acc = 0.0;
   for (int r = r0; r < r1; ++r) acc += (double)X[(size_t)r * ld + j] * v[r];
-  if (acc != 0.0) atomicAdd(&y[j], alpha * acc);
+  part[(size_t)blockIdx.y * cols + j] = acc;
+}
+
+// Y[t][j] = alpha sum_b part[b][t][j] + beta Y[t][j]  (beta 0: Y not read)
+__global__ __launch_bounds__(256) void gemv_reduce_kernel(const double* __restrict__ part, int nrb, int nv, int cols,
+                                                          double alpha, double beta, double* __restrict__ Y, int ys) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int t = blockIdx.y;
+  if (j >= cols) return;
+  double s = 0.0;
+  for (int b = 0; b < nrb; ++b) s += part[((size_t)b * nv + t) * cols + j];
+  double* y = Y + (size_t)t * ys + j;
+  *y = alpha * s + (beta == 0.0 ? 0.0 : beta * *y);
 }
 
 // y[i] = alpha sum_j X[i][j] v[j] + beta y[i], one wavefront per row
@@ -131,11 +148,11 @@ __device__ __forceinline__ void load4(const float* p, double (&x)[4]) {
 // c0 + 4l .. c0 + 4l + 3 of rows r0 + w, r0 + w + 4, ... (16-byte loads, the
 // wavefront reading 1 KB of one row at a time, four rows in flight); the
 // four wavefronts' sums
-// are added in LDS and each column gets one atomic per block of `rpb` rows.
+// are added in LDS and each block writes its column sums for its `rpb` rows.
 __global__ __launch_bounds__(256) void gemv_t4_kernel(const float* __restrict__ X, int rows, int cols, int ld,
-                                                      const double* __restrict__ v, double alpha,
-                                                      double* __restrict__ y, int rpb) {
-  __shared__ double part[3][64][4];
+                                                      const double* __restrict__ v, double* __restrict__ part,
+                                                      int rpb) {
+  __shared__ double sp[3][64][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = blockIdx.x * 256 + 4 * lane;
   const int r0 = blockIdx.y * rpb, r1 = min(rows, r0 + rpb);
@@ -162,14 +179,14 @@ __global__ __launch_bounds__(256) void gemv_t4_kernel(const float* __restrict__ 
   }
   if (wave > 0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) part[wave - 1][lane][q] = acc[q];
+    for (int q = 0; q < 4; ++q) sp[wave - 1][lane][q] = acc[q];
   }
   __syncthreads();
   if (wave == 0 && c < cols) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const double t = acc[q] + part[0][lane][q] + part[1][lane][q] + part[2][lane][q];
-      if (t != 0.0) atomicAdd(&y[c + q], alpha * t);
+      const double t = acc[q] + sp[0][lane][q] + sp[1][lane][q] + sp[2][lane][q];
+      part[(size_t)blockIdx.y * cols + c + q] = t;
     }
   }
 }
@@ -241,13 +258,13 @@ __global__ __launch_bounds__(256) void gemv_n4b_kernel(const float* __restrict__
   }
 }
 
-// Y[t][j] += sum_i X[i][j] V[t][i]: the layout of gemv_t4_kernel, the four
-// wavefronts' sums added in LDS one vector at a time.
+// part[b][t][j] = sum_{i in block b} X[i][j] V[t][i]: the layout of
+// gemv_t4_kernel, the four wavefronts' sums added in LDS one vector at a time.
 template <int NV>
 __global__ __launch_bounds__(256) void gemv_t4b_kernel(const float* __restrict__ X, int rows, int cols, int ld,
-                                                       const double* __restrict__ V, int vs, double* __restrict__ Y,
-                                                       int ys, int rpb) {
-  __shared__ double part[3][64][4];
+                                                       const double* __restrict__ V, int vs, double* __restrict__ part,
+                                                       int rpb) {
+  __shared__ double sp[3][64][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = blockIdx.x * 256 + 4 * lane;
   const int r0 = blockIdx.y * rpb, r1 = min(rows, r0 + rpb);
@@ -272,14 +289,14 @@ __global__ __launch_bounds__(256) void gemv_t4b_kernel(const float* __restrict__
   for (int t = 0; t < NV; ++t) {
     if (wave > 0) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) part[wave - 1][lane][q] = acc[t][q];
+      for (int q = 0; q < 4; ++q) sp[wave - 1][lane][q] = acc[t][q];
     }
     __syncthreads();
     if (wave == 0 && c < cols) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const double s = acc[t][q] + part[0][lane][q] + part[1][lane][q] + part[2][lane][q];
-        if (s != 0.0) atomicAdd(&Y[(size_t)t * ys + c + q], s);
+        const double s = acc[t][q] + sp[0][lane][q] + sp[1][lane][q] + sp[2][lane][q];
+        part[((size_t)blockIdx.y * NV + t) * cols + c + q] = s;
       }
     }
     __syncthreads();
@@ -288,8 +305,8 @@ __global__ __launch_bounds__(256) void gemv_t4b_kernel(const float* __restrict__
 
 // The same two batched products for any row layout and either precision:
 // one wavefront per row (forward), one thread per column (transposed,
-// coalesced across the workgroup, `rpb` rows per block, one atomic per
-// column and vector per block).
+// coalesced across the workgroup, `rpb` rows per block, each block's column
+// sums to the partial-sum buffer).
 template <typename T, int NV>
 __global__ __launch_bounds__(256) void gemv_nb_kernel(const T* __restrict__ X, int rows, int cols, int ld,
                                                       const double* __restrict__ V, int vs, double* __restrict__ Y,
@@ -317,8 +334,8 @@ __global__ __launch_bounds__(256) void gemv_nb_kernel(const T* __restrict__ X, i
 
 template <typename T, int NV>
 __global__ __launch_bounds__(256) void gemv_tb_kernel(const T* __restrict__ X, int rows, int cols, int ld,
-                                                      const double* __restrict__ V, int vs, double* __restrict__ Y,
-                                                      int ys, int rpb) {
+                                                      const double* __restrict__ V, int vs, double* __restrict__ part,
+                                                      int rpb) {
   const int c = blockIdx.x * 256 + threadIdx.x;
   if (c >= cols) return;
   const int r0 = blockIdx.y * rpb, r1 = min(rows, r0 + rpb);
@@ -331,24 +348,50 @@ __global__ __launch_bounds__(256) void gemv_tb_kernel(const T* __restrict__ X, i
     for (int t = 0; t < NV; ++t) acc[t] = fma(x, V[(size_t)t * vs + r], acc[t]);
   }
 #pragma unroll
-  for (int t = 0; t < NV; ++t)
-    if (acc[t] != 0.0) atomicAdd(&Y[(size_t)t * ys + c], acc[t]);
+  for (int t = 0; t < NV; ++t) part[((size_t)blockIdx.y * NV + t) * cols + c] = acc[t];
 }
 
 bool rows16(const void* X, int ld, int cols) {
   return ((uintptr_t)X % 16) == 0 && (ld % 4) == 0 && (cols % 4) == 0;
 }
 
-// Rows per block of gemv_t4_kernel: 512 when that still gives 256 blocks
-// (fewer atomics per column measured faster than more blocks), otherwise
-// halved down to 32 so that small products are not a few long loops.
-void launch_gemv_t4(const float* X, int rows, int cols, int ld, const double* v, double alpha, double* y,
-                    hipStream_t st) {
+// Rows per block of the transposed products: `start` when that still gives
+// 256 blocks, otherwise halved down to `floor` so that small products are
+// not a few long loops; at most kMaxRowBlocks row blocks (the partial-sum
+// buffer's bound).
+int rows_per_block(int rows, int cols, int start, int floor) {
   const int cb = (cols + 255) / 256;
-  int rpb = 512;
-  while (rpb > 32 && (size_t)cb * ((rows + rpb - 1) / rpb) < 256) rpb /= 2;
-  const dim3 g4(cb, (rows + rpb - 1) / rpb);
-  hipLaunchKernelGGL(gemv_t4_kernel, g4, dim3(256), 0, st, X, rows, cols, ld, v, alpha, y, rpb);
+  int rpb = start;
+  while (rpb > floor && (size_t)cb * ((rows + rpb - 1) / rpb) < 256) rpb /= 2;
+  return std::max(rpb, (rows + kMaxRowBlocks - 1) / kMaxRowBlocks);
+}
+
+hipError_t reduce_parts(const double* part, int nrb, int nv, int cols, double alpha, double beta, double* Y, int ys,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(gemv_reduce_kernel, dim3((cols + 255) / 256, nv), dim3(256), 0, st, part, nrb, nv, cols, alpha,
+                     beta, Y, ys);
+  return hipGetLastError();
+}
+
+// y = alpha X^T v + beta y for an FP32 X with 16-byte rows
+hipError_t launch_gemv_t4(const float* X, int rows, int cols, int ld, const double* v, double alpha, double beta,
+                          double* y, double* part, hipStream_t st) {
+  const int rpb = rows_per_block(rows, cols, 512, 32);
+  const int nrb = (rows + rpb - 1) / rpb;
+  hipLaunchKernelGGL(gemv_t4_kernel, dim3((cols + 255) / 256, nrb), dim3(256), 0, st, X, rows, cols, ld, v, part,
+                     rpb);
+  return reduce_parts(part, nrb, 1, cols, alpha, beta, y, cols, st);
+}
+
+// the same for any rows: one thread per column, 128 rows per block
+template <typename T>
+hipError_t launch_gemv_t_split(const T* X, int rows, int cols, int ld, const double* v, double alpha, double beta,
+                               double* y, double* part, hipStream_t st) {
+  const int chunk = std::max(128, (rows + kMaxRowBlocks - 1) / kMaxRowBlocks);
+  const int nrb = (rows + chunk - 1) / chunk;
+  hipLaunchKernelGGL(gemv_t_split_kernel<T>, dim3((cols + 255) / 256, nrb), dim3(256), 0, st, X, rows, cols, ld, v,
+                     part, chunk);
+  return reduce_parts(part, nrb, 1, cols, alpha, beta, y, cols, st);
 }
 
 __global__ void scale_kernel(int n, double beta, double* __restrict__ y) {
@@ -371,6 +414,56 @@ __global__ __launch_bounds__(256) void reg_from_diag_kernel(const T* __restrict_
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = coef * s[0];
+}
+
+// Weighted column sums of squares, stage 1: part[c][j] = sum over the rows
+// of chunk c of w[i mod wn] X[i][j]^2 (FP64 accumulation; w NULL: 1).  One
+// thread per column, so a wavefront reads 64 consecutive values of a row.
+template <typename T>
+__global__ __launch_bounds__(256) void colsq_part_kernel(const T* __restrict__ X, int rows, int cols, int ld,
+                                                         const double* __restrict__ w, int wn, int chunk,
+                                                         double* __restrict__ part) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= cols) return;
+  const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
+  double s = 0.0;
+  for (int i = r0; i < r1; ++i) {
+    const double x = (double)X[(size_t)i * ld + j];
+    s += (w ? w[i % wn] : 1.0) * x * x;
+  }
+  part[(size_t)blockIdx.y * cols + j] = s;
+}
+
+// stage 2: out[j] (+)= sum_c part[c][j], the chunks in order (deterministic)
+__global__ void colsq_sum_kernel(const double* __restrict__ part, int nch, int cols, int accumulate,
+                                 double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  double s = accumulate ? out[j] : 0.0;
+  for (int c = 0; c < nch; ++c) s += part[(size_t)c * cols + j];
+  out[j] = s;
+}
+
+// out = coef * max_j v[j]; one workgroup
+__global__ __launch_bounds__(256) void reg_from_vec_kernel(const double* __restrict__ v, int m, double coef,
+                                                          double* __restrict__ out) {
+  __shared__ double s[256];
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) mx = fmax(mx, v[i]);
+  s[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = coef * s[0];
+}
+
+__global__ void set_scalar_kernel(double* __restrict__ out, double v) { out[0] = v; }
+
+__global__ void unit_vector_kernel(int m, int j, double* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) x[i] = i == j ? 1.0 : 0.0;
 }
 
 template <typename T>
@@ -450,41 +543,24 @@ hipError_t launch_apply_w(int n, int d, const double* lam, const double* Ac, con
   return hipGetLastError();
 }
 
+size_t gemv_part_elems(int cols, int nv) { return (size_t)kMaxRowBlocks * (size_t)std::max(nv, 1) * (size_t)cols; }
+
 hipError_t launch_gemv_t_ld(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
-                            double beta, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(scale_kernel, dim3(nblocks(cols, 256)), dim3(256), 0, st, cols, beta, y);
-  if (rows <= 0) return hipGetLastError();
-  if (!f64 && rows16(X, ld, cols)) {
-    launch_gemv_t4((const float*)X, rows, cols, ld, v, alpha, y, st);
+                            double beta, double* y, double* part, hipStream_t st) {
+  if (cols <= 0) return hipSuccess;
+  if (rows <= 0) {
+    hipLaunchKernelGGL(scale_kernel, dim3(nblocks(cols, 256)), dim3(256), 0, st, cols, beta, y);
     return hipGetLastError();
   }
-  const int chunk = 128;
-  const dim3 g((cols + 255) / 256, (rows + chunk - 1) / chunk);
-  if (f64)
-    hipLaunchKernelGGL(gemv_t_split_kernel<double>, g, dim3(256), 0, st, (const double*)X, rows, cols, ld, v, alpha, y,
-                       chunk);
-  else
-    hipLaunchKernelGGL(gemv_t_split_kernel<float>, g, dim3(256), 0, st, (const float*)X, rows, cols, ld, v, alpha, y,
-                       chunk);
-  return hipGetLastError();
+  if (!f64 && rows16(X, ld, cols)) return launch_gemv_t4((const float*)X, rows, cols, ld, v, alpha, beta, y, part, st);
+  if (f64) return launch_gemv_t_split((const double*)X, rows, cols, ld, v, alpha, beta, y, part, st);
+  return launch_gemv_t_split((const float*)X, rows, cols, ld, v, alpha, beta, y, part, st);
 }
 
 hipError_t launch_gemv_t_acc(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
-                             double* y, hipStream_t st) {
+                             double* y, double* part, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  if (!f64 && rows16(X, ld, cols)) {
-    launch_gemv_t4((const float*)X, rows, cols, ld, v, alpha, y, st);
-    return hipGetLastError();
-  }
-  const int chunk = 128;
-  const dim3 g((cols + 255) / 256, (rows + chunk - 1) / chunk);
-  if (f64)
-    hipLaunchKernelGGL(gemv_t_split_kernel<double>, g, dim3(256), 0, st, (const double*)X, rows, cols, ld, v, alpha, y,
-                       chunk);
-  else
-    hipLaunchKernelGGL(gemv_t_split_kernel<float>, g, dim3(256), 0, st, (const float*)X, rows, cols, ld, v, alpha, y,
-                       chunk);
-  return hipGetLastError();
+  return launch_gemv_t_ld(f64, X, rows, cols, ld, v, alpha, 1.0, y, part, st);
 }
 
 hipError_t launch_gemv_n_ld(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
@@ -526,7 +602,7 @@ hipError_t launch_gemv_n4_batch(const float* X, int rows, int cols, int ld, cons
 
 template <typename T>
 hipError_t gemv_batch_generic(bool trans, const T* X, int rows, int cols, int ld, const double* V, int vs, int nv,
-                              double* Y, int ys, hipStream_t st) {
+                              double* Y, int ys, double* part, hipStream_t st) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
   if (!trans) {
     const dim3 g((rows + 3) / 4);
@@ -541,56 +617,89 @@ hipError_t gemv_batch_generic(bool trans, const T* X, int rows, int cols, int ld
         return hipErrorInvalidValue;
     }
   } else {
-    const int cb = (cols + 255) / 256;
-    int rpb = 512;
-    while (rpb > 16 && (size_t)cb * ((rows + rpb - 1) / rpb) < 256) rpb /= 2;
-    const dim3 g(cb, (rows + rpb - 1) / rpb);
+    const int rpb = rows_per_block(rows, cols, 512, 16);
+    const int nrb = (rows + rpb - 1) / rpb;
+    const dim3 g((cols + 255) / 256, nrb);
     switch (nv) {
 #define WOS_CASE(N_)                                                                                          \
   case N_:                                                                                                    \
-    hipLaunchKernelGGL((gemv_tb_kernel<T, N_>), g, dim3(256), 0, st, X, rows, cols, ld, V, vs, Y, ys, rpb);     \
+    hipLaunchKernelGGL((gemv_tb_kernel<T, N_>), g, dim3(256), 0, st, X, rows, cols, ld, V, vs, part, rpb);      \
     break;
       WOS_NV_CASES(WOS_CASE)
 #undef WOS_CASE
       default:
         return hipErrorInvalidValue;
     }
+    return reduce_parts(part, nrb, nv, cols, 1.0, 1.0, Y, ys, st);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_gemv_batch(bool f64, bool trans, const void* X, int rows, int cols, int ld, const double* V, int vs,
-                             int nv, double* Y, int ys, hipStream_t st) {
+                             int nv, double* Y, int ys, double* part, hipStream_t st) {
   const bool odd = nv >= 3 && nv <= 17 && (nv & 1);  // the 4-wide kernels' counts
   if (!f64 && odd && rows16(X, ld, cols))
-    return trans ? launch_gemv_t4_batch((const float*)X, rows, cols, ld, V, vs, nv, Y, ys, st)
+    return trans ? launch_gemv_t4_batch((const float*)X, rows, cols, ld, V, vs, nv, Y, ys, part, st)
                  : launch_gemv_n4_batch((const float*)X, rows, cols, ld, V, vs, nv, Y, ys, st);
-  if (f64) return gemv_batch_generic<double>(trans, (const double*)X, rows, cols, ld, V, vs, nv, Y, ys, st);
-  return gemv_batch_generic<float>(trans, (const float*)X, rows, cols, ld, V, vs, nv, Y, ys, st);
+  if (f64) return gemv_batch_generic<double>(trans, (const double*)X, rows, cols, ld, V, vs, nv, Y, ys, part, st);
+  return gemv_batch_generic<float>(trans, (const float*)X, rows, cols, ld, V, vs, nv, Y, ys, part, st);
 }
 
 hipError_t launch_gemv_t4_batch(const float* X, int rows, int cols, int ld, const double* V, int vs, int nv,
-                                double* Y, int ys, hipStream_t st) {
+                                double* Y, int ys, double* part, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   if (!rows16(X, ld, cols)) return hipErrorInvalidValue;
-  const int cb = (cols + 255) / 256;
-  int rpb = 512;
-  while (rpb > 32 && (size_t)cb * ((rows + rpb - 1) / rpb) < 256) rpb /= 2;
-  const dim3 g(cb, (rows + rpb - 1) / rpb);
+  const int rpb = rows_per_block(rows, cols, 512, 32);
+  const int nrb = (rows + rpb - 1) / rpb;
+  const dim3 g((cols + 255) / 256, nrb);
   switch (nv) {
 #define WOS_CASE(N_)                                                                                           \
   case N_:                                                                                                     \
-    hipLaunchKernelGGL(gemv_t4b_kernel<N_>, g, dim3(256), 0, st, X, rows, cols, ld, V, vs, Y, ys, rpb);        \
+    hipLaunchKernelGGL(gemv_t4b_kernel<N_>, g, dim3(256), 0, st, X, rows, cols, ld, V, vs, part, rpb);         \
     break;
     WOS_NV_CASES(WOS_CASE)
 #undef WOS_CASE
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+  return reduce_parts(part, nrb, nv, cols, 1.0, 1.0, Y, ys, st);
 }
 #undef WOS_NV_CASES
 #undef WOS_NV_ALL
+
+int colsq_chunks(int rows) { return std::max(1, std::min(kColsqChunks, (rows + 127) / 128)); }
+
+hipError_t launch_colsq(bool f64, const void* X, int rows, int cols, int ld, const double* w, int wn, bool accumulate,
+                        double* part, double* out, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const int nch = colsq_chunks(rows);
+  const int chunk = (rows + nch - 1) / nch;
+  const dim3 g((cols + 255) / 256, nch);
+  if (f64)
+    hipLaunchKernelGGL(colsq_part_kernel<double>, g, dim3(256), 0, st, (const double*)X, rows, cols, ld, w,
+                       std::max(wn, 1), chunk, part);
+  else
+    hipLaunchKernelGGL(colsq_part_kernel<float>, g, dim3(256), 0, st, (const float*)X, rows, cols, ld, w,
+                       std::max(wn, 1), chunk, part);
+  hipLaunchKernelGGL(colsq_sum_kernel, dim3((cols + 255) / 256), dim3(256), 0, st, part, nch, cols,
+                     accumulate ? 1 : 0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reg_from_vec(const double* v, int m, double coef, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(reg_from_vec_kernel, dim3(1), dim3(256), 0, st, v, m, coef, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_scalar(double* out, double v, hipStream_t st) {
+  hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, st, out, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_unit_vector(int m, int j, double* x, hipStream_t st) {
+  hipLaunchKernelGGL(unit_vector_kernel, dim3((m + 255) / 256), dim3(256), 0, st, m, j, x);
+  return hipGetLastError();
+}
 
 hipError_t launch_reg_from_diag(bool f64, const void* N, int m, int ld, double coef, double* out, hipStream_t st) {
   if (f64)

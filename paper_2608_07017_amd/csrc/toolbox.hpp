@@ -52,6 +52,8 @@ struct SolveWork {
   // regularised solve
   double* blk = nullptr;    // 2 block vectors of (d+1) n
   double* regv = nullptr;   // the regularisation parameter (device)
+  double* colp = nullptr;   // column sums of squares: kColsqChunks x m partial sums
+  double* cn = nullptr;     // 2 m: exact FP64 column sums of squares (diagonals)
   int* info = nullptr;      // Cholesky status (device)
   float* R32 = nullptr;     // (d+1) n x m weighted rows, FP32
   float* Lam32 = nullptr;   // m x m
@@ -65,6 +67,9 @@ struct SolveWork {
   size_t hs_cap = 0;        // doubles held at hs
   int* hs_bad = nullptr;    // p-HiSD: Gram-Schmidt status (device)
   double* hsb = nullptr;    // p-HiSD, batched gradients: 17 (2d + 2) n doubles
+  double* part = nullptr;   // partial sums of the transposed products (gemv_part_elems)
+  size_t part_cap = 0;      // doubles held at part
+  bool fixed = false;       // every buffer is provided by the caller: allocate nothing
   size_t bytes = 0;         // device memory held
 };
 

@@ -59,12 +59,18 @@ hipError_t launch_energy_wb_batch(int kind, int n, int d, double P, const double
 hipError_t launch_gemv_n4_batch(const float* X, int rows, int cols, int ld, const double* V, int vs, int nv,
                                 double* Y, int ys, hipStream_t st);
 hipError_t launch_gemv_t4_batch(const float* X, int rows, int cols, int ld, const double* V, int vs, int nv,
-                                double* Y, int ys, hipStream_t st);
+                                double* Y, int ys, double* part, hipStream_t st);
 // the same for any storage (FP32 rows of 16 bytes take the 4-wide kernels
 // above): Y[t] = X V[t] (trans false; nv in 1..17) or Y[t] += X^T V[t]
 // (trans true; nv odd in 3..17)
 hipError_t launch_gemv_batch(bool f64, bool trans, const void* X, int rows, int cols, int ld, const double* V, int vs,
-                             int nv, double* Y, int ys, hipStream_t st);
+                             int nv, double* Y, int ys, double* part, hipStream_t st);
+// The transposed products (X^T v) sum over row blocks deterministically:
+// every block writes its column sums to `part`, a buffer of
+// gemv_part_elems(cols, nv) doubles, and a second kernel adds the blocks in
+// order.  At most kMaxRowBlocks row blocks.
+constexpr int kMaxRowBlocks = 128;
+size_t gemv_part_elems(int cols, int nv);
 hipError_t launch_adam(int m, double* g, double b1, double b2, double eps, double aj, double* mv, double* vv,
                        double* fbar, const double* reset, hipStream_t st);
 hipError_t launch_picard_coef(int n, int d, const double* u, double* Ac, hipStream_t st);
@@ -108,11 +114,23 @@ hipError_t launch_apply_w(int n, int d, const double* lam, const double* Ac, con
                           const double* y, bool trans, const double* f, double* z, hipStream_t st);
 // y += alpha X^T v (no scaling of y first)
 hipError_t launch_gemv_t_acc(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
-                             double* y, hipStream_t st);
+                             double* y, double* part, hipStream_t st);
 hipError_t launch_gemv_t_ld(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
-                            double beta, double* y, hipStream_t st);
+                            double beta, double* y, double* part, hipStream_t st);
 hipError_t launch_gemv_n_ld(bool f64, const void* X, int rows, int cols, int ld, const double* v, double alpha,
                             double beta, double* y, hipStream_t st);
+// Weighted column sums of squares with FP64 accumulation, deterministic:
+// out[j] (+)= sum_i w[i mod wn] X[i][j]^2 (w NULL: 1); part holds
+// kColsqChunks x cols doubles.
+constexpr int kColsqChunks = 64;
+int colsq_chunks(int rows);
+hipError_t launch_colsq(bool f64, const void* X, int rows, int cols, int ld, const double* w, int wn, bool accumulate,
+                        double* part, double* out, hipStream_t st);
+// out = coef * max_j v[j]
+hipError_t launch_reg_from_vec(const double* v, int m, double coef, double* out, hipStream_t st);
+hipError_t launch_set_scalar(double* out, double v, hipStream_t st);
+// x = e_j (m entries)
+hipError_t launch_unit_vector(int m, int j, double* x, hipStream_t st);
 // out = coef * max_i N[i][i]
 hipError_t launch_reg_from_diag(bool f64, const void* N, int m, int ld, double coef, double* out, hipStream_t st);
 // Y = diag(w) X (rows x cols)

@@ -302,7 +302,9 @@ def _same_walks_fp32(g1, g2, walks):
     centres in another order: every exit counted once in both, a walk binned
     to the other of two equidistant nodes at most about once per 1e5 walks
     (exact FP32 ties), and otherwise the matrices equal to summation
-    rounding."""
+    rounding: the windowed sums are FP32 (relative rounding up to about
+    1e-5 of a cell that takes thousands of tallies, such as a site's own),
+    the row mode's exact fixed point."""
     h1, h2 = g1["Hcount"], g2["Hcount"]
     assert np.array_equal(h1.sum(1), h2.sum(1))
     moved = np.abs(h1 - h2).sum()
@@ -310,12 +312,12 @@ def _same_walks_fp32(g1, g2, walks):
     tied = h1 != h2                                     # entries a tie moved an exit into or out of
     for key in ("A", "B"):
         mass = np.abs(g1[key]).sum(axis=-1, keepdims=True)
-        assert np.all(np.abs(g1[key] - g2[key]) <= 1e-5 * mass), key
+        assert np.all(np.abs(g1[key] - g2[key]) <= 1e-4 * mass), key
     mass = np.abs(g1["K"]).sum(axis=-1, keepdims=True)
-    ok = np.abs(g1["K"] - g2["K"]) <= 1e-5 * mass
+    ok = np.abs(g1["K"] - g2["K"]) <= 1e-4 * mass
     assert np.all(ok | tied[None]), "K"
     # the row sums of K hold every exit's weight in both
-    assert np.allclose(g1["K"].sum(-1), g2["K"].sum(-1), rtol=1e-5, atol=1e-5 * mass[..., 0].max())
+    assert np.allclose(g1["K"].sum(-1), g2["K"].sum(-1), rtol=1e-4, atol=1e-4 * mass[..., 0].max())
 
 
 def test_rows_beyond_lds_fp64_sampled():

@@ -72,7 +72,9 @@ def test_results_same_alone_and_in_the_mix(toolboxes):
         ti, pi, prec = key
         lam = toolboxes[ti][1]
         ref = alone[key]
-        assert _lam_err(u.cpu().numpy(), ref, lam) <= 1e-9 * np.sqrt(np.sum(lam * ref ** 2)), key
+        # every reduction of the solve path has a fixed order: the result of a
+        # request is the same bits alone and in the mix
+        assert np.array_equal(u.cpu().numpy(), ref), (key, _lam_err(u.cpu().numpy(), ref, lam))
     assert sv.pending() == (0, 0)
     sv.close()
 
