@@ -357,6 +357,22 @@ typedef struct {
 wos_status wos_solve(wos_toolbox* tb, const wos_coeffs* coeffs, const double* f, const double* g,
                      double* u, double* grad_u, double* q, wos_solve_info* info, void* stream);
 
+/* wos_solve for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve, for kind LINEAR with solver TIKHONOV in FP64 only, with every work
+ * buffer taken from one fixed device array of 64 MiB that the library holds
+ * on each GPU it runs on until the process ends (instead of the toolbox's
+ * workspace).  Arguments, results and synchronisation as for wos_solve; the
+ * results are the same bits.  Calls no hipMalloc or hipFree.  The array is
+ * shared by every call on one GPU and keeps the last call's contents (each
+ * call writes what it reads): calls that overlap on one GPU race.  Work
+ * needed: about 8 ((d+1) n m + 2 m^2 + 128 max(m, p) + 10 max(n, m, p, d n))
+ * bytes plus the Cholesky work, i.e. m up to about 1100 sites in 2-D.
+ * Errors: WOS_EINVAL for another kind, solver or precision (or as wos_solve);
+ * WOS_ENOMEM when the work exceeds the array (nothing is launched).          */
+wos_status wos_solve_noalloc(wos_toolbox* tb, const wos_coeffs* coeffs, const double* f, const double* g, double* u,
+                             double* grad_u, double* q, wos_solve_info* info, void* stream);
+
 /* Evaluation off the sites (the approximations of u on the partition after
  * eq. min_el_discrete in Sec. "Euler-Lagrange boundary value problems"):
  * each point x_k is binned to its nearest site x_i (the Voronoi cell W_i,

@@ -209,6 +209,20 @@ class Toolbox:
                               ctypes.byref(info), _stream_handle(stream)))
         return u, gu, q, {k: getattr(info, k) for k, _ in info._fields_}
 
+    def solve_noalloc(self, f, g, u, grad_u, q, A=None, b=None, c=None, rcond=1e-3, stream=None):
+        """The FP64 Tikhonov solve of a linear problem into caller-provided
+        outputs u (n,), grad_u (d, n) or None, q (m,) or None, with the
+        library's fixed work array (include/wos.h, wos_solve_noalloc): no
+        device allocation by the library.  Returns the info dict."""
+        f, g, A, b, c, co = self._coeffs(f, g, "linear", A, b, c, 1.0, rcond, 0.0, 0, 0, "tikhonov", "f64", 0, 0.0)
+        info = WosSolveInfo()
+        null = ctypes.c_void_p(0)
+        check(lib().wos_solve_noalloc(self._h, ctypes.byref(co), _dptr(f), _dptr(g), _dptr(u),
+                                      _dptr(grad_u) if grad_u is not None else null,
+                                      _dptr(q) if q is not None else null, ctypes.byref(info),
+                                      _stream_handle(stream)))
+        return {k: getattr(info, k) for k, _ in info._fields_}
+
     def take(self, other, estimators, stream=None):
         """Copy the estimators named in `estimators` (any of "A", "B", "H",
         "K") from `other`, a toolbox built on the same domain, sites and

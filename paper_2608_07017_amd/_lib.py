@@ -138,6 +138,8 @@ SIGNATURES = {
     "wos_apply": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "wos_solve": (ctypes.c_int, [_P, ctypes.POINTER(WosCoeffs), _P, _P, _P, _P, _P,
                                  ctypes.POINTER(WosSolveInfo), _P]),
+    "wos_solve_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(WosCoeffs), _P, _P, _P, _P, _P,
+                                         ctypes.POINTER(WosSolveInfo), _P]),
     "wos_interpolate": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "wos_toolbox_take": (ctypes.c_int, [_P, _P, ctypes.c_uint32, _P]),
     "wos_minimize": (ctypes.c_int, [_P, ctypes.POINTER(WosAdamOpts), _P, _P, _P, _P, _P,
