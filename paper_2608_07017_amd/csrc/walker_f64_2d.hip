@@ -1,0 +1,22 @@
+// Walker instantiations: double, d = 2 (disk, box and polygon, each with the
+// median-of-three or the exact radial sampler).
+#include "walker_impl.hpp"
+
+namespace wos {
+
+hipError_t walker_dispatch_f64_2d(const WalkerParams<double>& P, int kind, size_t lds, int items, hipStream_t st) {
+  switch (kind) {
+    case WOS_BALL:
+      return P.exact_radius ? launch_typed<double, 2, WOS_BALL | kExactRadius>(P, lds, items, st)
+                            : launch_typed<double, 2, WOS_BALL>(P, lds, items, st);
+    case WOS_BOX:
+      return P.exact_radius ? launch_typed<double, 2, WOS_BOX | kExactRadius>(P, lds, items, st)
+                            : launch_typed<double, 2, WOS_BOX>(P, lds, items, st);
+    case WOS_POLYGON:
+      return P.exact_radius ? launch_typed<double, 2, WOS_POLYGON | kExactRadius>(P, lds, items, st)
+                            : launch_typed<double, 2, WOS_POLYGON>(P, lds, items, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace wos

@@ -203,15 +203,23 @@ __device__ __forceinline__ T centre_d2(const T* pts, int j, const T* q) {
   return d2;
 }
 
+// A point passed by value: the rare overflow lookup below is a real call,
+// and a pointer to the caller's coordinates would force them (and any array
+// they sit in) out of registers into scratch memory.
 template <typename T, int D>
-__device__ __noinline__ int grid_overflow(const GridDev<T>& g, const T* pts, int code, const T* q) {
+struct PointV {
+  T x[D];
+};
+
+template <typename T, int D>
+__device__ __noinline__ int grid_overflow(const GridDev<T>& g, const T* pts, int code, PointV<T, D> q) {
   const int* lst = g.list + (-code - 1);
   const int cnt = lst[0];
   int bj = lst[1];
-  T best = centre_d2<T, D>(pts, bj, q);
+  T best = centre_d2<T, D>(pts, bj, q.x);
   for (int c = 1; c < cnt; ++c) {
     const int j = lst[1 + c];
-    const T d2 = centre_d2<T, D>(pts, j, q);
+    const T d2 = centre_d2<T, D>(pts, j, q.x);
     if (d2 < best) {
       best = d2;
       bj = j;
@@ -225,7 +233,12 @@ __device__ __noinline__ int grid_overflow(const GridDev<T>& g, const T* pts, int
 // bandwidth, not issue slots, is what the lookups cost).
 template <typename T, int D>
 __device__ __forceinline__ int grid_resolve(const GridDev<T>& g, const T* pts, int4 r, const T* q) {
-  if (r.x < 0) return grid_overflow<T, D>(g, pts, r.x, q);
+  if (r.x < 0) {
+    PointV<T, D> qv;
+#pragma unroll
+    for (int a = 0; a < D; ++a) qv.x[a] = q[a];
+    return grid_overflow<T, D>(g, pts, r.x, qv);
+  }
   int bj = r.x;
   if (r.y != r.x) {
     T best = centre_d2<T, D>(pts, r.x, q);
