@@ -238,7 +238,9 @@ typedef enum {
   WOS_EXPORT_HCOUNT = 4,  /* n x p,      uint32 exit counts            */
   WOS_EXPORT_LAMBDA = 5,  /* n,          double lambda_i               */
   WOS_EXPORT_VCOUNT = 6,  /* n,          uint64 volume-point counts    */
-  WOS_EXPORT_LAMBDA_V = 7 /* m,          double |V_j| / |D| (= lambda when V = W) */
+  WOS_EXPORT_LAMBDA_V = 7, /* m,         double |V_j| / |D| (= lambda when V = W) */
+  WOS_EXPORT_SITE_STEPS = 8 /* n,        uint64 walk-steps of each site's walks of the
+                               last build (k = 0 tallies plus chain tallies)      */
 } wos_export_what;
 
 /* Copies one toolbox array into dst (device if dst_is_device, else host),
@@ -649,6 +651,24 @@ void wos_server_destroy(wos_server* sv);
 wos_status wos_toolbox_set_timing(wos_toolbox* tb, int32_t enable);
 wos_status wos_toolbox_get_timings(const wos_toolbox* tb, double* ms_walker, double* ms_volume,
                                    double* ms_finalize);
+
+/* Storing a built toolbox for later use (the toolbox of eq. LOT is
+ * precomputed once and reused with any coefficients and data).
+ * wos_toolbox_save writes the toolbox's inputs (domain, centres, nodes,
+ * build options), its statistics and its arrays (A, B, H, K, the exit
+ * counts, lambda and the volume counts, and the V partition's volumes) to
+ * `path` in a versioned binary format (little endian, tagged sections; see
+ * csrc/persist.cpp); it synchronises the last build's stream.
+ * wos_toolbox_load reads such a file: it creates the toolbox from the stored
+ * inputs (the grids are rebuilt) and copies the stored arrays into its device
+ * memory, so every export, apply and solve of the loaded toolbox gives the
+ * same bits as the saved one.  Host memory for staging: 64 MiB.
+ * Errors: WOS_EINVAL for NULL arguments, an unbuilt toolbox, an unreadable
+ * or unwritable file, a wrong magic or version or malformed sections
+ * (checked before any device allocation where the header is at fault);
+ * WOS_ENOMEM, WOS_EDEVICE.                                                    */
+wos_status wos_toolbox_save(const wos_toolbox* tb, const char* path);
+wos_status wos_toolbox_load(const char* path, void* stream, wos_toolbox** out);
 
 void wos_toolbox_free(wos_toolbox* tb);
 

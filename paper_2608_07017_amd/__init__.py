@@ -145,6 +145,29 @@ class Toolbox:
         check(lib().wos_toolbox_build(self._h, s, _stream_handle(stream)))
         return self
 
+    def save(self, path):
+        """Write the built toolbox to `path` (include/wos.h, wos_toolbox_save)."""
+        check(lib().wos_toolbox_save(self._h, str(path).encode()))
+
+    @classmethod
+    def load(cls, path, stream=None):
+        """A toolbox read from a file written by save() (include/wos.h,
+        wos_toolbox_load): the same inputs, options and arrays."""
+        h = ctypes.c_void_p()
+        check(lib().wos_toolbox_load(str(path).encode(), _stream_handle(stream), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self._h = h
+        inf = WosToolboxInfo()
+        check(lib().wos_toolbox_get_info(h, ctypes.byref(inf)))
+        self.dim, self.n, self.m, self.p = inf.dim, inf.n, inf.m, inf.p
+        self.precision = "f64" if inf.precision == 1 else "f32"
+        self.dtype = torch.float64 if self.precision == "f64" else torch.float32
+        self.walks = inf.walks_per_site
+        self.domain = None
+        self.sites = self.vcentres = self.bnodes = None
+        self.seed = 0
+        return self
+
     def set_timing(self, enable=True):
         check(lib().wos_toolbox_set_timing(self._h, 1 if enable else 0))
 
@@ -165,7 +188,7 @@ class Toolbox:
         return {"A": ((n, m), self.dtype), "B": ((d, n, m), self.dtype), "H": ((n, p), self.dtype),
                 "K": ((d, n, p), self.dtype), "Hcount": ((n, p), torch.int32),
                 "lambda": ((n,), torch.float64), "vcount": ((n,), torch.int64),
-                "lambda_v": ((m,), torch.float64)}[what]
+                "lambda_v": ((m,), torch.float64), "site_steps": ((n,), torch.int64)}[what]
 
     def export(self, what, stream=None):
         """A copy of one toolbox array as a device tensor (Hcount as int32

@@ -16,7 +16,7 @@ STATUS = {0: "WOS_OK", -1: "WOS_EINVAL", -2: "WOS_EDOMAIN", -3: "WOS_ENOMEM", -4
           -5: "WOS_ENOTCONV", -6: "WOS_EBUSY", -7: "WOS_ENOTIMPL"}
 KINDS = {"ball": 1, "box": 2, "polygon": 3, "box_minus_ball": 4}
 PRECISION = {"f32": 0, "f64": 1}
-EXPORTS = {"A": 0, "B": 1, "H": 2, "K": 3, "Hcount": 4, "lambda": 5, "vcount": 6, "lambda_v": 7}
+EXPORTS = {"A": 0, "B": 1, "H": 2, "K": 3, "Hcount": 4, "lambda": 5, "vcount": 6, "lambda_v": 7, "site_steps": 8}
 
 
 class WosDomain(ctypes.Structure):
@@ -149,6 +149,8 @@ SIGNATURES = {
     "wos_toolbox_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "wos_toolbox_get_timings": (ctypes.c_int, [_P, _D, _D, _D]),
     "wos_toolbox_free": (None, [_P]),
+    "wos_toolbox_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "wos_toolbox_load": (ctypes.c_int, [ctypes.c_char_p, _P, ctypes.POINTER(_P)]),
     "wos_last_error": (ctypes.c_char_p, []),
     "wos_version": (ctypes.c_char_p, []),
     "wos_server_create": (ctypes.c_int, [ctypes.POINTER(WosServerOpts), ctypes.POINTER(_P)]),

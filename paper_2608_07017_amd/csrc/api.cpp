@@ -267,7 +267,7 @@ void release(wos_toolbox* tb) {
                   tb->d_sites_f64, tb->d_bnodes, tb->d_segs, tb->d_verts, tb->d_A, tb->d_B,
                   tb->d_K, tb->d_H, tb->d_Hc, tb->d_vcount, tb->d_stats, tb->d_lambda,
                   tb->d_item_order, tb->gv_r.rec, tb->gv_r.list, tb->gg_r.rec, tb->gg_r.list,
-                  tb->d_vsites_r, tb->d_bnodes_r, tb->d_vrank, tb->d_brank, tb->d_win};
+                  tb->d_vsites_r, tb->d_bnodes_r, tb->d_vrank, tb->d_brank, tb->d_win, tb->d_site_steps};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (tb->wv) {  // the V-side arrays are separate allocations only with a V partition of their own
@@ -501,6 +501,7 @@ static wos_status zero_walker_outputs(wos_toolbox* tb, hipStream_t stream) {
   const size_t ts = tsize(tb);
   const size_t n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
   WOS_HIP(hipMemsetAsync(tb->d_stats, 0, 4 * 8, stream));
+  WOS_HIP(hipMemsetAsync(tb->d_site_steps, 0, 8 * n, stream));
   if (tb->items_per_site != 1 || tb->global_tally) {
     WOS_HIP(hipMemsetAsync(tb->d_A, 0, ts * n * m, stream));
     WOS_HIP(hipMemsetAsync(tb->d_B, 0, ts * d * n * m, stream));
@@ -554,6 +555,7 @@ static void fill_walker_params(const wos_toolbox* tb, uint32_t k0, uint32_t k1, 
   P.Hc = tb->d_Hc;
   P.K = static_cast<T*>(tb->d_K);
   P.stats = tb->d_stats;
+  P.site_steps = tb->d_site_steps;
 }
 
 // max_items > 0 launches only the first max_items items of the order (the
@@ -798,6 +800,7 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
   TRY(dev_alloc(tb, (void**)&tb->d_Hc, 4 * (size_t)n * p));
   TRY(dev_alloc(tb, (void**)&tb->d_vcount, 8 * (size_t)n));
   TRY(dev_alloc(tb, (void**)&tb->d_stats, 8 * 8));
+  TRY(dev_alloc(tb, (void**)&tb->d_site_steps, 8 * (size_t)n));
   TRY(dev_alloc(tb, (void**)&tb->d_lambda, 8 * (size_t)n));
   if (wv) {
     TRY(dev_alloc(tb, (void**)&tb->d_vcount_v, 8 * (size_t)m));
@@ -824,6 +827,7 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
   const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFull), k1 = (uint32_t)(seed >> 32);
 
   WOS_HIP(hipMemsetAsync(tb->d_stats, 0, 8 * 8, stream));
+  WOS_HIP(hipMemsetAsync(tb->d_site_steps, 0, 8 * (size_t)n, stream));
   WOS_HIP(hipMemsetAsync(tb->d_vcount, 0, 8 * (size_t)n, stream));
   if (accumulate) {
     WOS_HIP(hipMemsetAsync(tb->d_A, 0, ts * (size_t)n * m, stream));
@@ -1005,6 +1009,7 @@ wos_status wos_toolbox_export(const wos_toolbox* tb, int32_t what, void* dst, si
     case WOS_EXPORT_LAMBDA: src = tb->d_lambda; want = 8 * n; break;
     case WOS_EXPORT_VCOUNT: src = tb->d_vcount; want = 8 * n; break;
     case WOS_EXPORT_LAMBDA_V: src = tb->d_lambda_v; want = 8 * m; break;
+    case WOS_EXPORT_SITE_STEPS: src = tb->d_site_steps; want = 8 * n; break;
     default: return fail(WOS_EINVAL, "unknown export %d", what);
   }
   if (bytes != want) return fail(WOS_EINVAL, "export %d needs %zu bytes, got %zu", what, want, bytes);

@@ -128,6 +128,7 @@ struct wos_toolbox {
   uint32_t* d_Hc = nullptr;
   unsigned long long* d_vcount = nullptr;
   unsigned long long* d_stats = nullptr;  // [0..3] walker, [4] volume inside
+  unsigned long long* d_site_steps = nullptr;  // n: walk-steps of each site's walks
   double* d_lambda = nullptr;          // lambda_i = |W_i| / |D| (n)
   double* d_lambda_v = nullptr;        // |V_j| / |D| (m)
   unsigned long long* d_vcount_v = nullptr;

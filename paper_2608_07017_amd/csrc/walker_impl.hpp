@@ -600,6 +600,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
       atomicAdd(&P.stats[1], s_walks);
       atomicAdd(&P.stats[2], s_capped);
       atomicMax(&P.stats[3], (unsigned long long)s_maxk);
+      atomicAdd(&P.site_steps[site], s_steps);
     }
     return;
   } else {
@@ -646,6 +647,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
     atomicAdd(&P.stats[1], s_walks);
     atomicAdd(&P.stats[2], s_capped);
     atomicMax(&P.stats[3], (unsigned long long)s_maxk);
+    atomicAdd(&P.site_steps[site], s_steps);
   }
   }
 }

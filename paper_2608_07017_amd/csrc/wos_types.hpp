@@ -74,6 +74,7 @@ struct WalkerParams {
   uint32_t* Hc;
   T* K;
   unsigned long long* stats;  // [0] walk-steps, [1] walks, [2] capped, [3] max walk-steps
+  unsigned long long* site_steps;  // n: walk-steps of each site's walks
 };
 
 struct VolumeParams {

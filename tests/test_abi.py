@@ -109,3 +109,23 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(name, "size")] == ctypes.sizeof(st), name
         for f, _ in st._fields_:
             assert got[(name, f)] == getattr(st, f).offset, (name, f)
+
+
+def test_load_rejects_files_that_are_not_toolboxes(tmp_path):
+    # the header is checked before any device call
+    from paper_2608_07017_amd import _lib
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    bad = tmp_path / "bad.wostbx"
+    bad.write_bytes(b"not a toolbox at all")
+    assert L.wos_toolbox_load(str(bad).encode(), None, ctypes.byref(h)) == -1
+    assert b"not a saved toolbox" in L.wos_last_error()
+    old = tmp_path / "old.wostbx"
+    old.write_bytes(b"WOSTBOX1" + (99).to_bytes(4, "little"))
+    assert L.wos_toolbox_load(str(old).encode(), None, ctypes.byref(h)) == -1
+    assert b"version" in L.wos_last_error()
+    trunc = tmp_path / "trunc.wostbx"
+    trunc.write_bytes(b"WOSTBOX1" + (1).to_bytes(4, "little") + (1).to_bytes(4, "little") + (8).to_bytes(8, "little"))
+    assert L.wos_toolbox_load(str(trunc).encode(), None, ctypes.byref(h)) == -1
+    assert L.wos_toolbox_load(str(tmp_path / "missing").encode(), None, ctypes.byref(h)) == -1
+    assert not h.value
