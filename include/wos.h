@@ -141,6 +141,23 @@ typedef struct {
                                workgroups per compute unit)                      */
   int32_t window_bpages;    /* WINDOW: pages of boundary cells per site in LDS
                                (0: min(16, all))                                 */
+  const double* test_phi;   /* host, m values or NULL: a test function phi on the
+                               V cells; with test_psi, switches on the per-site
+                               moments (WOS_EXPORT_MOMENTS)                       */
+  const double* test_psi;   /* host, p values or NULL: a test function psi on the
+                               boundary cells.  When either is given, every walk
+                               of site i yields the four functionals of the
+                               pointwise estimators (Sec. "Monte Carlo
+                               estimators": eqs. u MC, gradu U MC, H MC, dh MC)
+                               with the binned data phi, psi:
+                                 c_A = omega r0^2/d phi(j_0) + sum_k t_k phi(j_k)
+                                 c_B = r0 (sum_{l<d} S^l) Zs phi(j_ball)
+                                       + w sum_{k>=1} t_k phi(j_k)
+                                 c_H = psi(j_T),   c_K = w psi(j_T)
+                               (so that the means are A phi, B phi, H psi, K psi)
+                               and the build sums c and c^2 per site (a NULL
+                               function counts as zero).  Median-of-three
+                               sampler only.                                     */
 } wos_build_opts;
 
 enum { WOS_TALLY_AUTO = 0, WOS_TALLY_LDS_ROWS = 1, WOS_TALLY_WINDOW = 2, WOS_TALLY_HBM = 3 };
@@ -239,8 +256,14 @@ typedef enum {
   WOS_EXPORT_LAMBDA = 5,  /* n,          double lambda_i               */
   WOS_EXPORT_VCOUNT = 6,  /* n,          uint64 volume-point counts    */
   WOS_EXPORT_LAMBDA_V = 7, /* m,         double |V_j| / |D| (= lambda when V = W) */
-  WOS_EXPORT_SITE_STEPS = 8 /* n,        uint64 walk-steps of each site's walks of the
+  WOS_EXPORT_SITE_STEPS = 8, /* n,       uint64 walk-steps of each site's walks of the
                                last build (k = 0 tallies plus chain tallies)      */
+  WOS_EXPORT_MOMENTS = 9    /* n x (4 + 4d) double, with the test functions of the
+                               build options: per site sum c_A, sum c_A^2,
+                               sum c_B (d), sum c_B^2 (d), sum c_H, sum c_H^2,
+                               sum c_K (d), sum c_K^2 (d) over its N walks; the
+                               standard error of a mean is
+                               sqrt((sum c^2 / N - (sum c / N)^2) / (N - 1))    */
 } wos_export_what;
 
 /* Copies one toolbox array into dst (device if dst_is_device, else host),

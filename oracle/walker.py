@@ -251,3 +251,27 @@ def pointwise(dom, x, i, walks, eps, seed, f=None, g=None, max_steps=DEFAULT_MAX
         out["H"], out["H_se"] = mean_se(gv)
         out["gradH"], out["gradH_se"] = mean_se(ev.term_w * gv[:, None])
     return out
+
+
+def site_functionals(dom, x, i, walks, eps, seed, vcentres, bnodes, phi, psi, max_steps=DEFAULT_MAX_STEPS,
+                     fixed_M=0, sampler="median3"):
+    """The per-walk values of the four estimators of Sec. "Monte Carlo
+    estimators" (eqs. u MC, gradu U MC, H MC, dh MC) with binned data: f is
+    phi at the nearest V centre, g is psi at the nearest boundary centre.
+    Returns (cA (N,), cB (N,d), cH (N,), cK (N,d)); their means are the rows
+    A phi, B phi, H psi and K psi of the binned toolbox."""
+    vc = np.asarray(vcentres, dtype=np.float64)
+    bn = np.asarray(bnodes, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    psi = np.asarray(psi, dtype=np.float64)
+    ev = site_events(dom, x, i, np.arange(walks), eps, seed, max_steps, fixed_M, sampler)
+    d = dom["dim"]
+    f_ev = phi[nearest(vc, ev.ev_pts)]
+    f_ball = phi[nearest(vc, ev.ball_pts)]
+    g_term = psi[nearest(bn, ev.term_pts)]
+    cA = np.bincount(ev.ev_walk, weights=ev.ev_tA * f_ev, minlength=walks)
+    cB = np.stack([np.bincount(ev.ev_walk, weights=ev.ev_tB[:, a] * f_ev, minlength=walks)
+                   + ev.ball_w[:, a] * f_ball for a in range(d)], axis=1)
+    cH = g_term
+    cK = ev.term_w * g_term[:, None]
+    return cA, cB, cH, cK

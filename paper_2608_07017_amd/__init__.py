@@ -50,9 +50,14 @@ def _dptr(t):
 
 def build_opts(walks, eps, seed=0, precision="f32", max_steps=0, fixed_M=0, volume_samples=0, walks_per_item=0,
                regen_threshold=0, autotune=True, tally="auto", sampler="median3", walker_block=0, tally_acc="auto",
-               window_pages=0, window_bpages=0):
-    """The wos_build_opts structure of include/wos.h."""
-    return WosBuildOpts(walks_per_site=int(walks), eps=float(eps), max_steps=int(max_steps),
+               window_pages=0, window_bpages=0, test_phi=None, test_psi=None):
+    """The wos_build_opts structure of include/wos.h.  `test_phi` / `test_psi`
+    are float64 numpy arrays (m and p values) that the caller keeps alive
+    until the structure has been used."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    return WosBuildOpts(test_phi=None if test_phi is None else test_phi.ctypes.data_as(dp),
+                        test_psi=None if test_psi is None else test_psi.ctypes.data_as(dp),
+                        walks_per_site=int(walks), eps=float(eps), max_steps=int(max_steps),
                         fixed_M=int(fixed_M), seed=int(seed), precision=PRECISION[precision],
                         volume_samples=int(volume_samples), walks_per_item=int(walks_per_item),
                         regen_threshold=int(regen_threshold), autotune=1 if autotune else 0,
@@ -100,12 +105,15 @@ class Toolbox:
     def __init__(self, domain, sites, bnodes, walks, eps, seed=0, precision="f32", max_steps=0,
                  fixed_M=0, volume_samples=0, walks_per_item=0, regen_threshold=0, autotune=True,
                  tally="auto", vcentres=None, sampler="median3", walker_block=0, tally_acc="auto",
-                 window_pages=0, window_bpages=0):
+                 window_pages=0, window_bpages=0, test_phi=None, test_psi=None):
         """`sites` are the W centres (the walks start there, n rows); with
         `vcentres` the tally points are binned to a V partition of its own
         (m columns; include/wos.h, wos_toolbox_create_wv), else V = W.
         `tally` is the walker's tally mode ("auto", "lds_rows", "window",
-        "hbm"; include/wos.h, wos_build_opts.tally_mode)."""
+        "hbm"; include/wos.h, wos_build_opts.tally_mode).  With test
+        values `test_phi` (m, one per V cell) and `test_psi` (p, one per
+        boundary node) the build also keeps each site's per-walk moments of
+        the four functionals (export "moments")."""
         self.domain = domain
         self.sites = np.ascontiguousarray(np.asarray(sites, dtype=np.float64))
         self.vcentres = None if vcentres is None else np.ascontiguousarray(np.asarray(vcentres, dtype=np.float64))
@@ -118,9 +126,18 @@ class Toolbox:
         self.precision = precision
         self.walks = int(walks)
         dom, keep = _domain_struct(domain)
+        if (test_phi is None) != (test_psi is None):
+            raise ValueError("test_phi and test_psi go together")
+        phi = psi = None
+        if test_phi is not None:
+            phi = np.ascontiguousarray(np.asarray(test_phi, dtype=np.float64).reshape(-1))
+            psi = np.ascontiguousarray(np.asarray(test_psi, dtype=np.float64).reshape(-1))
+            if phi.shape[0] != self.m or psi.shape[0] != self.p:
+                raise ValueError("test_phi needs m values and test_psi p values")
+        self.moments = phi is not None
         opts = build_opts(walks, eps, seed, precision, max_steps, fixed_M, volume_samples, walks_per_item,
                           regen_threshold, autotune, tally, sampler, walker_block, tally_acc, window_pages,
-                          window_bpages)
+                          window_bpages, phi, psi)
         h = ctypes.c_void_p()
         dp = ctypes.POINTER(ctypes.c_double)
         if self.vcentres is None:
@@ -134,7 +151,7 @@ class Toolbox:
                                               self.vcentres.ctypes.data_as(dp), self.m,
                                               self.bnodes.ctypes.data_as(dp), self.p, ctypes.byref(opts),
                                               ctypes.byref(h)))
-        del keep
+        del keep, phi, psi
         self._h = h
         self.dtype = torch.float64 if precision == "f64" else torch.float32
 
@@ -188,7 +205,8 @@ class Toolbox:
         return {"A": ((n, m), self.dtype), "B": ((d, n, m), self.dtype), "H": ((n, p), self.dtype),
                 "K": ((d, n, p), self.dtype), "Hcount": ((n, p), torch.int32),
                 "lambda": ((n,), torch.float64), "vcount": ((n,), torch.int64),
-                "lambda_v": ((m,), torch.float64), "site_steps": ((n,), torch.int64)}[what]
+                "lambda_v": ((m,), torch.float64), "site_steps": ((n,), torch.int64),
+                "moments": ((n, 4 + 4 * d), torch.float64)}[what]
 
     def export(self, what, stream=None):
         """A copy of one toolbox array as a device tensor (Hcount as int32

@@ -16,7 +16,8 @@ STATUS = {0: "WOS_OK", -1: "WOS_EINVAL", -2: "WOS_EDOMAIN", -3: "WOS_ENOMEM", -4
           -5: "WOS_ENOTCONV", -6: "WOS_EBUSY", -7: "WOS_ENOTIMPL"}
 KINDS = {"ball": 1, "box": 2, "polygon": 3, "box_minus_ball": 4}
 PRECISION = {"f32": 0, "f64": 1}
-EXPORTS = {"A": 0, "B": 1, "H": 2, "K": 3, "Hcount": 4, "lambda": 5, "vcount": 6, "lambda_v": 7, "site_steps": 8}
+EXPORTS = {"A": 0, "B": 1, "H": 2, "K": 3, "Hcount": 4, "lambda": 5, "vcount": 6, "lambda_v": 7, "site_steps": 8,
+           "moments": 9}
 
 
 class WosDomain(ctypes.Structure):
@@ -34,7 +35,8 @@ class WosBuildOpts(ctypes.Structure):
                 ("regen_threshold", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("tally_mode", ctypes.c_int32), ("sampler", ctypes.c_int32),
                 ("walker_block", ctypes.c_int32), ("tally_acc", ctypes.c_int32),
-                ("window_pages", ctypes.c_int32), ("window_bpages", ctypes.c_int32)]
+                ("window_pages", ctypes.c_int32), ("window_bpages", ctypes.c_int32),
+                ("test_phi", ctypes.POINTER(ctypes.c_double)), ("test_psi", ctypes.POINTER(ctypes.c_double))]
 
 
 class WosBuildPlan(ctypes.Structure):

@@ -267,7 +267,8 @@ void release(wos_toolbox* tb) {
                   tb->d_sites_f64, tb->d_bnodes, tb->d_segs, tb->d_verts, tb->d_A, tb->d_B,
                   tb->d_K, tb->d_H, tb->d_Hc, tb->d_vcount, tb->d_stats, tb->d_lambda,
                   tb->d_item_order, tb->gv_r.rec, tb->gv_r.list, tb->gg_r.rec, tb->gg_r.list,
-                  tb->d_vsites_r, tb->d_bnodes_r, tb->d_vrank, tb->d_brank, tb->d_win, tb->d_site_steps};
+                  tb->d_vsites_r, tb->d_bnodes_r, tb->d_vrank, tb->d_brank, tb->d_win, tb->d_site_steps,
+                  tb->d_mom_phi, tb->d_mom_psi, tb->d_mom};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (tb->wv) {  // the V-side arrays are separate allocations only with a V partition of their own
@@ -330,6 +331,8 @@ wos_status validate_inputs(const wos_domain* dom, const double* sites, int32_t n
     return fail(WOS_EINVAL, "walker_block must be 0, 256, 448, 512 or 1024");
   if (opts->window_pages < 0 || opts->window_pages > 255 || opts->window_bpages < 0 || opts->window_bpages > 255)
     return fail(WOS_EINVAL, "window_pages and window_bpages must be in [0, 255]");
+  if ((opts->test_phi || opts->test_psi) && opts->sampler != WOS_SAMPLER_MEDIAN3)
+    return fail(WOS_EINVAL, "the moments of the test functionals need the median-of-three sampler");
 
   HostDomain& hd = *out;
   hd.kind = dom->kind;
@@ -502,6 +505,7 @@ static wos_status zero_walker_outputs(wos_toolbox* tb, hipStream_t stream) {
   const size_t n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
   WOS_HIP(hipMemsetAsync(tb->d_stats, 0, 4 * 8, stream));
   WOS_HIP(hipMemsetAsync(tb->d_site_steps, 0, 8 * n, stream));
+  if (tb->moments) WOS_HIP(hipMemsetAsync(tb->d_mom, 0, 8 * n * (4 + 4 * d), stream));
   if (tb->items_per_site != 1 || tb->global_tally) {
     WOS_HIP(hipMemsetAsync(tb->d_A, 0, ts * n * m, stream));
     WOS_HIP(hipMemsetAsync(tb->d_B, 0, ts * d * n * m, stream));
@@ -556,6 +560,9 @@ static void fill_walker_params(const wos_toolbox* tb, uint32_t k0, uint32_t k1, 
   P.K = static_cast<T*>(tb->d_K);
   P.stats = tb->d_stats;
   P.site_steps = tb->d_site_steps;
+  P.mom_phi = static_cast<const T*>(tb->d_mom_phi);
+  P.mom_psi = static_cast<const T*>(tb->d_mom_psi);
+  P.mom = tb->moments ? tb->d_mom : nullptr;
 }
 
 // max_items > 0 launches only the first max_items items of the order (the
@@ -770,6 +777,33 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
     }
     TRY(upload(tb, (void**)&tb->d_win, win.data(), win.size() * sizeof(uint16_t)));
   }
+  if (opts->test_phi || opts->test_psi) {
+    // the test functions in the walker's numbering of the cells (Morton
+    // ranks in the windowed mode), in the toolbox precision
+    tb->moments = true;
+    tb->test_phi.assign(m, 0.0);
+    tb->test_psi.assign(p, 0.0);
+    if (opts->test_phi) tb->test_phi.assign(opts->test_phi, opts->test_phi + m);
+    if (opts->test_psi) tb->test_psi.assign(opts->test_psi, opts->test_psi + p);
+    tb->opts.test_phi = nullptr;  // the host copies above are the toolbox's
+    tb->opts.test_psi = nullptr;
+    std::vector<double> ph(tb->test_phi), ps(tb->test_psi);
+    if (pl.mode == WOS_TALLY_WINDOW) {
+      const std::vector<int> vo = morton_order(tb->vsites.data(), m, d, lo, hi);
+      const std::vector<int> bo = morton_order(bnodes, p, d, lo, hi);
+      for (int r = 0; r < m; ++r) ph[r] = tb->test_phi[vo[r]];
+      for (int r = 0; r < p; ++r) ps[r] = tb->test_psi[bo[r]];
+    }
+    if (tb->f64) {
+      TRY(upload(tb, &tb->d_mom_phi, ph.data(), 8 * (size_t)m));
+      TRY(upload(tb, &tb->d_mom_psi, ps.data(), 8 * (size_t)p));
+    } else {
+      std::vector<float> f1(ph.begin(), ph.end()), f2(ps.begin(), ps.end());
+      TRY(upload(tb, &tb->d_mom_phi, f1.data(), 4 * (size_t)m));
+      TRY(upload(tb, &tb->d_mom_psi, f2.data(), 4 * (size_t)p));
+    }
+    TRY(dev_alloc(tb, (void**)&tb->d_mom, 8 * (size_t)n * (4 + 4 * d)));
+  }
   {
     std::vector<double> seg(5 * std::max(nseg, 1), 0.0);
     for (int e = 0; e < nseg; ++e) {
@@ -828,6 +862,7 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
 
   WOS_HIP(hipMemsetAsync(tb->d_stats, 0, 8 * 8, stream));
   WOS_HIP(hipMemsetAsync(tb->d_site_steps, 0, 8 * (size_t)n, stream));
+  if (tb->moments) WOS_HIP(hipMemsetAsync(tb->d_mom, 0, 8 * (size_t)n * (4 + 4 * d), stream));
   WOS_HIP(hipMemsetAsync(tb->d_vcount, 0, 8 * (size_t)n, stream));
   if (accumulate) {
     WOS_HIP(hipMemsetAsync(tb->d_A, 0, ts * (size_t)n * m, stream));
@@ -1010,6 +1045,11 @@ wos_status wos_toolbox_export(const wos_toolbox* tb, int32_t what, void* dst, si
     case WOS_EXPORT_VCOUNT: src = tb->d_vcount; want = 8 * n; break;
     case WOS_EXPORT_LAMBDA_V: src = tb->d_lambda_v; want = 8 * m; break;
     case WOS_EXPORT_SITE_STEPS: src = tb->d_site_steps; want = 8 * n; break;
+    case WOS_EXPORT_MOMENTS:
+      if (!tb->moments) return fail(WOS_EINVAL, "the toolbox was built without test functions");
+      src = tb->d_mom;
+      want = 8 * n * (4 + 4 * d);
+      break;
     default: return fail(WOS_EINVAL, "unknown export %d", what);
   }
   if (bytes != want) return fail(WOS_EINVAL, "export %d needs %zu bytes, got %zu", what, want, bytes);

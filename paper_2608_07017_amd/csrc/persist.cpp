@@ -14,6 +14,9 @@
 //   15 lambda (f64, n)  16 volume counts (u64, n)
 //   17 |V_j| / |D| (f64, m)  18 V volume counts (u64, m)   (V partition only)
 //   19 walk-steps per site (u64, n)
+//   20 test function phi (f64, m)  21 psi (f64, p)  (after section 5)
+//   22 moments (f64, n (4 + 4 d))  (before the end; sections 20-22 only for a
+//      toolbox built with test functions)
 //   0 end
 // Loading creates the toolbox from the stored inputs (grids and layouts are
 // rebuilt on the host) and copies the stored arrays into its device memory.
@@ -43,7 +46,7 @@ constexpr size_t kChunk = (size_t)64 << 20;  // host staging per copy
 enum : uint32_t {
   kEnd = 0, kHeader = 1, kVerts = 2, kSites = 3, kVSites = 4, kBnodes = 5,
   kA = 10, kB = 11, kH = 12, kK = 13, kHc = 14, kLambda = 15, kVcount = 16, kLambdaV = 17, kVcountV = 18,
-  kSiteSteps = 19
+  kSiteSteps = 19, kTestPhi = 20, kTestPsi = 21, kMoments = 22
 };
 
 wos_status pfail(wos_status s, const char* fmt, ...) {
@@ -223,7 +226,9 @@ wos_status wos_toolbox_save(const wos_toolbox* tb, const char* path) {
             write_section(f, kVerts, tb->dom.verts.data(), 8 * tb->dom.verts.size()) &&
             write_section(f, kSites, tb->sites.data(), 8 * n * d) &&
             (!tb->wv || write_section(f, kVSites, tb->vsites.data(), 8 * m * d)) &&
-            write_section(f, kBnodes, tb->bnodes.data(), 8 * p * d);
+            write_section(f, kBnodes, tb->bnodes.data(), 8 * p * d) &&
+            (!tb->moments || (write_section(f, kTestPhi, tb->test_phi.data(), 8 * m) &&
+                              write_section(f, kTestPsi, tb->test_psi.data(), 8 * p)));
   if (!ok) return pfail(WOS_EINVAL, "write to %s failed", path);
   wos_status s;
   if ((s = write_device(f, kA, tb->d_A, ts * n * m)) != WOS_OK) return s;
@@ -238,6 +243,7 @@ wos_status wos_toolbox_save(const wos_toolbox* tb, const char* path) {
     if ((s = write_device(f, kVcountV, tb->d_vcount_v, 8 * m)) != WOS_OK) return s;
   }
   if ((s = write_device(f, kSiteSteps, tb->d_site_steps, 8 * n)) != WOS_OK) return s;
+  if (tb->moments && (s = write_device(f, kMoments, tb->d_mom, 8 * n * (4 + 4 * d))) != WOS_OK) return s;
   if (!write_section(f, kEnd, nullptr, 0) || std::fflush(f) != 0) return pfail(WOS_EINVAL, "write to %s failed", path);
   return WOS_OK;
 }
@@ -271,6 +277,14 @@ wos_status wos_toolbox_load(const char* path, void* stream, wos_toolbox** out) {
   if (!expect(kVerts, 16 * (uint64_t)h.nvert, &verts) || !expect(kSites, 8 * n * d, &sites) ||
       (h.wv && !expect(kVSites, 8 * m * d, &vsites)) || !expect(kBnodes, 8 * p * d, &bnodes))
     return pfail(WOS_EINVAL, "%s: bad input sections", path);
+  // optional test functions, then the first array section's head
+  std::vector<unsigned char> phi, psi;
+  if (!read_head(f, &tag, &bytes)) return pfail(WOS_EINVAL, "%s: file ends after the inputs", path);
+  if (tag == kTestPhi) {
+    if (bytes != 8 * m || !read_host(f, bytes, &phi) || !expect(kTestPsi, 8 * p, &psi) ||
+        !read_head(f, &tag, &bytes))
+      return pfail(WOS_EINVAL, "%s: bad test-function sections", path);
+  }
   wos_domain dom{};
   dom.kind = h.kind;
   dom.dim = h.dim;
@@ -299,6 +313,10 @@ wos_status wos_toolbox_load(const char* path, void* stream, wos_toolbox** out) {
   o.tally_acc = h.tally_acc;
   o.window_pages = h.window_pages;
   o.window_bpages = h.window_bpages;
+  if (!phi.empty()) {
+    o.test_phi = reinterpret_cast<const double*>(phi.data());
+    o.test_psi = reinterpret_cast<const double*>(psi.data());
+  }
   wos_toolbox* tb = nullptr;
   wos_status s = wos_toolbox_create_wv(&dom, reinterpret_cast<const double*>(sites.data()), h.n,
                                        h.wv ? reinterpret_cast<const double*>(vsites.data()) : nullptr, h.m,
@@ -319,12 +337,21 @@ wos_status wos_toolbox_load(const char* path, void* stream, wos_toolbox** out) {
     secs.push_back({kVcountV, tb->d_vcount_v, 8 * m});
   }
   secs.push_back({kSiteSteps, tb->d_site_steps, 8 * n});
+  bool first = true;  // the first array section's head was read above
   for (const Sec& sc : secs) {
-    if (!read_head(f, &tag, &bytes) || tag != sc.tag || bytes != sc.bytes)
+    if ((!first && !read_head(f, &tag, &bytes)) || tag != sc.tag || bytes != sc.bytes)
       return pfail(WOS_EINVAL, "%s: section %u missing or of the wrong size", path, sc.tag);
+    first = false;
     if ((s = read_device(f, sc.dev, bytes)) != WOS_OK) return s;
   }
-  if (!read_head(f, &tag, &bytes) || tag != kEnd) return pfail(WOS_EINVAL, "%s: no end marker", path);
+  if (!read_head(f, &tag, &bytes)) return pfail(WOS_EINVAL, "%s: no end marker", path);
+  if (tb->moments) {
+    if (tag != kMoments || bytes != 8 * n * (4 + 4 * d))
+      return pfail(WOS_EINVAL, "%s: moments section missing or of the wrong size", path);
+    if ((s = read_device(f, tb->d_mom, bytes)) != WOS_OK) return s;
+    if (!read_head(f, &tag, &bytes)) return pfail(WOS_EINVAL, "%s: no end marker", path);
+  }
+  if (tag != kEnd) return pfail(WOS_EINVAL, "%s: no end marker", path);
   {
     const hipError_t e = hipMemcpy(tb->d_stats, h.stats, sizeof h.stats, hipMemcpyHostToDevice);
     if (e != hipSuccess) return pfail(WOS_EDEVICE, "device copy failed: %s", hipGetErrorString(e));

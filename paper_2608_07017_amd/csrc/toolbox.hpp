@@ -109,6 +109,12 @@ struct wos_toolbox {
   int* d_vrank = nullptr;        // caller column j -> rank
   int* d_brank = nullptr;        // caller boundary node j -> rank
   uint16_t* d_win = nullptr;     // n x (win_pc + win_pb) page lists
+  // per-site moments of the test functionals (build options test_phi, test_psi)
+  bool moments = false;
+  std::vector<double> test_phi, test_psi;  // host copies (m, p)
+  void* d_mom_phi = nullptr;     // toolbox precision, in the walker's column numbering
+  void* d_mom_psi = nullptr;
+  double* d_mom = nullptr;       // n x (4 + 4 d)
   std::vector<double> sites, vsites, bnodes;  // W centres (n), V centres (m), boundary nodes (p)
   bool wv = false;  // separate V partition (else V = W and the V arrays alias the W ones)
   // device

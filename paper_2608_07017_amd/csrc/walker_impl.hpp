@@ -137,10 +137,12 @@ struct AccWord<kAccWindow, T> {
   using type = T;
 };
 
-// KIND carries the domain kind in its low four bits and, in bit 4
-// (kExactRadius), the d = 2 exact radial sampler, so that the default
-// kernels hold none of the sampler's code.
+// KIND carries the domain kind in its low four bits, in bit 4
+// (kExactRadius) the d = 2 exact radial sampler and in bit 5 (kMoments) the
+// per-site moments of the test functionals, so that the default kernels hold
+// none of that code.
 constexpr int kExactRadius = 16;
+constexpr int kMoments = 32;
 
 template <typename T, int D, int KIND, bool PTS_LDS, int kBlock, int ACC>
 __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
@@ -148,6 +150,8 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   constexpr bool EXACT = D == 2 && (KIND & kExactRadius) != 0;
   constexpr bool GLOBAL = ACC == kAccGlobal;
   constexpr bool WINDOW = ACC == kAccWindow;
+  constexpr bool MOM = (KIND & kMoments) != 0;
+  constexpr int NMOM = 4 + 4 * D;  // sums and sums of squares of c_A, c_B (d), c_H, c_K (d)
   using AW = typename AccWord<ACC, T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ unsigned int s_next;
@@ -357,6 +361,16 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   bool exhausted = false;
 #pragma unroll
   for (int a = 0; a < D; ++a) X[a] = Y[a] = w[a] = q[a] = pU1[a] = pY[a] = T(0);
+  // Moments (MOM only): per walk the test functionals' parts so far, the
+  // k = 0 term phi-weighted (m0), the ball term (mb) and the chain sum
+  // S = sum_{k >= 1} t_k phi(j_k); pool copies of the first two; per lane
+  // the sums of c and c^2 over its finished walks.
+  T pm0 = T(0), m0 = T(0), mS = T(0);
+  T pmb[D], mb[D], macc[NMOM];
+#pragma unroll
+  for (int a = 0; a < D; ++a) pmb[a] = mb[a] = T(0);
+#pragma unroll
+  for (int e = 0; e < NMOM; ++e) macc[e] = T(0);
   unsigned long long n_walks = 0;  // wave-uniform
   unsigned int lane_steps = 0, lane_capped = 0, lane_maxk = 0;
 
@@ -427,6 +441,12 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
         tally_B(jb, bt);
         const int j0 = grid_resolve<T, D>(P.gv, vpts, r0c, q0);
         tally_A(j0, pomd * r0sq);
+        if constexpr (MOM) {
+          const T phb = P.mom_phi[jb];
+#pragma unroll
+          for (int a = 0; a < D; ++a) pmb[a] = bt[a] * phb;
+          pm0 = pomd * r0sq * P.mom_phi[j0];
+        }
       }
       V += avail;
       n_walks += (unsigned long long)avail;
@@ -436,6 +456,25 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
     if (done) {
       const int j = grid_nearest<T, D>(P.gg, P.gg.pts, X);
       tally_HK(j, w);
+      if constexpr (MOM) {
+        // the walk's values of the four test functionals (eqs. u MC,
+        // gradu U MC, H MC, dh MC with the binned data phi and psi)
+        const T ps = P.mom_psi[j];
+        const T cA = m0 + mS;
+        macc[0] += cA;
+        macc[1] += cA * cA;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const T cB = mb[a] + w[a] * mS;
+          macc[2 + a] += cB;
+          macc[2 + D + a] += cB * cB;
+          const T cK = w[a] * ps;
+          macc[4 + 2 * D + a] += cK;
+          macc[4 + 3 * D + a] += cK * cK;
+        }
+        macc[2 + 2 * D] += ps;
+        macc[3 + 2 * D] += ps * ps;
+      }
       done = false;
     }
 
@@ -453,7 +492,21 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
         tY[a] = __shfl(pY[a], src);
       }
       const T tomd = __shfl(pomd, src);
+      T tm0 = T(0), tmb[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) tmb[a] = T(0);
+      if constexpr (MOM) {
+        tm0 = __shfl(pm0, src);
+#pragma unroll
+        for (int a = 0; a < D; ++a) tmb[a] = __shfl(pmb[a], src);
+      }
       if (take) {
+        if constexpr (MOM) {
+          m0 = tm0;
+          mS = T(0);
+#pragma unroll
+          for (int a = 0; a < D; ++a) mb[a] = tmb[a];
+        }
         // first step X_1 = x + r0 U1; w = (d / r0) U1
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -555,11 +608,24 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
     for (int s = 0; s < SS; ++s) {
       if (ts[s]) {
         const int j = grid_resolve<T, D>(P.gv, vpts, recs[s], qs[s]);
-        tally_AB(j, omd * rs[s] * rs[s], w);
+        const T t = omd * rs[s] * rs[s];
+        tally_AB(j, t, w);
+        if constexpr (MOM) mS += t * P.mom_phi[j];
       }
     }
   }
 
+  if constexpr (MOM) {
+    // the lanes' sums, added over the wavefront, then into the site's row
+    double* mrow = P.mom + (size_t)site * NMOM;
+#pragma unroll
+    for (int e = 0; e < NMOM; ++e) {
+      double v = (double)macc[e];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0 && v != 0.0) atomicAdd(&mrow[e], v);
+    }
+  }
   if (lane == 0) atomicAdd(&s_walks, n_walks);
   atomicAdd(&s_steps, (unsigned long long)lane_steps);
   if (lane_capped) atomicAdd(&s_capped, (unsigned long long)lane_capped);

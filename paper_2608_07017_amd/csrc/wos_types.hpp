@@ -75,6 +75,9 @@ struct WalkerParams {
   T* K;
   unsigned long long* stats;  // [0] walk-steps, [1] walks, [2] capped, [3] max walk-steps
   unsigned long long* site_steps;  // n: walk-steps of each site's walks
+  const T* mom_phi;  // moments: the test function on the V cells (walker's column numbering), or NULL
+  const T* mom_psi;  // moments: the test function on the boundary cells (walker's numbering)
+  double* mom;       // moments: n x (4 + 4 d) sums, NULL when off
 };
 
 struct VolumeParams {

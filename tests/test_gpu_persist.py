@@ -32,6 +32,8 @@ def test_save_load_round_trip(tmp_path, case):
         sites = W.sample_sites(dom, 200, 4, 1e-3)
         kw = dict(bnodes=np.concatenate([W.cube_face_nodes(3), W.fibonacci_sphere(30, dom["center"], dom["radius"])]),
                   precision="f32", tally="window", window_pages=2, window_bpages=1)
+        rng0 = np.random.default_rng(2)
+        kw.update(test_phi=rng0.normal(size=200), test_psi=rng0.normal(size=len(kw["bnodes"])))
     else:
         dom = W.unit_disk()
         sites = W.sample_sites(dom, 90, 5, 1e-3)
@@ -48,7 +50,8 @@ def test_save_load_round_trip(tmp_path, case):
     for k in ("dim", "n", "m", "p", "precision", "walks_per_site", "walk_steps", "walks", "capped_walks",
               "max_walk_steps", "volume_inside"):
         assert i1[k] == i2[k], k
-    for k in KEYS:
+    keys = KEYS + (("moments",) if case == "cubeball_window" else ())
+    for k in keys:
         assert torch.equal(tb.export(k), t2.export(k)), k
     # a solve on each gives the same bits
     n, p = tb.n, tb.p
@@ -79,5 +82,8 @@ def test_save_load_round_trip(tmp_path, case):
             assert torch.allclose(tb.export(k), t2.export(k), rtol=1e-12, atol=1e-15), k
     else:
         assert torch.equal(tb.export("Hcount").sum(1), t2.export("Hcount").sum(1))
+        # the loaded toolbox kept its test functions: the moments are rebuilt
+        # (FP64 device atomics: equal up to the order of the additions)
+        assert torch.allclose(tb.export("moments"), t2.export("moments"), rtol=1e-9, atol=1e-9)
     tb.free()
     t2.free()

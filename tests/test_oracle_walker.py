@@ -152,3 +152,31 @@ def test_exact_radius_sampler_closed_forms(x):
     q = 1 - x @ x
     assert _close(o["U"], o["U_se"], x[0] * q / 4, 1e-4)
     assert _close(o["gradU"], o["gradU_se"], (q * np.eye(2)[0] - 2 * x[0] * x) / 4, 1e-4)
+
+
+def test_site_functionals_means_and_invariants():
+    # The per-walk functionals behind the per-site moments: their means are
+    # the binned rows applied to phi / psi (a different route: one bincount
+    # per walk, not per cell), the variance of c_H vanishes for psi = 1, and
+    # |c_K|^2 = |w|^2 = (d / r0)^2 on every walk for psi = 1 (w = d/r0 U_1
+    # with U_1 on the unit sphere).
+    from oracle.walker import site_functionals
+    rng = np.random.default_rng(8)
+    for dom, n, p in [(DISK, 30, 20), (BALL, 24, 18)]:
+        d = dom["dim"]
+        sites = W.sample_sites(dom, n, 4, 1e-3)
+        bn = W.circle_nodes(p) if d == 2 else W.fibonacci_sphere(p)
+        phi = rng.normal(size=n)
+        psi = rng.normal(size=p)
+        i = 7
+        tb = build_toolbox(dom, sites, bn, 2000, 1e-3, 17, rows=[i])
+        cA, cB, cH, cK = site_functionals(dom, sites[i], i, 2000, 1e-3, 17, sites, bn, phi, psi)
+        assert np.isclose(cA.mean(), tb["A"][0] @ phi, rtol=1e-12, atol=1e-14)
+        assert np.allclose(cB.mean(0), tb["B"][:, 0] @ phi, rtol=1e-12, atol=1e-13)
+        assert np.isclose(cH.mean(), tb["H"][0] @ psi, rtol=1e-12, atol=1e-14)
+        assert np.allclose(cK.mean(0), tb["K"][:, 0] @ psi, rtol=1e-12, atol=1e-13)
+        ones_v, ones_b = np.ones(n), np.ones(p)
+        _, _, cH1, cK1 = site_functionals(dom, sites[i], i, 2000, 1e-3, 17, sites, bn, ones_v, ones_b)
+        assert np.all(cH1 == 1.0)
+        r0 = float(np.min(np.abs(1.0 - np.linalg.norm(sites[i]))))
+        assert np.allclose((cK1 ** 2).sum(1), (d / r0) ** 2, rtol=1e-12)
