@@ -204,6 +204,10 @@ GridDev<T> view(const DevGrid& g, const void* pts) {
   }
   v.rec = g.rec;
   v.list = g.list;
+  if constexpr (sizeof(T) == 4)
+    v.ovf = g.ovf32;
+  else
+    v.ovf = g.ovf64;
   v.pts = static_cast<const T*>(pts);
   return v;
 }
@@ -253,7 +257,15 @@ wos_status upload_grid(wos_toolbox* tb, const GridHost& h, DevGrid* g) {
   g->max_cand = h.max_cand;
   wos_status s = upload(tb, (void**)&g->rec, h.rec.data(), h.rec.size() * sizeof(int));
   if (s != WOS_OK) return s;
-  return upload(tb, (void**)&g->list, h.list.data(), h.list.size() * sizeof(int));
+  if ((s = upload(tb, (void**)&g->list, h.list.data(), h.list.size() * sizeof(int))) != WOS_OK) return s;
+  std::vector<float> o32(h.ovf.size());
+  for (size_t e = 0; e < h.ovf.size(); e += 4) {
+    for (int a = 0; a < 3; ++a) o32[e + a] = (float)h.ovf[e + a];
+    const int j = (int)h.ovf[e + 3];
+    std::memcpy(&o32[e + 3], &j, 4);
+  }
+  if ((s = upload(tb, (void**)&g->ovf32, o32.data(), o32.size() * sizeof(float))) != WOS_OK) return s;
+  return upload(tb, (void**)&g->ovf64, h.ovf.data(), h.ovf.size() * sizeof(double));
 }
 
 void release(wos_toolbox* tb) {
@@ -263,7 +275,8 @@ void release(wos_toolbox* tb) {
       (void)hipEventDestroy(e);
       e = nullptr;
     }
-  void* ptrs[] = {tb->gv.rec, tb->gv.list, tb->gg.rec, tb->gg.list, tb->d_sites_f32,
+  void* ptrs[] = {tb->gv.rec, tb->gv.list, tb->gv.ovf32, tb->gv.ovf64, tb->gg.rec, tb->gg.list, tb->gg.ovf32,
+                  tb->gg.ovf64, tb->gv_r.ovf32, tb->gv_r.ovf64, tb->gg_r.ovf32, tb->gg_r.ovf64, tb->d_sites_f32,
                   tb->d_sites_f64, tb->d_bnodes, tb->d_segs, tb->d_verts, tb->d_A, tb->d_B,
                   tb->d_K, tb->d_H, tb->d_Hc, tb->d_vcount, tb->d_stats, tb->d_lambda,
                   tb->d_item_order, tb->gv_r.rec, tb->gv_r.list, tb->gg_r.rec, tb->gg_r.list,
@@ -272,7 +285,7 @@ void release(wos_toolbox* tb) {
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (tb->wv) {  // the V-side arrays are separate allocations only with a V partition of their own
-    void* vptrs[] = {tb->gw.rec, tb->gw.list, tb->d_vsites_f32, tb->d_vsites_f64, tb->d_lambda_v, tb->d_vcount_v};
+    void* vptrs[] = {tb->gw.rec, tb->gw.list, tb->gw.ovf32, tb->gw.ovf64, tb->d_vsites_f32, tb->d_vsites_f64, tb->d_lambda_v, tb->d_vcount_v};
     for (void* q : vptrs)
       if (q) (void)hipFree(q);
   }

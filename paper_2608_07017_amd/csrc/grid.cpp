@@ -262,7 +262,21 @@ GridHost build_grid(const double* pts, int npts, int dim, const double* lo, cons
     while (c < 4 && g.rec[4 * cid + c] != g.rec[4 * cid]) ++c;
     maxc = std::max(maxc, c);
   }
+  // overflow entries: centre coordinates and index, in list order
+  for (long long cid = 0; cid < ncell; ++cid) {
+    if (g.rec[4 * cid] >= 0) continue;
+    const int off = -g.rec[4 * cid] - 1;
+    const int cnt = g.list[off];
+    g.rec[4 * cid + 1] = cnt;
+    g.rec[4 * cid + 2] = (int)(g.ovf.size() / 4);
+    for (int c = 0; c < cnt; ++c) {
+      const int j = g.list[off + 1 + c];
+      for (int a = 0; a < 3; ++a) g.ovf.push_back(a < dim ? pts[(size_t)j * dim + a] : 0.0);
+      g.ovf.push_back((double)j);
+    }
+  }
   if (g.list.empty()) g.list.push_back(0);
+  if (g.ovf.empty()) g.ovf.assign(4, 0.0);
   g.frac_single = 1.0 - (double)nmulti / (double)ncell;
   g.mean_multi = nmulti ? (double)sumc / nmulti : 1.0;
   g.max_cand = maxc;

@@ -22,6 +22,8 @@ struct DevGrid {
   double lo[3] = {0, 0, 0}, h[3] = {1, 1, 1};
   int4* rec = nullptr;
   int* list = nullptr;
+  float* ovf32 = nullptr;   // overflow entries (4 values each) in FP32 (index as the int's bits)
+  double* ovf64 = nullptr;  // and in FP64
   size_t ncell = 0, nlist = 0;
   double frac_single = 1, mean_multi = 1;
   int max_cand = 1;

@@ -232,9 +232,9 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
     if constexpr (WINDOW) {
       const unsigned int sl = tV[j >> 6];
       if (sl != kNoSlot)
-        atomicAdd(&sA[(sl << 6) | (j & 63)], v);
+        lds_atomic_add(&sA[(sl << 6) | (j & 63)], v);
       else
-        atomicAdd(&gA[j], v * P.inv_N);
+        dev_atomic_add(&gA[j], v * P.inv_N);
     } else {
       add_tally(&sA[j], v);
     }
@@ -245,10 +245,10 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
       if (sl != kNoSlot) {
         const int c = (sl << 6) | (j & 63);
 #pragma unroll
-        for (int a = 0; a < D; ++a) atomicAdd(&sB[a * bstride + c], v[a]);
+        for (int a = 0; a < D; ++a) lds_atomic_add(&sB[a * bstride + c], v[a]);
       } else {
 #pragma unroll
-        for (int a = 0; a < D; ++a) atomicAdd(&gB[a * gbs + j], v[a] * P.inv_N);
+        for (int a = 0; a < D; ++a) dev_atomic_add(&gB[a * gbs + j], v[a] * P.inv_N);
       }
     } else {
 #pragma unroll
@@ -260,14 +260,14 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
       const unsigned int sl = tV[j >> 6];
       if (sl != kNoSlot) {
         const int c = (sl << 6) | (j & 63);
-        atomicAdd(&sA[c], t);
+        lds_atomic_add(&sA[c], t);
 #pragma unroll
-        for (int a = 0; a < D; ++a) atomicAdd(&sB[a * bstride + c], t * wv[a]);
+        for (int a = 0; a < D; ++a) lds_atomic_add(&sB[a * bstride + c], t * wv[a]);
       } else {
         const T ts = t * P.inv_N;
-        atomicAdd(&gA[j], ts);
+        dev_atomic_add(&gA[j], ts);
 #pragma unroll
-        for (int a = 0; a < D; ++a) atomicAdd(&gB[a * gbs + j], ts * wv[a]);
+        for (int a = 0; a < D; ++a) dev_atomic_add(&gB[a * gbs + j], ts * wv[a]);
       }
     } else {
       add_tally(&sA[j], t);
@@ -280,13 +280,13 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
       const unsigned int sl = tG[j >> 6];
       if (sl != kNoSlot) {
         const int c = (sl << 6) | (j & 63);
-        atomicAdd(&sH[c], 1u);
+        lds_atomic_add(&sH[c], 1u);
 #pragma unroll
-        for (int a = 0; a < D; ++a) atomicAdd(&sK[a * kstride + c], wv[a]);
+        for (int a = 0; a < D; ++a) lds_atomic_add(&sK[a * kstride + c], wv[a]);
       } else {
-        atomicAdd(&gH[j], 1u);
+        dev_atomic_add(&gH[j], 1u);
 #pragma unroll
-        for (int a = 0; a < D; ++a) atomicAdd(&gK[a * gks + j], wv[a] * P.inv_N);
+        for (int a = 0; a < D; ++a) dev_atomic_add(&gK[a * gks + j], wv[a] * P.inv_N);
       }
     } else {
       atomicAdd(&sH[j], 1u);

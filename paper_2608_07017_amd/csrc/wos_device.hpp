@@ -166,6 +166,24 @@ __device__ __forceinline__ T boundary_distance(const DomainDev<T>& dom, const T*
   }
 }
 
+// ------------------------------------------------------ atomic adds
+// Relaxed atomic adds with the address space stated: LDS (workgroup scope)
+// or device memory (agent scope).  When an LDS add and a device add sit on
+// the two sides of a branch, plain atomicAdd on generic pointers lets the
+// compiler merge them into one generic (FLAT) atomic behind a pointer
+// select, and a FLAT instruction makes the wave wait on both memory
+// counters; with the address spaces stated they stay ds_add and
+// global_atomic_add.
+template <typename T>
+__device__ __forceinline__ void lds_atomic_add(T* p, T v) {
+  __hip_atomic_fetch_add((__attribute__((address_space(3))) T*)p, v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ void dev_atomic_add(T* p, T v) {
+  __hip_atomic_fetch_add((__attribute__((address_space(1))) T*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ------------------------------------------------------ nearest centre
 // Uniform grid over the bounding box.  Each cell's 16-byte record lists, in
 // ascending order, every centre that can be nearest somewhere in the cell;
@@ -211,18 +229,46 @@ struct PointV {
   T x[D];
 };
 
+// One overflow entry: the centre (padded to three coordinates) and its
+// index, loaded as one 16-byte (FP32) or 32-byte (FP64) vector.
+template <typename T>
+struct alignas(4 * sizeof(T)) OvfEntry {
+  T v[4];
+};
+__device__ __forceinline__ int ovf_index(float x) { return __float_as_int(x); }
+__device__ __forceinline__ int ovf_index(double x) { return (int)x; }
+
+// A cell with more than four candidates (record x < 0, y = count, z = first
+// entry): its entries are read four at a time, the four loads of a group in
+// flight together, and compared in ascending index order with a strict '<'
+// (a group's missing tail repeats the last entry, which changes nothing).
 template <typename T, int D>
-__device__ __noinline__ int grid_overflow(const GridDev<T>& g, const T* pts, int code, PointV<T, D> q) {
-  const int* lst = g.list + (-code - 1);
-  const int cnt = lst[0];
-  int bj = lst[1];
-  T best = centre_d2<T, D>(pts, bj, q.x);
-  for (int c = 1; c < cnt; ++c) {
-    const int j = lst[1 + c];
-    const T d2 = centre_d2<T, D>(pts, j, q.x);
-    if (d2 < best) {
-      best = d2;
-      bj = j;
+__device__ __noinline__ int grid_overflow(const GridDev<T>& g, int4 r, PointV<T, D> q) {
+  const __attribute__((address_space(1))) OvfEntry<T>* e =
+      (const __attribute__((address_space(1))) OvfEntry<T>*)(g.ovf) + r.z;
+  const int cnt = r.y;
+  int bj = 0;
+  T best = T(0);
+  for (int c0 = 0; c0 < cnt; c0 += 4) {
+    OvfEntry<T> ev[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int c = min(c0 + k, cnt - 1);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ev[k].v[i] = e[c].v[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      T d2 = T(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const T t = q.x[a] - ev[k].v[a];
+        d2 += t * t;
+      }
+      if ((c0 == 0 && k == 0) || d2 < best) {
+        best = d2;
+        bj = ovf_index(ev[k].v[3]);
+      }
     }
   }
   return bj;
@@ -237,7 +283,7 @@ __device__ __forceinline__ int grid_resolve(const GridDev<T>& g, const T* pts, i
     PointV<T, D> qv;
 #pragma unroll
     for (int a = 0; a < D; ++a) qv.x[a] = q[a];
-    return grid_overflow<T, D>(g, pts, r.x, qv);
+    return grid_overflow<T, D>(g, r, qv);
   }
   int bj = r.x;
   if (r.y != r.x) {

@@ -38,6 +38,8 @@ struct GridDev {
   T top[3];         // n[a] - 1
   const int4* rec;  // n0*n1*n2 cell records, x slowest
   const int* list;  // overflow lists [count, indices...]
+  const T* ovf;     // overflow entries, 4 values each: the centre (padded to
+                    // three coordinates) and its index (FP32: the int's bits)
   const T* pts;     // centres, PtStride<D> values each
 };
 

@@ -330,3 +330,41 @@ def test_tikhonov_4096_sites_wide_tiles(precision):
     if precision == "mixed":
         assert info["refine_iters"] <= 8
     assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < 1e-9
+
+
+def test_paper_elliptic_div_example_end_to_end():
+    """The example "elliptic div" end to end on the paper's disk layout
+    (300 ring sites, 60 boundary nodes, M = 30 steps per walk): A(x) =
+    [[2 + x^2, xy], [xy, 2 + y^2]], b = (-y, x), c = 1, u = (1 - |x|^2)
+    sin(pi x), solved through eq. linear_q by the truncated SVD with
+    rcond 1e-3 (Table "numerical parameters").  The GPU solve against the
+    oracle's on the same matrices; the singular values of Lambda in the
+    range the paper notes (sigma_max about 1e-2, sigma_min about 1e-7); the
+    L^2 error near the layout's discretisation floor (8.5e-2)."""
+    dom = W.unit_disk()
+    sites, bn = W.paper_disk_layout()
+    _say("GPU build: paper disk layout, 1e5 walks, M = 30")
+    tb = P.Toolbox(dom, sites, bn, 100_000, 0.0, seed=7, precision="f64", fixed_M=30, volume_samples=1 << 22)
+    tb.build()
+    torch.cuda.synchronize()
+    mats = {k: tb.export(k).cpu().numpy() for k in ("A", "B", "H", "K", "lambda")}
+    lam = mats["lambda"]
+    uex, guex, f = W.elliptic_div_disk(sites)
+    A, b, c = W.elliptic_div_coef(sites)
+    g = np.zeros(len(bn))
+    u, gu, q, info = tb.solve(f, g, kind="linear", A=A, b=b, c=c, rcond=1e-3, solver="tsvd")
+    torch.cuda.synchronize()
+    u = u.cpu().numpy()
+    Lam, _ = OL.assemble(mats, lam, A, b, c)
+    s = np.linalg.svd(Lam, compute_uv=False)
+    _say("sigma_max %.3e sigma_min %.3e rank %d" % (s[0], s[-1], info["rank"]))
+    assert np.isclose(info["sigma_max"], s[0], rtol=1e-9)
+    assert 2e-3 < s[0] < 5e-2 and 1e-9 < s[-1] < 1e-5
+    ref = OL.solve_linear(mats, lam, f, g, Acoef=A, bcoef=b, ccoef=c, rcond=1e-3)
+    if np.min(np.abs(s - 1e-3 * s[0])) > 1e-4 * 1e-3 * s[0]:
+        assert info["rank"] == int(np.sum(s > 1e-3 * s[0]))
+        assert _lam_rel(u, ref["u"], lam) < 1e-7
+    err = W.voronoi_l2_error(dom, sites, u, lambda x: W.elliptic_div_disk(x)[0], npoints=1 << 21)
+    site_rms = np.sqrt(np.sum(lam * (u - uex) ** 2))
+    _say("L2 error %.4f (floor 0.0853), lambda-weighted site RMS %.4f" % (err, site_rms))
+    assert err < 0.11

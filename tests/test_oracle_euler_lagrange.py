@@ -324,3 +324,44 @@ def test_elliptic_example_solution_satisfies_its_equation():
     gfd = np.stack([(W.elliptic_divmin_disk(x + h * e)[0] - W.elliptic_divmin_disk(x - h * e)[0]) / (2 * h)
                     for e in np.eye(2)], 1)
     assert np.allclose(gu, gfd, rtol=1e-7, atol=2e-7)  # O(h^2) truncation of the differences
+
+
+def test_elliptic_div_example_solution_satisfies_its_equation():
+    # the manufactured data of the example "elliptic div": f = div(A grad u)
+    # + b.grad u - c u checked by central differences of the flux A grad u
+    x = np.array([[0.3, -0.2], [-0.5, 0.4], [0.1, 0.7], [0.0, 0.0]])
+    u, gu, f = W.elliptic_div_disk(x)
+    A, b, c = W.elliptic_div_coef(x)
+    h = 1e-4
+
+    def flux(y):
+        Ay, _, _ = W.elliptic_div_coef(y)
+        return np.einsum("nab,nb->na", Ay, W.elliptic_div_disk(y)[1])
+
+    div = sum((flux(x + h * e)[:, a] - flux(x - h * e)[:, a]) / (2 * h) for a, e in enumerate(np.eye(2)))
+    assert np.allclose(div + np.sum(b * gu, 1) - c * u, f, rtol=1e-6, atol=1e-6)
+    th = np.linspace(0, 2 * np.pi, 7)
+    assert np.allclose(W.elliptic_div_disk(np.stack([np.cos(th), np.sin(th)], 1))[0], 0.0, atol=1e-15)
+    gfd = np.stack([(W.elliptic_div_disk(x + h * e)[0] - W.elliptic_div_disk(x - h * e)[0]) / (2 * h)
+                    for e in np.eye(2)], 1)
+    assert np.allclose(gu, gfd, rtol=1e-6, atol=1e-7)
+    assert np.all(np.linalg.eigvalsh(A) > 0)        # uniformly elliptic on the disk
+
+
+def test_t11_discretisation_floors_of_the_disk_examples():
+    # the L^2 distance between the exact solution and its piecewise-constant
+    # values at the sites of the disk layout (Voronoi cells): the paper notes
+    # about 8.5e-2 for "elliptic div" and about 3.1e-2 for "elliptic div min"
+    # (two printed digits; Monte Carlo over 2^21 points here, whose own
+    # relative error is a few 1e-4)
+    sites, _ = W.paper_disk_layout()
+    dom = W.unit_disk()
+    for fn, paper, tol in [(W.elliptic_div_disk, 8.5e-2, 0.01), (W.elliptic_divmin_disk, 3.1e-2, 0.05)]:
+        u = lambda q: fn(q)[0]
+        e = W.voronoi_l2_error(dom, sites, u(sites), u, npoints=1 << 21)
+        assert abs(e - paper) <= tol * paper, (fn.__name__, e)
+    # the measure itself: a constant field against its own values is zero,
+    # and against zero values it is |u| in L^2: |1|_L2(disk) = sqrt(pi)
+    one = lambda q: np.ones(len(q))
+    assert W.voronoi_l2_error(dom, sites, np.ones(len(sites)), one, npoints=1 << 16) == 0.0
+    assert abs(W.voronoi_l2_error(dom, sites, np.zeros(len(sites)), one, npoints=1 << 20) - np.sqrt(np.pi)) < 5e-3

@@ -219,6 +219,59 @@ def elliptic_divmin_disk(x):
     return u, np.stack([ux, uy], 1), f
 
 
+def elliptic_div_disk(x):
+    """The example "elliptic div" on the unit disk: div(A grad u) + b.grad u
+    - c u = f with A = [[2 + x^2, xy], [xy, 2 + y^2]], b = (-y, x), c = 1 and
+    u = (1 - x^2 - y^2) sin(pi x) (0 on the circle).  Returns u, grad u
+    (n, 2) and f by hand-differentiated closed forms (div A = (3x, 3y)).
+    Problem data, like the manufactured solutions here."""
+    x = np.asarray(x, dtype=np.float64)
+    X, Y = x[:, 0], x[:, 1]
+    s = 1.0 - X * X - Y * Y
+    sn, cs = np.sin(np.pi * X), np.cos(np.pi * X)
+    u = s * sn
+    ux = -2 * X * sn + s * np.pi * cs
+    uy = -2 * Y * sn
+    uxx = -2 * sn - 4 * X * np.pi * cs - s * np.pi ** 2 * sn
+    uyy = -2 * sn
+    uxy = -2 * Y * np.pi * cs
+    div = (2 + X * X) * uxx + 2 * X * Y * uxy + (2 + Y * Y) * uyy + 3 * X * ux + 3 * Y * uy
+    f = div + (-Y) * ux + X * uy - u
+    return u, np.stack([ux, uy], 1), f
+
+
+def elliptic_div_coef(x):
+    """The example's coefficients at the sites: A (n, 2, 2), b (n, 2), c (n,)."""
+    x = np.asarray(x, dtype=np.float64)
+    X, Y = x[:, 0], x[:, 1]
+    A = np.stack([np.stack([2 + X * X, X * Y], -1), np.stack([X * Y, 2 + Y * Y], -1)], -2)
+    return A, np.stack([-Y, X], 1), np.ones(len(x))
+
+
+def voronoi_l2_error(dom, sites, values, u_fn, npoints=1 << 21, seed=5):
+    """Absolute L^2(D) distance between a function u_fn (callable on points
+    (k, d)) and the piecewise-constant field equal to values[i] on the
+    Voronoi cell of sites[i]: (sum_i int_{V_i} (u - values_i)^2)^(1/2), by
+    Monte Carlo over uniform points of the domain's bounding box (the
+    measure of Table "errors" of the examples)."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    lo, hi = bbox(dom)
+    tree = cKDTree(np.asarray(sites, dtype=np.float64))
+    values = np.asarray(values, dtype=np.float64)
+    vol = float(np.prod(hi - lo))
+    acc, chunk, done = 0.0, 1 << 18, 0
+    while done < npoints:
+        k = min(chunk, npoints - done)
+        q = lo + (hi - lo) * rng.random((k, len(lo)))
+        q = q[interior_with_margin(dom, q, 0.0)]
+        if len(q):
+            j = tree.query(q)[1]
+            acc += float(((u_fn(q) - values[j]) ** 2).sum())
+        done += k
+    return np.sqrt(acc * vol / npoints)
+
+
 def elliptic_divmin_coef(x):
     """The example's coefficient fields at the sites: A (n, 2, 2), c (n,)
     and the weight w = exp(-phi) (n,)."""
