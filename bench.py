@@ -60,25 +60,27 @@ WALKER_BUDGET = {  # (C_step, C_walk) by workload geometry
 
 def walker_source_hash():
     h = hashlib.sha256()
-    for f in ("walker.hip", "wos_device.hpp", "wos_types.hpp"):
+    for f in ("walker.hip", "walker_impl.hpp", "walker_f32_2d.hip", "walker_f32_3d.hip", "wos_device.hpp",
+              "wos_types.hpp", "grid.cpp"):
         with open(os.path.join(ROOT, "paper_2608_07017_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
-    """HBM bytes per walker launch from the committed FETCH_SIZE / WRITE_SIZE
-    summary of this workload, or None when the walker source has changed
-    since the counters were taken (or no summary exists)."""
+def measured_traffic(workload, walk_steps):
+    """HBM bytes of one walker launch of `walk_steps` walk-steps, from the
+    committed FETCH_SIZE / WRITE_SIZE summary of this workload (bytes per
+    walk-step), or None when the walker source has changed since the
+    counters were taken (or no summary exists)."""
     path = os.path.join(ROOT, "profiles", "walker_%s.md" % workload)
     if not os.path.exists(path):
         return None
     text = open(path).read()
     h = re.search(r"sha256/16\): `([0-9a-f]+)`", text)
-    t = re.search(r"walker_traffic_bytes_per_launch = ([0-9.eE+]+)", text)
+    t = re.search(r"walker_traffic_bytes_per_walk_step = ([0-9.eE+]+)", text)
     if not h or not t or h.group(1) != walker_source_hash():
         return None
-    return float(t.group(1))
+    return float(t.group(1)) * walk_steps
 
 
 def parse():
@@ -735,7 +737,7 @@ def main():
                    "tally_mode": plan["tally_mode"], "window_pages": plan["window_pages"],
                    "window_bpages": plan["window_bpages"], "harmonic_extension_rms_err": herr},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(a.workload),
+                     "frac": achieved / peak, "traffic": measured_traffic(a.workload, mean_steps),
                      "budget": {"per_walk_step": c_step, "per_walk": c_walk}},
     }
     if a.probe:

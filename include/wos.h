@@ -106,10 +106,15 @@ typedef struct {
                                WINDOW (2, FP32): the V cells and the boundary
                                cells are numbered along a Morton curve in pages
                                of 64; each site keeps the pages nearest to it
-                               (window_pages, window_bpages) in LDS and adds the
-                               tallies that fall elsewhere straight into the
-                               toolbox (device atomics); the columns are put back
-                               in the caller's order at the end of the build.
+                               (window_pages, window_bpages) in LDS as exact
+                               64-bit fixed-point sums (its items hold few
+                               enough walks that the bound of
+                               wos_build_plan.fixed_bound stays below 1/2) and
+                               adds the tallies that fall elsewhere straight
+                               into the toolbox (device atomics); the columns
+                               are put back in the caller's order at the end of
+                               the build.  AUTO takes it only when items of at
+                               least 256 walks satisfy the bound.
                                HBM (3): every tally straight into the toolbox by
                                device atomics, pre-scaled by 1/N.
                                Outside LDS_ROWS the sums are in the toolbox
@@ -135,10 +140,11 @@ typedef struct {
                                bound of wos_build_plan.fixed_bound reaches 1/2,
                                then FP64), 1 fixed point (WOS_EINVAL when the bound
                                reaches 1/2), 2 FP64.  FP64 toolboxes always
-                               accumulate in FP64.                               */
+                               accumulate in FP64; WINDOW always in fixed point
+                               (2 is refused there).                             */
   int32_t window_pages;     /* WINDOW: pages of V cells per site in LDS (0: as many
-                               as fit 78 KiB with the boundary pages, i.e. two
-                               workgroups per compute unit)                      */
+                               as fit 152 KiB with the boundary pages, i.e. one
+                               workgroup of 1024 lanes per compute unit)         */
   int32_t window_bpages;    /* WINDOW: pages of boundary cells per site in LDS
                                (0: min(16, all))                                 */
   const double* test_phi;   /* host, m values or NULL: a test function phi on the
@@ -176,7 +182,8 @@ enum { WOS_ACC_AUTO = 0, WOS_ACC_FIXED = 1, WOS_ACC_F64 = 2 };
  * r0 the smallest distance of a site to the boundary.                        */
 typedef struct {
   int32_t tally_mode;       /* the mode used (never AUTO)                         */
-  int32_t tally_acc;        /* LDS_ROWS: WOS_ACC_FIXED or WOS_ACC_F64             */
+  int32_t tally_acc;        /* LDS_ROWS: WOS_ACC_FIXED or WOS_ACC_F64; WINDOW:
+                               WOS_ACC_FIXED                                      */
   int32_t walks_per_item;   /* walks one workgroup takes per site                 */
   int32_t items_per_site;
   int32_t window_pages;     /* WINDOW: V pages per site held in LDS              */

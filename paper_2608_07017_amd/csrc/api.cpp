@@ -417,7 +417,8 @@ struct Plan {
 };
 
 constexpr size_t kLdsBytes = 160 * 1024;
-constexpr size_t kWindowBudget = 78 * 1024;  // two walker workgroups per compute unit
+constexpr size_t kWindowBudget = 152 * 1024;  // one walker workgroup of 1024 lanes per compute unit
+constexpr int64_t kWindowMinItem = 256;        // smallest item that the fixed-point guard may ask for
 
 wos_status make_plan(const HostDomain& hd, const double* sites, int n, int m, int p, const wos_build_opts* o,
                      Plan* pl) {
@@ -427,13 +428,36 @@ wos_status make_plan(const HostDomain& hd, const double* sites, int n, int m, in
   const size_t lds_rows = walker_lds_bytes(d, m, p, nseg, f64);
   const bool rows_fit = lds_rows <= kLdsBytes;
   const bool win_ok = !f64 && (size_t)m <= permute_max_cols() && (size_t)p <= permute_max_cols();
+
+  // bound on the sums a fixed-point word receives, per walk of an item (see
+  // wos.h): |K| <= d / r0, |B| <= 4 (d / r0) R^2 / d, |A| <= 4 omega_max R^2 / d
+  // over the walk's tallies, R the half-diagonal of the bounding box
+  double lo[3], hi[3];
+  host_bbox(hd, lo, hi);
+  double R2 = 0;
+  for (int a = 0; a < d; ++a) R2 += 0.25 * (hi[a] - lo[a]) * (hi[a] - lo[a]);
+  double r0min = 1e300;
+  for (int i = 0; i < n; ++i) r0min = std::min(r0min, host_distance(hd, sites + (size_t)i * d));
+  const double om_max = (d == 2 && o->sampler == WOS_SAMPLER_MEDIAN3) ? 12.0 : 1.0;
+  const double per_walk = std::max(d / r0min, std::max(4.0 * (d / r0min) * R2 / d, 4.0 * om_max * R2 / d));
+  // the most walks per item that keep the bound below 1/2
+  const double wpi_fixed = 0.49 * 2147483648.0 / per_walk;
+
   int mode = o->tally_mode;
-  if (mode == WOS_TALLY_AUTO) mode = rows_fit ? WOS_TALLY_LDS_ROWS : win_ok ? WOS_TALLY_WINDOW : WOS_TALLY_HBM;
+  if (mode == WOS_TALLY_AUTO)
+    mode = rows_fit ? WOS_TALLY_LDS_ROWS
+                    : (win_ok && wpi_fixed >= (double)std::min<int64_t>(kWindowMinItem, o->walks_per_site))
+                          ? WOS_TALLY_WINDOW
+                          : WOS_TALLY_HBM;
   if (mode == WOS_TALLY_LDS_ROWS && !rows_fit)
     return fail(WOS_EINVAL, "tally_mode LDS_ROWS: a site's rows take %zu bytes of LDS (at most %zu)", lds_rows,
                 kLdsBytes);
   if (mode == WOS_TALLY_WINDOW && !win_ok)
     return fail(WOS_EINVAL, "tally_mode WINDOW needs an FP32 toolbox with m, p <= %zu", permute_max_cols());
+  if (mode == WOS_TALLY_WINDOW && o->tally_acc == WOS_ACC_F64)
+    return fail(WOS_EINVAL, "tally_mode WINDOW sums in fixed point (tally_acc FP64 is for LDS_ROWS)");
+  if (mode == WOS_TALLY_WINDOW && wpi_fixed < 1.0)
+    return fail(WOS_EINVAL, "tally_mode WINDOW: a site is too close to the boundary for fixed-point sums");
   pl->mode = mode;
 
   const int npv = (m + kPage - 1) / kPage, npb = (p + kPage - 1) / kPage;
@@ -443,7 +467,7 @@ wos_status make_plan(const HostDomain& hd, const double* sites, int n, int m, in
     pb = std::max(1, std::min(pb, npb));
     int pc = o->window_pages;
     if (pc <= 0) {
-      const size_t per_page = 4 * (size_t)(1 + d) * kPage;
+      const size_t per_page = 8 * (size_t)(1 + d) * kPage;
       const size_t fixed = walker_window_lds_bytes(d, 0, pb, npv, npb, nseg) + 2 * 255;
       pc = fixed < kWindowBudget ? (int)((kWindowBudget - fixed) / per_page) : 1;
     }
@@ -478,24 +502,16 @@ wos_status make_plan(const HostDomain& hd, const double* sites, int n, int m, in
     const int64_t floor_w = std::min<int64_t>(N, 4 * (int64_t)bs);  // >= 4 walks per lane
     wpi = std::max<int64_t>((N + ips - 1) / ips, floor_w);
   }
+  // the windowed mode always sums in fixed point: items small enough for it
+  if (mode == WOS_TALLY_WINDOW) wpi = std::max<int64_t>(1, std::min<int64_t>(wpi, (int64_t)wpi_fixed));
   pl->wpi = (int)wpi;
   pl->ips = (int)((N + wpi - 1) / wpi);
   if ((int64_t)pl->ips * n > (int64_t)INT32_MAX) return fail(WOS_EINVAL, "too many work items");
 
-  // bound on the per-item sums a fixed-point word receives (see wos.h)
-  double lo[3], hi[3];
-  host_bbox(hd, lo, hi);
-  double R2 = 0;
-  for (int a = 0; a < d; ++a) R2 += 0.25 * (hi[a] - lo[a]) * (hi[a] - lo[a]);
-  double r0min = 1e300;
-  for (int i = 0; i < n; ++i) r0min = std::min(r0min, host_distance(hd, sites + (size_t)i * d));
-  const double om_max = (d == 2 && o->sampler == WOS_SAMPLER_MEDIAN3) ? 12.0 : 1.0;
-  const double Ni = (double)wpi;
-  const double bK = Ni * d / r0min;
-  const double bB = 4.0 * Ni * (d / r0min) * R2 / d;
-  const double bA = 4.0 * Ni * om_max * R2 / d;
-  pl->fixed_bound = std::max(bK, std::max(bB, bA)) / 2147483648.0;
-  if (f64 || mode != WOS_TALLY_LDS_ROWS) {
+  pl->fixed_bound = (double)wpi * per_walk / 2147483648.0;
+  if (mode == WOS_TALLY_WINDOW) {
+    pl->acc = WOS_ACC_FIXED;
+  } else if (f64 || mode != WOS_TALLY_LDS_ROWS) {
     pl->acc = f64 ? WOS_ACC_F64 : WOS_ACC_AUTO;
   } else if (o->tally_acc == WOS_ACC_F64) {
     pl->acc = WOS_ACC_F64;
@@ -675,10 +691,14 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
   host_bbox(hd, lo, hi);
   double vol = 1;
   for (int a = 0; a < d; ++a) vol *= (hi[a] - lo[a]);
-  const double h_v = std::pow(vol / m, 1.0 / d) / (d == 2 ? 8.0 : 4.0);
+  // cell side: a fraction of the mean centre spacing, so that most cells
+  // hold at most four candidates (3-D: 1/6, which leaves about 2 % of the
+  // cells of uniformly scattered centres to the overflow entries)
+  const double h_div = d == 2 ? 8.0 : 6.0;
+  const double h_v = std::pow(vol / m, 1.0 / d) / h_div;
   GridHost gvh = build_grid(tb->vsites.data(), m, d, lo, hi, h_v, 1 << 24);
   GridHost gwh;
-  if (wv) gwh = build_grid(sites, n, d, lo, hi, std::pow(vol / n, 1.0 / d) / (d == 2 ? 8.0 : 4.0), 1 << 24);
+  if (wv) gwh = build_grid(sites, n, d, lo, hi, std::pow(vol / n, 1.0 / d) / h_div, 1 << 24);
   const double bm = host_boundary_measure(hd);
   const double sp_b = d == 2 ? bm / p : std::sqrt(bm / p);
   GridHost ggh = build_grid(bnodes, p, d, lo, hi, sp_b / 4.0, 1 << 23);

@@ -11,10 +11,11 @@ hipError_t walker_dispatch_f64_2d(const WalkerParams<double>& P, int kind, size_
 hipError_t walker_dispatch_f64_3d(const WalkerParams<double>& P, int kind, size_t lds, int items, hipStream_t st);
 
 size_t walker_window_lds_bytes(int dim, int pc, int pb, int npv, int npb, int nseg) {
-  // FP32 sums of A, B, K and the counts of H for the listed pages, the edges,
-  // the page lists (2 bytes each) and the page -> slot tables (1 byte each)
-  return 4 * (size_t)(1 + dim) * kPageCells * (size_t)(pc + pb) + 4 * 5 * (size_t)nseg + 2 * (size_t)(pc + pb) +
-         (size_t)(npv + npb);
+  // 64-bit fixed-point sums of A, B (listed V pages) and K (listed boundary
+  // pages), the 32-bit counts of H, the edges, the page lists (2 bytes each)
+  // and the page -> slot tables (1 byte each)
+  return 8 * (size_t)(1 + dim) * kPageCells * (size_t)pc + (8 * (size_t)dim + 4) * kPageCells * (size_t)pb +
+         4 * 5 * (size_t)nseg + 2 * (size_t)(pc + pb) + (size_t)(npv + npb);
 }
 
 size_t walker_lds_bytes(int dim, int m, int p, int nseg, bool f64) {

@@ -10,10 +10,14 @@
 // order of the atomics): on gfx950 both are several times faster than FP32
 // LDS atomics, which the tally rate would otherwise be bound by.  The
 // workgroup size (256 / 448 / 512 / 1024) is chosen by occupancy, or timed
-// on the first build.  When a site's rows do not fit in LDS (or the caller
-// asks for it) the kernel adds every tally, pre-scaled by 1/N, straight
-// into the toolbox with device atomics instead (`kAccGlobal`); the walks
-// are the same.
+// on the first build.  When a site's rows do not fit in LDS, the windowed
+// mode (`kAccWindow`) keeps the pages of cells nearest to the site (cells
+// numbered along a Morton curve) in LDS, again as exact 64-bit fixed-point
+// sums (FP32 LDS atomics are the slow kind), in one workgroup of 1024
+// lanes per compute unit, and adds the tallies that fall outside them,
+// pre-scaled by 1/N, straight into the toolbox with device atomics; or
+// (`kAccGlobal`) every tally goes there.  The walks are the same in every
+// mode.
 //
 // Lanes run walks back to back, so the long tail of walk lengths does not
 // idle a wavefront.  The loop advances in supersteps of four chain steps.
@@ -59,8 +63,8 @@ constexpr size_t kLdsMax = 160 * 1024;
 
 // Tally accumulators: FP64 or fixed point in LDS, or (rows too large for
 // LDS) atomics straight to the toolbox in HBM, pre-scaled by 1/N, or the
-// windowed mode: FP32 LDS sums for the pages of cells listed for the site,
-// device atomics (pre-scaled) for the cells outside them.
+// windowed mode: fixed-point LDS sums for the pages of cells listed for the
+// site, device atomics (pre-scaled) for the cells outside them.
 enum { kAccF64 = 0, kAccFixed = 1, kAccGlobal = 2, kAccWindow = 3 };
 constexpr int kPageCells = 64;     // cells per page (consecutive Morton ranks)
 constexpr unsigned char kNoSlot = 0xFF;
@@ -134,7 +138,7 @@ struct AccWord<kAccGlobal, T> {
 };
 template <typename T>
 struct AccWord<kAccWindow, T> {
-  using type = T;
+  using type = typename Acc<kAccFixed>::word;
 };
 
 // KIND carries the domain kind in its low four bits, in bit 4
@@ -186,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   const int pc = P.win_pc, pb = P.win_pb;
   if constexpr (WINDOW) {
     const size_t vs = (size_t)pc * kPageCells, gs = (size_t)pb * kPageCells;
-    sA = reinterpret_cast<AW*>(smem);
+    sA = reinterpret_cast<AW*>(smem);  // 64-bit fixed-point words
     sB = sA + vs;
     sK = sB + (size_t)D * vs;
     sH = reinterpret_cast<unsigned int*>(sK + (size_t)D * gs);
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
     if constexpr (WINDOW) {
       const unsigned int sl = tV[j >> 6];
       if (sl != kNoSlot)
-        lds_atomic_add(&sA[(sl << 6) | (j & 63)], v);
+        lds_atomic_add(&sA[(sl << 6) | (j & 63)], Acc<kAccFixed>::encode(v));
       else
         dev_atomic_add(&gA[j], v * P.inv_N);
     } else {
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
       if (sl != kNoSlot) {
         const int c = (sl << 6) | (j & 63);
 #pragma unroll
-        for (int a = 0; a < D; ++a) lds_atomic_add(&sB[a * bstride + c], v[a]);
+        for (int a = 0; a < D; ++a) lds_atomic_add(&sB[a * bstride + c], Acc<kAccFixed>::encode(v[a]));
       } else {
 #pragma unroll
         for (int a = 0; a < D; ++a) dev_atomic_add(&gB[a * gbs + j], v[a] * P.inv_N);
@@ -260,9 +264,9 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
       const unsigned int sl = tV[j >> 6];
       if (sl != kNoSlot) {
         const int c = (sl << 6) | (j & 63);
-        lds_atomic_add(&sA[c], t);
+        lds_atomic_add(&sA[c], Acc<kAccFixed>::encode(t));
 #pragma unroll
-        for (int a = 0; a < D; ++a) lds_atomic_add(&sB[a * bstride + c], t * wv[a]);
+        for (int a = 0; a < D; ++a) lds_atomic_add(&sB[a * bstride + c], Acc<kAccFixed>::encode(t * wv[a]));
       } else {
         const T ts = t * P.inv_N;
         dev_atomic_add(&gA[j], ts);
@@ -282,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
         const int c = (sl << 6) | (j & 63);
         lds_atomic_add(&sH[c], 1u);
 #pragma unroll
-        for (int a = 0; a < D; ++a) lds_atomic_add(&sK[a * kstride + c], wv[a]);
+        for (int a = 0; a < D; ++a) lds_atomic_add(&sK[a * kstride + c], Acc<kAccFixed>::encode(wv[a]));
       } else {
         dev_atomic_add(&gH[j], 1u);
 #pragma unroll
@@ -298,7 +302,9 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   const int tid = threadIdx.x;
   if constexpr (WINDOW) {
     const int cells = (pc + pb) * kPageCells;
-    for (int j = tid; j < (1 + D) * cells; j += kBlock) sA[j] = T(0);  // sH's zero bits included
+    for (int j = tid; j < (1 + D) * pc * kPageCells + D * pb * kPageCells; j += kBlock) sA[j] = AW(0);
+    for (int j = tid; j < pb * kPageCells; j += kBlock) sH[j] = 0u;
+    (void)cells;
     const unsigned short* lst = P.win + (size_t)site * (pc + pb);
     for (int j = tid; j < pc + pb; j += kBlock) wl[j] = lst[j];
     for (int j = tid; j < P.npv + P.npb; j += kBlock) tV[j] = kNoSlot;
@@ -366,11 +372,12 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   // S = sum_{k >= 1} t_k phi(j_k); pool copies of the first two; per lane
   // the sums of c and c^2 over its finished walks.
   T pm0 = T(0), m0 = T(0), mS = T(0);
-  T pmb[D], mb[D], macc[NMOM];
+  T pmb[D], mb[D];
+  double macc[NMOM];  // FP64, so that the sums do not depend on which lane ran which walk
 #pragma unroll
   for (int a = 0; a < D; ++a) pmb[a] = mb[a] = T(0);
 #pragma unroll
-  for (int e = 0; e < NMOM; ++e) macc[e] = T(0);
+  for (int e = 0; e < NMOM; ++e) macc[e] = 0.0;
   unsigned long long n_walks = 0;  // wave-uniform
   unsigned int lane_steps = 0, lane_capped = 0, lane_maxk = 0;
 
@@ -459,16 +466,16 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
       if constexpr (MOM) {
         // the walk's values of the four test functionals (eqs. u MC,
         // gradu U MC, H MC, dh MC with the binned data phi and psi)
-        const T ps = P.mom_psi[j];
-        const T cA = m0 + mS;
+        const double ps = (double)P.mom_psi[j];
+        const double cA = (double)(m0 + mS);
         macc[0] += cA;
         macc[1] += cA * cA;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          const T cB = mb[a] + w[a] * mS;
+          const double cB = (double)(mb[a] + w[a] * mS);
           macc[2 + a] += cB;
           macc[2 + D + a] += cB * cB;
-          const T cK = w[a] * ps;
+          const double cK = (double)w[a] * ps;
           macc[4 + 2 * D + a] += cK;
           macc[4 + 3 * D + a] += cK * cK;
         }
@@ -620,7 +627,7 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
     double* mrow = P.mom + (size_t)site * NMOM;
 #pragma unroll
     for (int e = 0; e < NMOM; ++e) {
-      double v = (double)macc[e];
+      double v = macc[e];
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
       if (lane == 0 && v != 0.0) atomicAdd(&mrow[e], v);
@@ -635,16 +642,16 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   if constexpr (GLOBAL || WINDOW) {
     if constexpr (WINDOW) {
       // the window's sums, scaled by 1/N, onto the toolbox rows
-      const T inv_N = P.inv_N;
+      const double inv_N = (double)P.inv_N;
       for (int c = tid; c < pc * kPageCells; c += kBlock) {
         const int j = ((int)wl[c >> 6] << 6) | (c & 63);
         if (j < m) {
-          const T va = sA[c];
-          if (va != T(0)) atomicAdd(&gA[j], va * inv_N);
+          const AW va = sA[c];
+          if (va != AW(0)) dev_atomic_add(&gA[j], (T)(Acc<kAccFixed>::value(va) * inv_N));
 #pragma unroll
           for (int a = 0; a < D; ++a) {
-            const T vb = sB[a * bstride + c];
-            if (vb != T(0)) atomicAdd(&gB[a * gbs + j], vb * inv_N);
+            const AW vb = sB[a * bstride + c];
+            if (vb != AW(0)) dev_atomic_add(&gB[a * gbs + j], (T)(Acc<kAccFixed>::value(vb) * inv_N));
           }
         }
       }
@@ -652,11 +659,11 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
         const int j = ((int)wl[pc + (c >> 6)] << 6) | (c & 63);
         if (j < p) {
           const unsigned int h = sH[c];
-          if (h) atomicAdd(&gH[j], h);
+          if (h) dev_atomic_add(&gH[j], h);
 #pragma unroll
           for (int a = 0; a < D; ++a) {
-            const T vk = sK[a * kstride + c];
-            if (vk != T(0)) atomicAdd(&gK[a * gks + j], vk * inv_N);
+            const AW vk = sK[a * kstride + c];
+            if (vk != AW(0)) dev_atomic_add(&gK[a * gks + j], (T)(Acc<kAccFixed>::value(vk) * inv_N));
           }
         }
       }

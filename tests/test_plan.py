@@ -16,21 +16,24 @@ def _plan(name, **kw):
 
 def test_workload_plans():
     # rows in LDS while they fit, the windowed mode for the 32768-site box
-    # minus ball (its rows take 640 KB), two walker workgroups per compute unit
+    # minus ball (its rows take 640 KB), one walker workgroup per compute unit,
+    # fixed-point sums
     assert _plan("square1024")["tally_mode"] == "lds_rows"
     assert _plan("ball4096")["tally_mode"] == "lds_rows"
     cb = _plan("cubeball32768")
     assert cb["tally_mode"] == "window"
     assert cb["window_bpages"] == 16 and 40 <= cb["window_pages"] <= 255
-    assert cb["lds_bytes"] <= 78 * 1024
+    assert 140 * 1024 <= cb["lds_bytes"] <= 160 * 1024
+    assert cb["tally_acc"] == "fixed" and cb["fixed_bound"] < 0.5
     assert cb["items_per_site"] * cb["walks_per_item"] >= 100000
 
 
 def test_window_size_options():
-    pl = _plan("cubeball32768", window_pages=100, window_bpages=24)
-    assert pl["window_pages"] == 100 and pl["window_bpages"] == 24
-    # 4 (1 + d) 64 bytes per page plus tables and lists
-    assert pl["lds_bytes"] == 4 * 4 * 64 * 124 + 2 * 124 + 512 + 128
+    pl = _plan("cubeball32768", window_pages=50, window_bpages=24)
+    assert pl["window_pages"] == 50 and pl["window_bpages"] == 24
+    # 8 (1 + d) 64 bytes per V page, (8 d + 4) 64 per boundary page, plus
+    # tables and lists
+    assert pl["lds_bytes"] == 8 * 4 * 64 * 50 + 28 * 64 * 24 + 2 * 74 + 512 + 128
     with pytest.raises(P.WosError):   # more than LDS holds
         _plan("cubeball32768", window_pages=255, window_bpages=255)
 
@@ -44,6 +47,8 @@ def test_forced_modes_and_their_limits():
         _plan("disk64", tally="window")          # FP64 toolbox
     with pytest.raises(P.WosError):
         _plan("square1024", walker_block=300)
+    with pytest.raises(P.WosError):
+        _plan("cubeball32768", tally="window", tally_acc="f64")   # the window sums in fixed point
 
 
 def _near_boundary_case(r0, walks, **kw):
@@ -78,6 +83,25 @@ def test_fixed_point_overflow_guard():
     small = P.build_plan(W.unit_square(), np.array([[0.5, 0.5], [1e-6, 0.5]]), W.square_nodes(4), 100000, 1e-9,
                          walks_per_item=100)
     assert small["fixed_bound"] < 0.5 and small["tally_acc"] == "fixed"
+
+
+def test_window_items_are_split_for_fixed_point():
+    # the windowed mode always sums in fixed point: a site 1e-6 from the
+    # boundary splits its 1e5 walks into items that keep the bound below 1/2
+    # (per walk: 4 (d / r0) R^2 / d with R^2 = 1/2 -> 2e6; items of at most
+    # 0.49 2^31 / 2e6 = 526 walks); automatic mode takes it as long as the
+    # items keep at least 256 walks, else the HBM mode
+    pl = _near_boundary_case(1e-6, 100000, tally="window")
+    assert pl["tally_mode"] == "window" and pl["tally_acc"] == "fixed"
+    assert pl["walks_per_item"] == int(0.49 * 2 ** 31 / 2e6)
+    assert pl["fixed_bound"] < 0.5
+    assert pl["items_per_site"] * pl["walks_per_item"] >= 100000
+    with pytest.raises(P.WosError):
+        _near_boundary_case(1e-10, 1000, tally="window")      # not even one walk per item fits
+    dom = W.unit_square()
+    sites = np.concatenate([W.sample_sites(dom, 8000, 3, 1e-3), [[1e-7, 0.5]]])
+    auto = P.build_plan(dom, sites, W.square_nodes(4), 100000, 1e-9)
+    assert auto["tally_mode"] == "hbm"          # rows beyond LDS, items of 52 walks would be too small
 
 
 def test_plan_rejects_bad_inputs():
