@@ -265,12 +265,16 @@ typedef enum {
   WOS_EXPORT_LAMBDA_V = 7, /* m,         double |V_j| / |D| (= lambda when V = W) */
   WOS_EXPORT_SITE_STEPS = 8, /* n,       uint64 walk-steps of each site's walks of the
                                last build (k = 0 tallies plus chain tallies)      */
-  WOS_EXPORT_MOMENTS = 9    /* n x (4 + 4d) double, with the test functions of the
+  WOS_EXPORT_MOMENTS = 9,   /* n x (4 + 4d) double, with the test functions of the
                                build options: per site sum c_A, sum c_A^2,
                                sum c_B (d), sum c_B^2 (d), sum c_H, sum c_H^2,
                                sum c_K (d), sum c_K^2 (d) over its N walks; the
                                standard error of a mean is
                                sqrt((sum c^2 / N - (sum c / N)^2) / (N - 1))    */
+  WOS_EXPORT_SHADOW_V = 10, /* uint16 BF16 bits, m x (d+1) n: the shadow of [B; A]
+                               transposed, S_V[j][a n + i] = B^(a)_ij (a < d),
+                               S_V[j][d n + i] = A_ij (rounded to nearest even)   */
+  WOS_EXPORT_SHADOW_G = 11  /* uint16 BF16 bits, p x (d+1) n: the same for [K; H] */
 } wos_export_what;
 
 /* Copies one toolbox array into dst (device if dst_is_device, else host),
@@ -303,6 +307,32 @@ wos_status wos_toolbox_take(wos_toolbox* dst, const wos_toolbox* src, uint32_t m
 wos_status wos_apply(const wos_toolbox* tb, const double* fbar, const double* g, double* u,
                      double* grad_u, void* stream);
 
+/* BF16 shadows of the built toolbox (low-precision copies kept resident for
+ * the matrix cores and for bandwidth-bound applies):
+ * S_V = [B; A]^T and S_G = [K; H]^T, rounded to nearest even, about
+ * 2 (d+1) n (m + p) bytes on the device, made on `stream` and remade by the
+ * next BF16 call after a build, load or take.  Asynchronous.                   */
+wos_status wos_toolbox_make_bf16(wos_toolbox* tb, void* stream);
+
+/* wos_apply from the BF16 shadows (made first if needed): the products read
+ * BF16 operands and accumulate in FP64 in a fixed order, so the result
+ * differs from wos_apply by the rounding of the toolbox to BF16 (relative
+ * about 2^-9 per entry).  Uses work buffers of the toolbox: calls on one
+ * toolbox must not overlap.  Asynchronous.                                      */
+wos_status wos_apply_bf16(wos_toolbox* tb, const double* fbar, const double* g, double* u, double* grad_u,
+                          void* stream);
+
+/* The matrix-core product behind the BF16 route, for callers that assemble
+ * their own systems from the shadows: C = alpha X Y^T + beta C with X (M x K,
+ * leading dimension ldx) and Y (N x K, ldy) BF16 (uint16 bits), both
+ * row-major with K contiguous, C (M x N, ldc) FP32 row-major, FP32
+ * accumulation (v_mfma_f32_16x16x32_bf16).  All device pointers.  16-byte
+ * loads when X, Y are 16-byte aligned and ldx, ldy are multiples of 8, else
+ * element loads.  Errors: WOS_EINVAL for a NULL pointer, negative sizes or
+ * leading dimensions below K (or N for C).  Asynchronous.                      */
+wos_status wos_gemm_bf16_nt(int32_t M, int32_t N, int32_t K, float alpha, const uint16_t* X, int64_t ldx,
+                            const uint16_t* Y, int64_t ldy, float beta, float* C, int64_t ldc, void* stream);
+
 /* ------------------------------------------------------------- solves */
 typedef enum {
   WOS_LINEAR = 0,            /* div(A grad u) + b . grad u - c u = f, u = g (eq. linearPDE) */
@@ -323,7 +353,7 @@ typedef enum {
 
 typedef enum {
   WOS_SOLVE_F64 = 0,   /* every step in FP64                                          */
-  WOS_SOLVE_MIXED = 1  /* Tikhonov on an FP32 toolbox: Lambda and the normal matrix
+  WOS_SOLVE_MIXED = 1, /* Tikhonov on an FP32 toolbox: Lambda and the normal matrix
                           formed and factored in FP32 on the matrix cores, then
                           iterative refinement with FP64 residuals of the exact
                           system (matrix-free) to refine_tol; falls back to FP64 when
@@ -331,6 +361,15 @@ typedef enum {
                           parameter is the FP64 route's (from exact FP64 columns
                           of Lambda, or the exact FP64 diagonal of the Newton
                           Hessian), so both routes solve the same system.       */
+  WOS_SOLVE_MIXED_BF16 = 2  /* Tikhonov (LINEAR, QUASILINEAR) from the toolbox's BF16
+                          shadows (made or remade as wos_toolbox_make_bf16 does):
+                          Lambda assembled on the matrix cores from BF16 operands
+                          (v_mfma_f32_16x16x32_bf16, FP32 accumulation), the
+                          normal matrix and its Cholesky factor in FP32, then
+                          preconditioned conjugate gradients on the normal
+                          equations with FP64 matrix-free products of the exact
+                          toolbox to refine_tol (max_refine 0 -> 50 iterations);
+                          the regularisation parameter is the FP64 route's.    */
 } wos_solve_precision;
 
 typedef struct {

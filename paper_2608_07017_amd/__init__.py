@@ -19,7 +19,7 @@ from ._lib import (ENERGIES, EXPORTS, HISD_INIT, HISD_PRECOND, KINDS, PRECISION,
                    WosBuildOpts, WosCoeffs, WosOperatorInfo, WosOperatorOpts, WosDomain, WosError, WosServerOpts,
                    WosSolveInfo, WosToolboxInfo, check, lib)
 
-__all__ = ["Toolbox", "Server", "build_toolbox", "build_plan", "WosError", "lib"]
+__all__ = ["Toolbox", "Server", "build_toolbox", "build_plan", "gemm_bf16_nt", "WosError", "lib"]
 
 
 def _stream_handle(stream=None):
@@ -97,6 +97,25 @@ def probe_valu(op, iters=4096, stream=None):
     rate = ctypes.c_double()
     check(lib().wos_probe_valu(PROBE_OPS[op], int(iters), ctypes.byref(rate), _stream_handle(stream)))
     return rate.value
+
+
+def gemm_bf16_nt(X, Y, C=None, alpha=1.0, beta=0.0, stream=None):
+    """C = alpha X Y^T + beta C on the matrix cores (include/wos.h,
+    wos_gemm_bf16_nt): X (M, K), Y (N, K) torch.bfloat16 device tensors,
+    C (M, N) float32 (a new one when None)."""
+    if X.dtype != torch.bfloat16 or Y.dtype != torch.bfloat16:
+        raise TypeError("X and Y must be bfloat16")
+    if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1] or X.stride(1) != 1 or Y.stride(1) != 1:
+        raise ValueError("X (M, K) and Y (N, K) with K contiguous")
+    M, K = X.shape
+    N = Y.shape[0]
+    if C is None:
+        C = torch.zeros((M, N), dtype=torch.float32, device=X.device)
+    if C.dtype != torch.float32 or tuple(C.shape) != (M, N) or C.stride(1) != 1:
+        raise ValueError("C must be float32 (M, N), rows contiguous")
+    check(lib().wos_gemm_bf16_nt(M, N, K, float(alpha), _dptr(X), X.stride(0), _dptr(Y), Y.stride(0), float(beta),
+                                 _dptr(C), C.stride(0), _stream_handle(stream)))
+    return C
 
 
 class Toolbox:
@@ -206,11 +225,13 @@ class Toolbox:
                 "K": ((d, n, p), self.dtype), "Hcount": ((n, p), torch.int32),
                 "lambda": ((n,), torch.float64), "vcount": ((n,), torch.int64),
                 "lambda_v": ((m,), torch.float64), "site_steps": ((n,), torch.int64),
-                "moments": ((n, 4 + 4 * d), torch.float64)}[what]
+                "moments": ((n, 4 + 4 * d), torch.float64),
+                "shadow_v": ((m, (d + 1) * n), torch.int16), "shadow_g": ((p, (d + 1) * n), torch.int16)}[what]
 
     def export(self, what, stream=None):
         """A copy of one toolbox array as a device tensor (Hcount as int32
-        holding the uint32 counts)."""
+        holding the uint32 counts; the BF16 shadows as int16 holding their
+        bits, `.view(torch.bfloat16)` reads them)."""
         shape, dt = self._shape(what)
         out = torch.empty(shape, dtype=dt, device="cuda")
         check(lib().wos_toolbox_export(self._h, EXPORTS[what], _dptr(out),
@@ -263,6 +284,23 @@ class Toolbox:
                                       _dptr(q) if q is not None else null, ctypes.byref(info),
                                       _stream_handle(stream)))
         return {k: getattr(info, k) for k, _ in info._fields_}
+
+    def make_bf16(self, stream=None):
+        """Make (or remake) the BF16 shadows of the built toolbox (include/wos.h,
+        wos_toolbox_make_bf16)."""
+        check(lib().wos_toolbox_make_bf16(self._h, _stream_handle(stream)))
+        return self
+
+    def apply_bf16(self, fbar, g, stream=None):
+        """wos_apply from the BF16 shadows: (u, grad_u) device float64 tensors."""
+        fbar = torch.as_tensor(fbar, dtype=torch.float64, device="cuda").contiguous()
+        g = torch.as_tensor(g, dtype=torch.float64, device="cuda").contiguous()
+        if fbar.numel() != self.m or g.numel() != self.p:
+            raise ValueError("fbar must have m entries and g p entries")
+        u = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        gu = torch.empty((self.dim, self.n), dtype=torch.float64, device="cuda")
+        check(lib().wos_apply_bf16(self._h, _dptr(fbar), _dptr(g), _dptr(u), _dptr(gu), _stream_handle(stream)))
+        return u, gu
 
     def take(self, other, estimators, stream=None):
         """Copy the estimators named in `estimators` (any of "A", "B", "H",

@@ -17,7 +17,7 @@ STATUS = {0: "WOS_OK", -1: "WOS_EINVAL", -2: "WOS_EDOMAIN", -3: "WOS_ENOMEM", -4
 KINDS = {"ball": 1, "box": 2, "polygon": 3, "box_minus_ball": 4}
 PRECISION = {"f32": 0, "f64": 1}
 EXPORTS = {"A": 0, "B": 1, "H": 2, "K": 3, "Hcount": 4, "lambda": 5, "vcount": 6, "lambda_v": 7, "site_steps": 8,
-           "moments": 9}
+           "moments": 9, "shadow_v": 10, "shadow_g": 11}
 
 
 class WosDomain(ctypes.Structure):
@@ -120,7 +120,7 @@ HISD_PRECOND = {"identity": 0, "A": 1}
 HISD_INIT = {"given": 0, "hessian": 1}
 PROBLEMS = {"linear": 0, "semilinear_cubic": 1, "quasilinear": 2}
 SOLVERS = {"tsvd": 0, "tikhonov": 1}
-SOLVE_PRECISION = {"f64": 0, "mixed": 1}
+SOLVE_PRECISION = {"f64": 0, "mixed": 1, "bf16": 2}
 
 # every symbol include/wos.h declares, with its ctypes signature
 _P = ctypes.c_void_p
@@ -138,6 +138,10 @@ SIGNATURES = {
     "wos_toolbox_get_info": (ctypes.c_int, [_P, ctypes.POINTER(WosToolboxInfo)]),
     "wos_toolbox_export": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_size_t, ctypes.c_int32, _P]),
     "wos_apply": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "wos_toolbox_make_bf16": (ctypes.c_int, [_P, _P]),
+    "wos_apply_bf16": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "wos_gemm_bf16_nt": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, _P,
+                                        ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_float, _P, ctypes.c_int64, _P]),
     "wos_solve": (ctypes.c_int, [_P, ctypes.POINTER(WosCoeffs), _P, _P, _P, _P, _P,
                                  ctypes.POINTER(WosSolveInfo), _P]),
     "wos_solve_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(WosCoeffs), _P, _P, _P, _P, _P,

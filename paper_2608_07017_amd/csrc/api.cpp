@@ -18,6 +18,7 @@
 #include "window.hpp"
 #include "toolbox.hpp"
 #include "wos_kernels.hpp"
+#include "wos_solve_kernels.hpp"
 
 using namespace wos;
 
@@ -281,7 +282,7 @@ void release(wos_toolbox* tb) {
                   tb->d_K, tb->d_H, tb->d_Hc, tb->d_vcount, tb->d_stats, tb->d_lambda,
                   tb->d_item_order, tb->gv_r.rec, tb->gv_r.list, tb->gg_r.rec, tb->gg_r.list,
                   tb->d_vsites_r, tb->d_bnodes_r, tb->d_vrank, tb->d_brank, tb->d_win, tb->d_site_steps,
-                  tb->d_mom_phi, tb->d_mom_psi, tb->d_mom};
+                  tb->d_mom_phi, tb->d_mom_psi, tb->d_mom, tb->d_SV, tb->d_SG, tb->d_bfy, tb->d_bfpart};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (tb->wv) {  // the V-side arrays are separate allocations only with a V partition of their own
@@ -991,6 +992,7 @@ wos_status wos_toolbox_build(wos_toolbox* tb, uint64_t seed, void* stream_) {
   if (tb->timing) WOS_HIP(hipEventRecord(tb->ev[3], stream));
   tb->last_stream = stream;
   tb->built = true;
+  tb->gen++;
   return WOS_OK;
 }
 
@@ -1083,6 +1085,13 @@ wos_status wos_toolbox_export(const wos_toolbox* tb, int32_t what, void* dst, si
       src = tb->d_mom;
       want = 8 * n * (4 + 4 * d);
       break;
+    case WOS_EXPORT_SHADOW_V:
+    case WOS_EXPORT_SHADOW_G:
+      if (!tb->d_SV || tb->bf16_gen != tb->gen)
+        return fail(WOS_EINVAL, "no BF16 shadows of the last build (wos_toolbox_make_bf16)");
+      src = what == WOS_EXPORT_SHADOW_V ? (const void*)tb->d_SV : (const void*)tb->d_SG;
+      want = 2 * (what == WOS_EXPORT_SHADOW_V ? m : p) * (d + 1) * n;
+      break;
     default: return fail(WOS_EINVAL, "unknown export %d", what);
   }
   if (bytes != want) return fail(WOS_EINVAL, "export %d needs %zu bytes, got %zu", what, want, bytes);
@@ -1138,6 +1147,65 @@ wos_status wos_toolbox_take(wos_toolbox* dst, const wos_toolbox* src, uint32_t m
   }
   if (mask & WOS_TAKE_K)
     WOS_HIP(hipMemcpyAsync(dst->d_K, src->d_K, ts * d * n * p, hipMemcpyDeviceToDevice, stream));
+  dst->gen++;
+  return WOS_OK;
+}
+
+extern "C++" {
+namespace wos {
+
+wos_status toolbox_bf16_current(wos_toolbox* tb, hipStream_t stream) {
+  if (!tb->built) return fail(WOS_EINVAL, "toolbox has not been built");
+  if (tb->d_SV && tb->bf16_gen == tb->gen) return WOS_OK;
+  const size_t n = tb->n, m = tb->m, p = tb->p, d = tb->dim, KB = (d + 1) * n;
+  wos_status s;
+  if (!tb->d_SV) {
+    if ((s = dev_alloc(tb, (void**)&tb->d_SV, 2 * m * KB)) != WOS_OK) return s;
+    if ((s = dev_alloc(tb, (void**)&tb->d_SG, 2 * p * KB)) != WOS_OK) return s;
+    if ((s = dev_alloc(tb, (void**)&tb->d_bfy, 8 * KB)) != WOS_OK) return s;
+    if ((s = dev_alloc(tb, (void**)&tb->d_bfpart, 8 * gemv_t_bf16_part_elems((int)KB))) != WOS_OK) return s;
+  }
+  WOS_HIP(launch_shadow_t(tb->f64, tb->d_B, (int)(d * n), (int)m, tb->d_SV, KB, 0, stream));
+  WOS_HIP(launch_shadow_t(tb->f64, tb->d_A, (int)n, (int)m, tb->d_SV, KB, (int)(d * n), stream));
+  WOS_HIP(launch_shadow_t(tb->f64, tb->d_K, (int)(d * n), (int)p, tb->d_SG, KB, 0, stream));
+  WOS_HIP(launch_shadow_t(tb->f64, tb->d_H, (int)n, (int)p, tb->d_SG, KB, (int)(d * n), stream));
+  tb->bf16_gen = tb->gen;
+  return WOS_OK;
+}
+
+}  // namespace wos
+}
+
+wos_status wos_gemm_bf16_nt(int32_t M, int32_t N, int32_t K, float alpha, const uint16_t* X, int64_t ldx,
+                            const uint16_t* Y, int64_t ldy, float beta, float* C, int64_t ldc, void* stream) {
+  g_err.clear();
+  if (M < 0 || N < 0 || K < 0) return fail(WOS_EINVAL, "negative size");
+  if (M == 0 || N == 0) return WOS_OK;
+  if (!C || (K > 0 && (!X || !Y))) return fail(WOS_EINVAL, "NULL argument");
+  if (ldx < K || ldy < K || ldc < N) return fail(WOS_EINVAL, "leading dimension below the row length");
+  WOS_HIP(gemm_nt_bf16(M, N, K, alpha, X, (size_t)ldx, Y, (size_t)ldy, beta, C, (size_t)ldc,
+                       static_cast<hipStream_t>(stream)));
+  return WOS_OK;
+}
+
+wos_status wos_toolbox_make_bf16(wos_toolbox* tb, void* stream) {
+  g_err.clear();
+  if (!tb) return fail(WOS_EINVAL, "toolbox is NULL");
+  return toolbox_bf16_current(tb, static_cast<hipStream_t>(stream));
+}
+
+wos_status wos_apply_bf16(wos_toolbox* tb, const double* fbar, const double* g, double* u, double* grad_u,
+                          void* stream_) {
+  g_err.clear();
+  if (!tb || !fbar || !g || !u) return fail(WOS_EINVAL, "NULL argument");
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  wos_status s = toolbox_bf16_current(tb, stream);
+  if (s != WOS_OK) return s;
+  const int n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
+  const size_t KB = (size_t)(d + 1) * n;
+  WOS_HIP(launch_gemv_t_bf16(tb->d_SV, m, (int)KB, KB, fbar, 1.0, 0.0, tb->d_bfy, tb->d_bfpart, stream));
+  WOS_HIP(launch_gemv_t_bf16(tb->d_SG, p, (int)KB, KB, g, 1.0, 1.0, tb->d_bfy, tb->d_bfpart, stream));
+  WOS_HIP(launch_split_apply(n, d, tb->d_bfy, u, grad_u, stream));
   return WOS_OK;
 }
 

@@ -357,6 +357,7 @@ wos_status wos_toolbox_load(const char* path, void* stream, wos_toolbox** out) {
     if (e != hipSuccess) return pfail(WOS_EDEVICE, "device copy failed: %s", hipGetErrorString(e));
   }
   tb->built = true;
+  tb->gen++;
   tb->last_stream = static_cast<hipStream_t>(stream);
   *out = guard.release();
   return WOS_OK;

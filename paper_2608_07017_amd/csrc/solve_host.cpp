@@ -255,9 +255,13 @@ wos_status dev_dot(SolveWork& w, const double* dx, const double* dy, const doubl
 // (Lambda = L^T W L applied as GEMVs over the toolbox rows with FP64
 // accumulation), until |r| <= refine_tol |Lambda^T rhs|.  If the FP32
 // factorisation meets a non-positive pivot the request is solved in FP64.
-wos_status ensure_tik(wos_toolbox* tb, SolveWork& w, bool mixed) {
+wos_status ensure_tik(wos_toolbox* tb, SolveWork& w, bool mixed, bool bf = false) {
   const size_t n = tb->n, m = tb->m, d = tb->dim;
   wos_status s;
+  if (bf && !w.RT) {
+    if ((s = walloc(w, &w.RT, (d + 1) * n * m)) != WOS_OK) return s;
+    if ((s = walloc(w, &w.cg, 3 * m)) != WOS_OK) return s;
+  }
   if (mixed && !w.colp) {
     if ((s = walloc(w, &w.colp, (size_t)kColsqChunks * m)) != WOS_OK) return s;
     if ((s = walloc(w, &w.cn, 2 * m)) != WOS_OK) return s;
@@ -268,8 +272,10 @@ wos_status ensure_tik(wos_toolbox* tb, SolveWork& w, bool mixed) {
     if ((s = walloc(w, &w.regv, 2)) != WOS_OK) return s;
     if ((s = walloc(w, &w.info, 2)) != WOS_OK) return s;
   }
-  if (mixed && !w.R32) {
+  if (mixed && !bf && !w.R32) {
     if ((s = walloc(w, &w.R32, (d + 1) * n * m)) != WOS_OK) return s;
+  }
+  if (mixed && !w.Lam32) {
     if ((s = walloc(w, &w.Lam32, m * m)) != WOS_OK) return s;
     if ((s = walloc(w, &w.N32, m * m)) != WOS_OK) return s;
     if ((s = walloc(w, &w.v32, m)) != WOS_OK) return s;
@@ -345,9 +351,11 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
                            const double* g, double* q, wos_solve_info* inf, hipStream_t st) {
   const int n = tb->n, m = tb->m, p = tb->p, d = tb->dim;
   const int K = d * n;
-  bool mixed = co->precision == WOS_SOLVE_MIXED && !tb->f64;
+  const bool bf = co->precision == WOS_SOLVE_MIXED_BF16;
+  bool mixed = (co->precision == WOS_SOLVE_MIXED && !tb->f64) || bf;
   wos_status s;
-  if ((s = ensure_tik(tb, w, mixed)) != WOS_OK) return s;
+  if ((s = ensure_tik(tb, w, mixed, bf)) != WOS_OK) return s;
+  if (bf && (s = toolbox_bf16_current(tb, st)) != WOS_OK) return s;
   double* rhs = w.vec + 5 * w.vlen;
   double* c = w.vec + 6 * w.vlen;
   double* r = w.vec + 7 * w.vlen;
@@ -365,11 +373,19 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
 
   if (mixed) {
     // Lambda (FP32) = L^T R, R = W L; N = Lambda^T Lambda + reg I; Cholesky
-    SHIP(launch_weight_rows_any(false, true, tb->d_A, tb->d_B, tb->d_H, tb->d_K, tb->d_lambda, co->A, co->b, co->c,
-                                n, m, p, d, m, w.R32, st));
-    SHIP(mfma_gemm_f32(true, false, m, m, K, 1.0f, (const float*)tb->d_B, m, w.R32, m, 0.0f, w.Lam32, m, st));
-    SHIP(mfma_gemm_f32(true, false, m, m, n, 1.0f, (const float*)tb->d_A, m, w.R32 + (size_t)K * m, m, 1.0f,
-                       w.Lam32, m, st));
+    if (bf) {
+      // from the BF16 shadows on the matrix cores (FP32 accumulation):
+      // Lambda[i][j] = sum_k S_V[i][k] RT[j][k]
+      const size_t KB = (size_t)(d + 1) * n;
+      SHIP(launch_weight_t_bf16(tb->d_SV, n, m, d, tb->d_lambda, co->A, co->b, co->c, w.RT, st));
+      SHIP(gemm_nt_bf16(m, m, (int)KB, 1.0f, tb->d_SV, KB, w.RT, KB, 0.0f, w.Lam32, m, st));
+    } else {
+      SHIP(launch_weight_rows_any(false, true, tb->d_A, tb->d_B, tb->d_H, tb->d_K, tb->d_lambda, co->A, co->b,
+                                  co->c, n, m, p, d, m, w.R32, st));
+      SHIP(mfma_gemm_f32(true, false, m, m, K, 1.0f, (const float*)tb->d_B, m, w.R32, m, 0.0f, w.Lam32, m, st));
+      SHIP(mfma_gemm_f32(true, false, m, m, n, 1.0f, (const float*)tb->d_A, m, w.R32 + (size_t)K * m, m, 1.0f,
+                         w.Lam32, m, st));
+    }
     SHIP(mfma_gemm_lower_f32(true, false, m, m, m, 1.0f, w.Lam32, m, w.Lam32, m, 0.0f, w.N32, m, st));
     if ((s = mixed_tikhonov_reg(tb, w, co, rcond, r, t, st)) != WOS_OK) return s;
     SHIP(launch_add_diag(false, w.N32, m, m, w.regv, st));
@@ -383,7 +399,55 @@ wos_status tikhonov_linear(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, 
       SHIP(hipMemsetAsync(w.info, 0, 2 * sizeof(int), st));
     }
   }
-  if (mixed) {
+  if (mixed && bf) {
+    // Preconditioned conjugate gradients on (Lambda^T Lambda + reg I) q = c,
+    // products in FP64 matrix-free, preconditioner X^T X from the FP32
+    // factor of the BF16-assembled normal matrix (symmetric positive
+    // definite, so the iteration converges where plain refinement with a
+    // preconditioner this rough would not)
+    const double tol = co->refine_tol > 0 ? co->refine_tol : 1e-10;
+    const int maxit = co->max_refine > 0 ? co->max_refine : 50;
+    double* z = w.cg;
+    double* pv = w.cg + m;
+    double* Ap = w.cg + 2 * (size_t)m;
+    double cn = 0.0, rn = 0.0, rz = 0.0, pAp = 0.0;
+    auto precond = [&](const double* x, double* y) -> wos_status {
+      SHIP(launch_gemv_n_ld(false, w.Lam32, m, m, m, x, 1.0, 0.0, t, st));
+      SHIP(launch_gemv_t_ld(false, w.Lam32, m, m, m, t, 1.0, 0.0, y, w.part, st));
+      return WOS_OK;
+    };
+    if ((s = dev_dot(w, c, c, nullptr, m, &cn, st)) != WOS_OK) return s;
+    cn = std::sqrt(cn);
+    SHIP(hipMemsetAsync(q, 0, sizeof(double) * m, st));
+    SHIP(hipMemcpyAsync(r, c, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    if ((s = precond(r, z)) != WOS_OK) return s;
+    SHIP(hipMemcpyAsync(pv, z, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    if ((s = dev_dot(w, r, z, nullptr, m, &rz, st)) != WOS_OK) return s;
+    rn = cn;
+    int it = 0;
+    for (it = 1; it <= maxit && rn > tol * cn; ++it) {
+      double* y = w.vec + 9 * w.vlen;
+      if ((s = apply_Lambda(tb, w, co, pv, false, y, st)) != WOS_OK) return s;
+      if ((s = apply_Lambda(tb, w, co, y, true, Ap, st)) != WOS_OK) return s;
+      SHIP(launch_axpy_reg(m, Ap, w.regv, 1.0, pv, Ap, st));
+      if ((s = dev_dot(w, pv, Ap, nullptr, m, &pAp, st)) != WOS_OK) return s;
+      if (!(pAp > 0.0)) break;
+      const double alpha = rz / pAp;
+      SHIP(launch_axpby(m, 1.0, q, alpha, pv, q, st));
+      SHIP(launch_axpby(m, 1.0, r, -alpha, Ap, r, st));
+      if ((s = dev_dot(w, r, r, nullptr, m, &rn, st)) != WOS_OK) return s;
+      rn = std::sqrt(rn);
+      if (rn <= tol * cn) break;
+      if ((s = precond(r, z)) != WOS_OK) return s;
+      double rz1 = 0.0;
+      if ((s = dev_dot(w, r, z, nullptr, m, &rz1, st)) != WOS_OK) return s;
+      SHIP(launch_axpby(m, 1.0, z, rz1 / rz, pv, pv, st));
+      rz = rz1;
+    }
+    inf->refine_iters = std::min(it, maxit);
+    inf->refine_residual = cn > 0 ? rn / cn : 0.0;
+    if (!(rn <= tol * cn)) inf->refine_converged = 0;
+  } else if (mixed) {
     const double tol = co->refine_tol > 0 ? co->refine_tol : 1e-10;
     const int maxit = co->max_refine > 0 ? co->max_refine : 10;
     double cn = 0.0, rn = 0.0;
@@ -605,7 +669,7 @@ namespace wos {
 void free_work(SolveWork& w) {
   void* ptrs[] = {w.R, w.Lam, w.Sig, w.Lam0, w.Sig0, w.Hess, w.G, w.V, w.E, w.rot, w.pq, w.vec, w.Ac, w.red,
                   w.blk, w.regv, w.colp, w.cn, w.info, w.R32, w.Lam32, w.N32, w.v32, w.P64, w.P32, w.L0_32, w.el, w.hs,
-                  w.hs_bad, w.hsb, w.part};
+                  w.hs_bad, w.hsb, w.part, w.RT, w.cg};
   if (!w.fixed)
     for (void* q : ptrs)
       if (q) (void)hipFree(q);
@@ -624,8 +688,11 @@ wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, co
   if (!(rcond < 1.0)) return sfail(WOS_EINVAL, "rcond must be in (0, 1)");
   if (co->solver != WOS_SOLVER_TSVD && co->solver != WOS_SOLVER_TIKHONOV)
     return sfail(WOS_EINVAL, "unknown solver %d", co->solver);
-  if (co->precision != WOS_SOLVE_F64 && co->precision != WOS_SOLVE_MIXED)
+  if (co->precision != WOS_SOLVE_F64 && co->precision != WOS_SOLVE_MIXED && co->precision != WOS_SOLVE_MIXED_BF16)
     return sfail(WOS_EINVAL, "unknown solve precision %d", co->precision);
+  if (co->precision == WOS_SOLVE_MIXED_BF16 &&
+      !(co->solver == WOS_SOLVER_TIKHONOV && (co->kind == WOS_LINEAR || co->kind == WOS_QUASILINEAR)))
+    return sfail(WOS_EINVAL, "the BF16 route solves LINEAR and QUASILINEAR problems with the Tikhonov solver");
   const int max_sweeps = co->max_sweeps > 0 ? co->max_sweeps : 40;
   wos_status s = ensure_work(tb, w);
   if (s != WOS_OK) return s;

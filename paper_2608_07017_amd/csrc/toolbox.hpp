@@ -64,6 +64,8 @@ struct SolveWork {
   double* P64 = nullptr;    // Cholesky work (chol_work_elems(m))
   float* P32 = nullptr;
   float* L0_32 = nullptr;   // Lambda_0 (A = I), FP32, for the mixed Newton route
+  uint16_t* RT = nullptr;   // BF16 route: the weighted rows W L, transposed, m x (d+1) n
+  double* cg = nullptr;     // BF16 route: 3 m conjugate-gradient vectors
   double* el = nullptr;     // Euler-Lagrange route: (3d + 4) n + 4 m + 2 work doubles
   double* hs = nullptr;     // p-HiSD: 78 m + 8 work doubles (+ 3 m^2 with M = A)
   size_t hs_cap = 0;        // doubles held at hs
@@ -76,6 +78,9 @@ struct SolveWork {
 };
 
 // One solve on workspace `w` (C ABI wos_solve uses the toolbox's own).
+// Makes (or remakes, after a build) the toolbox's BF16 shadows on `st`.
+wos_status toolbox_bf16_current(wos_toolbox* tb, hipStream_t st);
+
 wos_status solve_request(wos_toolbox* tb, SolveWork& w, const wos_coeffs* co, const double* f, const double* g,
                          double* u, double* grad_u, double* q_out, wos_solve_info* info, hipStream_t st);
 // Adam on the discrete functional J (C ABI wos_minimize).
@@ -143,6 +148,14 @@ struct wos_toolbox {
   size_t bytes = 0;
   hipStream_t last_stream = nullptr;
   bool built = false;
+  uint64_t gen = 0;       // builds (and loads, takes) so far: what the BF16 shadows are checked against
+  // BF16 shadows (bf16.hip): S_V m x (d+1) n of [B; A] and S_G p x (d+1) n of
+  // [K; H], transposed (the sites' index contiguous), and their apply work
+  uint16_t* d_SV = nullptr;
+  uint16_t* d_SG = nullptr;
+  double* d_bfy = nullptr;     // (d+1) n
+  double* d_bfpart = nullptr;  // gemv_t_bf16_part_elems((d+1) n)
+  uint64_t bf16_gen = 0;       // gen the shadows were made from (0: none)
   bool timing = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };

@@ -3,6 +3,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
 
 namespace wos {
 
@@ -157,5 +159,21 @@ hipError_t launch_identity_minus(int m, double* D, hipStream_t st);
 // Y[t] = c for t < nv (m-vectors, stride m)
 hipError_t launch_hisd_broadcast(int m, int nv, const double* c, double* Y, hipStream_t st);
 hipError_t launch_add_f32(int n, const float* dlt, double* q, hipStream_t st);
+
+// ---- BF16 shadows and products (bf16.hip)
+// S[c][off + r] = bf16(X[r][c]), X rows x cols row-major, S leading dimension lds
+hipError_t launch_shadow_t(bool f64, const void* X, int rows, int cols, uint16_t* S, size_t lds, int off,
+                           hipStream_t st);
+// RT = (W L)^T in BF16 from the shadow S = L^T (m x (d+1) n)
+hipError_t launch_weight_t_bf16(const uint16_t* S, int n, int m, int d, const double* lam, const double* Ac,
+                                const double* bc, const double* cc, uint16_t* RT, hipStream_t st);
+// C (M x N, FP32) = alpha X Y^T + beta C, X (M x K), Y (N x K) BF16, k-contiguous
+hipError_t gemm_nt_bf16(int M, int N, int K, float alpha, const uint16_t* X, size_t ldx, const uint16_t* Y,
+                        size_t ldy, float beta, float* C, size_t ldc, hipStream_t st);
+size_t gemv_t_bf16_part_elems(int K);
+// y (K) = alpha S^T v + beta y, S (rows x K) BF16, deterministic order
+hipError_t launch_gemv_t_bf16(const uint16_t* S, int rows, int K, size_t ld, const double* v, double alpha,
+                              double beta, double* y, double* part, hipStream_t st);
+hipError_t launch_split_apply(int n, int d, const double* y, double* u, double* grad_u, hipStream_t st);
 
 }  // namespace wos
