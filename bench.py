@@ -49,6 +49,7 @@ MI355X_CLOCK = 2.4e9
 # (non-packed) FP32 and INT32 VALU ops issue at 128 lanes/clk/CU, FP64 FMA,
 # v_mul_hi at 64, transcendentals and 32x32->64 multiplies at 32.
 LANE_OPS_PEAK = MI355X_CUS * 128 * MI355X_CLOCK
+BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix-core peak
 # Algorithmic lane-op budget of the walker (slots: full-rate op = 1,
 # transcendental / 32-bit integer multiply = 4), per walk-step and per walk
 # (the per-step and per-walk counts of the method: distance, tally point,
@@ -99,6 +100,7 @@ def parse():
     ap.add_argument("--probe", action="store_true", help="also report the VALU issue-rate probe")
     ap.add_argument("--minimal-surface", action="store_true", help="also run the minimal surface energies")
     ap.add_argument("--no-serving", action="store_true", help="skip the served-solve stream")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 shadows, applies and products")
     ap.add_argument("--no-newton", action="store_true", help="skip the 3-D Newton run")
     ap.add_argument("--newton-iters", type=int, default=10)
     ap.add_argument("--no-el", action="store_true", help="skip the Euler-Lagrange (Adam) runs")
@@ -312,6 +314,14 @@ def serving(a, torch, W, P):
         rate = rho * sat["solves_per_s"]
         out["mixed"]["open_loop"].append(dict(run("mixed", a.serve_requests, rate, check=True), rho=rho,
                                               arrival_rate=rate))
+    print("serving: BF16 saturation and open loop", file=sys.stderr, flush=True)
+    for tb, _, _ in boxes:
+        tb.make_bf16()
+    torch.cuda.synchronize()
+    satb = run("bf16", a.serve_saturation, 0.0, check=True)
+    out["bf16"] = {"saturation": satb,
+                   "open_loop": [dict(run("bf16", a.serve_requests, 0.8 * satb["solves_per_s"], check=True), rho=0.8,
+                                      arrival_rate=0.8 * satb["solves_per_s"])]}
     print("serving: FP64 saturation and open loop", file=sys.stderr, flush=True)
     sat64 = run("f64", max(200, a.serve_saturation // 4), 0.0)
     rho = 0.8
@@ -319,6 +329,9 @@ def serving(a, torch, W, P):
                   "open_loop": [dict(run("f64", a.serve_f64_requests, rho * sat64["solves_per_s"]), rho=rho,
                                      arrival_rate=rho * sat64["solves_per_s"])]}
     out["mixed_vs_f64_saturation"] = sat["solves_per_s"] / sat64["solves_per_s"]
+    out["bf16_vs_f64_saturation"] = satb["solves_per_s"] / sat64["solves_per_s"]
+    out["bf16_at_fp64_l2_error"] = min([satb["at_fp64_l2_error"]] +
+                                       [r["at_fp64_l2_error"] for r in out["bf16"]["open_loop"]])
     out["mixed_at_fp64_l2_error"] = min([sat["at_fp64_l2_error"]] +
                                         [r["at_fp64_l2_error"] for r in out["mixed"]["open_loop"]])
 
@@ -372,6 +385,64 @@ def serving(a, torch, W, P):
     return out
 
 
+def bf16_products(torch, P):
+    """The BF16 matrix-core product of the BF16 route (C = X Y^T, FP32
+    accumulation) at the assembly shapes of the 4096-site 3-D ball (4096 x
+    4096 from K = 4 x 4096) and of a 8192-site problem, in TFLOP/s against
+    the dense BF16 peak, timed with HIP events on the launch stream."""
+    out = []
+    for M, K in ((4096, 4 * 4096), (8192, 4 * 8192)):
+        X = torch.randn(M, K, device="cuda").bfloat16()
+        Y = torch.randn(M, K, device="cuda").bfloat16()
+        C = torch.empty(M, M, device="cuda")
+        P.gemm_bf16_nt(X, Y, C)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            P.gemm_bf16_nt(X, Y, C)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = 2.0 * M * M * K / (ms * 1e-3) / 1e12
+        out.append({"M": M, "N": M, "K": K, "ms": ms, "tflops": tf, "frac_of_bf16_peak": tf / BF16_PEAK_TFLOPS})
+        del X, Y, C
+    torch.cuda.empty_cache()
+    return out
+
+
+def bf16_applies(torch, tb, g):
+    """BF16 shadows of the headline toolbox: their size and making time, and
+    the direct application u = A fbar + H g, grad u = B fbar + K g from the
+    FP32 toolbox and from the shadows (HBM-bound: the shadows are half the
+    bytes), with the relative difference of the two."""
+    fbar = torch.randn(tb.m, dtype=torch.float64, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    tb.make_bf16()
+    e1.record()
+    torch.cuda.synchronize()
+    make_ms = e0.elapsed_time(e1)
+    res = {}
+    for name, fn in (("f32", lambda: tb.apply(fbar, g)), ("bf16", lambda: tb.apply_bf16(fbar, g))):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            u, gu = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = (e0.elapsed_time(e1) / 5, u, gu)
+    d, n, m, p = tb.dim, tb.n, tb.m, tb.p
+    rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    return {"shadow_gib": 2.0 * (d + 1) * n * (m + p) / 2 ** 30, "make_bf16_ms": make_ms,
+            "apply_f32_ms": res["f32"][0], "apply_bf16_ms": res["bf16"][0],
+            "apply_bytes_f32": 4.0 * (d + 1) * n * (m + p), "apply_bytes_bf16": 2.0 * (d + 1) * n * (m + p),
+            "bf16_vs_f32_rel_diff_u": rel(res["bf16"][1], res["f32"][1]),
+            "bf16_vs_f32_rel_diff_grad_u": rel(res["bf16"][2], res["f32"][2])}
+
+
 def picard_cubeball(a, torch, W, P):
     """The 3-D unit cube minus the ball of radius 0.3 (32768 sites, 8192
     boundary nodes, 1e5 walks/site, eps 1e-5, FP32 tallies written straight to
@@ -394,16 +465,24 @@ def picard_cubeball(a, torch, W, P):
     out = {"workload": cfg["label"] + "; -div((1 + u^2) grad u) = f, Picard (3 steps), Tikhonov rcond 1e-2",
            "walker_ms": t["walker_ms"], "walk_steps": inf["walk_steps"],
            "walk_steps_per_s": inf["walk_steps"] / (t["walker_ms"] * 1e-3), "device_gib": inf["device_bytes"] / 2**30}
-    for prec in ("mixed", "f64"):
+    tb.make_bf16()
+    for prec in ("bf16", "mixed", "f64"):
         print("cubeball: picard", prec, file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         u, _, _, info = tb.solve(f, g, kind="quasilinear", rcond=1e-2, tol=1e-300, max_iter=3, solver="tikhonov",
                                  precision=prec, refine_tol=1e-8)
         torch.cuda.synchronize()
-        out[prec] = {"seconds": time.perf_counter() - t0,
+        out[prec] = {"seconds": time.perf_counter() - t0, "refine_converged": info["refine_converged"],
                      "rel_l2_error": float(np.sqrt(np.sum(lam * (u.cpu().numpy() - u0) ** 2))) / nrm}
+        us = out.setdefault("_u", {})
+        us[prec] = u.cpu().numpy()
+    us = out.pop("_u")
+    for prec in ("bf16", "mixed"):
+        out[prec + "_vs_f64_rel_diff_u"] = float(np.sqrt(np.sum(lam * (us[prec] - us["f64"]) ** 2)
+                                                         / np.sum(lam * us["f64"] ** 2)))
     out["mixed_vs_f64"] = out["f64"]["seconds"] / out["mixed"]["seconds"]
+    out["bf16_vs_f64"] = out["f64"]["seconds"] / out["bf16"]["seconds"]
     tb.free()
     return out
 
@@ -443,7 +522,7 @@ def newton_ball(a, torch, W, P):
                      "refine_converged": info["refine_converged"],
                      "rel_l2_error": float(np.sqrt(np.sum(lam * (us[prec] - ue(x)) ** 2))) / nrm}
     # the mixed route's result against the FP64 route's (same regularised
-    # system; the survey's bar for this configuration is 1e-8)
+    # system, refined to 1e-8 or better)
     out["mixed_vs_f64_rel_diff_u"] = float(np.sqrt(np.sum(lam * (us["mixed"] - us["f64"]) ** 2)
                                                / np.sum(lam * us["f64"] ** 2)))
     out["mixed_vs_f64"] = out["f64"]["seconds"] / out["mixed"]["seconds"]
@@ -714,6 +793,7 @@ def main():
     torch.cuda.synchronize()
     exact = cfg["sites"][:, 0] ** 2 - cfg["sites"][:, 1] ** 2
     herr = float(np.sqrt(np.mean((u.cpu().numpy() - exact) ** 2)))
+    bf16 = None if a.no_bf16 else bf16_applies(torch, tb, g)
     tb.free()
     del tb
     torch.cuda.empty_cache()
@@ -740,6 +820,9 @@ def main():
                      "frac": achieved / peak, "traffic": measured_traffic(a.workload, mean_steps),
                      "budget": {"per_walk_step": c_step, "per_walk": c_walk}},
     }
+    if bf16 is not None:
+        bf16["products"] = bf16_products(torch, P)
+        out["bf16"] = bf16
     if a.probe:
         out["valu_probe_lane_ops_per_s"] = {op: P.probe_valu(op) for op in P.PROBE_OPS}
     if a.calibrate_copy > 0:

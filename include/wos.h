@@ -511,6 +511,12 @@ typedef struct {
   const double* coef_A; /* n x d x d, row-major (NULL: the identity)          */
   const double* coef_c; /* n (NULL: 0)                                        */
   const double* coef_w; /* n (NULL: 1)                                        */
+  int32_t graph;        /* 1: the iterations between norm checks (check_every of
+                           them with tol > 0, else 64) are captured once in a
+                           HIP graph and replayed (one launch per block of
+                           iterations instead of one per kernel); the step size
+                           of each iteration is read from device memory.  The
+                           results are the same bits as with 0.               */
 } wos_adam_opts;
 
 typedef struct {
@@ -688,7 +694,9 @@ wos_status wos_server_create(const wos_server_opts* opts, wos_server** out);
 
 /* Queues one solve (arguments as for wos_solve; device buffers must stay
  * valid until the request is polled as finished).  The coefficients struct
- * is copied.  Returns at once with a ticket.                                  */
+ * is copied.  Returns at once with a ticket.  A WOS_SOLVE_MIXED_BF16 request
+ * needs the toolbox's BF16 shadows of its last build made beforehand
+ * (wos_toolbox_make_bf16 and a synchronised stream), else WOS_EINVAL.        */
 wos_status wos_server_submit(wos_server* sv, wos_toolbox* tb, const wos_coeffs* coeffs, const double* f,
                              const double* g, double* u, double* grad_u, uint64_t* ticket);
 

@@ -333,14 +333,15 @@ class Toolbox:
         return out, site
 
     def minimize(self, f, g, p_exp, alpha, max_iter, fbar0=1.0, tol=0.0, check_every=0, beta1=-1.0, beta2=-1.0,
-                 eps=0.0, energy="plaplace", coef_A=None, coef_c=None, coef_w=None, stream=None):
+                 eps=0.0, energy="plaplace", coef_A=None, coef_c=None, coef_w=None, graph=False, stream=None):
         """Adam on the discrete functional J of the Euler-Lagrange route
         (include/wos.h, wos_minimize), from the source fbar0 (a scalar for a
         constant start, or an (m,) array); energy is "plaplace" (exponent
         p_exp), "minimal_surface", "semilinear" or "elliptic" (with the
         per-site coefficient fields coef_A (n, d, d), coef_c (n,), coef_w
-        (n,), each optional; p_exp unused).  Returns (u, grad_u, fbar, info)
-        with device float64 tensors."""
+        (n,), each optional; p_exp unused).  graph=True replays the
+        iterations between checks as one captured HIP graph.  Returns (u,
+        grad_u, fbar, info) with device float64 tensors."""
         dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
         f, g = dev(f), dev(g)
         if f.numel() != self.n or g.numel() != self.p:
@@ -360,7 +361,7 @@ class Toolbox:
                     raise ValueError("%s must have shape %s" % (key, shape))
         opts = WosAdamOpts(energy=ENERGIES[energy], p_exp=float(p_exp), alpha=float(alpha), beta1=float(beta1),
                            beta2=float(beta2), eps=float(eps), max_iter=int(max_iter), tol=float(tol),
-                           check_every=int(check_every),
+                           check_every=int(check_every), graph=1 if graph else 0,
                            **{k: ctypes.c_void_p(v.data_ptr()) for k, v in co.items()})
         u = torch.empty(self.n, dtype=torch.float64, device="cuda")
         gu = torch.empty((self.dim, self.n), dtype=torch.float64, device="cuda")

@@ -94,7 +94,8 @@ class WosAdamOpts(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_int32), ("p_exp", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("check_every", ctypes.c_int32),
-                ("coef_A", ctypes.c_void_p), ("coef_c", ctypes.c_void_p), ("coef_w", ctypes.c_void_p)]
+                ("coef_A", ctypes.c_void_p), ("coef_c", ctypes.c_void_p), ("coef_w", ctypes.c_void_p),
+                ("graph", ctypes.c_int32)]
 
 
 class WosAdamInfo(ctypes.Structure):

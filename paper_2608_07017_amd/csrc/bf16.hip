@@ -200,15 +200,37 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, 
 // sums over row blocks (FP64), added in block order.
 constexpr int kBfRowBlocks = 64;
 
+// A thread owns 8 consecutive columns (one 16-byte load per row when the
+// rows are 16-byte aligned).
 __global__ __launch_bounds__(256) void gemv_t_bf16_part_kernel(const uint16_t* __restrict__ S, int rows, int K,
                                                                size_t ld, const double* __restrict__ v,
-                                                               int rows_per_block, double* __restrict__ part) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
+                                                               int rows_per_block, int vec, double* __restrict__ part) {
+  const int k0 = 8 * (blockIdx.x * blockDim.x + threadIdx.x);
+  if (k0 >= K) return;
   const int r0 = blockIdx.y * rows_per_block, r1 = min(rows, r0 + rows_per_block);
-  double s = 0.0;
-  for (int r = r0; r < r1; ++r) s += (double)bf16_f32(S[(size_t)r * ld + k]) * v[r];
-  part[(size_t)blockIdx.y * K + k] = s;
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (vec && k0 + 8 <= K) {
+    for (int r = r0; r < r1; ++r) {
+      const uint4 q = *reinterpret_cast<const uint4*>(S + (size_t)r * ld + k0);
+      const double vr = v[r];
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        s[2 * e] += (double)__uint_as_float(w[e] << 16) * vr;
+        s[2 * e + 1] += (double)__uint_as_float(w[e] & 0xFFFF0000u) * vr;
+      }
+    }
+  } else {
+    for (int r = r0; r < r1; ++r) {
+      const double vr = v[r];
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (k0 + e < K) s[e] += (double)bf16_f32(S[(size_t)r * ld + k0 + e]) * vr;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    if (k0 + e < K) part[(size_t)blockIdx.y * K + k0 + e] = s[e];
 }
 
 __global__ void gemv_t_bf16_reduce_kernel(int K, int nb, const double* __restrict__ part, double alpha, double beta,
@@ -275,8 +297,9 @@ hipError_t launch_gemv_t_bf16(const uint16_t* S, int rows, int K, size_t ld, con
   if (K <= 0) return hipSuccess;
   const int nb = std::max(1, std::min(kBfRowBlocks, (rows + 63) / 64));
   const int rpb = (rows + nb - 1) / nb;
-  hipLaunchKernelGGL(gemv_t_bf16_part_kernel, dim3(nblk(K, 256), nb), dim3(256), 0, st, S, rows, K, ld, v, rpb,
-                     part);
+  const int vec = ((uintptr_t)S % 16) == 0 && ld % 8 == 0;
+  hipLaunchKernelGGL(gemv_t_bf16_part_kernel, dim3(nblk(K, 8 * 256), nb), dim3(256), 0, st, S, rows, K, ld, v, rpb,
+                     vec, part);
   hipLaunchKernelGGL(gemv_t_bf16_reduce_kernel, dim3(nblk(K, 256)), dim3(256), 0, st, K, nb, (const double*)part,
                      alpha, beta, y);
   return hipGetLastError();

@@ -82,6 +82,7 @@ size_t workspace_bytes(const wos_toolbox* tb) {
   b += 12 * chol_work_elems((int)m);
   b += 8 * ((size_t)kColsqChunks + 2) * m;  // exact column norms of the mixed route
   b += 8 * gemv_part_elems((int)std::max(m, p), 1);  // partial sums of the transposed products
+  b += 2 * (d + 1) * n * m + 24 * m;                 // BF16 route: weighted rows, CG vectors
   return b;
 }
 
@@ -257,6 +258,10 @@ wos_status wos_server_submit(wos_server* sv, wos_toolbox* tb, const wos_coeffs* 
                              const double* g, double* u, double* grad_u, uint64_t* ticket) {
   if (!sv || !tb || !co || !f || !g || !u || !ticket) return sv_fail(WOS_EINVAL, "NULL argument");
   if (!tb->built) return sv_fail(WOS_EINVAL, "toolbox has not been built");
+  // the shadows are shared by every slot: made beforehand, never by a worker
+  if (co->precision == WOS_SOLVE_MIXED_BF16 && (!tb->d_SV || tb->bf16_gen != tb->gen))
+    return sv_fail(WOS_EINVAL, "BF16 requests need the toolbox's BF16 shadows of its last build "
+                               "(wos_toolbox_make_bf16, its stream synchronised) before submission");
   std::unique_ptr<Request> r(new (std::nothrow) Request());
   if (!r) return sv_fail(WOS_ENOMEM, "out of host memory");
   r->tb = tb;

@@ -302,10 +302,11 @@ __global__ void energy_wb_kernel(int kind, int n, int d, double P, const double*
 // with the bias-corrected step a_j computed on the host.  With `reset`,
 // g is then set to it (the constant part of the next gradient, onto which
 // the next one is accumulated).
-__global__ void adam_kernel(int m, double* __restrict__ g, double b1, double b2, double eps, double aj,
-                            double* __restrict__ mv, double* __restrict__ vv, double* __restrict__ fbar,
-                            const double* __restrict__ reset) {
+__global__ void adam_kernel(int m, double* __restrict__ g, double b1, double b2, double eps, double aj_host,
+                            const double* __restrict__ aj_dev, double* __restrict__ mv, double* __restrict__ vv,
+                            double* __restrict__ fbar, const double* __restrict__ reset) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const double aj = aj_dev ? *aj_dev : aj_host;
   for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < (size_t)m; j += stride) {
     const double gj = g[j];
     const double mj = b1 * mv[j] + (1.0 - b1) * gj;
@@ -699,8 +700,15 @@ hipError_t launch_energy_wb_batch(int kind, int n, int d, double P, const double
 
 hipError_t launch_adam(int m, double* g, double b1, double b2, double eps, double aj, double* mv, double* vv,
                        double* fbar, const double* reset, hipStream_t st) {
-  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, g, b1, b2, eps, aj, mv, vv, fbar,
-                     reset);
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, g, b1, b2, eps, aj,
+                     (const double*)nullptr, mv, vv, fbar, reset);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_dev(int m, double* g, double b1, double b2, double eps, const double* aj, double* mv,
+                           double* vv, double* fbar, const double* reset, hipStream_t st) {
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, m, g, b1, b2, eps, 0.0, aj, mv, vv,
+                     fbar, reset);
   return hipGetLastError();
 }
 

@@ -669,10 +669,11 @@ namespace wos {
 void free_work(SolveWork& w) {
   void* ptrs[] = {w.R, w.Lam, w.Sig, w.Lam0, w.Sig0, w.Hess, w.G, w.V, w.E, w.rot, w.pq, w.vec, w.Ac, w.red,
                   w.blk, w.regv, w.colp, w.cn, w.info, w.R32, w.Lam32, w.N32, w.v32, w.P64, w.P32, w.L0_32, w.el, w.hs,
-                  w.hs_bad, w.hsb, w.part, w.RT, w.cg};
+                  w.hs_bad, w.hsb, w.part, w.RT, w.cg, w.aj};
   if (!w.fixed)
     for (void* q : ptrs)
       if (q) (void)hipFree(q);
+  if (w.cap) (void)hipStreamDestroy(w.cap);
   w = SolveWork();
 }
 
@@ -973,13 +974,83 @@ wos_status minimize_request(wos_toolbox* tb, SolveWork& w, const wos_adam_opts* 
   if ((s = weighted(grad, grad, &gg)) != WOS_OK) return s;
   inf.grad_norm0 = std::sqrt(gg);
   const auto t0 = std::chrono::steady_clock::now();
-  double b1j = 1.0, b2j = 1.0;
+  // the step sizes alpha sqrt(1 - beta2^j) / (1 - beta1^j)
+  std::vector<double> ajh(o->max_iter);
+  {
+    double b1j = 1.0, b2j = 1.0;
+    for (int j = 1; j <= o->max_iter; ++j) {
+      b1j *= b1;
+      b2j *= b2;
+      ajh[j - 1] = o->alpha * std::sqrt(1.0 - b2j) / (1.0 - b1j);
+    }
+  }
   int it = 0;
-  for (int j = 1; j <= o->max_iter; ++j) {
-    b1j *= b1;
-    b2j *= b2;
-    const double aj = o->alpha * std::sqrt(1.0 - b2j) / (1.0 - b1j);
-    SHIP(launch_adam(m, grad, b1, b2, eps, aj, mv, vv, fbar, cvec, st));  // grad <- c afterwards
+  bool done = false;
+  // blocks of C iterations replayed from one captured graph: the Adam
+  // kernel of the block's i-th iteration reads its step size from slot i,
+  // which is filled from the table of all step sizes before each replay
+  const int C = o->tol > 0.0 ? check : 64;
+  if (o->graph && o->max_iter >= C) {
+    const size_t need = (size_t)o->max_iter + C;
+    if (w.aj_cap < need) {
+      if (w.aj) {
+        SHIP(hipStreamSynchronize(st));
+        SHIP(hipFree(w.aj));
+        w.bytes -= w.aj_cap * sizeof(double);
+        w.aj = nullptr;
+        w.aj_cap = 0;
+      }
+      if ((s = walloc(w, &w.aj, need)) != WOS_OK) return s;
+      w.aj_cap = need;
+    }
+    double* slot = w.aj + o->max_iter;
+    SHIP(hipMemcpyAsync(w.aj, ajh.data(), sizeof(double) * o->max_iter, hipMemcpyHostToDevice, st));
+    SHIP(hipStreamSynchronize(st));
+    if (!w.cap) SHIP(hipStreamCreateWithFlags(&w.cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    SHIP(hipStreamBeginCapture(w.cap, hipStreamCaptureModeThreadLocal));
+    eg.st = w.cap;
+    wos_status cs = WOS_OK;
+    for (int i = 0; i < C && cs == WOS_OK; ++i) {
+      if (launch_adam_dev(m, grad, b1, b2, eps, slot + i, mv, vv, fbar, cvec, w.cap) != hipSuccess)
+        cs = sfail(WOS_EDEVICE, "Adam: launch failed during graph capture");
+      else
+        cs = eg.acc(fbar, grad);
+    }
+    eg.st = st;
+    const hipError_t ce = hipStreamEndCapture(w.cap, &graph);
+    if (cs != WOS_OK) {
+      if (ce == hipSuccess && graph) (void)hipGraphDestroy(graph);
+      return cs;
+    }
+    SHIP(ce);
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      SHIP(ie);
+    }
+    hipError_t le = hipSuccess;
+    for (int j0 = 0; j0 + C <= o->max_iter && le == hipSuccess; j0 += C) {
+      le = hipMemcpyAsync(slot, w.aj + j0, sizeof(double) * C, hipMemcpyDeviceToDevice, st);
+      if (le == hipSuccess) le = hipGraphLaunch(exec, st);
+      it = j0 + C;
+      if (le == hipSuccess && o->tol > 0.0 && it % check == 0) {
+        if ((s = weighted(grad, grad, &gg)) != WOS_OK) break;
+        if (std::sqrt(gg) <= o->tol) {
+          done = true;
+          break;
+        }
+      }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    SHIP(le);
+    if (s != WOS_OK) return s;
+  }
+  for (int j = it + 1; j <= o->max_iter && !done; ++j) {
+    SHIP(launch_adam(m, grad, b1, b2, eps, ajh[j - 1], mv, vv, fbar, cvec, st));  // grad <- c afterwards
     it = j;
     if ((s = gradient(fbar)) != WOS_OK) return s;  // at the new fbar: next step and the checks
     if (o->tol > 0.0 && j % check == 0) {

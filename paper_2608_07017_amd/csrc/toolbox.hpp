@@ -65,6 +65,9 @@ struct SolveWork {
   float* P32 = nullptr;
   float* L0_32 = nullptr;   // Lambda_0 (A = I), FP32, for the mixed Newton route
   uint16_t* RT = nullptr;   // BF16 route: the weighted rows W L, transposed, m x (d+1) n
+  double* aj = nullptr;     // captured Adam iterations: every step size, then a block's
+  size_t aj_cap = 0;        // doubles held at aj
+  hipStream_t cap = nullptr;  // the stream graphs are captured on (never run on)
   double* cg = nullptr;     // BF16 route: 3 m conjugate-gradient vectors
   double* el = nullptr;     // Euler-Lagrange route: (3d + 4) n + 4 m + 2 work doubles
   double* hs = nullptr;     // p-HiSD: 78 m + 8 work doubles (+ 3 m^2 with M = A)

@@ -75,6 +75,9 @@ constexpr int kMaxRowBlocks = 128;
 size_t gemv_part_elems(int cols, int nv);
 hipError_t launch_adam(int m, double* g, double b1, double b2, double eps, double aj, double* mv, double* vv,
                        double* fbar, const double* reset, hipStream_t st);
+// the same with the step size read from device memory (for captured graphs)
+hipError_t launch_adam_dev(int m, double* g, double b1, double b2, double eps, const double* aj, double* mv,
+                           double* vv, double* fbar, const double* reset, hipStream_t st);
 hipError_t launch_picard_coef(int n, int d, const double* u, double* Ac, hipStream_t st);
 // out (one double slot) = max |e_i|;  count of |e_i| > thr (as an integer in the slot)
 hipError_t launch_absmax(int n, const double* e, double* out, hipStream_t st);

@@ -437,3 +437,26 @@ def test_u_dependent_energies_separate_v_partition(energy):
     assert np.allclose(u.cpu().numpy(), ref["u"], rtol=0, atol=1e-8 * np.abs(ref["u"]).max())
     assert info["grad_norm"] == pytest.approx(ref["grad_norm"], rel=1e-6)
     assert info["J"] == pytest.approx(ref["J"], rel=1e-8, abs=1e-10)
+
+
+@pytest.mark.parametrize("energy,tol,iters", [("plaplace", 0.0, 300), ("semilinear", 0.0, 200),
+                                              ("plaplace", 1e-300, 260)])
+def test_captured_graph_iterations_are_the_same_bits(disk_tb, energy, tol, iters):
+    """Adam with the iterations between checks replayed from one captured
+    HIP graph (blocks of 64 without a tolerance, of check_every = 20 with
+    one; the tail beyond the last whole block runs launch by launch) against
+    the launch-by-launch loop: the same kernels on the same data, so every
+    iterate, and so the result, is the same bits, on every replay of the
+    graph (several per call).  Run twice in a row with eager work between."""
+    tb, mats = disk_tb
+    f, g = _data(tb.n, tb.p, 5)
+    kw = dict(energy=energy, tol=tol, check_every=20 if tol > 0 else 0)
+    outs = []
+    for graph in (False, True, False, True):
+        u, gu, fb, info = tb.minimize(f, g, 2.0, 0.01, iters, fbar0=0.5, graph=graph, **kw)
+        torch.cuda.synchronize()
+        outs.append((u.cpu(), gu.cpu(), fb.cpu(), info))
+    for u, gu, fb, info in outs[1:]:
+        assert torch.equal(u, outs[0][0]) and torch.equal(gu, outs[0][1]) and torch.equal(fb, outs[0][2])
+        assert info["iters"] == outs[0][3]["iters"] == iters
+        assert info["J"] == outs[0][3]["J"] and info["grad_norm"] == outs[0][3]["grad_norm"]

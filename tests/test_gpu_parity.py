@@ -425,7 +425,7 @@ def _check_f32_rows(g, ref, rows, bn_g, site_steps=None):
     assert np.all(np.abs(fg["B1"] - fr["B1"]) <= 4 * ref["seB1"].T)
     assert np.all(np.abs(fg["Hg"] - fr["Hg"]) <= 4 * ref["seHg"])
     assert np.all(np.abs(fg["Kg"] - fr["Kg"]) <= 4 * ref["seKg"].T)
-    # entries (the survey's per-entry rule): among the entries the oracle's
+    # entries, one by one: among the entries the oracle's
     # walks reached at least 10 times, at least 99.9 % within 4 SE_ij and all
     # within 6 SE_ij; the rest enter the moved-mass check below
     for key, hit in (("A", "hitA"), ("B", "hitB"), ("H", "hitH"), ("K", "hitH")):
@@ -442,8 +442,7 @@ def _check_f32_rows(g, ref, rows, bn_g, site_steps=None):
         mass = np.abs(ra).sum(axis=-1)
         assert np.all(moved <= 0.01 * mass), (key, (moved / mass).max())
     # step counts: the walks take the oracle's steps up to rare FP32 flips of
-    # the eps test (the survey's diagnostic asks 99 % of walks exact; the
-    # per-site totals agree to 1e-3)
+    # the eps test (per-site totals agree to 1e-3)
     if site_steps is not None:
         rel = np.abs(site_steps - ref["steps"]) / ref["steps"]
         assert np.all(rel <= 1e-3), rel.max()
