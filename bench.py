@@ -558,10 +558,20 @@ def el_plaplace(a, torch, W, P):
         rows["P=%g" % Pexp] = {"alpha": alpha, "iters": info["iters"], "seconds": info["seconds"],
                                "iters_per_s": info["iters"] / info["seconds"], "grad_norm": info["grad_norm"],
                                "tol": tol, "J": info["J"], "rel_l2_error": err}
+    # the same small problem is launch-bound: the iterations launch by
+    # launch against blocks of 64 replayed from one captured HIP graph
+    rate = {}
+    for graph in (False, True):
+        tb.minimize(np.ones(tb.n), np.zeros(tb.p), 2.0, 1e-3, 128, graph=graph)
+        _, _, fb, info = tb.minimize(np.ones(tb.n), np.zeros(tb.p), 2.0, 1e-3, 20000, graph=graph)
+        rate["graph" if graph else "eager"] = {"iters": info["iters"], "iters_per_s": info["iters"] / info["seconds"],
+                                               "J": info["J"]}
+    rate["graph_speedup"] = rate["graph"]["iters_per_s"] / rate["eager"]["iters_per_s"]
+    rate["same_result"] = rate["graph"]["J"] == rate["eager"]["J"]
     tb.free()
     out = {"workload": "paper disk p-torsion: 300 ring sites, 60 nodes, %g walks/site, eps 1e-4, FP32; Adam "
                        "(beta 0.9/0.999, eps 1e-10, fbar_0 = 1) to the paper's gradient norms" % a.el_walks,
-           "disk": rows}
+           "disk": rows, "disk_P2_iteration_rate": rate}
     # run on to 20000 iterations (near the minimiser of J): with W = V the
     # minimiser is far from the closed form; with a finer W partition (1200
     # ring sites) for the same 300 V cells it is not
@@ -707,20 +717,28 @@ def el_energies(a, torch, W, P):
             "iters": info["iters"], "seconds": info["seconds"], "ms_per_iter": 1e3 * info["seconds"] / info["iters"],
             "grad_norm": info["grad_norm"], "J": info["J"], "u_range": [float(u.min()), float(u.max())],
             "newton_schulz_iters": info["ns_iters"], "newton_schulz_residual": info["ns_residual"]}
-    # s = 8000 with the paper's parameters for it: Adam with alpha = 10, and
-    # p-HiSD as above
+    tb.free()
+    # s = 8000: the runs of the paper's parameter table (Adam, p-HiSD of
+    # index 1..8 from fbar_0 = 1000 at eta 20, 5, 80, and restarts from the
+    # dips of the (k, eta) = (4, 20), (5, 20), (5, 5), (6, 20) runs), on the
+    # toolbox of its square layout with its walk parameters (N = 1e7, M = 30
+    # steps), solutions counted modulo the square's symmetries
+    from paper_2608_07017_amd import search as S
+    tb = P.Toolbox(W.unit_square(), sites, bnd, 10 ** 7, 0.0, seed=11, precision="f32", fixed_M=30,
+                   volume_samples=1 << 22)
+    tb.build()
     f = 8000.0 * np.sin(np.pi * sites[:, 0]) * np.sin(np.pi * sites[:, 1])
-    u, _, _, info = tb.minimize(f, np.zeros(tb.p), 0.0, 10.0, a.el_max_iter * 3, fbar0=1.0, energy="semilinear",
-                                tol=1e-6, check_every=50)
-    out["semilinear_s8000_adam"] = {"alpha": 10.0, "iters": info["iters"], "seconds": info["seconds"],
-                                    "grad_norm": info["grad_norm"], "J": info["J"],
-                                    "u_range": [float(u.min()), float(u.max())]}
-    for k in (1, 2, 3):
-        u, _, _, _, info = tb.saddle(f, np.zeros(tb.p), k, 20.0, 10.0, a.hisd_max_iter, fbar0=1000.0, precond="A",
-                                     tol=1e-6, check_every=50)
-        out["semilinear_s8000_phisd_k%d" % k] = {
-            "iters": info["iters"], "seconds": info["seconds"], "grad_norm": info["grad_norm"], "J": info["J"],
-            "u_range": [float(u.min()), float(u.max())]}
+    t0 = time.perf_counter()
+    runs = S.semilinear_s8000_table(tb, f, np.zeros(tb.p), a.hisd_max_iter, 1e-6)
+    keep = S.distinct(runs, S.square_symmetries(sites))
+    out["semilinear_s8000_search"] = {
+        "toolbox": "paper square layout, 1e7 walks/site, M = 30 steps, FP32",
+        "seconds": time.perf_counter() - t0, "max_iter": a.hisd_max_iter, "tol": 1e-6,
+        "distinct_solutions": len(keep), "paper_distinct_solutions": 22,
+        "runs": [{"k": r["k"], "eta": r["eta"], "start": r["start"], "iters": r["iters"], "converged": r["converged"],
+                  "grad_norm": r["grad_norm"], "J": r["J"], "distinct": i in keep, "error": r.get("error"),
+                  "u_range": None if r["u"] is None else [float(np.min(r["u"])), float(np.max(r["u"]))]}
+                 for i, r in enumerate(runs)]}
     tb.free()
     cfg = W.config("lshape4096")
     tb = P.Toolbox(cfg["domain"], cfg["sites"], cfg["bnodes"], 1000, cfg["eps"], seed=cfg["seed"], precision="f32")

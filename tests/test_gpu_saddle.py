@@ -271,3 +271,44 @@ def test_saddle_other_energies_match_oracle(ring_tb, energy, p_exp):
     assert np.abs(fb - ref_fb).max() <= 1e-7 * np.abs(ref_fb).max()
     assert np.abs(V.T - ref_V).max() <= 1e-6 * np.abs(ref_V).max()
     assert info["grad_norm"] == pytest.approx(E.grad_norm(lam, gr(ref_fb)), rel=1e-5)
+
+
+def test_saddle_paper_s8000_distinct_solutions():
+    # Lap u + u^2 = 8000 sin(pi x) sin(pi y) on the paper's square layout
+    # with its walk parameters (N = 1e7, M = 30 steps, FP32) and its table's
+    # runs for the minimum and the saddles of index 1..5 (Adam alpha = 10;
+    # p-HiSD M = A, fbar_0 = 1000, eta = 20, tau = 10, directions from the
+    # Hessian), each to its final norm 1e-6: six essentially distinct
+    # solutions (none the image of another under the square's symmetries),
+    # each a critical point whose Hessian (the oracle's, on the exported
+    # toolbox) has exactly k negative eigenvalues.
+    from paper_2608_07017_amd import search as S
+    sites, bn = W.paper_square_layout()
+    _say("GPU build paper square, 1e7 walks, M = 30, FP32")
+    tb = P.Toolbox(W.unit_square(), sites, bn, 10 ** 7, 0.0, seed=11, precision="f32", fixed_M=30,
+                   volume_samples=1 << 22)
+    tb.build()
+    torch.cuda.synchronize()
+    mats = {key: tb.export(key).cpu().numpy().astype(np.float64) for key in ("A", "B", "H", "K", "lambda")}
+    lam = mats["lambda"]
+    f = 8000.0 * np.sin(np.pi * sites[:, 0]) * np.sin(np.pi * sites[:, 1])
+    g = np.zeros(tb.p)
+    _, _, fb, info = tb.minimize(f, g, 0.0, 10.0, 40000, fbar0=1.0, energy="semilinear", tol=1e-6, check_every=50)
+    u, _ = tb.apply(fb, g)
+    runs = [{"k": 0, "fbar": fb, "u": u.cpu().numpy(), "converged": info["grad_norm"] <= 1e-6}]
+    for k in (1, 2, 3, 4, 5):
+        _say("saddle s=8000 k=%d" % k)
+        r = S.run(tb, f, g, k, 20.0, 10.0, 1000.0, 40000, 1e-6)
+        _say("  %d iters, grad norm %.2e" % (r["iters"], r["grad_norm"]))
+        runs.append(r)
+    for r in runs:
+        assert r["converged"], r["k"]
+        fb = r["fbar"].cpu().numpy()
+        gr = E.energy_grad("semilinear", mats, lam, fb, g, 0.0, f)
+        assert E.grad_norm(lam, gr) <= 1.1e-6
+        Hf = E.semilinear_hessian(mats, lam, fb, g)
+        assert np.sum(np.linalg.eigvalsh(0.5 * (Hf + Hf.T)) < 0) == r["k"]
+    assert len(S.distinct(runs, S.square_symmetries(sites))) == 6
+    # the symmetry test itself: a reflected copy of a solution is the same one
+    perms = S.square_symmetries(sites)
+    assert S.same_solution(runs[1]["u"], runs[1]["u"][perms[4]], perms, 1e-12)
