@@ -712,11 +712,21 @@ def el_energies(a, torch, W, P):
     # (M = A, fbar_0 = 1000, eta = 20, tau = 10, directions from the Hessian)
     for k in (1, 2, 3):
         u, _, _, _, info = tb.saddle(f, np.zeros(tb.p), k, 20.0, 10.0, a.hisd_max_iter, fbar0=1000.0, precond="A",
-                                     tol=1e-6, check_every=50)
+                                     tol=1e-6, check_every=50, graph=True)
         out["semilinear_s800_phisd_k%d" % k] = {
             "iters": info["iters"], "seconds": info["seconds"], "ms_per_iter": 1e3 * info["seconds"] / info["iters"],
             "grad_norm": info["grad_norm"], "J": info["J"], "u_range": [float(u.min()), float(u.max())],
             "newton_schulz_iters": info["ns_iters"], "newton_schulz_residual": info["ns_residual"]}
+    # the iteration rate launch by launch against blocks replayed from one
+    # captured graph (k = 2, a fixed 4000 iterations; the same bits)
+    rate = {}
+    for graph in (False, True):
+        _, _, fbg, _, info = tb.saddle(f, np.zeros(tb.p), 2, 20.0, 10.0, 4000, fbar0=1000.0, precond="A",
+                                       graph=graph)
+        rate["graph" if graph else "eager"] = {"ms_per_iter": 1e3 * info["seconds"] / info["iters"], "J": info["J"]}
+    rate["graph_speedup"] = rate["eager"]["ms_per_iter"] / rate["graph"]["ms_per_iter"]
+    rate["same_result"] = rate["graph"]["J"] == rate["eager"]["J"]
+    out["semilinear_s800_phisd_k2_iteration_rate"] = rate
     tb.free()
     # s = 8000: the runs of the paper's parameter table (Adam, p-HiSD of
     # index 1..8 from fbar_0 = 1000 at eta 20, 5, 80, and restarts from the

@@ -580,6 +580,10 @@ typedef struct {
                            eigenvectors of the k smallest eigenvalues of the
                            Hessian of J at the start (the paper's choice; the
                            semilinear energy only)                            */
+  int32_t graph;        /* 1: after the first block, every block of C
+                           iterations (C = check_every with tol > 0, else 64;
+                           C must be even, else 0 is used) is replayed from
+                           one captured HIP graph; the same bits as 0         */
 } wos_hisd_opts;
 
 typedef struct {

@@ -371,11 +371,12 @@ class Toolbox:
         return u, gu, fbar, {k: getattr(info, k) for k, _ in info._fields_}
 
     def saddle(self, f, g, k, eta, tau, max_iter, fbar0=1.0, V0=None, precond="A", energy="semilinear", p_exp=0.0,
-               tol=0.0, check_every=0, stream=None):
+               tol=0.0, check_every=0, graph=False, stream=None):
         """p-HiSD saddle search on J (include/wos.h, wos_saddle) from the
         source fbar0 (scalar or (m,) array) with k directions: V0 (k, m) if
         given, else the eigenvectors of the k smallest eigenvalues of the
         Hessian at fbar0.  precond is "A" (the paper's M = A) or "identity".
+        graph=True replays blocks of iterations from one captured HIP graph.
         Returns (u, grad_u, fbar, V, info) with device float64 tensors."""
         dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
         f, g = dev(f), dev(g)
@@ -397,7 +398,8 @@ class Toolbox:
                 raise ValueError("V0 must have shape (k, m)")
         opts = WosHisdOpts(energy=ENERGIES[energy], p_exp=float(p_exp), k=int(k), eta=float(eta), tau=float(tau),
                            max_iter=int(max_iter), tol=float(tol), check_every=int(check_every),
-                           precond=HISD_PRECOND[precond], init=HISD_INIT["given" if V0 is not None else "hessian"])
+                           precond=HISD_PRECOND[precond], init=HISD_INIT["given" if V0 is not None else "hessian"],
+                           graph=1 if graph else 0)
         u = torch.empty(self.n, dtype=torch.float64, device="cuda")
         gu = torch.empty((self.dim, self.n), dtype=torch.float64, device="cuda")
         info = WosHisdInfo()

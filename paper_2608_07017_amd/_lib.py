@@ -107,7 +107,7 @@ class WosHisdOpts(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_int32), ("p_exp", ctypes.c_double), ("k", ctypes.c_int32),
                 ("eta", ctypes.c_double), ("tau", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("init", ctypes.c_int32)]
+                ("init", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class WosHisdInfo(ctypes.Structure):

@@ -1166,6 +1166,7 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   eg.uterm = kind == WOS_EL_SEMILINEAR || kind == WOS_EL_ELLIPTIC;
   eg.f = f;
   eg.part = w.part;
+  hipStream_t cs = st;  // the stream the iteration's launches go to (switched while capturing)
   eg.st = st;
   double* F = eg.carve(w.el);  // n
   double* red = F + n;         // 2 (the Adam route's slots are not used here)
@@ -1197,36 +1198,36 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   // y = M^-1 x, and M x, for one vector
   auto minv = [&](const double* x, double* y) -> wos_status {
     if (useA)
-      SHIP(launch_gemv_n(true, Minv, m, m, x, 1.0, 0.0, y, st));
+      SHIP(launch_gemv_n(true, Minv, m, m, x, 1.0, 0.0, y, cs));
     else
-      SHIP(hipMemcpyAsync(y, x, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+      SHIP(hipMemcpyAsync(y, x, sizeof(double) * m, hipMemcpyDeviceToDevice, cs));
     return WOS_OK;
   };
   // Y[t] = M^-1 X[t] for nv vectors: one pass over M^-1
   auto minv_batch = [&](const double* X, int nvec, double* Y) -> wos_status {
     if (useA)
-      SHIP(launch_gemv_batch(true, false, Minv, m, m, m, X, m, nvec, Y, m, w.part, st));
+      SHIP(launch_gemv_batch(true, false, Minv, m, m, m, X, m, nvec, Y, m, w.part, cs));
     else
-      SHIP(hipMemcpyAsync(Y, X, sizeof(double) * nvec * (size_t)m, hipMemcpyDeviceToDevice, st));
+      SHIP(hipMemcpyAsync(Y, X, sizeof(double) * nvec * (size_t)m, hipMemcpyDeviceToDevice, cs));
     return WOS_OK;
   };
   auto mult = [&](const double* x, double* y) -> wos_status {
     if (useA)
-      SHIP(launch_gemv_n_ld(tb->f64, tb->d_A, m, m, m, x, 1.0, 0.0, y, st));
+      SHIP(launch_gemv_n_ld(tb->f64, tb->d_A, m, m, m, x, 1.0, 0.0, y, cs));
     else
-      SHIP(hipMemcpyAsync(y, x, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+      SHIP(hipMemcpyAsync(y, x, sizeof(double) * m, hipMemcpyDeviceToDevice, cs));
     return WOS_OK;
   };
   // the Gram-Schmidt flag is sticky: cleared once, read (with a
   // synchronisation) after the first pass, at the norm checks and at the end
   auto orthonormalise = [&](double* Vx) -> wos_status {
     if (useA && k >= 2) {  // M V in one pass over A
-      SHIP(launch_gemv_batch(tb->f64, false, tb->d_A, m, m, m, Vx, m, k, MV, m, w.part, st));
+      SHIP(launch_gemv_batch(tb->f64, false, tb->d_A, m, m, m, Vx, m, k, MV, m, w.part, cs));
     } else {
       for (int i = 0; i < k; ++i)
         if ((s = mult(Vx + (size_t)i * m, MV + (size_t)i * m)) != WOS_OK) return s;
     }
-    SHIP(launch_hisd_gs(m, k, Vx, MV, w.hs_bad, st));
+    SHIP(launch_hisd_gs(m, k, Vx, MV, w.hs_bad, cs));
     return WOS_OK;
   };
   auto check_bad = [&]() -> wos_status {
@@ -1274,31 +1275,97 @@ wos_status saddle_request(wos_toolbox* tb, SolveWork& w, const wos_hisd_opts* o,
   if ((s = weighted_norm(gr, &inf.grad_norm0)) != WOS_OK) return s;
   const auto t0 = std::chrono::steady_clock::now();
   int it = 0;
-  for (int j = 1; j <= o->max_iter; ++j) {
+  // one iteration, launched on cs
+  auto iteration = [&]() -> wos_status {
     // fbar_j = fbar_{j-1} - eta R M^-1 grad J(fbar_{j-1})  (gr holds the
     // gradient, wcur its product with M^-1)
-    SHIP(launch_hisd_fbar(m, k, Vc, gr, wcur, o->eta, fbar, hbuf, st));
+    SHIP(launch_hisd_fbar(m, k, Vc, gr, wcur, o->eta, fbar, hbuf, cs));
     // the 2k + 1 gradients at fbar_j +- h v_i and fbar_j (one pass over the
     // toolbox when batchable): H(fbar_j) v_i by central differences, and
     // grad J(fbar_j) for the next step and the checks
-    SHIP(launch_hisd_shift(m, k, fbar, Vc, hbuf, Xs, st));
-    if ((s = eg.eval_batch(Xs, Gs, nv, w.hsb)) != WOS_OK) return s;
+    SHIP(launch_hisd_shift(m, k, fbar, Vc, hbuf, Xs, cs));
+    eg.st = cs;
+    wos_status es = eg.eval_batch(Xs, Gs, nv, w.hsb);
+    eg.st = st;
+    if (es != WOS_OK) return es;
     gr = Gs + 2 * (size_t)k * m;
     // H v_i and grad J(fbar_j), then M^-1 of all k + 1 in one pass: y_i for
     // the directions, and the next step's M^-1 grad J
-    SHIP(launch_hisd_hv(m, k, Gs, hbuf, HV, st));
-    if ((s = minv_batch(HV, k + 1, Yv)) != WOS_OK) return s;
+    SHIP(launch_hisd_hv(m, k, Gs, hbuf, HV, cs));
+    if ((es = minv_batch(HV, k + 1, Yv)) != WOS_OK) return es;
     wcur = Yv + (size_t)k * m;
-    SHIP(launch_hisd_v(m, k, Vc, HV, Yv, o->tau, Vn, st));
-    if ((s = orthonormalise(Vn)) != WOS_OK) return s;
+    SHIP(launch_hisd_v(m, k, Vc, HV, Yv, o->tau, Vn, cs));
+    if ((es = orthonormalise(Vn)) != WOS_OK) return es;
     std::swap(Vc, Vn);
-    it = j;
-    if (o->tol > 0.0 && j % check == 0) {
-      if ((s = check_bad()) != WOS_OK) return s;
-      if ((s = weighted_norm(gr, &gn)) != WOS_OK) return s;
-      if (gn <= o->tol) break;
+    return WOS_OK;
+  };
+  // Blocks of C iterations replayed from one captured graph, after a first
+  // block launch by launch (the first iteration reads the starting
+  // gradient's buffers; afterwards every pointer an iteration uses recurs
+  // after two iterations, so a graph of an even number of them returns the
+  // buffers to where it found them).
+  const int C = o->tol > 0.0 ? check : 64;
+  const bool use_graph = o->graph != 0 && C % 2 == 0 && o->max_iter >= 2 * C;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool stop = false;
+  for (int j = 1; j <= o->max_iter && !stop;) {
+    if (use_graph && j > C && j + C - 1 <= o->max_iter) {
+      if (!exec) {
+        if (!w.cap) SHIP(hipStreamCreateWithFlags(&w.cap, hipStreamNonBlocking));
+        SHIP(hipStreamBeginCapture(w.cap, hipStreamCaptureModeThreadLocal));
+        cs = w.cap;
+        const double* gr_s = gr;
+        const double* wc_s = wcur;
+        double* vc_s = Vc;
+        double* vn_s = Vn;
+        wos_status es = WOS_OK;
+        for (int i = 0; i < C && es == WOS_OK; ++i) es = iteration();
+        cs = st;
+        const hipError_t ce = hipStreamEndCapture(w.cap, &graph);
+        // the capture ran nothing: the state is the one before it
+        gr = gr_s;
+        wcur = wc_s;
+        Vc = vc_s;
+        Vn = vn_s;
+        if (es != WOS_OK) {
+          if (ce == hipSuccess && graph) (void)hipGraphDestroy(graph);
+          return es;
+        }
+        SHIP(ce);
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+          (void)hipGraphDestroy(graph);
+          SHIP(ie);
+        }
+      }
+      const hipError_t le = hipGraphLaunch(exec, st);
+      if (le != hipSuccess) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        SHIP(le);
+      }
+      // the same pointers as after C launch-by-launch iterations
+      gr = Gs + 2 * (size_t)k * m;
+      wcur = Yv + (size_t)k * m;
+      j += C;
+    } else {
+      if ((s = iteration()) != WOS_OK) return s;
+      ++j;
+    }
+    it = j - 1;
+    if (o->tol > 0.0 && it % check == 0) {
+      if ((s = check_bad()) != WOS_OK) break;
+      if ((s = weighted_norm(gr, &gn)) != WOS_OK) break;
+      if (gn <= o->tol) stop = true;
     }
   }
+  if (exec) {
+    (void)hipStreamSynchronize(st);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+  }
+  if (s != WOS_OK) return s;
   SHIP(hipStreamSynchronize(st));
   inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   inf.iters = it;

@@ -312,3 +312,28 @@ def test_saddle_paper_s8000_distinct_solutions():
     # the symmetry test itself: a reflected copy of a solution is the same one
     perms = S.square_symmetries(sites)
     assert S.same_solution(runs[1]["u"], runs[1]["u"][perms[4]], perms, 1e-12)
+
+
+@pytest.mark.parametrize("precond,eta,tau,tol,iters", [("A", 0.5, 0.5, 0.0, 300), ("identity", 20.0, 20.0, 1e-300, 230),
+                                                        ("A", 0.5, 0.5, 1e-300, 130)])
+def test_saddle_captured_graph_iterations_are_the_same_bits(ring_tb, precond, eta, tau, tol, iters):
+    """p-HiSD with blocks of iterations replayed from one captured HIP graph
+    (after a first block launch by launch; blocks of 64 without a
+    tolerance, of check_every = 20 with one; the tail launch by launch)
+    against the launch-by-launch loop: every iterate the same bits, so the
+    end point, the directions and the statistics too; calls alternate."""
+    tb, mats = ring_tb
+    f, g = _problem(tb.n, tb.p, 41)
+    rng = np.random.default_rng(42)
+    V0 = rng.normal(size=(2, tb.m))
+    fb0 = 1.0 + 0.1 * rng.normal(size=tb.m)
+    outs = []
+    for graph in (False, True, False, True):
+        u, gu, fb, V, info = tb.saddle(f, g, 2, eta, tau, iters, fbar0=fb0, V0=V0, precond=precond, tol=tol,
+                                       check_every=20 if tol > 0 else 0, graph=graph)
+        torch.cuda.synchronize()
+        outs.append((u.cpu(), fb.cpu(), V.cpu(), info))
+    for u, fb, V, info in outs[1:]:
+        assert torch.equal(u, outs[0][0]) and torch.equal(fb, outs[0][1]) and torch.equal(V, outs[0][2])
+        assert info["iters"] == outs[0][3]["iters"] == iters
+        assert info["J"] == outs[0][3]["J"] and info["grad_norm"] == outs[0][3]["grad_norm"]
