@@ -16,6 +16,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "wos_solve_kernels.hpp"
@@ -299,9 +302,63 @@ bool rows_aligned(const S* X, int ld) {
   return ((uintptr_t)X % 16) == 0 && ((size_t)ld * sizeof(S)) % 16 == 0;
 }
 
+// Tile autotuner of the FP32 pipelined products: the first product of a
+// shape class (transposes, triangle mode, M and N in tiles of 128, K to a
+// power of two) that overwrites C (beta = 0) runs with both tilings, timed
+// with HIP events on its stream, and the faster is kept for the class.
+// Both tilings add the same products in the same order for every element
+// of C, so the choice changes the time only, never a bit of the result.
+// Other products of an untuned class take the occupancy rule below.
+struct TileKey {
+  int ta, tb, lower, mt, nt, kl;
+  bool operator<(const TileKey& o) const {
+    return std::tie(ta, tb, lower, mt, nt, kl) < std::tie(o.ta, o.tb, o.lower, o.mt, o.nt, o.kl);
+  }
+};
+std::mutex g_tile_mu;
+std::map<std::pair<int, TileKey>, int> g_tile;  // (device, class) -> 1: 128 x 128 tiles, 0: 64 x 64
+
 template <typename T, typename SA, typename SB>
 hipError_t gemm_dispatch(bool ta, bool tb, int M, int N, int K, T alpha, const SA* A, int lda, const SB* B, int ldb,
-                         T beta, T* C, int ldc, hipStream_t st, bool lower = false) {
+                         T beta, T* C, int ldc, hipStream_t st, bool lower = false, int force_wide = -1);
+
+template <typename T, typename SA, typename SB>
+int tuned_wide(bool ta, bool tb, int M, int N, int K, T alpha, const SA* A, int lda, const SB* B, int ldb, T beta,
+               T* C, int ldc, hipStream_t st, bool lower, bool rule) {
+  int kl = 0;
+  while ((1 << (kl + 1)) <= K) ++kl;
+  const TileKey key{ta ? 1 : 0, tb ? 1 : 0, lower ? 1 : 0, (M + 127) / 128, (N + 127) / 128, kl};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  {
+    std::lock_guard<std::mutex> g(g_tile_mu);
+    auto it = g_tile.find({dev, key});
+    if (it != g_tile.end()) return it->second;
+  }
+  if (beta != T(0)) return rule ? 1 : 0;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) return rule ? 1 : 0;
+  float t_narrow = 0.0f, t_wide = 0.0f;
+  bool ok = hipEventRecord(ev[0], st) == hipSuccess &&
+            gemm_dispatch<T, SA, SB>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st, lower, 0) ==
+                hipSuccess &&
+            hipEventRecord(ev[1], st) == hipSuccess &&
+            gemm_dispatch<T, SA, SB>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st, lower, 1) ==
+                hipSuccess &&
+            hipEventRecord(ev[2], st) == hipSuccess && hipEventSynchronize(ev[2]) == hipSuccess &&
+            hipEventElapsedTime(&t_narrow, ev[0], ev[1]) == hipSuccess &&
+            hipEventElapsedTime(&t_wide, ev[1], ev[2]) == hipSuccess;
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  const int pick = ok ? (t_wide < t_narrow ? 1 : 0) : (rule ? 1 : 0);
+  std::lock_guard<std::mutex> g(g_tile_mu);
+  g_tile[{dev, key}] = pick;
+  return ok ? -1 - pick : pick;  // -1 - pick: C already holds the product
+}
+
+template <typename T, typename SA, typename SB>
+hipError_t gemm_dispatch(bool ta, bool tb, int M, int N, int K, T alpha, const SA* A, int lda, const SB* B, int ldb,
+                         T beta, T* C, int ldc, hipStream_t st, bool lower, int force_wide) {
   const int lo = lower ? 1 : 0;
   if (M <= 0 || N <= 0) return hipSuccess;
   // larger products: the pipelined kernel, FP32 128 x 128 tiles, FP64
@@ -316,7 +373,16 @@ hipError_t gemm_dispatch(bool ta, bool tb, int M, int N, int K, T alpha, const S
     // still fill the chip four times over, else the last round runs
     // mostly empty)
     const size_t t128 = (size_t)((M + 127) / 128) * ((N + 127) / 128);
-    const bool wide = std::is_same<T, float>::value && (lower ? (t128 + (M + 127) / 128) / 2 >= 1024 : t128 >= 256);
+    bool wide = std::is_same<T, float>::value && (lower ? (t128 + (M + 127) / 128) / 2 >= 1024 : t128 >= 256);
+    if constexpr (std::is_same<T, float>::value) {
+      if (force_wide >= 0) {
+        wide = force_wide != 0;
+      } else {
+        const int w = tuned_wide<T, SA, SB>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st, lower, wide);
+        if (w < 0) return hipSuccess;  // the timing runs computed the product
+        wide = w != 0;
+      }
+    }
 #define WOS_PIPE(W_, TA_, TB_)                                                                                  \
   hipLaunchKernelGGL((mfma_gemm_pipe_kernel<T, SA, SB, TA_, TB_, W_, W_>),                                      \
                      dim3((N + 32 * W_ - 1) / (32 * W_), (M + 32 * W_ - 1) / (32 * W_)), dim3(256), 0, st, M, N, K, \

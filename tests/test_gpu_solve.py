@@ -330,6 +330,13 @@ def test_tikhonov_4096_sites_wide_tiles(precision):
     if precision == "mixed":
         assert info["refine_iters"] <= 8
     assert _lam_rel(u.cpu().numpy(), ref["u"], lam) < 1e-9
+    # the first FP32 product of each shape class times both tilings (and
+    # keeps the faster); the tilings add in the same order, so a second
+    # solve, on the kept tiling, gives the same bits
+    u2, _, _, info2 = tb.solve(f, g, kind="linear", A=A, b=b, c=c, rcond=1e-2, solver="tikhonov",
+                               precision=precision, refine_tol=1e-13, max_refine=30)
+    torch.cuda.synchronize()
+    assert torch.equal(u, u2) and info2["refine_iters"] == info["refine_iters"]
 
 
 def test_paper_elliptic_div_example_end_to_end():
