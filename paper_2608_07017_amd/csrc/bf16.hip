@@ -18,6 +18,8 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
+#include <set>
 
 #include "wos_solve_kernels.hpp"
 
@@ -100,20 +102,21 @@ __global__ __launch_bounds__(256) void weight_t_kernel(const uint16_t* __restric
 
 // C = alpha X Y^T + beta C.  A 256-thread workgroup owns a 128 x 128 tile of
 // C, each wavefront a 64 x 64 quarter of 4 x 4 MFMA blocks; K advances in
-// slabs of 32 staged in LDS (rows padded to 40 values, so that the 16-byte
-// reads of a lane group fall in distinct banks; two buffers), the next slab
-// in flight during the current one's MFMAs.
-constexpr int BT = 128, BK = 32, BPAD = 8;
+// slabs of 64 staged in dynamic LDS (rows padded to 72 values, so that the
+// 16-byte reads of a lane group fall in distinct banks; two buffers, 72 KiB,
+// two workgroups per compute unit), the next slab in flight during the
+// current one's MFMAs (two k-steps of 32 per slab and barrier).
+constexpr int BT = 128, BK = 64, BPAD = 8;
 
 struct SlabLoader {
-  // thread t loads rows t / 4 + 64 e (e = 0, 1), k chunk (t % 4) 8
+  // thread t loads rows t / 8 + 32 e (e = 0..3), k chunk (t % 8) 8
   int row, kc;
-  __device__ __forceinline__ explicit SlabLoader(int tid) : row(tid >> 2), kc((tid & 3) * 8) {}
+  __device__ __forceinline__ explicit SlabLoader(int tid) : row(tid >> 3), kc((tid & 7) * 8) {}
   __device__ __forceinline__ void load(const uint16_t* X, size_t ld, int x0, int xext, int k0, int K, bool vec,
-                                       uint4 (&r)[2]) const {
+                                       uint4 (&r)[4]) const {
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int gx = x0 + row + 64 * e, gk = k0 + kc;
+    for (int e = 0; e < 4; ++e) {
+      const int gx = x0 + row + 32 * e, gk = k0 + kc;
       const uint16_t* src = X + (size_t)gx * ld + gk;
       if (vec && gx < xext && gk + 8 <= K) {
         r[e] = *reinterpret_cast<const uint4*>(src);
@@ -126,9 +129,9 @@ struct SlabLoader {
       }
     }
   }
-  __device__ __forceinline__ void store(uint16_t (*sl)[BK + BPAD], const uint4 (&r)[2]) const {
+  __device__ __forceinline__ void store(uint16_t (*sl)[BK + BPAD], const uint4 (&r)[4]) const {
 #pragma unroll
-    for (int e = 0; e < 2; ++e) *reinterpret_cast<uint4*>(&sl[row + 64 * e][kc]) = r[e];
+    for (int e = 0; e < 4; ++e) *reinterpret_cast<uint4*>(&sl[row + 32 * e][kc]) = r[e];
   }
 };
 
@@ -136,8 +139,9 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, 
                                                            const uint16_t* __restrict__ X, size_t ldx,
                                                            const uint16_t* __restrict__ Y, size_t ldy, float beta,
                                                            float* __restrict__ C, size_t ldc, int vec) {
-  __shared__ __align__(16) uint16_t sX[2][BT][BK + BPAD];
-  __shared__ __align__(16) uint16_t sY[2][BT][BK + BPAD];
+  extern __shared__ __align__(16) uint16_t gsm[];
+  uint16_t(*sX)[BT][BK + BPAD] = reinterpret_cast<uint16_t(*)[BT][BK + BPAD]>(gsm);
+  uint16_t(*sY)[BT][BK + BPAD] = reinterpret_cast<uint16_t(*)[BT][BK + BPAD]>(gsm + 2 * BT * (BK + BPAD));
   const int m0 = blockIdx.y * BT, n0 = blockIdx.x * BT;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -150,7 +154,7 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, 
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-  uint4 rx[2], ry[2];
+  uint4 rx[4], ry[4];
   ld.load(X, ldx, m0, M, 0, K, vec != 0, rx);
   ld.load(Y, ldy, n0, N, 0, K, vec != 0, ry);
   ld.store(sX[0], rx);
@@ -163,12 +167,13 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, 
       ld.load(X, ldx, m0, M, k0 + BK, K, vec != 0, rx);
       ld.load(Y, ldy, n0, N, k0 + BK, K, vec != 0, ry);
     }
-    {
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 32) {
       bf16x8 xv[4], yv[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) xv[a] = *reinterpret_cast<const bf16x8*>(&sX[buf][wm + 16 * a + li][lk]);
+      for (int a = 0; a < 4; ++a) xv[a] = *reinterpret_cast<const bf16x8*>(&sX[buf][wm + 16 * a + li][ks + lk]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) yv[b] = *reinterpret_cast<const bf16x8*>(&sY[buf][wn + 16 * b + li][lk]);
+      for (int b = 0; b < 4; ++b) yv[b] = *reinterpret_cast<const bf16x8*>(&sY[buf][wn + 16 * b + li][ks + lk]);
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -286,7 +291,22 @@ hipError_t gemm_nt_bf16(int M, int N, int K, float alpha, const uint16_t* X, siz
   if (M <= 0 || N <= 0) return hipSuccess;
   const bool vec = ((uintptr_t)X % 16) == 0 && ((uintptr_t)Y % 16) == 0 && ldx % 8 == 0 && ldy % 8 == 0;
   const dim3 g(nblk(N, BT), nblk(M, BT)), b(256);
-  hipLaunchKernelGGL(gemm_nt_bf16_kernel, g, b, 0, st, M, N, K, alpha, X, ldx, Y, ldy, beta, C, ldc, vec ? 1 : 0);
+  const size_t lds = 4 * (size_t)BT * (BK + BPAD) * sizeof(uint16_t);
+  {
+    // more than the default 64 KiB of dynamic LDS: allowed once per device
+    static std::mutex mu;
+    static std::set<int> done;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g_(mu);
+    if (!done.count(dev)) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_nt_bf16_kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      done.insert(dev);
+    }
+  }
+  hipLaunchKernelGGL(gemm_nt_bf16_kernel, g, b, lds, st, M, N, K, alpha, X, ldx, Y, ldy, beta, C, ldc, vec ? 1 : 0);
   return hipGetLastError();
 }
 
