@@ -146,7 +146,7 @@ typedef struct {
                                as fit 152 KiB with the boundary pages, i.e. one
                                workgroup of 1024 lanes per compute unit)         */
   int32_t window_bpages;    /* WINDOW: pages of boundary cells per site in LDS
-                               (0: min(16, all))                                 */
+                               (0: min(8, all))                                  */
   const double* test_phi;   /* host, m values or NULL: a test function phi on the
                                V cells; with test_psi, switches on the per-site
                                moments (WOS_EXPORT_MOMENTS)                       */

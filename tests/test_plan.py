@@ -22,7 +22,7 @@ def test_workload_plans():
     assert _plan("ball4096")["tally_mode"] == "lds_rows"
     cb = _plan("cubeball32768")
     assert cb["tally_mode"] == "window"
-    assert cb["window_bpages"] == 16 and 40 <= cb["window_pages"] <= 255
+    assert cb["window_bpages"] == 8 and 40 <= cb["window_pages"] <= 255
     assert 140 * 1024 <= cb["lds_bytes"] <= 160 * 1024
     assert cb["tally_acc"] == "fixed" and cb["fixed_bound"] < 0.5
     assert cb["items_per_site"] * cb["walks_per_item"] >= 100000
