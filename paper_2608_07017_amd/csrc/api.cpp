@@ -803,7 +803,14 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
     TRY(upload(tb, &tb->d_bnodes_r, b32.data(), b32.size() * 4));
     TRY(upload(tb, (void**)&tb->d_vrank, vr.data(), vr.size() * sizeof(int)));
     TRY(upload(tb, (void**)&tb->d_brank, br.data(), br.size() * sizeof(int)));
-    const std::vector<uint16_t> pv = nearest_pages(sites, n, vs.data(), m, d, pl.pc);
+    // V pages by their expected share of the step tallies, boundary pages
+    // (one exit per walk) by distance
+    std::vector<double> vbd(m);
+    for (int r = 0; r < m; ++r) vbd[r] = host_distance(hd, vs.data() + (size_t)r * d);
+    double bvol = 1;
+    for (int a = 0; a < d; ++a) bvol *= hi[a] - lo[a];
+    const double hsp = std::pow(bvol / m, 1.0 / d);
+    const std::vector<uint16_t> pv = tally_pages(sites, n, vs.data(), vbd.data(), m, d, pl.pc, hsp);
     const std::vector<uint16_t> pg = nearest_pages(sites, n, bs.data(), p, d, pl.pb);
     std::vector<uint16_t> win((size_t)n * (pl.pc + pl.pb));
     for (int i = 0; i < n; ++i) {

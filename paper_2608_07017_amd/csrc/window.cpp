@@ -111,4 +111,49 @@ std::vector<uint16_t> nearest_pages(const double* sites, int n, const double* so
   return out;
 }
 
+std::vector<uint16_t> tally_pages(const double* sites, int n, const double* sorted, const double* bdist, int count,
+                                  int dim, int want, double h) {
+  const int npages = (count + kPage - 1) / kPage;
+  want = std::min(want, npages);
+  std::vector<double> plo((size_t)npages * dim), phi((size_t)npages * dim), cen((size_t)npages * dim, 0.0),
+      mass(npages, 0.0);
+  for (int g = 0; g < npages; ++g) {
+    const int r0 = g * kPage, r1 = std::min(count, (g + 1) * kPage);
+    for (int a = 0; a < dim; ++a) {
+      double l = 1e300, u = -1e300, c = 0;
+      for (int r = r0; r < r1; ++r) {
+        const double v = sorted[(size_t)r * dim + a];
+        l = std::min(l, v);
+        u = std::max(u, v);
+        c += v;
+      }
+      plo[(size_t)g * dim + a] = l;
+      phi[(size_t)g * dim + a] = u;
+      cen[(size_t)g * dim + a] = c / (r1 - r0);
+    }
+    for (int r = r0; r < r1; ++r) mass[g] += 1.0 / (std::max(bdist[r], 0.0) + h);
+  }
+  std::vector<uint16_t> out((size_t)n * want);
+  parallel_for(n, [&](int i0, int i1) {
+    std::vector<std::pair<double, int>> key(npages);
+    for (int i = i0; i < i1; ++i) {
+      const double* x = sites + (size_t)i * dim;
+      for (int g = 0; g < npages; ++g) {
+        double sb = 0, sc = 0;
+        for (int a = 0; a < dim; ++a) {
+          const double e = std::max(std::max(plo[(size_t)g * dim + a] - x[a], x[a] - phi[(size_t)g * dim + a]), 0.0);
+          const double c = cen[(size_t)g * dim + a] - x[a];
+          sb += e * e;
+          sc += c * c;
+        }
+        const double rho = 0.5 * (std::sqrt(sb) + std::sqrt(sc)) + h;
+        key[g] = {-mass[g] / (rho * rho), g};  // ascending order = largest score first
+      }
+      std::partial_sort(key.begin(), key.begin() + want, key.end());
+      for (int k = 0; k < want; ++k) out[(size_t)i * want + k] = (uint16_t)key[k].second;
+    }
+  });
+  return out;
+}
+
 }  // namespace wos
