@@ -105,8 +105,10 @@ typedef struct {
                                written to the toolbox once per work item.
                                WINDOW (2, FP32): the V cells and the boundary
                                cells are numbered along a Morton curve in pages
-                               of 64; each site keeps the pages nearest to it
-                               (window_pages, window_bpages) in LDS as exact
+                               of 64; each site keeps the pages that receive
+                               most of its tallies (window_pages V pages ranked
+                               by an estimate of their share, window_bpages
+                               nearest boundary pages) in LDS as exact
                                64-bit fixed-point sums (its items hold few
                                enough walks that the bound of
                                wos_build_plan.fixed_bound stays below 1/2) and
@@ -143,7 +145,7 @@ typedef struct {
                                accumulate in FP64; WINDOW always in fixed point
                                (2 is refused there).                             */
   int32_t window_pages;     /* WINDOW: pages of V cells per site in LDS (0: as many
-                               as fit 152 KiB with the boundary pages, i.e. one
+                               as fit 159 KiB with the boundary pages, i.e. one
                                workgroup of 1024 lanes per compute unit)         */
   int32_t window_bpages;    /* WINDOW: pages of boundary cells per site in LDS
                                (0: min(8, all))                                  */

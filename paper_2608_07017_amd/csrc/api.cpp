@@ -418,7 +418,9 @@ struct Plan {
 };
 
 constexpr size_t kLdsBytes = 160 * 1024;
-constexpr size_t kWindowBudget = 152 * 1024;  // one walker workgroup of 1024 lanes per compute unit
+// one walker workgroup of 1024 lanes per compute unit, using all of its LDS
+// but 1 KiB (the kernel's static variables)
+constexpr size_t kWindowBudget = 159 * 1024;
 constexpr int64_t kWindowMinItem = 256;        // smallest item that the fixed-point guard may ask for
 
 wos_status make_plan(const HostDomain& hd, const double* sites, int n, int m, int p, const wos_build_opts* o,
