@@ -108,7 +108,7 @@ typedef struct {
                                of 64; each site keeps the pages that receive
                                most of its tallies (window_pages V pages ranked
                                by an estimate of their share, window_bpages
-                               nearest boundary pages) in LDS as exact
+                               nearest boundary pages) in LDS as
                                64-bit fixed-point sums (its items hold few
                                enough walks that the bound of
                                wos_build_plan.fixed_bound stays below 1/2) and
@@ -138,7 +138,9 @@ typedef struct {
   int32_t walker_block;     /* walker workgroup size: 0 automatic (occupancy, or the
                                autotuned size), or 256, 448, 512, 1024           */
   int32_t tally_acc;        /* LDS_ROWS accumulators of an FP32 toolbox: 0 automatic
-                               (exact 64-bit fixed point in 2^-32 units, unless the
+                               (64-bit fixed point in 2^-32 units, exact integer
+                               sums; a negative tally above -1 is kept to 2^-25
+                               absolute, like one FP32 add near 1; unless the
                                bound of wos_build_plan.fixed_bound reaches 1/2,
                                then FP64), 1 fixed point (WOS_EINVAL when the bound
                                reaches 1/2), 2 FP64.  FP64 toolboxes always

@@ -5,15 +5,15 @@
 // of A, B (d x m) and K (d x p) live in LDS as 8-byte accumulators, H's exit
 // counts as 32-bit integers, so every tally is an LDS atomic; the rows are
 // written to HBM once, at the end, scaled by 1/N (plain stores when one item
-// covers a whole site).  The accumulators are either FP64 or exact 64-bit
-// fixed point (2^-32 units, integer adds, so the sums do not depend on the
+// covers a whole site).  The accumulators are either FP64 or 64-bit fixed
+// point (2^-32 units, exact integer adds, so the sums do not depend on the
 // order of the atomics): on gfx950 both are several times faster than FP32
 // LDS atomics, which the tally rate would otherwise be bound by.  The
 // workgroup size (256 / 448 / 512 / 1024) is chosen by occupancy, or timed
 // on the first build.  When a site's rows do not fit in LDS, the windowed
 // mode (`kAccWindow`) keeps the pages of cells nearest to the site (cells
-// numbered along a Morton curve) in LDS, again as exact 64-bit fixed-point
-// sums (FP32 LDS atomics are the slow kind), in one workgroup of 1024
+// numbered along a Morton curve) in LDS, again as 64-bit fixed-point sums
+// (FP32 LDS atomics are the slow kind), in one workgroup of 1024
 // lanes per compute unit, and adds the tallies that fall outside them,
 // pre-scaled by 1/N, straight into the toolbox with device atomics; or
 // (`kAccGlobal`) every tally goes there.  The walks are the same in every
@@ -84,14 +84,19 @@ struct Acc<kAccF64> {
 
 // Two's-complement 64-bit fixed point, 2^-32 units: v = hi + frac with
 // hi = floor(v) in the high word and floor(frac * 2^32) in the low word.
-// Every tally here is far below 2^31 in magnitude and the sums of a site's
-// walks stay below 2^31 too.
+// For v >= 0 the split is exact and the word is v truncated to 2^-32.  For a
+// negative v with |v| < 1, frac = 1 + v is rounded to FP32 (to 2^-24 near
+// 1): the error of one FP32 add of v to a sum near 1, unbiased.  Converting
+// from the float's bits instead (exact to 2^-32) costs 6 to 25 % of the
+// walker's time.  The integer sums themselves are exact.  Every tally here
+// is far below 2^31 in magnitude and the sums of a site's walks stay below
+// 2^31 too.
 template <>
 struct Acc<kAccFixed> {
   using word = unsigned long long;
   __device__ __forceinline__ static word encode(float v) {
     const float fl = floorf(v);
-    const float fr = v - fl;  // exact, in [0, 1)
+    const float fr = v - fl;  // in [0, 1]; exact for v >= 0
     const unsigned int lo = (unsigned int)(fr * 4294967296.0f);
     const unsigned int hi = (unsigned int)(int)fl;
     return ((word)hi << 32) | lo;
