@@ -100,96 +100,102 @@ __global__ __launch_bounds__(256) void weight_t_kernel(const uint16_t* __restric
   }
 }
 
-// C = alpha X Y^T + beta C.  A 256-thread workgroup owns a 128 x 128 tile of
-// C, each wavefront a 64 x 64 quarter of 4 x 4 MFMA blocks; K advances in
-// slabs of 64 staged in dynamic LDS (rows padded to 72 values, so that the
-// 16-byte reads of a lane group fall in distinct banks; two buffers, 72 KiB,
-// two workgroups per compute unit), the next slab in flight during the
-// current one's MFMAs (two k-steps of 32 per slab and barrier).
-constexpr int BT = 128, BK = 64, BPAD = 8;
+// C = alpha X Y^T + beta C.  A workgroup of 64 WGM WGN lanes owns a TM x TN
+// tile of C, each wavefront a (TM / WGM) x (TN / WGN) part of 16 x 16 MFMA
+// blocks; K advances in slabs of BK = 64 staged in dynamic LDS (rows padded
+// to 72 values, so that the 16-byte reads of a lane group fall in distinct
+// banks; two buffers), the next slab's 16-byte global loads in flight during
+// the current one's MFMAs (two k-steps of 32 per slab and barrier).  Two
+// shapes: 256 x 256 with eight wavefronts of 64 x 128 (144 KiB of LDS, one
+// workgroup per compute unit; the most reuse of each staged slab) for
+// products of at least one tile per compute unit, 128 x 128 with four
+// wavefronts of 64 x 64 (72 KiB, two per compute unit) below that.  Every
+// element of C adds the same products in the same order in both.
+constexpr int BK = 64, BPAD = 8;
 
-struct SlabLoader {
-  // thread t loads rows t / 8 + 32 e (e = 0..3), k chunk (t % 8) 8
-  int row, kc;
-  __device__ __forceinline__ explicit SlabLoader(int tid) : row(tid >> 3), kc((tid & 7) * 8) {}
-  __device__ __forceinline__ void load(const uint16_t* X, size_t ld, int x0, int xext, int k0, int K, bool vec,
-                                       uint4 (&r)[4]) const {
+template <int TM, int TN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_bf16_kernel(int M, int N, int K, float alpha,
+                                                                      const uint16_t* __restrict__ X, size_t ldx,
+                                                                      const uint16_t* __restrict__ Y, size_t ldy,
+                                                                      float beta, float* __restrict__ C,
+                                                                      size_t ldc, int vec) {
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int RP = NT / 8;  // rows per load pass: 8 threads of 8 values per 64-value row
+  constexpr int PX = TM / RP, PY = TN / RP;
+  constexpr int FM = TM / WGM / 16, FN = TN / WGN / 16;  // MFMA blocks per wavefront
+  static_assert(TM % RP == 0 && TN % RP == 0 && FM > 0 && FN > 0, "tile shape");
+  extern __shared__ __align__(16) uint16_t gsm[];
+  uint16_t(*sX)[TM][BK + BPAD] = reinterpret_cast<uint16_t(*)[TM][BK + BPAD]>(gsm);
+  uint16_t(*sY)[TN][BK + BPAD] = reinterpret_cast<uint16_t(*)[TN][BK + BPAD]>(gsm + 2 * TM * (BK + BPAD));
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave / WGN) * (TM / WGM), wn = (wave % WGN) * (TN / WGN);
+  const int li = lane & 15, lk = (lane >> 4) * 8;
+  // thread t loads rows t / 8 + RP e of a slab, k chunk (t % 8) 8
+  const int lrow = tid >> 3, lkc = (tid & 7) * 8;
+  const bool vc = vec != 0;
+  auto load = [&](const uint16_t* Z, size_t ld, int z0, int zext, int k0, uint4* r, int P) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int gx = x0 + row + 32 * e, gk = k0 + kc;
-      const uint16_t* src = X + (size_t)gx * ld + gk;
-      if (vec && gx < xext && gk + 8 <= K) {
+    for (int e = 0; e < P; ++e) {
+      const int gz = z0 + lrow + RP * e, gk = k0 + lkc;
+      const uint16_t* src = Z + (size_t)gz * ld + gk;
+      if (vc && gz < zext && gk + 8 <= K) {
         r[e] = *reinterpret_cast<const uint4*>(src);
       } else {
         uint16_t v[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = (gx < xext && gk + q < K) ? src[q] : (uint16_t)0;
-        r[e] = make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
-                          v[6] | ((uint32_t)v[7] << 16));
+        for (int q = 0; q < 8; ++q) v[q] = (gz < zext && gk + q < K) ? src[q] : (uint16_t)0;
+        r[e] = make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16),
+                          v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16));
       }
     }
-  }
-  __device__ __forceinline__ void store(uint16_t (*sl)[BK + BPAD], const uint4 (&r)[4]) const {
+  };
+  f32x4 acc[FM][FN];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) *reinterpret_cast<uint4*>(&sl[row + 32 * e][kc]) = r[e];
-  }
-};
-
-__global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, float alpha,
-                                                           const uint16_t* __restrict__ X, size_t ldx,
-                                                           const uint16_t* __restrict__ Y, size_t ldy, float beta,
-                                                           float* __restrict__ C, size_t ldc, int vec) {
-  extern __shared__ __align__(16) uint16_t gsm[];
-  uint16_t(*sX)[BT][BK + BPAD] = reinterpret_cast<uint16_t(*)[BT][BK + BPAD]>(gsm);
-  uint16_t(*sY)[BT][BK + BPAD] = reinterpret_cast<uint16_t(*)[BT][BK + BPAD]>(gsm + 2 * BT * (BK + BPAD));
-  const int m0 = blockIdx.y * BT, n0 = blockIdx.x * BT;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  const int li = lane & 15, lk = (lane >> 4) * 8;
-  const SlabLoader ld(tid);
-
-  f32x4 acc[4][4];
+  for (int a = 0; a < FM; ++a)
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < FN; ++b) acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  uint4 rx[PX], ry[PY];
+  load(X, ldx, m0, M, 0, rx, PX);
+  load(Y, ldy, n0, N, 0, ry, PY);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-
-  uint4 rx[4], ry[4];
-  ld.load(X, ldx, m0, M, 0, K, vec != 0, rx);
-  ld.load(Y, ldy, n0, N, 0, K, vec != 0, ry);
-  ld.store(sX[0], rx);
-  ld.store(sY[0], ry);
+  for (int e = 0; e < PX; ++e) *reinterpret_cast<uint4*>(&sX[0][lrow + RP * e][lkc]) = rx[e];
+#pragma unroll
+  for (int e = 0; e < PY; ++e) *reinterpret_cast<uint4*>(&sY[0][lrow + RP * e][lkc]) = ry[e];
   __syncthreads();
   int buf = 0;
   for (int k0 = 0; k0 < K; k0 += BK) {
     const bool more = k0 + BK < K;
     if (more) {
-      ld.load(X, ldx, m0, M, k0 + BK, K, vec != 0, rx);
-      ld.load(Y, ldy, n0, N, k0 + BK, K, vec != 0, ry);
+      load(X, ldx, m0, M, k0 + BK, rx, PX);
+      load(Y, ldy, n0, N, k0 + BK, ry, PY);
     }
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 32) {
-      bf16x8 xv[4], yv[4];
+      bf16x8 xv[FM], yv[FN];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) xv[a] = *reinterpret_cast<const bf16x8*>(&sX[buf][wm + 16 * a + li][ks + lk]);
+      for (int a = 0; a < FM; ++a) xv[a] = *reinterpret_cast<const bf16x8*>(&sX[buf][wm + 16 * a + li][ks + lk]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) yv[b] = *reinterpret_cast<const bf16x8*>(&sY[buf][wn + 16 * b + li][ks + lk]);
+      for (int b = 0; b < FN; ++b) yv[b] = *reinterpret_cast<const bf16x8*>(&sY[buf][wn + 16 * b + li][ks + lk]);
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xv[a], yv[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < FN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xv[a], yv[b], acc[a][b], 0, 0, 0);
     }
     if (more) {
-      ld.store(sX[buf ^ 1], rx);
-      ld.store(sY[buf ^ 1], ry);
+#pragma unroll
+      for (int e = 0; e < PX; ++e) *reinterpret_cast<uint4*>(&sX[buf ^ 1][lrow + RP * e][lkc]) = rx[e];
+#pragma unroll
+      for (int e = 0; e < PY; ++e) *reinterpret_cast<uint4*>(&sY[buf ^ 1][lrow + RP * e][lkc]) = ry[e];
     }
     __syncthreads();
     buf ^= 1;
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < FN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gi = m0 + wm + 16 * a + (lane >> 4) * 4 + r;
@@ -286,28 +292,39 @@ hipError_t launch_weight_t_bf16(const uint16_t* S, int n, int m, int d, const do
   return hipGetLastError();
 }
 
-hipError_t gemm_nt_bf16(int M, int N, int K, float alpha, const uint16_t* X, size_t ldx, const uint16_t* Y,
-                        size_t ldy, float beta, float* C, size_t ldc, hipStream_t st) {
-  if (M <= 0 || N <= 0) return hipSuccess;
-  const bool vec = ((uintptr_t)X % 16) == 0 && ((uintptr_t)Y % 16) == 0 && ldx % 8 == 0 && ldy % 8 == 0;
-  const dim3 g(nblk(N, BT), nblk(M, BT)), b(256);
-  const size_t lds = 4 * (size_t)BT * (BK + BPAD) * sizeof(uint16_t);
+// One tile shape's launch; the LDS attribute (beyond the default 64 KiB of
+// dynamic LDS) is set once per device.
+template <int TM, int TN, int WGM, int WGN>
+hipError_t launch_gemm_bf16(int M, int N, int K, float alpha, const uint16_t* X, size_t ldx, const uint16_t* Y,
+                            size_t ldy, float beta, float* C, size_t ldc, bool vec, hipStream_t st) {
+  auto kern = gemm_nt_bf16_kernel<TM, TN, WGM, WGN>;
+  const size_t lds = 2 * (size_t)(TM + TN) * (BK + BPAD) * sizeof(uint16_t);
   {
-    // more than the default 64 KiB of dynamic LDS: allowed once per device
     static std::mutex mu;
     static std::set<int> done;
     int dev = 0;
     (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> g_(mu);
     if (!done.count(dev)) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_nt_bf16_kernel),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      const hipError_t e =
+          hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
       done.insert(dev);
     }
   }
-  hipLaunchKernelGGL(gemm_nt_bf16_kernel, g, b, lds, st, M, N, K, alpha, X, ldx, Y, ldy, beta, C, ldc, vec ? 1 : 0);
+  hipLaunchKernelGGL(kern, dim3(nblk(N, TN), nblk(M, TM)), dim3(64 * WGM * WGN), lds, st, M, N, K, alpha, X, ldx, Y,
+                     ldy, beta, C, ldc, vec ? 1 : 0);
   return hipGetLastError();
+}
+
+hipError_t gemm_nt_bf16(int M, int N, int K, float alpha, const uint16_t* X, size_t ldx, const uint16_t* Y,
+                        size_t ldy, float beta, float* C, size_t ldc, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const bool vec = ((uintptr_t)X % 16) == 0 && ((uintptr_t)Y % 16) == 0 && ldx % 8 == 0 && ldy % 8 == 0;
+  // the 256 x 256 tiles once there is at least one per compute unit
+  if ((size_t)nblk(M, 256) * nblk(N, 256) >= 256)
+    return launch_gemm_bf16<256, 256, 4, 2>(M, N, K, alpha, X, ldx, Y, ldy, beta, C, ldc, vec, st);
+  return launch_gemm_bf16<128, 128, 2, 2>(M, N, K, alpha, X, ldx, Y, ldy, beta, C, ldc, vec, st);
 }
 
 size_t gemv_t_bf16_part_elems(int K) { return (size_t)kBfRowBlocks * (size_t)K; }

@@ -53,6 +53,31 @@ def test_gemm_bf16_nt_matches_fp64(M, N, K, ragged):
     assert torch.all((C2.cpu().double() - ref2).abs() <= 1e-5 * (0.5 * scale + 2.0 * C0.double().abs()) + 1e-30)
 
 
+@pytest.mark.parametrize("ragged", [False, True])
+def test_gemm_bf16_nt_large_tiles(ragged):
+    # at least one 256 x 256 tile per compute unit: the large-tile kernel,
+    # ragged in both sides; its leading block must equal, bit for bit, the
+    # product of the leading rows alone (the 128 x 128 kernel): every element
+    # adds the same products in the same order
+    M, N, K = 4100, 4097, 200
+    g = torch.Generator().manual_seed(5 + ragged)
+    if ragged:
+        Xb = torch.randn(M, K + 3, generator=g).bfloat16()[:, 1:K + 1]
+        Yb = torch.randn(N, K + 5, generator=g).bfloat16()[:, 2:K + 2]
+    else:
+        Xb = torch.randn(M, K, generator=g).bfloat16()
+        Yb = torch.randn(N, K, generator=g).bfloat16()
+    _say("gemm bf16 large tiles", M, N, K, "ragged" if ragged else "")
+    Xd, Yd = Xb.cuda(), Yb.cuda()
+    C = P.gemm_bf16_nt(Xd, Yd)
+    Cs = P.gemm_bf16_nt(Xd[:300], Yd[:260])
+    torch.cuda.synchronize()
+    ref = Xb.double() @ Yb.double().T
+    scale = Xb.double().abs() @ Yb.double().abs().T
+    assert torch.all((C.cpu().double() - ref).abs() <= 1e-5 * scale + 1e-30)
+    assert torch.equal(C[:300, :260].cpu(), Cs.cpu())
+
+
 @pytest.fixture(scope="module")
 def square_tb():
     dom = W.unit_square()
