@@ -183,13 +183,18 @@ enum { WOS_ACC_AUTO = 0, WOS_ACC_FIXED = 1, WOS_ACC_F64 = 2 };
  * (R the half diagonal of the bounding box, R^2 / d a bound on the mean
  * exit time, 4 a margin for its fluctuation over the item's walks,
  * omega_max = 12 the largest d = 2 weight with 24-bit uniforms, 1 in 3-D),
- * r0 the smallest distance of a site to the boundary.                        */
+ * r0 the smallest distance of a site to the boundary.  In the WINDOW mode
+ * each site is split by its own bound (its own r0), so sites far from the
+ * boundary keep larger items than sites near it; walks_per_item is then the
+ * smallest item of any site, items_per_site the most items of any site,
+ * and fixed_bound the largest over the sites.                                */
 typedef struct {
   int32_t tally_mode;       /* the mode used (never AUTO)                         */
   int32_t tally_acc;        /* LDS_ROWS: WOS_ACC_FIXED or WOS_ACC_F64; WINDOW:
                                WOS_ACC_FIXED                                      */
-  int32_t walks_per_item;   /* walks one workgroup takes per site                 */
-  int32_t items_per_site;
+  int32_t walks_per_item;   /* walks one workgroup takes per site (WINDOW: the
+                               smallest over the sites)                          */
+  int32_t items_per_site;   /* (WINDOW: the most over the sites)                 */
   int32_t window_pages;     /* WINDOW: V pages per site held in LDS              */
   int32_t window_bpages;    /* WINDOW: boundary pages per site held in LDS       */
   int64_t lds_bytes;        /* LDS of one walker workgroup                        */

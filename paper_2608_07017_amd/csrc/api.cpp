@@ -281,7 +281,7 @@ void release(wos_toolbox* tb) {
                   tb->d_sites_f64, tb->d_bnodes, tb->d_segs, tb->d_verts, tb->d_A, tb->d_B,
                   tb->d_K, tb->d_H, tb->d_Hc, tb->d_vcount, tb->d_stats, tb->d_lambda,
                   tb->d_item_order, tb->gv_r.rec, tb->gv_r.list, tb->gg_r.rec, tb->gg_r.list,
-                  tb->d_vsites_r, tb->d_bnodes_r, tb->d_vrank, tb->d_brank, tb->d_win, tb->d_site_steps,
+                  tb->d_vsites_r, tb->d_bnodes_r, tb->d_vrank, tb->d_brank, tb->d_win, tb->d_items, tb->d_site_steps,
                   tb->d_mom_phi, tb->d_mom_psi, tb->d_mom, tb->d_SV, tb->d_SG, tb->d_bfy, tb->d_bfpart};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -415,6 +415,11 @@ struct Plan {
   int wpi = 1, ips = 1, pc = 0, pb = 0;
   size_t lds = 0;
   double fixed_bound = 0;
+  // windowed mode: walks per item of each site (its own fixed-point bound),
+  // and the number of items over all sites; wpi is then the smallest and
+  // ips the most items of a site
+  std::vector<int> site_wpi;
+  int64_t items = 0;
 };
 
 constexpr size_t kLdsBytes = 160 * 1024;
@@ -439,10 +444,17 @@ wos_status make_plan(const HostDomain& hd, const double* sites, int n, int m, in
   host_bbox(hd, lo, hi);
   double R2 = 0;
   for (int a = 0; a < d; ++a) R2 += 0.25 * (hi[a] - lo[a]) * (hi[a] - lo[a]);
+  std::vector<double> r0s(n);
   double r0min = 1e300;
-  for (int i = 0; i < n; ++i) r0min = std::min(r0min, host_distance(hd, sites + (size_t)i * d));
+  for (int i = 0; i < n; ++i) {
+    r0s[i] = host_distance(hd, sites + (size_t)i * d);
+    r0min = std::min(r0min, r0s[i]);
+  }
   const double om_max = (d == 2 && o->sampler == WOS_SAMPLER_MEDIAN3) ? 12.0 : 1.0;
-  const double per_walk = std::max(d / r0min, std::max(4.0 * (d / r0min) * R2 / d, 4.0 * om_max * R2 / d));
+  auto per_walk_at = [&](double r0) {
+    return std::max(d / r0, std::max(4.0 * (d / r0) * R2 / d, 4.0 * om_max * R2 / d));
+  };
+  const double per_walk = per_walk_at(r0min);
   // the most walks per item that keep the bound below 1/2
   const double wpi_fixed = 0.49 * 2147483648.0 / per_walk;
 
@@ -508,13 +520,36 @@ wos_status make_plan(const HostDomain& hd, const double* sites, int n, int m, in
     const int64_t floor_w = std::min<int64_t>(N, 4 * (int64_t)bs);  // >= 4 walks per lane
     wpi = std::max<int64_t>((N + ips - 1) / ips, floor_w);
   }
-  // the windowed mode always sums in fixed point: items small enough for it
-  if (mode == WOS_TALLY_WINDOW) wpi = std::max<int64_t>(1, std::min<int64_t>(wpi, (int64_t)wpi_fixed));
-  pl->wpi = (int)wpi;
-  pl->ips = (int)((N + wpi - 1) / wpi);
-  if ((int64_t)pl->ips * n > (int64_t)INT32_MAX) return fail(WOS_EINVAL, "too many work items");
-
-  pl->fixed_bound = (double)wpi * per_walk / 2147483648.0;
+  if (mode == WOS_TALLY_WINDOW) {
+    // the windowed mode always sums in fixed point: each site's items small
+    // enough for its own bound (a site far from the boundary keeps whole
+    // items; fewer items, fewer flushes)
+    if (N > (int64_t)INT32_MAX) return fail(WOS_EINVAL, "tally_mode WINDOW: at most 2^31 - 1 walks per site");
+    pl->site_wpi.resize(n);
+    int64_t wmin = wpi, imax = 1, total = 0;
+    double fb = 0;
+    for (int i = 0; i < n; ++i) {
+      const double pw = per_walk_at(r0s[i]);
+      const int64_t wi = std::max<int64_t>(1, std::min<int64_t>(wpi, (int64_t)(0.49 * 2147483648.0 / pw)));
+      const int64_t k = (N + wi - 1) / wi;
+      pl->site_wpi[i] = (int)wi;
+      wmin = std::min(wmin, wi);
+      imax = std::max(imax, k);
+      total += k;
+      fb = std::max(fb, (double)wi * pw / 2147483648.0);
+    }
+    if (total > (int64_t)INT32_MAX) return fail(WOS_EINVAL, "too many work items");
+    pl->wpi = (int)wmin;
+    pl->ips = (int)imax;
+    pl->items = total;
+    pl->fixed_bound = fb;
+  } else {
+    pl->wpi = (int)wpi;
+    pl->ips = (int)((N + wpi - 1) / wpi);
+    if ((int64_t)pl->ips * n > (int64_t)INT32_MAX) return fail(WOS_EINVAL, "too many work items");
+    pl->items = (int64_t)pl->ips * n;
+    pl->fixed_bound = (double)wpi * per_walk / 2147483648.0;
+  }
   if (mode == WOS_TALLY_WINDOW) {
     pl->acc = WOS_ACC_FIXED;
   } else if (f64 || mode != WOS_TALLY_LDS_ROWS) {
@@ -574,6 +609,7 @@ static void fill_walker_params(const wos_toolbox* tb, uint32_t k0, uint32_t k1, 
   P.regen_T = tb->regen_T;
   P.block_override = block;
   P.item_order = tb->d_item_order;
+  P.items = tb->d_items;  // windowed mode (NULL otherwise)
   P.direct_store = tb->items_per_site == 1 ? 1 : 0;
   P.global_tally = tb->global_tally ? 1 : 0;
   P.window = tb->tally_mode == WOS_TALLY_WINDOW ? 1 : 0;
@@ -604,7 +640,7 @@ static void fill_walker_params(const wos_toolbox* tb, uint32_t k0, uint32_t k1, 
 // autotuner's timing runs)
 static wos_status launch_walker(const wos_toolbox* tb, uint32_t k0, uint32_t k1, int block, hipStream_t stream,
                                 int max_items = 0) {
-  int items = tb->items_per_site * tb->n;
+  int items = tb->n_items;
   if (max_items > 0) items = std::min(items, max_items);
   if (tb->f64) {
     WalkerParams<double> P{};
@@ -686,6 +722,7 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
   tb->acc_fixed = pl.acc == WOS_ACC_FIXED ? 1 : 0;
   tb->walks_per_item = pl.wpi;
   tb->items_per_site = pl.ips;
+  tb->n_items = (int)pl.items;
   tb->win_pc = pl.pc;
   tb->win_pb = pl.pb;
   tb->autotune = opts->autotune != 0;
@@ -723,19 +760,27 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
     std::vector<int> order;
     order.reserve((size_t)n * tb->items_per_site);
     if (pl.mode == WOS_TALLY_WINDOW) {
-      // items of sites in Morton order, in eight contiguous runs dealt to
-      // the workgroup slots round-robin (workgroup b runs on accelerator
-      // die b mod 8, so each die walks one compact part of the domain and
-      // its L2 holds that part's grid records and toolbox rows)
+      // items of sites in Morton order, each site split by its own item
+      // size, in eight contiguous runs dealt to the workgroup slots
+      // round-robin (workgroup b runs on accelerator die b mod 8, so each
+      // die walks one compact part of the domain and its L2 holds that
+      // part's grid records and toolbox rows)
       std::vector<int> so = morton_order(sites, n, d, lo, hi);
-      std::vector<int> items;
-      items.reserve(order.capacity());
-      for (int i : so)
-        for (int c = 0; c < tb->items_per_site; ++c) items.push_back(i * tb->items_per_site + c);
+      const int64_t N = tb->opts.walks_per_site;
+      std::vector<int4> items;
+      items.reserve((size_t)pl.items);
+      for (int i : so) {
+        const int64_t wi = pl.site_wpi[i], k = (N + wi - 1) / wi;
+        for (int64_t c = 0; c < k; ++c)
+          items.push_back(make_int4(i, (int)(c * wi), (int)std::min<int64_t>(N, (c + 1) * wi), k == 1 ? 1 : 0));
+      }
+      std::vector<int4> dealt;
+      dealt.reserve(items.size());
       const size_t T = items.size(), run = (T + 7) / 8;
       for (size_t k = 0; k < run; ++k)
         for (size_t x = 0; x < 8; ++x)
-          if (x * run + k < T && k < run) order.push_back(items[x * run + k]);
+          if (x * run + k < T) dealt.push_back(items[x * run + k]);
+      TRY(upload(tb, (void**)&tb->d_items, dealt.data(), dealt.size() * sizeof(int4)));
     } else {
       // items in order of decreasing expected work: walks from sites far
       // from the boundary take more steps
@@ -749,7 +794,7 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
       for (int i : site_rank)
         for (int c = 0; c < tb->items_per_site; ++c) order.push_back(i * tb->items_per_site + c);
     }
-    TRY(upload(tb, (void**)&tb->d_item_order, order.data(), order.size() * sizeof(int)));
+    if (!order.empty()) TRY(upload(tb, (void**)&tb->d_item_order, order.data(), order.size() * sizeof(int)));
   }
   TRY(upload_grid(tb, gvh, &tb->gv));
   TRY(upload_grid(tb, ggh, &tb->gg));

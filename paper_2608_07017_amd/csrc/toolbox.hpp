@@ -110,6 +110,10 @@ struct wos_toolbox {
   int tally_mode = WOS_TALLY_LDS_ROWS;  // wos_tally_mode in use (never AUTO)
   bool global_tally = false;  // HBM or WINDOW: tallies reach the toolbox by device atomics
   int* d_item_order = nullptr;
+  // windowed mode: the items in launch order, {site, first walk, end walk,
+  // 1 if the site's only item}
+  int n_items = 0;
+  int4* d_items = nullptr;
   // windowed tally mode: V centres and boundary nodes ranked along a Morton
   // curve (the walker's columns are ranks until the final permutation)
   int win_pc = 0, win_pb = 0;    // pages of V cells / boundary cells per site in LDS

@@ -167,11 +167,23 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
   __shared__ unsigned long long s_steps, s_walks, s_capped;
   __shared__ unsigned int s_maxk;
 
-  const int item = P.item_order[blockIdx.x];
-  const int site = item / P.items_per_site;
-  const int chunk = item - site * P.items_per_site;
-  const int64_t l_begin = (int64_t)chunk * P.walks_per_item;
-  const int64_t l_end = min(P.walks, l_begin + (int64_t)P.walks_per_item);
+  int site;
+  int64_t l_begin, l_end;
+  bool sole_item;  // the site's only item: its window cells are this workgroup's alone
+  if (P.items) {
+    const int4 it = P.items[blockIdx.x];
+    site = it.x;
+    l_begin = it.y;
+    l_end = it.z;
+    sole_item = it.w != 0;
+  } else {
+    const int item = P.item_order[blockIdx.x];
+    site = item / P.items_per_site;
+    const int chunk = item - site * P.items_per_site;
+    l_begin = (int64_t)chunk * P.walks_per_item;
+    l_end = min(P.walks, l_begin + (int64_t)P.walks_per_item);
+    sole_item = P.items_per_site == 1;
+  }
   const int m = P.m, p = P.p;
   constexpr int PS = PtStride<D>::value;
 
@@ -646,17 +658,28 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
 
   if constexpr (GLOBAL || WINDOW) {
     if constexpr (WINDOW) {
-      // the window's sums, scaled by 1/N, onto the toolbox rows
+      // the window's sums, scaled by 1/N, onto the toolbox rows: plain
+      // stores when this is the site's only item (no other workgroup writes
+      // the window's cells of this row, and the device atomics of this one
+      // go to other cells), else device atomics
       const double inv_N = (double)P.inv_N;
       for (int c = tid; c < pc * kPageCells; c += kBlock) {
         const int j = ((int)wl[c >> 6] << 6) | (c & 63);
         if (j < m) {
           const AW va = sA[c];
-          if (va != AW(0)) dev_atomic_add(&gA[j], (T)(Acc<kAccFixed>::value(va) * inv_N));
+          const T ta = (T)(Acc<kAccFixed>::value(va) * inv_N);
+          if (sole_item)
+            gA[j] = ta;
+          else if (va != AW(0))
+            dev_atomic_add(&gA[j], ta);
 #pragma unroll
           for (int a = 0; a < D; ++a) {
             const AW vb = sB[a * bstride + c];
-            if (vb != AW(0)) dev_atomic_add(&gB[a * gbs + j], (T)(Acc<kAccFixed>::value(vb) * inv_N));
+            const T tb = (T)(Acc<kAccFixed>::value(vb) * inv_N);
+            if (sole_item)
+              gB[a * gbs + j] = tb;
+            else if (vb != AW(0))
+              dev_atomic_add(&gB[a * gbs + j], tb);
           }
         }
       }
@@ -664,11 +687,18 @@ __global__ __launch_bounds__(kBlock) void walker_kernel(WalkerParams<T> P) {
         const int j = ((int)wl[pc + (c >> 6)] << 6) | (c & 63);
         if (j < p) {
           const unsigned int h = sH[c];
-          if (h) dev_atomic_add(&gH[j], h);
+          if (sole_item)
+            gH[j] = h;
+          else if (h)
+            dev_atomic_add(&gH[j], h);
 #pragma unroll
           for (int a = 0; a < D; ++a) {
             const AW vk = sK[a * kstride + c];
-            if (vk != AW(0)) dev_atomic_add(&gK[a * gks + j], (T)(Acc<kAccFixed>::value(vk) * inv_N));
+            const T tk = (T)(Acc<kAccFixed>::value(vk) * inv_N);
+            if (sole_item)
+              gK[a * gks + j] = tk;
+            else if (vk != AW(0))
+              dev_atomic_add(&gK[a * gks + j], tk);
           }
         }
       }

@@ -65,6 +65,10 @@ struct WalkerParams {
   int global_tally;    // tallies by atomics to the toolbox in HBM (rows too large for LDS)
   int exact_radius;    // d = 2: R from the exact radial law (Lambert W), weight 1
   const int* item_order;  // blockIdx -> item (longest expected work first)
+  // windowed mode: blockIdx -> {site, first walk, end walk, 1 if the site's
+  // only item} (each site split by its own fixed-point bound); NULL: items
+  // of items_per_site x walks_per_item through item_order
+  const int4* items;
   int direct_store;
   int acc_fixed;   // tally accumulators: 0 FP64, 1 64-bit fixed point
   int window;      // windowed tallies: columns are Morton ranks, pages listed per site
