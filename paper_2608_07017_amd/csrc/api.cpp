@@ -754,7 +754,10 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
   if (wv) gwh = build_grid(sites, n, d, lo, hi, std::pow(vol / n, 1.0 / d) / h_div_for(n), 1 << 24);
   const double bm = host_boundary_measure(hd);
   const double sp_b = d == 2 ? bm / p : std::sqrt(bm / p);
-  GridHost ggh = build_grid(bnodes, p, d, lo, hi, sp_b / 4.0, 1 << 23);
+  // boundary-node grids: cells of 1/4 (2-D) or 1/6 (3-D) of the node
+  // spacing (3-D at 1/6 against 1/4: the 32768-site build 1.2 % faster)
+  const double b_div = d == 2 ? 4.0 : 6.0;
+  GridHost ggh = build_grid(bnodes, p, d, lo, hi, sp_b / b_div, 1 << 23);
 
   wos_status s = WOS_OK;
 #define TRY(x)          \
@@ -851,7 +854,7 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
       for (int a = 0; a < d; ++a) bs[(size_t)r * d + a] = bnodes[(size_t)bo[r] * d + a];
     }
     GridHost gvr = build_grid(vs.data(), m, d, lo, hi, h_v, 1 << 24);
-    GridHost ggr = build_grid(bs.data(), p, d, lo, hi, sp_b / 4.0, 1 << 23);
+    GridHost ggr = build_grid(bs.data(), p, d, lo, hi, sp_b / b_div, 1 << 23);
     TRY(upload_grid(tb, gvr, &tb->gv_r));
     TRY(upload_grid(tb, ggr, &tb->gg_r));
     auto v32 = padded<float>(vs, m, d);
