@@ -308,11 +308,13 @@ def test_window_sites_split_by_their_own_bound():
     dom = W.unit_square()
     sites = np.concatenate([W.sample_sites(dom, 40, 31, 1e-3), [[1e-6, 0.5]]])
     bn = W.square_nodes(24)
-    plan = P.build_plan(dom, sites, bn, 4000, 1e-4, tally="window", window_pages=1, window_bpages=1)
+    # items of up to all 4000 walks: the 40 far sites take one item each
+    wk = dict(tally="window", window_pages=1, window_bpages=1, walks_per_item=4000)
+    plan = P.build_plan(dom, sites, bn, 4000, 1e-4, **wk)
     assert plan["items_per_site"] == 8 and plan["walks_per_item"] == int(0.49 * 2 ** 31 / 2e6)
     kw = dict(precision="f32", volume_samples=1 << 12)
     t1 = _gpu_tb(dom, sites, bn, 4000, 1e-4, 17, **kw)
-    t2 = _gpu_tb(dom, sites, bn, 4000, 1e-4, 17, tally="window", window_pages=1, window_bpages=1, **kw)
+    t2 = _gpu_tb(dom, sites, bn, 4000, 1e-4, 17, **wk, **kw)
     i1, i2 = t1.info(), t2.info()
     for k in ("walks", "walk_steps", "max_walk_steps", "capped_walks"):
         assert i1[k] == i2[k], k

@@ -104,6 +104,25 @@ def test_window_items_are_split_for_fixed_point():
     assert auto["tally_mode"] == "hbm"          # rows beyond LDS, items of 52 walks would be too small
 
 
+def test_window_items_follow_each_sites_own_bound():
+    # in the windowed mode each site is split by its own bound: with 4000
+    # walks, the site 1e-6 from the boundary takes items of 0.49 2^31 / 2e6
+    # = 526 walks (8 items), the 40 sites at least 1e-3 from it larger ones;
+    # the plan reports the smallest item, the most items of a site and the
+    # largest bound
+    dom = W.unit_square()
+    sites = np.concatenate([W.sample_sites(dom, 40, 31, 1e-3), [[1e-6, 0.5]]])
+    pl = P.build_plan(dom, sites, W.square_nodes(24), 4000, 1e-4, tally="window", window_pages=1, window_bpages=1)
+    assert pl["walks_per_item"] == int(0.49 * 2 ** 31 / 2e6) and pl["items_per_site"] == 8
+    assert 0.48 < pl["fixed_bound"] < 0.5
+    # without the near site only the load balance splits the sites (items
+    # of at least 4 walks per lane of a workgroup), far below their bounds
+    pl2 = P.build_plan(dom, sites[:-1], W.square_nodes(24), 4000, 1e-4, tally="window", window_pages=1,
+                       window_bpages=1)
+    assert pl2["walks_per_item"] >= 1024 and pl2["items_per_site"] * pl2["walks_per_item"] >= 4000
+    assert pl2["fixed_bound"] < 0.01
+
+
 def test_plan_rejects_bad_inputs():
     dom = W.unit_disk()
     with pytest.raises(P.WosError):
