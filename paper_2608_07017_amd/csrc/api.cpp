@@ -737,17 +737,18 @@ wos_status wos_toolbox_create_wv(const wos_domain* dom, const double* sites, int
   double vol = 1;
   for (int a = 0; a < d; ++a) vol *= (hi[a] - lo[a]);
   // cell side: a fraction 1/h_div of the mean centre spacing, so that most
-  // cells hold at most four candidates.  2-D: 1/8.  3-D: the finest of 1/6
-  // .. 1/10 whose records (16 bytes a cell, count h_div^3 per centre) stay
-  // within 64 MiB: finer cells list fewer candidates, so fewer centre loads
-  // per lookup, until the records outgrow the caches (measured: the
-  // 4096-site ball walker 13.0 ms at 1/6, 11.7 at 1/9 and 1/10, 12.2 at
-  // 1/12; the 32768-site cube minus ball best at 1/6 and 1/7, slower at
-  // 1/8).  At 1/6 about 2 % of the cells of uniformly scattered centres go
-  // to the overflow entries.
+  // cells hold at most four candidates.  2-D: 1/8.  3-D: the finest cells
+  // whose records (16 bytes a cell, h_div^3 cells per centre) stay within
+  // 150 MiB, with h_div between 6 and 10: finer cells list fewer
+  // candidates, so fewer centre loads per lookup, until the records
+  // outgrow the caches.  Measured on the walker: the 4096-site ball 13.0 ms
+  // at 1/6, 11.7 at 1/9 and 1/10, 12.2 at 1/12; the 32768-site cube minus
+  // ball (1e5 walks) 1374 ms at 1/6, 1348 at 1/6.75, 1368 at 1/7 (this
+  // rule gives 1/6.7 there and 1/10 for the ball).  At 1/6 about 2 % of the
+  // cells of uniformly scattered centres go to the overflow entries.
   auto h_div_for = [&](int count) {
     if (d == 2) return 8.0;
-    const double h = std::floor(std::cbrt(64.0 * 1024.0 * 1024.0 / (16.0 * count)));
+    const double h = std::cbrt(150.0 * 1024.0 * 1024.0 / (16.0 * count));
     return std::min(10.0, std::max(6.0, h));
   };
   const double h_v = std::pow(vol / m, 1.0 / d) / h_div_for(m);
